@@ -1,0 +1,170 @@
+/*
+ * cosparse.h -- C-ABI of the MI355X (gfx950) co-sparse data-term library.
+ *
+ * Method: Nieuwenhuis, Hawe, Kleinsteuber, Cremers, "Co-Sparse Textural
+ * Similarity for Image Segmentation" (arXiv 1312.4746).  The library computes,
+ * for every pixel x and label i, the log-likelihood l_i(x) = -f_i(x) of the
+ * supervised data term (Sec. 3.1, Sec. 3.2): every pixel's normalised gray
+ * patch is analysed by the operator O (Sec. 2), the analysed vector is
+ * thresholded into a co-support, co-supports are compared with the texture
+ * similarity TSM (Sec. 2), and TSM is combined with colour and location
+ * Gaussian kernels in the spatially varying Parzen sum over each label's
+ * scribble samples (Sec. 3.1).
+ *
+ * Conventions shared by every call:
+ *  - Images are three float32 planes R, G, B, each H*W, in DEVICE memory;
+ *    pixel x = (col, row) has linear index row*W + col.  N = H*W.
+ *  - Patches are p x p (p odd, 3..15), n = p*p, element t = (u+h)*p + (v+h)
+ *    for row offset u and column offset v in [-h, h], h = (p-1)/2; borders
+ *    use symmetric reflection that repeats the edge pixel.
+ *  - The operator O is k x n float32 row-major in DEVICE memory, 1 <= k <= 256.
+ *  - A co-support mask is ceil(k/64) uint64 words per pixel; index j is bit
+ *    (j mod 64) of word j/64; bits at j >= k are 0.
+ *  - Every pointer marked "device" is caller-owned device memory, "host" is
+ *    caller-owned host memory.  The library never frees or keeps caller
+ *    pointers beyond the work it enqueues; device buffers must stay alive until
+ *    the context's stream has completed that work.
+ *  - All calls enqueue asynchronously on the context's HIP stream and return,
+ *    except where a call returns a host value (noted), which synchronises it.
+ *  - Calls return CS_OK or an error code; they never abort or throw.  Argument
+ *    errors are detected before anything is launched.  cs_last_error gives a
+ *    message.  A context is used by one host thread at a time.
+ */
+#ifndef COSPARSE_H
+#define COSPARSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CS_OK 0
+#define CS_ERR_ARG 1          /* invalid argument (null pointer, size or range) */
+#define CS_ERR_EMPTY_LABEL 2  /* some label has no scribble sample (m_i = 0)     */
+#define CS_ERR_HIP 3          /* a HIP runtime call failed                        */
+#define CS_ERR_NOMEM 4        /* device workspace allocation failed               */
+
+#define CS_FP32 0 /* O s on FP32 MFMA, FP32 accumulation                        */
+#define CS_BF16 1 /* O s on BF16 MFMA (both operands rounded), FP32 accumulation */
+
+typedef struct cs_ctx cs_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The context owns a device
+ * workspace that grows on demand and is freed by cs_destroy. */
+int cs_create(cs_ctx **ctx, int device, void *hip_stream);
+int cs_destroy(cs_ctx *ctx);
+/* Switch the stream later calls enqueue on (the workspace is not copied). */
+int cs_set_stream(cs_ctx *ctx, void *hip_stream);
+/* Message of the last failed call on this context ("" if none). */
+const char *cs_last_error(const cs_ctx *ctx);
+
+/*
+ * Analysed vectors a = O s_x of every pixel (Sec. 2; the patch s_x of Sec. 3.1
+ * is the gray patch, multiplied element-wise by the Gaussian mask
+ * w_t = exp(-(u^2+v^2)/(2 mask_sigma^2)) and normalised to zero mean and unit
+ * norm; a patch of zero norm gives s = 0).  The patch is formed in FP64; the
+ * contraction runs on MFMA in `precision` with FP32 accumulation.
+ *   rgb    device, 3*H*W float32         omega  device, k*n float32
+ *   alpha  device out, N*k float32, pixel-major (alpha[x*k + j])
+ * Errors: CS_ERR_ARG for null pointers, even p, p outside 3..15, H or W < h+1,
+ * k outside 1..256, mask_sigma <= 0, unknown precision.
+ */
+int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                       const float *omega, int k, int precision, float *alpha);
+
+/*
+ * Exact co-support threshold tau = frac * median{|a_j(x)|} over all N*k
+ * entries, the median being the entry of rank floor((N*k-1)/2) in ascending
+ * order of the exact (FP64) analysed vectors.  The threshold replaces the
+ * exact-zero test of the Sec. 2 co-support definition.  `alpha` must be the
+ * output of cs_analyze_patches for the same inputs and precision; entries whose
+ * rounded value lies within the proven error bound of the selected median are
+ * recomputed in FP64, so tau equals the FP64 value bit for bit.
+ *   tau_out host out.  Synchronises the stream (returns a host value).
+ * Errors: as cs_analyze_patches, plus CS_ERR_ARG for frac < 0 or NaN.
+ */
+int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                  const float *omega, int k, int precision, const float *alpha, double frac,
+                  double *tau_out);
+
+typedef struct {
+    int64_t recomputed; /* entries decided by the FP64 recompute          */
+    double max_margin;  /* largest per-row margin used                      */
+} cs_cosupport_stats;
+
+/*
+ * Co-support masks (Sec. 2 co-support definition with threshold tau):
+ * bit j of pixel x is 1 iff |a_j(x)| <= tau for the exact (FP64) a.  The
+ * analysed vectors are recomputed on MFMA in `precision` inside the call;
+ * every entry whose rounded |a| lies within `margin` of tau is recomputed in
+ * FP64 (the library's only FP64 contraction) and decided exactly.
+ * margin < 0 selects the proven per-row error bound of the precision, which
+ * makes the masks equal to the FP64 masks bit for bit; margin >= 0 is an
+ * absolute margin (entries outside it are decided by the rounded value).
+ *   masks  device out, N*ceil(k/64) uint64
+ *   stats  host out or NULL; non-NULL synchronises the stream.
+ * Errors: as cs_analyze_patches, plus CS_ERR_ARG for tau < 0 or NaN.
+ */
+int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                 const float *omega, int k, int precision, double tau, double margin,
+                 uint64_t *masks, cs_cosupport_stats *stats);
+
+/*
+ * Texture similarity (Sec. 2, TSM definition): out[a*nb + b] = number of
+ * indices j < k in exactly one of the co-supports A[a] and B[b] (the Hamming
+ * distance of the masks; bits at j >= k are ignored).
+ *   A device, na*ceil(k/64) uint64; B device, nb*ceil(k/64); out device, na*nb int32.
+ * Errors: CS_ERR_ARG for null pointers with nonzero counts, k outside 1..256,
+ * negative counts.
+ */
+int cs_texture_similarity(cs_ctx *ctx, const uint64_t *A, int64_t na, const uint64_t *B,
+                          int64_t nb, int k, int32_t *out);
+
+typedef struct {
+    double alpha_rho;    /* spatial bandwidth scale (Sec. 3.1 sets 1.3)               */
+    double sigma_c;      /* colour kernel standard deviation, RGB units (0.05)        */
+    double beta_scale;   /* b in beta_i(x) = b * rho_i(x) (beta proportional to rho)  */
+    double rho_floor_px; /* rho_i(x) = alpha_rho * max(d_i(x), rho_floor_px)          */
+    int normalise;       /* 1: subtract log sum_i exp l_i(x) (labels normalise)       */
+} cs_loglik_params;
+
+/*
+ * Per-pixel, per-label log-likelihood of the supervised data term
+ * (Sec. 3.1 Parzen sum; Sec. 3.2 data term f_i = -l_i):
+ *   l_i(x) = log( 1/m_i * sum_{y in S_i} N2(x; y, rho_i(x)^2) * N3(I(x); I(y), sigma_c^2)
+ *                                        * exp(-TSM(x, y) / beta_i(x)) )
+ * where S_i are the samples with label i (m_i = |S_i|), rho_i(x) = alpha_rho *
+ * max(d_i(x), rho_floor_px) with d_i(x) the exact Euclidean distance from x to
+ * the nearest sample of label i, beta_i(x) = beta_scale * rho_i(x), N2/N3 are
+ * normalised isotropic Gaussians, and each sample's colour, position and mask
+ * are those of its pixel.  Computed in FP32 with log-sum-exp accumulation.
+ *   rgb           device, 3*H*W float32
+ *   masks         device, N*ceil(k/64) uint64 (co-supports of every pixel)
+ *   sample_pix    device, M int32 linear pixel indices (0..N-1)
+ *   sample_label  device, M int32 labels (0..L-1), 1 <= L <= 64
+ *   prm           host
+ *   pix_subset    device, n_subset int32 pixel indices, or NULL for all N pixels
+ *   loglik        device out, (n_subset or N) * L float32, loglik[r*L + i]
+ *                 (may be NULL when pix_subset is non-NULL and n_subset is 0)
+ * Synchronises once after sorting the samples by label (to check labels).
+ * Errors: CS_ERR_ARG (null pointers, sizes, prm values <= 0, sample pixel or
+ * label out of range), CS_ERR_EMPTY_LABEL when some label has no sample.
+ */
+int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
+                    const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
+                    const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
+                    float *loglik);
+
+/* Kernel timing on the context stream (HIP events around each launch of the
+ * named kernel).  cs_profile_enable(ctx, 1) starts recording and clears totals;
+ * cs_profile_read synchronises and returns the summed milliseconds and launch
+ * count of kernel `name` ("parzen", "analyze", "edt", ...). */
+int cs_profile_enable(cs_ctx *ctx, int on);
+int cs_profile_read(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

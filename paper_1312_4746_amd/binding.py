@@ -1,0 +1,240 @@
+"""ctypes binding of libcosparse.so.  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libcosparse.so")
+
+CS_OK = 0
+CS_ERR_ARG = 1
+CS_ERR_EMPTY_LABEL = 2
+CS_ERR_HIP = 3
+CS_ERR_NOMEM = 4
+CS_FP32 = 0
+CS_BF16 = 1
+
+_PREC = {"fp32": CS_FP32, "bf16": CS_BF16, CS_FP32: CS_FP32, CS_BF16: CS_BF16}
+
+# Every entry point the header declares, with (restype, argtypes).
+_P, _I, _I64, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+
+
+class _LoglikParamsC(ctypes.Structure):
+    _fields_ = [("alpha_rho", ctypes.c_double), ("sigma_c", ctypes.c_double),
+                ("beta_scale", ctypes.c_double), ("rho_floor_px", ctypes.c_double),
+                ("normalise", ctypes.c_int)]
+
+
+class _CosupportStatsC(ctypes.Structure):
+    _fields_ = [("recomputed", ctypes.c_int64), ("max_margin", ctypes.c_double)]
+
+
+SIGNATURES = {
+    "cs_create": (_I, [ctypes.POINTER(_P), _I, _P]),
+    "cs_destroy": (_I, [_P]),
+    "cs_set_stream": (_I, [_P, _P]),
+    "cs_last_error": (ctypes.c_char_p, [_P]),
+    "cs_analyze_patches": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P]),
+    "cs_tau_median": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, ctypes.POINTER(_D)]),
+    "cs_cosupport": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _D, _D, _P,
+                          ctypes.POINTER(_CosupportStatsC)]),
+    "cs_texture_similarity": (_I, [_P, _P, _I64, _P, _I64, _I, _P]),
+    "cs_label_loglik": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, _I64, _I,
+                             ctypes.POINTER(_LoglikParamsC), _P, _I64, _P]),
+    "cs_profile_enable": (_I, [_P, _I]),
+    "cs_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+}
+
+_lib = None
+
+
+class CosparseError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cosparse error {code}: {msg}")
+        self.code = code
+
+
+def library_path() -> str:
+    return _SO
+
+
+def lib():
+    """Load libcosparse.so; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        raise RuntimeError(f"{_SO} is missing: build it with __graft_entry__.build() "
+                           "(python paper_1312_4746_amd/build.py)")
+    L = ctypes.CDLL(_SO)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class LoglikParams:
+    alpha_rho: float = 1.3
+    sigma_c: float = 0.05
+    beta_scale: float = 1.0
+    rho_floor_px: float = 1.0
+    normalise: bool = False
+
+    def c(self) -> _LoglikParamsC:
+        return _LoglikParamsC(self.alpha_rho, self.sigma_c, self.beta_scale, self.rho_floor_px,
+                              int(bool(self.normalise)))
+
+
+class Context:
+    """One library context on one device; calls enqueue on torch's current
+    stream of that device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self._h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(device).cuda_stream
+        rc = lib().cs_create(ctypes.byref(self._h), device, ctypes.c_void_p(stream))
+        if rc != CS_OK:
+            raise CosparseError(rc, "cs_create failed")
+
+    def close(self):
+        if self._h:
+            lib().cs_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers --------------------------------------------------------
+    def _sync_stream(self):
+        lib().cs_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _check(self, rc: int):
+        if rc != CS_OK:
+            raise CosparseError(rc, lib().cs_last_error(self._h).decode())
+
+    def _dev(self, t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    # -- C-ABI calls ----------------------------------------------------
+    def analyze_patches(self, rgb: torch.Tensor, p: int, mask_sigma: float, omega: torch.Tensor,
+                        precision="fp32", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(omega, torch.float32, "omega")
+        _, H, W = rgb.shape
+        k = omega.shape[0]
+        if omega.shape[1] != p * p:
+            raise ValueError("omega must be k x p*p")
+        if out is None:
+            out = torch.empty((H * W, k), dtype=torch.float32, device=rgb.device)
+        self._dev(out, torch.float32, "alpha")
+        self._sync_stream()
+        self._check(lib().cs_analyze_patches(self._h, _ptr(rgb), H, W, p, float(mask_sigma),
+                                             _ptr(omega), k, _PREC[precision], _ptr(out)))
+        return out
+
+    def tau_median(self, rgb, p, mask_sigma, omega, alpha, frac=0.1, precision="fp32") -> float:
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(omega, torch.float32, "omega")
+        self._dev(alpha, torch.float32, "alpha")
+        _, H, W = rgb.shape
+        k = omega.shape[0]
+        if alpha.numel() != H * W * k:
+            raise ValueError("alpha must hold H*W*k entries")
+        tau = ctypes.c_double()
+        self._sync_stream()
+        self._check(lib().cs_tau_median(self._h, _ptr(rgb), H, W, p, float(mask_sigma), _ptr(omega),
+                                        k, _PREC[precision], _ptr(alpha), float(frac),
+                                        ctypes.byref(tau)))
+        return tau.value
+
+    def cosupport(self, rgb, p, mask_sigma, omega, tau, margin=-1.0, precision="fp32",
+                  out: Optional[torch.Tensor] = None, stats: bool = False):
+        """Masks as an int64 tensor (N, ceil(k/64)) holding the uint64 bit
+        patterns; with stats=True returns (masks, {recomputed, max_margin})."""
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(omega, torch.float32, "omega")
+        _, H, W = rgb.shape
+        k = omega.shape[0]
+        if out is None:
+            out = torch.empty((H * W, (k + 63) // 64), dtype=torch.int64, device=rgb.device)
+        self._dev(out, torch.int64, "masks")
+        st = _CosupportStatsC()
+        self._sync_stream()
+        self._check(lib().cs_cosupport(self._h, _ptr(rgb), H, W, p, float(mask_sigma), _ptr(omega),
+                                       k, _PREC[precision], float(tau), float(margin), _ptr(out),
+                                       ctypes.byref(st) if stats else None))
+        if stats:
+            return out, {"recomputed": int(st.recomputed), "max_margin": float(st.max_margin)}
+        return out
+
+    def texture_similarity(self, A: torch.Tensor, B: torch.Tensor, k: int,
+                           out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._dev(A, torch.int64, "A")
+        self._dev(B, torch.int64, "B")
+        na, nb = A.shape[0], B.shape[0]
+        if out is None:
+            out = torch.empty((na, nb), dtype=torch.int32, device=A.device)
+        self._dev(out, torch.int32, "out")
+        self._sync_stream()
+        self._check(lib().cs_texture_similarity(self._h, _ptr(A), na, _ptr(B), nb, k, _ptr(out)))
+        return out
+
+    def label_loglik(self, rgb, masks, k: int, sample_pix, sample_label, L: int,
+                     params: Optional[LoglikParams] = None, pix_subset=None,
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(masks, torch.int64, "masks")
+        self._dev(sample_pix, torch.int32, "sample_pix")
+        self._dev(sample_label, torch.int32, "sample_label")
+        _, H, W = rgb.shape
+        params = params or LoglikParams()
+        if pix_subset is not None:
+            self._dev(pix_subset, torch.int32, "pix_subset")
+        npix = H * W if pix_subset is None else pix_subset.numel()
+        if out is None:
+            out = torch.empty((npix, L), dtype=torch.float32, device=rgb.device)
+        self._dev(out, torch.float32, "loglik")
+        prm = params.c()
+        subset_ptr = _ptr(pix_subset)
+        if pix_subset is not None and pix_subset.numel() == 0:
+            # an empty subset is (non-null pointer, count 0); NULL means every pixel
+            subset_ptr = ctypes.c_void_p(sample_pix.data_ptr())
+        self._sync_stream()
+        self._check(lib().cs_label_loglik(self._h, _ptr(rgb), H, W, _ptr(masks), k,
+                                          _ptr(sample_pix), _ptr(sample_label), sample_pix.numel(),
+                                          L, ctypes.byref(prm), subset_ptr,
+                                          0 if pix_subset is None else pix_subset.numel(),
+                                          _ptr(out) if out.numel() else None))
+        return out
+
+    def profile_enable(self, on: bool = True):
+        self._check(lib().cs_profile_enable(self._h, int(on)))
+
+    def profile_read(self, name: str):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(lib().cs_profile_read(self._h, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,531 @@
+// Host layer of the co-sparse data-term library: context, argument checks,
+// device workspace, kernel-event timing and the order of launches behind each
+// C-ABI call declared in include/cosparse.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cosparse.h"
+#include "cs_internal.h"
+
+using namespace cs;
+
+struct cs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 0;
+    std::string err;
+    // growable device workspace (carved per call) and a separate candidate buffer
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    char *cand = nullptr;
+    size_t cand_bytes = 0;
+    // pinned host staging for small device-to-host results
+    char *pinned = nullptr;
+    // Gaussian patch mask of the last (p, sigma)
+    double *wmask = nullptr;
+    int wmask_p = 0;
+    double wmask_sigma = 0.0;
+    // kernel-event timing
+    bool prof = false;
+    struct Span {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<double, int64_t>> totals;
+};
+
+namespace {
+
+constexpr size_t kPinnedBytes = 4096;
+
+int fail(cs_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ctx, CS_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+LaunchCtx lc_of(const cs_ctx *c) { return LaunchCtx{c->stream, c->num_cu}; }
+
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+int ensure_ws(cs_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->ws_bytes) return CS_OK;
+    const size_t want = std::max(bytes, ctx->ws_bytes + ctx->ws_bytes / 4);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (ctx->ws) HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    if (hipMalloc((void **)&ctx->ws, want) != hipSuccess) {
+        ctx->ws = nullptr;
+        return fail(ctx, CS_ERR_NOMEM, "device workspace of %zu bytes could not be allocated", want);
+    }
+    ctx->ws_bytes = want;
+    return CS_OK;
+}
+
+int ensure_cand(cs_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->cand_bytes) return CS_OK;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (ctx->cand) HIP_TRY(hipFree(ctx->cand));
+    ctx->cand = nullptr;
+    ctx->cand_bytes = 0;
+    if (hipMalloc((void **)&ctx->cand, bytes) != hipSuccess) {
+        ctx->cand = nullptr;
+        return fail(ctx, CS_ERR_NOMEM, "candidate buffer of %zu bytes could not be allocated", bytes);
+    }
+    ctx->cand_bytes = bytes;
+    return CS_OK;
+}
+
+// HIP events around one launch when timing is on.
+struct Timed {
+    cs_ctx *c;
+    const char *name;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(cs_ctx *ctx, const char *nm) : c(ctx), name(nm) {
+        if (!c->prof) return;
+        a = take();
+        b = take();
+        if (a) hipEventRecord(a, c->stream);
+    }
+    hipEvent_t take() {
+        if (!c->pool.empty()) {
+            hipEvent_t e = c->pool.back();
+            c->pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    ~Timed() {
+        if (!c->prof || !a || !b) return;
+        hipEventRecord(b, c->stream);
+        c->spans.push_back({name, a, b});
+    }
+};
+
+// Gaussian mask w_t = exp(-(u^2+v^2) / (2 sigma^2)) of Sec. 3.1, host FP64,
+// uploaded once per (p, sigma).
+int ensure_mask(cs_ctx *ctx, int p, double sigma) {
+    if (ctx->wmask && ctx->wmask_p == p && ctx->wmask_sigma == sigma) return CS_OK;
+    double w[15 * 15];
+    const int h = (p - 1) / 2;
+    for (int u = -h; u <= h; ++u)
+        for (int v = -h; v <= h; ++v) {
+            const double r2 = (double)(u * u + v * v);
+            w[(u + h) * p + (v + h)] = std::exp(-r2 / (2.0 * sigma * sigma));
+        }
+    if (!ctx->wmask) HIP_TRY(hipMalloc((void **)&ctx->wmask, sizeof(double) * 15 * 15));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(ctx->wmask, w, sizeof(double) * p * p, hipMemcpyHostToDevice));
+    ctx->wmask_p = p;
+    ctx->wmask_sigma = sigma;
+    return CS_OK;
+}
+
+int check_patch_args(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                     const float *omega, int k, int precision) {
+    if (!rgb || !omega) return fail(ctx, CS_ERR_ARG, "rgb and omega must be non-null");
+    if (p < 3 || p > 15 || (p % 2) == 0) return fail(ctx, CS_ERR_ARG, "p must be odd in 3..15 (got %d)", p);
+    const int h = (p - 1) / 2;
+    if (H < h + 1 || W < h + 1)
+        return fail(ctx, CS_ERR_ARG, "image %dx%d too small for %dx%d patches", W, H, p, p);
+    if ((int64_t)H * W > ((int64_t)1 << 31) - 1)
+        return fail(ctx, CS_ERR_ARG, "image of %lld pixels exceeds 2^31-1", (long long)H * W);
+    if (H > 65535) return fail(ctx, CS_ERR_ARG, "H must be <= 65535");
+    if (k < 1 || k > kMaxK) return fail(ctx, CS_ERR_ARG, "k must be in 1..%d (got %d)", kMaxK, k);
+    if (!(mask_sigma > 0.0) || !std::isfinite(mask_sigma))
+        return fail(ctx, CS_ERR_ARG, "mask_sigma must be positive and finite");
+    if (precision != CS_FP32 && precision != CS_BF16)
+        return fail(ctx, CS_ERR_ARG, "unknown precision %d", precision);
+    return CS_OK;
+}
+
+// Coefficient of the proven bound |a_rounded - a| <= coef * ||O_j||_2 (unit-norm patch):
+// FP32: s and the accumulation each contribute at most (n + 2) unit roundoffs, doubled
+// to allow round-toward-zero accumulation; BF16: both operands rounded to 8-bit
+// significands (2^-8 each), the FP32 rounding of s, and the FP32 accumulation.
+double margin_coef(int precision, int n) {
+    const double u32 = std::ldexp(1.0, -24);
+    if (precision == CS_BF16) return std::ldexp(1.0, -7) + std::ldexp(1.0, -15) + 2.0 * (n + 4) * u32;
+    return 2.0 * (n + 4) * u32;
+}
+
+int n_pad_of(int n) { return (n + 15) / 16 * 16; }
+
+}  // namespace
+
+extern "C" {
+
+int cs_create(cs_ctx **out, int device, void *hip_stream) {
+    if (!out) return CS_ERR_ARG;
+    *out = nullptr;
+    cs_ctx *ctx = new (std::nothrow) cs_ctx();
+    if (!ctx) return CS_ERR_NOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->pinned, kPinnedBytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete ctx;
+        return CS_ERR_HIP;
+    }
+    *out = ctx;
+    return CS_OK;
+}
+
+int cs_destroy(cs_ctx *ctx) {
+    if (!ctx) return CS_ERR_ARG;
+    hipStreamSynchronize(ctx->stream);
+    for (auto &s : ctx->spans) {
+        hipEventDestroy(s.a);
+        hipEventDestroy(s.b);
+    }
+    for (auto e : ctx->pool) hipEventDestroy(e);
+    if (ctx->ws) hipFree(ctx->ws);
+    if (ctx->cand) hipFree(ctx->cand);
+    if (ctx->wmask) hipFree(ctx->wmask);
+    if (ctx->pinned) hipHostFree(ctx->pinned);
+    delete ctx;
+    return CS_OK;
+}
+
+int cs_set_stream(cs_ctx *ctx, void *hip_stream) {
+    if (!ctx) return CS_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return CS_OK;
+}
+
+const char *cs_last_error(const cs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                       const float *omega, int k, int precision, float *alpha) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
+    if (rc) return rc;
+    if (!alpha) return fail(ctx, CS_ERR_ARG, "alpha must be non-null");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
+    AnalyzeArgs a{};
+    a.rgb = rgb;
+    a.H = H;
+    a.W = W;
+    a.p = p;
+    a.n = p * p;
+    a.n_pad = n_pad_of(a.n);
+    a.k = k;
+    a.wmask = ctx->wmask;
+    a.omega = omega;
+    a.alpha = alpha;
+    Timed t(ctx, "analyze");
+    HIP_TRY(launch_analyze(lc_of(ctx), a, precision));
+    return CS_OK;
+}
+
+int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                 const float *omega, int k, int precision, double tau, double margin,
+                 uint64_t *masks, cs_cosupport_stats *stats) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
+    if (rc) return rc;
+    if (!masks) return fail(ctx, CS_ERR_ARG, "masks must be non-null");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ctx, CS_ERR_ARG, "tau must be finite and >= 0");
+    if (std::isnan(margin) || std::isinf(margin)) return fail(ctx, CS_ERR_ARG, "margin must be finite");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
+    Carve cv;
+    const size_t o_tin = cv.take(sizeof(float) * k), o_tout = cv.take(sizeof(float) * k);
+    const size_t o_marg = cv.take(sizeof(double) * k), o_max = cv.take(sizeof(double));
+    const size_t o_cnt = cv.take(sizeof(unsigned long long));
+    if ((rc = ensure_ws(ctx, cv.off))) return rc;
+    float *t_in = (float *)(ctx->ws + o_tin), *t_out = (float *)(ctx->ws + o_tout);
+    double *marg = (double *)(ctx->ws + o_marg), *mmax = (double *)(ctx->ws + o_max);
+    unsigned long long *cnt = (unsigned long long *)(ctx->ws + o_cnt);
+    const LaunchCtx lc = lc_of(ctx);
+    const int n = p * p;
+    {
+        Timed t(ctx, "thresholds");
+        HIP_TRY(launch_thresholds(lc, omega, k, n, tau, margin, margin_coef(precision, n), t_in, t_out,
+                                  marg, mmax));
+    }
+    HIP_TRY(launch_fill_u32(lc, (unsigned int *)cnt, 2, 0u));
+    AnalyzeArgs a{};
+    a.rgb = rgb;
+    a.H = H;
+    a.W = W;
+    a.p = p;
+    a.n = n;
+    a.n_pad = n_pad_of(n);
+    a.k = k;
+    a.wmask = ctx->wmask;
+    a.omega = omega;
+    a.masks = masks;
+    a.t_in = t_in;
+    a.t_out = t_out;
+    a.tau = tau;
+    a.recomputed = cnt;
+    {
+        Timed t(ctx, "cosupport");
+        HIP_TRY(launch_analyze(lc, a, precision));
+    }
+    if (stats) {
+        HIP_TRY(hipMemcpyAsync(ctx->pinned, cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipMemcpyAsync(ctx->pinned + 8, mmax, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        unsigned long long c;
+        double m;
+        std::memcpy(&c, ctx->pinned, 8);
+        std::memcpy(&m, ctx->pinned + 8, 8);
+        stats->recomputed = (int64_t)c;
+        stats->max_margin = m;
+    }
+    return CS_OK;
+}
+
+int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                  const float *omega, int k, int precision, const float *alpha, double frac,
+                  double *tau_out) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
+    if (rc) return rc;
+    if (!alpha || !tau_out) return fail(ctx, CS_ERR_ARG, "alpha and tau_out must be non-null");
+    if (!(frac >= 0.0) || !std::isfinite(frac)) return fail(ctx, CS_ERR_ARG, "frac must be finite and >= 0");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
+    const int64_t count = (int64_t)H * W * k;
+    const int n = p * p;
+    Carve cv;
+    const size_t o_hist = cv.take(sizeof(unsigned int) * 2048);
+    const size_t o_st = cv.take(sizeof(TauState));
+    const size_t o_marg = cv.take(sizeof(double) * k), o_max = cv.take(sizeof(double));
+    if ((rc = ensure_ws(ctx, cv.off))) return rc;
+    unsigned int *hist = (unsigned int *)(ctx->ws + o_hist);
+    TauState *st = (TauState *)(ctx->ws + o_st);
+    double *marg = (double *)(ctx->ws + o_marg), *mmax = (double *)(ctx->ws + o_max);
+    const LaunchCtx lc = lc_of(ctx);
+    int64_t cap = (int64_t)std::min<int64_t>(count, (int64_t)1 << 20);
+    if ((rc = ensure_cand(ctx, (size_t)cap * 16))) return rc;
+    {
+        Timed t(ctx, "tau_select");
+        HIP_TRY(launch_thresholds(lc, omega, k, n, 0.0, -1.0, margin_coef(precision, n), nullptr,
+                                  nullptr, marg, mmax));
+        HIP_TRY(tau_select_float(lc, alpha, count, hist, st));
+        HIP_TRY(tau_gather(lc, alpha, count, mmax, st, (int64_t *)ctx->cand, cap));
+    }
+    TauState hs;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, st, sizeof(TauState), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    std::memcpy(&hs, ctx->pinned, sizeof(TauState));
+    if ((int64_t)hs.ncand > cap) {
+        cap = (int64_t)hs.ncand;
+        if ((rc = ensure_cand(ctx, (size_t)cap * 16))) return rc;
+        HIP_TRY(tau_reset_gather(lc, st));
+        HIP_TRY(tau_gather(lc, alpha, count, mmax, st, (int64_t *)ctx->cand, cap));
+        HIP_TRY(hipMemcpyAsync(ctx->pinned, st, sizeof(TauState), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        std::memcpy(&hs, ctx->pinned, sizeof(TauState));
+        if ((int64_t)hs.ncand > cap) return fail(ctx, CS_ERR_HIP, "candidate count changed between passes");
+    }
+    int64_t *cand = (int64_t *)ctx->cand;
+    double *vals = (double *)(ctx->cand + (size_t)cap * 8);
+    {
+        Timed t(ctx, "tau_exact");
+        HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, (int64_t)hs.ncand, vals,
+                           frac, st));
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, st, sizeof(TauState), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    std::memcpy(&hs, ctx->pinned, sizeof(TauState));
+    if (std::isnan(hs.median))
+        return fail(ctx, CS_ERR_HIP, "exact median outside the candidate window (error bound violated)");
+    *tau_out = hs.tau;
+    return CS_OK;
+}
+
+int cs_texture_similarity(cs_ctx *ctx, const uint64_t *A, int64_t na, const uint64_t *B,
+                          int64_t nb, int k, int32_t *out) {
+    if (!ctx) return CS_ERR_ARG;
+    if (na < 0 || nb < 0) return fail(ctx, CS_ERR_ARG, "counts must be >= 0");
+    if (k < 1 || k > kMaxK) return fail(ctx, CS_ERR_ARG, "k must be in 1..%d (got %d)", kMaxK, k);
+    if ((na && !A) || (nb && !B) || (na && nb && !out))
+        return fail(ctx, CS_ERR_ARG, "null pointer with nonzero count");
+    HIP_TRY(hipSetDevice(ctx->device));
+    Timed t(ctx, "tsm");
+    HIP_TRY(launch_tsm(lc_of(ctx), A, na, B, nb, k, out));
+    return CS_OK;
+}
+
+int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
+                    const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
+                    const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
+                    float *loglik) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!rgb || !masks || !sample_pix || !sample_label || !prm)
+        return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    if (!loglik && !(pix_subset && n_subset == 0))
+        return fail(ctx, CS_ERR_ARG, "loglik must be non-null unless the pixel subset is empty");
+    if (H < 1 || W < 1 || H > 32767 || W > 32767)
+        return fail(ctx, CS_ERR_ARG, "H and W must be in 1..32767");
+    if (k < 1 || k > kMaxK) return fail(ctx, CS_ERR_ARG, "k must be in 1..%d (got %d)", kMaxK, k);
+    if (L < 1 || L > kMaxLabels) return fail(ctx, CS_ERR_ARG, "L must be in 1..%d (got %d)", kMaxLabels, L);
+    if (M < 1 || M > (((int64_t)1 << 31) - 1)) return fail(ctx, CS_ERR_ARG, "M must be in 1..2^31-1");
+    auto pos = [](double v) { return v > 0.0 && std::isfinite(v); };
+    if (!pos(prm->alpha_rho) || !pos(prm->sigma_c) || !pos(prm->beta_scale) || !pos(prm->rho_floor_px))
+        return fail(ctx, CS_ERR_ARG, "alpha_rho, sigma_c, beta_scale and rho_floor_px must be positive and finite");
+    const int64_t N = (int64_t)H * W;
+    const int64_t npix = pix_subset ? n_subset : N;
+    if (npix < 0) return fail(ctx, CS_ERR_ARG, "n_subset must be >= 0");
+    const int64_t tiles = (npix + 63) / 64;
+    if (tiles * L > (((int64_t)1 << 31) - 1)) return fail(ctx, CS_ERR_ARG, "too many pixels x labels");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int nblocks = (int)((M + 255) / 256);
+    Carve cv;
+    const size_t o_bc = cv.take(sizeof(int32_t) * (size_t)L * nblocks);
+    const size_t o_tf = cv.take(sizeof(int32_t) * (L + 1));
+    const size_t o_cnt = cv.take(sizeof(unsigned int) * 2);
+    const size_t o_rec = cv.take(sizeof(SampleRec) * (size_t)M);
+    const size_t o_seed = cv.take((size_t)L * N);
+    const size_t o_col = cv.take(sizeof(int32_t) * (size_t)L * N);
+    const size_t o_d2 = cv.take(sizeof(int32_t) * (size_t)L * N);
+    const size_t o_nn = cv.take(sizeof(int32_t) * (size_t)L * N);
+    int rc = ensure_ws(ctx, cv.off);
+    if (rc) return rc;
+    int32_t *bc = (int32_t *)(ctx->ws + o_bc), *tf = (int32_t *)(ctx->ws + o_tf);
+    unsigned int *cnt = (unsigned int *)(ctx->ws + o_cnt);
+    SampleRec *recs = (SampleRec *)(ctx->ws + o_rec);
+    uint8_t *seeds = (uint8_t *)(ctx->ws + o_seed);
+    int32_t *colrow = (int32_t *)(ctx->ws + o_col), *d2 = (int32_t *)(ctx->ws + o_d2),
+            *nearest = (int32_t *)(ctx->ws + o_nn);
+    const LaunchCtx lc = lc_of(ctx);
+
+    {
+        Timed t(ctx, "samples");
+        HIP_TRY(launch_fill_u32(lc, (unsigned int *)tf, (size_t)L + 1, 0u));
+        HIP_TRY(launch_sample_count(lc, sample_label, sample_pix, M, L, N, bc, tf, nblocks));
+        if (pix_subset) HIP_TRY(launch_check_pix(lc, pix_subset, npix, N, tf + L));
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, tf, sizeof(int32_t) * (L + 1), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    int32_t counts[kMaxLabels + 1];
+    std::memcpy(counts, ctx->pinned, sizeof(int32_t) * (L + 1));
+    if (counts[L] & 1) return fail(ctx, CS_ERR_ARG, "a sample label or pixel index is out of range");
+    if (counts[L] & 2) return fail(ctx, CS_ERR_ARG, "a pixel index of pix_subset is out of range");
+    for (int l = 0; l < L; ++l)
+        if (counts[l] == 0) return fail(ctx, CS_ERR_EMPTY_LABEL, "label %d has no scribble sample", l);
+    if (npix == 0) return CS_OK;
+
+    {
+        Timed t(ctx, "samples");
+        HIP_TRY(launch_fill_u8(lc, seeds, (size_t)L * N, 0));
+        HIP_TRY(launch_sample_scatter(lc, sample_label, sample_pix, M, L, H, W, rgb, masks, k, bc,
+                                      nblocks, recs, seeds));
+    }
+    {
+        Timed t(ctx, "edt");
+        HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest));
+    }
+    ParzenArgs pa{};
+    pa.rgb = rgb;
+    pa.masks = masks;
+    pa.recs = recs;
+    pa.d2 = d2;
+    pa.nearest = nearest;
+    pa.subset = pix_subset;
+    pa.loglik = loglik;
+    pa.work_counter = cnt;
+    pa.fixups = cnt + 1;
+    pa.H = H;
+    pa.W = W;
+    pa.L = L;
+    pa.k = k;
+    pa.nw32 = (k + 31) / 32;
+    pa.npix = npix;
+    pa.tiles = (int)tiles;
+    pa.alpha_rho = prm->alpha_rho;
+    pa.sigma_c = prm->sigma_c;
+    pa.beta_scale = prm->beta_scale;
+    pa.rho_floor = prm->rho_floor_px;
+    const double pi = 3.14159265358979323846;
+    pa.seg_off[0] = 0;
+    for (int l = 0; l < L; ++l) {
+        pa.seg_off[l + 1] = pa.seg_off[l] + counts[l];
+        pa.kconst[l] = -std::log((double)counts[l]) - std::log(2.0 * pi) -
+                       1.5 * std::log(2.0 * pi * prm->sigma_c * prm->sigma_c);
+        pa.label_order[l] = l;
+    }
+    std::stable_sort(pa.label_order, pa.label_order + L,
+                     [&](int x, int y) { return counts[x] > counts[y]; });
+    HIP_TRY(launch_fill_u32(lc, cnt, 2, 0u));
+    {
+        Timed t(ctx, "parzen");
+        HIP_TRY(launch_parzen(lc, pa));
+    }
+    if (prm->normalise) {
+        Timed t(ctx, "normalise");
+        HIP_TRY(launch_normalise(lc, loglik, npix, L));
+    }
+    return CS_OK;
+}
+
+int cs_profile_enable(cs_ctx *ctx, int on) {
+    if (!ctx) return CS_ERR_ARG;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (auto &s : ctx->spans) {
+        ctx->pool.push_back(s.a);
+        ctx->pool.push_back(s.b);
+    }
+    ctx->spans.clear();
+    ctx->totals.clear();
+    ctx->prof = on != 0;
+    return CS_OK;
+}
+
+int cs_profile_read(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches) {
+    if (!ctx || !name || !total_ms || !launches) return CS_ERR_ARG;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (auto &s : ctx->spans) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, s.a, s.b));
+        auto &t = ctx->totals[s.name];
+        t.first += ms;
+        t.second += 1;
+        ctx->pool.push_back(s.a);
+        ctx->pool.push_back(s.b);
+    }
+    ctx->spans.clear();
+    auto it = ctx->totals.find(name);
+    *total_ms = it == ctx->totals.end() ? 0.0 : it->second.first;
+    *launches = it == ctx->totals.end() ? 0 : it->second.second;
+    return CS_OK;
+}
+
+}  // extern "C"

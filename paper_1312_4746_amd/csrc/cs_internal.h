@@ -1,0 +1,116 @@
+// Internal declarations shared by the host layer and the HIP kernels of the
+// co-sparse data-term library (gfx950).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace cs {
+
+// Pixels per analysis tile (one row segment of the image).
+constexpr int kTilePx = 64;
+// Words of a sample record (see SampleRec).
+constexpr int kRecWords = 16;
+// Maximum label count and co-support length handled by the kernels.
+constexpr int kMaxLabels = 64;
+constexpr int kMaxK = 256;
+
+// One scribble sample, gathered from its pixel, 64 bytes so that a wave
+// fetches it with one scalar load: x (column), y (row), r, g, b as float32
+// bit patterns, three unused words, then up to 8 32-bit co-support words.
+struct SampleRec {
+    uint32_t w[kRecWords];
+};
+
+struct LaunchCtx {
+    hipStream_t stream;
+    int num_cu;
+};
+
+// ---- analysis (k_analyze.hip) ----
+struct AnalyzeArgs {
+    const float *rgb;
+    int H, W, p, n, n_pad, k;
+    const double *wmask;  // n doubles, device
+    const float *omega;   // k x n
+    float *alpha;         // N x k or null
+    uint64_t *masks;      // N x ceil(k/64) or null
+    const float *t_in;    // k thresholds (|a| <= t_in: in)
+    const float *t_out;   // k thresholds (|a| > t_out: out)
+    double tau;
+    unsigned long long *recomputed;  // device counter or null
+};
+hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precision);
+
+// Per-row thresholds t_in/t_out = tau -/+ margin_j, rounded outward to float.
+// margin < 0 selects the proven bound coef * ||O_j||_2 + tiny; writes the
+// largest margin to *max_margin.
+hipError_t launch_thresholds(const LaunchCtx &lc, const float *omega, int k, int n, double tau,
+                             double margin, double coef, float *t_in, float *t_out,
+                             double *margins, double *max_margin);
+
+// ---- exact median of |alpha| (k_tau.hip) ----
+struct TauState {
+    unsigned long long rank0;     // target rank floor((count-1)/2)
+    unsigned long long rank;      // remaining rank inside the current prefix
+    unsigned int prefix;          // float bits selected so far
+    unsigned int pad0;
+    unsigned long long below;     // entries strictly below the candidate window
+    unsigned long long ncand;     // candidates found (may exceed capacity)
+    double lo, hi;                // candidate window on |alpha| (float values)
+    double median;                // exact FP64 median
+    double tau;                   // frac * median
+};
+hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t count,
+                            unsigned int *hist, TauState *st);
+hipError_t tau_reset_gather(const LaunchCtx &lc, TauState *st);
+hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
+                      const double *max_margin, TauState *st, int64_t *cand, int64_t cap);
+hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
+                      const double *wmask, const float *omega, int k, const int64_t *cand,
+                      int64_t ncand, double *vals, double frac, TauState *st);
+
+// ---- texture similarity (k_tsm.hip) ----
+hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const uint64_t *B,
+                      int64_t nb, int k, int32_t *out);
+
+// ---- samples, distance transform, Parzen sum (k_parzen.hip, k_edt.hip) ----
+hipError_t launch_sample_count(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
+                               int64_t M, int L, int64_t N, int32_t *block_counts,
+                               int32_t *totals_flags, int nblocks);
+hipError_t launch_sample_scatter(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
+                                 int64_t M, int L, int H, int W, const float *rgb,
+                                 const uint64_t *masks, int k, const int32_t *block_counts,
+                                 int nblocks, SampleRec *recs, uint8_t *seeds);
+hipError_t launch_check_pix(const LaunchCtx &lc, const int32_t *pix, int64_t n, int64_t N,
+                            int32_t *flags);
+hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, int L,
+                      int32_t *colrow, int32_t *d2, int32_t *nearest);
+
+struct ParzenArgs {
+    const float *rgb;
+    const uint64_t *masks;
+    const SampleRec *recs;
+    const int32_t *d2;       // L x N
+    const int32_t *nearest;  // L x N
+    const int32_t *subset;   // or null
+    float *loglik;
+    unsigned int *work_counter;
+    unsigned int *fixups;
+    int H, W, L, k, nw32;
+    int64_t npix;
+    int tiles;               // ceil(npix / 64)
+    double alpha_rho, sigma_c, beta_scale, rho_floor;
+    int seg_off[kMaxLabels + 1];
+    int label_order[kMaxLabels];
+    double kconst[kMaxLabels];  // -log m_i - log(2 pi) - 1.5 log(2 pi sigma_c^2)
+};
+hipError_t launch_parzen(const LaunchCtx &lc, const ParzenArgs &a);
+hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
+hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, unsigned int v);
+hipError_t launch_fill_u8(const LaunchCtx &lc, uint8_t *p, size_t count, uint8_t v);
+
+}  // namespace cs

@@ -1,0 +1,246 @@
+// Patch analysis on gfx950: normalised Gaussian-masked gray patches, the
+// contraction a = O s on MFMA, and the co-support threshold epilogue.
+//
+// Paper: Sec. 2 (analysed vector a = O s, co-support of zero entries, bias
+// and gain normalisation) and Sec. 3.1 (gray patch s_x centred at x, Gaussian
+// mask applied before normalisation).
+//
+// One workgroup (4 waves) owns a row segment of kTilePx = 64 pixels.  The
+// FP64 gray values of the segment and its halo are staged in LDS, every
+// pixel's patch s is formed in FP64 in LDS (this is the exact patch; its sums
+// run sequentially with no FMA contraction so that the FP64 recompute below is
+// reproducible bit for bit), and the contraction runs on MFMA with A = patches
+// (rows = pixels, from LDS) and B = O^T (columns = operator rows, read from
+// L2).  Each wave owns every fourth 16-row block of O and reuses each B
+// fragment for the four 16-pixel blocks of the tile.
+//
+// Output layout of the 16x16 MFMA tile: lane l, accumulator r holds
+// pixel 4*(l/16) + r of the block and operator row l%16 of the j-block, so one
+// wave ballot over a predicate on accumulator r yields four 16-bit co-support
+// pieces (one per pixel), which land directly in the packed mask words.
+//
+// Entries whose rounded |a| lies within the per-row margin of tau are
+// recomputed in FP64 from the exact patch in LDS and decided exactly.
+#pragma clang fp contract(off)
+
+#include "cs_internal.h"
+#include "cs_device.h"
+#include "../../include/cosparse.h"
+
+namespace cs {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int h = (a.p - 1) / 2;
+    const int n = a.n, np = a.n_pad, ss = a.n_pad + 1;
+    const int hw = kTilePx + 2 * h;
+    const int W64 = (a.k + 63) / 64;
+    double *gh = reinterpret_cast<double *>(smem);  // (2h+1) x hw gray halo
+    double *s = gh + (2 * h + 1) * hw;               // kTilePx x ss patches
+    double *nu = s + kTilePx * ss;                   // kTilePx norms
+    uint16_t *mk = reinterpret_cast<uint16_t *>(nu + kTilePx);  // kTilePx x 4*W64 pieces
+
+    const int row = blockIdx.y, c0 = blockIdx.x * kTilePx;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t N = (int64_t)a.H * a.W;
+    const int valid_px = min(kTilePx, a.W - c0);
+
+    // 1. FP64 gray halo of the segment.
+    const int ncols = valid_px + 2 * h;
+    for (int idx = tid; idx < (2 * h + 1) * hw; idx += 256) {
+        int rr = idx / hw, cc = idx - rr * hw;
+        double g = 0.0;
+        if (cc < ncols) {
+            int gr = reflect_idx(row - h + rr, a.H), gc = reflect_idx(c0 - h + cc, a.W);
+            g = gray64(a.rgb, N, (int64_t)gr * a.W + gc);
+        }
+        gh[idx] = g;
+    }
+    if (a.masks)
+        for (int idx = tid; idx < kTilePx * 4 * W64; idx += 256) mk[idx] = 0;
+    __syncthreads();
+
+    // 2. masked patch q_t = w_t g_t (zero for pixels past the row end and t >= n).
+    for (int idx = tid; idx < kTilePx * np; idx += 256) {
+        int i = idx / np, t = idx - i * np;
+        double q = 0.0;
+        if (i < valid_px && t < n) {
+            int u = t / a.p, v = t - u * a.p;
+            q = a.wmask[t] * gh[u * hw + i + v];
+        }
+        s[i * ss + t] = q;
+    }
+    __syncthreads();
+
+    // 3. zero mean and norm, sequential in t (one thread per pixel).
+    if (tid < kTilePx) {
+#pragma clang fp contract(off)
+        double *si = s + tid * ss;
+        double sum = 0.0;
+        for (int t = 0; t < n; ++t) sum = sum + si[t];
+        double mu = sum / (double)n;
+        for (int t = 0; t < n; ++t) si[t] = si[t] - mu;
+        double nu2 = 0.0;
+        for (int t = 0; t < n; ++t) nu2 = nu2 + si[t] * si[t];
+        nu[tid] = (nu2 == 0.0) ? 0.0 : sqrt(nu2);
+    }
+    __syncthreads();
+
+    // 4. unit norm (a zero-norm patch becomes s = 0).
+    for (int idx = tid; idx < kTilePx * n; idx += 256) {
+        int i = idx / n, t = idx - i * n;
+        double v = nu[i];
+        s[i * ss + t] = (v == 0.0) ? 0.0 : s[i * ss + t] / v;
+    }
+    __syncthreads();
+
+    // 5. a = O s on MFMA, one 16-row block of O per pass, four pixel blocks.
+    const int nblk_j = (a.k + 15) / 16;
+    unsigned long long nrecomp = 0;
+    for (int jb = wave; jb < nblk_j; jb += 4) {
+        f32x4 acc[4];
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int j = jb * 16 + (lane & 15);
+        const bool jv = j < a.k;
+        const float *om = a.omega + (int64_t)(jv ? j : 0) * n;
+        if (PREC == CS_FP32) {
+            for (int kb = 0; kb < np; kb += 4) {
+                const int t = kb + (lane >> 4);
+                const float b = (jv && t < n) ? om[t] : 0.f;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const float av = (float)s[(rb * 16 + (lane & 15)) * ss + t];
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[rb], 0, 0, 0);
+                }
+            }
+        } else {
+            for (int kb = 0; kb < np; kb += 16) {
+                const int t0 = kb + 4 * (lane >> 4);
+                s16x4 b;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) b[q] = bf16_rne((jv && t0 + q < n) ? om[t0 + q] : 0.f);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const double *sp = s + (rb * 16 + (lane & 15)) * ss + t0;
+                    s16x4 av;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) av[q] = bf16_rne((float)sp[q]);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b, acc[rb], 0, 0, 0);
+                }
+            }
+        }
+
+        // Epilogue: store a and/or decide the co-support bits.
+        const float tin = (a.masks && jv) ? a.t_in[j] : 0.f;
+        const float tout = (a.masks && jv) ? a.t_out[j] : 0.f;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int il = rb * 16 + 4 * (lane >> 4) + r;
+                const bool pv = il < valid_px;
+                const float v = acc[rb][r];
+                const int64_t pix = (int64_t)row * a.W + c0 + il;
+                if (a.alpha && pv && jv) a.alpha[pix * a.k + j] = v;
+                if (a.masks) {
+                    const float av = fabsf(v);
+                    bool in = av <= tin;
+                    const bool out = av > tout;
+                    const bool near = !in && !out && pv && jv;
+                    if (near) {
+                        const double ex = dot64(om, s + il * ss, n);
+                        in = fabs(ex) <= a.tau;
+                    }
+                    nrecomp += (unsigned long long)__popcll(__ballot(near));
+                    const unsigned long long bits = __ballot(in && pv && jv);
+                    if (lane < 4)
+                        mk[(rb * 16 + 4 * lane + r) * (4 * W64) + jb] =
+                            (uint16_t)((bits >> (16 * lane)) & 0xFFFFull);
+                }
+            }
+        }
+    }
+
+    if (a.masks) {
+        __syncthreads();
+        const uint64_t *mk64 = reinterpret_cast<const uint64_t *>(mk);
+        for (int idx = tid; idx < valid_px * W64; idx += 256) {
+            int i = idx / W64, w = idx - i * W64;
+            a.masks[((int64_t)row * a.W + c0 + i) * W64 + w] = mk64[i * W64 + w];
+        }
+        if (a.recomputed && lane == 0 && nrecomp) atomicAdd(a.recomputed, nrecomp);
+    }
+}
+
+hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precision) {
+    const int h = (a.p - 1) / 2;
+    const int hw = kTilePx + 2 * h;
+    const int W64 = (a.k + 63) / 64;
+    const size_t lds = sizeof(double) * ((size_t)(2 * h + 1) * hw + (size_t)kTilePx * (a.n_pad + 1) +
+                                         kTilePx) +
+                       sizeof(uint16_t) * (size_t)kTilePx * 4 * W64;
+    dim3 grid((a.W + kTilePx - 1) / kTilePx, a.H);
+    hipError_t e;
+    if (precision == CS_BF16) {
+        e = hipFuncSetAttribute((const void *)k_analyze<CS_BF16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_analyze<CS_BF16>, grid, dim3(256), lds, lc.stream, a);
+    } else {
+        e = hipFuncSetAttribute((const void *)k_analyze<CS_FP32>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_analyze<CS_FP32>, grid, dim3(256), lds, lc.stream, a);
+    }
+    return hipGetLastError();
+}
+
+// Per-row decision thresholds.  One workgroup of 256 threads (k <= 256).
+__global__ __launch_bounds__(256) void k_thresholds(const float *omega, int k, int n, double tau,
+                                                     double margin, double coef, float *t_in,
+                                                     float *t_out, double *margins,
+                                                     double *max_margin) {
+    __shared__ double red[256];
+    const int j = threadIdx.x;
+    double m = 0.0;
+    if (j < k) {
+        double ss = 0.0;
+        for (int t = 0; t < n; ++t) {
+            double o = (double)omega[(int64_t)j * n + t];
+            ss = ss + o * o;
+        }
+        // Proven bound: |a_rounded - a| <= coef * sum_t |O_jt||s_t| <= coef * ||O_j||_2,
+        // since ||s||_2 = 1; a relative safety factor covers the FP64 evaluation of the
+        // bound itself and a tiny absolute term covers flushed subnormal products.
+        m = margin >= 0.0 ? margin : coef * sqrt(ss) * (1.0 + 0x1p-20) + 0x1p-100;
+        const double lo = tau - m, hi = tau + m;
+        float fl = (float)lo;
+        if ((double)fl > lo) fl = nextafterf(fl, -INFINITY);
+        float fh = (float)hi;
+        if ((double)fh < hi) fh = nextafterf(fh, INFINITY);
+        if (t_in) t_in[j] = fl;
+        if (t_out) t_out[j] = fh;
+        if (margins) margins[j] = m;
+    }
+    red[j] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (j < st) red[j] = fmax(red[j], red[j + st]);
+        __syncthreads();
+    }
+    if (j == 0 && max_margin) *max_margin = red[0];
+}
+
+hipError_t launch_thresholds(const LaunchCtx &lc, const float *omega, int k, int n, double tau,
+                             double margin, double coef, float *t_in, float *t_out,
+                             double *margins, double *max_margin) {
+    hipLaunchKernelGGL(k_thresholds, dim3(1), dim3(256), 0, lc.stream, omega, k, n, tau, margin,
+                       coef, t_in, t_out, margins, max_margin);
+    return hipGetLastError();
+}
+
+}  // namespace cs

@@ -1,0 +1,186 @@
+// Scribble samples on gfx950 (the sets S_i of Sec. 3.1): validation, a
+// stable counting sort by label into contiguous segments, and gathering of
+// each sample's position, colour and co-support from its pixel into a 64-byte
+// record that a wave reads with one scalar load.  Also marks the samples of
+// each label in a per-label seed plane for the distance transform.
+#include "cs_internal.h"
+
+namespace cs {
+
+constexpr int kChunk = 256;
+
+// Per-chunk label counts (label-major: block_counts[l * nblocks + b]); bad
+// labels or pixels set bit 0 of flags.
+__global__ __launch_bounds__(kChunk) void k_sample_count(const int32_t *label, const int32_t *pix,
+                                                          int64_t M, int L, int64_t N,
+                                                          int32_t *block_counts, int32_t *flags,
+                                                          int nblocks) {
+    __shared__ int cnt[kMaxLabels];
+    if (threadIdx.x < kMaxLabels) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t idx = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    if (idx < M) {
+        const int l = label[idx];
+        const int32_t px = pix[idx];
+        if (l < 0 || l >= L || px < 0 || (int64_t)px >= N)
+            atomicOr(flags, 1);
+        else
+            atomicAdd(&cnt[l], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < L) block_counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of block_counts in label-major order (in place) and label
+// totals.  One workgroup.
+__global__ __launch_bounds__(1024) void k_sample_scan(int32_t *block_counts, int L, int nblocks,
+                                                       int32_t *totals) {
+    __shared__ int32_t buf[1024];
+    __shared__ int32_t carry;
+    const int64_t total = (int64_t)L * nblocks;
+    if (threadIdx.x == 0) carry = 0;
+    if (threadIdx.x < L) totals[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < total; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int32_t v = i < total ? block_counts[i] : 0;
+        if (i < total) atomicAdd(&totals[i / nblocks], v);
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+            int32_t t = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < total) block_counts[i] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_sample_count(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
+                               int64_t M, int L, int64_t N, int32_t *block_counts,
+                               int32_t *totals_flags, int nblocks) {
+    hipLaunchKernelGGL(k_sample_count, dim3(nblocks), dim3(kChunk), 0, lc.stream, label, pix, M, L,
+                       N, block_counts, totals_flags + L, nblocks);
+    hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, lc.stream, block_counts, L, nblocks,
+                       totals_flags);
+    return hipGetLastError();
+}
+
+// Stable scatter: a sample's slot is its chunk's offset for its label plus
+// the number of earlier samples of the same label inside the chunk.
+__global__ __launch_bounds__(kChunk) void k_sample_scatter(
+    const int32_t *label, const int32_t *pix, int64_t M, int L, int H, int W, const float *rgb,
+    const uint64_t *masks, int k, const int32_t *offsets, int nblocks, SampleRec *recs,
+    uint8_t *seeds) {
+    __shared__ int32_t lab[kChunk];
+    const int64_t idx = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+    const int64_t N = (int64_t)H * W;
+    int l = -1;
+    int32_t px = 0;
+    if (idx < M) {
+        l = label[idx];
+        px = pix[idx];
+        if (l < 0 || l >= L || px < 0 || (int64_t)px >= N) l = -1;
+    }
+    lab[threadIdx.x] = l;
+    __syncthreads();
+    if (l < 0) return;
+    int rank = 0;
+    for (int i = 0; i < (int)threadIdx.x; ++i) rank += (lab[i] == l);
+    const int64_t slot = (int64_t)offsets[(int64_t)l * nblocks + blockIdx.x] + rank;
+    SampleRec r;
+    r.w[0] = __float_as_uint((float)(px % W));
+    r.w[1] = __float_as_uint((float)(px / W));
+    r.w[2] = __float_as_uint(rgb[px]);
+    r.w[3] = __float_as_uint(rgb[N + px]);
+    r.w[4] = __float_as_uint(rgb[2 * N + px]);
+    r.w[5] = r.w[6] = r.w[7] = 0;
+    const int W64 = (k + 63) / 64;
+    const uint64_t lastmask = (k % 64) ? ((1ull << (k % 64)) - 1ull) : ~0ull;
+    for (int w = 0; w < 4; ++w) {
+        uint64_t v = w < W64 ? masks[(int64_t)px * W64 + w] : 0ull;
+        if (w == W64 - 1) v &= lastmask;
+        r.w[8 + 2 * w] = (uint32_t)v;
+        r.w[9 + 2 * w] = (uint32_t)(v >> 32);
+    }
+    recs[slot] = r;
+    seeds[(int64_t)l * N + px] = 1;
+}
+
+hipError_t launch_sample_scatter(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
+                                 int64_t M, int L, int H, int W, const float *rgb,
+                                 const uint64_t *masks, int k, const int32_t *block_counts,
+                                 int nblocks, SampleRec *recs, uint8_t *seeds) {
+    hipLaunchKernelGGL(k_sample_scatter, dim3(nblocks), dim3(kChunk), 0, lc.stream, label, pix, M, L,
+                       H, W, rgb, masks, k, block_counts, nblocks, recs, seeds);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(unsigned int *p, size_t count, unsigned int v) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_u8x16(uint4 *p, size_t count16, unsigned int v4) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count16; i += stride)
+        p[i] = make_uint4(v4, v4, v4, v4);
+}
+
+__global__ void k_fill_u8(uint8_t *p, size_t count, uint8_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, unsigned int v) {
+    if (!count) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > (size_t)lc.num_cu * 8) blocks = (size_t)lc.num_cu * 8;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, lc.stream, p, count, v);
+    return hipGetLastError();
+}
+
+// p must be 16-byte aligned (workspace allocations are).
+hipError_t launch_fill_u8(const LaunchCtx &lc, uint8_t *p, size_t count, uint8_t v) {
+    if (!count) return hipSuccess;
+    const unsigned int v4 = 0x01010101u * v;
+    const size_t c16 = count / 16;
+    if (c16) {
+        size_t blocks = (c16 + 255) / 256;
+        if (blocks > (size_t)lc.num_cu * 8) blocks = (size_t)lc.num_cu * 8;
+        hipLaunchKernelGGL(k_fill_u8x16, dim3((unsigned)blocks), dim3(256), 0, lc.stream,
+                           reinterpret_cast<uint4 *>(p), c16, v4);
+    }
+    const size_t rem = count - c16 * 16;
+    if (rem)
+        hipLaunchKernelGGL(k_fill_u8, dim3(1), dim3(16), 0, lc.stream, p + c16 * 16, rem, v);
+    return hipGetLastError();
+}
+
+}  // namespace cs
+
+namespace cs {
+
+// Range check of a caller-supplied pixel list; sets bit 1 of *flags.
+__global__ void k_check_pix(const int32_t *pix, int64_t n, int64_t N, int32_t *flags) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int32_t v = pix[i];
+        if (v < 0 || (int64_t)v >= N) atomicOr(flags, 2);
+    }
+}
+
+hipError_t launch_check_pix(const LaunchCtx &lc, const int32_t *pix, int64_t n, int64_t N,
+                            int32_t *flags) {
+    if (!n) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > (int64_t)lc.num_cu * 8) blocks = (int64_t)lc.num_cu * 8;
+    hipLaunchKernelGGL(k_check_pix, dim3((unsigned)blocks), dim3(256), 0, lc.stream, pix, n, N, flags);
+    return hipGetLastError();
+}
+
+}  // namespace cs
