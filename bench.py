@@ -1,0 +1,200 @@
+"""Benchmark of the co-sparse data term on one MI355X.
+
+One step = the whole data-term path over one synthetic image: analysed
+vectors (MFMA), exact threshold tau, co-support masks, and the per-pixel,
+per-label log-likelihood (distance transform + Parzen sum).  The workload is
+the BSDS-sized case: 481x321 RGB, 7x7 patches, k = 98, 10 labels, 7,720
+scribble samples, FP32.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line with the whole-job throughput (pixel x sample pairs/s),
+the roofline of the dominant kernel (the Parzen sum, measured with HIP events
+on the stream it runs on) and the FP64 oracle timed on the host on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs at 2.4 GHz; the published FP32 vector rate 157.3 TFLOP/s is
+# 128 FMA lanes per clock per CU, i.e. 7.86e13 single-rate VALU lane-operations
+# per second; HBM3E 8 TB/s; FP32 matrix 157.3 TFLOP/s; BF16 dense 2.5 PFLOP/s.
+PEAK_LANE_OPS = 157.3e12 / 2
+PEAK_HBM = 8.0e12
+PEAK_MFMA = {"fp32": 157.3e12, "bf16": 2.5e15}
+
+
+def parzen_ops_per_pair(k: int) -> int:
+    """Algorithmic VALU lane-operations per pixel x sample pair: location
+    difference and square (4), colour differences and squares (6), XOR and
+    popcount per 32-bit co-support word (2 ceil(k/32)), conversion of the count
+    and the three-term exponent (4), exponent shift, exp and accumulate (3)."""
+    return 17 + 2 * ((k + 31) // 32)
+
+
+def load_traffic(name: str):
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except Exception:
+        return None
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_parzen.hip", "cs_internal.h"):
+        with open(os.path.join(ROOT, "paper_1312_4746_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(w, n_sample: int):
+    """The FP64 oracle on the host: full-image analysis, tau and masks (needed
+    for any pixel), then the Parzen log-likelihood on a strided subset of
+    pixels; the per-pixel front-end time is scaled to the subset."""
+    import numpy as np
+
+    import oracle
+    oracle.lib()
+    t0 = time.perf_counter()
+    alpha = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega)
+    tau, _ = oracle.tau_median(alpha, w.tau_frac)
+    masks = oracle.cosupport(alpha, tau)
+    t_front = time.perf_counter() - t0
+    pix = np.linspace(0, w.N - 1, n_sample).astype(np.int32)
+    t1 = time.perf_counter()
+    oracle.label_loglik(w.rgb, masks, w.k, w.sample_pix, w.sample_label, w.L, pix=pix)
+    t_ll = time.perf_counter() - t1
+    t_equiv = t_ll + t_front * n_sample / w.N
+    pairs = n_sample * w.M
+    return {
+        "value": pairs / t_equiv,
+        "unit": "pairs/s",
+        "cores": oracle.get_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle: analysis, tau and masks of all {w.N} pixels ({t_front:.2f} s, "
+                   f"scaled to the subset) + Parzen log-likelihood of {n_sample} evenly strided "
+                   f"pixels x {w.M} samples ({t_ll:.2f} s)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the data term runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1312_4746_amd import Context, LoglikParams
+    from workloads import make_config
+
+    w = make_config(args.config)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rgb, om = dev(w.rgb), dev(w.omega)
+    spix, slab = dev(w.sample_pix), dev(w.sample_label)
+    prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
+                       rho_floor_px=w.rho_floor_px)
+    ctx = Context(0)
+    alpha = torch.empty((w.N, w.k), dtype=torch.float32, device="cuda")
+    masks = torch.empty((w.N, (w.k + 63) // 64), dtype=torch.int64, device="cuda")
+    ll = torch.empty((w.N, w.L), dtype=torch.float32, device="cuda")
+
+    def step():
+        ctx.analyze_patches(rgb, w.p, w.mask_sigma, om, precision=w.precision, out=alpha)
+        tau = ctx.tau_median(rgb, w.p, w.mask_sigma, om, alpha, w.tau_frac, precision=w.precision)
+        ctx.cosupport(rgb, w.p, w.mask_sigma, om, tau, precision=w.precision, out=masks)
+        ctx.label_loglik(rgb, masks, w.k, spix, slab, w.L, prm, out=ll)
+        return tau
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    parzen_ms, parzen_n = ctx.profile_read("parzen")
+    analyze_ms, analyze_n = ctx.profile_read("analyze")
+    cos_ms, cos_n = ctx.profile_read("cosupport")
+    edt_ms, _ = ctx.profile_read("edt")
+    ctx.profile_enable(False)
+
+    ms_per_step = dt * 1e3 / args.steps
+    pairs = w.N * w.M
+    value = pairs / (ms_per_step / 1e3)
+
+    avg_parzen_s = parzen_ms / 1e3 / max(parzen_n, 1)
+    ops = pairs * parzen_ops_per_pair(w.k)
+    achieved = ops / avg_parzen_s
+    traffic = None
+    tr = load_traffic("parzen_bsds_traffic.json")
+    if tr and tr.get("source_digest") == kernel_source_digest():
+        traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                "kernel": "k_parzen", "avg_launch_ms": avg_parzen_s * 1e3,
+                "ops_per_pair": parzen_ops_per_pair(w.k)}
+    avg_an = analyze_ms / 1e3 / max(analyze_n, 1)
+    gemm_flops = 2.0 * w.k * w.n * w.N
+    extra = {
+        "analyze_mfma": {"avg_launch_ms": avg_an * 1e3, "achieved_tflops": gemm_flops / avg_an / 1e12,
+                         "peak_tflops": PEAK_MFMA[w.precision] / 1e12,
+                         "frac": gemm_flops / avg_an / PEAK_MFMA[w.precision]},
+        "cosupport_avg_launch_ms": cos_ms / max(cos_n, 1),
+        "edt_ms_per_step": edt_ms / args.steps,
+        "px_per_s": w.N / (ms_per_step / 1e3),
+    }
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, min(args.cpu_sample, w.N))
+
+    out = {
+        "metric": "data-term pixel x sample pairs/s",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w.precision == "fp32" else "bf16+f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "H": w.H, "W": w.W, "p": w.p, "k": w.k, "labels": w.L,
+                   "samples": w.M, "pixels": w.N, "pairs": pairs, "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
