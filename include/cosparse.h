@@ -82,8 +82,11 @@ int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, doubl
  * output of cs_analyze_patches for the same inputs and precision; entries whose
  * rounded value lies within the proven error bound of the selected median are
  * recomputed in FP64, so tau equals the FP64 value bit for bit.
+ *   alpha   device, N*k float32, 16-byte aligned
  *   tau_out host out.  Synchronises the stream (returns a host value).
- * Errors: as cs_analyze_patches, plus CS_ERR_ARG for frac < 0 or NaN.
+ * Errors: as cs_analyze_patches, plus CS_ERR_ARG for frac < 0 or NaN or a
+ * misaligned alpha; CS_ERR_HIP if the exact median falls outside the
+ * candidate window (the error bound would have been violated).
  */
 int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
                   const float *omega, int k, int precision, const float *alpha, double frac,
@@ -149,8 +152,10 @@ typedef struct {
  *   loglik        device out, (n_subset or N) * L float32, loglik[r*L + i]
  *                 (may be NULL when pix_subset is non-NULL and n_subset is 0)
  * Synchronises once after sorting the samples by label (to check labels).
- * Errors: CS_ERR_ARG (null pointers, sizes, prm values <= 0, sample pixel or
- * label out of range), CS_ERR_EMPTY_LABEL when some label has no sample.
+ * Errors: CS_ERR_ARG (null pointers, H outside 1..32767, W outside 1..16384,
+ * k outside 1..256, L outside 1..64, prm values <= 0 or not finite, sample
+ * pixel, sample label or subset pixel out of range), CS_ERR_EMPTY_LABEL when
+ * some label has no sample.
  */
 int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
                     const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,

@@ -318,6 +318,7 @@ int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
     int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
     if (rc) return rc;
     if (!alpha || !tau_out) return fail(ctx, CS_ERR_ARG, "alpha and tau_out must be non-null");
+    if (reinterpret_cast<uintptr_t>(alpha) % 16) return fail(ctx, CS_ERR_ARG, "alpha must be 16-byte aligned");
     if (!(frac >= 0.0) || !std::isfinite(frac)) return fail(ctx, CS_ERR_ARG, "frac must be finite and >= 0");
     HIP_TRY(hipSetDevice(ctx->device));
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
@@ -393,8 +394,8 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         return fail(ctx, CS_ERR_ARG, "null pointer argument");
     if (!loglik && !(pix_subset && n_subset == 0))
         return fail(ctx, CS_ERR_ARG, "loglik must be non-null unless the pixel subset is empty");
-    if (H < 1 || W < 1 || H > 32767 || W > 32767)
-        return fail(ctx, CS_ERR_ARG, "H and W must be in 1..32767");
+    if (H < 1 || W < 1 || H > 32767 || W > 16384)
+        return fail(ctx, CS_ERR_ARG, "H must be in 1..32767 and W in 1..16384");
     if (k < 1 || k > kMaxK) return fail(ctx, CS_ERR_ARG, "k must be in 1..%d (got %d)", kMaxK, k);
     if (L < 1 || L > kMaxLabels) return fail(ctx, CS_ERR_ARG, "L must be in 1..%d (got %d)", kMaxLabels, L);
     if (M < 1 || M > (((int64_t)1 << 31) - 1)) return fail(ctx, CS_ERR_ARG, "M must be in 1..2^31-1");
@@ -417,6 +418,15 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_col = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_d2 = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_nn = cv.take(sizeof(int32_t) * (size_t)L * N);
+    const size_t o_edt = cv.take(edt_scratch_bytes(H, W, L));
+    // full-image path: FP8 sample features for the MFMA texture term and the fix-up queue
+    const bool fast = pix_subset == nullptr;
+    const int KP = (k + 4 + 127) / 128 * 128;
+    const int tiles_x = (W + 7) / 8, tiles_y = (H + 2 * kParzenRB - 1) / (2 * kParzenRB);
+    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
+    const size_t o_feat = fast ? cv.take((size_t)M * KP) : 0;
+    const size_t o_fix = fast ? cv.take(sizeof(int2) * (size_t)(ntiles + 3) / 4 * 4 * L) : 0;
+    const size_t o_fcnt = cv.take(sizeof(unsigned int) * 4);
     int rc = ensure_ws(ctx, cv.off);
     if (rc) return rc;
     int32_t *bc = (int32_t *)(ctx->ws + o_bc), *tf = (int32_t *)(ctx->ws + o_tf);
@@ -451,8 +461,13 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     }
     {
         Timed t(ctx, "edt");
-        HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest));
+        HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest, (int32_t *)(ctx->ws + o_edt)));
     }
+    if (fast) {
+        Timed t(ctx, "features");
+        HIP_TRY(launch_sample_features(lc, recs, M, k, KP, (uint8_t *)(ctx->ws + o_feat)));
+    }
+    unsigned int *fcnt = (unsigned int *)(ctx->ws + o_fcnt);
     ParzenArgs pa{};
     pa.rgb = rgb;
     pa.masks = masks;
@@ -485,7 +500,51 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     std::stable_sort(pa.label_order, pa.label_order + L,
                      [&](int x, int y) { return counts[x] > counts[y]; });
     HIP_TRY(launch_fill_u32(lc, cnt, 2, 0u));
-    {
+    if (fast) {
+        ParzenFastArgs fa{};
+        fa.rgb = rgb;
+        fa.masks = masks;
+        fa.recs = recs;
+        fa.feat = (const uint8_t *)(ctx->ws + o_feat);
+        fa.d2 = d2;
+        fa.nearest = nearest;
+        fa.loglik = loglik;
+        fa.work_counter = fcnt;
+        fa.fix_count = fcnt + 1;
+        fa.fixlist = (int2 *)(ctx->ws + o_fix);
+        fa.H = H;
+        fa.W = W;
+        fa.L = L;
+        fa.k = k;
+        fa.ksteps = KP / 128;
+        fa.tiles_x = tiles_x;
+        fa.tiles_y = tiles_y;
+        fa.ntiles = (int)ntiles;
+        fa.ngroups = (int)((ntiles + 3) / 4);
+        fa.fix_cap = fa.ngroups * 4 * L;
+        fa.alpha_rho = pa.alpha_rho;
+        fa.sigma_c = pa.sigma_c;
+        fa.beta_scale = pa.beta_scale;
+        fa.rho_floor = pa.rho_floor;
+        std::memcpy(fa.seg_off, pa.seg_off, sizeof(pa.seg_off));
+        std::memcpy(fa.label_order, pa.label_order, sizeof(pa.label_order));
+        std::memcpy(fa.kconst, pa.kconst, sizeof(pa.kconst));
+        HIP_TRY(launch_fill_u32(lc, fcnt, 4, 0u));
+        {
+            Timed t(ctx, "parzen");
+            HIP_TRY(launch_parzen_mfma(lc, fa));
+        }
+        // exact two-pass kernel for the (label, tile) pairs the fast kernel queued
+        pa.fixlist = fa.fixlist;
+        pa.fix_count = fa.fix_count;
+        pa.fix_cap = fa.fix_cap;
+        pa.tiles_x = tiles_x;
+        pa.tiles = (int)((ntiles + 3) / 4 * 4);
+        {
+            Timed t(ctx, "parzen_fixup");
+            HIP_TRY(launch_parzen(lc, pa));
+        }
+    } else {
         Timed t(ctx, "parzen");
         HIP_TRY(launch_parzen(lc, pa));
     }

@@ -14,6 +14,9 @@ namespace cs {
 constexpr int kTilePx = 64;
 // Words of a sample record (see SampleRec).
 constexpr int kRecWords = 16;
+// 16-pixel row blocks per wave in the MFMA Parzen kernel: a wave owns an
+// 8 x (2 kParzenRB) pixel tile.
+constexpr int kParzenRB = 2;
 // Maximum label count and co-support length handled by the kernels.
 constexpr int kMaxLabels = 64;
 constexpr int kMaxK = 256;
@@ -87,8 +90,9 @@ hipError_t launch_sample_scatter(const LaunchCtx &lc, const int32_t *label, cons
                                  int nblocks, SampleRec *recs, uint8_t *seeds);
 hipError_t launch_check_pix(const LaunchCtx &lc, const int32_t *pix, int64_t n, int64_t N,
                             int32_t *flags);
+size_t edt_scratch_bytes(int H, int W, int L);
 hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, int L,
-                      int32_t *colrow, int32_t *d2, int32_t *nearest);
+                      int32_t *colrow, int32_t *d2, int32_t *nearest, int32_t *scratch);
 
 struct ParzenArgs {
     const float *rgb;
@@ -100,6 +104,11 @@ struct ParzenArgs {
     float *loglik;
     unsigned int *work_counter;
     unsigned int *fixups;
+    // fix-up mode: items are (label, 8x8 tile) pairs queued by the MFMA kernel
+    const int2 *fixlist;
+    const unsigned int *fix_count;
+    int fix_cap;
+    int tiles_x;
     int H, W, L, k, nw32;
     int64_t npix;
     int tiles;               // ceil(npix / 64)
@@ -109,6 +118,29 @@ struct ParzenArgs {
     double kconst[kMaxLabels];  // -log m_i - log(2 pi) - 1.5 log(2 pi sigma_c^2)
 };
 hipError_t launch_parzen(const LaunchCtx &lc, const ParzenArgs &a);
+
+struct ParzenFastArgs {
+    const float *rgb;
+    const uint64_t *masks;
+    const SampleRec *recs;
+    const uint8_t *feat;     // M x 128*ksteps FP8 sample features
+    const int32_t *d2;       // L x N
+    const int32_t *nearest;  // L x N
+    float *loglik;
+    unsigned int *work_counter;
+    unsigned int *fix_count;
+    int2 *fixlist;
+    int fix_cap;
+    int H, W, L, k, ksteps;
+    int tiles_x, tiles_y, ntiles, ngroups;
+    double alpha_rho, sigma_c, beta_scale, rho_floor;
+    int seg_off[kMaxLabels + 1];
+    int label_order[kMaxLabels];
+    double kconst[kMaxLabels];
+};
+hipError_t launch_sample_features(const LaunchCtx &lc, const SampleRec *recs, int64_t M, int k,
+                                  int KP, uint8_t *feat);
+hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a);
 hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
 hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, unsigned int v);
 hipError_t launch_fill_u8(const LaunchCtx &lc, uint8_t *p, size_t count, uint8_t v);

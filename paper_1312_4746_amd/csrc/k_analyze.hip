@@ -32,11 +32,11 @@ namespace cs {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 
-template <int PREC>
+template <int PREC, int P>
 __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int h = (a.p - 1) / 2;
-    const int n = a.n, np = a.n_pad, ss = a.n_pad + 1;
+    constexpr int h = (P - 1) / 2;
+    constexpr int n = P * P, np = (n + 15) / 16 * 16, ss = np + 1;
     const int hw = kTilePx + 2 * h;
     const int W64 = (a.k + 63) / 64;
     double *gh = reinterpret_cast<double *>(smem);  // (2h+1) x hw gray halo
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
         int i = idx / np, t = idx - i * np;
         double q = 0.0;
         if (i < valid_px && t < n) {
-            int u = t / a.p, v = t - u * a.p;
+            int u = t / P, v = t - u * P;
             q = a.wmask[t] * gh[u * hw + i + v];
         }
         s[i * ss + t] = q;
@@ -108,28 +108,41 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
         const bool jv = j < a.k;
         const float *om = a.omega + (int64_t)(jv ? j : 0) * n;
         if (PREC == CS_FP32) {
-            for (int kb = 0; kb < np; kb += 4) {
-                const int t = kb + (lane >> 4);
-                const float b = (jv && t < n) ? om[t] : 0.f;
+            // B fragments of the whole K range first (independent loads in flight).
+            float bf[np / 4];
+#pragma unroll
+            for (int kb = 0; kb < np / 4; ++kb) {
+                const int t = kb * 4 + (lane >> 4);
+                bf[kb] = (jv && t < n) ? om[t] : 0.f;
+            }
+#pragma unroll
+            for (int kb = 0; kb < np / 4; ++kb) {
+                const int t = kb * 4 + (lane >> 4);
 #pragma unroll
                 for (int rb = 0; rb < 4; ++rb) {
                     const float av = (float)s[(rb * 16 + (lane & 15)) * ss + t];
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[kb], acc[rb], 0, 0, 0);
                 }
             }
         } else {
-            for (int kb = 0; kb < np; kb += 16) {
-                const int t0 = kb + 4 * (lane >> 4);
-                s16x4 b;
+            s16x4 bf[np / 16];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) b[q] = bf16_rne((jv && t0 + q < n) ? om[t0 + q] : 0.f);
+            for (int kb = 0; kb < np / 16; ++kb) {
+                const int t0 = kb * 16 + 4 * (lane >> 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    bf[kb][q] = bf16_rne((jv && t0 + q < n) ? om[t0 + q] : 0.f);
+            }
+#pragma unroll
+            for (int kb = 0; kb < np / 16; ++kb) {
+                const int t0 = kb * 16 + 4 * (lane >> 4);
 #pragma unroll
                 for (int rb = 0; rb < 4; ++rb) {
                     const double *sp = s + (rb * 16 + (lane & 15)) * ss + t0;
                     s16x4 av;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) av[q] = bf16_rne((float)sp[q]);
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, b, acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bf[kb], acc[rb], 0, 0, 0);
                 }
             }
         }
@@ -176,27 +189,39 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
     }
 }
 
-hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precision) {
-    const int h = (a.p - 1) / 2;
+template <int PREC, int P>
+static hipError_t launch_analyze_p(const LaunchCtx &lc, const AnalyzeArgs &a) {
+    constexpr int h = (P - 1) / 2, n = P * P, np = (n + 15) / 16 * 16;
     const int hw = kTilePx + 2 * h;
     const int W64 = (a.k + 63) / 64;
-    const size_t lds = sizeof(double) * ((size_t)(2 * h + 1) * hw + (size_t)kTilePx * (a.n_pad + 1) +
+    const size_t lds = sizeof(double) * ((size_t)(2 * h + 1) * hw + (size_t)kTilePx * (np + 1) +
                                          kTilePx) +
                        sizeof(uint16_t) * (size_t)kTilePx * 4 * W64;
     dim3 grid((a.W + kTilePx - 1) / kTilePx, a.H);
-    hipError_t e;
-    if (precision == CS_BF16) {
-        e = hipFuncSetAttribute((const void *)k_analyze<CS_BF16>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_analyze<CS_BF16>, grid, dim3(256), lds, lc.stream, a);
-    } else {
-        e = hipFuncSetAttribute((const void *)k_analyze<CS_FP32>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_analyze<CS_FP32>, grid, dim3(256), lds, lc.stream, a);
-    }
+    hipError_t e = hipFuncSetAttribute((const void *)k_analyze<PREC, P>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_analyze<PREC, P>), grid, dim3(256), lds, lc.stream, a);
     return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_analyze_prec(const LaunchCtx &lc, const AnalyzeArgs &a) {
+    switch (a.p) {
+        case 3: return launch_analyze_p<PREC, 3>(lc, a);
+        case 5: return launch_analyze_p<PREC, 5>(lc, a);
+        case 7: return launch_analyze_p<PREC, 7>(lc, a);
+        case 9: return launch_analyze_p<PREC, 9>(lc, a);
+        case 11: return launch_analyze_p<PREC, 11>(lc, a);
+        case 13: return launch_analyze_p<PREC, 13>(lc, a);
+        case 15: return launch_analyze_p<PREC, 15>(lc, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precision) {
+    if (precision == CS_BF16) return launch_analyze_prec<CS_BF16>(lc, a);
+    return launch_analyze_prec<CS_FP32>(lc, a);
 }
 
 // Per-row decision thresholds.  One workgroup of 256 threads (k <= 256).

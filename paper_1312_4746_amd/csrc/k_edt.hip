@@ -2,112 +2,162 @@
 // sample of each label, with the identity of that sample, on gfx950.  This is
 // the |x - x_{v_i}| that sets the spatial bandwidth rho_i(x) in Sec. 3.1.
 //
-// Separable two-pass transform on integer distances (exact):
-//  1. columns: for every (label, column) a thread scans the column down and up
-//     and keeps the row of the nearest seed in that column (coalesced: the
-//     threads of a wave own adjacent columns);
-//  2. rows: for every (label, row) a thread builds the lower envelope of the
-//     parabolas (c - q)^2 + f(q) over the columns q that hold a seed, with
-//     f(q) the squared column distance, and reads it off for every column.
-//     Envelope breakpoints are compared by exact 64-bit cross-multiplication,
-//     so no rounding enters; the stack of envelope sites lives in LDS.
+// Separable transform on integer distances (exact):
+//  1. columns: the rows of every column are cut into short segments; a first
+//     kernel records the first and last seed row of each segment, a second one
+//     carries the nearest seed rows from the other segments in and scans its
+//     own segment both ways (lanes own adjacent columns, so loads coalesce);
+//  2. rows: one workgroup per (label, row) stages f(q) = squared column
+//     distance of every column q in LDS; each thread owns columns c and scans
+//     outward, q = c -+ delta, keeping the best (c - q)^2 + f(q), and stops as
+//     soon as delta^2 reaches the best value, so the work per pixel is
+//     proportional to its distance to the nearest sample.
 #include "cs_internal.h"
 
 namespace cs {
 
-__global__ __launch_bounds__(256) void k_edt_cols(const uint8_t *seeds, int H, int W,
-                                                   int32_t *colrow) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    const int l = blockIdx.y;
+constexpr int kSegRows = 16;
+constexpr int kNoSeed = -1;
+constexpr int32_t kInf = 0x3FFFFFFF;
+
+// Per (label, segment, column): first and last seed row inside the segment.
+__global__ __launch_bounds__(64) void k_edt_col_summary(const uint8_t *seeds, int H, int W,
+                                                         int nseg, int32_t *first, int32_t *last) {
+    const int c = blockIdx.x * 64 + threadIdx.x;
+    const int seg = blockIdx.y, l = blockIdx.z;
     if (c >= W) return;
     const int64_t N = (int64_t)H * W;
     const uint8_t *sd = seeds + (int64_t)l * N + c;
+    const int r0 = seg * kSegRows, r1 = min(H, r0 + kSegRows);
+    int f = kNoSeed, la = kNoSeed;
+#pragma unroll 4
+    for (int r = r0; r < r1; ++r) {
+        if (sd[(int64_t)r * W]) {
+            if (f < 0) f = r;
+            la = r;
+        }
+    }
+    const int64_t o = ((int64_t)l * nseg + seg) * W + c;
+    first[o] = f;
+    last[o] = la;
+}
+
+// Nearest seed row in the column for every pixel of the segment.
+__global__ __launch_bounds__(64) void k_edt_col_fill(const uint8_t *seeds, int H, int W, int nseg,
+                                                      const int32_t *first, const int32_t *last,
+                                                      int32_t *colrow) {
+    const int c = blockIdx.x * 64 + threadIdx.x;
+    const int seg = blockIdx.y, l = blockIdx.z;
+    if (c >= W) return;
+    const int64_t N = (int64_t)H * W;
+    const int64_t sbase = (int64_t)l * nseg * W + c;
+    int above = kNoSeed;  // last seed row in the segments above
+    for (int s = seg - 1; s >= 0; --s) {
+        const int v = last[sbase + (int64_t)s * W];
+        if (v >= 0) {
+            above = v;
+            break;
+        }
+    }
+    int below = kNoSeed;  // first seed row in the segments below
+    for (int s = seg + 1; s < nseg; ++s) {
+        const int v = first[sbase + (int64_t)s * W];
+        if (v >= 0) {
+            below = v;
+            break;
+        }
+    }
+    const uint8_t *sd = seeds + (int64_t)l * N + c;
     int32_t *cr = colrow + (int64_t)l * N + c;
-    int last = -1;
-    for (int r = 0; r < H; ++r) {
-        if (sd[(int64_t)r * W]) last = r;
-        cr[(int64_t)r * W] = last;
+    const int r0 = seg * kSegRows, r1 = min(H, r0 + kSegRows);
+    int up[kSegRows];
+    int lastr = above;
+#pragma unroll
+    for (int i = 0; i < kSegRows; ++i) {
+        const int r = r0 + i;
+        if (r < r1 && sd[(int64_t)r * W]) lastr = r;
+        up[i] = lastr;
     }
-    int next = -1;
-    for (int r = H - 1; r >= 0; --r) {
-        if (sd[(int64_t)r * W]) next = r;
-        const int cur = cr[(int64_t)r * W];
-        if (next >= 0 && (cur < 0 || next - r < r - cur)) cr[(int64_t)r * W] = next;
+    int nextr = below;
+#pragma unroll
+    for (int i = kSegRows - 1; i >= 0; --i) {
+        const int r = r0 + i;
+        if (r >= r1) continue;
+        if (sd[(int64_t)r * W]) nextr = r;
+        const int a = up[i];
+        int best = a;
+        if (nextr >= 0 && (a < 0 || nextr - r < r - a)) best = nextr;
+        cr[(int64_t)r * W] = best;
     }
 }
 
-__device__ __forceinline__ int64_t env_F(int q, int fr) {  // f(q) + q^2
-    return (int64_t)fr * fr + (int64_t)q * q;
-}
-
-__global__ void k_edt_rows(const int32_t *colrow, int H, int W, int L, int32_t *d2,
-                           int32_t *nearest) {
-    extern __shared__ int16_t stack_mem[];
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)H * L) return;
-    const int l = (int)(gid / H), r = (int)(gid - (int64_t)(gid / H) * H);
+__global__ __launch_bounds__(256) void k_edt_rows(const int32_t *colrow, int H, int W,
+                                                   int32_t *d2, int32_t *nearest) {
+    extern __shared__ int32_t lds[];
+    int32_t *f = lds;        // squared column distance, kInf where the column has no seed
+    int32_t *rowof = lds + W;
+    const int r = blockIdx.x, l = blockIdx.y;
     const int64_t N = (int64_t)H * W;
     const int32_t *cr = colrow + (int64_t)l * N + (int64_t)r * W;
-    int16_t *v = stack_mem + (int64_t)threadIdx.x * W;
-    // f(q) = (r - colrow[q])^2 ; F(q) = f(q) + q^2
-    int top = -1;
-    for (int q = 0; q < W; ++q) {
-        const int rq = cr[q];
-        if (rq < 0) continue;
-        const int64_t Fq = env_F(q, r - rq);
-        while (top >= 1) {
-            const int a = v[top - 1], b = v[top];
-            const int64_t Fa = env_F(a, r - cr[a]), Fb = env_F(b, r - cr[b]);
-            // breakpoint(b, q) <= breakpoint(a, b)  ->  b is never the minimum
-            if ((Fq - Fb) * (int64_t)(b - a) <= (Fb - Fa) * (int64_t)(q - b))
-                --top;
-            else
-                break;
-        }
-        v[++top] = (int16_t)q;
+    for (int c = threadIdx.x; c < W; c += 256) {
+        const int q = cr[c];
+        rowof[c] = q;
+        f[c] = q < 0 ? kInf : (r - q) * (r - q);
     }
+    __syncthreads();
     int32_t *dd = d2 + (int64_t)l * N + (int64_t)r * W;
     int32_t *nn = nearest + (int64_t)l * N + (int64_t)r * W;
-    if (top < 0) {  // no seed of this label anywhere (rejected before launch)
-        for (int c = 0; c < W; ++c) {
+    for (int c = threadIdx.x; c < W; c += 256) {
+        int best = f[c], bq = c;
+        const int span = max(c, W - 1 - c);
+        for (int d = 1; d <= span; ++d) {
+            const int d2v = d * d;
+            if (d2v >= best) break;
+            const int ql = c - d, qr = c + d;
+            if (ql >= 0) {
+                const int v = d2v + f[ql];
+                if (v < best) {
+                    best = v;
+                    bq = ql;
+                }
+            }
+            if (qr < W) {
+                const int v = d2v + f[qr];
+                if (v < best) {
+                    best = v;
+                    bq = qr;
+                }
+            }
+        }
+        if (best >= kInf) {  // no seed of this label anywhere (rejected before launch)
             dd[c] = -1;
             nn[c] = -1;
+        } else {
+            dd[c] = best;
+            nn[c] = rowof[bq] * W + bq;
         }
-        return;
     }
-    int kk = 0;
-    for (int c = 0; c < W; ++c) {
-        while (kk < top) {
-            const int a = v[kk], b = v[kk + 1];
-            const int64_t Fa = env_F(a, r - cr[a]), Fb = env_F(b, r - cr[b]);
-            // breakpoint(a, b) = (Fb - Fa) / (2 (b - a)) <= c  ->  move to b
-            if (Fb - Fa <= (int64_t)c * 2 * (b - a))
-                ++kk;
-            else
-                break;
-        }
-        const int q = v[kk];
-        const int dr = r - cr[q];
-        dd[c] = (c - q) * (c - q) + dr * dr;
-        nn[c] = cr[q] * W + q;
-    }
+}
+
+// Scratch: first/last summaries, 2 * L * ceil(H/16) * W int32.
+size_t edt_scratch_bytes(int H, int W, int L) {
+    const int nseg = (H + kSegRows - 1) / kSegRows;
+    return sizeof(int32_t) * 2 * (size_t)L * nseg * W;
 }
 
 hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, int L,
-                      int32_t *colrow, int32_t *d2, int32_t *nearest) {
-    hipLaunchKernelGGL(k_edt_cols, dim3((W + 255) / 256, L), dim3(256), 0, lc.stream, seeds, H, W,
+                      int32_t *colrow, int32_t *d2, int32_t *nearest, int32_t *scratch) {
+    const int nseg = (H + kSegRows - 1) / kSegRows;
+    int32_t *first = scratch, *last = scratch + (size_t)L * nseg * W;
+    dim3 g1((W + 63) / 64, nseg, L);
+    hipLaunchKernelGGL(k_edt_col_summary, g1, dim3(64), 0, lc.stream, seeds, H, W, nseg, first, last);
+    hipLaunchKernelGGL(k_edt_col_fill, g1, dim3(64), 0, lc.stream, seeds, H, W, nseg, first, last,
                        colrow);
-    // Threads per workgroup bounded by a 64 KiB LDS stack budget.
-    int tpb = (int)(65536 / (2 * (int64_t)W));
-    if (tpb > 64) tpb = 64;
-    if (tpb < 1) tpb = 1;
-    const int64_t total = (int64_t)H * L;
-    const size_t lds = (size_t)tpb * W * sizeof(int16_t);
+    const size_t lds = sizeof(int32_t) * 2 * (size_t)W;
     hipError_t e = hipFuncSetAttribute((const void *)k_edt_rows,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edt_rows, dim3((unsigned)((total + tpb - 1) / tpb)), dim3(tpb), lds,
-                       lc.stream, colrow, H, W, L, d2, nearest);
+    hipLaunchKernelGGL(k_edt_rows, dim3(H, L), dim3(256), lds, lc.stream, colrow, H, W, d2, nearest);
     return hipGetLastError();
 }
 

@@ -60,7 +60,12 @@ __global__ __launch_bounds__(256) void k_parzen(ParzenArgs a, const uint32_t *__
     const int lane = threadIdx.x & 63;
     const int64_t N = (int64_t)a.H * a.W;
     const int W64 = (a.k + 63) / 64;
-    const int total = a.tiles * a.L;
+    const bool fixmode = a.fixlist != nullptr;
+    int total = a.tiles * a.L;
+    if (fixmode) {
+        const unsigned int nf = *a.fix_count;
+        total = (int)(nf < (unsigned int)a.fix_cap ? nf : (unsigned int)a.fix_cap);
+    }
     const float nC = (float)(-kLog2e / (2.0 * a.sigma_c * a.sigma_c));
     const uint32_t *mask32 = reinterpret_cast<const uint32_t *>(a.masks);
 
@@ -70,11 +75,26 @@ __global__ __launch_bounds__(256) void k_parzen(ParzenArgs a, const uint32_t *__
         item = __shfl(item, 0);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total) break;
-        const int l = a.label_order[item / a.tiles];
-        const int tile = item - (item / a.tiles) * a.tiles;
-        const int64_t i = (int64_t)tile * 64 + lane;
-        const bool valid = i < a.npix;
-        const int64_t pix = valid ? (a.subset ? (int64_t)a.subset[i] : i) : 0;
+        int l, tile;
+        int64_t i, pix;
+        bool valid;
+        if (fixmode) {
+            const int2 fx = a.fixlist[item];
+            l = __builtin_amdgcn_readfirstlane(fx.x);
+            tile = __builtin_amdgcn_readfirstlane(fx.y);
+            const int tyy = tile / a.tiles_x;
+            const int px = (tile - tyy * a.tiles_x) * 8 + (lane & 7);
+            const int py = tyy * 2 * kParzenRB + (lane >> 3);
+            valid = (lane >> 3) < 2 * kParzenRB && px < a.W && py < a.H;
+            pix = valid ? (int64_t)py * a.W + px : 0;
+            i = pix;
+        } else {
+            l = a.label_order[item / a.tiles];
+            tile = item - (item / a.tiles) * a.tiles;
+            i = (int64_t)tile * 64 + lane;
+            valid = i < a.npix;
+            pix = valid ? (a.subset ? (int64_t)a.subset[i] : i) : 0;
+        }
 
         const float px = (float)(pix % a.W), py = (float)(pix / a.W);
         const float pr = a.rgb[pix], pg = a.rgb[N + pix], pb = a.rgb[2 * N + pix];
@@ -125,8 +145,8 @@ __global__ __launch_bounds__(256) void k_parzen(ParzenArgs a, const uint32_t *__
             S += __builtin_amdgcn_exp2f(pair_e<NW>(px, py, pr, pg, pb, mx, rw, nA, nB, nC) - R);
         }
         S += S1;
-        const bool bad = valid && !(S <= 0x1p100f);
-        if (__ballot(bad)) {
+        const bool bad = valid && !(S <= 0x1p100f && S > 0.0f);
+        if (fixmode || __ballot(bad)) {
             float E = -INFINITY;
             for (int s2 = s0; s2 < s1; ++s2) {
                 const uint32_t *rw = recw + (int64_t)s2 * kRecWords;
@@ -138,7 +158,7 @@ __global__ __launch_bounds__(256) void k_parzen(ParzenArgs a, const uint32_t *__
                 S += __builtin_amdgcn_exp2f(pair_e<NW>(px, py, pr, pg, pb, mx, rw, nA, nB, nC) - E);
             }
             R = E;
-            if (lane == 0) atomicAdd(fixups, 1u);
+            if (lane == 0 && !fixmode) atomicAdd(fixups, 1u);
         }
         if (valid) {
             const double lg = kLn2 * ((double)R + (double)__builtin_amdgcn_logf(S)) + K;

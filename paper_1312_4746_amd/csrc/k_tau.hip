@@ -22,66 +22,106 @@ namespace cs {
 
 constexpr int kHistBins = 2048;
 
-__global__ void k_tau_init(TauState *st, unsigned long long rank0) {
-    st->rank0 = rank0;
-    st->rank = rank0;
-    st->prefix = 0;
-    st->below = 0;
-    st->ncand = 0;
-    st->lo = st->hi = 0.0;
-    st->median = 0.0;
-    st->tau = 0.0;
+__global__ __launch_bounds__(256) void k_tau_init(TauState *st, unsigned long long rank0,
+                                                   unsigned int *hist) {
+    if (threadIdx.x == 0) {
+        st->rank0 = rank0;
+        st->rank = rank0;
+        st->prefix = 0;
+        st->below = 0;
+        st->ncand = 0;
+        st->lo = st->hi = 0.0;
+        st->median = 0.0;
+        st->tau = 0.0;
+    }
+    for (int i = threadIdx.x; i < kHistBins; i += 256) hist[i] = 0;
 }
 
+// Histogram of one 11-bit digit of the |a| bit patterns that match the
+// prefix selected so far.  Eight sub-histograms per workgroup (by lane % 8)
+// spread the LDS atomics of lanes that fall into the same few bins.
+constexpr int kSub = 8;
 __global__ __launch_bounds__(256) void k_tau_hist(const float *alpha, int64_t count, int shift,
                                                    unsigned int pmask, const TauState *st,
                                                    unsigned int *hist) {
-    __shared__ unsigned int lh[kHistBins];
-    for (int i = threadIdx.x; i < kHistBins; i += 256) lh[i] = 0;
+    __shared__ unsigned int lh[kSub * kHistBins];
+    for (int i = threadIdx.x; i < kSub * kHistBins; i += 256) lh[i] = 0;
     __syncthreads();
     const unsigned int pval = st->prefix & pmask;
+    unsigned int *mine = lh + (threadIdx.x & (kSub - 1)) * kHistBins;
+    const int64_t n4 = count / 4;
+    const float4 *a4 = reinterpret_cast<const float4 *>(alpha);
     const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += stride) {
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += stride) {
+        const float4 v = a4[q];
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const unsigned int key = __float_as_uint(vv[u]) & 0x7FFFFFFFu;
+            if ((key & pmask) == pval) atomicAdd(&mine[(key >> shift) & (kHistBins - 1)], 1u);
+        }
+    }
+    for (int64_t e = n4 * 4 + (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += stride) {
         const unsigned int key = __float_as_uint(alpha[e]) & 0x7FFFFFFFu;
-        if ((key & pmask) == pval) atomicAdd(&lh[(key >> shift) & (kHistBins - 1)], 1u);
+        if ((key & pmask) == pval) atomicAdd(&mine[(key >> shift) & (kHistBins - 1)], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kHistBins; i += 256)
-        if (lh[i]) atomicAdd(&hist[i], lh[i]);
+    for (int i = threadIdx.x; i < kHistBins; i += 256) {
+        unsigned int t = 0;
+#pragma unroll
+        for (int c = 0; c < kSub; ++c) t += lh[c * kHistBins + i];
+        if (t) atomicAdd(&hist[i], t);
+    }
 }
 
-// Pick the digit holding the remaining rank, then clear the histogram.
+// Pick the digit holding the remaining rank (parallel prefix over the bins),
+// then clear the histogram for the next pass.
 __global__ __launch_bounds__(256) void k_tau_pick(unsigned int *hist, int shift, TauState *st) {
-    if (threadIdx.x == 0) {
-        unsigned long long r = st->rank;
-        for (int b = 0; b < kHistBins; ++b) {
-            if (r < hist[b]) {
-                st->prefix |= (unsigned int)b << shift;
+    constexpr int per = kHistBins / 256;
+    __shared__ unsigned long long scan[256];
+    const int t = threadIdx.x;
+    unsigned int loc[per];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        loc[i] = hist[t * per + i];
+        sum += loc[i];
+    }
+    scan[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const unsigned long long v = t >= off ? scan[t - off] : 0ull;
+        __syncthreads();
+        scan[t] += v;
+        __syncthreads();
+    }
+    const unsigned long long r = st->rank;
+    const unsigned long long before = scan[t] - sum;
+    __syncthreads();
+    if (r >= before && r < scan[t]) {
+        unsigned long long rr = r - before;
+        for (int i = 0; i < per; ++i) {
+            if (rr < loc[i]) {
+                st->prefix |= (unsigned int)(t * per + i) << shift;
+                st->rank = rr;
                 break;
             }
-            r -= hist[b];
+            rr -= loc[i];
         }
-        st->rank = r;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kHistBins; i += 256) hist[i] = 0;
-}
-
-__global__ __launch_bounds__(256) void k_tau_clear(unsigned int *hist) {
-    for (int i = threadIdx.x; i < kHistBins; i += 256) hist[i] = 0;
+    for (int i = 0; i < per; ++i) hist[t * per + i] = 0;
 }
 
 hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t count,
                             unsigned int *hist, TauState *st) {
-    hipLaunchKernelGGL(k_tau_init, dim3(1), dim3(1), 0, lc.stream, st,
-                       (unsigned long long)((count - 1) / 2));
+    hipLaunchKernelGGL(k_tau_init, dim3(1), dim3(256), 0, lc.stream, st,
+                       (unsigned long long)((count - 1) / 2), hist);
     const int shifts[3] = {21, 10, 0};
     const unsigned int pmasks[3] = {0u, 0xFFE00000u, 0xFFFFFC00u};
-    int64_t blocks = (count + 255) / 256;
-    const int64_t cap = (int64_t)lc.num_cu * 16;
+    int64_t blocks = (count / 4 + 255) / 256;
+    const int64_t cap = (int64_t)lc.num_cu * 4;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_tau_clear, dim3(1), dim3(256), 0, lc.stream, hist);
     for (int pass = 0; pass < 3; ++pass) {
         hipLaunchKernelGGL(k_tau_hist, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, count,
                            shifts[pass], pmasks[pass], st, hist);
@@ -114,19 +154,32 @@ __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t 
     }
     unsigned long long below = 0;
     const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += stride) {
-        const double x = (double)fabsf(alpha[e]);
-        if (x < lo) {
-            ++below;
-        } else if (x <= hi) {
-            unsigned long long slot = atomicAdd(&st->ncand, 1ull);
-            if ((int64_t)slot < cap) cand[slot] = e;
+    const int64_t n4 = count / 4;
+    const float4 *a4 = reinterpret_cast<const float4 *>(alpha);
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n4 + 1; q += stride) {
+        float vv[4];
+        int cnt = 4;
+        if (q < n4) {
+            const float4 f = a4[q];
+            vv[0] = f.x; vv[1] = f.y; vv[2] = f.z; vv[3] = f.w;
+        } else {
+            cnt = (int)(count - n4 * 4);
+            for (int u = 0; u < cnt; ++u) vv[u] = alpha[n4 * 4 + u];
+        }
+        for (int u = 0; u < cnt; ++u) {
+            const double x = (double)fabsf(vv[u]);
+            if (x < lo) {
+                ++below;
+            } else if (x <= hi) {
+                const unsigned long long slot = atomicAdd(&st->ncand, 1ull);
+                if ((int64_t)slot < cap) cand[slot] = q * 4 + u;
+            }
         }
     }
     red[threadIdx.x] = below;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
         __syncthreads();
     }
     if (threadIdx.x == 0 && red[0]) atomicAdd(&st->below, red[0]);
@@ -134,8 +187,8 @@ __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t 
 
 hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
                       const double *max_margin, TauState *st, int64_t *cand, int64_t cap) {
-    int64_t blocks = (count + 255) / 256;
-    const int64_t bcap = (int64_t)lc.num_cu * 16;
+    int64_t blocks = (count / 4 + 256) / 256;
+    const int64_t bcap = (int64_t)lc.num_cu * 8;
     if (blocks > bcap) blocks = bcap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_tau_gather, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, count,
@@ -143,20 +196,88 @@ hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
     return hipGetLastError();
 }
 
-// FP64 recompute of each candidate entry e = pixel * k + j.
+// FP64 recompute of each candidate entry e = pixel * k + j, one wave per
+// candidate: element-wise steps run across lanes, every sum runs in lane 0 in
+// t order, so the result is the same bit pattern as a sequential evaluation.
 __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, int W, int p,
                                                        const double *wmask, const float *omega,
                                                        int k, const int64_t *cand, int64_t ncand,
                                                        double *vals) {
-    const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
+#pragma clang fp contract(off)
+    __shared__ double s[15 * 15];
+    __shared__ double sh_mu, sh_nu2;
+    const int64_t c = blockIdx.x;
     if (c >= ncand) return;
-    double s[15 * 15];
     const int64_t e = cand[c];
     const int64_t pix = e / k;
     const int j = (int)(e - pix * k);
-    const int n = p * p;
-    patch_s64(rgb, H, W, p, wmask, pix, s);
-    vals[c] = fabs(dot64(omega + (int64_t)j * n, s, n));
+    const int n = p * p, h = (p - 1) / 2;
+    const int64_t N = (int64_t)H * W;
+    const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
+    const int lane = threadIdx.x;
+    for (int t = lane; t < n; t += 64) {
+        const int u = t / p, v = t - u * p;
+        const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + v - h, W);
+        s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
+    }
+    __syncthreads();
+    if (lane == 0) {
+        double sum = 0.0;
+        for (int t = 0; t < n; ++t) sum = sum + s[t];
+        sh_mu = sum / (double)n;
+    }
+    __syncthreads();
+    const double mu = sh_mu;
+    for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
+    __syncthreads();
+    if (lane == 0) {
+        double nu2 = 0.0;
+        for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
+        sh_nu2 = nu2;
+    }
+    __syncthreads();
+    const double nu2 = sh_nu2;
+    const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
+    for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / nu;
+    __syncthreads();
+    if (lane == 0) {
+        const float *om = omega + (int64_t)j * n;
+        double acc = 0.0;
+        for (int t = 0; t < n; ++t) acc = acc + (double)om[t] * s[t];
+        vals[c] = fabs(acc);
+    }
+}
+
+// Small candidate sets: rank of every candidate by direct comparison (ties
+// broken by index) in one workgroup; the candidate of the target rank wins.
+constexpr int kDirect = 4096;
+__global__ __launch_bounds__(1024) void k_tau_select_direct(const double *vals, int64_t ncand,
+                                                             double frac, TauState *st) {
+    __shared__ double v[kDirect];
+    for (int i = threadIdx.x; i < ncand; i += 1024) v[i] = vals[i];
+    __syncthreads();
+    const unsigned long long r0 = st->rank0, below = st->below;
+    const bool ok = (r0 >= below) && (r0 - below < (unsigned long long)ncand);
+    if (!ok) {
+        if (threadIdx.x == 0) {
+            st->median = __longlong_as_double(0x7FF8000000000000ll);
+            st->tau = st->median;
+        }
+        return;
+    }
+    const int target = (int)(r0 - below);
+    for (int i = threadIdx.x; i < ncand; i += 1024) {
+        const double x = v[i];
+        int rank = 0;
+        for (int q = 0; q < ncand; ++q) {
+            const double y = v[q];
+            rank += (y < x) || (y == x && q < i);
+        }
+        if (rank == target) {
+            st->median = x;
+            st->tau = frac * x;
+        }
+    }
 }
 
 // Single-workgroup radix select of rank (rank0 - below) among the FP64
@@ -216,9 +337,13 @@ hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p
                       int64_t ncand, double *vals, double frac, TauState *st) {
     (void)n;
     if (ncand > 0)
-        hipLaunchKernelGGL(k_tau_recompute, dim3((unsigned)((ncand + 63) / 64)), dim3(64), 0,
-                           lc.stream, rgb, H, W, p, wmask, omega, k, cand, ncand, vals);
-    hipLaunchKernelGGL(k_tau_select64, dim3(1), dim3(1024), 0, lc.stream, vals, ncand, frac, st);
+        hipLaunchKernelGGL(k_tau_recompute, dim3((unsigned)ncand), dim3(64), 0, lc.stream, rgb, H, W,
+                           p, wmask, omega, k, cand, ncand, vals);
+    if (ncand <= kDirect)
+        hipLaunchKernelGGL(k_tau_select_direct, dim3(1), dim3(1024), 0, lc.stream, vals, ncand, frac,
+                           st);
+    else
+        hipLaunchKernelGGL(k_tau_select64, dim3(1), dim3(1024), 0, lc.stream, vals, ncand, frac, st);
     return hipGetLastError();
 }
 

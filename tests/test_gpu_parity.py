@@ -232,6 +232,25 @@ def test_loglik_overflow_fixup_case(ctx):
     _ll_check(got, ref)
 
 
+def test_loglik_overflow_case_full_image(ctx):
+    """Same construction on the full-image path (texture term on the matrix
+    cores): the reference must move up by the dynamic rescale."""
+    H, W = 16, 24
+    rgb = np.full((3, H, W), 0.5, np.float32)
+    rgb[:, 8, 9] = 1.5
+    rgb[:, 3, 20] = -0.7
+    w = make_workload("fix2", H=H, W=W, R=1, p=3, k=8, seed=1, per_region=2)
+    w.rgb = rgb
+    w.sample_pix = np.array([8 * W + 9, 8 * W + 11, 0, 3 * W + 20, 3 * W + 23], np.int32)
+    w.sample_label = np.array([0, 0, 0, 1, 1], np.int32)
+    w.L = 2
+    w.k = 8
+    masks = np.zeros((H * W, 1), np.uint64)
+    masks[::3, 0] = np.uint64(0b10110)
+    got, ref = _loglik_both(ctx, w, masks)
+    _ll_check(got, ref)
+
+
 def test_loglik_empty_subset_and_single_sample_labels(ctx):
     w = make_workload("one", H=20, W=23, R=3, p=5, k=40, seed=3, per_region=1)
     masks, _, _ = oracle.full_masks(w)
