@@ -137,6 +137,7 @@ def main():
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    lse_stats = ctx.last_loglik_stats()
     parzen_ms, parzen_n = ctx.profile_read("parzen")
     analyze_ms, analyze_n = ctx.profile_read("analyze")
     cos_ms, cos_n = ctx.profile_read("cosupport")
@@ -167,6 +168,7 @@ def main():
         "cosupport_avg_launch_ms": cos_ms / max(cos_n, 1),
         "edt_ms_per_step": edt_ms / args.steps,
         "px_per_s": w.N / (ms_per_step / 1e3),
+        "lse_reference_events": lse_stats,
     }
 
     cpu = None

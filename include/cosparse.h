@@ -162,6 +162,17 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
                     const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
                     float *loglik);
 
+typedef struct {
+    int64_t rescaled_chunks;  /* wave-chunks whose log-sum-exp reference moved up   */
+    int64_t overflow_tiles;   /* (label, tile) pairs whose fast sum overflowed       */
+    int64_t exact_tiles;      /* (label, tile) pairs finished by the exact two-pass  */
+                              /* kernel (overflow, non-finite or empty sums)         */
+} cs_loglik_stats;
+
+/* Counters of the last cs_label_loglik call on this context (full-image path;
+ * zeros for a pixel subset).  Synchronises the stream. */
+int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats);
+
 /* Kernel timing on the context stream (HIP events around each launch of the
  * named kernel).  cs_profile_enable(ctx, 1) starts recording and clears totals;
  * cs_profile_read synchronises and returns the summed milliseconds and launch

@@ -9,7 +9,7 @@ from typing import Optional
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libcosparse.so")
+_SO = os.environ.get("COSPARSE_LIBRARY") or os.path.join(_HERE, "libcosparse.so")
 
 CS_OK = 0
 CS_ERR_ARG = 1
@@ -31,6 +31,11 @@ class _LoglikParamsC(ctypes.Structure):
                 ("normalise", ctypes.c_int)]
 
 
+class _LoglikStatsC(ctypes.Structure):
+    _fields_ = [("rescaled_chunks", ctypes.c_int64), ("overflow_tiles", ctypes.c_int64),
+                ("exact_tiles", ctypes.c_int64)]
+
+
 class _CosupportStatsC(ctypes.Structure):
     _fields_ = [("recomputed", ctypes.c_int64), ("max_margin", ctypes.c_double)]
 
@@ -47,6 +52,7 @@ SIGNATURES = {
     "cs_texture_similarity": (_I, [_P, _P, _I64, _P, _I64, _I, _P]),
     "cs_label_loglik": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, _I64, _I,
                              ctypes.POINTER(_LoglikParamsC), _P, _I64, _P]),
+    "cs_last_loglik_stats": (_I, [_P, ctypes.POINTER(_LoglikStatsC)]),
     "cs_profile_enable": (_I, [_P, _I]),
     "cs_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }
@@ -229,6 +235,12 @@ class Context:
                                           0 if pix_subset is None else pix_subset.numel(),
                                           _ptr(out) if out.numel() else None))
         return out
+
+    def last_loglik_stats(self) -> dict:
+        st = _LoglikStatsC()
+        self._check(lib().cs_last_loglik_stats(self._h, ctypes.byref(st)))
+        return {"rescaled_chunks": int(st.rescaled_chunks),
+                "overflow_tiles": int(st.overflow_tiles), "exact_tiles": int(st.exact_tiles)}
 
     def profile_enable(self, on: bool = True):
         self._check(lib().cs_profile_enable(self._h, int(on)))

@@ -21,6 +21,8 @@ SOURCES = ["cs_host.hip", "k_analyze.hip", "k_tau.hip", "k_tsm.hip", "k_samples.
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # MFMA results straight into VGPRs (no accumulation-register reads)
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wno-unused-command-line-argument"]
 
 

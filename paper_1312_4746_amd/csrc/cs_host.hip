@@ -41,6 +41,8 @@ struct cs_ctx {
     std::vector<Span> spans;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<double, int64_t>> totals;
+    // device counters of the last full-image log-likelihood call (4 x u32) or null
+    const unsigned int *loglik_counters = nullptr;
 };
 
 namespace {
@@ -421,12 +423,18 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_edt = cv.take(edt_scratch_bytes(H, W, L));
     // full-image path: FP8 sample features for the MFMA texture term and the fix-up queue
     const bool fast = pix_subset == nullptr;
-    const int KP = (k + 4 + 127) / 128 * 128;
+    const int KP = (k + 2 + 127) / 128 * 128;
     const int tiles_x = (W + 7) / 8, tiles_y = (H + 2 * kParzenRB - 1) / (2 * kParzenRB);
     const int64_t ntiles = (int64_t)tiles_x * tiles_y;
-    const size_t o_feat = fast ? cv.take((size_t)M * KP) : 0;
-    const size_t o_fix = fast ? cv.take(sizeof(int2) * (size_t)(ntiles + 3) / 4 * 4 * L) : 0;
+    const int64_t ngroups = (ntiles + 3) / 4, ntiles_pad = ngroups * 4;
+    const int64_t Mpad_max = M + (int64_t)(kStreamChunk - 1) * L;
+    const size_t o_feat = fast ? cv.take((size_t)Mpad_max * KP) : 0;
+    const size_t o_srec = fast ? cv.take(sizeof(float) * 8 * (size_t)Mpad_max) : 0;
+    const size_t o_fix = fast ? cv.take(sizeof(int2) * (size_t)ntiles_pad * L) : 0;
     const size_t o_fcnt = cv.take(sizeof(unsigned int) * 4);
+    const size_t o_meta = cv.take(sizeof(int32_t) * (2 * (size_t)L + 1));
+    const size_t o_coef = cv.take(sizeof(float4) * (size_t)L *
+                                  (size_t)(fast ? ntiles_pad * kTilePix : npix));
     int rc = ensure_ws(ctx, cv.off);
     if (rc) return rc;
     int32_t *bc = (int32_t *)(ctx->ws + o_bc), *tf = (int32_t *)(ctx->ws + o_tf);
@@ -463,9 +471,15 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         Timed t(ctx, "edt");
         HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest, (int32_t *)(ctx->ws + o_edt)));
     }
+    StreamSegs segs{};
+    for (int l = 0; l < L; ++l) {
+        segs.seg[l + 1] = segs.seg[l] + counts[l];
+        segs.pseg[l + 1] = segs.pseg[l] + (counts[l] + kStreamChunk - 1) / kStreamChunk * kStreamChunk;
+    }
     if (fast) {
-        Timed t(ctx, "features");
-        HIP_TRY(launch_sample_features(lc, recs, M, k, KP, (uint8_t *)(ctx->ws + o_feat)));
+        Timed t(ctx, "stream");
+        HIP_TRY(launch_stream_build(lc, recs, k, KP, L, segs, segs.pseg[L], (uint8_t *)(ctx->ws + o_feat),
+                                    (float *)(ctx->ws + o_srec)));
     }
     unsigned int *fcnt = (unsigned int *)(ctx->ws + o_fcnt);
     ParzenArgs pa{};
@@ -499,15 +513,24 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     }
     std::stable_sort(pa.label_order, pa.label_order + L,
                      [&](int x, int y) { return counts[x] > counts[y]; });
+    float4 *coef = (float4 *)(ctx->ws + o_coef);
+    pa.coef = coef;
+    pa.coef_tiled = fast ? 1 : 0;
+    pa.tiles_x = tiles_x;
+    pa.ntiles_real = (int)ntiles;
+    pa.ntiles_pad = (int)ntiles_pad;
+    {
+        Timed t(ctx, "coef");
+        HIP_TRY(launch_coef(lc, pa, coef));
+    }
     HIP_TRY(launch_fill_u32(lc, cnt, 2, 0u));
     if (fast) {
         ParzenFastArgs fa{};
         fa.rgb = rgb;
         fa.masks = masks;
-        fa.recs = recs;
         fa.feat = (const uint8_t *)(ctx->ws + o_feat);
-        fa.d2 = d2;
-        fa.nearest = nearest;
+        fa.rec = (const float *)(ctx->ws + o_srec);
+        fa.coef = coef;
         fa.loglik = loglik;
         fa.work_counter = fcnt;
         fa.fix_count = fcnt + 1;
@@ -518,18 +541,22 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         fa.k = k;
         fa.ksteps = KP / 128;
         fa.tiles_x = tiles_x;
-        fa.tiles_y = tiles_y;
         fa.ntiles = (int)ntiles;
-        fa.ngroups = (int)((ntiles + 3) / 4);
-        fa.fix_cap = fa.ngroups * 4 * L;
-        fa.alpha_rho = pa.alpha_rho;
+        fa.ngroups = (int)ngroups;
+        fa.fix_cap = (int)(ntiles_pad * L);
         fa.sigma_c = pa.sigma_c;
-        fa.beta_scale = pa.beta_scale;
-        fa.rho_floor = pa.rho_floor;
-        std::memcpy(fa.seg_off, pa.seg_off, sizeof(pa.seg_off));
-        std::memcpy(fa.label_order, pa.label_order, sizeof(pa.label_order));
-        std::memcpy(fa.kconst, pa.kconst, sizeof(pa.kconst));
+        // per-label chunk ranges and the label order, staged through the upper
+        // half of the pinned buffer (its previous copy finished at the
+        // synchronisation above)
+        int32_t *meta_h = (int32_t *)(ctx->pinned + kPinnedBytes / 2);
+        for (int l = 0; l <= L; ++l) meta_h[l] = segs.pseg[l] / kStreamChunk;
+        for (int l = 0; l < L; ++l) meta_h[L + 1 + l] = pa.label_order[l];
+        int32_t *meta_d = (int32_t *)(ctx->ws + o_meta);
+        HIP_TRY(hipMemcpyAsync(meta_d, meta_h, sizeof(int32_t) * (2 * (size_t)L + 1), hipMemcpyHostToDevice,
+                               ctx->stream));
+        fa.meta = meta_d;
         HIP_TRY(launch_fill_u32(lc, fcnt, 4, 0u));
+        ctx->loglik_counters = fcnt;
         {
             Timed t(ctx, "parzen");
             HIP_TRY(launch_parzen_mfma(lc, fa));
@@ -538,13 +565,13 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         pa.fixlist = fa.fixlist;
         pa.fix_count = fa.fix_count;
         pa.fix_cap = fa.fix_cap;
-        pa.tiles_x = tiles_x;
-        pa.tiles = (int)((ntiles + 3) / 4 * 4);
+        pa.tiles = (int)ntiles_pad;
         {
             Timed t(ctx, "parzen_fixup");
             HIP_TRY(launch_parzen(lc, pa));
         }
     } else {
+        ctx->loglik_counters = nullptr;
         Timed t(ctx, "parzen");
         HIP_TRY(launch_parzen(lc, pa));
     }
@@ -552,6 +579,21 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         Timed t(ctx, "normalise");
         HIP_TRY(launch_normalise(lc, loglik, npix, L));
     }
+    return CS_OK;
+}
+
+int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats) {
+    if (!ctx || !stats) return CS_ERR_ARG;
+    stats->rescaled_chunks = stats->overflow_tiles = stats->exact_tiles = 0;
+    if (!ctx->loglik_counters) return CS_OK;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, ctx->loglik_counters, 4 * sizeof(unsigned int),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    unsigned int c[4];
+    std::memcpy(c, ctx->pinned, sizeof c);
+    stats->exact_tiles = c[1];
+    stats->rescaled_chunks = c[2];
+    stats->overflow_tiles = c[3];
     return CS_OK;
 }
 

@@ -15,8 +15,12 @@ constexpr int kTilePx = 64;
 // Words of a sample record (see SampleRec).
 constexpr int kRecWords = 16;
 // 16-pixel row blocks per wave in the MFMA Parzen kernel: a wave owns an
-// 8 x (2 kParzenRB) pixel tile.
+// 8 x (2 kParzenRB) pixel tile of kTilePix pixels.
 constexpr int kParzenRB = 2;
+constexpr int kTilePix = 8 * 2 * kParzenRB;
+// Samples per chunk of the padded sample stream (label segments are rounded
+// up to whole chunks).
+constexpr int kStreamChunk = 64;
 // Maximum label count and co-support length handled by the kernels.
 constexpr int kMaxLabels = 64;
 constexpr int kMaxK = 256;
@@ -109,6 +113,10 @@ struct ParzenArgs {
     const unsigned int *fix_count;
     int fix_cap;
     int tiles_x;
+    // coefficients {nA, nB, -R, K} (k_coef): [label][npix] for a pixel list, or
+    // tiled [label][ntiles_pad][kTilePix] for the full image
+    const float4 *coef;
+    int coef_tiled, ntiles_real, ntiles_pad;
     int H, W, L, k, nw32;
     int64_t npix;
     int tiles;               // ceil(npix / 64)
@@ -118,28 +126,32 @@ struct ParzenArgs {
     double kconst[kMaxLabels];  // -log m_i - log(2 pi) - 1.5 log(2 pi sigma_c^2)
 };
 hipError_t launch_parzen(const LaunchCtx &lc, const ParzenArgs &a);
+hipError_t launch_coef(const LaunchCtx &lc, const ParzenArgs &a, float4 *coef);
 
+struct StreamSegs {
+    int seg[kMaxLabels + 1];   // label segments of the sorted samples
+    int pseg[kMaxLabels + 1];  // the same segments rounded up to whole chunks
+};
 struct ParzenFastArgs {
     const float *rgb;
     const uint64_t *masks;
-    const SampleRec *recs;
-    const uint8_t *feat;     // M x 128*ksteps FP8 sample features
-    const int32_t *d2;       // L x N
-    const int32_t *nearest;  // L x N
+    const uint8_t *feat;   // Mpad x 128*ksteps FP8 sample features (swizzled rows)
+    const float *rec;      // Mpad x 8 {x, y, r, g, b, 0, 0, 0}
+    const float4 *coef;    // tiled: [label][group*4 + tile][kTilePix] {nA, nB, -R, K}
     float *loglik;
     unsigned int *work_counter;
-    unsigned int *fix_count;
+    unsigned int *fix_count;  // [0] queued (label, tile), [1] rescaled wave-chunks, [2] overflows
     int2 *fixlist;
     int fix_cap;
     int H, W, L, k, ksteps;
-    int tiles_x, tiles_y, ntiles, ngroups;
-    double alpha_rho, sigma_c, beta_scale, rho_floor;
-    int seg_off[kMaxLabels + 1];
-    int label_order[kMaxLabels];
-    double kconst[kMaxLabels];
+    int tiles_x, ntiles, ngroups;
+    double sigma_c;
+    // device: [0..L] first chunk of each label's padded segment (chunk units),
+    // [L+1 .. 2L] the labels by decreasing sample count
+    const int *meta;
 };
-hipError_t launch_sample_features(const LaunchCtx &lc, const SampleRec *recs, int64_t M, int k,
-                                  int KP, uint8_t *feat);
+hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,
+                               const StreamSegs &segs, int64_t Mpad, uint8_t *feat, float *rec);
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a);
 hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
 hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, unsigned int v);

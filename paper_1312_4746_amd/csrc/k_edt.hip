@@ -91,15 +91,15 @@ __global__ __launch_bounds__(64) void k_edt_col_fill(const uint8_t *seeds, int H
     }
 }
 
-__global__ __launch_bounds__(256) void k_edt_rows(const int32_t *colrow, int H, int W,
-                                                   int32_t *d2, int32_t *nearest) {
+__global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H, int W,
+                                                    int32_t *d2, int32_t *nearest) {
     extern __shared__ int32_t lds[];
     int32_t *f = lds;        // squared column distance, kInf where the column has no seed
     int32_t *rowof = lds + W;
     const int r = blockIdx.x, l = blockIdx.y;
     const int64_t N = (int64_t)H * W;
     const int32_t *cr = colrow + (int64_t)l * N + (int64_t)r * W;
-    for (int c = threadIdx.x; c < W; c += 256) {
+    for (int c = threadIdx.x; c < W; c += blockDim.x) {
         const int q = cr[c];
         rowof[c] = q;
         f[c] = q < 0 ? kInf : (r - q) * (r - q);
@@ -107,24 +107,25 @@ __global__ __launch_bounds__(256) void k_edt_rows(const int32_t *colrow, int H, 
     __syncthreads();
     int32_t *dd = d2 + (int64_t)l * N + (int64_t)r * W;
     int32_t *nn = nearest + (int64_t)l * N + (int64_t)r * W;
-    for (int c = threadIdx.x; c < W; c += 256) {
+    for (int c = threadIdx.x; c < W; c += blockDim.x) {
         int best = f[c], bq = c;
         const int span = max(c, W - 1 - c);
-        for (int d = 1; d <= span; ++d) {
-            const int d2v = d * d;
-            if (d2v >= best) break;
-            const int ql = c - d, qr = c + d;
-            if (ql >= 0) {
-                const int v = d2v + f[ql];
-                if (v < best) {
-                    best = v;
+        // outward scan in blocks of 4 offsets (independent LDS reads), stopping
+        // once the smallest remaining offset squared reaches the best value
+        for (int d0 = 1; d0 <= span && d0 * d0 < best; d0 += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int d = d0 + u;
+                const int d2v = d * d;
+                const int ql = c - d, qr = c + d;
+                const int vl = ql >= 0 ? d2v + f[ql] : kInf;
+                const int vr = qr < W ? d2v + f[qr] : kInf;
+                if (vl < best) {
+                    best = vl;
                     bq = ql;
                 }
-            }
-            if (qr < W) {
-                const int v = d2v + f[qr];
-                if (v < best) {
-                    best = v;
+                if (vr < best) {
+                    best = vr;
                     bq = qr;
                 }
             }
@@ -157,7 +158,9 @@ hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, i
     hipError_t e = hipFuncSetAttribute((const void *)k_edt_rows,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edt_rows, dim3(H, L), dim3(256), lds, lc.stream, colrow, H, W, d2, nearest);
+    int threads = (W + 63) / 64 * 64;
+    if (threads > 1024) threads = 1024;
+    hipLaunchKernelGGL(k_edt_rows, dim3(H, L), dim3(threads), lds, lc.stream, colrow, H, W, d2, nearest);
     return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@ namespace cs {
 
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
+constexpr int kRefSubset = 8;
+constexpr float kRefMargin = 48.0f;
 
 template <int NW>
 __device__ __forceinline__ float pair_e(float px, float py, float pr, float pg, float pb,
@@ -49,6 +51,76 @@ __device__ __forceinline__ float pair_e(float px, float py, float pr, float pg, 
     return e;
 }
 
+// Per (label, pixel) coefficients of the pair exponent in log2 units, from
+// the exact nearest-sample distance d (FP64, rounded once):
+//   nA = -log2(e) / (2 rho^2), nB = -log2(e) / beta, rho = alpha_rho max(d, r_f),
+//   K  = -log m_i - log(2 pi) - 1.5 log(2 pi sigma_c^2) - log(rho^2),
+//   nR = -R with the log-sum-exp reference R = min(U, e^ + kRefMargin):
+//   U = nA d^2 bounds every exponent from above, e^ is the largest exponent
+//   over the nearest sample and kRefSubset strided samples of the label (an
+//   achieved value, so the sum is at least 2^-kRefMargin).
+// coef[l * npix + i] = {nA, nB, nR, K}; pixel i is subset[i] or i.
+// Tiled layout: slot i = tile * kTilePix + q, q -> (x0 + q % 8, y0 + q / 8);
+// slots outside the image get {0, 0, -200, 0} (their terms vanish).
+template <int NW>
+__global__ __launch_bounds__(256) void k_coef(ParzenArgs a, float4 *__restrict__ coef) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int l = blockIdx.y;
+    const int64_t nslots = a.coef_tiled ? (int64_t)a.ntiles_pad * kTilePix : a.npix;
+    if (i >= nslots) return;
+    const int64_t N = (int64_t)a.H * a.W;
+    const int W64 = (a.k + 63) / 64;
+    int64_t pix;
+    if (a.coef_tiled) {
+        const int t = (int)(i / kTilePix), q = (int)(i - (int64_t)t * kTilePix);
+        const int ty = t / a.tiles_x;
+        const int px = (t - ty * a.tiles_x) * 8 + (q & 7), py = ty * 2 * kParzenRB + (q >> 3);
+        if (t >= a.ntiles_real || px >= a.W || py >= a.H) {
+            coef[(int64_t)l * nslots + i] = make_float4(0.0f, 0.0f, -200.0f, 0.0f);
+            return;
+        }
+        pix = (int64_t)py * a.W + px;
+    } else {
+        pix = a.subset ? (int64_t)a.subset[i] : i;
+    }
+    const uint32_t *mask32 = reinterpret_cast<const uint32_t *>(a.masks);
+    const float nC = (float)(-kLog2e / (2.0 * a.sigma_c * a.sigma_c));
+    const int d2min = a.d2[(int64_t)l * N + pix];
+    const int64_t nearp = a.nearest[(int64_t)l * N + pix];
+    const double fl2 = a.rho_floor * a.rho_floor;
+    const double dm = (double)d2min > fl2 ? (double)d2min : fl2;
+    const double rho2 = a.alpha_rho * a.alpha_rho * dm;
+    const double rho = sqrt(rho2);
+    const float nA = (float)(-kLog2e / (2.0 * rho2));
+    const float nB = (float)(-kLog2e / (a.beta_scale * rho));
+    const float K = (float)(a.kconst[l] - log(rho2));
+    uint32_t mx[NW], nrec[kRecWords];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        mx[w] = mask32[pix * 2 * W64 + w];
+        nrec[8 + w] = mask32[nearp * 2 * W64 + w];
+    }
+    nrec[0] = __float_as_uint((float)(nearp % a.W));
+    nrec[1] = __float_as_uint((float)(nearp / a.W));
+    nrec[2] = __float_as_uint(a.rgb[nearp]);
+    nrec[3] = __float_as_uint(a.rgb[N + nearp]);
+    nrec[4] = __float_as_uint(a.rgb[2 * N + nearp]);
+    const float px = (float)(pix % a.W), py = (float)(pix / a.W);
+    const float pr = a.rgb[pix], pg = a.rgb[N + pix], pb = a.rgb[2 * N + pix];
+    float est = pair_e<NW>(px, py, pr, pg, pb, mx, nrec, nA, nB, nC);
+    // Largest exponent over the nearest sample and an evenly strided subset of
+    // the label's samples: an achieved value close to the maximum.
+    const int s0 = a.seg_off[l], m = a.seg_off[l + 1] - s0;
+    const int nsub = m < kRefSubset ? m : kRefSubset;
+    const uint32_t *recw = reinterpret_cast<const uint32_t *>(a.recs);
+    for (int j = 0; j < nsub; ++j) {
+        const int64_t sidx = s0 + (int64_t)j * m / nsub;
+        est = fmaxf(est, pair_e<NW>(px, py, pr, pg, pb, mx, recw + sidx * kRecWords, nA, nB, nC));
+    }
+    const float U = nA * (float)d2min;
+    coef[(int64_t)l * nslots + i] = make_float4(nA, nB, -fminf(U, est + kRefMargin), K);
+}
+
 // The sample records and the outputs are separate restrict-qualified
 // arguments so that the compiler can prove the records are never written in
 // the kernel and fetch them with scalar loads.
@@ -56,7 +128,8 @@ template <int NW>
 __global__ __launch_bounds__(256) void k_parzen(ParzenArgs a, const uint32_t *__restrict__ recw,
                                                  float *__restrict__ loglik,
                                                  unsigned int *__restrict__ work_counter,
-                                                 unsigned int *__restrict__ fixups) {
+                                                 unsigned int *__restrict__ fixups,
+                                                 const float4 *__restrict__ coef) {
     const int lane = threadIdx.x & 63;
     const int64_t N = (int64_t)a.H * a.W;
     const int W64 = (a.k + 63) / 64;
@@ -65,6 +138,7 @@ __global__ __launch_bounds__(256) void k_parzen(ParzenArgs a, const uint32_t *__
     if (fixmode) {
         const unsigned int nf = *a.fix_count;
         total = (int)(nf < (unsigned int)a.fix_cap ? nf : (unsigned int)a.fix_cap);
+        if (total == 0) return;
     }
     const float nC = (float)(-kLog2e / (2.0 * a.sigma_c * a.sigma_c));
     const uint32_t *mask32 = reinterpret_cast<const uint32_t *>(a.masks);
@@ -102,29 +176,12 @@ __global__ __launch_bounds__(256) void k_parzen(ParzenArgs a, const uint32_t *__
 #pragma unroll
         for (int w = 0; w < NW; ++w) mx[w] = mask32[pix * 2 * W64 + w];
 
-        // Per (pixel, label) coefficients in FP64, rounded once.
-        const int d2min = a.d2[(int64_t)l * N + pix];
-        const int64_t nearp = a.nearest[(int64_t)l * N + pix];
-        const double fl2 = a.rho_floor * a.rho_floor;
-        const double dm = (double)d2min > fl2 ? (double)d2min : fl2;
-        const double rho2 = a.alpha_rho * a.alpha_rho * dm;
-        const double rho = sqrt(rho2);
-        const float nA = (float)(-kLog2e / (2.0 * rho2));
-        const float nB = (float)(-kLog2e / (a.beta_scale * rho));
-        const double K = a.kconst[l] - log(rho2);
-
-        // Reference from the nearest sample of the label.
-        uint32_t nrec[kRecWords];
-        nrec[0] = __float_as_uint((float)(nearp % a.W));
-        nrec[1] = __float_as_uint((float)(nearp / a.W));
-        nrec[2] = __float_as_uint(a.rgb[nearp]);
-        nrec[3] = __float_as_uint(a.rgb[N + nearp]);
-        nrec[4] = __float_as_uint(a.rgb[2 * N + nearp]);
-#pragma unroll
-        for (int w = 0; w < NW; ++w) nrec[8 + w] = mask32[nearp * 2 * W64 + w];
-        const float estar = pair_e<NW>(px, py, pr, pg, pb, mx, nrec, nA, nB, nC);
-        const float U = nA * (float)d2min;
-        float R = fminf(U, estar + 64.0f);
+        // Per (pixel, label) coefficients (see k_coef).
+        const float4 cf = fixmode ? coef[((int64_t)l * a.ntiles_pad + tile) * kTilePix + (lane & (kTilePix - 1))]
+                                  : coef[(int64_t)l * a.npix + i];
+        const float nA = cf.x, nB = cf.y;
+        float R = -cf.z;
+        const double K = (double)cf.w;
 
         const int s0 = a.seg_off[l], s1 = a.seg_off[l + 1];
         float S = 0.0f, S1 = 0.0f;
@@ -179,8 +236,30 @@ static hipError_t launch_parzen_nw(const LaunchCtx &lc, const ParzenArgs &a) {
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_parzen<NW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, a,
                        reinterpret_cast<const uint32_t *>(a.recs), a.loglik, a.work_counter,
-                       a.fixups);
+                       a.fixups, a.coef);
     return hipGetLastError();
+}
+
+template <int NW>
+static hipError_t launch_coef_nw(const LaunchCtx &lc, const ParzenArgs &a, float4 *coef) {
+    const int64_t nslots = a.coef_tiled ? (int64_t)a.ntiles_pad * kTilePix : a.npix;
+    hipLaunchKernelGGL(k_coef<NW>, dim3((unsigned)((nslots + 255) / 256), a.L), dim3(256), 0,
+                       lc.stream, a, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef(const LaunchCtx &lc, const ParzenArgs &a, float4 *coef) {
+    if (a.npix == 0) return hipSuccess;
+    switch (a.nw32) {
+        case 1: return launch_coef_nw<1>(lc, a, coef);
+        case 2: return launch_coef_nw<2>(lc, a, coef);
+        case 3: return launch_coef_nw<3>(lc, a, coef);
+        case 4: return launch_coef_nw<4>(lc, a, coef);
+        case 5: return launch_coef_nw<5>(lc, a, coef);
+        case 6: return launch_coef_nw<6>(lc, a, coef);
+        case 7: return launch_coef_nw<7>(lc, a, coef);
+        default: return launch_coef_nw<8>(lc, a, coef);
+    }
 }
 
 hipError_t launch_parzen(const LaunchCtx &lc, const ParzenArgs &a) {

@@ -3,43 +3,54 @@
 // bandwidth; Sec. 2 texture similarity inside the sum; Sec. 3.2 data term).
 //
 // The texture similarity of a pixel x and a sample y is the Hamming distance
-// of their co-support masks, TSM = |A| + |B| - 2 |A n B|.  It is a dot product
-// of two short feature vectors, so a whole 16-pixel x 16-sample block of it is
-// one MFMA: v_mfma_scale_f32_16x16x128_f8f6f4 with FP8 (E4M3) operands and
-// unit scales.  Pixel features: mask bit j in {0, 1} for j < k, then
-// [16 floor(|A|/16), |A| mod 16, 1, 1]; sample features: -2 x bit j, then
-// [1, 1, 16 floor(|B|/16), |B| mod 16].  Every operand is an exactly
-// representable FP8 value and every partial sum an integer below 2^10, so the
-// FP32 accumulator holds TSM exactly.
+// of their co-support masks, TSM = |A| + |B| - 2 |A n B|.  Its sample-dependent
+// part |B| - 2 |A n B| is a dot product of two short feature vectors, so a
+// whole 16-pixel x 16-sample block of it is one MFMA:
+// v_mfma_scale_f32_16x16x128_f8f6f4 with FP8 (E4M3) operands and unit scales.
+// Pixel features: mask bit j in {0, 1} for j < k, then [1, 1]; sample
+// features: -2 x bit j, then [16 floor(|B|/16), |B| mod 16].  Every operand is
+// an exactly representable FP8 value and every partial sum an integer below
+// 2^10, so the FP32 accumulator holds it exactly; the pixel's own |A| joins
+// the location operand below.
 //
-// Work decomposition.  A workgroup of 4 waves owns a group of four 8x8 pixel
-// tiles and one label; items come from an atomic queue, largest labels first.
-// The label's samples stream through LDS in chunks of 64 (features padded
-// against bank conflicts, position and colour as separate arrays), prefetched
-// into registers one chunk ahead.  Per 16-sample step a wave issues 4 x
-// KSTEPS MFMAs (one per 16-pixel row block and 128-feature slice) and then,
-// for its 16 pixels per lane x 1 sample per lane, the VALU work: the location
-// term needs one FMA per pair because the pixel offsets inside the tile are
-// compile-time constants, plus three colour differences and squares, three
-// FMAs combining the exponent with the log-sum-exp reference folded in, one
+// The location term nA |p - s|^2 is a second, FP32 MFMA (16x16x4): with the
+// pixel and sample positions taken relative to the tile origin it is the dot
+// product of nA [|p|^2, -2 px, -2 py, 1] and [1, sx, sy, |s|^2], exact in its
+// integer part, and the log-sum-exp reference rides in as the accumulator
+// input.  Per pair the VALU is left with the colour distance (three
+// differences, a square and two FMAs), two FMAs combining the terms, one
 // v_exp_f32 and one add.
 //
-// The reference R = min(U, e* + 64) (U = upper bound from the nearest sample
-// distance, e* = the nearest sample's exponent) keeps the sum in
-// [2^-64, 2^100] unless some sample beats the nearest one by more than about
-// 2^127; a wave that sees a sum outside that range queues its (label, tile)
-// for the exact two-pass kernel instead of writing.
+// Work decomposition.  A workgroup of 4 waves owns four 8x4 pixel tiles (one
+// per wave); a work item is such a group and one label, taken from an atomic
+// queue (labels of a group by decreasing sample count).  The samples of each
+// label are padded to whole chunks of 64 with samples that contribute exactly
+// 0.  Chunks are copied from HBM/L2 straight into LDS with global_load_lds (no
+// registers), double-buffered: chunk c+1 is in flight while chunk c is
+// computed.
+//
+// Log-sum-exp: every lane keeps its own reference per pixel, starting at the
+// per-pixel value from the coefficient kernel (an achieved exponent plus a
+// margin, capped by the upper bound from the nearest sample distance).  After
+// each chunk a lane sum above 2^64 moves that reference up by a whole power of
+// two (exact rescale).  At the end of the item the 16 lanes that share a pixel
+// (one sample column each) are combined at their largest reference.  An
+// overflowed, non-finite or empty sum queues the (label, tile) for the exact
+// two-pass kernel.
+#include <type_traits>
+
 #include "cs_internal.h"
 
 namespace cs {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void lds_void;
 
-constexpr double kLog2eF = 1.4426950408889634;
 constexpr double kLn2F = 0.6931471805599453;
-constexpr int kChunkS = 64;       // samples per LDS chunk
-constexpr float kFarAway = 1e30f;  // position of padding samples (term underflows to 0)
+constexpr double kLog2eF = 1.4426950408889634;
+constexpr int kChunkS = kStreamChunk;  // samples per chunk
+constexpr float kFarAway = 1e15f;      // x of padding samples: d^2 ~ 1e30, finite, term underflows to 0
 
 // E4M3 (bias 7) bit pattern of an integer 0..256 that is exactly representable
 // (0..16 and multiples of 16 up to 256).
@@ -50,59 +61,94 @@ __device__ __forceinline__ uint32_t fp8_of_int(uint32_t v) {
     return ((uint32_t)(e + 7) << 3) | m;
 }
 
-// Spread the 4 bits of a nibble into the 4 bytes of a word, each byte 0 or b.
+// Spread the 4 bits of a nibble into the 4 bytes of a word, each byte 0 or b:
+// the copies nib << 7i do not overlap, so bit i lands alone at bit 8i.
 __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib, uint32_t b) {
-    const uint32_t s = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
-    return s * b;
+    return ((nib * 0x00204081u) & 0x01010101u) * b;
 }
 
-// Sample features in MFMA order, KP bytes per sample (built from the sorted
-// sample records; see the header comment for the layout).
-__global__ __launch_bounds__(256) void k_sample_features(const SampleRec *recs, int64_t M, int k,
-                                                          int KP, uint8_t *feat) {
+// Physical 16-byte slot of logical slot p in a sample row (XOR swizzle inside
+// each 128-byte slice, keyed by the row inside its chunk, spreads LDS banks).
+__device__ __forceinline__ int swz(int p, int row) { return (p & ~7) | ((p & 7) ^ (row & 7)); }
+
+// Padded sample stream: for every padded slot s (label segments rounded up to
+// whole chunks), the FP8 feature row (swizzled) and a 32-byte record
+// {x, y, r, g, b, 0, 0, 0}; padding slots have zero features and x = 1e15.
+__global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int k, int KP, int L,
+                                                       StreamSegs segs, int64_t Mpad,
+                                                       uint8_t *feat, float *rec) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= M) return;
-    const uint32_t *rw = recs[s].w;
+    if (s >= Mpad) return;
+    int l = 0;
+    while (l + 1 < L && s >= segs.pseg[l + 1]) ++l;
+    const int64_t j = s - segs.pseg[l];
+    const bool real = j < (int64_t)(segs.seg[l + 1] - segs.seg[l]);
+    uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t cnt = 0;
-    uint32_t words[8];
-    for (int w = 0; w < 8; ++w) {
-        uint32_t v = rw[8 + w];
-        const int lo = 32 * w;
-        if (lo >= k) v = 0;
-        else if (k - lo < 32) v &= (1u << (k - lo)) - 1u;
-        words[w] = v;
-        cnt += __popc(v);
-    }
-    uint32_t *out = reinterpret_cast<uint32_t *>(feat + s * KP);
-    for (int q = 0; q < KP / 4; ++q) {  // 4 features per word
-        const int f0 = 4 * q;
-        uint32_t val = 0;
-        if (f0 < 256) val = nibble_bytes((words[f0 >> 5] >> (f0 & 31)) & 0xFu, 0xC0u);  // -2.0
-        for (int b = 0; b < 4; ++b) {
-            const int f = f0 + b;
-            uint32_t byte = 0xFFFFFFFFu;
-            if (f == k || f == k + 1) byte = 0x38u;  // 1.0
-            else if (f == k + 2) byte = fp8_of_int(16u * (cnt >> 4));
-            else if (f == k + 3) byte = fp8_of_int(cnt & 15u);
-            if (byte != 0xFFFFFFFFu) val = (val & ~(0xFFu << (8 * b))) | (byte << (8 * b));
+    float *ro = rec + s * 8;
+    if (real) {
+        const uint32_t *rw = recs[segs.seg[l] + j].w;
+        for (int w = 0; w < 8; ++w) {
+            uint32_t v = rw[8 + w];
+            const int lo = 32 * w;
+            if (lo >= k) v = 0;
+            else if (k - lo < 32) v &= (1u << (k - lo)) - 1u;
+            words[w] = v;
+            cnt += __popc(v);
         }
-        out[q] = val;
+        for (int q = 0; q < 5; ++q) ro[q] = __uint_as_float(rw[q]);
+    } else {
+        ro[0] = kFarAway;
+        for (int q = 1; q < 5; ++q) ro[q] = 0.0f;
+    }
+    ro[5] = ro[6] = ro[7] = 0.0f;
+    const int row = (int)(s & (kChunkS - 1));
+    uint32_t *fo = reinterpret_cast<uint32_t *>(feat + s * KP);
+    for (int p = 0; p < KP / 16; ++p) {  // logical 16-byte slot p holds features 16p..16p+15
+        uint32_t out4[4];
+        for (int q = 0; q < 4; ++q) {
+            const int f0 = 16 * p + 4 * q;
+            uint32_t val = 0;
+            if (real) {
+                if (f0 < 256) val = nibble_bytes((words[f0 >> 5] >> (f0 & 31)) & 0xFu, 0xC0u);  // -2.0
+                for (int b = 0; b < 4; ++b) {
+                    const int f = f0 + b;
+                    uint32_t byte = 0xFFFFFFFFu;
+                    if (f == k) byte = fp8_of_int(16u * (cnt >> 4));
+                    else if (f == k + 1) byte = fp8_of_int(cnt & 15u);
+                    if (byte != 0xFFFFFFFFu) val = (val & ~(0xFFu << (8 * b))) | (byte << (8 * b));
+                }
+            }
+            out4[q] = val;
+        }
+        uint32_t *dst = fo + 4 * swz(p, row);
+        for (int q = 0; q < 4; ++q) dst[q] = out4[q];
     }
 }
 
-hipError_t launch_sample_features(const LaunchCtx &lc, const SampleRec *recs, int64_t M, int k,
-                                  int KP, uint8_t *feat) {
-    hipLaunchKernelGGL(k_sample_features, dim3((unsigned)((M + 255) / 256)), dim3(256), 0,
-                       lc.stream, recs, M, k, KP, feat);
+hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,
+                               const StreamSegs &segs, int64_t Mpad, uint8_t *feat, float *rec) {
+    hipLaunchKernelGGL(k_stream_build, dim3((unsigned)((Mpad + 255) / 256)), dim3(256), 0, lc.stream,
+                       recs, k, KP, L, segs, Mpad, feat, rec);
     return hipGetLastError();
 }
 
-template <int KSTEPS, int RB>
-__global__ __launch_bounds__(256) void k_parzen_mfma(ParzenFastArgs a) {
+
+// Register budget: four waves per SIMD (128 VGPRs) with one 128-feature MFMA
+// step, two with the wider feature rows.
+template <int KSTEPS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 ? 4 : 2)))
+void k_parzen_mfma(ParzenFastArgs a) {
+    constexpr int RB = kParzenRB;
     constexpr int KP = 128 * KSTEPS;
-    constexpr int FSTRIDE = KP + 16;  // LDS row stride of the sample features (bank spread)
-    __shared__ __align__(16) uint8_t s_feat[kChunkS * FSTRIDE];
-    __shared__ float s_x[kChunkS], s_y[kChunkS], s_r[kChunkS], s_g[kChunkS], s_b[kChunkS];
+    constexpr int FEAT_B = kChunkS * KP;  // feature bytes per chunk
+    // Separate LDS objects per buffer: with the buffer known at compile time the
+    // compiler can tell that reads of one buffer do not depend on the copy in
+    // flight into the other, and does not wait for it.
+    __shared__ __align__(16) uint8_t s_feat0[FEAT_B];
+    __shared__ __align__(16) uint8_t s_feat1[FEAT_B];
+    __shared__ __align__(16) float s_rec0[kChunkS * 8];
+    __shared__ __align__(16) float s_rec1[kChunkS * 8];
     __shared__ int s_item;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -110,27 +156,62 @@ __global__ __launch_bounds__(256) void k_parzen_mfma(ParzenFastArgs a) {
     const int64_t N = (int64_t)a.H * a.W;
     const int W64 = (a.k + 63) / 64;
     const float nC = (float)(-kLog2eF / (2.0 * a.sigma_c * a.sigma_c));
-    const int total = a.ngroups * a.L;
     const uint32_t *mask32 = reinterpret_cast<const uint32_t *>(a.masks);
-    const uint64_t lastmask = (a.k % 64) ? ((1ull << (a.k % 64)) - 1ull) : ~0ull;
+    const int nitems = a.ngroups * a.L;
+    const int64_t coef_label_stride = (int64_t)a.ngroups * 4 * kTilePix;
+    // the lane's 32-feature slice q of the pixel features covers mask word
+    // 4q + g: which of its bits are real mask bits, which are the unit features
+    const int nw32 = (a.k + 31) / 32;
+    const uint32_t lastmask = (a.k & 31) ? (1u << (a.k & 31)) - 1u : ~0u;
+    uint32_t lowm[KSTEPS], spec[KSTEPS];
+#pragma unroll
+    for (int q = 0; q < KSTEPS; ++q) {
+        const int wi = 4 * q + g, rel = a.k - 32 * wi;
+        lowm[q] = wi < nw32 - 1 ? ~0u : wi == nw32 - 1 ? lastmask : 0u;
+        spec[q] = (rel >= 0 && rel < 32 ? 1u << rel : 0u) | (rel + 1 >= 0 && rel + 1 < 32 ? 1u << (rel + 1) : 0u);
+    }
+    const float wc = g == 0 ? 1.0f : 0.0f, wx = g == 1 ? 1.0f : 0.0f, wy = g == 2 ? 1.0f : 0.0f,
+                wq = g == 3 ? 1.0f : 0.0f;
+    uint32_t n_rescale = 0;  // wave-chunks whose reference moved (wave-uniform)
+    uint32_t n_overflow = 0; // (label, tile) items handed to the exact kernel on overflow
 
     for (;;) {
-        __syncthreads();
+        __syncthreads();  // the previous item's LDS reads are done
         if (tid == 0) s_item = (int)atomicAdd(a.work_counter, 1u);
         __syncthreads();
         const int item = s_item;
-        if (item >= total) break;
-        const int l = a.label_order[item / a.ngroups];
-        const int tile = (item - (item / a.ngroups) * a.ngroups) * 4 + wave;
+        if (item >= nitems) break;
+        // item -> (group of 4 tiles, label); labels of a group in order of
+        // decreasing sample count, so the queue ends with the short items
+        const int grp = item / a.L;
+        const int lab = a.meta[a.L + 1 + (item - grp * a.L)];
+        const int c0 = a.meta[lab], c1 = a.meta[lab + 1];
+        const int tile = grp * 4 + wave;
         const bool tile_ok = tile < a.ntiles;
         const int ty_t = tile_ok ? tile / a.tiles_x : 0;
         const int x0 = (tile_ok ? tile - ty_t * a.tiles_x : 0) * 8, y0 = ty_t * 2 * RB;
 
-        // ---- pixel state: lane holds pixels (rb, r) -> (x0 + 4(g&1) + r, y0 + 2rb + (g>>1))
-        float pr[RB][4], pg[RB][4], pb[RB][4], nA[RB][4], nB[RB][4], nR[RB][4], S[RB][4];
+        // Async copy of chunk c into a buffer pair.
+        auto issue = [&](int c, uint8_t *sf, float *sr) {
+            const int64_t s0 = (int64_t)c * kChunkS;
+#pragma unroll
+            for (int u = 0; u < FEAT_B / 4096; ++u) {
+                const uint8_t *src = a.feat + s0 * KP + u * 4096 + tid * 16;
+                __builtin_amdgcn_global_load_lds(src, (lds_void *)(sf + u * 4096 + wave * 1024), 16, 0, 0);
+            }
+            if (wave < 2) {
+                const float *src = a.rec + s0 * 8 + tid * 4;
+                __builtin_amdgcn_global_load_lds(src, (lds_void *)(sr + wave * 256), 16, 0, 0);
+            }
+        };
+        issue(c0, s_feat0, s_rec0);
+
+        // ---- pixel colours: lane holds pixels (rb, r) -> (x0 + 4(g&1) + r, y0 + 2rb + (g>>1)),
+        // the rows 4g + r of the MFMA result blocks
+        float pr[RB][4], pg[RB][4], pb[RB][4];
         bool anyvalid = false;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
@@ -140,294 +221,224 @@ __global__ __launch_bounds__(256) void k_parzen_mfma(ParzenFastArgs a) {
                 pr[rb][r] = a.rgb[pix];
                 pg[rb][r] = a.rgb[N + pix];
                 pb[rb][r] = a.rgb[2 * N + pix];
-                const int d2min = a.d2[(int64_t)l * N + pix];
-                const int64_t nearp = a.nearest[(int64_t)l * N + pix];
-                const double fl2 = a.rho_floor * a.rho_floor;
-                const double dm = (double)d2min > fl2 ? (double)d2min : fl2;
-                const double rho2 = a.alpha_rho * a.alpha_rho * dm;
-                const double rho = sqrt(rho2);
-                const float fA = (float)(-kLog2eF / (2.0 * rho2));
-                const float fB = (float)(-kLog2eF / (a.beta_scale * rho));
-                nA[rb][r] = fA;
-                nB[rb][r] = fB;
-                // exponent of the nearest sample (same operations as the pair loop)
-                int t = 0;
-                for (int w = 0; w < W64; ++w) {
-                    uint64_t m1 = a.masks[pix * W64 + w] ^ a.masks[nearp * W64 + w];
-                    if (w == W64 - 1) m1 &= lastmask;
-                    t += __popcll(m1);
-                }
-                const int nx = (int)(nearp % a.W), ny = (int)(nearp / a.W);
-                const float dx = (float)(px - nx), dy = (float)(py - ny);
-                const float d2n = fmaf(dx, dx, dy * dy);
-                const float dr = pr[rb][r] - a.rgb[nearp], dg = pg[rb][r] - a.rgb[N + nearp],
-                            db = pb[rb][r] - a.rgb[2 * N + nearp];
-                const float c2n = fmaf(db, db, fmaf(dg, dg, dr * dr));
-                const float estar = fmaf(fA, d2n, fmaf(nC, c2n, (float)t * fB));
-                const float U = fA * (float)d2min;
-                nR[rb][r] = -fminf(U, estar + 64.0f);
-                S[rb][r] = 0.0f;
             }
-        }
+        bool active = __ballot(anyvalid) != 0ull;  // wave-uniform
+        const bool wave_valid = active;
 
-        const bool wave_active = __ballot(anyvalid) != 0ull;
-
-        // ---- pixel features (MFMA A operand): row i = l%16 of row block rb is
-        // pixel rb*16 + jl of the tile = (x0 + (jl & 7), y0 + 2rb + (jl >> 3)).
-        i32x8 Aop[RB][KSTEPS];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            const int px = x0 + (jl & 7), py = y0 + 2 * rb + (jl >> 3);
-            const bool v = tile_ok && px < a.W && py < a.H;
-            const int64_t pix = v ? (int64_t)py * a.W + px : 0;
-            uint32_t cnt = 0;
-            for (int w = 0; w < 2 * W64; ++w) {
-                uint32_t m = mask32[pix * 2 * W64 + w];
-                const int lo = 32 * w;
-                if (lo >= a.k) m = 0;
-                else if (a.k - lo < 32) m &= (1u << (a.k - lo)) - 1u;
-                cnt += __popc(m);
-            }
-#pragma unroll
-            for (int q = 0; q < KSTEPS; ++q) {
-                const int f0 = 128 * q + 32 * g;  // first feature of this lane's slice
-                const int wi = f0 >> 5;
-                uint32_t bits = 0;
-                if (f0 < a.k && wi < 2 * W64) {
-                    bits = mask32[pix * 2 * W64 + wi];
-                    if (a.k - f0 < 32) bits &= (1u << (a.k - f0)) - 1u;
-                }
-#pragma unroll
-                for (int vv = 0; vv < 8; ++vv) {
-                    uint32_t val = nibble_bytes((bits >> (4 * vv)) & 0xFu, 0x38u);
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int f = f0 + 4 * vv + b;
-                        uint32_t byte = 0xFFFFFFFFu;
-                        if (f == a.k) byte = fp8_of_int(16u * (cnt >> 4));
-                        else if (f == a.k + 1) byte = fp8_of_int(cnt & 15u);
-                        else if (f == a.k + 2 || f == a.k + 3) byte = 0x38u;
-                        if (byte != 0xFFFFFFFFu) val = (val & ~(0xFFu << (8 * b))) | (byte << (8 * b));
-                    }
-                    if (!v) val = 0;
-                    Aop[rb][q][vv] = (int)val;
-                }
-            }
-        }
-
-        // ---- stream the label's samples
-        const int s0 = a.seg_off[l], s1 = a.seg_off[l + 1];
-        const int nchunk = (s1 - s0 + kChunkS - 1) / kChunkS;
-        // register prefetch of one chunk: features (KP/16 uint4 per sample, 64 samples)
-        constexpr int FV = kChunkS * KP / 16 / 256;  // uint4 per thread
-        uint4 pf[FV];
-        float pfx = kFarAway, pfy = 0.f, pfr = 0.f, pfg = 0.f, pfb = 0.f;
-        auto fetch = [&](int c) {
-            const int base = s0 + c * kChunkS;
-#pragma unroll
-            for (int u = 0; u < FV; ++u) {
-                const int e = tid + 256 * u;  // uint4 index inside the chunk
-                const int smp = e / (KP / 16), part = e - smp * (KP / 16);
-                if (base + smp < s1)
-                    pf[u] = reinterpret_cast<const uint4 *>(a.feat + (int64_t)(base + smp) * KP)[part];
-                else
-                    pf[u] = make_uint4(0u, 0u, 0u, 0u);
-            }
-            if (tid < kChunkS) {
-                if (base + tid < s1) {
-                    const uint32_t *rw = a.recs[base + tid].w;
-                    pfx = __uint_as_float(rw[0]);
-                    pfy = __uint_as_float(rw[1]);
-                    pfr = __uint_as_float(rw[2]);
-                    pfg = __uint_as_float(rw[3]);
-                    pfb = __uint_as_float(rw[4]);
-                } else {
-                    pfx = kFarAway;
-                    pfy = pfr = pfg = pfb = 0.f;
-                }
-            }
-        };
-        fetch(0);
-        const float xl = (float)(x0 + 4 * (g & 1)), yl = (float)(y0 + (g >> 1));
-
-        // One 16-sample step: the texture block on the matrix cores, then the
-        // per-pair VALU work; returns nothing, accumulates into S and tracks
-        // the largest exponent (relative to the lane's reference) in mx.
-        auto step = [&](int st, float (&mx)[RB][4]) {
-            const int js = st * 16 + jl;
-            i32x8 Bop[KSTEPS];
-#pragma unroll
-            for (int q = 0; q < KSTEPS; ++q) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(s_feat + js * FSTRIDE + 128 * q + 32 * g);
-                const uint4 lo4 = src[0], hi4 = src[1];
-                Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
-                               (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
-            }
-            f32x4 T[RB];
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                T[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int q = 0; q < KSTEPS; ++q)
-                    T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                        Aop[rb][q], Bop[q], T[rb], 0, 0, 0, 127, 0, 127);
-            }
-            const float sx = s_x[js], sy = s_y[js], sr = s_r[js], sg = s_g[js], sb = s_b[js];
-            const float tx = xl - sx, ty = yl - sy;
-            float dx[4], dy2[RB];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dx[r] = tx + (float)r;
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const float dy = ty + (float)(2 * rb);
-                dy2[rb] = dy * dy;
-            }
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float d2 = fmaf(dx[r], dx[r], dy2[rb]);
-                    const float dr = pr[rb][r] - sr, dg = pg[rb][r] - sg, db = pb[rb][r] - sb;
-                    const float c2 = fmaf(db, db, fmaf(dg, dg, dr * dr));
-                    float u = fmaf(T[rb][r], nB[rb][r], nR[rb][r]);
-                    u = fmaf(nC, c2, u);
-                    u = fmaf(nA[rb][r], d2, u);
-                    mx[rb][r] = fmaxf(mx[rb][r], u);
-                    S[rb][r] += __builtin_amdgcn_exp2f(u);
-                }
-            }
-        };
-
-        for (int c = 0; c < nchunk; ++c) {
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < FV; ++u) {
-                const int e = tid + 256 * u;
-                const int smp = e / (KP / 16), part = e - smp * (KP / 16);
-                *reinterpret_cast<uint4 *>(s_feat + smp * FSTRIDE + part * 16) = pf[u];
-            }
-            if (tid < kChunkS) {
-                s_x[tid] = pfx;
-                s_y[tid] = pfy;
-                s_r[tid] = pfr;
-                s_g[tid] = pfg;
-                s_b[tid] = pfb;
-            }
-            __syncthreads();
-            if (c + 1 < nchunk) fetch(c + 1);
-            if (!wave_active) continue;
-            float Ssave[RB][4], mx[RB][4];
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    Ssave[rb][r] = S[rb][r];
-                    mx[rb][r] = -INFINITY;
-                }
-#pragma unroll 1
-            for (int st = 0; st < kChunkS / 16; ++st) step(st, mx);
-            // Dynamic reference: a lane whose exponents reached 2^32 above its
-            // reference moves the reference up by a whole power of two (exact
-            // rescale of its partial sum); above 2^100 the chunk may have
-            // overflowed and is recomputed from the saved sums.
-            float mall = -INFINITY;
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) mall = fmaxf(mall, mx[rb][r]);
-            if (__ballot(mall > 32.0f)) {
-                bool redo = false;
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        if (mx[rb][r] > 32.0f) {
-                            const float sh = ceilf(mx[rb][r]);
-                            nR[rb][r] -= sh;
-                            const float f = __builtin_amdgcn_exp2f(-sh);
-                            S[rb][r] *= f;
-                            Ssave[rb][r] *= f;
-                            if (mx[rb][r] > 100.0f) redo = true;
-                        }
-                    }
-                if (__ballot(redo)) {
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            S[rb][r] = Ssave[rb][r];
-                            mx[rb][r] = -INFINITY;
-                        }
-#pragma unroll 1
-                    for (int st = 0; st < kChunkS / 16; ++st) step(st, mx);
-                }
-            }
-        }
-
-        // ---- combine the 16 lanes that share each pixel (one sample column
-        // each): common reference = their largest, partial sums rescaled.
-        bool bad = false;
-        float Rtot[RB][4], Stot[RB][4];
+        // ---- per-pixel coefficients of this label (log2 units)
+        const float4 *cf = a.coef + (int64_t)lab * coef_label_stride + (int64_t)tile * kTilePix;
+        float nB[RB][4];
+        f32x4 nRv[RB];  // -reference, the accumulator input of the location MFMA
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float Rl = -nR[rb][r];
-                float Rm = Rl;
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1) Rm = fmaxf(Rm, __shfl_xor(Rm, off));
-                float sp = S[rb][r] * __builtin_amdgcn_exp2f(Rl - Rm);
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1) sp += __shfl_xor(sp, off);
-                Rtot[rb][r] = Rm;
-                Stot[rb][r] = sp;
-                const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
-                const bool v = tile_ok && px < a.W && py < a.H;
-                if (v && !(sp <= 0x1p126f && sp > 0.0f)) bad = true;
+                const float4 v = cf[(2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r];
+                nB[rb][r] = v.y;
+                nRv[rb][r] = v.z;
             }
-        if (__ballot(bad)) {
-            if (lane == 0) {
-                const unsigned int slot = atomicAdd(a.fix_count, 1u);
-                if (slot < (unsigned int)a.fix_cap) a.fixlist[slot] = make_int2(l, tile);
+
+        // ---- pixel rows of both MFMAs: row i = lane%16 of row block rb is
+        // pixel rb*16 + jl of the tile = (x0 + (jl & 7), y0 + 2rb + (jl >> 3)).
+        // FP8 operand: the lane's 32-feature slice of the mask bits plus the
+        // two unit features at k, k+1.
+        // Location operand (FP32 MFMA, K = 4), positions relative to the tile
+        // origin: A[i] = [nA_i (dx^2 + dy^2) + nB_i |A_i|, -2 nA_i dx, -2 nA_i dy, nA_i]
+        // against B[j] = [1, sx, sy, sx^2 + sy^2], so that (A B)[i][j] =
+        // nA_i |p_i - s_j|^2 + nB_i |A_i|; the reference rides in as the
+        // accumulator input.
+        i32x8 Aop[RB][KSTEPS];
+        float Aloc[RB];
+        bool weak = false;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const int dxi = jl & 7, dyi = 2 * rb + (jl >> 3);
+            const bool v = tile_ok && x0 + dxi < a.W && y0 + dyi < a.H;
+            const int64_t pix = v ? (int64_t)(y0 + dyi) * a.W + x0 + dxi : 0;
+            const uint32_t *mw = mask32 + pix * 2 * W64;
+            uint32_t cnt = 0;
+            for (int w = 0; w < nw32; ++w) cnt += __popc(mw[w] & (w == nw32 - 1 ? lastmask : ~0u));
+#pragma unroll
+            for (int q = 0; q < KSTEPS; ++q) {
+                const uint32_t m = lowm[q] ? mw[4 * q + g] & lowm[q] : 0u;
+                const uint32_t ext = v ? (m | spec[q]) : 0u;
+#pragma unroll
+                for (int vv = 0; vv < 8; ++vv) Aop[rb][q][vv] = (int)nibble_bytes((ext >> (4 * vv)) & 0xFu, 0x38u);
             }
-            continue;
+            const float4 crow = cf[rb * 16 + jl];
+            const float nA = crow.x;
+            const float dx = (float)dxi, dy = (float)dyi;
+            Aloc[rb] = g == 0 ? fmaf(nA, fmaf(dx, dx, dy * dy), crow.y * (float)cnt)
+                     : g == 1 ? -2.0f * dx * nA : g == 2 ? -2.0f * dy * nA : nA;
+            // padding samples sit 1e15 px away; a bandwidth wide enough to
+            // reach them (or a non-finite one) goes to the exact kernel
+            weak |= v && !(nA < -1e-18f);
         }
-        if (jl == 0) {
+        bool item_bad = __ballot(weak) != 0ull;
+        if (item_bad) active = false;
+
+        const float x0f = (float)x0, y0f = (float)y0;
+        float S[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) S[rb][r] = 0.0f;
+
+        // One chunk computed from buffers (F, Rr) while the next one streams
+        // into (Fn, Rn).
+        auto process = [&](int c, const uint8_t *F, const float *Rr, uint8_t *Fn, float *Rn) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();  // chunk c resident in (F, Rr); the other pair is free
+            if (c + 1 < c1) issue(c + 1, Fn, Rn);
+            if (!active) return;
+#pragma unroll 1
+            for (int st = 0; st < kChunkS / 16; ++st) {
+                const int js = st * 16 + jl;
+                i32x8 Bop[KSTEPS];
+#pragma unroll
+                for (int q = 0; q < KSTEPS; ++q) {
+                    const int p0 = 8 * q + 2 * g;
+                    const uint4 lo4 = *reinterpret_cast<const uint4 *>(F + js * KP + 16 * swz(p0, js));
+                    const uint4 hi4 = *reinterpret_cast<const uint4 *>(F + js * KP + 16 * swz(p0 + 1, js));
+                    Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
+                                   (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
+                }
+                const float4 sxyrg = *reinterpret_cast<const float4 *>(Rr + js * 8);
+                const float sb = Rr[js * 8 + 4];
+                f32x4 T[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    T[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int q = 0; q < KSTEPS; ++q)
+                        T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(Aop[rb][q], Bop[q], T[rb], 0, 0,
+                                                                                  0, 127, 0, 127);
+                }
+                // this lane's entry g of the location column (one-hot weights,
+                // no divergent select)
+                const float sx = sxyrg.x - x0f, sy = sxyrg.y - y0f;
+                const float bl = fmaf(wq, fmaf(sx, sx, sy * sy), fmaf(wy, sy, fmaf(wx, sx, wc)));
+                f32x4 D[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) D[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Aloc[rb], bl, nRv[rb], 0, 0, 0);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float dr = pr[rb][r] - sxyrg.z, dg = pg[rb][r] - sxyrg.w, db = pb[rb][r] - sb;
+                        const float c2 = fmaf(db, db, fmaf(dg, dg, dr * dr));
+                        float u = fmaf(T[rb][r], nB[rb][r], D[rb][r]);
+                        u = fmaf(nC, c2, u);
+                        S[rb][r] += __builtin_amdgcn_exp2f(u);
+                    }
+            }
+            // A lane sum above 2^64 moves that pixel's reference up by a whole
+            // power of two (exact rescale).  Entering a chunk the sums are at
+            // most 2^64, so an overflowed sum means terms beyond 2^128 that make
+            // the earlier part negligible; such a tile goes to the exact kernel.
+            bool big = false;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) big |= !(S[rb][r] <= 0x1p64f);
+            if (__ballot(big)) {
+                ++n_rescale;
+                bool over = false;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float s = S[rb][r];
+                        if (!(s <= 0x1p64f)) {
+                            if (s <= 3.0e38f) {
+                                const int e = (int)((__float_as_uint(s) >> 23) & 0xFFu) - 127;
+                                S[rb][r] = ldexpf(s, -e);
+                                nRv[rb][r] -= (float)e;
+                            } else {
+                                over = true;
+                            }
+                        }
+                    }
+                if (__ballot(over)) {
+                    item_bad = true;
+                    active = false;
+                    ++n_overflow;
+                }
+            }
+        };
+        for (int c = c0; c < c1; c += 2) {
+            process(c, s_feat0, s_rec0, s_feat1, s_rec1);
+            if (c + 1 < c1) process(c + 1, s_feat1, s_rec1, s_feat0, s_rec0);
+        }
+        if (!wave_valid) continue;
+
+        // ---- end of item: combine the 16 lanes sharing each pixel (one sample
+        // column each) at their largest reference
+        bool bad = item_bad;
+        float Rtot[RB][4], Stot[RB][4];
+        if (!bad) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
+                    const float Rl = -nRv[rb][r];
+                    float Rm = Rl;
+#pragma unroll
+                    for (int off = 1; off < 16; off <<= 1) Rm = fmaxf(Rm, __shfl_xor(Rm, off));
+                    float sp = S[rb][r] * __builtin_amdgcn_exp2f(Rl - Rm);
+#pragma unroll
+                    for (int off = 1; off < 16; off <<= 1) sp += __shfl_xor(sp, off);
+                    Rtot[rb][r] = Rm;
+                    Stot[rb][r] = sp;
                     const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
                     const bool v = tile_ok && px < a.W && py < a.H;
-                    if (v) {
-                        const int64_t pix = (int64_t)py * a.W + px;
-                        const int d2min = a.d2[(int64_t)l * N + pix];
-                        const double fl2 = a.rho_floor * a.rho_floor;
-                        const double dm = (double)d2min > fl2 ? (double)d2min : fl2;
-                        const double rho2 = a.alpha_rho * a.alpha_rho * dm;
-                        const double K = a.kconst[l] - log(rho2);
-                        const double lg = kLn2F * ((double)Rtot[rb][r] +
-                                                   (double)__builtin_amdgcn_logf(Stot[rb][r])) + K;
-                        a.loglik[pix * a.L + l] = (float)lg;
-                    }
+                    if (v && !(sp <= 0x1p126f && sp > 0.0f)) bad = true;
                 }
         }
+        if (__ballot(bad)) {
+            if (lane == 0) {
+                const unsigned int slot = atomicAdd(a.fix_count, 1u);
+                if (slot < (unsigned int)a.fix_cap) a.fixlist[slot] = make_int2(lab, tile);
+            }
+            continue;
+        }
+        // lane jl < 8 of each 16-lane group writes pixel (rb, r) = (jl >> 2, jl & 3)
+        if (jl < 4 * RB) {
+            float Rw = 0.0f, Sw = 1.0f;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (jl == 4 * rb + r) {
+                        Rw = Rtot[rb][r];
+                        Sw = Stot[rb][r];
+                    }
+            const int rb = jl >> 2, r = jl & 3;
+            const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
+            if (tile_ok && px < a.W && py < a.H) {
+                const double K = (double)cf[(2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r].w;
+                const double lg = kLn2F * ((double)Rw + (double)__builtin_amdgcn_logf(Sw)) + K;
+                a.loglik[((int64_t)py * a.W + px) * a.L + lab] = (float)lg;
+            }
+        }
+    }
+    if (lane == 0 && (n_rescale | n_overflow)) {
+        if (n_rescale) atomicAdd(a.fix_count + 1, n_rescale);
+        if (n_overflow) atomicAdd(a.fix_count + 2, n_overflow);
     }
 }
 
 template <int KSTEPS>
 static hipError_t launch_mfma_k(const LaunchCtx &lc, const ParzenFastArgs &a) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS, kParzenRB>,
-                                                                256, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS>, 256, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     int64_t blocks = (int64_t)lc.num_cu * per_cu;
-    const int64_t need = (int64_t)a.ngroups * a.L;
-    if (blocks > need) blocks = need;
+    const int64_t items = (int64_t)a.ngroups * a.L;
+    if (blocks > items) blocks = items;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_parzen_mfma<KSTEPS, kParzenRB>), dim3((unsigned)blocks), dim3(256), 0,
-                       lc.stream, a);
+    hipLaunchKernelGGL(k_parzen_mfma<KSTEPS>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
     return hipGetLastError();
 }
 

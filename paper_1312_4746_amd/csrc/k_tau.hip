@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t 
     const int64_t n4 = count / 4;
     const float4 *a4 = reinterpret_cast<const float4 *>(alpha);
     for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n4 + 1; q += stride) {
-        float vv[4];
+        float vv[4] = {0.f, 0.f, 0.f, 0.f};
         int cnt = 4;
         if (q < n4) {
             const float4 f = a4[q];
@@ -166,13 +166,23 @@ __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t 
             cnt = (int)(count - n4 * 4);
             for (int u = 0; u < cnt; ++u) vv[u] = alpha[n4 * 4 + u];
         }
-        for (int u = 0; u < cnt; ++u) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
             const double x = (double)fabsf(vv[u]);
-            if (x < lo) {
-                ++below;
-            } else if (x <= hi) {
-                const unsigned long long slot = atomicAdd(&st->ncand, 1ull);
-                if ((int64_t)slot < cap) cand[slot] = q * 4 + u;
+            const bool live = u < cnt;
+            below += (live && x < lo) ? 1ull : 0ull;
+            const bool in = live && x >= lo && x <= hi;
+            // one atomic per wave: lanes with a candidate take consecutive slots
+            const unsigned long long m = __ballot(in);
+            if (m) {
+                const int lane = threadIdx.x & 63;
+                unsigned long long base = 0;
+                if (lane == __ffsll((long long)m) - 1) base = atomicAdd(&st->ncand, (unsigned long long)__popcll(m));
+                base = __shfl(base, __ffsll((long long)m) - 1);
+                if (in) {
+                    const unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                    if ((int64_t)slot < cap) cand[slot] = q * 4 + u;
+                }
             }
         }
     }
@@ -248,34 +258,41 @@ __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, i
     }
 }
 
-// Small candidate sets: rank of every candidate by direct comparison (ties
-// broken by index) in one workgroup; the candidate of the target rank wins.
-constexpr int kDirect = 4096;
+// Small candidate sets: bitonic sort in LDS (padded with +inf) by one
+// workgroup, then the entry of the remaining rank.
+constexpr int kDirect = 8192;
 __global__ __launch_bounds__(1024) void k_tau_select_direct(const double *vals, int64_t ncand,
                                                              double frac, TauState *st) {
     __shared__ double v[kDirect];
-    for (int i = threadIdx.x; i < ncand; i += 1024) v[i] = vals[i];
+    int n2 = 1;
+    while (n2 < ncand) n2 <<= 1;
+    for (int i = threadIdx.x; i < n2; i += 1024) v[i] = i < ncand ? vals[i] : INFINITY;
     __syncthreads();
-    const unsigned long long r0 = st->rank0, below = st->below;
-    const bool ok = (r0 >= below) && (r0 - below < (unsigned long long)ncand);
-    if (!ok) {
-        if (threadIdx.x == 0) {
-            st->median = __longlong_as_double(0x7FF8000000000000ll);
-            st->tau = st->median;
+    for (int size = 2; size <= n2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < n2; i += 1024) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const double a = v[i], b = v[j];
+                    if ((a > b) == up) {
+                        v[i] = b;
+                        v[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
         }
-        return;
     }
-    const int target = (int)(r0 - below);
-    for (int i = threadIdx.x; i < ncand; i += 1024) {
-        const double x = v[i];
-        int rank = 0;
-        for (int q = 0; q < ncand; ++q) {
-            const double y = v[q];
-            rank += (y < x) || (y == x && q < i);
-        }
-        if (rank == target) {
+    if (threadIdx.x == 0) {
+        const unsigned long long r0 = st->rank0, below = st->below;
+        if (r0 >= below && r0 - below < (unsigned long long)ncand) {
+            const double x = v[r0 - below];
             st->median = x;
             st->tau = frac * x;
+        } else {
+            st->median = __longlong_as_double(0x7FF8000000000000ll);
+            st->tau = st->median;
         }
     }
 }
