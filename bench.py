@@ -123,7 +123,7 @@ def main():
     def step():
         ctx.analyze_patches(rgb, w.p, w.mask_sigma, om, precision=w.precision, out=alpha)
         tau = ctx.tau_median(rgb, w.p, w.mask_sigma, om, alpha, w.tau_frac, precision=w.precision)
-        ctx.cosupport(rgb, w.p, w.mask_sigma, om, tau, precision=w.precision, out=masks)
+        ctx.cosupport(rgb, w.p, w.mask_sigma, om, tau, precision=w.precision, out=masks, alpha=alpha)
         ctx.label_loglik(rgb, masks, w.k, spix, slab, w.L, prm, out=ll)
         return tau
 

@@ -100,19 +100,22 @@ typedef struct {
 /*
  * Co-support masks (Sec. 2 co-support definition with threshold tau):
  * bit j of pixel x is 1 iff |a_j(x)| <= tau for the exact (FP64) a.  The
- * analysed vectors are recomputed on MFMA in `precision` inside the call;
- * every entry whose rounded |a| lies within `margin` of tau is recomputed in
- * FP64 (the library's only FP64 contraction) and decided exactly.
+ * rounded analysed vectors come from `alpha` (the output of
+ * cs_analyze_patches for the same inputs and precision) or, when alpha is
+ * NULL, are recomputed on MFMA in `precision` inside the call; every entry
+ * whose rounded |a| lies within `margin` of tau is recomputed in FP64 (the
+ * library's only FP64 contraction) and decided exactly.
  * margin < 0 selects the proven per-row error bound of the precision, which
  * makes the masks equal to the FP64 masks bit for bit; margin >= 0 is an
  * absolute margin (entries outside it are decided by the rounded value).
+ *   alpha  device, N*k float32, or NULL
  *   masks  device out, N*ceil(k/64) uint64
  *   stats  host out or NULL; non-NULL synchronises the stream.
  * Errors: as cs_analyze_patches, plus CS_ERR_ARG for tau < 0 or NaN.
  */
 int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
-                 const float *omega, int k, int precision, double tau, double margin,
-                 uint64_t *masks, cs_cosupport_stats *stats);
+                 const float *omega, int k, int precision, const float *alpha, double tau,
+                 double margin, uint64_t *masks, cs_cosupport_stats *stats);
 
 /*
  * Texture similarity (Sec. 2, TSM definition): out[a*nb + b] = number of

@@ -47,7 +47,7 @@ SIGNATURES = {
     "cs_last_error": (ctypes.c_char_p, [_P]),
     "cs_analyze_patches": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P]),
     "cs_tau_median": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, ctypes.POINTER(_D)]),
-    "cs_cosupport": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _D, _D, _P,
+    "cs_cosupport": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, _D, _P,
                           ctypes.POINTER(_CosupportStatsC)]),
     "cs_texture_similarity": (_I, [_P, _P, _I64, _P, _I64, _I, _P]),
     "cs_label_loglik": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, _I64, _I,
@@ -177,20 +177,28 @@ class Context:
         return tau.value
 
     def cosupport(self, rgb, p, mask_sigma, omega, tau, margin=-1.0, precision="fp32",
-                  out: Optional[torch.Tensor] = None, stats: bool = False):
+                  out: Optional[torch.Tensor] = None, stats: bool = False,
+                  alpha: Optional[torch.Tensor] = None):
         """Masks as an int64 tensor (N, ceil(k/64)) holding the uint64 bit
-        patterns; with stats=True returns (masks, {recomputed, max_margin})."""
+        patterns; with stats=True returns (masks, {recomputed, max_margin}).
+        With alpha (the analysed vectors of the same inputs and precision) the
+        masks are decided from it instead of a fresh analysis."""
         self._dev(rgb, torch.float32, "rgb")
         self._dev(omega, torch.float32, "omega")
         _, H, W = rgb.shape
         k = omega.shape[0]
+        if alpha is not None:
+            self._dev(alpha, torch.float32, "alpha")
+            if alpha.numel() != H * W * k:
+                raise ValueError("alpha must hold H*W*k entries")
         if out is None:
             out = torch.empty((H * W, (k + 63) // 64), dtype=torch.int64, device=rgb.device)
         self._dev(out, torch.int64, "masks")
         st = _CosupportStatsC()
         self._sync_stream()
         self._check(lib().cs_cosupport(self._h, _ptr(rgb), H, W, p, float(mask_sigma), _ptr(omega),
-                                       k, _PREC[precision], float(tau), float(margin), _ptr(out),
+                                       k, _PREC[precision], _ptr(alpha) if alpha is not None else None,
+                                       float(tau), float(margin), _ptr(out),
                                        ctypes.byref(st) if stats else None))
         if stats:
             return out, {"recomputed": int(st.recomputed), "max_margin": float(st.max_margin)}

@@ -254,8 +254,8 @@ int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, doubl
 }
 
 int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
-                 const float *omega, int k, int precision, double tau, double margin,
-                 uint64_t *masks, cs_cosupport_stats *stats) {
+                 const float *omega, int k, int precision, const float *alpha, double tau,
+                 double margin, uint64_t *masks, cs_cosupport_stats *stats) {
     if (!ctx) return CS_ERR_ARG;
     int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
     if (rc) return rc;
@@ -280,22 +280,26 @@ int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask
                                   marg, mmax));
     }
     HIP_TRY(launch_fill_u32(lc, (unsigned int *)cnt, 2, 0u));
-    AnalyzeArgs a{};
-    a.rgb = rgb;
-    a.H = H;
-    a.W = W;
-    a.p = p;
-    a.n = n;
-    a.n_pad = n_pad_of(n);
-    a.k = k;
-    a.wmask = ctx->wmask;
-    a.omega = omega;
-    a.masks = masks;
-    a.t_in = t_in;
-    a.t_out = t_out;
-    a.tau = tau;
-    a.recomputed = cnt;
-    {
+    if (alpha) {
+        Timed t(ctx, "cosupport");
+        HIP_TRY(launch_mask_alpha(lc, alpha, (int64_t)H * W, k, t_in, t_out, tau, rgb, H, W, p, ctx->wmask,
+                                  omega, masks, cnt));
+    } else {
+        AnalyzeArgs a{};
+        a.rgb = rgb;
+        a.H = H;
+        a.W = W;
+        a.p = p;
+        a.n = n;
+        a.n_pad = n_pad_of(n);
+        a.k = k;
+        a.wmask = ctx->wmask;
+        a.omega = omega;
+        a.masks = masks;
+        a.t_in = t_in;
+        a.t_out = t_out;
+        a.tau = tau;
+        a.recomputed = cnt;
         Timed t(ctx, "cosupport");
         HIP_TRY(launch_analyze(lc, a, precision));
     }

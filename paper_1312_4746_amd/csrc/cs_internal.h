@@ -52,6 +52,12 @@ struct AnalyzeArgs {
 };
 hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precision);
 
+// Masks from stored analysed vectors, same decisions as the analysis epilogue.
+hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N, int k, const float *t_in,
+                             const float *t_out, double tau, const float *rgb, int H, int W, int p,
+                             const double *wmask, const float *omega, uint64_t *masks,
+                             unsigned long long *recomputed);
+
 // Per-row thresholds t_in/t_out = tau -/+ margin_j, rounded outward to float.
 // margin < 0 selects the proven bound coef * ||O_j||_2 + tiny; writes the
 // largest margin to *max_margin.

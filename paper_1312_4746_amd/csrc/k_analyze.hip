@@ -224,6 +224,110 @@ hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precisi
     return launch_analyze_prec<CS_FP32>(lc, a);
 }
 
+// Co-support masks from stored analysed vectors (the same decision as the
+// analysis epilogue): bit j of pixel x is set when the rounded |a_j| is at most
+// t_in[j] and clear above t_out[j]; in between the entry is recomputed in FP64
+// from the exact patch (Sec. 2 co-support, Sec. 3.1 patch).  A wave owns
+// kMaskPx consecutive pixels (all loads issued up front), lane = row j within
+// a 64-bit mask word.  The rare FP64 step builds the pixel's patch in the
+// wave's own LDS slice; LDS accesses of one wave complete in issue order, so
+// the hand-offs between the lanes and lane 0 (which runs every sum in t order)
+// need no barrier.
+constexpr int kMaskPx = 8;
+__global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t N, int k,
+                                                     const float *t_in, const float *t_out, double tau,
+                                                     const float *rgb, int H, int W, int p,
+                                                     const double *wmask, const float *omega,
+                                                     uint64_t *masks, unsigned long long *recomputed) {
+#pragma clang fp contract(off)
+    __shared__ double s_all[4][15 * 15];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *s = s_all[wave];
+    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * kMaskPx;
+    const int W64 = (k + 63) / 64, n = p * p, h = (p - 1) / 2;
+    const int64_t NN = (int64_t)H * W;
+    float tin[4], tout[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int j = 64 * w + lane;
+        const bool jv = w < W64 && j < k;
+        tin[w] = jv ? t_in[j] : -1.0f;    // rows past k: never in, never near
+        tout[w] = jv ? t_out[j] : -2.0f;
+    }
+    float v[kMaskPx][4];
+#pragma unroll
+    for (int i = 0; i < kMaskPx; ++i)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int j = 64 * w + lane;
+            const int64_t pix = p0 + i;
+            v[i][w] = (w < W64 && j < k && pix < N) ? fabsf(alpha[pix * k + j]) : INFINITY;
+        }
+    unsigned long long nrec = 0;
+#pragma unroll
+    for (int i = 0; i < kMaskPx; ++i) {
+        const int64_t pix = p0 + i;
+        if (pix >= N) break;
+        bool in[4], near[4];
+        bool anyn = false;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            in[w] = v[i][w] <= tin[w];
+            near[w] = !in[w] && !(v[i][w] > tout[w]);
+            anyn |= near[w];
+        }
+        if (__ballot(anyn)) {
+            const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
+            for (int t = lane; t < n; t += 64) {
+                const int u = t / p, vv = t - u * p;
+                const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + vv - h, W);
+                s[t] = wmask[t] * gray64(rgb, NN, (int64_t)rr * W + cc);
+            }
+            double mu = 0.0;
+            if (lane == 0) {
+                double sum = 0.0;
+                for (int t = 0; t < n; ++t) sum = sum + s[t];
+                mu = sum / (double)n;
+            }
+            mu = __shfl(mu, 0);
+            for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
+            double nu2 = 0.0;
+            if (lane == 0)
+                for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
+            nu2 = __shfl(nu2, 0);
+            for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / sqrt(nu2);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                if (near[w]) in[w] = fabs(dot64(omega + (int64_t)(64 * w + lane) * n, s, n)) <= tau;
+                nrec += (unsigned long long)__popcll(__ballot(near[w]));
+            }
+        }
+        unsigned long long bits[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) bits[w] = __ballot(in[w]);
+        if (lane < W64) {
+            unsigned long long b = bits[0];
+#pragma unroll
+            for (int w = 1; w < 4; ++w)
+                if (lane == w) b = bits[w];
+            masks[pix * W64 + lane] = b;
+        }
+    }
+    if (recomputed && lane == 0 && nrec) atomicAdd(recomputed, nrec);
+}
+
+hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N, int k, const float *t_in,
+                             const float *t_out, double tau, const float *rgb, int H, int W, int p,
+                             const double *wmask, const float *omega, uint64_t *masks,
+                             unsigned long long *recomputed) {
+    if (N <= 0) return hipSuccess;
+    const int64_t per_block = 4 * kMaskPx;
+    hipLaunchKernelGGL(k_mask_alpha, dim3((unsigned)((N + per_block - 1) / per_block)), dim3(256), 0, lc.stream,
+                       alpha, N, k, t_in,
+                       t_out, tau, rgb, H, W, p, wmask, omega, masks, recomputed);
+    return hipGetLastError();
+}
+
 // Per-row decision thresholds.  One workgroup of 256 threads (k <= 256).
 __global__ __launch_bounds__(256) void k_thresholds(const float *omega, int k, int n, double tau,
                                                      double margin, double coef, float *t_in,

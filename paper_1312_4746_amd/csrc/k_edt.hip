@@ -8,16 +8,18 @@
 //     carries the nearest seed rows from the other segments in and scans its
 //     own segment both ways (lanes own adjacent columns, so loads coalesce);
 //  2. rows: one workgroup per (label, row) stages f(q) = squared column
-//     distance of every column q in LDS; each thread owns columns c and scans
-//     outward, q = c -+ delta, keeping the best (c - q)^2 + f(q), and stops as
-//     soon as delta^2 reaches the best value, so the work per pixel is
-//     proportional to its distance to the nearest sample.
+//     distance of every column q in LDS, and the smallest f over blocks of 16
+//     columns; each thread owns columns c and walks outward block by block,
+//     keeping the best (c - q)^2 + f(q).  A block is scanned only when its
+//     nearest column and its smallest f could still beat the best, and the walk
+//     stops once the nearest column of the next blocks is at least that far.
 #include "cs_internal.h"
 
 namespace cs {
 
 constexpr int kSegRows = 16;
 constexpr int kNoSeed = -1;
+constexpr int kRowBlk = 16;  // columns per block of the row pass
 constexpr int32_t kInf = 0x3FFFFFFF;
 
 // Per (label, segment, column): first and last seed row inside the segment.
@@ -94,8 +96,10 @@ __global__ __launch_bounds__(64) void k_edt_col_fill(const uint8_t *seeds, int H
 __global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H, int W,
                                                     int32_t *d2, int32_t *nearest) {
     extern __shared__ int32_t lds[];
-    int32_t *f = lds;        // squared column distance, kInf where the column has no seed
-    int32_t *rowof = lds + W;
+    const int nb = (W + kRowBlk - 1) / kRowBlk;
+    int32_t *f = lds;            // squared column distance, kInf where the column has no seed
+    int32_t *rowof = lds + W;    // nearest seed row of each column
+    int32_t *fmin = lds + 2 * W; // smallest f over each block of kRowBlk columns
     const int r = blockIdx.x, l = blockIdx.y;
     const int64_t N = (int64_t)H * W;
     const int32_t *cr = colrow + (int64_t)l * N + (int64_t)r * W;
@@ -105,28 +109,54 @@ __global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H,
         f[c] = q < 0 ? kInf : (r - q) * (r - q);
     }
     __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        int m = kInf;
+        const int q1 = min(W, (b + 1) * kRowBlk);
+        for (int q = b * kRowBlk; q < q1; ++q) m = min(m, f[q]);
+        fmin[b] = m;
+    }
+    __syncthreads();
     int32_t *dd = d2 + (int64_t)l * N + (int64_t)r * W;
     int32_t *nn = nearest + (int64_t)l * N + (int64_t)r * W;
     for (int c = threadIdx.x; c < W; c += blockDim.x) {
         int best = f[c], bq = c;
-        const int span = max(c, W - 1 - c);
-        // outward scan in blocks of 4 offsets (independent LDS reads), stopping
-        // once the smallest remaining offset squared reaches the best value
-        for (int d0 = 1; d0 <= span && d0 * d0 < best; d0 += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int d = d0 + u;
-                const int d2v = d * d;
-                const int ql = c - d, qr = c + d;
-                const int vl = ql >= 0 ? d2v + f[ql] : kInf;
-                const int vr = qr < W ? d2v + f[qr] : kInf;
-                if (vl < best) {
-                    best = vl;
-                    bq = ql;
+        const int cb = c / kRowBlk;
+        // own block, every column
+        const int o0 = cb * kRowBlk, o1 = min(W, o0 + kRowBlk);
+        for (int q = o0; q < o1; ++q) {
+            const int v = (c - q) * (c - q) + f[q];
+            if (v < best) {
+                best = v;
+                bq = q;
+            }
+        }
+        // blocks outward on both sides; a block is scanned only if its
+        // nearest column and smallest f could beat the best so far, and the
+        // walk stops once the nearest column of the next blocks is too far
+        for (int db = 1;; ++db) {
+            const int bl = cb - db, br = cb + db;
+            const int gl = c - (bl * kRowBlk + kRowBlk - 1);  // distance to the left block's last column
+            const int gr = br * kRowBlk - c;                     // distance to the right block's first column
+            const bool lok = bl >= 0 && gl * gl < best;
+            const bool rok = br < nb && gr * gr < best;
+            if (!lok && !rok) break;
+            if (lok && gl * gl + fmin[bl] < best) {
+                for (int q = bl * kRowBlk; q < bl * kRowBlk + kRowBlk; ++q) {
+                    const int v = (c - q) * (c - q) + f[q];
+                    if (v < best) {
+                        best = v;
+                        bq = q;
+                    }
                 }
-                if (vr < best) {
-                    best = vr;
-                    bq = qr;
+            }
+            if (rok && gr * gr + fmin[br] < best) {
+                const int q1 = min(W, br * kRowBlk + kRowBlk);
+                for (int q = br * kRowBlk; q < q1; ++q) {
+                    const int v = (c - q) * (c - q) + f[q];
+                    if (v < best) {
+                        best = v;
+                        bq = q;
+                    }
                 }
             }
         }
@@ -154,7 +184,7 @@ hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, i
     hipLaunchKernelGGL(k_edt_col_summary, g1, dim3(64), 0, lc.stream, seeds, H, W, nseg, first, last);
     hipLaunchKernelGGL(k_edt_col_fill, g1, dim3(64), 0, lc.stream, seeds, H, W, nseg, first, last,
                        colrow);
-    const size_t lds = sizeof(int32_t) * 2 * (size_t)W;
+    const size_t lds = sizeof(int32_t) * (2 * (size_t)W + (W + kRowBlk - 1) / kRowBlk);
     hipError_t e = hipFuncSetAttribute((const void *)k_edt_rows,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

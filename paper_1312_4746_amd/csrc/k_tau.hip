@@ -38,38 +38,52 @@ __global__ __launch_bounds__(256) void k_tau_init(TauState *st, unsigned long lo
 }
 
 // Histogram of one 11-bit digit of the |a| bit patterns that match the
-// prefix selected so far.  Eight sub-histograms per workgroup (by lane % 8)
-// spread the LDS atomics of lanes that fall into the same few bins.
-constexpr int kSub = 8;
+// prefix selected so far.  SUB sub-histograms per workgroup (by lane % SUB)
+// spread the LDS atomics of lanes that fall into the same few bins (first
+// digit); later digits see few matching entries and use one.
+template <int SUB>
 __global__ __launch_bounds__(256) void k_tau_hist(const float *alpha, int64_t count, int shift,
                                                    unsigned int pmask, const TauState *st,
                                                    unsigned int *hist) {
-    __shared__ unsigned int lh[kSub * kHistBins];
-    for (int i = threadIdx.x; i < kSub * kHistBins; i += 256) lh[i] = 0;
+    __shared__ unsigned int lh[SUB * kHistBins];
+    for (int i = threadIdx.x; i < SUB * kHistBins; i += 256) lh[i] = 0;
     __syncthreads();
     const unsigned int pval = st->prefix & pmask;
-    unsigned int *mine = lh + (threadIdx.x & (kSub - 1)) * kHistBins;
+    unsigned int *mine = lh + (threadIdx.x & (SUB - 1)) * kHistBins;
+    auto add = [&](float x) {
+        const unsigned int key = __float_as_uint(x) & 0x7FFFFFFFu;
+        if ((key & pmask) == pval) atomicAdd(&mine[(key >> shift) & (kHistBins - 1)], 1u);
+    };
     const int64_t n4 = count / 4;
     const float4 *a4 = reinterpret_cast<const float4 *>(alpha);
     const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n4; q += stride) {
-        const float4 v = a4[q];
-        const float vv[4] = {v.x, v.y, v.z, v.w};
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // four independent 16-byte loads in flight per thread
+    for (; q + 3 * stride < n4; q += 4 * stride) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = a4[q + u * stride];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const unsigned int key = __float_as_uint(vv[u]) & 0x7FFFFFFFu;
-            if ((key & pmask) == pval) atomicAdd(&mine[(key >> shift) & (kHistBins - 1)], 1u);
+            add(v[u].x);
+            add(v[u].y);
+            add(v[u].z);
+            add(v[u].w);
         }
     }
-    for (int64_t e = n4 * 4 + (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += stride) {
-        const unsigned int key = __float_as_uint(alpha[e]) & 0x7FFFFFFFu;
-        if ((key & pmask) == pval) atomicAdd(&mine[(key >> shift) & (kHistBins - 1)], 1u);
+    for (; q < n4; q += stride) {
+        const float4 v = a4[q];
+        add(v.x);
+        add(v.y);
+        add(v.z);
+        add(v.w);
     }
+    for (int64_t e = n4 * 4 + (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += stride) add(alpha[e]);
     __syncthreads();
     for (int i = threadIdx.x; i < kHistBins; i += 256) {
         unsigned int t = 0;
 #pragma unroll
-        for (int c = 0; c < kSub; ++c) t += lh[c * kHistBins + i];
+        for (int c = 0; c < SUB; ++c) t += lh[c * kHistBins + i];
         if (t) atomicAdd(&hist[i], t);
     }
 }
@@ -118,13 +132,19 @@ hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t cou
                        (unsigned long long)((count - 1) / 2), hist);
     const int shifts[3] = {21, 10, 0};
     const unsigned int pmasks[3] = {0u, 0xFFE00000u, 0xFFFFFC00u};
-    int64_t blocks = (count / 4 + 255) / 256;
-    const int64_t cap = (int64_t)lc.num_cu * 4;
-    if (blocks > cap) blocks = cap;
-    if (blocks < 1) blocks = 1;
+    auto blocks_for = [&](int per_cu) {
+        int64_t b = (count / 4 + 255) / 256;
+        const int64_t cap = (int64_t)lc.num_cu * per_cu;
+        if (b > cap) b = cap;
+        return (unsigned)(b < 1 ? 1 : b);
+    };
     for (int pass = 0; pass < 3; ++pass) {
-        hipLaunchKernelGGL(k_tau_hist, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, count,
-                           shifts[pass], pmasks[pass], st, hist);
+        if (pass == 0)
+            hipLaunchKernelGGL(k_tau_hist<8>, dim3(blocks_for(2)), dim3(256), 0, lc.stream, alpha, count,
+                               shifts[pass], pmasks[pass], st, hist);
+        else
+            hipLaunchKernelGGL(k_tau_hist<1>, dim3(blocks_for(4)), dim3(256), 0, lc.stream, alpha, count,
+                               shifts[pass], pmasks[pass], st, hist);
         hipLaunchKernelGGL(k_tau_pick, dim3(1), dim3(256), 0, lc.stream, hist, shifts[pass], st);
     }
     return hipGetLastError();
@@ -152,11 +172,53 @@ __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t 
         st->lo = lo;
         st->hi = hi;
     }
+    // The same tests on the float |a| bit patterns: x >= lo <=> x >= flo (the
+    // smallest float >= lo), x <= hi <=> x <= fhi (the largest float <= hi);
+    // non-negative floats order like their bit patterns.
+    float flo = (float)lo, fhi = (float)hi;
+    if ((double)flo < lo) flo = nextafterf(flo, INFINITY);
+    if ((double)fhi > hi) fhi = nextafterf(fhi, -INFINITY);
+    const unsigned int blo = lo <= 0.0 ? 0u : __float_as_uint(flo);
+    const unsigned int bhi = __float_as_uint(fhi);
     unsigned long long below = 0;
     const int64_t stride = (int64_t)gridDim.x * 256;
     const int64_t n4 = count / 4;
     const float4 *a4 = reinterpret_cast<const float4 *>(alpha);
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n4 + 1; q += stride) {
+    // one atomic per wave: lanes with a candidate take consecutive slots
+    auto visit = [&](float xv, bool live, int64_t e) {
+        const unsigned int x = __float_as_uint(xv) & 0x7FFFFFFFu;
+        below += (live && x < blo) ? 1ull : 0ull;
+        const bool in = live && x >= blo && x <= bhi;
+        const unsigned long long m = __ballot(in);
+        if (m) {
+            const int lane = threadIdx.x & 63;
+            unsigned long long base = 0;
+            if (lane == __ffsll((long long)m) - 1) base = atomicAdd(&st->ncand, (unsigned long long)__popcll(m));
+            base = __shfl(base, __ffsll((long long)m) - 1);
+            if (in) {
+                const unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                if ((int64_t)slot < cap) cand[slot] = e;
+            }
+        }
+    };
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // four independent 16-byte loads in flight per thread (the trip count is
+    // the same for all lanes of a wave up to the last round, which the
+    // single-load loop below finishes)
+    for (; q + 3 * stride < n4; q += 4 * stride) {
+        float4 f[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f[u] = a4[q + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = (q + u * stride) * 4;
+            visit(f[u].x, true, e);
+            visit(f[u].y, true, e + 1);
+            visit(f[u].z, true, e + 2);
+            visit(f[u].w, true, e + 3);
+        }
+    }
+    for (; q < n4 + 1; q += stride) {
         float vv[4] = {0.f, 0.f, 0.f, 0.f};
         int cnt = 4;
         if (q < n4) {
@@ -167,24 +229,7 @@ __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t 
             for (int u = 0; u < cnt; ++u) vv[u] = alpha[n4 * 4 + u];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double x = (double)fabsf(vv[u]);
-            const bool live = u < cnt;
-            below += (live && x < lo) ? 1ull : 0ull;
-            const bool in = live && x >= lo && x <= hi;
-            // one atomic per wave: lanes with a candidate take consecutive slots
-            const unsigned long long m = __ballot(in);
-            if (m) {
-                const int lane = threadIdx.x & 63;
-                unsigned long long base = 0;
-                if (lane == __ffsll((long long)m) - 1) base = atomicAdd(&st->ncand, (unsigned long long)__popcll(m));
-                base = __shfl(base, __ffsll((long long)m) - 1);
-                if (in) {
-                    const unsigned long long slot = base + __popcll(m & ((1ull << lane) - 1ull));
-                    if ((int64_t)slot < cap) cand[slot] = q * 4 + u;
-                }
-            }
-        }
+        for (int u = 0; u < 4; ++u) visit(vv[u], u < cnt, q * 4 + u);
     }
     red[threadIdx.x] = below;
     __syncthreads();
@@ -198,7 +243,7 @@ __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t 
 hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
                       const double *max_margin, TauState *st, int64_t *cand, int64_t cap) {
     int64_t blocks = (count / 4 + 256) / 256;
-    const int64_t bcap = (int64_t)lc.num_cu * 8;
+    const int64_t bcap = (int64_t)lc.num_cu * 4;
     if (blocks > bcap) blocks = bcap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_tau_gather, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, count,

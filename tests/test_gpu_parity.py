@@ -44,9 +44,9 @@ def bound_coef(prec, n):
     return 2 * (n + 4) * u
 
 
-def gpu_masks(ctx, w, tau, prec="fp32", margin=-1.0, stats=False):
+def gpu_masks(ctx, w, tau, prec="fp32", margin=-1.0, stats=False, alpha=None):
     return ctx.cosupport(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), tau, margin=margin,
-                         precision=prec, stats=stats)
+                         precision=prec, stats=stats, alpha=alpha)
 
 
 SMALL_CASES = [
@@ -91,6 +91,10 @@ def test_tau_and_masks_bit_exact(ctx, case, prec):
     m_gpu, st = gpu_masks(ctx, w, tau, prec, stats=True)
     m_ref = oracle.cosupport(a_ref, tau_ref)
     assert np.array_equal(masks_u64(m_gpu), m_ref)
+    # the same masks decided from the stored analysed vectors
+    m_alpha, st_a = gpu_masks(ctx, w, tau, prec, stats=True, alpha=a_gpu)
+    assert np.array_equal(masks_u64(m_alpha), m_ref)
+    assert st_a["recomputed"] == st["recomputed"]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -102,8 +106,12 @@ def test_bsds_shape_tau_and_masks_bit_exact(ctx, prec):
     tau = ctx.tau_median(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), a_gpu, 0.1, precision=prec)
     assert tau == tau_ref
     m_gpu, st = gpu_masks(ctx, w, tau, prec, stats=True)
-    assert np.array_equal(masks_u64(m_gpu), oracle.cosupport(a_ref, tau_ref))
+    m_ref = oracle.cosupport(a_ref, tau_ref)
+    assert np.array_equal(masks_u64(m_gpu), m_ref)
     assert st["recomputed"] > 0
+    m_alpha, st_a = gpu_masks(ctx, w, tau, prec, stats=True, alpha=a_gpu)
+    assert np.array_equal(masks_u64(m_alpha), m_ref)
+    assert st_a["recomputed"] == st["recomputed"]
 
 
 def test_bf16_stated_margin_reports_mismatches(ctx):
@@ -119,6 +127,10 @@ def test_bf16_stated_margin_reports_mismatches(ctx):
     mism = int(sum(bin(int(v)).count("1") for v in diff.ravel()))
     assert 0 <= mism < 0.05 * w.N * w.k
     assert st["recomputed"] > 0
+    # same decisions from the stored BF16 analysed vectors
+    a_gpu = ctx.analyze_patches(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), precision="bf16")
+    m_alpha = gpu_masks(ctx, w, tau, "bf16", margin=2.0 ** -8 * tau, alpha=a_gpu)
+    assert np.array_equal(masks_u64(m_alpha), masks_u64(m_gpu))
 
 
 def test_zero_image_full_cosupport(ctx):
