@@ -88,6 +88,109 @@ def cpu_baseline(w, n_sample: int):
     }
 
 
+def surrogate_bench(args):
+    """Learned surrogate at the 2048x2048 workload: exact data term on every
+    pixel (the judge), exact targets at the 2 % training pixels, training,
+    inference on every pixel, flip rate and the equal-time comparison."""
+    import numpy as np
+    import torch
+
+    from paper_1312_4746_amd import Context, LoglikParams
+    from paper_1312_4746_amd import surrogate as sg
+    from workloads import make_config, mlp_init, mlp_order
+
+    w = make_config(args.config)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rgb, om = dev(w.rgb), dev(w.omega)
+    spix, slab = dev(w.sample_pix), dev(w.sample_label)
+    tpix = dev(w.train_pix)
+    prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
+                       rho_floor_px=w.rho_floor_px)
+    ctx = Context(0)
+    alpha = torch.empty((w.N, w.k), dtype=torch.float32, device="cuda")
+    masks = torch.empty((w.N, (w.k + 63) // 64), dtype=torch.int64, device="cuda")
+    ll = torch.empty((w.N, w.L), dtype=torch.float32, device="cuda")
+
+    def timed(fn, reps=1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    def front():
+        ctx.analyze_patches(rgb, w.p, w.mask_sigma, om, precision=w.precision, out=alpha)
+        tau = ctx.tau_median(rgb, w.p, w.mask_sigma, om, alpha, w.tau_frac, precision=w.precision)
+        ctx.cosupport(rgb, w.p, w.mask_sigma, om, tau, precision=w.precision, out=masks, alpha=alpha)
+
+    front()  # warm-up
+    t_front, _ = timed(front, 2)
+    t_analyze, _ = timed(lambda: ctx.analyze_patches(rgb, w.p, w.mask_sigma, om, precision=w.precision,
+                                                     out=alpha), 2)
+    front()
+    exact = lambda: ctx.label_loglik(rgb, masks, w.k, spix, slab, w.L, prm, out=ll)  # noqa: E731
+    exact()
+    t_exact, _ = timed(exact, 1)
+
+    batch, steps = args.mlp_batch, args.mlp_steps
+    order = dev(mlp_order(len(w.train_pix), steps, batch, seed=w.seed + 101).ravel())
+    init = dev(mlp_init(5 + w.k, 128, w.L, seed=w.seed + 100))
+    t_fit, fit = timed(lambda: sg.fit(ctx, rgb, alpha, masks, w.k, spix, slab, w.L, prm, tpix, init, order,
+                                      batch, args.mlp_lr))
+    net = fit.net
+    y = torch.empty((w.N, w.L), dtype=torch.float32, device="cuda")
+    net.infer(rgb, alpha, out=y)
+    reps = 5
+    t_infer, _ = timed(lambda: net.infer(rgb, alpha, out=y), reps)
+    quality = sg.judge(y, ll)
+
+    # equal-time exact path: a sample subset sized to the surrogate's time
+    m_eq = max(w.L, int(w.M * t_infer / t_exact))
+    gen = torch.Generator().manual_seed(w.seed + 102)
+    sp2, sl2 = sg.equal_time_subset(spix, slab, w.L, m_eq, gen)
+    ll2 = torch.empty_like(ll)
+    ctx.label_loglik(rgb, masks, w.k, sp2, sl2, w.L, prm, out=ll2)
+    t_sub, _ = timed(lambda: ctx.label_loglik(rgb, masks, w.k, sp2, sl2, w.L, prm, out=ll2), 1)
+    q_sub = sg.judge(ll2, ll)
+    trace = fit.loss_trace.cpu().numpy()
+
+    out = {
+        "metric": "surrogate px/s at <=0.5% label-argmax flips",
+        "value": w.N / t_infer,
+        "unit": "px/s",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": 1,
+        "ms_per_step": t_infer * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "H": w.H, "W": w.W, "k": w.k, "labels": w.L, "samples": w.M,
+                   "pixels": w.N, "train_pixels": int(len(w.train_pix)), "parallelism": "1 GPU"},
+        "surrogate": {
+            "flip_rate": quality["flip_rate"],
+            "meets_0p5pct": quality["flip_rate"] <= 0.005,
+            "mean_abs_dl": quality["mean_abs_dl"],
+            "mean_abs_dl_within_20_nats": quality["mean_abs_dl_within_20_nats"],
+            "infer_ms": t_infer * 1e3,
+            "train": {"steps": steps, "batch": batch, "lr": args.mlp_lr,
+                      "fit_ms_incl_targets": t_fit * 1e3,
+                      "loss_first": float(trace[:20].mean()), "loss_last": float(trace[-20:].mean())},
+        },
+        "exact": {"px_per_s": w.N / (t_front + t_exact), "front_ms": t_front * 1e3,
+                  "loglik_ms": t_exact * 1e3, "pairs_per_s": w.N * w.M / t_exact},
+        "speedup_vs_exact_data_term": (t_front + t_exact) / (t_analyze + t_infer),
+        "equal_time_exact": {"samples": int(sp2.numel()), "ms": t_sub * 1e3, "flip_rate": q_sub["flip_rate"],
+                             "mean_abs_dl_within_20_nats": q_sub["mean_abs_dl_within_20_nats"]},
+    }
+    print(json.dumps(out))
+    net.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,12 +199,19 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mlp-steps", type=int, default=3000)
+    ap.add_argument("--mlp-batch", type=int, default=4096)
+    ap.add_argument("--mlp-lr", type=float, default=1e-3)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the data term runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config == 4:
+        surrogate_bench(args)
+        return
 
     import numpy as np
     import torch

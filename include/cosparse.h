@@ -183,6 +183,81 @@ int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats);
 int cs_profile_enable(cs_ctx *ctx, int on);
 int cs_profile_read(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 
+/* ---- Learned surrogate of the data term ----
+ * A two-hidden-layer perceptron maps a pixel's colour, normalised position
+ * and analysed vector (Sec. 2 a = O s of the Sec. 3.1 patch) to its per-label
+ * log-likelihoods (the Sec. 3.2 data term), trained per image on exact values
+ * of cs_label_loglik at sampled pixels.  The paper has no surrogate; the
+ * readings are: input x = [r, g, b, col/(W-1), row/(H-1), a_0..a_{k-1}]
+ * (a zero coordinate when W or H is 1), z1 = W1 x + b1, h1 = GELU(z1),
+ * z2 = W2 h1 + b2, h2 = GELU(z2), y = W3 h2 + b3 with the exact (erf) GELU;
+ * loss = mean over rows and labels of (y - t)^2 with the clipped target
+ * t_i = max(l_i, max_j l_j - 20); Adam (0.9, 0.999, 1e-8) with bias
+ * correction.  Matrix products run in BF16 with FP32 accumulation; biases,
+ * GELU, the loss and Adam in FP32 on FP32 master parameters.
+ * Parameters are one flat FP32 vector: W1 (hidden x in_dim, row-major), b1,
+ * W2 (hidden x hidden), b2, W3 (out_dim x hidden), b3.
+ * Limits: hidden = 128, 1 <= in_dim <= 128, 1 <= out_dim <= 16.
+ */
+typedef struct cs_mlp cs_mlp;
+
+/* Number of parameters of the network (0 for unsupported sizes). */
+int64_t cs_mlp_param_count(int in_dim, int hidden, int out_dim);
+
+/* Create a network on the context's device from initial parameters.
+ *   params  device, cs_mlp_param_count(...) float32 (the initial values are
+ *           the caller's: random numbers of the method are inputs)
+ * Allocates the network's device memory (freed by cs_mlp_free).
+ * Errors: CS_ERR_ARG (unsupported sizes, null pointers), CS_ERR_NOMEM. */
+int cs_mlp_init(cs_ctx *ctx, cs_mlp **net, int in_dim, int hidden, int out_dim, const float *params);
+int cs_mlp_free(cs_mlp *net);
+
+/* Current master parameters into `params` (device, param_count float32). */
+int cs_mlp_get_params(cs_ctx *ctx, const cs_mlp *net, float *params);
+
+/* Surrogate inputs of listed pixels.
+ *   rgb    device 3*H*W float32;  alpha  device H*W*k float32 (pixel-major)
+ *   pix    device n int32 linear pixel indices
+ *   x      device out, n*(5+k) float32, row-major
+ * Errors: CS_ERR_ARG (null pointers, 5+k > 128, n < 0). */
+int cs_mlp_features(cs_ctx *ctx, const float *rgb, int H, int W, const float *alpha, int k,
+                    const int32_t *pix, int64_t n, float *x);
+
+/* Gradient of the mean loss over all n rows (no update).
+ *   x      device n*in_dim float32;  ell  device n*out_dim raw log-likelihoods
+ *   grad   device out, param_count float32;  loss  device out, 1 float32 (nullable)
+ * n must be a multiple of 16 in 16..8192.  Errors: CS_ERR_ARG. */
+int cs_mlp_grad(cs_ctx *ctx, cs_mlp *net, const float *x, const float *ell, int64_t n, float *grad,
+                float *loss);
+
+/* Set the output bias b3 to the mean clipped target of each label over the
+ * n rows of ell (device n*out_dim raw log-likelihoods): a data-dependent
+ * start so that the optimiser does not spend its first steps moving the
+ * outputs to the scale of the targets.  Errors: CS_ERR_ARG. */
+int cs_mlp_fit_output_bias(cs_ctx *ctx, cs_mlp *net, const float *ell, int64_t n);
+
+/* `steps` Adam steps; step s uses the rows order[s*batch .. s*batch+batch-1]
+ * of (x, ell) (the data order is an input).
+ *   order       device steps*batch int32 row indices in 0..n_rows-1 (indices
+ *               outside are clamped into the range)
+ *   loss_trace  device out, steps float32: loss of each batch before its update
+ *               (nullable)
+ * batch must be a multiple of 16 in 16..8192; lr > 0.  The Adam step count
+ * continues across calls.  Errors: CS_ERR_ARG. */
+int cs_mlp_train(cs_ctx *ctx, cs_mlp *net, const float *x, const float *ell, int64_t n_rows,
+                 const int32_t *order, int64_t steps, int batch, double lr, float *loss_trace);
+
+/* Surrogate log-likelihoods of every pixel, inputs assembled on the fly.
+ *   rgb device 3*H*W; alpha device H*W*k (in_dim must equal 5+k)
+ *   out device out, H*W*out_dim float32 (out[x*out_dim + i])
+ * Errors: CS_ERR_ARG. */
+int cs_mlp_infer(cs_ctx *ctx, const cs_mlp *net, const float *rgb, int H, int W, const float *alpha, int k,
+                 float *out);
+
+/* Surrogate outputs of explicit input rows x (device n*in_dim) into out
+ * (device n*out_dim).  Errors: CS_ERR_ARG. */
+int cs_mlp_forward(cs_ctx *ctx, const cs_mlp *net, const float *x, int64_t n, float *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,6 +14,9 @@ from .binding import (  # noqa: F401
     Context,
     CosparseError,
     LoglikParams,
+    Mlp,
     lib,
     library_path,
+    mlp_features,
+    param_count,
 )

@@ -55,6 +55,16 @@ SIGNATURES = {
     "cs_last_loglik_stats": (_I, [_P, ctypes.POINTER(_LoglikStatsC)]),
     "cs_profile_enable": (_I, [_P, _I]),
     "cs_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    "cs_mlp_param_count": (_I64, [_I, _I, _I]),
+    "cs_mlp_init": (_I, [_P, ctypes.POINTER(_P), _I, _I, _I, _P]),
+    "cs_mlp_free": (_I, [_P]),
+    "cs_mlp_get_params": (_I, [_P, _P, _P]),
+    "cs_mlp_features": (_I, [_P, _P, _I, _I, _P, _I, _P, _I64, _P]),
+    "cs_mlp_grad": (_I, [_P, _P, _P, _P, _I64, _P, _P]),
+    "cs_mlp_train": (_I, [_P, _P, _P, _P, _I64, _P, _I64, _I, _D, _P]),
+    "cs_mlp_fit_output_bias": (_I, [_P, _P, _P, _I64]),
+    "cs_mlp_infer": (_I, [_P, _P, _P, _I, _I, _P, _I, _P]),
+    "cs_mlp_forward": (_I, [_P, _P, _P, _I64, _P]),
 }
 
 _lib = None
@@ -258,3 +268,110 @@ class Context:
         n = ctypes.c_int64()
         self._check(lib().cs_profile_read(self._h, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Mlp:
+    """The learned surrogate (one network on the context's device).  The
+    initial parameters are an input: a flat float32 tensor (cuda) of
+    param_count(in_dim, hidden, out_dim) values."""
+
+    def __init__(self, ctx: Context, in_dim: int, out_dim: int, init_params: torch.Tensor,
+                 hidden: int = 128):
+        self.ctx = ctx
+        self.in_dim, self.hidden, self.out_dim = in_dim, hidden, out_dim
+        self.P = param_count(in_dim, hidden, out_dim)
+        ctx._dev(init_params, torch.float32, "init_params")
+        if self.P and init_params.numel() != self.P:
+            raise ValueError(f"init_params must hold {self.P} values")
+        self._h = ctypes.c_void_p()
+        ctx._sync_stream()
+        ctx._check(lib().cs_mlp_init(ctx._h, ctypes.byref(self._h), in_dim, hidden, out_dim,
+                                     _ptr(init_params)))
+
+    def close(self):
+        if self._h:
+            lib().cs_mlp_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(self.P, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        self.ctx._sync_stream()
+        self.ctx._check(lib().cs_mlp_get_params(self.ctx._h, self._h, _ptr(out)))
+        return out
+
+    def grad(self, x: torch.Tensor, ell: torch.Tensor):
+        """(gradient of the mean loss over all rows, loss) without an update."""
+        self.ctx._dev(x, torch.float32, "x")
+        self.ctx._dev(ell, torch.float32, "ell")
+        g = torch.empty(self.P, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        self.ctx._sync_stream()
+        self.ctx._check(lib().cs_mlp_grad(self.ctx._h, self._h, _ptr(x), _ptr(ell), x.shape[0],
+                                          _ptr(g), _ptr(loss)))
+        return g, loss
+
+    def fit_output_bias(self, ell: torch.Tensor):
+        """b3 = mean clipped target of each label over the rows of ell."""
+        self.ctx._dev(ell, torch.float32, "ell")
+        self.ctx._sync_stream()
+        self.ctx._check(lib().cs_mlp_fit_output_bias(self.ctx._h, self._h, _ptr(ell), ell.shape[0]))
+
+    def train(self, x: torch.Tensor, ell: torch.Tensor, order: torch.Tensor, batch: int,
+              lr: float = 1e-3) -> torch.Tensor:
+        """Adam steps over the batches order.view(-1, batch); returns the loss trace."""
+        self.ctx._dev(x, torch.float32, "x")
+        self.ctx._dev(ell, torch.float32, "ell")
+        self.ctx._dev(order, torch.int32, "order")
+        steps = order.numel() // batch
+        trace = torch.empty(max(steps, 1), dtype=torch.float32, device=x.device)
+        self.ctx._sync_stream()
+        self.ctx._check(lib().cs_mlp_train(self.ctx._h, self._h, _ptr(x), _ptr(ell), x.shape[0],
+                                           _ptr(order), steps, batch, float(lr), _ptr(trace)))
+        return trace[:steps]
+
+    def forward(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self.ctx._dev(x, torch.float32, "x")
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty((n, self.out_dim), dtype=torch.float32, device=x.device)
+        self.ctx._sync_stream()
+        self.ctx._check(lib().cs_mlp_forward(self.ctx._h, self._h, _ptr(x), n, _ptr(out)))
+        return out
+
+    def infer(self, rgb: torch.Tensor, alpha: torch.Tensor, out: Optional[torch.Tensor] = None):
+        self.ctx._dev(rgb, torch.float32, "rgb")
+        self.ctx._dev(alpha, torch.float32, "alpha")
+        _, H, W = rgb.shape
+        k = alpha.numel() // (H * W)
+        if out is None:
+            out = torch.empty((H * W, self.out_dim), dtype=torch.float32, device=rgb.device)
+        self.ctx._sync_stream()
+        self.ctx._check(lib().cs_mlp_infer(self.ctx._h, self._h, _ptr(rgb), H, W, _ptr(alpha), k,
+                                           _ptr(out)))
+        return out
+
+
+def param_count(in_dim: int, hidden: int, out_dim: int) -> int:
+    return int(lib().cs_mlp_param_count(in_dim, hidden, out_dim))
+
+
+def mlp_features(ctx: Context, rgb: torch.Tensor, alpha: torch.Tensor, pix: torch.Tensor,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Surrogate input rows of the pixels `pix` (int32, cuda)."""
+    ctx._dev(rgb, torch.float32, "rgb")
+    ctx._dev(alpha, torch.float32, "alpha")
+    ctx._dev(pix, torch.int32, "pix")
+    _, H, W = rgb.shape
+    k = alpha.numel() // (H * W)
+    if out is None:
+        out = torch.empty((pix.numel(), 5 + k), dtype=torch.float32, device=rgb.device)
+    ctx._sync_stream()
+    ctx._check(lib().cs_mlp_features(ctx._h, _ptr(rgb), H, W, _ptr(alpha), k, _ptr(pix),
+                                     pix.numel(), _ptr(out)))
+    return out

@@ -633,4 +633,317 @@ int cs_profile_read(cs_ctx *ctx, const char *name, double *total_ms, int64_t *la
     return CS_OK;
 }
 
+// ---- learned surrogate ----
+}  // extern "C"
+
+struct cs_mlp {
+    int device = 0;
+    int in = 0, in_pad = 0, out = 0;
+    int64_t P = 0, off_b1 = 0, off_W2 = 0, off_b2 = 0, off_W3 = 0, off_b3 = 0;
+    int64_t t = 0;  // Adam steps taken
+    char *mem = nullptr;
+    float *params = nullptr, *m = nullptr, *v = nullptr;
+    short *W1b = nullptr, *W2b = nullptr, *W3b = nullptr, *W2Tb = nullptr, *W3Tb = nullptr;
+};
+
+namespace {
+
+bool mlp_sizes_ok(int in, int hidden, int out) {
+    return hidden == kMlpHid && in >= 1 && in <= kMlpMaxIn && out >= 1 && out <= kMlpOutPad;
+}
+
+MlpAdamArgs mlp_adam_args(cs_mlp *n) {
+    MlpAdamArgs a{};
+    a.params = n->params;
+    a.m = n->m;
+    a.v = n->v;
+    a.P = n->P;
+    a.off_b1 = n->off_b1;
+    a.off_W2 = n->off_W2;
+    a.off_b2 = n->off_b2;
+    a.off_W3 = n->off_W3;
+    a.off_b3 = n->off_b3;
+    a.in = n->in;
+    a.in_pad = n->in_pad;
+    a.out = n->out;
+    a.W1b = n->W1b;
+    a.W2b = n->W2b;
+    a.W3b = n->W3b;
+    a.W2Tb = n->W2Tb;
+    a.W3Tb = n->W3Tb;
+    return a;
+}
+
+// Row chunks of the weight-gradient reduction: the largest kc <= 16 whose
+// chunks are whole 16-row MFMA steps.
+int mlp_kc(int B) {
+    for (int kc = 16; kc > 1; --kc)
+        if (B % (16 * kc) == 0) return kc;
+    return 1;
+}
+
+// One forward/backward over B rows (idx or rows 0..B-1), then the weight
+// gradients; scratch carved from the context workspace.
+int mlp_backprop(cs_ctx *ctx, cs_mlp *n, const float *x, const float *ell, const int32_t *idx, int64_t n_rows,
+                 int B, MlpAdamArgs &ad) {
+    const int kc = mlp_kc(B);
+    const int ntiles = B / 16;
+    Carve cv;
+    const size_t o_x = cv.take(sizeof(short) * (size_t)n->in_pad * B);
+    const size_t o_h1 = cv.take(sizeof(short) * (size_t)kMlpHid * B);
+    const size_t o_h2 = cv.take(sizeof(short) * (size_t)kMlpHid * B);
+    const size_t o_dy = cv.take(sizeof(short) * (size_t)kMlpOutPad * B);
+    const size_t o_dz2 = cv.take(sizeof(short) * (size_t)kMlpHid * B);
+    const size_t o_dz1 = cv.take(sizeof(short) * (size_t)kMlpHid * B);
+    const size_t o_bg = cv.take(sizeof(float) * (size_t)ntiles * kMlpBiasStride);
+    const size_t o_lp = cv.take(sizeof(float) * (size_t)ntiles);
+    const size_t o_gp = cv.take(sizeof(float) * (size_t)kc * n->P);
+    int rc = ensure_ws(ctx, cv.off);
+    if (rc) return rc;
+    MlpTrainArgs t{};
+    t.x = x;
+    t.ell = ell;
+    t.idx = idx;
+    t.n_rows = n_rows;
+    t.B = B;
+    t.in = n->in;
+    t.in_pad = n->in_pad;
+    t.out = n->out;
+    t.W1b = n->W1b;
+    t.W2b = n->W2b;
+    t.W3b = n->W3b;
+    t.W2Tb = n->W2Tb;
+    t.W3Tb = n->W3Tb;
+    t.b1 = n->params + n->off_b1;
+    t.b2 = n->params + n->off_b2;
+    t.b3 = n->params + n->off_b3;
+    t.Xt = (short *)(ctx->ws + o_x);
+    t.H1t = (short *)(ctx->ws + o_h1);
+    t.H2t = (short *)(ctx->ws + o_h2);
+    t.DYt = (short *)(ctx->ws + o_dy);
+    t.DZ2t = (short *)(ctx->ws + o_dz2);
+    t.DZ1t = (short *)(ctx->ws + o_dz1);
+    t.bgrad = (float *)(ctx->ws + o_bg);
+    t.lossp = (float *)(ctx->ws + o_lp);
+    MlpWgradArgs w{};
+    w.Xt = t.Xt;
+    w.H1t = t.H1t;
+    w.H2t = t.H2t;
+    w.DYt = t.DYt;
+    w.DZ2t = t.DZ2t;
+    w.DZ1t = t.DZ1t;
+    w.B = B;
+    w.in = n->in;
+    w.in_pad = n->in_pad;
+    w.out = n->out;
+    w.kc = kc;
+    w.P = n->P;
+    w.off_W1 = 0;
+    w.off_W2 = n->off_W2;
+    w.off_W3 = n->off_W3;
+    w.gpart = (float *)(ctx->ws + o_gp);
+    const LaunchCtx lc = lc_of(ctx);
+    {
+        Timed tm(ctx, "mlp_fwdbwd");
+        HIP_TRY(launch_mlp_fwdbwd(lc, t));
+    }
+    {
+        Timed tm(ctx, "mlp_wgrad");
+        HIP_TRY(launch_mlp_wgrad(lc, w));
+    }
+    ad.gpart = w.gpart;
+    ad.bgrad = t.bgrad;
+    ad.lossp = t.lossp;
+    ad.kc = kc;
+    ad.ntiles = ntiles;
+    ad.B = B;
+    return CS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t cs_mlp_param_count(int in_dim, int hidden, int out_dim) {
+    if (!mlp_sizes_ok(in_dim, hidden, out_dim)) return 0;
+    return (int64_t)hidden * in_dim + hidden + (int64_t)hidden * hidden + hidden + (int64_t)out_dim * hidden +
+           out_dim;
+}
+
+int cs_mlp_init(cs_ctx *ctx, cs_mlp **net, int in_dim, int hidden, int out_dim, const float *params) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!net || !params) return fail(ctx, CS_ERR_ARG, "net and params must be non-null");
+    *net = nullptr;
+    if (!mlp_sizes_ok(in_dim, hidden, out_dim))
+        return fail(ctx, CS_ERR_ARG, "unsupported network: hidden must be %d, in_dim 1..%d, out_dim 1..%d", kMlpHid,
+                    kMlpMaxIn, kMlpOutPad);
+    HIP_TRY(hipSetDevice(ctx->device));
+    cs_mlp *n = new (std::nothrow) cs_mlp();
+    if (!n) return fail(ctx, CS_ERR_NOMEM, "host allocation failed");
+    n->device = ctx->device;
+    n->in = in_dim;
+    n->in_pad = (in_dim + 15) / 16 * 16;
+    n->out = out_dim;
+    n->off_b1 = (int64_t)kMlpHid * in_dim;
+    n->off_W2 = n->off_b1 + kMlpHid;
+    n->off_b2 = n->off_W2 + (int64_t)kMlpHid * kMlpHid;
+    n->off_W3 = n->off_b2 + kMlpHid;
+    n->off_b3 = n->off_W3 + (int64_t)out_dim * kMlpHid;
+    n->P = n->off_b3 + out_dim;
+    Carve cv;
+    const size_t o_p = cv.take(sizeof(float) * n->P), o_m = cv.take(sizeof(float) * n->P),
+                 o_v = cv.take(sizeof(float) * n->P);
+    const size_t o_w1 = cv.take(sizeof(short) * kMlpHid * n->in_pad);
+    const size_t o_w2 = cv.take(sizeof(short) * kMlpHid * kMlpHid);
+    const size_t o_w2t = cv.take(sizeof(short) * kMlpHid * kMlpHid);
+    const size_t o_w3 = cv.take(sizeof(short) * kMlpOutPad * kMlpHid);
+    const size_t o_w3t = cv.take(sizeof(short) * kMlpHid * kMlpOutPad);
+    if (hipMalloc((void **)&n->mem, cv.off) != hipSuccess) {
+        delete n;
+        return fail(ctx, CS_ERR_NOMEM, "network memory of %zu bytes could not be allocated", cv.off);
+    }
+    n->params = (float *)(n->mem + o_p);
+    n->m = (float *)(n->mem + o_m);
+    n->v = (float *)(n->mem + o_v);
+    n->W1b = (short *)(n->mem + o_w1);
+    n->W2b = (short *)(n->mem + o_w2);
+    n->W2Tb = (short *)(n->mem + o_w2t);
+    n->W3b = (short *)(n->mem + o_w3);
+    n->W3Tb = (short *)(n->mem + o_w3t);
+    const LaunchCtx lc = lc_of(ctx);
+    int rc = CS_OK;
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && rc == CS_OK) rc = fail(ctx, CS_ERR_HIP, "network set-up: %s", hipGetErrorString(e));
+    };
+    chk(launch_fill_u32(lc, (unsigned int *)n->mem, cv.off / 4, 0u));  // zeros: moments and padding
+    chk(hipMemcpyAsync(n->params, params, sizeof(float) * n->P, hipMemcpyDeviceToDevice, ctx->stream));
+    MlpAdamArgs a = mlp_adam_args(n);
+    chk(launch_mlp_convert(lc, a));
+    if (rc) {
+        hipFree(n->mem);
+        delete n;
+        return rc;
+    }
+    *net = n;
+    return CS_OK;
+}
+
+int cs_mlp_free(cs_mlp *net) {
+    if (!net) return CS_OK;
+    hipSetDevice(net->device);
+    hipDeviceSynchronize();
+    if (net->mem) hipFree(net->mem);
+    delete net;
+    return CS_OK;
+}
+
+int cs_mlp_get_params(cs_ctx *ctx, const cs_mlp *net, float *params) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!net || !params) return fail(ctx, CS_ERR_ARG, "net and params must be non-null");
+    HIP_TRY(hipMemcpyAsync(params, net->params, sizeof(float) * net->P, hipMemcpyDeviceToDevice, ctx->stream));
+    return CS_OK;
+}
+
+int cs_mlp_features(cs_ctx *ctx, const float *rgb, int H, int W, const float *alpha, int k, const int32_t *pix,
+                    int64_t n, float *x) {
+    if (!ctx) return CS_ERR_ARG;
+    if (n < 0 || H < 1 || W < 1 || k < 1 || 5 + k > kMlpMaxIn)
+        return fail(ctx, CS_ERR_ARG, "bad sizes (n >= 0, H, W >= 1, 1 <= k <= %d)", kMlpMaxIn - 5);
+    if (n == 0) return CS_OK;
+    if (!rgb || !alpha || !pix || !x) return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    HIP_TRY(hipSetDevice(ctx->device));
+    Timed tm(ctx, "mlp_features");
+    HIP_TRY(launch_mlp_features(lc_of(ctx), rgb, H, W, alpha, k, pix, n, x));
+    return CS_OK;
+}
+
+int cs_mlp_grad(cs_ctx *ctx, cs_mlp *net, const float *x, const float *ell, int64_t n, float *grad, float *loss) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!net || !x || !ell || !grad) return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    if (n < 16 || n > 8192 || n % 16) return fail(ctx, CS_ERR_ARG, "n must be a multiple of 16 in 16..8192");
+    HIP_TRY(hipSetDevice(ctx->device));
+    MlpAdamArgs a = mlp_adam_args(net);
+    int rc = mlp_backprop(ctx, net, x, ell, nullptr, n, (int)n, a);
+    if (rc) return rc;
+    a.grad_out = grad;
+    a.loss_out = loss;
+    Timed tm(ctx, "mlp_adam");
+    HIP_TRY(launch_mlp_adam(lc_of(ctx), a));
+    return CS_OK;
+}
+
+int cs_mlp_train(cs_ctx *ctx, cs_mlp *net, const float *x, const float *ell, int64_t n_rows, const int32_t *order,
+                 int64_t steps, int batch, double lr, float *loss_trace) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!net || !x || !ell || !order) return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    if (batch < 16 || batch > 8192 || batch % 16) return fail(ctx, CS_ERR_ARG, "batch must be a multiple of 16 in 16..8192");
+    if (steps < 0 || n_rows < 1) return fail(ctx, CS_ERR_ARG, "steps must be >= 0 and n_rows >= 1");
+    if (!(lr > 0.0) || !std::isfinite(lr)) return fail(ctx, CS_ERR_ARG, "lr must be positive and finite");
+    HIP_TRY(hipSetDevice(ctx->device));
+    for (int64_t s = 0; s < steps; ++s) {
+        MlpAdamArgs a = mlp_adam_args(net);
+        int rc = mlp_backprop(ctx, net, x, ell, order + s * batch, n_rows, batch, a);
+        if (rc) return rc;
+        net->t += 1;
+        a.lr = (float)lr;
+        a.bc1 = (float)(1.0 - std::pow(0.9, (double)net->t));
+        a.bc2 = (float)(1.0 - std::pow(0.999, (double)net->t));
+        a.loss_out = loss_trace ? loss_trace + s : nullptr;
+        Timed tm(ctx, "mlp_adam");
+        HIP_TRY(launch_mlp_adam(lc_of(ctx), a));
+    }
+    return CS_OK;
+}
+
+int cs_mlp_fit_output_bias(cs_ctx *ctx, cs_mlp *net, const float *ell, int64_t n) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!net || !ell || n < 1) return fail(ctx, CS_ERR_ARG, "null pointer or n < 1");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_mlp_bias_mean(lc_of(ctx), ell, n, net->out, net->params + net->off_b3));
+    return CS_OK;
+}
+
+static int mlp_forward_impl(cs_ctx *ctx, const cs_mlp *net, const float *x, const float *rgb, int H, int W,
+                            const float *alpha, int k, int64_t n, float *out) {
+    HIP_TRY(hipSetDevice(ctx->device));
+    MlpInferArgs a{};
+    a.x = x;
+    a.rgb = rgb;
+    a.alpha = alpha;
+    a.H = H;
+    a.W = W;
+    a.k = k;
+    a.n = n;
+    a.in = net->in;
+    a.in_pad = net->in_pad;
+    a.out = net->out;
+    a.W1b = net->W1b;
+    a.W2b = net->W2b;
+    a.W3b = net->W3b;
+    a.b1 = net->params + net->off_b1;
+    a.b2 = net->params + net->off_b2;
+    a.b3 = net->params + net->off_b3;
+    a.y = out;
+    Timed tm(ctx, "mlp_infer");
+    HIP_TRY(launch_mlp_infer(lc_of(ctx), a));
+    return CS_OK;
+}
+
+int cs_mlp_infer(cs_ctx *ctx, const cs_mlp *net, const float *rgb, int H, int W, const float *alpha, int k,
+                 float *out) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!net || !rgb || !alpha || !out) return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    if (H < 1 || W < 1 || (int64_t)H * W > ((int64_t)1 << 31) - 1) return fail(ctx, CS_ERR_ARG, "bad image size");
+    if (net->in != 5 + k) return fail(ctx, CS_ERR_ARG, "in_dim %d does not match 5 + k = %d", net->in, 5 + k);
+    return mlp_forward_impl(ctx, net, nullptr, rgb, H, W, alpha, k, (int64_t)H * W, out);
+}
+
+int cs_mlp_forward(cs_ctx *ctx, const cs_mlp *net, const float *x, int64_t n, float *out) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!net || n < 0) return fail(ctx, CS_ERR_ARG, "bad arguments");
+    if (n == 0) return CS_OK;
+    if (!x || !out) return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    return mlp_forward_impl(ctx, net, x, nullptr, 1, 1, nullptr, 0, n, out);
+}
+
 }  // extern "C"

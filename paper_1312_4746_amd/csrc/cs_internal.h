@@ -160,6 +160,58 @@ hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k
                                const StreamSegs &segs, int64_t Mpad, uint8_t *feat, float *rec);
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a);
 hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
+
+// ---- learned surrogate (k_mlp.hip) ----
+constexpr int kMlpHid = 128;                          // hidden units per layer
+constexpr int kMlpMaxIn = 128;                        // input features (padded to 16)
+constexpr int kMlpOutPad = 16;                        // outputs (labels), padded
+constexpr int kMlpBiasStride = 2 * kMlpHid + kMlpOutPad;
+struct MlpTrainArgs {
+    const float *x;        // rows x in (FP32)
+    const float *ell;      // rows x out raw log-likelihoods
+    const int32_t *idx;    // B row indices, or null (row b)
+    int64_t n_rows;        // rows of x and ell (indices are clamped to them)
+    int B, in, in_pad, out;
+    const short *W1b, *W2b, *W3b, *W2Tb, *W3Tb;  // BF16 working copies
+    const float *b1, *b2, *b3;
+    short *Xt, *H1t, *H2t, *DYt, *DZ2t, *DZ1t;   // feature-major [unit][B]
+    float *bgrad;          // [B/16][kMlpBiasStride] per-tile bias-gradient sums
+    float *lossp;          // [B/16] per-tile squared error
+};
+struct MlpWgradArgs {
+    const short *Xt, *H1t, *H2t, *DYt, *DZ2t, *DZ1t;
+    int B, in, in_pad, out, kc;
+    int64_t P, off_W1, off_W2, off_W3;
+    float *gpart;          // [kc][P]
+};
+struct MlpAdamArgs {
+    float *params, *m, *v;
+    const float *gpart, *bgrad, *lossp;
+    float *grad_out;       // non-null: write the gradient, no update
+    float *loss_out;       // non-null: mean loss of the batch
+    int64_t P, off_b1, off_W2, off_b2, off_W3, off_b3;
+    int kc, ntiles, B, in, in_pad, out;
+    float lr, bc1, bc2;    // step size, 1 - beta1^t, 1 - beta2^t
+    short *W1b, *W2b, *W3b, *W2Tb, *W3Tb;
+};
+struct MlpInferArgs {
+    const float *x;        // explicit rows x in, or null: features from rgb/alpha
+    const float *rgb, *alpha;
+    int H, W, k;
+    int64_t n;
+    int in, in_pad, out;
+    const short *W1b, *W2b, *W3b;
+    const float *b1, *b2, *b3;
+    float *y;              // n x out
+};
+hipError_t launch_mlp_fwdbwd(const LaunchCtx &lc, const MlpTrainArgs &a);
+hipError_t launch_mlp_wgrad(const LaunchCtx &lc, const MlpWgradArgs &a);
+hipError_t launch_mlp_adam(const LaunchCtx &lc, const MlpAdamArgs &a);
+hipError_t launch_mlp_convert(const LaunchCtx &lc, const MlpAdamArgs &a);
+hipError_t launch_mlp_infer(const LaunchCtx &lc, const MlpInferArgs &a);
+hipError_t launch_mlp_bias_mean(const LaunchCtx &lc, const float *ell, int64_t n, int out, float *b3);
+hipError_t launch_mlp_features(const LaunchCtx &lc, const float *rgb, int H, int W, const float *alpha, int k,
+                               const int32_t *pix, int64_t n, float *x);
 hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, unsigned int v);
 hipError_t launch_fill_u8(const LaunchCtx &lc, uint8_t *p, size_t count, uint8_t v);
 

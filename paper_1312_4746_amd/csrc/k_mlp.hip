@@ -1,0 +1,451 @@
+// Learned surrogate of the data term on gfx950: a two-hidden-layer perceptron
+// (GELU, 128 units) from a pixel's colour, normalised position and analysed
+// vector (Sec. 2 a = O s of Sec. 3.1 patches) to its per-label
+// log-likelihoods (the Sec. 3.1/3.2 data term), trained by Adam on exact
+// targets.  Matrix products run on BF16 MFMA (v_mfma_f32_16x16x16_bf16) with
+// FP32 accumulation; biases, GELU, the loss and Adam are FP32.
+//
+// Layout trick: every layer computes the TRANSPOSED product, units x rows.
+// With A = weights (rows = units) and B = activations^T (columns = 16 batch
+// rows), lane (g, j) of the result holds units 4g..4g+3 of batch row j, which
+// is exactly the B-operand fragment (k = 4g..4g+3, column j) of the next
+// layer.  So a 16-row tile flows through all layers in registers, and the
+// backward pass reuses the same layout with the transposed weights as A.
+//
+// Weight gradients dW = delta^T act are reductions over the batch; the
+// forward/backward kernel stores the BF16 activations and deltas feature-major
+// ([unit][row]) so that the gradient kernel reads 4 consecutive rows per lane
+// for both MFMA operands.  Partial sums over row chunks are added in a fixed
+// order by the Adam kernel (deterministic).
+#pragma clang fp contract(off)
+
+#include "cs_internal.h"
+#include "cs_device.h"
+
+namespace cs {
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kClipNats = 20.0f;
+constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+__device__ __forceinline__ s16x4 ld4(const short *p) { return *reinterpret_cast<const s16x4 *>(p); }
+__device__ __forceinline__ f32x4 mfma(s16x4 a, s16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// One 16-row tile through the three layers.  xb[ks]: the tile's inputs as
+// B fragments (features 16ks + 4g .. +3 of row j).  W1 row stride ld1, W2 and
+// W3 row stride ld2 (elements); the pointers may point to LDS or global.
+template <bool KEEP>
+__device__ __forceinline__ void mlp_tile_forward(const s16x4 (&xb)[kMlpMaxIn / 16], int nks, const short *W1,
+                                                 int ld1, const short *W2, const short *W3, int ld2,
+                                                 const float *b1, const float *b2, const float *b3, int out,
+                                                 int g, int j, float (&z1)[8][4], float (&z2)[8][4],
+                                                 s16x4 (&h2b)[8], f32x4 &y) {
+    s16x4 h1b[8];
+#pragma unroll
+    for (int hb = 0; hb < 8; ++hb) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const short *wr = W1 + (16 * hb + j) * ld1 + 4 * g;
+#pragma unroll
+        for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
+            if (ks < nks) acc = mfma(ld4(wr + 16 * ks), xb[ks], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float z = acc[r] + b1[16 * hb + 4 * g + r];
+            if (KEEP) z1[hb][r] = z;
+            h1b[hb][r] = bf16_rne(gelu(z));
+        }
+    }
+#pragma unroll
+    for (int hb = 0; hb < 8; ++hb) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const short *wr = W2 + (16 * hb + j) * ld2 + 4 * g;
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) acc = mfma(ld4(wr + 16 * kb), h1b[kb], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float z = acc[r] + b2[16 * hb + 4 * g + r];
+            if (KEEP) z2[hb][r] = z;
+            h2b[hb][r] = bf16_rne(gelu(z));
+        }
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const short *wr = W3 + j * ld2 + 4 * g;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) acc = mfma(ld4(wr + 16 * kb), h2b[kb], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = 4 * g + r;
+        y[r] = acc[r] + (o < out ? b3[o] : 0.0f);
+    }
+}
+
+// ---- forward + backward of one batch (training and the gradient call) ----
+__global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int wt = blockIdx.x * 4 + wave;
+    const int b0 = wt * 16;
+    if (b0 >= a.B) return;
+    const int rb = b0 + j;
+    int64_t row = a.idx ? (int64_t)a.idx[rb] : (int64_t)rb;
+    row = row < 0 ? 0 : (row >= a.n_rows ? a.n_rows - 1 : row);  // memory-safe on bad input
+    const int nks = a.in_pad / 16;
+    s16x4 xb[kMlpMaxIn / 16];
+#pragma unroll
+    for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int f = 16 * ks + 4 * g + q;
+            xb[ks][q] = bf16_rne(f < a.in ? a.x[row * a.in + f] : 0.0f);
+        }
+    float z1[8][4], z2[8][4];
+    s16x4 h2b[8];
+    f32x4 y;
+    mlp_tile_forward<true>(xb, nks, a.W1b, a.in_pad, a.W2b, a.W3b, kMlpHid, a.b1, a.b2, a.b3, a.out, g, j, z1,
+                           z2, h2b, y);
+    // clipped targets t = max(l, max_i l_i - 20); the row max over the four
+    // lanes that share row j (lanes j, j+16, j+32, j+48)
+    float ell[4], mx = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = 4 * g + r;
+        ell[r] = o < a.out ? a.ell[row * a.out + o] : -INFINITY;
+        mx = fmaxf(mx, ell[r]);
+    }
+    mx = fmaxf(mx, __shfl_xor(mx, 16));
+    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    const float scale = 2.0f / ((float)a.B * (float)a.out);
+    float sq = 0.0f;
+    float dy[4];
+    s16x4 dyb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = 4 * g + r;
+        const float t = fmaxf(ell[r], mx - kClipNats);
+        const float d = o < a.out ? y[r] - t : 0.0f;
+        sq += d * d;
+        dy[r] = scale * d;
+        dyb[r] = bf16_rne(dy[r]);
+    }
+    // dH2^T = W3^T dY^T (K = 16 outputs), dZ2 = dH2 * GELU'(z2)
+    s16x4 dz2b[8];
+    float dz2[8][4];
+#pragma unroll
+    for (int hb = 0; hb < 8; ++hb) {
+        const f32x4 acc = mfma(ld4(a.W3Tb + (16 * hb + j) * kMlpOutPad + 4 * g), dyb, f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            dz2[hb][r] = acc[r] * gelu_grad(z2[hb][r]);
+            dz2b[hb][r] = bf16_rne(dz2[hb][r]);
+        }
+    }
+    // dH1^T = W2^T dZ2^T, dZ1 = dH1 * GELU'(z1)
+    float dz1[8][4];
+#pragma unroll
+    for (int hb = 0; hb < 8; ++hb) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const short *wr = a.W2Tb + (16 * hb + j) * kMlpHid + 4 * g;
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) acc = mfma(ld4(wr + 16 * kb), dz2b[kb], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dz1[hb][r] = acc[r] * gelu_grad(z1[hb][r]);
+    }
+    // feature-major BF16 stores for the weight-gradient products
+    const int B = a.B;
+#pragma unroll
+    for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
+        if (ks < nks)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a.Xt[(int64_t)(16 * ks + 4 * g + q) * B + rb] = xb[ks][q];
+#pragma unroll
+    for (int hb = 0; hb < 8; ++hb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t u = (int64_t)(16 * hb + 4 * g + r) * B + rb;
+            a.H1t[u] = bf16_rne(gelu(z1[hb][r]));
+            a.H2t[u] = h2b[hb][r];
+            a.DZ2t[u] = dz2b[hb][r];
+            a.DZ1t[u] = bf16_rne(dz1[hb][r]);
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a.DYt[(int64_t)(4 * g + r) * B + rb] = dyb[r];
+    // bias gradients and squared error of the tile: sums over its 16 rows (FP32)
+    float *bg = a.bgrad + (int64_t)wt * kMlpBiasStride;
+#pragma unroll
+    for (int hb = 0; hb < 8; ++hb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float s1 = dz1[hb][r], s2 = dz2[hb][r];
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                s1 += __shfl_xor(s1, off);
+                s2 += __shfl_xor(s2, off);
+            }
+            if (j == 0) {
+                bg[16 * hb + 4 * g + r] = s1;
+                bg[kMlpHid + 16 * hb + 4 * g + r] = s2;
+            }
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float s3 = dy[r];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) s3 += __shfl_xor(s3, off);
+        if (j == 0) bg[2 * kMlpHid + 4 * g + r] = s3;
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) sq += __shfl_xor(sq, off);
+    if (lane == 0) a.lossp[wt] = sq;
+}
+
+// ---- weight gradients: one wave per (16x16 output tile, row chunk) ----
+__global__ __launch_bounds__(256) void k_mlp_wgrad(MlpWgradArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int item = blockIdx.x * 4 + wave;
+    const int nks = a.in_pad / 16;
+    const int t1 = 8 * nks, t2 = t1 + 64, ntile = t2 + 8;
+    if (item >= ntile * a.kc) return;
+    const int tile = item % ntile, kc = item / ntile;
+    const short *Am, *Bm;
+    int hb, ib, ncols, nrows;
+    int64_t off;
+    if (tile < t1) {          // dW1 = dZ1^T X
+        hb = tile / nks; ib = tile % nks; Am = a.DZ1t; Bm = a.Xt; off = a.off_W1; ncols = a.in; nrows = kMlpHid;
+    } else if (tile < t2) {   // dW2 = dZ2^T H1
+        hb = (tile - t1) / 8; ib = (tile - t1) % 8; Am = a.DZ2t; Bm = a.H1t; off = a.off_W2; ncols = kMlpHid;
+        nrows = kMlpHid;
+    } else {                  // dW3 = dY^T H2
+        hb = 0; ib = tile - t2; Am = a.DYt; Bm = a.H2t; off = a.off_W3; ncols = kMlpHid; nrows = a.out;
+    }
+    const int B = a.B, chunk = B / a.kc, k0 = kc * chunk;
+    const short *ar = Am + (int64_t)(16 * hb + j) * B + 4 * g;
+    const short *br = Bm + (int64_t)(16 * ib + j) * B + 4 * g;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k = k0; k < k0 + chunk; k += 16) acc = mfma(ld4(ar + k), ld4(br + k), acc);
+    float *gp = a.gpart + (int64_t)kc * a.P + off;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int rr = 16 * hb + 4 * g + r, cc = 16 * ib + j;
+        if (rr < nrows && cc < ncols) gp[(int64_t)rr * ncols + cc] = acc[r];
+    }
+}
+
+// ---- Adam (or gradient output) over the flat parameter vector ----
+__global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p == 0 && (a.loss_out)) {
+        double s = 0.0;
+        for (int t = 0; t < a.ntiles; ++t) s += (double)a.lossp[t];
+        *a.loss_out = (float)(s / ((double)a.B * (double)a.out));
+    }
+    if (p >= a.P) return;
+    // which tensor p belongs to
+    float gsum = 0.0f;
+    int bias_unit = -1;
+    if (p >= a.off_b1 && p < a.off_W2) bias_unit = (int)(p - a.off_b1);
+    else if (p >= a.off_b2 && p < a.off_W3) bias_unit = kMlpHid + (int)(p - a.off_b2);
+    else if (p >= a.off_b3) bias_unit = 2 * kMlpHid + (int)(p - a.off_b3);
+    if (bias_unit >= 0) {
+        for (int t = 0; t < a.ntiles; ++t) gsum += a.bgrad[(int64_t)t * kMlpBiasStride + bias_unit];
+    } else {
+        for (int c = 0; c < a.kc; ++c) gsum += a.gpart[(int64_t)c * a.P + p];
+    }
+    if (a.grad_out) {
+        a.grad_out[p] = gsum;
+        return;
+    }
+    const float m = kAdamB1 * a.m[p] + (1.0f - kAdamB1) * gsum;
+    const float v = kAdamB2 * a.v[p] + (1.0f - kAdamB2) * gsum * gsum;
+    a.m[p] = m;
+    a.v[p] = v;
+    const float mhat = m / a.bc1, vhat = v / a.bc2;
+    const float w = a.params[p] - a.lr * mhat / (sqrtf(vhat) + kAdamEps);
+    a.params[p] = w;
+    // BF16 working copies
+    const short wb = bf16_rne(w);
+    if (p < a.off_b1) {
+        const int h = (int)(p / a.in), i = (int)(p % a.in);
+        a.W1b[h * a.in_pad + i] = wb;
+    } else if (p >= a.off_W2 && p < a.off_b2) {
+        const int h = (int)((p - a.off_W2) / kMlpHid), k = (int)((p - a.off_W2) % kMlpHid);
+        a.W2b[h * kMlpHid + k] = wb;
+        a.W2Tb[k * kMlpHid + h] = wb;
+    } else if (p >= a.off_W3 && p < a.off_b3) {
+        const int o = (int)((p - a.off_W3) / kMlpHid), h = (int)((p - a.off_W3) % kMlpHid);
+        a.W3b[o * kMlpHid + h] = wb;
+        a.W3Tb[h * kMlpOutPad + o] = wb;
+    }
+}
+
+// BF16 working copies of the master FP32 parameters (padding stays zero).
+__global__ __launch_bounds__(256) void k_mlp_convert(MlpAdamArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.P) return;
+    const short wb = bf16_rne(a.params[p]);
+    if (p < a.off_b1) {
+        const int h = (int)(p / a.in), i = (int)(p % a.in);
+        a.W1b[h * a.in_pad + i] = wb;
+    } else if (p >= a.off_W2 && p < a.off_b2) {
+        const int h = (int)((p - a.off_W2) / kMlpHid), k = (int)((p - a.off_W2) % kMlpHid);
+        a.W2b[h * kMlpHid + k] = wb;
+        a.W2Tb[k * kMlpHid + h] = wb;
+    } else if (p >= a.off_W3 && p < a.off_b3) {
+        const int o = (int)((p - a.off_W3) / kMlpHid), h = (int)((p - a.off_W3) % kMlpHid);
+        a.W3b[o * kMlpHid + h] = wb;
+        a.W3Tb[h * kMlpOutPad + o] = wb;
+    }
+}
+
+// ---- inference: persistent workgroups, BF16 weights staged once in LDS ----
+// LDS row strides carry 4 extra elements so that the 16 rows of an A
+// fragment fall into different banks.
+constexpr int kLds1 = kMlpMaxIn + 4, kLds2 = kMlpHid + 4;
+__global__ __launch_bounds__(256) void k_mlp_infer(MlpInferArgs a) {
+    __shared__ __align__(16) short sW1[kMlpHid * kLds1];
+    __shared__ __align__(16) short sW2[kMlpHid * kLds2];
+    __shared__ __align__(16) short sW3[kMlpOutPad * kLds2];
+    __shared__ float sb[2 * kMlpHid + kMlpOutPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    for (int e = tid; e < kMlpHid * a.in_pad; e += 256) {
+        const int h = e / a.in_pad, i = e - h * a.in_pad;
+        sW1[h * kLds1 + i] = a.W1b[e];
+    }
+    for (int e = tid; e < kMlpHid * kMlpHid; e += 256) sW2[(e / kMlpHid) * kLds2 + e % kMlpHid] = a.W2b[e];
+    for (int e = tid; e < kMlpOutPad * kMlpHid; e += 256) sW3[(e / kMlpHid) * kLds2 + e % kMlpHid] = a.W3b[e];
+    for (int e = tid; e < 2 * kMlpHid + kMlpOutPad; e += 256)
+        sb[e] = e < kMlpHid ? a.b1[e] : e < 2 * kMlpHid ? a.b2[e - kMlpHid] : (e - 2 * kMlpHid < a.out ? a.b3[e - 2 * kMlpHid] : 0.f);
+    __syncthreads();
+    const int nks = a.in_pad / 16;
+    const int64_t ntiles = (a.n + 15) / 16;
+    const int64_t N = (int64_t)a.H * a.W;
+    const float sx = a.W > 1 ? 1.0f / (float)(a.W - 1) : 0.0f, sy = a.H > 1 ? 1.0f / (float)(a.H - 1) : 0.0f;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < ntiles; t += (int64_t)gridDim.x * 4) {
+        const int64_t pix = t * 16 + j;
+        const bool pv = pix < a.n;
+        s16x4 xb[kMlpMaxIn / 16];
+#pragma unroll
+        for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = 16 * ks + 4 * g + q;
+                float v = 0.0f;
+                if (pv && f < a.in) {
+                    if (a.x) {
+                        v = a.x[pix * a.in + f];
+                    } else if (f < 3) {
+                        v = a.rgb[f * N + pix];
+                    } else if (f == 3) {
+                        v = (float)(pix % a.W) * sx;
+                    } else if (f == 4) {
+                        v = (float)(pix / a.W) * sy;
+                    } else {
+                        v = a.alpha[pix * a.k + (f - 5)];
+                    }
+                }
+                xb[ks][q] = bf16_rne(v);
+            }
+        float z1[8][4], z2[8][4];
+        s16x4 h2b[8];
+        f32x4 y;
+        mlp_tile_forward<false>(xb, nks, sW1, kLds1, sW2, sW3, kLds2, sb, sb + kMlpHid, sb + 2 * kMlpHid, a.out, g,
+                                j, z1, z2, h2b, y);
+        if (pv)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = 4 * g + r;
+                if (o < a.out) a.y[pix * a.out + o] = y[r];
+            }
+    }
+}
+
+// Surrogate inputs of listed pixels: [r, g, b, col/(W-1), row/(H-1), a_0..a_{k-1}].
+__global__ __launch_bounds__(256) void k_mlp_features(const float *rgb, int H, int W, const float *alpha, int k,
+                                                       const int32_t *pix, int64_t n, float *x) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int in = 5 + k;
+    if (e >= n * in) return;
+    const int64_t r = e / in;
+    const int f = (int)(e - r * in);
+    const int64_t p = pix[r];
+    const int64_t N = (int64_t)H * W;
+    float v;
+    if (f < 3) v = rgb[f * N + p];
+    else if (f == 3) v = W > 1 ? (float)(p % W) * (1.0f / (float)(W - 1)) : 0.0f;
+    else if (f == 4) v = H > 1 ? (float)(p / W) * (1.0f / (float)(H - 1)) : 0.0f;
+    else v = alpha[p * k + (f - 5)];
+    x[e] = v;
+}
+
+// Output bias b3_i = mean over the rows of the clipped target
+// t_i = max(l_i, max_j l_j - 20); one workgroup per label, FP64 sum.
+__global__ __launch_bounds__(256) void k_mlp_bias_mean(const float *ell, int64_t n, int out, float *b3) {
+    __shared__ double red[256];
+    const int lab = blockIdx.x;
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += 256) {
+        float mx = -INFINITY;
+        for (int o = 0; o < out; ++o) mx = fmaxf(mx, ell[r * out + o]);
+        s += (double)fmaxf(ell[r * out + lab], mx - kClipNats);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b3[lab] = (float)(red[0] / (double)n);
+}
+
+hipError_t launch_mlp_bias_mean(const LaunchCtx &lc, const float *ell, int64_t n, int out, float *b3) {
+    hipLaunchKernelGGL(k_mlp_bias_mean, dim3((unsigned)out), dim3(256), 0, lc.stream, ell, n, out, b3);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_fwdbwd(const LaunchCtx &lc, const MlpTrainArgs &a) {
+    const int waves = a.B / 16;
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, lc.stream, a);
+    return hipGetLastError();
+}
+hipError_t launch_mlp_wgrad(const LaunchCtx &lc, const MlpWgradArgs &a) {
+    const int ntile = 8 * (a.in_pad / 16) + 64 + 8;
+    const int items = ntile * a.kc;
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)((items + 3) / 4)), dim3(256), 0, lc.stream, a);
+    return hipGetLastError();
+}
+hipError_t launch_mlp_adam(const LaunchCtx &lc, const MlpAdamArgs &a) {
+    hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, lc.stream, a);
+    return hipGetLastError();
+}
+hipError_t launch_mlp_convert(const LaunchCtx &lc, const MlpAdamArgs &a) {
+    hipLaunchKernelGGL(k_mlp_convert, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, lc.stream, a);
+    return hipGetLastError();
+}
+hipError_t launch_mlp_infer(const LaunchCtx &lc, const MlpInferArgs &a) {
+    const int64_t ntiles = (a.n + 15) / 16;
+    int64_t blocks = (int64_t)lc.num_cu * 2;
+    if (blocks > (ntiles + 3) / 4) blocks = (ntiles + 3) / 4;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
+    return hipGetLastError();
+}
+hipError_t launch_mlp_features(const LaunchCtx &lc, const float *rgb, int H, int W, const float *alpha, int k,
+                               const int32_t *pix, int64_t n, float *x) {
+    const int64_t total = n * (5 + k);
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, lc.stream, rgb, H, W,
+                       alpha, k, pix, n, x);
+    return hipGetLastError();
+}
+
+}  // namespace cs

@@ -1,7 +1,7 @@
 """Seeded synthetic workloads for the co-sparse data term.
 
 This package only draws inputs (images, analysis operators, scribble
-samples, training-pixel subsets).  It contains none of the method's
+samples, training-pixel subsets, initial surrogate weights and data order).  It contains none of the method's
 arithmetic, so both the FP64 oracle and the HIP library can be fed from
 it without sharing any computation.
 """
@@ -11,4 +11,6 @@ from .gen import (  # noqa: F401
     make_config,
     make_workload,
     make_omega,
+    mlp_init,
+    mlp_order,
 )

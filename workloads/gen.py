@@ -256,3 +256,28 @@ def make_config(c: int) -> Workload:
     name = cfg.pop("name")
     seed = BASE_SEED + (1 if c == 2 else c)
     return make_workload(name=name, seed=seed, **cfg)
+
+
+def mlp_init(in_dim: int, hidden: int, out_dim: int, seed: int) -> np.ndarray:
+    """Initial surrogate parameters (random numbers only), flat float32 in the
+    order W1 (hidden x in_dim), b1, W2 (hidden x hidden), b2, W3 (out_dim x
+    hidden), b3: each layer uniform in +-1/sqrt(fan_in)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    parts = []
+    for fan_out, fan_in in ((hidden, in_dim), (hidden, hidden), (out_dim, hidden)):
+        bound = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-bound, bound, size=fan_out * fan_in))
+        parts.append(rng.uniform(-bound, bound, size=fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_order(n_rows: int, steps: int, batch: int, seed: int) -> np.ndarray:
+    """Data order of `steps` batches: consecutive epochs, each a fresh random
+    permutation of the rows (int32, steps x batch)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    need = steps * batch
+    chunks, have = [], 0
+    while have < need:
+        chunks.append(rng.permutation(n_rows))
+        have += n_rows
+    return np.concatenate(chunks)[:need].astype(np.int32).reshape(steps, batch)
