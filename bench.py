@@ -31,11 +31,13 @@ PEAK_MFMA = {"fp32": 157.3e12, "bf16": 2.5e15}
 
 
 def parzen_ops_per_pair(k: int) -> int:
-    """Algorithmic VALU lane-operations per pixel x sample pair: location
-    difference and square (4), colour differences and squares (6), XOR and
-    popcount per 32-bit co-support word (2 ceil(k/32)), conversion of the count
-    and the three-term exponent (4), exponent shift, exp and accumulate (3)."""
-    return 17 + 2 * ((k + 31) // 32)
+    """Algorithmic VALU issue slots per pixel x sample pair of the direct
+    evaluation: location difference and square (4), colour differences and
+    squares (6), XOR and popcount per 32-bit co-support word (2 ceil(k/32)),
+    conversion of the count and the three-term exponent (4), log-sum-exp
+    max, shift and accumulate (3), and one v_exp_f32 at a quarter of the
+    FP32 issue rate (4 slots)."""
+    return 17 + 2 * ((k + 31) // 32) + 4
 
 
 def load_traffic(name: str):
@@ -52,10 +54,36 @@ def load_traffic(name: str):
 def kernel_source_digest() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_parzen.hip", "cs_internal.h"):
+    for f in ("k_parzen_mfma.hip", "cs_internal.h"):
         with open(os.path.join(ROOT, "paper_1312_4746_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def precision_sweep(ctx, w, rgb, om, alpha, spix, slab, prm):
+    """BF16 analysis with FP64 recompute inside a margin of tau: co-support
+    bits that differ from the exact masks (those of the proven margin, which
+    equal the FP64 masks bit for bit), the entries recomputed, and the effect
+    of the differing bits on the log-likelihoods."""
+    import numpy as np
+    import torch
+    tau = ctx.tau_median(rgb, w.p, w.mask_sigma, om, alpha, w.tau_frac, precision="bf16")
+    exact, st = ctx.cosupport(rgb, w.p, w.mask_sigma, om, tau, precision="bf16", alpha=alpha, stats=True)
+    ll_exact = ctx.label_loglik(rgb, exact, w.k, spix, slab, w.L, prm)
+    rows = []
+    for name, margin in (("2^-8 tau", 2.0 ** -8 * tau), ("2^-6 tau", 2.0 ** -6 * tau),
+                         ("2^-4 tau", 2.0 ** -4 * tau), ("proven bound", -1.0)):
+        m, s = ctx.cosupport(rgb, w.p, w.mask_sigma, om, tau, margin=margin, precision="bf16", alpha=alpha,
+                             stats=True)
+        x = torch.bitwise_xor(m, exact)
+        bits = int(np.unpackbits(x.cpu().numpy().view(np.uint8)).sum())
+        ll = ctx.label_loglik(rgb, m, w.k, spix, slab, w.L, prm)
+        d = (ll - ll_exact).abs()
+        rows.append({"margin": name, "margin_value": (margin if margin >= 0 else s["max_margin"]),
+                     "mismatched_bits": bits, "recomputed": s["recomputed"],
+                     "recompute_fraction": s["recomputed"] / float(w.N * w.k),
+                     "max_abs_dl_vs_exact_masks": float(d.max()), "mean_abs_dl": float(d.mean())})
+    return {"tau": tau, "proven_margin_max": st["max_margin"], "rows": rows}
 
 
 def cpu_baseline(w, n_sample: int):
@@ -199,6 +227,9 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times), to scale the HBM "
+                         "byte counters of a profiler run")
     ap.add_argument("--mlp-steps", type=int, default=3000)
     ap.add_argument("--mlp-batch", type=int, default=4096)
     ap.add_argument("--mlp-lr", type=float, default=1e-3)
@@ -209,6 +240,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch_read": n * 4, "written": n * 4, "launches": 5}))
+        return
     if args.config == 4:
         surrogate_bench(args)
         return
@@ -242,9 +283,13 @@ def main():
     torch.cuda.synchronize()
     ctx.profile_enable(True)
     torch.cuda.synchronize()
+    per_step = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         step()
+        torch.cuda.synchronize()
+        per_step.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lse_stats = ctx.last_loglik_stats()
@@ -267,7 +312,7 @@ def main():
         traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                "kernel": "k_parzen", "avg_launch_ms": avg_parzen_s * 1e3,
+                "kernel": "k_parzen_mfma", "avg_launch_ms": avg_parzen_s * 1e3,
                 "ops_per_pair": parzen_ops_per_pair(w.k)}
     avg_an = analyze_ms / 1e3 / max(analyze_n, 1)
     gemm_flops = 2.0 * w.k * w.n * w.N
@@ -278,8 +323,12 @@ def main():
         "cosupport_avg_launch_ms": cos_ms / max(cos_n, 1),
         "edt_ms_per_step": edt_ms / args.steps,
         "px_per_s": w.N / (ms_per_step / 1e3),
+        "step_ms_min_median_max": [min(per_step) * 1e3, float(np.median(per_step)) * 1e3,
+                                   max(per_step) * 1e3],
         "lse_reference_events": lse_stats,
     }
+    if w.precision == "bf16":
+        extra["precision_sweep"] = precision_sweep(ctx, w, rgb, om, alpha, spix, slab, prm)
 
     cpu = None
     if not args.no_cpu:

@@ -81,7 +81,10 @@ int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, doubl
  * exact-zero test of the Sec. 2 co-support definition.  `alpha` must be the
  * output of cs_analyze_patches for the same inputs and precision; entries whose
  * rounded value lies within the proven error bound of the selected median are
- * recomputed in FP64, so tau equals the FP64 value bit for bit.
+ * recomputed in FP64, so tau equals the FP64 value bit for bit.  With
+ * precision CS_BF16 the selection runs on an FP32 analysis made inside the
+ * call (its error bound, and so its candidate window, is far smaller); the
+ * context keeps that N*k float buffer until it is destroyed.
  *   alpha   device, N*k float32, 16-byte aligned
  *   tau_out host out.  Synchronises the stream (returns a host value).
  * Errors: as cs_analyze_patches, plus CS_ERR_ARG for frac < 0 or NaN or a

@@ -26,6 +26,9 @@ struct cs_ctx {
     size_t ws_bytes = 0;
     char *cand = nullptr;
     size_t cand_bytes = 0;
+    // FP32 analysed vectors for the exact median of a BF16 analysis
+    float *alpha32 = nullptr;
+    size_t alpha32_bytes = 0;
     // pinned host staging for small device-to-host results
     char *pinned = nullptr;
     // Gaussian patch mask of the last (p, sigma)
@@ -215,6 +218,7 @@ int cs_destroy(cs_ctx *ctx) {
     for (auto e : ctx->pool) hipEventDestroy(e);
     if (ctx->ws) hipFree(ctx->ws);
     if (ctx->cand) hipFree(ctx->cand);
+    if (ctx->alpha32) hipFree(ctx->alpha32);
     if (ctx->wmask) hipFree(ctx->wmask);
     if (ctx->pinned) hipHostFree(ctx->pinned);
     delete ctx;
@@ -330,6 +334,26 @@ int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     const int64_t count = (int64_t)H * W * k;
     const int n = p * p;
+    if (precision == CS_BF16) {
+        // The median is defined by the FP64 values; the candidate window of the
+        // BF16 error bound holds a large share of all entries, the FP32 one a
+        // tiny share.  Select from an FP32 analysis instead (same result).
+        const size_t bytes = sizeof(float) * (size_t)count;
+        if (bytes > ctx->alpha32_bytes) {
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+            if (ctx->alpha32) HIP_TRY(hipFree(ctx->alpha32));
+            ctx->alpha32 = nullptr;
+            ctx->alpha32_bytes = 0;
+            if (hipMalloc((void **)&ctx->alpha32, bytes) != hipSuccess) {
+                ctx->alpha32 = nullptr;
+                return fail(ctx, CS_ERR_NOMEM, "FP32 analysis buffer of %zu bytes could not be allocated", bytes);
+            }
+            ctx->alpha32_bytes = bytes;
+        }
+        if ((rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, CS_FP32, ctx->alpha32))) return rc;
+        alpha = ctx->alpha32;
+        precision = CS_FP32;
+    }
     Carve cv;
     const size_t o_hist = cv.take(sizeof(unsigned int) * 2048);
     const size_t o_st = cv.take(sizeof(TauState));
@@ -482,7 +506,8 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     }
     if (fast) {
         Timed t(ctx, "stream");
-        HIP_TRY(launch_stream_build(lc, recs, k, KP, L, segs, segs.pseg[L], (uint8_t *)(ctx->ws + o_feat),
+        const float cscale = (float)std::sqrt(1.4426950408889634 / (2.0 * prm->sigma_c * prm->sigma_c));
+        HIP_TRY(launch_stream_build(lc, recs, k, KP, L, segs, segs.pseg[L], cscale, (uint8_t *)(ctx->ws + o_feat),
                                     (float *)(ctx->ws + o_srec)));
     }
     unsigned int *fcnt = (unsigned int *)(ctx->ws + o_fcnt);

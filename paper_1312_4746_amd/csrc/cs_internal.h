@@ -142,7 +142,7 @@ struct ParzenFastArgs {
     const float *rgb;
     const uint64_t *masks;
     const uint8_t *feat;   // Mpad x 128*ksteps FP8 sample features (swizzled rows)
-    const float *rec;      // Mpad x 8 {x, y, r, g, b, 0, 0, 0}
+    const float *rec;      // per chunk of 64 slots: 64 float4 {x, y, r, g}, 64 floats b, padding (2 KiB)
     const float4 *coef;    // tiled: [label][group*4 + tile][kTilePix] {nA, nB, -R, K}
     float *loglik;
     unsigned int *work_counter;
@@ -157,7 +157,7 @@ struct ParzenFastArgs {
     const int *meta;
 };
 hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,
-                               const StreamSegs &segs, int64_t Mpad, uint8_t *feat, float *rec);
+                               const StreamSegs &segs, int64_t Mpad, float cscale, uint8_t *feat, float *rec);
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a);
 hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
 

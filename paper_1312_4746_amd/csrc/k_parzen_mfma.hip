@@ -17,8 +17,9 @@
 // pixel and sample positions taken relative to the tile origin it is the dot
 // product of nA [|p|^2, -2 px, -2 py, 1] and [1, sx, sy, |s|^2], exact in its
 // integer part, and the log-sum-exp reference rides in as the accumulator
-// input.  Per pair the VALU is left with the colour distance (three
-// differences, a square and two FMAs), two FMAs combining the terms, one
+// input.  Colours are stored pre-scaled by sqrt(log2(e) / (2 sigma_c^2)), so
+// per pair the VALU is left with three colour differences, four FMAs (the
+// texture term onto the MFMA result and the three negated squares), one
 // v_exp_f32 and one add.
 //
 // Work decomposition.  A workgroup of 4 waves owns four 8x4 pixel tiles (one
@@ -67,15 +68,20 @@ __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib, uint32_t b) {
     return ((nib * 0x00204081u) & 0x01010101u) * b;
 }
 
-// Physical 16-byte slot of logical slot p in a sample row (XOR swizzle inside
-// each 128-byte slice, keyed by the row inside its chunk, spreads LDS banks).
-__device__ __forceinline__ int swz(int p, int row) { return (p & ~7) | ((p & 7) ^ (row & 7)); }
+// Physical 16-byte slot of logical slot p in a sample row.  Rows are 128 B
+// (or a multiple), so two consecutive rows share one 256-byte span of the 64
+// LDS banks; XOR-ing the slot with (row / 2) mod 8 puts the 16 rows that one
+// 16-lane group reads at the same logical slot into 16 distinct 16-byte bank
+// windows.
+__device__ __forceinline__ int swz(int p, int row) { return (p & ~7) | ((p & 7) ^ ((row >> 1) & 7)); }
 
 // Padded sample stream: for every padded slot s (label segments rounded up to
-// whole chunks), the FP8 feature row (swizzled) and a 32-byte record
-// {x, y, r, g, b, 0, 0, 0}; padding slots have zero features and x = 1e15.
+// whole chunks), the FP8 feature row (swizzled) and its record; the records
+// of a chunk of 64 slots take 2 KiB: 64 float4 {x, y, r, g}, then 64 floats b
+// (then padding), so that 16 lanes reading 16 consecutive slots touch distinct
+// LDS banks.  Padding slots have zero features and x = 1e15.
 __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int k, int KP, int L,
-                                                       StreamSegs segs, int64_t Mpad,
+                                                       StreamSegs segs, int64_t Mpad, float cscale,
                                                        uint8_t *feat, float *rec) {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= Mpad) return;
@@ -85,7 +91,9 @@ __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int
     const bool real = j < (int64_t)(segs.seg[l + 1] - segs.seg[l]);
     uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t cnt = 0;
-    float *ro = rec + s * 8;
+    const int row = (int)(s & (kChunkS - 1));
+    float *rc = rec + (s - row) * 8;  // this chunk's 2 KiB of records
+    float v5[5] = {kFarAway, 0.0f, 0.0f, 0.0f, 0.0f};
     if (real) {
         const uint32_t *rw = recs[segs.seg[l] + j].w;
         for (int w = 0; w < 8; ++w) {
@@ -96,13 +104,14 @@ __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int
             words[w] = v;
             cnt += __popc(v);
         }
-        for (int q = 0; q < 5; ++q) ro[q] = __uint_as_float(rw[q]);
-    } else {
-        ro[0] = kFarAway;
-        for (int q = 1; q < 5; ++q) ro[q] = 0.0f;
+        for (int q = 0; q < 5; ++q) v5[q] = __uint_as_float(rw[q]);
+        for (int q = 2; q < 5; ++q) v5[q] *= cscale;  // colours in units of the kernel width
     }
-    ro[5] = ro[6] = ro[7] = 0.0f;
-    const int row = (int)(s & (kChunkS - 1));
+    for (int q = 0; q < 4; ++q) rc[4 * row + q] = v5[q];
+    rc[4 * kChunkS + row] = v5[4];
+    rc[5 * kChunkS + row] = 0.0f;  // padding (keeps the whole 2 KiB defined)
+    rc[6 * kChunkS + row] = 0.0f;
+    rc[7 * kChunkS + row] = 0.0f;
     uint32_t *fo = reinterpret_cast<uint32_t *>(feat + s * KP);
     for (int p = 0; p < KP / 16; ++p) {  // logical 16-byte slot p holds features 16p..16p+15
         uint32_t out4[4];
@@ -127,9 +136,9 @@ __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int
 }
 
 hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,
-                               const StreamSegs &segs, int64_t Mpad, uint8_t *feat, float *rec) {
+                               const StreamSegs &segs, int64_t Mpad, float cscale, uint8_t *feat, float *rec) {
     hipLaunchKernelGGL(k_stream_build, dim3((unsigned)((Mpad + 255) / 256)), dim3(256), 0, lc.stream,
-                       recs, k, KP, L, segs, Mpad, feat, rec);
+                       recs, k, KP, L, segs, Mpad, cscale, feat, rec);
     return hipGetLastError();
 }
 
@@ -155,7 +164,9 @@ void k_parzen_mfma(ParzenFastArgs a) {
     const int g = lane >> 4, jl = lane & 15;
     const int64_t N = (int64_t)a.H * a.W;
     const int W64 = (a.k + 63) / 64;
-    const float nC = (float)(-kLog2eF / (2.0 * a.sigma_c * a.sigma_c));
+    // colours are scaled by sqrt(log2(e) / (2 sigma_c^2)) (samples by the
+    // stream builder), so the colour term is minus the squared difference
+    const float cscale = (float)sqrt(kLog2eF / (2.0 * a.sigma_c * a.sigma_c));
     const uint32_t *mask32 = reinterpret_cast<const uint32_t *>(a.masks);
     const int nitems = a.ngroups * a.L;
     const int64_t coef_label_stride = (int64_t)a.ngroups * 4 * kTilePix;
@@ -218,9 +229,9 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 const bool v = tile_ok && px < a.W && py < a.H;
                 anyvalid |= v;
                 const int64_t pix = v ? (int64_t)py * a.W + px : 0;
-                pr[rb][r] = a.rgb[pix];
-                pg[rb][r] = a.rgb[N + pix];
-                pb[rb][r] = a.rgb[2 * N + pix];
+                pr[rb][r] = cscale * a.rgb[pix];
+                pg[rb][r] = cscale * a.rgb[N + pix];
+                pb[rb][r] = cscale * a.rgb[2 * N + pix];
             }
         bool active = __ballot(anyvalid) != 0ull;  // wave-uniform
         const bool wave_valid = active;
@@ -303,8 +314,8 @@ void k_parzen_mfma(ParzenFastArgs a) {
                     Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
                                    (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
                 }
-                const float4 sxyrg = *reinterpret_cast<const float4 *>(Rr + js * 8);
-                const float sb = Rr[js * 8 + 4];
+                const float4 sxyrg = *reinterpret_cast<const float4 *>(Rr + js * 4);
+                const float sb = Rr[4 * kChunkS + js];
                 f32x4 T[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
@@ -326,9 +337,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float dr = pr[rb][r] - sxyrg.z, dg = pg[rb][r] - sxyrg.w, db = pb[rb][r] - sb;
-                        const float c2 = fmaf(db, db, fmaf(dg, dg, dr * dr));
                         float u = fmaf(T[rb][r], nB[rb][r], D[rb][r]);
-                        u = fmaf(nC, c2, u);
+                        u = fmaf(-dr, dr, u);
+                        u = fmaf(-dg, dg, u);
+                        u = fmaf(-db, db, u);
                         S[rb][r] += __builtin_amdgcn_exp2f(u);
                     }
             }
@@ -373,9 +385,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
         if (!wave_valid) continue;
 
         // ---- end of item: combine the 16 lanes sharing each pixel (one sample
-        // column each) at their largest reference
+        // column each) at their largest reference; lane jl < 8 of each 16-lane
+        // group keeps pixel (rb, r) = (jl >> 2, jl & 3) for the write
         bool bad = item_bad;
-        float Rtot[RB][4], Stot[RB][4];
+        float Rw = 0.0f, Sw = 1.0f;
         if (!bad) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -388,11 +401,13 @@ void k_parzen_mfma(ParzenFastArgs a) {
                     float sp = S[rb][r] * __builtin_amdgcn_exp2f(Rl - Rm);
 #pragma unroll
                     for (int off = 1; off < 16; off <<= 1) sp += __shfl_xor(sp, off);
-                    Rtot[rb][r] = Rm;
-                    Stot[rb][r] = sp;
                     const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
                     const bool v = tile_ok && px < a.W && py < a.H;
                     if (v && !(sp <= 0x1p126f && sp > 0.0f)) bad = true;
+                    if (jl == 4 * rb + r) {
+                        Rw = Rm;
+                        Sw = sp;
+                    }
                 }
         }
         if (__ballot(bad)) {
@@ -402,17 +417,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
             }
             continue;
         }
-        // lane jl < 8 of each 16-lane group writes pixel (rb, r) = (jl >> 2, jl & 3)
         if (jl < 4 * RB) {
-            float Rw = 0.0f, Sw = 1.0f;
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (jl == 4 * rb + r) {
-                        Rw = Rtot[rb][r];
-                        Sw = Stot[rb][r];
-                    }
             const int rb = jl >> 2, r = jl & 3;
             const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
             if (tile_ok && px < a.W && py < a.H) {

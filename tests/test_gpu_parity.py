@@ -305,3 +305,43 @@ def test_patch_errors(ctx):
     with pytest.raises(CosparseError) as e:
         ctx.analyze_patches(dev(w.rgb), 5, 0.0, dev(w.omega))
     assert e.value.code == 1
+
+
+def _full_image_sampled(ctx, w, masks, n_sample, seed):
+    """The full-image (fast) path in the launch configuration the benchmark
+    times, checked against the oracle on sampled pixels (border and corner
+    pixels included)."""
+    from paper_1312_4746_amd import LoglikParams
+    prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
+                       rho_floor_px=w.rho_floor_px)
+    got = ctx.label_loglik(dev(w.rgb), dev(masks.view(np.int64)), w.k, dev(w.sample_pix),
+                           dev(w.sample_label), w.L, prm).cpu().numpy()
+    rng = np.random.default_rng(seed)
+    pix = np.unique(np.concatenate([rng.choice(w.N, n_sample, replace=False),
+                                    [0, w.W - 1, w.N - w.W, w.N - 1], w.sample_pix[:8]])).astype(np.int32)
+    ref = oracle.label_loglik(w.rgb, masks, w.k, w.sample_pix, w.sample_label, w.L, alpha_rho=prm.alpha_rho,
+                              sigma_c=prm.sigma_c, beta_scale=prm.beta_scale, rho_floor=prm.rho_floor_px,
+                              pix=pix)
+    _ll_check(got[pix], ref)
+    assert np.all(np.isfinite(got))
+    return ctx.last_loglik_stats()
+
+
+def test_loglik_bsds_full_image_fast_path(ctx):
+    w = make_config(1)
+    masks, _, _ = oracle.full_masks(w)
+    st = _full_image_sampled(ctx, w, masks, 1500, 11)
+    assert st["overflow_tiles"] == 0
+
+
+def test_loglik_large_full_image_fast_path(ctx):
+    """1024x1024, k = 242 (two FP8 feature steps), 16 labels, 50,000 samples;
+    the masks come from the library (bit-exact with the oracle at every
+    smaller case above, p = 11 and k = 242 included)."""
+    w = make_config(3)
+    rgb = dev(w.rgb)
+    a = ctx.analyze_patches(rgb, w.p, w.mask_sigma, dev(w.omega))
+    tau = ctx.tau_median(rgb, w.p, w.mask_sigma, dev(w.omega), a, 0.1)
+    m = ctx.cosupport(rgb, w.p, w.mask_sigma, dev(w.omega), tau, alpha=a)
+    masks = masks_u64(m)
+    _full_image_sampled(ctx, w, masks, 400, 12)
