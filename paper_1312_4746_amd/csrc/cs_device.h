@@ -58,6 +58,21 @@ __device__ __noinline__ inline void patch_s64(const float *rgb, int H, int W, in
     for (int t = 0; t < n; ++t) s[t] = s[t] / nu;
 }
 
+// Per-row decision margin: the given absolute margin when >= 0, else the
+// proven bound coef * ||O_j||_2 of the rounded analysed vector (unit-norm
+// patch) with a relative safety factor for the FP64 evaluation of the bound
+// itself and a tiny absolute term for flushed subnormal products.
+__device__ __forceinline__ double row_margin(const float *omega, int j, int n, double margin, double coef) {
+#pragma clang fp contract(off)
+    if (margin >= 0.0) return margin;
+    double ss = 0.0;
+    for (int t = 0; t < n; ++t) {
+        const double o = (double)omega[(int64_t)j * n + t];
+        ss = ss + o * o;
+    }
+    return coef * sqrt(ss) * (1.0 + 0x1p-20) + 0x1p-100;
+}
+
 __device__ __forceinline__ short bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
     u += 0x7FFFu + ((u >> 16) & 1u);

@@ -357,45 +357,38 @@ int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
     Carve cv;
     const size_t o_hist = cv.take(sizeof(unsigned int) * 2048);
     const size_t o_st = cv.take(sizeof(TauState));
-    const size_t o_marg = cv.take(sizeof(double) * k), o_max = cv.take(sizeof(double));
+    const size_t o_max = cv.take(sizeof(double));
     if ((rc = ensure_ws(ctx, cv.off))) return rc;
     unsigned int *hist = (unsigned int *)(ctx->ws + o_hist);
     TauState *st = (TauState *)(ctx->ws + o_st);
-    double *marg = (double *)(ctx->ws + o_marg), *mmax = (double *)(ctx->ws + o_max);
+    double *mmax = (double *)(ctx->ws + o_max);
     const LaunchCtx lc = lc_of(ctx);
     int64_t cap = (int64_t)std::min<int64_t>(count, (int64_t)1 << 20);
-    if ((rc = ensure_cand(ctx, (size_t)cap * 16))) return rc;
-    {
-        Timed t(ctx, "tau_select");
-        HIP_TRY(launch_thresholds(lc, omega, k, n, 0.0, -1.0, margin_coef(precision, n), nullptr,
-                                  nullptr, marg, mmax));
-        HIP_TRY(tau_select_float(lc, alpha, count, hist, st));
-        HIP_TRY(tau_gather(lc, alpha, count, mmax, st, (int64_t *)ctx->cand, cap));
-    }
     TauState hs;
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, st, sizeof(TauState), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    std::memcpy(&hs, ctx->pinned, sizeof(TauState));
-    if ((int64_t)hs.ncand > cap) {
-        cap = (int64_t)hs.ncand;
+    for (int attempt = 0;; ++attempt) {
         if ((rc = ensure_cand(ctx, (size_t)cap * 16))) return rc;
-        HIP_TRY(tau_reset_gather(lc, st));
-        HIP_TRY(tau_gather(lc, alpha, count, mmax, st, (int64_t *)ctx->cand, cap));
+        int64_t *cand = (int64_t *)ctx->cand;
+        double *vals = (double *)(ctx->cand + (size_t)cap * 8);
+        {
+            Timed t(ctx, "tau_select");
+            if (attempt == 0) {
+                HIP_TRY(tau_select_float(lc, alpha, count, hist, st, omega, k, n, margin_coef(precision, n), mmax));
+            } else {
+                HIP_TRY(tau_reset_gather(lc, st));
+            }
+            HIP_TRY(tau_gather(lc, alpha, count, mmax, st, cand, cap));
+        }
+        {
+            Timed t(ctx, "tau_exact");
+            HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, cap, vals, frac, st));
+        }
         HIP_TRY(hipMemcpyAsync(ctx->pinned, st, sizeof(TauState), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
         std::memcpy(&hs, ctx->pinned, sizeof(TauState));
-        if ((int64_t)hs.ncand > cap) return fail(ctx, CS_ERR_HIP, "candidate count changed between passes");
+        if ((int64_t)hs.ncand <= cap) break;
+        if (attempt > 0) return fail(ctx, CS_ERR_HIP, "candidate count changed between passes");
+        cap = (int64_t)hs.ncand;  // one retry with room for every candidate
     }
-    int64_t *cand = (int64_t *)ctx->cand;
-    double *vals = (double *)(ctx->cand + (size_t)cap * 8);
-    {
-        Timed t(ctx, "tau_exact");
-        HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, (int64_t)hs.ncand, vals,
-                           frac, st));
-    }
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, st, sizeof(TauState), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    std::memcpy(&hs, ctx->pinned, sizeof(TauState));
     if (std::isnan(hs.median))
         return fail(ctx, CS_ERR_HIP, "exact median outside the candidate window (error bound violated)");
     *tau_out = hs.tau;
@@ -441,8 +434,11 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const int nblocks = (int)((M + 255) / 256);
     Carve cv;
     const size_t o_bc = cv.take(sizeof(int32_t) * (size_t)L * nblocks);
-    const size_t o_tf = cv.take(sizeof(int32_t) * (L + 1));
-    const size_t o_cnt = cv.take(sizeof(unsigned int) * 2);
+    // label counts (L+1), the exact kernel's two counters and the fast
+    // kernel's four counters share one region, cleared by one fill
+    const size_t o_tf = cv.take(sizeof(int32_t) * (L + 1 + 2 + 4));
+    const size_t o_cnt = o_tf + sizeof(int32_t) * (L + 1);
+    const size_t o_fcnt = o_cnt + sizeof(unsigned int) * 2;
     const size_t o_rec = cv.take(sizeof(SampleRec) * (size_t)M);
     const size_t o_seed = cv.take((size_t)L * N);
     const size_t o_col = cv.take(sizeof(int32_t) * (size_t)L * N);
@@ -459,7 +455,6 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_feat = fast ? cv.take((size_t)Mpad_max * KP) : 0;
     const size_t o_srec = fast ? cv.take(sizeof(float) * 8 * (size_t)Mpad_max) : 0;
     const size_t o_fix = fast ? cv.take(sizeof(int2) * (size_t)ntiles_pad * L) : 0;
-    const size_t o_fcnt = cv.take(sizeof(unsigned int) * 4);
     const size_t o_meta = cv.take(sizeof(int32_t) * (2 * (size_t)L + 1));
     const size_t o_coef = cv.take(sizeof(float4) * (size_t)L *
                                   (size_t)(fast ? ntiles_pad * kTilePix : npix));
@@ -475,7 +470,7 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
 
     {
         Timed t(ctx, "samples");
-        HIP_TRY(launch_fill_u32(lc, (unsigned int *)tf, (size_t)L + 1, 0u));
+        HIP_TRY(launch_fill_u32(lc, (unsigned int *)tf, (size_t)L + 1 + 2 + 4, 0u));
         HIP_TRY(launch_sample_count(lc, sample_label, sample_pix, M, L, N, bc, tf, nblocks));
         if (pix_subset) HIP_TRY(launch_check_pix(lc, pix_subset, npix, N, tf + L));
     }
@@ -552,7 +547,6 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         Timed t(ctx, "coef");
         HIP_TRY(launch_coef(lc, pa, coef));
     }
-    HIP_TRY(launch_fill_u32(lc, cnt, 2, 0u));
     if (fast) {
         ParzenFastArgs fa{};
         fa.rgb = rgb;
@@ -584,7 +578,6 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         HIP_TRY(hipMemcpyAsync(meta_d, meta_h, sizeof(int32_t) * (2 * (size_t)L + 1), hipMemcpyHostToDevice,
                                ctx->stream));
         fa.meta = meta_d;
-        HIP_TRY(launch_fill_u32(lc, fcnt, 4, 0u));
         ctx->loglik_counters = fcnt;
         {
             Timed t(ctx, "parzen");

@@ -77,14 +77,19 @@ struct TauState {
     double median;                // exact FP64 median
     double tau;                   // frac * median
 };
+// Radix select of the float |alpha| of the target rank; the first kernel also
+// writes the largest per-row error bound (coef) of the rows of omega.
 hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t count,
-                            unsigned int *hist, TauState *st);
+                            unsigned int *hist, TauState *st, const float *omega, int k, int n,
+                            double coef, double *max_margin);
 hipError_t tau_reset_gather(const LaunchCtx &lc, TauState *st);
 hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
                       const double *max_margin, TauState *st, int64_t *cand, int64_t cap);
+// FP64 recompute of the candidates and the exact selection; the candidate
+// count is read on the device (at most cap are used; more leaves NaN).
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
-                      int64_t ncand, double *vals, double frac, TauState *st);
+                      int64_t cap, double *vals, double frac, TauState *st);
 
 // ---- texture similarity (k_tsm.hip) ----
 hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const uint64_t *B,

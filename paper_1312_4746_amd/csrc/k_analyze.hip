@@ -228,12 +228,15 @@ hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precisi
 // analysis epilogue): bit j of pixel x is set when the rounded |a_j| is at most
 // t_in[j] and clear above t_out[j]; in between the entry is recomputed in FP64
 // from the exact patch (Sec. 2 co-support, Sec. 3.1 patch).  A wave owns
-// kMaskPx consecutive pixels (all loads issued up front), lane = row j within
-// a 64-bit mask word.  The rare FP64 step builds the pixel's patch in the
-// wave's own LDS slice; LDS accesses of one wave complete in issue order, so
-// the hand-offs between the lanes and lane 0 (which runs every sum in t order)
-// need no barrier.
+// kMaskPx consecutive pixels, lane = row j within a 64-bit mask word, so the
+// loads are coalesced and each mask word is the ballot of one comparison.
+// The rare entries in between are resolved per pixel by the whole wave: the
+// pixel's exact patch is built in the wave's LDS slice (LDS accesses of one
+// wave complete in issue order, so the hand-offs between the lanes and lane
+// 0, which runs every sum in t order, need no barrier), then lane j
+// recomputes row j.
 constexpr int kMaskPx = 8;
+template <int W64>
 __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t N, int k,
                                                      const float *t_in, const float *t_out, double tau,
                                                      const float *rgb, int H, int W, int p,
@@ -243,40 +246,51 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
     __shared__ double s_all[4][15 * 15];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *s = s_all[wave];
-    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * kMaskPx;
-    const int W64 = (k + 63) / 64, n = p * p, h = (p - 1) / 2;
+    const int n = p * p, h = (p - 1) / 2;
     const int64_t NN = (int64_t)H * W;
-    float tin[4], tout[4];
+    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * kMaskPx;
+    if (p0 >= N) return;
+    float tin[W64], tout[W64];
+    uint64_t vmask[W64];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < W64; ++w) {
         const int j = 64 * w + lane;
-        const bool jv = w < W64 && j < k;
-        tin[w] = jv ? t_in[j] : -1.0f;    // rows past k: never in, never near
-        tout[w] = jv ? t_out[j] : -2.0f;
+        const bool jv = j < k;
+        tin[w] = jv ? t_in[j] : 0.0f;
+        tout[w] = jv ? t_out[j] : 0.0f;
+        vmask[w] = __ballot(jv);
     }
-    float v[kMaskPx][4];
+    float v[kMaskPx][W64];
 #pragma unroll
     for (int i = 0; i < kMaskPx; ++i)
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < W64; ++w) {
             const int j = 64 * w + lane;
             const int64_t pix = p0 + i;
-            v[i][w] = (w < W64 && j < k && pix < N) ? fabsf(alpha[pix * k + j]) : INFINITY;
+            v[i][w] = (j < k && pix < N) ? fabsf(alpha[pix * k + j]) : INFINITY;
+        }
+    uint64_t words[kMaskPx][W64], nearw[kMaskPx][W64];
+    uint64_t anyn = 0;
+#pragma unroll
+    for (int i = 0; i < kMaskPx; ++i)
+#pragma unroll
+        for (int w = 0; w < W64; ++w) {
+            const uint64_t inb = __ballot(v[i][w] <= tin[w]);
+            const uint64_t outb = __ballot(v[i][w] > tout[w]);
+            words[i][w] = inb & vmask[w];
+            nearw[i][w] = ~(inb | outb) & vmask[w];  // NaN: neither, so recomputed
+            anyn |= nearw[i][w];
         }
     unsigned long long nrec = 0;
+    if (anyn) {
 #pragma unroll
-    for (int i = 0; i < kMaskPx; ++i) {
-        const int64_t pix = p0 + i;
-        if (pix >= N) break;
-        bool in[4], near[4];
-        bool anyn = false;
+        for (int i = 0; i < kMaskPx; ++i) {
+            const int64_t pix = p0 + i;
+            if (pix >= N) break;
+            uint64_t any_i = 0;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            in[w] = v[i][w] <= tin[w];
-            near[w] = !in[w] && !(v[i][w] > tout[w]);
-            anyn |= near[w];
-        }
-        if (__ballot(anyn)) {
+            for (int w = 0; w < W64; ++w) any_i |= nearw[i][w];
+            if (!any_i) continue;
             const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
             for (int t = lane; t < n; t += 64) {
                 const int u = t / p, vv = t - u * p;
@@ -297,22 +311,25 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
             nu2 = __shfl(nu2, 0);
             for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / sqrt(nu2);
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                if (near[w]) in[w] = fabs(dot64(omega + (int64_t)(64 * w + lane) * n, s, n)) <= tau;
-                nrec += (unsigned long long)__popcll(__ballot(near[w]));
+            for (int w = 0; w < W64; ++w) {
+                const uint64_t nm = nearw[i][w];
+                if (!nm) continue;
+                bool in = false;
+                if ((nm >> lane) & 1ull) in = fabs(dot64(omega + (int64_t)(64 * w + lane) * n, s, n)) <= tau;
+                words[i][w] = (words[i][w] & ~nm) | (__ballot(in) & nm);
+                nrec += (unsigned long long)__popcll(nm);
             }
         }
-        unsigned long long bits[4];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) bits[w] = __ballot(in[w]);
-        if (lane < W64) {
-            unsigned long long b = bits[0];
-#pragma unroll
-            for (int w = 1; w < 4; ++w)
-                if (lane == w) b = bits[w];
-            masks[pix * W64 + lane] = b;
-        }
     }
+    // lane l < kMaskPx * W64 stores word (l / W64, l % W64)
+    const int li = lane / W64, lw = lane - li * W64;
+    uint64_t outw = 0;
+#pragma unroll
+    for (int i = 0; i < kMaskPx; ++i)
+#pragma unroll
+        for (int w = 0; w < W64; ++w)
+            if (li == i && lw == w) outw = words[i][w];
+    if (lane < kMaskPx * W64 && p0 + li < N) masks[(p0 + li) * W64 + lw] = outw;
     if (recomputed && lane == 0 && nrec) atomicAdd(recomputed, nrec);
 }
 
@@ -321,10 +338,17 @@ hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N,
                              const double *wmask, const float *omega, uint64_t *masks,
                              unsigned long long *recomputed) {
     if (N <= 0) return hipSuccess;
-    const int64_t per_block = 4 * kMaskPx;
-    hipLaunchKernelGGL(k_mask_alpha, dim3((unsigned)((N + per_block - 1) / per_block)), dim3(256), 0, lc.stream,
-                       alpha, N, k, t_in,
-                       t_out, tau, rgb, H, W, p, wmask, omega, masks, recomputed);
+    const int64_t blocks = (N + 4 * kMaskPx - 1) / (4 * kMaskPx);
+#define CS_MASK_LAUNCH(WW)                                                                              \
+    hipLaunchKernelGGL(k_mask_alpha<WW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, N, k, t_in, \
+                       t_out, tau, rgb, H, W, p, wmask, omega, masks, recomputed)
+    switch ((k + 63) / 64) {
+        case 1: CS_MASK_LAUNCH(1); break;
+        case 2: CS_MASK_LAUNCH(2); break;
+        case 3: CS_MASK_LAUNCH(3); break;
+        default: CS_MASK_LAUNCH(4); break;
+    }
+#undef CS_MASK_LAUNCH
     return hipGetLastError();
 }
 
@@ -337,15 +361,9 @@ __global__ __launch_bounds__(256) void k_thresholds(const float *omega, int k, i
     const int j = threadIdx.x;
     double m = 0.0;
     if (j < k) {
-        double ss = 0.0;
-        for (int t = 0; t < n; ++t) {
-            double o = (double)omega[(int64_t)j * n + t];
-            ss = ss + o * o;
-        }
         // Proven bound: |a_rounded - a| <= coef * sum_t |O_jt||s_t| <= coef * ||O_j||_2,
-        // since ||s||_2 = 1; a relative safety factor covers the FP64 evaluation of the
-        // bound itself and a tiny absolute term covers flushed subnormal products.
-        m = margin >= 0.0 ? margin : coef * sqrt(ss) * (1.0 + 0x1p-20) + 0x1p-100;
+        // since ||s||_2 = 1.
+        m = row_margin(omega, j, n, margin, coef);
         const double lo = tau - m, hi = tau + m;
         float fl = (float)lo;
         if ((double)fl > lo) fl = nextafterf(fl, -INFINITY);

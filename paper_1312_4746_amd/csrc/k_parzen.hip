@@ -28,7 +28,7 @@ namespace cs {
 
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
-constexpr int kRefSubset = 8;
+constexpr int kRefSubset = 4;
 constexpr float kRefMargin = 48.0f;
 
 template <int NW>

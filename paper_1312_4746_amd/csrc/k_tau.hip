@@ -12,7 +12,9 @@
 //    window are counted.
 // 3. The candidates are recomputed in FP64 (same operation order as the
 //    oracle's patch and product) and a single-workgroup radix select over their
-//    64-bit patterns picks the rank that remains after the count below.
+//    64-bit patterns picks the rank that remains after the count below.  The
+//    whole chain runs without a host round trip; the host reads the result
+//    once and retries with a larger candidate buffer if it overflowed.
 #pragma clang fp contract(off)
 
 #include "cs_internal.h"
@@ -22,8 +24,19 @@ namespace cs {
 
 constexpr int kHistBins = 2048;
 
+// Clears the selection state and the histogram, and writes the largest
+// per-row error bound (the half-width of the candidate window).
 __global__ __launch_bounds__(256) void k_tau_init(TauState *st, unsigned long long rank0,
-                                                   unsigned int *hist) {
+                                                   unsigned int *hist, const float *omega, int k, int n,
+                                                   double coef, double *max_margin) {
+    __shared__ double red[256];
+    red[threadIdx.x] = (int)threadIdx.x < k ? row_margin(omega, threadIdx.x, n, -1.0, coef) : 0.0;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if ((int)threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *max_margin = red[0];
     if (threadIdx.x == 0) {
         st->rank0 = rank0;
         st->rank = rank0;
@@ -127,9 +140,10 @@ __global__ __launch_bounds__(256) void k_tau_pick(unsigned int *hist, int shift,
 }
 
 hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t count,
-                            unsigned int *hist, TauState *st) {
+                            unsigned int *hist, TauState *st, const float *omega, int k, int n,
+                            double coef, double *max_margin) {
     hipLaunchKernelGGL(k_tau_init, dim3(1), dim3(256), 0, lc.stream, st,
-                       (unsigned long long)((count - 1) / 2), hist);
+                       (unsigned long long)((count - 1) / 2), hist, omega, k, n, coef, max_margin);
     const int shifts[3] = {21, 10, 0};
     const unsigned int pmasks[3] = {0u, 0xFFE00000u, 0xFFFFFC00u};
     auto blocks_for = [&](int per_cu) {
@@ -254,140 +268,152 @@ hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
 // FP64 recompute of each candidate entry e = pixel * k + j, one wave per
 // candidate: element-wise steps run across lanes, every sum runs in lane 0 in
 // t order, so the result is the same bit pattern as a sequential evaluation.
+// Persistent waves read the candidate count from the device state (no host
+// round trip); counts beyond the capacity are left to the host's retry.
 __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, int W, int p,
                                                        const double *wmask, const float *omega,
-                                                       int k, const int64_t *cand, int64_t ncand,
-                                                       double *vals) {
+                                                       int k, const int64_t *cand, const TauState *st,
+                                                       int64_t cap, double *vals) {
 #pragma clang fp contract(off)
     __shared__ double s[15 * 15];
     __shared__ double sh_mu, sh_nu2;
-    const int64_t c = blockIdx.x;
-    if (c >= ncand) return;
-    const int64_t e = cand[c];
-    const int64_t pix = e / k;
-    const int j = (int)(e - pix * k);
+    const unsigned long long nc = st->ncand;
+    const int64_t ncand = (int64_t)nc < cap ? (int64_t)nc : cap;
     const int n = p * p, h = (p - 1) / 2;
     const int64_t N = (int64_t)H * W;
-    const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
     const int lane = threadIdx.x;
-    for (int t = lane; t < n; t += 64) {
-        const int u = t / p, v = t - u * p;
-        const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + v - h, W);
-        s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
-    }
-    __syncthreads();
-    if (lane == 0) {
-        double sum = 0.0;
-        for (int t = 0; t < n; ++t) sum = sum + s[t];
-        sh_mu = sum / (double)n;
-    }
-    __syncthreads();
-    const double mu = sh_mu;
-    for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
-    __syncthreads();
-    if (lane == 0) {
-        double nu2 = 0.0;
-        for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
-        sh_nu2 = nu2;
-    }
-    __syncthreads();
-    const double nu2 = sh_nu2;
-    const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
-    for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / nu;
-    __syncthreads();
-    if (lane == 0) {
-        const float *om = omega + (int64_t)j * n;
-        double acc = 0.0;
-        for (int t = 0; t < n; ++t) acc = acc + (double)om[t] * s[t];
-        vals[c] = fabs(acc);
-    }
-}
-
-// Small candidate sets: bitonic sort in LDS (padded with +inf) by one
-// workgroup, then the entry of the remaining rank.
-constexpr int kDirect = 8192;
-__global__ __launch_bounds__(1024) void k_tau_select_direct(const double *vals, int64_t ncand,
-                                                             double frac, TauState *st) {
-    __shared__ double v[kDirect];
-    int n2 = 1;
-    while (n2 < ncand) n2 <<= 1;
-    for (int i = threadIdx.x; i < n2; i += 1024) v[i] = i < ncand ? vals[i] : INFINITY;
-    __syncthreads();
-    for (int size = 2; size <= n2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < n2; i += 1024) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const bool up = (i & size) == 0;
-                    const double a = v[i], b = v[j];
-                    if ((a > b) == up) {
-                        v[i] = b;
-                        v[j] = a;
-                    }
-                }
-            }
-            __syncthreads();
+    for (int64_t c = blockIdx.x; c < ncand; c += gridDim.x) {
+        const int64_t e = cand[c];
+        const int64_t pix = e / k;
+        const int j = (int)(e - pix * k);
+        const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
+        for (int t = lane; t < n; t += 64) {
+            const int u = t / p, v = t - u * p;
+            const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + v - h, W);
+            s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
         }
-    }
-    if (threadIdx.x == 0) {
-        const unsigned long long r0 = st->rank0, below = st->below;
-        if (r0 >= below && r0 - below < (unsigned long long)ncand) {
-            const double x = v[r0 - below];
-            st->median = x;
-            st->tau = frac * x;
-        } else {
-            st->median = __longlong_as_double(0x7FF8000000000000ll);
-            st->tau = st->median;
+        __syncthreads();
+        if (lane == 0) {
+            double sum = 0.0;
+            for (int t = 0; t < n; ++t) sum = sum + s[t];
+            sh_mu = sum / (double)n;
         }
+        __syncthreads();
+        const double mu = sh_mu;
+        for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
+        __syncthreads();
+        if (lane == 0) {
+            double nu2 = 0.0;
+            for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
+            sh_nu2 = nu2;
+        }
+        __syncthreads();
+        const double nu2 = sh_nu2;
+        const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
+        for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / nu;
+        __syncthreads();
+        if (lane == 0) {
+            const float *om = omega + (int64_t)j * n;
+            double acc = 0.0;
+            for (int t = 0; t < n; ++t) acc = acc + (double)om[t] * s[t];
+            vals[c] = fabs(acc);
+        }
+        __syncthreads();  // s is rewritten by the next candidate
     }
 }
 
 // Single-workgroup radix select of rank (rank0 - below) among the FP64
 // candidate values (non-negative doubles order like their bit patterns).
-__global__ __launch_bounds__(1024) void k_tau_select64(const double *vals, int64_t ncand,
-                                                        double frac, TauState *st) {
+// The digits above the highest bit in which the smallest and largest key
+// differ are common to all candidates and skipped; the remaining digits are
+// selected 8 bits at a time with an LDS histogram and a one-wave scan.
+__global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t cap, double frac,
+                                                      TauState *st) {
     __shared__ unsigned int hist[256];
-    __shared__ unsigned long long s_prefix, s_rank;
+    __shared__ unsigned long long s_min, s_max, s_prefix, s_rank;
     __shared__ int s_ok;
-    if (threadIdx.x == 0) {
-        s_prefix = 0;
-        const unsigned long long r0 = st->rank0, below = st->below;
-        s_ok = (r0 >= below) && (r0 - below < (unsigned long long)ncand);
-        s_rank = s_ok ? r0 - below : 0;
-    }
-    __syncthreads();
-    if (!s_ok) {
-        if (threadIdx.x == 0) {
-            st->median = __longlong_as_double(0x7FF8000000000000ll);  // NaN: bound violated
+    const int tid = threadIdx.x;
+    const unsigned long long nc = st->ncand;
+    const unsigned long long r0 = st->rank0, below = st->below;
+    const bool ok = nc <= (unsigned long long)cap && r0 >= below && r0 - below < nc;
+    if (!ok) {
+        if (tid == 0) {
+            st->median = __longlong_as_double(0x7FF8000000000000ll);  // NaN: retry or bound violated
             st->tau = st->median;
         }
         return;
     }
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = 56 - 8 * pass;
-        const unsigned long long pmask = pass == 0 ? 0ull : (~0ull << (64 - 8 * pass));
-        for (int i = threadIdx.x; i < 256; i += 1024) hist[i] = 0;
+    const int64_t ncand = (int64_t)nc;
+    if (tid == 0) {
+        s_min = ~0ull;
+        s_max = 0ull;
+        s_rank = r0 - below;
+    }
+    __syncthreads();
+    unsigned long long mn = ~0ull, mx = 0ull;
+    for (int64_t c = tid; c < ncand; c += 1024) {
+        const unsigned long long key = (unsigned long long)__double_as_longlong(vals[c]);
+        mn = key < mn ? key : mn;
+        mx = key > mx ? key : mx;
+    }
+    atomicMin(&s_min, mn);
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    const unsigned long long diff = s_min ^ s_max;
+    if (diff == 0ull) {
+        if (tid == 0) {
+            const double med = __longlong_as_double((long long)s_min);
+            st->median = med;
+            st->tau = frac * med;
+        }
+        return;
+    }
+    const int top = 63 - __clzll((long long)diff);
+    const int start = (top / 8) * 8;
+    if (tid == 0) s_prefix = start + 8 >= 64 ? 0ull : (s_min & (~0ull << (start + 8)));
+    __syncthreads();
+    for (int shift = start; shift >= 0; shift -= 8) {
+        if (tid < 256) hist[tid] = 0;
         __syncthreads();
-        const unsigned long long pval = s_prefix;
-        for (int64_t c = threadIdx.x; c < ncand; c += 1024) {
+        const unsigned long long hmask = shift + 8 >= 64 ? 0ull : (~0ull << (shift + 8));
+        const unsigned long long pv = s_prefix;
+        for (int64_t c = tid; c < ncand; c += 1024) {
             const unsigned long long key = (unsigned long long)__double_as_longlong(vals[c]);
-            if ((key & pmask) == pval) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
+            if ((key & hmask) == pv) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long r = s_rank;
-            for (int b = 0; b < 256; ++b) {
-                if (r < hist[b]) {
-                    s_prefix |= (unsigned long long)b << shift;
-                    break;
-                }
-                r -= hist[b];
+        if (tid < 64) {
+            // lane l owns bins 4l..4l+3; inclusive scan of the lane totals
+            unsigned int b[4], tot = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                b[q] = hist[4 * tid + q];
+                tot += b[q];
             }
-            s_rank = r;
+            unsigned int incl = tot;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const unsigned int y = __shfl_up(incl, off);
+                if (tid >= off) incl += y;
+            }
+            const unsigned long long r = s_rank;
+            const unsigned int excl = incl - tot;
+            if (r >= excl && r < incl) {
+                unsigned long long rr = r - excl;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (rr < b[q]) {
+                        s_prefix = pv | ((unsigned long long)(4 * tid + q) << shift);
+                        s_rank = rr;
+                        break;
+                    }
+                    rr -= b[q];
+                }
+            }
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         const double med = __longlong_as_double((long long)s_prefix);
         st->median = med;
         st->tau = frac * med;
@@ -396,16 +422,14 @@ __global__ __launch_bounds__(1024) void k_tau_select64(const double *vals, int64
 
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
-                      int64_t ncand, double *vals, double frac, TauState *st) {
+                      int64_t cap, double *vals, double frac, TauState *st) {
     (void)n;
-    if (ncand > 0)
-        hipLaunchKernelGGL(k_tau_recompute, dim3((unsigned)ncand), dim3(64), 0, lc.stream, rgb, H, W,
-                           p, wmask, omega, k, cand, ncand, vals);
-    if (ncand <= kDirect)
-        hipLaunchKernelGGL(k_tau_select_direct, dim3(1), dim3(1024), 0, lc.stream, vals, ncand, frac,
-                           st);
-    else
-        hipLaunchKernelGGL(k_tau_select64, dim3(1), dim3(1024), 0, lc.stream, vals, ncand, frac, st);
+    int64_t blocks = (int64_t)lc.num_cu * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_tau_recompute, dim3((unsigned)blocks), dim3(64), 0, lc.stream, rgb, H, W, p, wmask, omega,
+                       k, cand, st, cap, vals);
+    hipLaunchKernelGGL(k_tau_select, dim3(1), dim3(1024), 0, lc.stream, vals, cap, frac, st);
     return hipGetLastError();
 }
 
