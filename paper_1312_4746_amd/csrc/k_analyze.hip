@@ -5,22 +5,27 @@
 // and gain normalisation) and Sec. 3.1 (gray patch s_x centred at x, Gaussian
 // mask applied before normalisation).
 //
-// One workgroup (4 waves) owns a row segment of kTilePx = 64 pixels.  The
-// FP64 gray values of the segment and its halo are staged in LDS, every
-// pixel's patch s is formed in FP64 in LDS (this is the exact patch; its sums
-// run sequentially with no FMA contraction so that the FP64 recompute below is
-// reproducible bit for bit), and the contraction runs on MFMA with A = patches
-// (rows = pixels, from LDS) and B = O^T (columns = operator rows, read from
-// L2).  Each wave owns every fourth 16-row block of O and reuses each B
-// fragment for the four 16-pixel blocks of the tile.
+// One workgroup owns a row segment of TP pixels (128 for p <= 9, else 64).
+// 1. The FP64 gray values of the segment and its halo are staged in LDS.
+// 2. One thread per pixel computes the exact statistics of its masked patch
+//    q_t = w_t g_t: mu = (sum_t q_t)/n and nu2 = sum_t (q_t - mu)^2, each sum
+//    sequential in t with no FMA contraction (the oracle's operations).
+// 3. The normalised patch s_t = (q_t - mu)/sqrt(nu2) is written to LDS in
+//    FP32 (via the FP64 reciprocal: within one FP64 ulp of the exact quotient,
+//    far inside the FP32 rounding the error bound already counts).
+// 4. a = O s on MFMA with A = patches (rows = pixels, LDS) and B = O^T
+//    (columns = operator rows, from L2); each wave owns every fourth 16-pixel
+//    block and walks all 16-row blocks of O.
 //
-// Output layout of the 16x16 MFMA tile: lane l, accumulator r holds
-// pixel 4*(l/16) + r of the block and operator row l%16 of the j-block, so one
-// wave ballot over a predicate on accumulator r yields four 16-bit co-support
+// Output layout of the 16x16 MFMA tile: lane l, accumulator r holds pixel
+// 4*(l/16) + r of the block and operator row l%16 of the j-block, so one wave
+// ballot over a predicate on accumulator r yields four 16-bit co-support
 // pieces (one per pixel), which land directly in the packed mask words.
 //
 // Entries whose rounded |a| lies within the per-row margin of tau are
-// recomputed in FP64 from the exact patch in LDS and decided exactly.
+// recomputed in FP64 from the exact patch (rebuilt on the fly from the LDS
+// gray values and the exact statistics, in the oracle's operation order) and
+// decided exactly.
 #pragma clang fp contract(off)
 
 #include "cs_internal.h"
@@ -32,147 +37,188 @@ namespace cs {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 
+template <int P>
+struct AnalyzeTile {
+    static constexpr int h = (P - 1) / 2, n = P * P, np = (n + 15) / 16 * 16, ss = np + 1;
+    static constexpr int np4 = (n + 3) / 4 * 4;    // K extent of the FP32 MFMA steps
+    static constexpr int TP = P <= 9 ? 128 : 64;  // pixels per workgroup
+    static constexpr int hw = TP + 2 * h;
+};
+
+// Exact FP64 a_j = sum_t O_jt s_t of pixel il of the tile, the patch rebuilt
+// from the LDS gray halo and the exact statistics: q_t = w_t g_t,
+// s_t = (q_t - mu) / sqrt(nu2) (0 when nu2 = 0), summed in t order.
+template <int P>
+__device__ __noinline__ double exact_dot(const float *om, const double *gh, const double *wmask, int il,
+                                         double mu, double nu2) {
+#pragma clang fp contract(off)
+    using T = AnalyzeTile<P>;
+    const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
+    double acc = 0.0;
+    for (int t = 0; t < T::n; ++t) {
+        const int u = t / P, v = t - u * P;
+        const double q = wmask[t] * gh[u * T::hw + il + v];
+        const double st = nu2 == 0.0 ? 0.0 : (q - mu) / nu;
+        acc = acc + (double)om[t] * st;
+    }
+    return acc;
+}
+
 template <int PREC, int P>
 __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
+    using T = AnalyzeTile<P>;
+    constexpr int h = T::h, n = T::n, np = T::np, ss = T::ss, TP = T::TP, hw = T::hw;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int h = (P - 1) / 2;
-    constexpr int n = P * P, np = (n + 15) / 16 * 16, ss = np + 1;
-    const int hw = kTilePx + 2 * h;
+    double *gh = reinterpret_cast<double *>(smem);   // (2h+1) x hw gray halo
+    double *st_mu = gh + (2 * h + 1) * hw;            // TP exact means
+    double *st_nu2 = st_mu + TP;                       // TP exact squared norms
+    double *st_rinv = st_nu2 + TP;                     // TP values 1/sqrt(nu2) (0 if nu2 = 0)
+    float *s = reinterpret_cast<float *>(st_rinv + TP); // TP x ss FP32 patches
+    uint16_t *mk = reinterpret_cast<uint16_t *>(s + TP * ss);  // TP x 4*W64 pieces
     const int W64 = (a.k + 63) / 64;
-    double *gh = reinterpret_cast<double *>(smem);  // (2h+1) x hw gray halo
-    double *s = gh + (2 * h + 1) * hw;               // kTilePx x ss patches
-    double *nu = s + kTilePx * ss;                   // kTilePx norms
-    uint16_t *mk = reinterpret_cast<uint16_t *>(nu + kTilePx);  // kTilePx x 4*W64 pieces
 
-    const int row = blockIdx.y, c0 = blockIdx.x * kTilePx;
+    const int row = blockIdx.y, c0 = blockIdx.x * TP;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t N = (int64_t)a.H * a.W;
-    const int valid_px = min(kTilePx, a.W - c0);
+    const int valid_px = min(TP, a.W - c0);
 
     // 1. FP64 gray halo of the segment.
     const int ncols = valid_px + 2 * h;
     for (int idx = tid; idx < (2 * h + 1) * hw; idx += 256) {
-        int rr = idx / hw, cc = idx - rr * hw;
+        const int rr = idx / hw, cc = idx - rr * hw;
         double g = 0.0;
         if (cc < ncols) {
-            int gr = reflect_idx(row - h + rr, a.H), gc = reflect_idx(c0 - h + cc, a.W);
+            const int gr = reflect_idx(row - h + rr, a.H), gc = reflect_idx(c0 - h + cc, a.W);
             g = gray64(a.rgb, N, (int64_t)gr * a.W + gc);
         }
         gh[idx] = g;
     }
     if (a.masks)
-        for (int idx = tid; idx < kTilePx * 4 * W64; idx += 256) mk[idx] = 0;
+        for (int idx = tid; idx < TP * 4 * W64; idx += 256) mk[idx] = 0;
     __syncthreads();
 
-    // 2. masked patch q_t = w_t g_t (zero for pixels past the row end and t >= n).
-    for (int idx = tid; idx < kTilePx * np; idx += 256) {
-        int i = idx / np, t = idx - i * np;
-        double q = 0.0;
-        if (i < valid_px && t < n) {
-            int u = t / P, v = t - u * P;
-            q = a.wmask[t] * gh[u * hw + i + v];
-        }
-        s[i * ss + t] = q;
-    }
-    __syncthreads();
-
-    // 3. zero mean and norm, sequential in t (one thread per pixel).
-    if (tid < kTilePx) {
+    // 2. exact statistics, one thread per pixel, sequential in t.
+    for (int i = tid; i < TP; i += 256) {
 #pragma clang fp contract(off)
-        double *si = s + tid * ss;
         double sum = 0.0;
-        for (int t = 0; t < n; ++t) sum = sum + si[t];
-        double mu = sum / (double)n;
-        for (int t = 0; t < n; ++t) si[t] = si[t] - mu;
+        for (int t = 0; t < n; ++t) {
+            const int u = t / P, v = t - u * P;
+            sum = sum + a.wmask[t] * gh[u * hw + i + v];
+        }
+        const double mu = sum / (double)n;
         double nu2 = 0.0;
-        for (int t = 0; t < n; ++t) nu2 = nu2 + si[t] * si[t];
-        nu[tid] = (nu2 == 0.0) ? 0.0 : sqrt(nu2);
+        for (int t = 0; t < n; ++t) {
+            const int u = t / P, v = t - u * P;
+            const double z = a.wmask[t] * gh[u * hw + i + v] - mu;
+            nu2 = nu2 + z * z;
+        }
+        st_mu[i] = mu;
+        st_nu2[i] = nu2;
+        st_rinv[i] = nu2 == 0.0 ? 0.0 : 1.0 / sqrt(nu2);
     }
     __syncthreads();
 
-    // 4. unit norm (a zero-norm patch becomes s = 0).
-    for (int idx = tid; idx < kTilePx * n; idx += 256) {
-        int i = idx / n, t = idx - i * n;
-        double v = nu[i];
-        s[i * ss + t] = (v == 0.0) ? 0.0 : s[i * ss + t] / v;
+    // 3. FP32 normalised patches (zero for pixels past the row end and t >= n).
+    for (int idx = tid; idx < TP * np; idx += 256) {
+        const int i = idx / np, t = idx - i * np;
+        float sv = 0.0f;
+        if (i < valid_px && t < n) {
+            const int u = t / P, v = t - u * P;
+            sv = (float)((a.wmask[t] * gh[u * hw + i + v] - st_mu[i]) * st_rinv[i]);
+        }
+        s[i * ss + t] = sv;
     }
     __syncthreads();
 
-    // 5. a = O s on MFMA, one 16-row block of O per pass, four pixel blocks.
+    // 4. a = O s on MFMA: wave w owns pixel blocks rb = w, w+4, ...; all j-blocks.
     const int nblk_j = (a.k + 15) / 16;
     unsigned long long nrecomp = 0;
-    for (int jb = wave; jb < nblk_j; jb += 4) {
-        f32x4 acc[4];
-        for (int rb = 0; rb < 4; ++rb) acc[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // B fragments of j-block jb (FP32 path), loaded one block ahead
+    float bnext[T::np4 / 4];
+    auto load_b = [&](int jb, float (&dst)[T::np4 / 4]) {
+        const int jj = jb * 16 + (lane & 15);
+        const bool ok = jb < nblk_j && jj < a.k;
+        const float *o = a.omega + (int64_t)(ok ? jj : 0) * n;
+#pragma unroll
+        for (int kb = 0; kb < T::np4 / 4; ++kb) {
+            const int t = kb * 4 + (lane >> 4);
+            dst[kb] = (ok && t < n) ? o[t] : 0.f;
+        }
+    };
+    if (PREC == CS_FP32) load_b(0, bnext);
+    for (int jb = 0; jb < nblk_j; ++jb) {
         const int j = jb * 16 + (lane & 15);
         const bool jv = j < a.k;
         const float *om = a.omega + (int64_t)(jv ? j : 0) * n;
+        float bf[T::np4 / 4];
+        s16x4 bb[np / 16];
         if (PREC == CS_FP32) {
-            // B fragments of the whole K range first (independent loads in flight).
-            float bf[np / 4];
 #pragma unroll
-            for (int kb = 0; kb < np / 4; ++kb) {
-                const int t = kb * 4 + (lane >> 4);
-                bf[kb] = (jv && t < n) ? om[t] : 0.f;
-            }
-#pragma unroll
-            for (int kb = 0; kb < np / 4; ++kb) {
-                const int t = kb * 4 + (lane >> 4);
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    const float av = (float)s[(rb * 16 + (lane & 15)) * ss + t];
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[kb], acc[rb], 0, 0, 0);
-                }
-            }
+            for (int kb = 0; kb < T::np4 / 4; ++kb) bf[kb] = bnext[kb];
+            load_b(jb + 1, bnext);
         } else {
-            s16x4 bf[np / 16];
 #pragma unroll
             for (int kb = 0; kb < np / 16; ++kb) {
                 const int t0 = kb * 16 + 4 * (lane >> 4);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    bf[kb][q] = bf16_rne((jv && t0 + q < n) ? om[t0 + q] : 0.f);
-            }
-#pragma unroll
-            for (int kb = 0; kb < np / 16; ++kb) {
-                const int t0 = kb * 16 + 4 * (lane >> 4);
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    const double *sp = s + (rb * 16 + (lane & 15)) * ss + t0;
-                    s16x4 av;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) av[q] = bf16_rne((float)sp[q]);
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bf[kb], acc[rb], 0, 0, 0);
-                }
+                for (int q = 0; q < 4; ++q) bb[kb][q] = bf16_rne((jv && t0 + q < n) ? om[t0 + q] : 0.f);
             }
         }
-
-        // Epilogue: store a and/or decide the co-support bits.
         const float tin = (a.masks && jv) ? a.t_in[j] : 0.f;
         const float tout = (a.masks && jv) ? a.t_out[j] : 0.f;
+        // two 16-pixel blocks per pass (rb and rb + 4): independent MFMA chains
+        for (int rb0 = wave; rb0 < TP / 16; rb0 += 8) {
+            if (rb0 * 16 >= valid_px) break;
+            const int rb1 = rb0 + 4;
+            const bool two = rb1 < TP / 16 && rb1 * 16 < valid_px;
+            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            const float *srow0 = s + (rb0 * 16 + (lane & 15)) * ss;
+            const float *srow1 = s + ((two ? rb1 : rb0) * 16 + (lane & 15)) * ss;
+            if (PREC == CS_FP32) {
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
+                for (int kb = 0; kb < T::np4 / 4; ++kb) {
+                    const int t = kb * 4 + (lane >> 4);
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(srow0[t], bf[kb], acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(srow1[t], bf[kb], acc[1], 0, 0, 0);
+                }
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int il = rb * 16 + 4 * (lane >> 4) + r;
-                const bool pv = il < valid_px;
-                const float v = acc[rb][r];
-                const int64_t pix = (int64_t)row * a.W + c0 + il;
-                if (a.alpha && pv && jv) a.alpha[pix * a.k + j] = v;
-                if (a.masks) {
-                    const float av = fabsf(v);
-                    bool in = av <= tin;
-                    const bool out = av > tout;
-                    const bool near = !in && !out && pv && jv;
-                    if (near) {
-                        const double ex = dot64(om, s + il * ss, n);
-                        in = fabs(ex) <= a.tau;
+                for (int kb = 0; kb < np / 16; ++kb) {
+                    const int t0 = kb * 16 + 4 * (lane >> 4);
+                    s16x4 av0, av1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        av0[q] = bf16_rne(srow0[t0 + q]);
+                        av1[q] = bf16_rne(srow1[t0 + q]);
                     }
-                    nrecomp += (unsigned long long)__popcll(__ballot(near));
-                    const unsigned long long bits = __ballot(in && pv && jv);
-                    if (lane < 4)
-                        mk[(rb * 16 + 4 * lane + r) * (4 * W64) + jb] =
-                            (uint16_t)((bits >> (16 * lane)) & 0xFFFFull);
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av0, bb[kb], acc[0], 0, 0, 0);
+                    acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av1, bb[kb], acc[1], 0, 0, 0);
+                }
+            }
+            // Epilogue: store a and/or decide the co-support bits.
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                if (tt == 1 && !two) break;
+                const int rb = tt == 0 ? rb0 : rb1;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int il = rb * 16 + 4 * (lane >> 4) + r;
+                    const bool pv = il < valid_px;
+                    const float v = acc[tt][r];
+                    const int64_t pix = (int64_t)row * a.W + c0 + il;
+                    if (a.alpha && pv && jv) a.alpha[pix * a.k + j] = v;
+                    if (a.masks) {
+                        const float av = fabsf(v);
+                        bool in = av <= tin;
+                        const bool out = av > tout;
+                        const bool near = !in && !out && pv && jv;
+                        if (near) in = fabs(exact_dot<P>(om, gh, a.wmask, il, st_mu[il], st_nu2[il])) <= a.tau;
+                        nrecomp += (unsigned long long)__popcll(__ballot(near));
+                        const unsigned long long bits = __ballot(in && pv && jv);
+                        if (lane < 4)
+                            mk[(rb * 16 + 4 * lane + r) * (4 * W64) + jb] =
+                                (uint16_t)((bits >> (16 * lane)) & 0xFFFFull);
+                    }
                 }
             }
         }
@@ -182,7 +228,7 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
         __syncthreads();
         const uint64_t *mk64 = reinterpret_cast<const uint64_t *>(mk);
         for (int idx = tid; idx < valid_px * W64; idx += 256) {
-            int i = idx / W64, w = idx - i * W64;
+            const int i = idx / W64, w = idx - i * W64;
             a.masks[((int64_t)row * a.W + c0 + i) * W64 + w] = mk64[i * W64 + w];
         }
         if (a.recomputed && lane == 0 && nrecomp) atomicAdd(a.recomputed, nrecomp);
@@ -191,13 +237,11 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
 
 template <int PREC, int P>
 static hipError_t launch_analyze_p(const LaunchCtx &lc, const AnalyzeArgs &a) {
-    constexpr int h = (P - 1) / 2, n = P * P, np = (n + 15) / 16 * 16;
-    const int hw = kTilePx + 2 * h;
+    using T = AnalyzeTile<P>;
     const int W64 = (a.k + 63) / 64;
-    const size_t lds = sizeof(double) * ((size_t)(2 * h + 1) * hw + (size_t)kTilePx * (np + 1) +
-                                         kTilePx) +
-                       sizeof(uint16_t) * (size_t)kTilePx * 4 * W64;
-    dim3 grid((a.W + kTilePx - 1) / kTilePx, a.H);
+    const size_t lds = sizeof(double) * ((size_t)(2 * T::h + 1) * T::hw + 3 * (size_t)T::TP) +
+                       sizeof(float) * (size_t)T::TP * T::ss + sizeof(uint16_t) * (size_t)T::TP * 4 * W64;
+    dim3 grid((a.W + T::TP - 1) / T::TP, a.H);
     hipError_t e = hipFuncSetAttribute((const void *)k_analyze<PREC, P>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
