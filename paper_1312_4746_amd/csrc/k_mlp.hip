@@ -2,8 +2,9 @@
 // (GELU, 128 units) from a pixel's colour, normalised position and analysed
 // vector (Sec. 2 a = O s of Sec. 3.1 patches) to its per-label
 // log-likelihoods (the Sec. 3.1/3.2 data term), trained by Adam on exact
-// targets.  Matrix products run on BF16 MFMA (v_mfma_f32_16x16x16_bf16) with
-// FP32 accumulation; biases, GELU, the loss and Adam are FP32.
+// targets.  Matrix products run on BF16 MFMA (v_mfma_f32_16x16x16_bf16 for
+// training, 16x16x32 for inference) with FP32 accumulation; biases, GELU, the
+// loss and Adam are FP32.
 //
 // Layout trick: every layer computes the TRANSPOSED product, units x rows.
 // With A = weights (rows = units) and B = activations^T (columns = 16 batch
@@ -30,9 +31,28 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr float kClipNats = 20.0f;
 constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf by the rational approximation 7.1.26 of Abramowitz and Stegun
+// (Handbook of Mathematical Functions), |error| <= 1.5e-7: a polynomial in
+// t = 1 / (1 + p |x|) times exp(-x^2), branch-free.  GELU(z) = z Phi(z) with
+// Phi(z) = (1 + erf(z / sqrt 2)) / 2.
+__device__ __forceinline__ float erf_as(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float poly = fmaf(1.061405429f, t, -1.453152027f);
+    poly = fmaf(poly, t, 1.421413741f);
+    poly = fmaf(poly, t, -0.284496736f);
+    poly = fmaf(poly, t, 0.254829592f);
+    poly *= t;
+    const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+    const float r = fmaf(-poly, e, 1.0f);
+    return copysignf(r, x);
+}
+__device__ __forceinline__ float gelu(float z) { return z * fmaf(0.5f, erf_as(z * 0.70710678118654752f), 0.5f); }
+// FP32 -> BF16 bit pattern, round to nearest even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ short to_bf16(float v) { return __builtin_bit_cast(short, (__bf16)v); }
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+    return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
+           z * __builtin_amdgcn_exp2f(-0.5f * 1.4426950408889634f * z * z) * 0.39894228040143268f;
 }
 
 __device__ __forceinline__ s16x4 ld4(const short *p) { return *reinterpret_cast<const s16x4 *>(p); }
@@ -61,7 +81,7 @@ __device__ __forceinline__ void mlp_tile_forward(const s16x4 (&xb)[kMlpMaxIn / 1
         for (int r = 0; r < 4; ++r) {
             const float z = acc[r] + b1[16 * hb + 4 * g + r];
             if (KEEP) z1[hb][r] = z;
-            h1b[hb][r] = bf16_rne(gelu(z));
+            h1b[hb][r] = to_bf16(gelu(z));
         }
     }
 #pragma unroll
@@ -74,7 +94,7 @@ __device__ __forceinline__ void mlp_tile_forward(const s16x4 (&xb)[kMlpMaxIn / 1
         for (int r = 0; r < 4; ++r) {
             const float z = acc[r] + b2[16 * hb + 4 * g + r];
             if (KEEP) z2[hb][r] = z;
-            h2b[hb][r] = bf16_rne(gelu(z));
+            h2b[hb][r] = to_bf16(gelu(z));
         }
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -105,7 +125,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int f = 16 * ks + 4 * g + q;
-            xb[ks][q] = bf16_rne(f < a.in ? a.x[row * a.in + f] : 0.0f);
+            xb[ks][q] = to_bf16(f < a.in ? a.x[row * a.in + f] : 0.0f);
         }
     float z1[8][4], z2[8][4];
     s16x4 h2b[8];
@@ -134,7 +154,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
         const float d = o < a.out ? y[r] - t : 0.0f;
         sq += d * d;
         dy[r] = scale * d;
-        dyb[r] = bf16_rne(dy[r]);
+        dyb[r] = to_bf16(dy[r]);
     }
     // dH2^T = W3^T dY^T (K = 16 outputs), dZ2 = dH2 * GELU'(z2)
     s16x4 dz2b[8];
@@ -145,7 +165,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             dz2[hb][r] = acc[r] * gelu_grad(z2[hb][r]);
-            dz2b[hb][r] = bf16_rne(dz2[hb][r]);
+            dz2b[hb][r] = to_bf16(dz2[hb][r]);
         }
     }
     // dH1^T = W2^T dZ2^T, dZ1 = dH1 * GELU'(z1)
@@ -171,10 +191,10 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t u = (int64_t)(16 * hb + 4 * g + r) * B + rb;
-            a.H1t[u] = bf16_rne(gelu(z1[hb][r]));
+            a.H1t[u] = to_bf16(gelu(z1[hb][r]));
             a.H2t[u] = h2b[hb][r];
             a.DZ2t[u] = dz2b[hb][r];
-            a.DZ1t[u] = bf16_rne(dz1[hb][r]);
+            a.DZ1t[u] = to_bf16(dz1[hb][r]);
         }
 #pragma unroll
     for (int r = 0; r < 4; ++r) a.DYt[(int64_t)(4 * g + r) * B + rb] = dyb[r];
@@ -272,7 +292,7 @@ __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a) {
     const float w = a.params[p] - a.lr * mhat / (sqrtf(vhat) + kAdamEps);
     a.params[p] = w;
     // BF16 working copies
-    const short wb = bf16_rne(w);
+    const short wb = to_bf16(w);
     if (p < a.off_b1) {
         const int h = (int)(p / a.in), i = (int)(p % a.in);
         a.W1b[h * a.in_pad + i] = wb;
@@ -291,7 +311,7 @@ __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a) {
 __global__ __launch_bounds__(256) void k_mlp_convert(MlpAdamArgs a) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= a.P) return;
-    const short wb = bf16_rne(a.params[p]);
+    const short wb = to_bf16(a.params[p]);
     if (p < a.off_b1) {
         const int h = (int)(p / a.in), i = (int)(p % a.in);
         a.W1b[h * a.in_pad + i] = wb;
@@ -307,64 +327,166 @@ __global__ __launch_bounds__(256) void k_mlp_convert(MlpAdamArgs a) {
 }
 
 // ---- inference: persistent workgroups, BF16 weights staged once in LDS ----
-// LDS row strides carry 4 extra elements so that the 16 rows of an A
-// fragment fall into different banks.
-constexpr int kLds1 = kMlpMaxIn + 4, kLds2 = kMlpHid + 4;
-__global__ __launch_bounds__(256) void k_mlp_infer(MlpInferArgs a) {
-    __shared__ __align__(16) short sW1[kMlpHid * kLds1];
-    __shared__ __align__(16) short sW2[kMlpHid * kLds2];
-    __shared__ __align__(16) short sW3[kMlpOutPad * kLds2];
+// Uses v_mfma_f32_16x16x32_bf16 (K = 32 per instruction).  A layer's result
+// holds units 4g..4g+3 of each 16-unit block in lane (g, j); the K = 32 step
+// over blocks 2s and 2s+1 takes the B fragment [block 2s units 4g..4g+3,
+// block 2s+1 units 4g..4g+3] and the matching weight columns in the same
+// (permuted) order, so no data moves between lanes.  Each wave stages the
+// inputs of its 16 pixels in LDS (the analysed vectors of 16 consecutive
+// pixels are one contiguous block, read with coalesced loads).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+constexpr int kInfWaves = 8;
+constexpr int kInfIn = 128;             // input features padded to whole K = 32 steps
+constexpr int kInfLd = kMlpHid + 8;     // LDS row stride (elements) of weights and staged inputs
+constexpr int kInfLoads = (16 * (kInfIn - 5) + 255) / 256;  // 16-byte loads per lane for 16 rows of a
+
+__device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+__device__ __forceinline__ s16x8 cat4(s16x4 lo, s16x4 hi) {
+    return s16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+__global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(MlpInferArgs a) {
+    __shared__ __align__(16) short sW1[kMlpHid * kInfLd];
+    __shared__ __align__(16) short sW2[kMlpHid * kInfLd];
+    __shared__ __align__(16) short sW3[kMlpOutPad * kInfLd];
+    __shared__ __align__(16) short sX[kInfWaves][16 * kInfLd];
     __shared__ float sb[2 * kMlpHid + kMlpOutPad];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
-    for (int e = tid; e < kMlpHid * a.in_pad; e += 256) {
-        const int h = e / a.in_pad, i = e - h * a.in_pad;
-        sW1[h * kLds1 + i] = a.W1b[e];
+    for (int e = tid; e < kMlpHid * kInfIn; e += 64 * kInfWaves) {
+        const int h = e / kInfIn, i = e - h * kInfIn;
+        sW1[h * kInfLd + i] = i < a.in_pad ? a.W1b[h * a.in_pad + i] : (short)0;
     }
-    for (int e = tid; e < kMlpHid * kMlpHid; e += 256) sW2[(e / kMlpHid) * kLds2 + e % kMlpHid] = a.W2b[e];
-    for (int e = tid; e < kMlpOutPad * kMlpHid; e += 256) sW3[(e / kMlpHid) * kLds2 + e % kMlpHid] = a.W3b[e];
-    for (int e = tid; e < 2 * kMlpHid + kMlpOutPad; e += 256)
+    for (int e = tid; e < kMlpHid * kMlpHid; e += 64 * kInfWaves) sW2[(e / kMlpHid) * kInfLd + e % kMlpHid] = a.W2b[e];
+    for (int e = tid; e < kMlpOutPad * kMlpHid; e += 64 * kInfWaves) sW3[(e / kMlpHid) * kInfLd + e % kMlpHid] = a.W3b[e];
+    for (int e = tid; e < 2 * kMlpHid + kMlpOutPad; e += 64 * kInfWaves)
         sb[e] = e < kMlpHid ? a.b1[e] : e < 2 * kMlpHid ? a.b2[e - kMlpHid] : (e - 2 * kMlpHid < a.out ? a.b3[e - 2 * kMlpHid] : 0.f);
     __syncthreads();
-    const int nks = a.in_pad / 16;
+    short *X = sX[wave];
+    const int ks1 = (a.in + 31) / 32;
     const int64_t ntiles = (a.n + 15) / 16;
     const int64_t N = (int64_t)a.H * a.W;
     const float sx = a.W > 1 ? 1.0f / (float)(a.W - 1) : 0.0f, sy = a.H > 1 ? 1.0f / (float)(a.H - 1) : 0.0f;
-    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < ntiles; t += (int64_t)gridDim.x * 4) {
-        const int64_t pix = t * 16 + j;
-        const bool pv = pix < a.n;
-        s16x4 xb[kMlpMaxIn / 16];
+    // Inputs of a tile in registers: the analysed vectors (16-byte loads) and
+    // colour / position (lane l < 80: row l / 5, feature l % 5).  The loads of
+    // the next tile are issued before the current tile is computed.
+    float4 vb[kInfLoads];
+    float vc[2];
+    auto fetch = [&](int64_t t) {
+        const int64_t p0 = t * 16;
+        const int np = t < ntiles ? (int)(a.n - p0 < 16 ? a.n - p0 : 16) : 0;
+        if (a.x) return;
+        const float *ab = a.alpha + p0 * a.k;
+        const int nval = np * a.k;
 #pragma unroll
-        for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
+        for (int u = 0; u < kInfLoads; ++u) {
+            const int e0 = 4 * (lane + 64 * u);
+            if (e0 + 3 < nval) {
+                vb[u] = *reinterpret_cast<const float4 *>(ab + e0);
+            } else {
+                vb[u].x = e0 < nval ? ab[e0] : 0.0f;
+                vb[u].y = e0 + 1 < nval ? ab[e0 + 1] : 0.0f;
+                vb[u].z = e0 + 2 < nval ? ab[e0 + 2] : 0.0f;
+                vb[u].w = 0.0f;
+            }
+        }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int f = 16 * ks + 4 * g + q;
-                float v = 0.0f;
-                if (pv && f < a.in) {
-                    if (a.x) {
-                        v = a.x[pix * a.in + f];
-                    } else if (f < 3) {
-                        v = a.rgb[f * N + pix];
-                    } else if (f == 3) {
-                        v = (float)(pix % a.W) * sx;
-                    } else if (f == 4) {
-                        v = (float)(pix / a.W) * sy;
-                    } else {
-                        v = a.alpha[pix * a.k + (f - 5)];
+        for (int u = 0; u < 2; ++u) {
+            const int e = lane + 64 * u, r = e / 5, f = e - r * 5;
+            float v = 0.0f;
+            if (r < np) {
+                const int pix = (int)(p0 + r);  // images hold fewer than 2^31 pixels
+                const int prow = pix / a.W;
+                v = f < 3 ? a.rgb[f * N + pix] : f == 3 ? (float)(pix - prow * a.W) * sx : (float)prow * sy;
+            }
+            vc[u] = v;
+        }
+    };
+    int64_t t = (int64_t)blockIdx.x * kInfWaves + wave;
+    fetch(t);
+    for (; t < ntiles; t += (int64_t)gridDim.x * kInfWaves) {
+        const int64_t p0 = t * 16;
+        const int np = (int)(a.n - p0 < 16 ? a.n - p0 : 16);
+        // stage the 16 input rows (BF16), zero beyond the real features
+        if (a.x) {
+            for (int e = lane; e < 16 * kInfIn; e += 64) {
+                const int r = e / kInfIn, f = e - r * kInfIn;
+                X[r * kInfLd + f] = to_bf16(r < np && f < a.in ? a.x[(p0 + r) * a.in + f] : 0.0f);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kInfLoads; ++u) {
+                const int e0 = 4 * (lane + 64 * u);
+                if (e0 >= 16 * a.k) break;
+                int r = e0 / a.k, f = e0 - r * a.k;
+                const float vv[4] = {vb[u].x, vb[u].y, vb[u].z, vb[u].w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (r < 16) X[r * kInfLd + 5 + f] = to_bf16(vv[c]);
+                    if (++f == a.k) {
+                        f = 0;
+                        ++r;
                     }
                 }
-                xb[ks][q] = bf16_rne(v);
             }
-        float z1[8][4], z2[8][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = lane + 64 * u, r = e / 5, f = e - r * 5;
+                if (r < 16) X[r * kInfLd + f] = to_bf16(vc[u]);
+            }
+            for (int e = lane; e < 16 * (kInfIn - a.in); e += 64) {
+                const int r = e / (kInfIn - a.in), f = a.in + (e - r * (kInfIn - a.in));
+                X[r * kInfLd + f] = 0;
+            }
+            fetch(t + (int64_t)gridDim.x * kInfWaves);  // next tile's loads in flight
+        }
+        // layer 1 (natural K order: features 32 ks + 8 g .. +7)
+        s16x8 xb[kInfIn / 32];
+#pragma unroll
+        for (int ks = 0; ks < kInfIn / 32; ++ks) xb[ks] = *reinterpret_cast<const s16x8 *>(X + j * kInfLd + 32 * ks + 8 * g);
+        s16x4 h1b[8];
+#pragma unroll
+        for (int hb = 0; hb < 8; ++hb) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const short *wr = sW1 + (16 * hb + j) * kInfLd + 8 * g;
+#pragma unroll
+            for (int ks = 0; ks < kInfIn / 32; ++ks)
+                if (ks < ks1) acc = mfma32(*reinterpret_cast<const s16x8 *>(wr + 32 * ks), xb[ks], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h1b[hb][r] = to_bf16(gelu(acc[r] + sb[16 * hb + 4 * g + r]));
+            // every second block: keeps the weight loads of later blocks from
+            // piling up in VGPRs while two blocks' chains still overlap
+            if (hb & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 2 (permuted K order over block pairs)
         s16x4 h2b[8];
-        f32x4 y;
-        mlp_tile_forward<false>(xb, nks, sW1, kLds1, sW2, sW3, kLds2, sb, sb + kMlpHid, sb + 2 * kMlpHid, a.out, g,
-                                j, z1, z2, h2b, y);
-        if (pv)
+#pragma unroll
+        for (int hb = 0; hb < 8; ++hb) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const short *wr = sW2 + (16 * hb + j) * kInfLd + 4 * g;
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+                acc = mfma32(cat4(ld4(wr + 32 * s2), ld4(wr + 32 * s2 + 16)), cat4(h1b[2 * s2], h1b[2 * s2 + 1]), acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h2b[hb][r] = to_bf16(gelu(acc[r] + sb[kMlpHid + 16 * hb + 4 * g + r]));
+            if (hb & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        f32x4 y = {0.f, 0.f, 0.f, 0.f};
+        {
+            const short *wr = sW3 + j * kInfLd + 4 * g;
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+                y = mfma32(cat4(ld4(wr + 32 * s2), ld4(wr + 32 * s2 + 16)), cat4(h2b[2 * s2], h2b[2 * s2 + 1]), y);
+        }
+        if (j < np)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int o = 4 * g + r;
-                if (o < a.out) a.y[pix * a.out + o] = y[r];
+                if (o < a.out) a.y[(p0 + j) * a.out + o] = y[r] + sb[2 * kMlpHid + o];
             }
     }
 }
@@ -433,10 +555,10 @@ hipError_t launch_mlp_convert(const LaunchCtx &lc, const MlpAdamArgs &a) {
 }
 hipError_t launch_mlp_infer(const LaunchCtx &lc, const MlpInferArgs &a) {
     const int64_t ntiles = (a.n + 15) / 16;
-    int64_t blocks = (int64_t)lc.num_cu * 2;
-    if (blocks > (ntiles + 3) / 4) blocks = (ntiles + 3) / 4;
+    int64_t blocks = (int64_t)lc.num_cu;
+    if (blocks > (ntiles + kInfWaves - 1) / kInfWaves) blocks = (ntiles + kInfWaves - 1) / kInfWaves;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(64 * kInfWaves), 0, lc.stream, a);
     return hipGetLastError();
 }
 hipError_t launch_mlp_features(const LaunchCtx &lc, const float *rgb, int H, int W, const float *alpha, int k,
