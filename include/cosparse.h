@@ -121,6 +121,26 @@ int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask
                  double margin, uint64_t *masks, cs_cosupport_stats *stats);
 
 /*
+ * The whole co-support step of Sec. 2 from pixels, with no host round trip:
+ * analysed vectors (as cs_analyze_patches), tau = frac * median{|a|} selected
+ * exactly on the device (as cs_tau_median), and the masks at that tau (as
+ * cs_cosupport with alpha).  Results equal those of the three calls bit for
+ * bit.  The call only enqueues work; tau stays on the device.  The context
+ * reserves 16 bytes of device memory per entry (N*k) for the candidates of
+ * the exact selection, so that their count never needs the host.
+ *   alpha    device out, N*k float32, 16-byte aligned
+ *   masks    device out, N*ceil(k/64) uint64
+ *   tau_dev  device out (one double) or NULL: tau, written in stream order.
+ *            NaN if the exact median fell outside the candidate window (the
+ *            error bound would have been violated; the masks are then 0).
+ * Errors: as cs_analyze_patches, plus CS_ERR_ARG for frac < 0 or NaN, a
+ * non-finite margin, null or misaligned alpha, null masks.
+ */
+int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                        const float *omega, int k, int precision, double frac, double margin, float *alpha,
+                        uint64_t *masks, double *tau_dev);
+
+/*
  * Texture similarity (Sec. 2, TSM definition): out[a*nb + b] = number of
  * indices j < k in exactly one of the co-supports A[a] and B[b] (the Hamming
  * distance of the masks; bits at j >= k are ignored).
@@ -184,6 +204,9 @@ int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats);
  * cs_profile_read synchronises and returns the summed milliseconds and launch
  * count of kernel `name` ("parzen", "analyze", "edt", ...). */
 int cs_profile_enable(cs_ctx *ctx, int on);
+/* Record only the kernel `name` (NULL: every kernel); each recorded launch
+ * adds two events to the stream. */
+int cs_profile_only(cs_ctx *ctx, const char *name);
 int cs_profile_read(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 
 /* ---- Learned surrogate of the data term ----

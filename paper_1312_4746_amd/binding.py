@@ -49,11 +49,13 @@ SIGNATURES = {
     "cs_tau_median": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, ctypes.POINTER(_D)]),
     "cs_cosupport": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, _D, _P,
                           ctypes.POINTER(_CosupportStatsC)]),
+    "cs_cosupport_median": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _D, _D, _P, _P, _P]),
     "cs_texture_similarity": (_I, [_P, _P, _I64, _P, _I64, _I, _P]),
     "cs_label_loglik": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, _I64, _I,
                              ctypes.POINTER(_LoglikParamsC), _P, _I64, _P]),
     "cs_last_loglik_stats": (_I, [_P, ctypes.POINTER(_LoglikStatsC)]),
     "cs_profile_enable": (_I, [_P, _I]),
+    "cs_profile_only": (_I, [_P, ctypes.c_char_p]),
     "cs_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "cs_mlp_param_count": (_I64, [_I, _I, _I]),
     "cs_mlp_init": (_I, [_P, ctypes.POINTER(_P), _I, _I, _I, _P]),
@@ -214,6 +216,33 @@ class Context:
             return out, {"recomputed": int(st.recomputed), "max_margin": float(st.max_margin)}
         return out
 
+    def cosupport_median(self, rgb, p, mask_sigma, omega, frac=0.1, margin=-1.0, precision="fp32",
+                         alpha: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                         tau: Optional[torch.Tensor] = None):
+        """Analysed vectors, tau = frac * median|a| and the masks at that tau
+        in one enqueue-only call.  Returns (alpha (N, k) float32, masks (N,
+        ceil(k/64)) int64, tau (1,) float64 on the device)."""
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(omega, torch.float32, "omega")
+        _, H, W = rgb.shape
+        k = omega.shape[0]
+        if alpha is None:
+            alpha = torch.empty((H * W, k), dtype=torch.float32, device=rgb.device)
+        self._dev(alpha, torch.float32, "alpha")
+        if alpha.numel() != H * W * k:
+            raise ValueError("alpha must hold H*W*k entries")
+        if out is None:
+            out = torch.empty((H * W, (k + 63) // 64), dtype=torch.int64, device=rgb.device)
+        self._dev(out, torch.int64, "masks")
+        if tau is None:
+            tau = torch.empty(1, dtype=torch.float64, device=rgb.device)
+        self._dev(tau, torch.float64, "tau")
+        self._sync_stream()
+        self._check(lib().cs_cosupport_median(self._h, _ptr(rgb), H, W, p, float(mask_sigma), _ptr(omega), k,
+                                              _PREC[precision], float(frac), float(margin), _ptr(alpha),
+                                              _ptr(out), _ptr(tau)))
+        return alpha, out, tau
+
     def texture_similarity(self, A: torch.Tensor, B: torch.Tensor, k: int,
                            out: Optional[torch.Tensor] = None) -> torch.Tensor:
         self._dev(A, torch.int64, "A")
@@ -262,6 +291,9 @@ class Context:
 
     def profile_enable(self, on: bool = True):
         self._check(lib().cs_profile_enable(self._h, int(on)))
+
+    def profile_only(self, name: Optional[str]):
+        self._check(lib().cs_profile_only(self._h, name.encode() if name else None))
 
     def profile_read(self, name: str):
         ms = ctypes.c_double()

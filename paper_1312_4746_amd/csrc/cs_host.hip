@@ -29,14 +29,17 @@ struct cs_ctx {
     // FP32 analysed vectors for the exact median of a BF16 analysis
     float *alpha32 = nullptr;
     size_t alpha32_bytes = 0;
-    // pinned host staging for small device-to-host results
+    // pinned host staging for small device-to-host results, and the event
+    // that marks the label counts of a log-likelihood call as copied
     char *pinned = nullptr;
+    hipEvent_t ev_counts = nullptr;
     // Gaussian patch mask of the last (p, sigma)
     double *wmask = nullptr;
     int wmask_p = 0;
     double wmask_sigma = 0.0;
-    // kernel-event timing
+    // kernel-event timing (of every span, or only of the spans named `only`)
     bool prof = false;
+    std::string only;
     struct Span {
         std::string name;
         hipEvent_t a, b;
@@ -115,7 +118,7 @@ struct Timed {
     const char *name;
     hipEvent_t a = nullptr, b = nullptr;
     Timed(cs_ctx *ctx, const char *nm) : c(ctx), name(nm) {
-        if (!c->prof) return;
+        if (!c->prof || (!c->only.empty() && c->only != nm)) return;
         a = take();
         b = take();
         if (a) hipEventRecord(a, c->stream);
@@ -200,7 +203,9 @@ int cs_create(cs_ctx **out, int device, void *hip_stream) {
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->pinned, kPinnedBytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_counts, hipEventDisableTiming);
     if (e != hipSuccess) {
+        if (ctx->pinned) hipHostFree(ctx->pinned);
         delete ctx;
         return CS_ERR_HIP;
     }
@@ -221,6 +226,7 @@ int cs_destroy(cs_ctx *ctx) {
     if (ctx->alpha32) hipFree(ctx->alpha32);
     if (ctx->wmask) hipFree(ctx->wmask);
     if (ctx->pinned) hipHostFree(ctx->pinned);
+    if (ctx->ev_counts) hipEventDestroy(ctx->ev_counts);
     delete ctx;
     return CS_OK;
 }
@@ -257,37 +263,29 @@ int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, doubl
     return CS_OK;
 }
 
-int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
-                 const float *omega, int k, int precision, const float *alpha, double tau,
-                 double margin, uint64_t *masks, cs_cosupport_stats *stats) {
-    if (!ctx) return CS_ERR_ARG;
-    int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
-    if (rc) return rc;
-    if (!masks) return fail(ctx, CS_ERR_ARG, "masks must be non-null");
-    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ctx, CS_ERR_ARG, "tau must be finite and >= 0");
-    if (std::isnan(margin) || std::isinf(margin)) return fail(ctx, CS_ERR_ARG, "margin must be finite");
-    HIP_TRY(hipSetDevice(ctx->device));
-    if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
-    Carve cv;
-    const size_t o_tin = cv.take(sizeof(float) * k), o_tout = cv.take(sizeof(float) * k);
-    const size_t o_marg = cv.take(sizeof(double) * k), o_max = cv.take(sizeof(double));
-    const size_t o_cnt = cv.take(sizeof(unsigned long long));
-    if ((rc = ensure_ws(ctx, cv.off))) return rc;
-    float *t_in = (float *)(ctx->ws + o_tin), *t_out = (float *)(ctx->ws + o_tout);
-    double *marg = (double *)(ctx->ws + o_marg), *mmax = (double *)(ctx->ws + o_max);
-    unsigned long long *cnt = (unsigned long long *)(ctx->ws + o_cnt);
+}  // extern "C"
+
+namespace {
+
+// Masks of Sec. 2 at tau (or at *tau_dev, read on the device, when non-null):
+// per-row thresholds, then the decision from the stored analysed vectors or
+// from a fused analysis.  Fills *cnt (device) with the recomputed-entry count
+// and *mmax (device) with the largest margin.
+int cosupport_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, const float *omega, int k,
+                    int precision, const float *alpha, double tau, const double *tau_dev, double margin,
+                    uint64_t *masks, unsigned long long *cnt, double *mmax, float *t_in, float *t_out,
+                    double *marg) {
     const LaunchCtx lc = lc_of(ctx);
     const int n = p * p;
     {
         Timed t(ctx, "thresholds");
-        HIP_TRY(launch_thresholds(lc, omega, k, n, tau, margin, margin_coef(precision, n), t_in, t_out,
-                                  marg, mmax));
+        HIP_TRY(launch_thresholds(lc, omega, k, n, tau, tau_dev, margin, margin_coef(precision, n), t_in, t_out,
+                                  marg, mmax, cnt));
     }
-    HIP_TRY(launch_fill_u32(lc, (unsigned int *)cnt, 2, 0u));
     if (alpha) {
         Timed t(ctx, "cosupport");
-        HIP_TRY(launch_mask_alpha(lc, alpha, (int64_t)H * W, k, t_in, t_out, tau, rgb, H, W, p, ctx->wmask,
-                                  omega, masks, cnt));
+        HIP_TRY(launch_mask_alpha(lc, alpha, (int64_t)H * W, k, t_in, t_out, tau, tau_dev, rgb, H, W, p,
+                                  ctx->wmask, omega, masks, cnt));
     } else {
         AnalyzeArgs a{};
         a.rgb = rgb;
@@ -307,6 +305,110 @@ int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask
         Timed t(ctx, "cosupport");
         HIP_TRY(launch_analyze(lc, a, precision));
     }
+    return CS_OK;
+}
+
+// Workspace of cosupport_stage.
+struct CosupportWs {
+    size_t o_tin, o_tout, o_marg, o_max, o_cnt;
+    void carve(Carve &cv, int k) {
+        o_tin = cv.take(sizeof(float) * k);
+        o_tout = cv.take(sizeof(float) * k);
+        o_marg = cv.take(sizeof(double) * k);
+        o_max = cv.take(sizeof(double));
+        o_cnt = cv.take(sizeof(unsigned long long));
+    }
+};
+
+// FP32 analysed vectors that define the exact median for a call at
+// `precision`: alpha itself for FP32; for BF16 an internal FP32 analysis (the
+// BF16 error bound would put a large share of all entries in the candidate
+// window, the FP32 one a tiny share; the selected value is the same).
+int median_source(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma, const float *omega,
+                  int k, int precision, const float *alpha, const float **src) {
+    *src = alpha;
+    if (precision != CS_BF16) return CS_OK;
+    const size_t bytes = sizeof(float) * (size_t)H * W * k;
+    if (bytes > ctx->alpha32_bytes) {
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if (ctx->alpha32) HIP_TRY(hipFree(ctx->alpha32));
+        ctx->alpha32 = nullptr;
+        ctx->alpha32_bytes = 0;
+        if (hipMalloc((void **)&ctx->alpha32, bytes) != hipSuccess) {
+            ctx->alpha32 = nullptr;
+            return fail(ctx, CS_ERR_NOMEM, "FP32 analysis buffer of %zu bytes could not be allocated", bytes);
+        }
+        ctx->alpha32_bytes = bytes;
+    }
+    int rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, CS_FP32, ctx->alpha32);
+    if (rc) return rc;
+    *src = ctx->alpha32;
+    return CS_OK;
+}
+
+// Exact tau = frac * median |a| (Sec. 2) of the FP32 vectors `a32` into st
+// (device), with room for `cap` candidates.  With first = false only the
+// gather and the exact stage run again (a retry with a larger cap).
+int tau_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, const float *omega, int k, const float *a32,
+              double frac, int64_t cap, bool first, unsigned int *hist, TauState *st, double *mmax,
+              double *tau_out) {
+    const LaunchCtx lc = lc_of(ctx);
+    const int64_t count = (int64_t)H * W * k;
+    const int n = p * p;
+    int rc = ensure_cand(ctx, (size_t)cap * 16);
+    if (rc) return rc;
+    int64_t *cand = (int64_t *)ctx->cand;
+    double *vals = (double *)(ctx->cand + (size_t)cap * 8);
+    {
+        Timed t(ctx, "tau_select");
+        if (first) {
+            HIP_TRY(tau_select_float(lc, a32, count, hist, st, omega, k, n, margin_coef(CS_FP32, n), mmax));
+        } else {
+            HIP_TRY(tau_reset_gather(lc, st));
+        }
+        HIP_TRY(tau_gather(lc, a32, count, mmax, st, cand, cap));
+    }
+    {
+        Timed t(ctx, "tau_exact");
+        HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, cap, vals, frac, st, tau_out));
+    }
+    return CS_OK;
+}
+
+struct TauWs {
+    size_t o_hist, o_st, o_max;
+    void carve(Carve &cv) {
+        o_hist = cv.take(sizeof(unsigned int) * 2048);
+        o_st = cv.take(sizeof(TauState));
+        o_max = cv.take(sizeof(double));
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                 const float *omega, int k, int precision, const float *alpha, double tau,
+                 double margin, uint64_t *masks, cs_cosupport_stats *stats) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
+    if (rc) return rc;
+    if (!masks) return fail(ctx, CS_ERR_ARG, "masks must be non-null");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ctx, CS_ERR_ARG, "tau must be finite and >= 0");
+    if (std::isnan(margin) || std::isinf(margin)) return fail(ctx, CS_ERR_ARG, "margin must be finite");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
+    Carve cv;
+    CosupportWs cw;
+    cw.carve(cv, k);
+    if ((rc = ensure_ws(ctx, cv.off))) return rc;
+    unsigned long long *cnt = (unsigned long long *)(ctx->ws + cw.o_cnt);
+    double *mmax = (double *)(ctx->ws + cw.o_max);
+    rc = cosupport_stage(ctx, rgb, H, W, p, omega, k, precision, alpha, tau, nullptr, margin, masks, cnt, mmax,
+                         (float *)(ctx->ws + cw.o_tin), (float *)(ctx->ws + cw.o_tout),
+                         (double *)(ctx->ws + cw.o_marg));
+    if (rc) return rc;
     if (stats) {
         HIP_TRY(hipMemcpyAsync(ctx->pinned, cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipMemcpyAsync(ctx->pinned + 8, mmax, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -333,55 +435,20 @@ int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
     HIP_TRY(hipSetDevice(ctx->device));
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     const int64_t count = (int64_t)H * W * k;
-    const int n = p * p;
-    if (precision == CS_BF16) {
-        // The median is defined by the FP64 values; the candidate window of the
-        // BF16 error bound holds a large share of all entries, the FP32 one a
-        // tiny share.  Select from an FP32 analysis instead (same result).
-        const size_t bytes = sizeof(float) * (size_t)count;
-        if (bytes > ctx->alpha32_bytes) {
-            HIP_TRY(hipStreamSynchronize(ctx->stream));
-            if (ctx->alpha32) HIP_TRY(hipFree(ctx->alpha32));
-            ctx->alpha32 = nullptr;
-            ctx->alpha32_bytes = 0;
-            if (hipMalloc((void **)&ctx->alpha32, bytes) != hipSuccess) {
-                ctx->alpha32 = nullptr;
-                return fail(ctx, CS_ERR_NOMEM, "FP32 analysis buffer of %zu bytes could not be allocated", bytes);
-            }
-            ctx->alpha32_bytes = bytes;
-        }
-        if ((rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, CS_FP32, ctx->alpha32))) return rc;
-        alpha = ctx->alpha32;
-        precision = CS_FP32;
-    }
+    const float *a32 = nullptr;
+    if ((rc = median_source(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha, &a32))) return rc;
     Carve cv;
-    const size_t o_hist = cv.take(sizeof(unsigned int) * 2048);
-    const size_t o_st = cv.take(sizeof(TauState));
-    const size_t o_max = cv.take(sizeof(double));
+    TauWs tw;
+    tw.carve(cv);
     if ((rc = ensure_ws(ctx, cv.off))) return rc;
-    unsigned int *hist = (unsigned int *)(ctx->ws + o_hist);
-    TauState *st = (TauState *)(ctx->ws + o_st);
-    double *mmax = (double *)(ctx->ws + o_max);
-    const LaunchCtx lc = lc_of(ctx);
+    unsigned int *hist = (unsigned int *)(ctx->ws + tw.o_hist);
+    TauState *st = (TauState *)(ctx->ws + tw.o_st);
+    double *mmax = (double *)(ctx->ws + tw.o_max);
     int64_t cap = (int64_t)std::min<int64_t>(count, (int64_t)1 << 20);
     TauState hs;
     for (int attempt = 0;; ++attempt) {
-        if ((rc = ensure_cand(ctx, (size_t)cap * 16))) return rc;
-        int64_t *cand = (int64_t *)ctx->cand;
-        double *vals = (double *)(ctx->cand + (size_t)cap * 8);
-        {
-            Timed t(ctx, "tau_select");
-            if (attempt == 0) {
-                HIP_TRY(tau_select_float(lc, alpha, count, hist, st, omega, k, n, margin_coef(precision, n), mmax));
-            } else {
-                HIP_TRY(tau_reset_gather(lc, st));
-            }
-            HIP_TRY(tau_gather(lc, alpha, count, mmax, st, cand, cap));
-        }
-        {
-            Timed t(ctx, "tau_exact");
-            HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, cap, vals, frac, st));
-        }
+        if ((rc = tau_stage(ctx, rgb, H, W, p, omega, k, a32, frac, cap, attempt == 0, hist, st, mmax, nullptr)))
+            return rc;
         HIP_TRY(hipMemcpyAsync(ctx->pinned, st, sizeof(TauState), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
         std::memcpy(&hs, ctx->pinned, sizeof(TauState));
@@ -393,6 +460,40 @@ int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
         return fail(ctx, CS_ERR_HIP, "exact median outside the candidate window (error bound violated)");
     *tau_out = hs.tau;
     return CS_OK;
+}
+
+int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                        const float *omega, int k, int precision, double frac, double margin, float *alpha,
+                        uint64_t *masks, double *tau_dev) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
+    if (rc) return rc;
+    if (!alpha || !masks) return fail(ctx, CS_ERR_ARG, "alpha and masks must be non-null");
+    if (reinterpret_cast<uintptr_t>(alpha) % 16) return fail(ctx, CS_ERR_ARG, "alpha must be 16-byte aligned");
+    if (!(frac >= 0.0) || !std::isfinite(frac)) return fail(ctx, CS_ERR_ARG, "frac must be finite and >= 0");
+    if (std::isnan(margin) || std::isinf(margin)) return fail(ctx, CS_ERR_ARG, "margin must be finite");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
+    const int64_t count = (int64_t)H * W * k;
+    if ((rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha))) return rc;
+    const float *a32 = nullptr;
+    if ((rc = median_source(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha, &a32))) return rc;
+    Carve cv;
+    TauWs tw;
+    tw.carve(cv);
+    CosupportWs cw;
+    cw.carve(cv, k);
+    if ((rc = ensure_ws(ctx, cv.off))) return rc;
+    TauState *st = (TauState *)(ctx->ws + tw.o_st);
+    // room for every entry: the selection never needs the host
+    rc = tau_stage(ctx, rgb, H, W, p, omega, k, a32, frac, count, true, (unsigned int *)(ctx->ws + tw.o_hist), st,
+                   (double *)(ctx->ws + tw.o_max), tau_dev);
+    if (rc) return rc;
+    rc = cosupport_stage(ctx, rgb, H, W, p, omega, k, precision, alpha, 0.0, &st->tau, margin, masks,
+                         (unsigned long long *)(ctx->ws + cw.o_cnt), (double *)(ctx->ws + cw.o_max),
+                         (float *)(ctx->ws + cw.o_tin), (float *)(ctx->ws + cw.o_tout),
+                         (double *)(ctx->ws + cw.o_marg));
+    return rc;
 }
 
 int cs_texture_similarity(cs_ctx *ctx, const uint64_t *A, int64_t na, const uint64_t *B,
@@ -475,7 +576,21 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         if (pix_subset) HIP_TRY(launch_check_pix(lc, pix_subset, npix, N, tf + L));
     }
     HIP_TRY(hipMemcpyAsync(ctx->pinned, tf, sizeof(int32_t) * (L + 1), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipEventRecord(ctx->ev_counts, ctx->stream));
+    // The scatter and the distance transforms need no host decision (invalid
+    // samples are skipped on the device): they run while the host waits for
+    // the counts, which it needs for the segment layout and the constants.
+    {
+        Timed t(ctx, "samples");
+        HIP_TRY(launch_fill_u8(lc, seeds, (size_t)L * N, 0));
+        HIP_TRY(launch_sample_scatter(lc, sample_label, sample_pix, M, L, H, W, rgb, masks, k, bc,
+                                      nblocks, recs, seeds));
+    }
+    if (npix > 0) {
+        Timed t(ctx, "edt");
+        HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest, (int32_t *)(ctx->ws + o_edt)));
+    }
+    HIP_TRY(hipEventSynchronize(ctx->ev_counts));
     int32_t counts[kMaxLabels + 1];
     std::memcpy(counts, ctx->pinned, sizeof(int32_t) * (L + 1));
     if (counts[L] & 1) return fail(ctx, CS_ERR_ARG, "a sample label or pixel index is out of range");
@@ -484,16 +599,6 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         if (counts[l] == 0) return fail(ctx, CS_ERR_EMPTY_LABEL, "label %d has no scribble sample", l);
     if (npix == 0) return CS_OK;
 
-    {
-        Timed t(ctx, "samples");
-        HIP_TRY(launch_fill_u8(lc, seeds, (size_t)L * N, 0));
-        HIP_TRY(launch_sample_scatter(lc, sample_label, sample_pix, M, L, H, W, rgb, masks, k, bc,
-                                      nblocks, recs, seeds));
-    }
-    {
-        Timed t(ctx, "edt");
-        HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest, (int32_t *)(ctx->ws + o_edt)));
-    }
     StreamSegs segs{};
     for (int l = 0; l < L; ++l) {
         segs.seg[l + 1] = segs.seg[l] + counts[l];
@@ -569,8 +674,8 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         fa.fix_cap = (int)(ntiles_pad * L);
         fa.sigma_c = pa.sigma_c;
         // per-label chunk ranges and the label order, staged through the upper
-        // half of the pinned buffer (its previous copy finished at the
-        // synchronisation above)
+        // half of the pinned buffer (the copy of the previous call, enqueued
+        // before the counts, finished before the event above)
         int32_t *meta_h = (int32_t *)(ctx->pinned + kPinnedBytes / 2);
         for (int l = 0; l <= L; ++l) meta_h[l] = segs.pseg[l] / kStreamChunk;
         for (int l = 0; l < L; ++l) meta_h[L + 1 + l] = pa.label_order[l];
@@ -629,6 +734,12 @@ int cs_profile_enable(cs_ctx *ctx, int on) {
     ctx->spans.clear();
     ctx->totals.clear();
     ctx->prof = on != 0;
+    return CS_OK;
+}
+
+int cs_profile_only(cs_ctx *ctx, const char *name) {
+    if (!ctx) return CS_ERR_ARG;
+    ctx->only = name ? name : "";
     return CS_OK;
 }
 

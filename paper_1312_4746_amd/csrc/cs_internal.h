@@ -53,17 +53,20 @@ struct AnalyzeArgs {
 hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precision);
 
 // Masks from stored analysed vectors, same decisions as the analysis epilogue.
+// A non-null tau_dev (device) replaces tau, read by the kernel.
 hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N, int k, const float *t_in,
-                             const float *t_out, double tau, const float *rgb, int H, int W, int p,
+                             const float *t_out, double tau, const double *tau_dev, const float *rgb, int H,
+                             int W, int p,
                              const double *wmask, const float *omega, uint64_t *masks,
                              unsigned long long *recomputed);
 
 // Per-row thresholds t_in/t_out = tau -/+ margin_j, rounded outward to float.
 // margin < 0 selects the proven bound coef * ||O_j||_2 + tiny; writes the
-// largest margin to *max_margin.
+// largest margin to *max_margin.  A non-null tau_dev (device) replaces tau;
+// a non-null zero (device counter) is cleared.
 hipError_t launch_thresholds(const LaunchCtx &lc, const float *omega, int k, int n, double tau,
-                             double margin, double coef, float *t_in, float *t_out,
-                             double *margins, double *max_margin);
+                             const double *tau_dev, double margin, double coef, float *t_in, float *t_out,
+                             double *margins, double *max_margin, unsigned long long *zero);
 
 // ---- exact median of |alpha| (k_tau.hip) ----
 struct TauState {
@@ -86,10 +89,11 @@ hipError_t tau_reset_gather(const LaunchCtx &lc, TauState *st);
 hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
                       const double *max_margin, TauState *st, int64_t *cand, int64_t cap);
 // FP64 recompute of the candidates and the exact selection; the candidate
-// count is read on the device (at most cap are used; more leaves NaN).
+// count is read on the device (at most cap are used; more leaves NaN).  tau
+// also goes to tau_out (device) when non-null.
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
-                      int64_t cap, double *vals, double frac, TauState *st);
+                      int64_t cap, double *vals, double frac, TauState *st, double *tau_out);
 
 // ---- texture similarity (k_tsm.hip) ----
 hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const uint64_t *B,

@@ -283,11 +283,12 @@ constexpr int kMaskPx = 8;
 template <int W64>
 __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t N, int k,
                                                      const float *t_in, const float *t_out, double tau,
-                                                     const float *rgb, int H, int W, int p,
-                                                     const double *wmask, const float *omega,
+                                                     const double *tau_dev, const float *rgb, int H, int W,
+                                                     int p, const double *wmask, const float *omega,
                                                      uint64_t *masks, unsigned long long *recomputed) {
 #pragma clang fp contract(off)
     __shared__ double s_all[4][15 * 15];
+    if (tau_dev) tau = *tau_dev;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *s = s_all[wave];
     const int n = p * p, h = (p - 1) / 2;
@@ -378,14 +379,15 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
 }
 
 hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N, int k, const float *t_in,
-                             const float *t_out, double tau, const float *rgb, int H, int W, int p,
+                             const float *t_out, double tau, const double *tau_dev, const float *rgb, int H,
+                             int W, int p,
                              const double *wmask, const float *omega, uint64_t *masks,
                              unsigned long long *recomputed) {
     if (N <= 0) return hipSuccess;
     const int64_t blocks = (N + 4 * kMaskPx - 1) / (4 * kMaskPx);
 #define CS_MASK_LAUNCH(WW)                                                                              \
     hipLaunchKernelGGL(k_mask_alpha<WW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, N, k, t_in, \
-                       t_out, tau, rgb, H, W, p, wmask, omega, masks, recomputed)
+                       t_out, tau, tau_dev, rgb, H, W, p, wmask, omega, masks, recomputed)
     switch ((k + 63) / 64) {
         case 1: CS_MASK_LAUNCH(1); break;
         case 2: CS_MASK_LAUNCH(2); break;
@@ -398,10 +400,12 @@ hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N,
 
 // Per-row decision thresholds.  One workgroup of 256 threads (k <= 256).
 __global__ __launch_bounds__(256) void k_thresholds(const float *omega, int k, int n, double tau,
-                                                     double margin, double coef, float *t_in,
-                                                     float *t_out, double *margins,
-                                                     double *max_margin) {
+                                                     const double *tau_dev, double margin, double coef,
+                                                     float *t_in, float *t_out, double *margins,
+                                                     double *max_margin, unsigned long long *zero) {
     __shared__ double red[256];
+    if (tau_dev) tau = *tau_dev;
+    if (zero && threadIdx.x == 0) *zero = 0ull;
     const int j = threadIdx.x;
     double m = 0.0;
     if (j < k) {
@@ -427,10 +431,10 @@ __global__ __launch_bounds__(256) void k_thresholds(const float *omega, int k, i
 }
 
 hipError_t launch_thresholds(const LaunchCtx &lc, const float *omega, int k, int n, double tau,
-                             double margin, double coef, float *t_in, float *t_out,
-                             double *margins, double *max_margin) {
-    hipLaunchKernelGGL(k_thresholds, dim3(1), dim3(256), 0, lc.stream, omega, k, n, tau, margin,
-                       coef, t_in, t_out, margins, max_margin);
+                             const double *tau_dev, double margin, double coef, float *t_in, float *t_out,
+                             double *margins, double *max_margin, unsigned long long *zero) {
+    hipLaunchKernelGGL(k_thresholds, dim3(1), dim3(256), 0, lc.stream, omega, k, n, tau, tau_dev, margin,
+                       coef, t_in, t_out, margins, max_margin, zero);
     return hipGetLastError();
 }
 

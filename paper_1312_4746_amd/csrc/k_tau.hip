@@ -328,7 +328,7 @@ __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, i
 // differ are common to all candidates and skipped; the remaining digits are
 // selected 8 bits at a time with an LDS histogram and a one-wave scan.
 __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t cap, double frac,
-                                                      TauState *st) {
+                                                      TauState *st, double *tau_out) {
     __shared__ unsigned int hist[256];
     __shared__ unsigned long long s_min, s_max, s_prefix, s_rank;
     __shared__ int s_ok;
@@ -340,6 +340,7 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
         if (tid == 0) {
             st->median = __longlong_as_double(0x7FF8000000000000ll);  // NaN: retry or bound violated
             st->tau = st->median;
+            if (tau_out) *tau_out = st->median;
         }
         return;
     }
@@ -365,6 +366,7 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
             const double med = __longlong_as_double((long long)s_min);
             st->median = med;
             st->tau = frac * med;
+            if (tau_out) *tau_out = frac * med;
         }
         return;
     }
@@ -417,19 +419,20 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
         const double med = __longlong_as_double((long long)s_prefix);
         st->median = med;
         st->tau = frac * med;
+        if (tau_out) *tau_out = frac * med;
     }
 }
 
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
-                      int64_t cap, double *vals, double frac, TauState *st) {
+                      int64_t cap, double *vals, double frac, TauState *st, double *tau_out) {
     (void)n;
     int64_t blocks = (int64_t)lc.num_cu * 16;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_tau_recompute, dim3((unsigned)blocks), dim3(64), 0, lc.stream, rgb, H, W, p, wmask, omega,
                        k, cand, st, cap, vals);
-    hipLaunchKernelGGL(k_tau_select, dim3(1), dim3(1024), 0, lc.stream, vals, cap, frac, st);
+    hipLaunchKernelGGL(k_tau_select, dim3(1), dim3(1024), 0, lc.stream, vals, cap, frac, st, tau_out);
     return hipGetLastError();
 }
 

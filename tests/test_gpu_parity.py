@@ -114,6 +114,40 @@ def test_bsds_shape_tau_and_masks_bit_exact(ctx, prec):
     assert st_a["recomputed"] == st["recomputed"]
 
 
+@pytest.mark.parametrize("case", [SMALL_CASES[1], SMALL_CASES[2], SMALL_CASES[4]], ids=lambda c: c["name"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_cosupport_median_matches_separate_calls(ctx, case, prec):
+    """The enqueue-only co-support call gives the oracle's tau and masks and
+    the same analysed vectors as the separate calls; two calls in a row with
+    different images leave no state behind."""
+    for seed in (7, 8):
+        w = _small(case, seed=seed)
+        a_ref = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega)
+        tau_ref, _ = oracle.tau_median(a_ref, 0.1)
+        alpha, m, tau_d = ctx.cosupport_median(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), 0.1, precision=prec)
+        assert float(tau_d.item()) == tau_ref
+        assert np.array_equal(masks_u64(m), oracle.cosupport(a_ref, tau_ref))
+        a_sep = ctx.analyze_patches(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), precision=prec)
+        assert torch.equal(alpha, a_sep.view(alpha.shape))
+
+
+def test_cosupport_median_bsds_shape_and_zero_image(ctx):
+    w = make_config(1)
+    a_ref = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega)
+    tau_ref, _ = oracle.tau_median(a_ref, 0.1)
+    _, m, tau_d = ctx.cosupport_median(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), 0.1)
+    assert float(tau_d.item()) == tau_ref
+    assert np.array_equal(masks_u64(m), oracle.cosupport(a_ref, tau_ref))
+    # every entry is a candidate of the exact selection (all |a| = 0)
+    rgb = np.zeros((3, 20, 21), np.float32)
+    om = np.random.default_rng(0).standard_normal((70, 25)).astype(np.float32)
+    _, m0, t0 = ctx.cosupport_median(dev(rgb), 5, 1.25, dev(om), 0.1)
+    assert float(t0.item()) == 0.0
+    mm = masks_u64(m0)
+    assert np.all(mm[:, 0] == np.uint64(0xFFFFFFFFFFFFFFFF))
+    assert np.all(mm[:, 1] == np.uint64(63))
+
+
 def test_bf16_stated_margin_reports_mismatches(ctx):
     """Precision form at the stated margin 2^-8 tau: entries outside it are
     decided by the BF16 value; the mismatch count is reported, and the proven
