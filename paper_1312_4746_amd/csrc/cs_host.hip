@@ -546,17 +546,18 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_d2 = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_nn = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_edt = cv.take(edt_scratch_bytes(H, W, L));
-    // full-image path: FP8 sample features for the MFMA texture term and the fix-up queue
-    const bool fast = pix_subset == nullptr;
-    const int KP = (k + 2 + 127) / 128 * 128;
+    // full-image path (matrix-core kernel; its exact integer location product
+    // needs positions below 2048): FP8 sample features, records, fix-up queue
+    const bool fast = pix_subset == nullptr && W <= 2048 && H <= 2048;
+    const int KP = (k + 4 + 127) / 128 * 128;
     const int tiles_x = (W + 7) / 8, tiles_y = (H + 2 * kParzenRB - 1) / (2 * kParzenRB);
     const int64_t ntiles = (int64_t)tiles_x * tiles_y;
     const int64_t ngroups = (ntiles + 3) / 4, ntiles_pad = ngroups * 4;
     const int64_t Mpad_max = M + (int64_t)(kStreamChunk - 1) * L;
     const size_t o_feat = fast ? cv.take((size_t)Mpad_max * KP) : 0;
-    const size_t o_srec = fast ? cv.take(sizeof(float) * 8 * (size_t)Mpad_max) : 0;
+    const size_t o_srec = fast ? cv.take(sizeof(float) * 12 * (size_t)Mpad_max) : 0;
     const size_t o_fix = fast ? cv.take(sizeof(int2) * (size_t)ntiles_pad * L) : 0;
-    const size_t o_meta = cv.take(sizeof(int32_t) * (2 * (size_t)L + 1));
+    const size_t o_meta = cv.take(sizeof(int32_t) * (3 * (size_t)L + 1));
     const size_t o_coef = cv.take(sizeof(float4) * (size_t)L *
                                   (size_t)(fast ? ntiles_pad * kTilePix : npix));
     int rc = ensure_ws(ctx, cv.off);
@@ -679,8 +680,12 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         int32_t *meta_h = (int32_t *)(ctx->pinned + kPinnedBytes / 2);
         for (int l = 0; l <= L; ++l) meta_h[l] = segs.pseg[l] / kStreamChunk;
         for (int l = 0; l < L; ++l) meta_h[L + 1 + l] = pa.label_order[l];
+        for (int l = 0; l < L; ++l) {
+            const int in_last = counts[l] - (segs.pseg[l + 1] - segs.pseg[l] - kStreamChunk);
+            meta_h[2 * L + 1 + l] = (in_last + 15) / 16;
+        }
         int32_t *meta_d = (int32_t *)(ctx->ws + o_meta);
-        HIP_TRY(hipMemcpyAsync(meta_d, meta_h, sizeof(int32_t) * (2 * (size_t)L + 1), hipMemcpyHostToDevice,
+        HIP_TRY(hipMemcpyAsync(meta_d, meta_h, sizeof(int32_t) * (3 * (size_t)L + 1), hipMemcpyHostToDevice,
                                ctx->stream));
         fa.meta = meta_d;
         ctx->loglik_counters = fcnt;

@@ -151,7 +151,8 @@ struct ParzenFastArgs {
     const float *rgb;
     const uint64_t *masks;
     const uint8_t *feat;   // Mpad x 128*ksteps FP8 sample features (swizzled rows)
-    const float *rec;      // per chunk of 64 slots: 64 float4 {x, y, r, g}, 64 floats b, padding (2 KiB)
+                           // (positions below 2048: the location product is exact)
+    const float *rec;      // per chunk of 64 slots: BF16 location pieces (2 x 1 KiB), colours (1 KiB)
     const float4 *coef;    // tiled: [label][group*4 + tile][kTilePix] {nA, nB, -R, K}
     float *loglik;
     unsigned int *work_counter;
@@ -162,7 +163,8 @@ struct ParzenFastArgs {
     int tiles_x, ntiles, ngroups;
     double sigma_c;
     // device: [0..L] first chunk of each label's padded segment (chunk units),
-    // [L+1 .. 2L] the labels by decreasing sample count
+    // [L+1 .. 2L] the labels by decreasing sample count, [2L+1 .. 3L] the
+    // 16-sample steps of each label's last chunk that hold real samples
     const int *meta;
 };
 hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,

@@ -7,20 +7,25 @@
 // part |B| - 2 |A n B| is a dot product of two short feature vectors, so a
 // whole 16-pixel x 16-sample block of it is one MFMA:
 // v_mfma_scale_f32_16x16x128_f8f6f4 with FP8 (E4M3) operands and unit scales.
-// Pixel features: mask bit j in {0, 1} for j < k, then [1, 1]; sample
-// features: -2 x bit j, then [16 floor(|B|/16), |B| mod 16].  Every operand is
-// an exactly representable FP8 value and every partial sum an integer below
-// 2^10, so the FP32 accumulator holds it exactly; the pixel's own |A| joins
-// the location operand below.
+// Pixel features: mask bit j in {0, 1} for j < k, then [1, 1, 16 floor(|A|/16),
+// |A| mod 16]; sample features: -2 x bit j, then [16 floor(|B|/16), |B| mod 16,
+// 1, 1].  The product is the whole TSM.  Every operand is an exactly
+// representable FP8 value and every partial sum an integer below 2^10, so the
+// FP32 accumulator holds it exactly.
 //
-// The location term nA |p - s|^2 is a second, FP32 MFMA (16x16x4): with the
-// pixel and sample positions taken relative to the tile origin it is the dot
-// product of nA [|p|^2, -2 px, -2 py, 1] and [1, sx, sy, |s|^2], exact in its
-// integer part, and the log-sum-exp reference rides in as the accumulator
-// input.  Colours are stored pre-scaled by sqrt(log2(e) / (2 sigma_c^2)), so
-// per pair the VALU is left with three colour differences, four FMAs (the
-// texture term onto the MFMA result and the three negated squares), one
-// v_exp_f32 and one add.
+// The location term nA |p - s|^2 needs the integer Q = |p - s|^2 = |p|^2 -
+// 2 p.s + |s|^2 of two pixel positions.  With every coordinate below 2048 each
+// factor splits into at most three BF16 pieces of 8 significant bits (exact),
+// every product of pieces is exact, and every partial sum is an integer of
+// magnitude at most |p|^2 + |s|^2 < 2^24, so a BF16 MFMA (16x16x32, 14 of the
+// 32 K slots used) returns Q exactly in FP32 whatever its summation order.  The
+// sample pieces are precomputed in the sample stream; the pixel pieces are
+// set once per work item.  Colours are stored pre-scaled by
+// sqrt(log2(e) / (2 sigma_c^2)), so per pair the VALU is left with the texture
+// and location factors (two FMAs onto the log-sum-exp reference), three
+// colour differences and three negated squares (FMAs), one v_exp_f32 and one
+// add.  (An FP32 MFMA, K = 4, also fits the location term, but on gfx950 it
+// holds the VALU for its whole duration; the BF16 one largely overlaps it.)
 //
 // Work decomposition.  A workgroup of 4 waves owns four 8x4 pixel tiles (one
 // per wave); a work item is such a group and one label, taken from an atomic
@@ -46,12 +51,20 @@ namespace cs {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr double kLn2F = 0.6931471805599453;
 constexpr double kLog2eF = 1.4426950408889634;
 constexpr int kChunkS = kStreamChunk;  // samples per chunk
-constexpr float kFarAway = 1e15f;      // x of padding samples: d^2 ~ 1e30, finite, term underflows to 0
+constexpr float kFarQ = 0x1p100f;      // location feature of padding samples: Q ~ 2^100, term underflows to 0
+// Floats of one chunk's records: location pieces K 0..7 (64 x 16 B), K 8..15
+// (64 x 16 B), colours (64 x float4).
+constexpr int kRecChunkF = kChunkS * 12;
+
+// BF16 bit pattern of a float that BF16 holds exactly.
+__device__ __forceinline__ short bf16_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
 
 // E4M3 (bias 7) bit pattern of an integer 0..256 that is exactly representable
 // (0..16 and multiples of 16 up to 256).
@@ -76,10 +89,13 @@ __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib, uint32_t b) {
 __device__ __forceinline__ int swz(int p, int row) { return (p & ~7) | ((p & 7) ^ ((row >> 1) & 7)); }
 
 // Padded sample stream: for every padded slot s (label segments rounded up to
-// whole chunks), the FP8 feature row (swizzled) and its record; the records
-// of a chunk of 64 slots take 2 KiB: 64 float4 {x, y, r, g}, then 64 floats b
-// (then padding), so that 16 lanes reading 16 consecutive slots touch distinct
-// LDS banks.  Padding slots have zero features and x = 1e15.
+// whole chunks), the FP8 feature row (swizzled) and its record.  The records
+// of a chunk of 64 slots take 3 KiB, three planes of 64 x 16 B so that 16 lanes
+// reading 16 consecutive slots touch distinct LDS banks: the BF16 location
+// pieces for K 0..7 [1, 1, 1, sx_h, sx_l, sx_h, sx_l, sy_h] and K 8..15
+// [sy_l, sy_h, sy_l, q_h, q_m, q_l, far, 0] (q = sx^2 + sy^2), then the
+// scaled colours {r, g, b, 0}.  Padding slots have zero features and pieces
+// except far = 2^100.
 __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int k, int KP, int L,
                                                        StreamSegs segs, int64_t Mpad, float cscale,
                                                        uint8_t *feat, float *rec) {
@@ -92,8 +108,10 @@ __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int
     uint32_t words[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t cnt = 0;
     const int row = (int)(s & (kChunkS - 1));
-    float *rc = rec + (s - row) * 8;  // this chunk's 2 KiB of records
-    float v5[5] = {kFarAway, 0.0f, 0.0f, 0.0f, 0.0f};
+    float *rc = rec + (s / kChunkS) * kRecChunkF;  // this chunk's 3 KiB of records
+    float lp[16];
+    for (int q = 0; q < 16; ++q) lp[q] = 0.0f;
+    float col[3] = {0.0f, 0.0f, 0.0f};
     if (real) {
         const uint32_t *rw = recs[segs.seg[l] + j].w;
         for (int w = 0; w < 8; ++w) {
@@ -104,14 +122,32 @@ __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int
             words[w] = v;
             cnt += __popc(v);
         }
-        for (int q = 0; q < 5; ++q) v5[q] = __uint_as_float(rw[q]);
-        for (int q = 2; q < 5; ++q) v5[q] *= cscale;  // colours in units of the kernel width
+        const uint32_t sx = (uint32_t)__uint_as_float(rw[0]), sy = (uint32_t)__uint_as_float(rw[1]);
+        const uint32_t q = sx * sx + sy * sy;
+        const float sxh = (float)(sx & ~0xFFu), sxl = (float)(sx & 0xFFu);
+        const float syh = (float)(sy & ~0xFFu), syl = (float)(sy & 0xFFu);
+        const float v0[16] = {1.0f, 1.0f, 1.0f, sxh, sxl, sxh, sxl, syh,
+                              syl, syh, syl, (float)(q & ~0xFFFFu), (float)(q & 0xFF00u), (float)(q & 0xFFu),
+                              0.0f, 0.0f};
+        for (int t = 0; t < 16; ++t) lp[t] = v0[t];
+        for (int c = 0; c < 3; ++c) col[c] = cscale * __uint_as_float(rw[2 + c]);
+    } else {
+        lp[14] = kFarQ;
     }
-    for (int q = 0; q < 4; ++q) rc[4 * row + q] = v5[q];
-    rc[4 * kChunkS + row] = v5[4];
-    rc[5 * kChunkS + row] = 0.0f;  // padding (keeps the whole 2 KiB defined)
-    rc[6 * kChunkS + row] = 0.0f;
-    rc[7 * kChunkS + row] = 0.0f;
+    uint32_t pk[8];
+    for (int t = 0; t < 8; ++t)
+        pk[t] = (uint32_t)(uint16_t)bf16_bits(lp[2 * t]) | ((uint32_t)(uint16_t)bf16_bits(lp[2 * t + 1]) << 16);
+    uint32_t *r0 = reinterpret_cast<uint32_t *>(rc) + 4 * row;
+    uint32_t *r1 = reinterpret_cast<uint32_t *>(rc) + 4 * kChunkS + 4 * row;
+    for (int t = 0; t < 4; ++t) {
+        r0[t] = pk[t];
+        r1[t] = pk[4 + t];
+    }
+    float *rcol = rc + 8 * kChunkS + 4 * row;
+    rcol[0] = col[0];
+    rcol[1] = col[1];
+    rcol[2] = col[2];
+    rcol[3] = 0.0f;
     uint32_t *fo = reinterpret_cast<uint32_t *>(feat + s * KP);
     for (int p = 0; p < KP / 16; ++p) {  // logical 16-byte slot p holds features 16p..16p+15
         uint32_t out4[4];
@@ -125,6 +161,7 @@ __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int
                     uint32_t byte = 0xFFFFFFFFu;
                     if (f == k) byte = fp8_of_int(16u * (cnt >> 4));
                     else if (f == k + 1) byte = fp8_of_int(cnt & 15u);
+                    else if (f == k + 2 || f == k + 3) byte = 0x38u;  // 1.0
                     if (byte != 0xFFFFFFFFu) val = (val & ~(0xFFu << (8 * b))) | (byte << (8 * b));
                 }
             }
@@ -156,8 +193,8 @@ void k_parzen_mfma(ParzenFastArgs a) {
     // flight into the other, and does not wait for it.
     __shared__ __align__(16) uint8_t s_feat0[FEAT_B];
     __shared__ __align__(16) uint8_t s_feat1[FEAT_B];
-    __shared__ __align__(16) float s_rec0[kChunkS * 8];
-    __shared__ __align__(16) float s_rec1[kChunkS * 8];
+    __shared__ __align__(16) float s_rec0[kRecChunkF];
+    __shared__ __align__(16) float s_rec1[kRecChunkF];
     __shared__ int s_item;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -181,8 +218,21 @@ void k_parzen_mfma(ParzenFastArgs a) {
         lowm[q] = wi < nw32 - 1 ? ~0u : wi == nw32 - 1 ? lastmask : 0u;
         spec[q] = (rel >= 0 && rel < 32 ? 1u << rel : 0u) | (rel + 1 >= 0 && rel + 1 < 32 ? 1u << (rel + 1) : 0u);
     }
-    const float wc = g == 0 ? 1.0f : 0.0f, wx = g == 1 ? 1.0f : 0.0f, wy = g == 2 ? 1.0f : 0.0f,
-                wq = g == 3 ? 1.0f : 0.0f;
+    // where the pixel's |A| features (k + 2, k + 3) sit: lane group, step, byte
+    const int fa = a.k + 2;
+    const int fa_g = (fa >> 5) & 3, fa_q = fa >> 7, fa_b = fa & 31;
+    const int fb = a.k + 3;
+    const int fb_g = (fb >> 5) & 3, fb_q = fb >> 7, fb_b = fb & 31;
+    // LDS byte offsets of the lane's operands in step 0 of a chunk buffer (step
+    // st adds st * 16 rows; the swizzle depends on the row only through
+    // (row / 2) mod 8, the same for rows jl and 16 st + jl)
+    int foff[KSTEPS][2];
+#pragma unroll
+    for (int q = 0; q < KSTEPS; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) foff[q][h] = jl * KP + 16 * swz(8 * q + 2 * g + h, jl);
+    const int loff = (g & 1) * (16 * kChunkS) + 16 * jl;  // location pieces, K 0..7 or 8..15
+    const int coff = 32 * kChunkS + 16 * jl;              // colours
     uint32_t n_rescale = 0;  // wave-chunks whose reference moved (wave-uniform)
     uint32_t n_overflow = 0; // (label, tile) items handed to the exact kernel on overflow
 
@@ -197,6 +247,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
         const int grp = item / a.L;
         const int lab = a.meta[a.L + 1 + (item - grp * a.L)];
         const int c0 = a.meta[lab], c1 = a.meta[lab + 1];
+        const int last_steps = a.meta[2 * a.L + 1 + lab];  // 16-sample steps of the last chunk
         const int tile = grp * 4 + wave;
         const bool tile_ok = tile < a.ntiles;
         const int ty_t = tile_ok ? tile / a.tiles_x : 0;
@@ -210,8 +261,8 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 const uint8_t *src = a.feat + s0 * KP + u * 4096 + tid * 16;
                 __builtin_amdgcn_global_load_lds(src, (lds_void *)(sf + u * 4096 + wave * 1024), 16, 0, 0);
             }
-            if (wave < 2) {
-                const float *src = a.rec + s0 * 8 + tid * 4;
+            if (wave < 3) {
+                const float *src = a.rec + (int64_t)c * kRecChunkF + tid * 4;
                 __builtin_amdgcn_global_load_lds(src, (lds_void *)(sr + wave * 256), 16, 0, 0);
             }
         };
@@ -238,34 +289,36 @@ void k_parzen_mfma(ParzenFastArgs a) {
 
         // ---- per-pixel coefficients of this label (log2 units)
         const float4 *cf = a.coef + (int64_t)lab * coef_label_stride + (int64_t)tile * kTilePix;
-        float nB[RB][4];
-        f32x4 nRv[RB];  // -reference, the accumulator input of the location MFMA
+        float nA[RB][4], nB[RB][4], nR[RB][4];  // location and texture factors, -reference
+        bool weak = false;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float4 v = cf[(2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r];
+                nA[rb][r] = v.x;
                 nB[rb][r] = v.y;
-                nRv[rb][r] = v.z;
+                nR[rb][r] = v.z;
+                const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
+                // padding samples sit at Q ~ 2^100; a bandwidth wide enough to
+                // reach them (or a non-finite one) goes to the exact kernel
+                weak |= tile_ok && px < a.W && py < a.H && !(v.x < -1e-18f);
             }
 
         // ---- pixel rows of both MFMAs: row i = lane%16 of row block rb is
         // pixel rb*16 + jl of the tile = (x0 + (jl & 7), y0 + 2rb + (jl >> 3)).
         // FP8 operand: the lane's 32-feature slice of the mask bits plus the
-        // two unit features at k, k+1.
-        // Location operand (FP32 MFMA, K = 4), positions relative to the tile
-        // origin: A[i] = [nA_i (dx^2 + dy^2) + nB_i |A_i|, -2 nA_i dx, -2 nA_i dy, nA_i]
-        // against B[j] = [1, sx, sy, sx^2 + sy^2], so that (A B)[i][j] =
-        // nA_i |p_i - s_j|^2 + nB_i |A_i|; the reference rides in as the
-        // accumulator input.
+        // unit features at k, k+1 and |A| at k+2, k+3.  BF16 operand: the
+        // pieces of |p|^2, -2 px and -2 py against the sample pieces (lane
+        // groups 0 and 1 hold K 0..7 and 8..15, groups 2 and 3 zeros).
         i32x8 Aop[RB][KSTEPS];
-        float Aloc[RB];
-        bool weak = false;
+        s16x8 Abf[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const int dxi = jl & 7, dyi = 2 * rb + (jl >> 3);
-            const bool v = tile_ok && x0 + dxi < a.W && y0 + dyi < a.H;
-            const int64_t pix = v ? (int64_t)(y0 + dyi) * a.W + x0 + dxi : 0;
+            const int px = x0 + dxi, py = y0 + dyi;
+            const bool v = tile_ok && px < a.W && py < a.H;
+            const int64_t pix = v ? (int64_t)py * a.W + px : 0;
             const uint32_t *mw = mask32 + pix * 2 * W64;
             uint32_t cnt = 0;
             for (int w = 0; w < nw32; ++w) cnt += __popc(mw[w] & (w == nw32 - 1 ? lastmask : ~0u));
@@ -275,20 +328,30 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 const uint32_t ext = v ? (m | spec[q]) : 0u;
 #pragma unroll
                 for (int vv = 0; vv < 8; ++vv) Aop[rb][q][vv] = (int)nibble_bytes((ext >> (4 * vv)) & 0xFu, 0x38u);
+                if (v && g == fa_g && q == fa_q)
+                    Aop[rb][q][fa_b >> 2] |= (int)(fp8_of_int(16u * (cnt >> 4)) << (8 * (fa_b & 3)));
+                if (v && g == fb_g && q == fb_q)
+                    Aop[rb][q][fb_b >> 2] |= (int)(fp8_of_int(cnt & 15u) << (8 * (fb_b & 3)));
             }
-            const float4 crow = cf[rb * 16 + jl];
-            const float nA = crow.x;
-            const float dx = (float)dxi, dy = (float)dyi;
-            Aloc[rb] = g == 0 ? fmaf(nA, fmaf(dx, dx, dy * dy), crow.y * (float)cnt)
-                     : g == 1 ? -2.0f * dx * nA : g == 2 ? -2.0f * dy * nA : nA;
-            // padding samples sit 1e15 px away; a bandwidth wide enough to
-            // reach them (or a non-finite one) goes to the exact kernel
-            weak |= v && !(nA < -1e-18f);
+            const uint32_t p2 = (uint32_t)(px * px + py * py), X = 2u * (uint32_t)px, Y = 2u * (uint32_t)py;
+            const float xh = -(float)(X & ~0xFFu), xl = -(float)(X & 0xFFu);
+            const float yh = -(float)(Y & ~0xFFu), yl = -(float)(Y & 0xFFu);
+            float e[8];
+            if (g == 0) {
+                e[0] = (float)(p2 & ~0xFFFFu); e[1] = (float)(p2 & 0xFF00u); e[2] = (float)(p2 & 0xFFu);
+                e[3] = xh; e[4] = xh; e[5] = xl; e[6] = xl; e[7] = yh;
+            } else if (g == 1) {
+                e[0] = yh; e[1] = yl; e[2] = yl; e[3] = 1.0f; e[4] = 1.0f; e[5] = 1.0f; e[6] = 1.0f; e[7] = 0.0f;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) e[t] = 0.0f;
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) Abf[rb][t] = bf16_bits(e[t]);
         }
         bool item_bad = __ballot(weak) != 0ull;
         if (item_bad) active = false;
 
-        const float x0f = (float)x0, y0f = (float)y0;
         float S[RB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -296,27 +359,30 @@ void k_parzen_mfma(ParzenFastArgs a) {
             for (int r = 0; r < 4; ++r) S[rb][r] = 0.0f;
 
         // One chunk computed from buffers (F, Rr) while the next one streams
-        // into (Fn, Rn).
+        // into (Fn, Rn); the last chunk of the label stops after its last
+        // 16-sample step that holds a real sample.
         auto process = [&](int c, const uint8_t *F, const float *Rr, uint8_t *Fn, float *Rn) {
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();  // chunk c resident in (F, Rr); the other pair is free
             if (c + 1 < c1) issue(c + 1, Fn, Rn);
             if (!active) return;
-#pragma unroll 1
+            const int nst = c + 1 == c1 ? last_steps : kChunkS / 16;
+#pragma unroll
             for (int st = 0; st < kChunkS / 16; ++st) {
-                const int js = st * 16 + jl;
+                if (st >= nst) break;
+                const uint8_t *Fs = F + st * 16 * KP;
+                const uint8_t *Rs = reinterpret_cast<const uint8_t *>(Rr) + st * 256;
                 i32x8 Bop[KSTEPS];
 #pragma unroll
                 for (int q = 0; q < KSTEPS; ++q) {
-                    const int p0 = 8 * q + 2 * g;
-                    const uint4 lo4 = *reinterpret_cast<const uint4 *>(F + js * KP + 16 * swz(p0, js));
-                    const uint4 hi4 = *reinterpret_cast<const uint4 *>(F + js * KP + 16 * swz(p0 + 1, js));
+                    const uint4 lo4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][0]);
+                    const uint4 hi4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][1]);
                     Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
                                    (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
                 }
-                const float4 sxyrg = *reinterpret_cast<const float4 *>(Rr + js * 4);
-                const float sb = Rr[4 * kChunkS + js];
-                f32x4 T[RB];
+                const s16x8 Bbf = *reinterpret_cast<const s16x8 *>(Rs + loff);
+                const float4 col = *reinterpret_cast<const float4 *>(Rs + coff);
+                f32x4 T[RB], Q[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
                     T[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -324,20 +390,17 @@ void k_parzen_mfma(ParzenFastArgs a) {
                     for (int q = 0; q < KSTEPS; ++q)
                         T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(Aop[rb][q], Bop[q], T[rb], 0, 0,
                                                                                   0, 127, 0, 127);
+                    Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Abf[rb]),
+                                                                    __builtin_bit_cast(bf16x8, Bbf),
+                                                                    f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
                 }
-                // this lane's entry g of the location column (one-hot weights,
-                // no divergent select)
-                const float sx = sxyrg.x - x0f, sy = sxyrg.y - y0f;
-                const float bl = fmaf(wq, fmaf(sx, sx, sy * sy), fmaf(wy, sy, fmaf(wx, sx, wc)));
-                f32x4 D[RB];
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) D[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Aloc[rb], bl, nRv[rb], 0, 0, 0);
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float dr = pr[rb][r] - sxyrg.z, dg = pg[rb][r] - sxyrg.w, db = pb[rb][r] - sb;
-                        float u = fmaf(T[rb][r], nB[rb][r], D[rb][r]);
+                        const float dr = pr[rb][r] - col.x, dg = pg[rb][r] - col.y, db = pb[rb][r] - col.z;
+                        float u = fmaf(T[rb][r], nB[rb][r], nR[rb][r]);
+                        u = fmaf(Q[rb][r], nA[rb][r], u);
                         u = fmaf(-dr, dr, u);
                         u = fmaf(-dg, dg, u);
                         u = fmaf(-db, db, u);
@@ -365,7 +428,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
                             if (s <= 3.0e38f) {
                                 const int e = (int)((__float_as_uint(s) >> 23) & 0xFFu) - 127;
                                 S[rb][r] = ldexpf(s, -e);
-                                nRv[rb][r] -= (float)e;
+                                nR[rb][r] -= (float)e;
                             } else {
                                 over = true;
                             }
@@ -394,7 +457,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float Rl = -nRv[rb][r];
+                    const float Rl = -nR[rb][r];
                     float Rm = Rl;
 #pragma unroll
                     for (int off = 1; off < 16; off <<= 1) Rm = fmaxf(Rm, __shfl_xor(Rm, off));

@@ -379,3 +379,35 @@ def test_loglik_large_full_image_fast_path(ctx):
     m = ctx.cosupport(rgb, w.p, w.mask_sigma, dev(w.omega), tau, alpha=a)
     masks = masks_u64(m)
     _full_image_sampled(ctx, w, masks, 400, 12)
+
+
+@pytest.mark.parametrize("shape", [(16, 2048), (2048, 12)], ids=["W2048", "H2048"])
+def test_loglik_largest_coordinates_fast_path(ctx, shape):
+    """Positions up to 2047 on the matrix-core path, whose location product is
+    exact only below 2048: last row and column included in the samples."""
+    import dataclasses
+    H, W = shape
+    w = make_workload("edge", H=H, W=W, R=2, p=5, k=40, seed=5, per_region=40)
+    corners = np.array([W - 1, (H - 1) * W, H * W - 1], np.int32)
+    sp = np.unique(np.concatenate([w.sample_pix, corners])).astype(np.int32)
+    w = dataclasses.replace(w, sample_pix=sp, sample_label=w.region.ravel()[sp].astype(np.int32))
+    masks, _, _ = oracle.full_masks(w)
+    _full_image_sampled(ctx, w, masks, 600, 21)
+
+
+def test_loglik_wide_image_exact_route(ctx):
+    """Images wider than 2048 take the exact kernel on the full image."""
+    w = make_workload("wide", H=10, W=2050, R=2, p=3, k=18, seed=6, per_region=30)
+    masks, _, _ = oracle.full_masks(w)
+    st = _full_image_sampled(ctx, w, masks, 600, 22)
+    assert st == {"rescaled_chunks": 0, "overflow_tiles": 0, "exact_tiles": 0}
+
+
+@pytest.mark.parametrize("k", [123, 124, 125, 126])
+def test_loglik_feature_width_boundary(ctx, k):
+    """k + 4 features (the mask bits, two |B| and two |A| features) fill one
+    128-wide FP8 step up to k = 124 and take two from k = 125."""
+    w = make_workload(f"kb{k}", H=18, W=27, R=3, p=5, k=k, seed=k, per_region=8)
+    masks, _, _ = oracle.full_masks(w)
+    got, ref = _loglik_both(ctx, w, masks)
+    _ll_check(got, ref)
