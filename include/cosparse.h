@@ -125,14 +125,19 @@ int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask
  * analysed vectors (as cs_analyze_patches), tau = frac * median{|a|} selected
  * exactly on the device (as cs_tau_median), and the masks at that tau (as
  * cs_cosupport with alpha).  Results equal those of the three calls bit for
- * bit.  The call only enqueues work; tau stays on the device.  The context
- * reserves 16 bytes of device memory per entry (N*k) for the candidates of
- * the exact selection, so that their count never needs the host.
+ * bit.  The call only enqueues work; tau stays on the device.  With FP32 and
+ * the proven margin (margin < 0) the masks are decided in the pass that
+ * gathers the candidates of the exact median: an entry clear of the interval
+ * that tau is known to lie in by then is decided at once, the few others once
+ * tau is selected.  The context reserves device memory for lists that could
+ * hold every entry (24 bytes per entry of N*k; 16 bytes in the other forms),
+ * so that their lengths never need the host.
  *   alpha    device out, N*k float32, 16-byte aligned
  *   masks    device out, N*ceil(k/64) uint64
  *   tau_dev  device out (one double) or NULL: tau, written in stream order.
  *            NaN if the exact median fell outside the candidate window (the
- *            error bound would have been violated; the masks are then 0).
+ *            error bound would have been violated; the masks are then not
+ *            meaningful).
  * Errors: as cs_analyze_patches, plus CS_ERR_ARG for frac < 0 or NaN, a
  * non-finite margin, null or misaligned alpha, null masks.
  */

@@ -351,7 +351,7 @@ int median_source(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
 // gather and the exact stage run again (a retry with a larger cap).
 int tau_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, const float *omega, int k, const float *a32,
               double frac, int64_t cap, bool first, unsigned int *hist, TauState *st, double *mmax,
-              double *tau_out) {
+              unsigned long long *parts, double *tau_out) {
     const LaunchCtx lc = lc_of(ctx);
     const int64_t count = (int64_t)H * W * k;
     const int n = p * p;
@@ -362,25 +362,26 @@ int tau_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, const float *o
     {
         Timed t(ctx, "tau_select");
         if (first) {
-            HIP_TRY(tau_select_float(lc, a32, count, hist, st, omega, k, n, margin_coef(CS_FP32, n), mmax));
+            HIP_TRY(tau_select_float(lc, a32, count, hist, st, omega, k, n, margin_coef(CS_FP32, n), mmax, nullptr));
         } else {
             HIP_TRY(tau_reset_gather(lc, st));
         }
-        HIP_TRY(tau_gather(lc, a32, count, mmax, st, cand, cap));
+        HIP_TRY(tau_gather(lc, a32, count, mmax, st, cand, cap, parts));
     }
     {
         Timed t(ctx, "tau_exact");
-        HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, cap, vals, frac, st, tau_out));
+        HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, cap, vals, frac, st, parts, tau_out));
     }
     return CS_OK;
 }
 
 struct TauWs {
-    size_t o_hist, o_st, o_max;
+    size_t o_hist, o_st, o_max, o_parts;
     void carve(Carve &cv) {
         o_hist = cv.take(sizeof(unsigned int) * 2048);
         o_st = cv.take(sizeof(TauState));
         o_max = cv.take(sizeof(double));
+        o_parts = cv.take(sizeof(unsigned long long) * kTauParts);
     }
 };
 
@@ -447,7 +448,8 @@ int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
     int64_t cap = (int64_t)std::min<int64_t>(count, (int64_t)1 << 20);
     TauState hs;
     for (int attempt = 0;; ++attempt) {
-        if ((rc = tau_stage(ctx, rgb, H, W, p, omega, k, a32, frac, cap, attempt == 0, hist, st, mmax, nullptr)))
+        if ((rc = tau_stage(ctx, rgb, H, W, p, omega, k, a32, frac, cap, attempt == 0, hist, st, mmax,
+                            (unsigned long long *)(ctx->ws + tw.o_parts), nullptr)))
             return rc;
         HIP_TRY(hipMemcpyAsync(ctx->pinned, st, sizeof(TauState), hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -476,6 +478,47 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     const int64_t count = (int64_t)H * W * k;
     if ((rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha))) return rc;
+    if (precision == CS_FP32 && margin < 0.0) {
+        // the masks are decided in the candidate gather of the median: four
+        // passes over alpha instead of five
+        const int n = p * p;
+        const LaunchCtx lc = lc_of(ctx);
+        Carve cv;
+        TauWs tw;
+        tw.carve(cv);
+        const size_t o_marg = cv.take(sizeof(double) * k);
+        if ((rc = ensure_ws(ctx, cv.off))) return rc;
+        // candidates, their FP64 values, listed mask entries (room for all)
+        if ((rc = ensure_cand(ctx, (size_t)count * 24))) return rc;
+        TauState *st = (TauState *)(ctx->ws + tw.o_st);
+        unsigned int *hist = (unsigned int *)(ctx->ws + tw.o_hist);
+        double *mmax = (double *)(ctx->ws + tw.o_max);
+        unsigned long long *parts = (unsigned long long *)(ctx->ws + tw.o_parts);
+        double *marg = (double *)(ctx->ws + o_marg);
+        int64_t *cand = (int64_t *)ctx->cand;
+        double *vals = (double *)(ctx->cand + (size_t)count * 8);
+        int64_t *didx = (int64_t *)(ctx->cand + (size_t)count * 16);
+        {
+            Timed t(ctx, "tau_select");
+            HIP_TRY(tau_select_float(lc, alpha, count, hist, st, omega, k, n, margin_coef(CS_FP32, n), mmax, marg));
+        }
+        {
+            Timed t(ctx, "cosupport");
+            HIP_TRY(median_mask_gather(lc, alpha, (int64_t)H * W, k, mmax, marg, frac, st, cand, count, parts, didx,
+                                       masks));
+        }
+        {
+            Timed t(ctx, "tau_exact");
+            HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, count, vals, frac, st, parts,
+                               tau_dev));
+        }
+        {
+            // the second list reuses the candidate array (the selection is done)
+            Timed t(ctx, "cosupport_fix");
+            HIP_TRY(median_mask_finish(lc, alpha, rgb, H, W, p, ctx->wmask, omega, k, didx, marg, st, cand, masks));
+        }
+        return CS_OK;
+    }
     const float *a32 = nullptr;
     if ((rc = median_source(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha, &a32))) return rc;
     Carve cv;
@@ -487,7 +530,7 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
     TauState *st = (TauState *)(ctx->ws + tw.o_st);
     // room for every entry: the selection never needs the host
     rc = tau_stage(ctx, rgb, H, W, p, omega, k, a32, frac, count, true, (unsigned int *)(ctx->ws + tw.o_hist), st,
-                   (double *)(ctx->ws + tw.o_max), tau_dev);
+                   (double *)(ctx->ws + tw.o_max), (unsigned long long *)(ctx->ws + tw.o_parts), tau_dev);
     if (rc) return rc;
     rc = cosupport_stage(ctx, rgb, H, W, p, omega, k, precision, alpha, 0.0, &st->tau, margin, masks,
                          (unsigned long long *)(ctx->ws + cw.o_cnt), (double *)(ctx->ws + cw.o_max),

@@ -73,27 +73,56 @@ struct TauState {
     unsigned long long rank0;     // target rank floor((count-1)/2)
     unsigned long long rank;      // remaining rank inside the current prefix
     unsigned int prefix;          // float bits selected so far
-    unsigned int pad0;
-    unsigned long long below;     // entries strictly below the candidate window
+    unsigned int nparts;          // per-workgroup counts of entries below the window
+    unsigned long long below;     // their sum (written by the selection)
     unsigned long long ncand;     // candidates found (may exceed capacity)
     double lo, hi;                // candidate window on |alpha| (float values)
     double median;                // exact FP64 median
     double tau;                   // frac * median
+    unsigned long long n_d;       // deferred mask entries (fused co-support pass)
+    unsigned long long n_r;       // deferred entries for the FP64 decision
 };
+// Upper bound of the workgroups of a candidate gather (per-workgroup counts).
+constexpr int kTauParts = 4096;
 // Radix select of the float |alpha| of the target rank; the first kernel also
-// writes the largest per-row error bound (coef) of the rows of omega.
+// writes the largest per-row error bound (coef) of the rows of omega, and the
+// per-row bounds to margins when non-null.
 hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t count,
                             unsigned int *hist, TauState *st, const float *omega, int k, int n,
-                            double coef, double *max_margin);
+                            double coef, double *max_margin, double *margins);
 hipError_t tau_reset_gather(const LaunchCtx &lc, TauState *st);
+// The state reset, the row bounds and the first (11-bit) digit only.
+hipError_t tau_first_digit(const LaunchCtx &lc, const float *alpha, int64_t count, unsigned int *hist,
+                           TauState *st, const float *omega, int k, int n, double coef, double *max_margin,
+                           double *margins);
+// Pick the digit at `shift` holding the remaining rank; clears the histogram.
+hipError_t tau_pick(const LaunchCtx &lc, unsigned int *hist, int shift, TauState *st);
+// Candidates of the window around the selected float; parts (kTauParts
+// entries) receives per-workgroup counts of the entries below the window.
 hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
-                      const double *max_margin, TauState *st, int64_t *cand, int64_t cap);
+                      const double *max_margin, TauState *st, int64_t *cand, int64_t cap,
+                      unsigned long long *parts);
 // FP64 recompute of the candidates and the exact selection; the candidate
 // count is read on the device (at most cap are used; more leaves NaN).  tau
 // also goes to tau_out (device) when non-null.
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
-                      int64_t cap, double *vals, double frac, TauState *st, double *tau_out);
+                      int64_t cap, double *vals, double frac, TauState *st, const unsigned long long *parts,
+                      double *tau_out);
+
+// ---- co-support at frac * median|a| fused with the candidate gather
+// (k_cosupport_median.hip) ----
+// After the three digits: the candidate window and the masks of every entry
+// whose rounded |a| is clear of the tau interval by more than its row margin;
+// the others are listed in didx (room for N*k).
+hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N, int k,
+                              const double *max_margin, const double *margins, double frac, TauState *st,
+                              int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
+                              uint64_t *masks);
+// After the exact tau: the listed entries (ridx: room for N*k indices).
+hipError_t median_mask_finish(const LaunchCtx &lc, const float *alpha, const float *rgb, int H, int W, int p,
+                              const double *wmask, const float *omega, int k, const int64_t *didx,
+                              const double *margins, TauState *st, int64_t *ridx, uint64_t *masks);
 
 // ---- texture similarity (k_tsm.hip) ----
 hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const uint64_t *B,

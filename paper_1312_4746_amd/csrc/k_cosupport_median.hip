@@ -1,0 +1,264 @@
+// Co-support masks at tau = frac * median|a| with the mask decision fused
+// into the candidate gather of the exact median (Sec. 2 co-support of a
+// thresholded analysed vector; the threshold is a fixed fraction of the
+// median magnitude).
+//
+// The separate path reads the N*k analysed vectors five times: three radix
+// digits, the candidate gather and then the masks at the exact tau.  Here the
+// gather pass decides the masks as well.  After the three digits the float
+// median v of the rounded |a| is known, and the exact median lies in
+// [v - m, v + m] (m the largest proven rounding bound), so tau lies in a short
+// interval.  Every entry whose rounded |a| is clear of that interval by more
+// than its row's margin is decided in the gather pass; the few others are
+// listed and decided against the exact tau once it is selected, in FP64 where
+// the rounded value is within the margin.  Masks and tau equal those of the
+// separate path bit for bit.  The lists have room for every entry, so nothing
+// depends on a host round trip.
+#pragma clang fp contract(off)
+
+#include "cs_internal.h"
+#include "cs_device.h"
+
+namespace cs {
+
+namespace {
+constexpr int kPx = 8;  // pixels per wave and round in the pixel-major pass
+
+// Reserve slots for the lanes set in m (one atomic per wave), return the slot
+// of this lane (meaningful where its bit is set).
+__device__ __forceinline__ unsigned long long wave_slot(unsigned long long m, unsigned long long *counter,
+                                                        int lane) {
+    const int first = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == first) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+    base = __shfl(base, first);
+    return base + __popcll(m & ((1ull << lane) - 1ull));
+}
+}  // namespace
+
+// The gather pass.  A persistent grid; each wave takes rounds of kPx
+// consecutive pixels, lane = row within a 64-bit mask word.  Per workgroup the
+// count of entries below the candidate window goes to parts[blockIdx.x].
+template <int W64>
+__global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, int64_t N, int k,
+                                                            const double *max_margin, const double *margins,
+                                                            double frac, TauState *st, int64_t *cand, int64_t cap,
+                                                            unsigned long long *parts, int64_t *didx,
+                                                            uint64_t *masks) {
+    __shared__ unsigned long long red[256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // candidate window [v - 2m, v + 2m] as float bit patterns (non-negative
+    // floats order like their bit patterns), as in the separate gather
+    const double v = (double)__uint_as_float(st->prefix);
+    const double mm = *max_margin;
+    const double wlo = v - 2.0 * mm, whi = v + 2.0 * mm;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->lo = wlo;
+        st->hi = whi;
+    }
+    float flo = (float)wlo, fhi = (float)whi;
+    if ((double)flo < wlo) flo = nextafterf(flo, INFINITY);
+    if ((double)fhi > whi) fhi = nextafterf(fhi, -INFINITY);
+    const uint32_t blo = wlo <= 0.0 ? 0u : __float_as_uint(flo);
+    const uint32_t bhi = __float_as_uint(fhi);
+    // tau = fl(frac * median) is monotone in the median, which lies in
+    // [v - m, v + m]; both ends are widened by the rounding of the bounds
+    double mlo = v - mm;
+    mlo = mlo > 0.0 ? nextafter(mlo, 0.0) : 0.0;
+    const double mhi = nextafter(v + mm, INFINITY);
+    const double tlo = mlo > 0.0 ? nextafter(frac * mlo, 0.0) : 0.0;
+    const double thi = nextafter(frac * mhi, INFINITY);
+    float tin[W64], tout[W64];
+    uint64_t vmask[W64];
+#pragma unroll
+    for (int w = 0; w < W64; ++w) {
+        const int j = 64 * w + lane;
+        const bool jv = j < k;
+        const double m = jv ? margins[j] : 0.0;
+        const double a = tlo - m, b = thi + m;
+        float fa = (float)a;
+        if ((double)fa > a) fa = nextafterf(fa, -INFINITY);
+        float fb = (float)b;
+        if ((double)fb < b) fb = nextafterf(fb, INFINITY);
+        tin[w] = fa;
+        tout[w] = fb;
+        vmask[w] = __ballot(jv);
+    }
+    unsigned long long below = 0;
+    const int64_t nrounds = (N + kPx - 1) / kPx;
+    for (int64_t rd = (int64_t)blockIdx.x * 4 + wave; rd < nrounds; rd += (int64_t)gridDim.x * 4) {
+        const int64_t p0 = rd * kPx;
+        uint32_t key[kPx][W64];
+#pragma unroll
+        for (int i = 0; i < kPx; ++i)
+#pragma unroll
+            for (int w = 0; w < W64; ++w) {
+                const int j = 64 * w + lane;
+                const int64_t pix = p0 + i;
+                key[i][w] = (j < k && pix < N) ? (__float_as_uint(alpha[pix * k + j]) & 0x7FFFFFFFu) : 0x7F800000u;
+            }
+        uint64_t words[kPx][W64];
+#pragma unroll
+        for (int i = 0; i < kPx; ++i)
+#pragma unroll
+            for (int w = 0; w < W64; ++w) {
+                const bool live = ((vmask[w] >> lane) & 1ull) && p0 + i < N;
+                const uint32_t x = key[i][w];
+                below += (live && x < blo) ? 1ull : 0ull;
+                const bool is_cand = live && x >= blo && x <= bhi;
+                const unsigned long long cm = __ballot(is_cand);
+                if (cm) {
+                    const unsigned long long slot = wave_slot(cm, &st->ncand, lane);
+                    if (is_cand && (int64_t)slot < cap) cand[slot] = (p0 + i) * k + 64 * w + lane;
+                }
+                const float f = __uint_as_float(x);
+                const uint64_t inb = __ballot(f <= tin[w]);
+                const uint64_t outb = __ballot(f > tout[w]);
+                words[i][w] = inb & vmask[w];
+                const bool defer = live && !(f <= tin[w]) && !(f > tout[w]);  // NaN: deferred
+                const unsigned long long dm = __ballot(defer);
+                if (dm) {
+                    const unsigned long long slot = wave_slot(dm, &st->n_d, lane);
+                    if (defer) didx[slot] = (p0 + i) * k + 64 * w + lane;
+                }
+            }
+        // lane l < kPx * W64 stores word (l / W64, l % W64)
+        const int li = lane / W64, lw = lane - li * W64;
+        uint64_t outw = 0;
+#pragma unroll
+        for (int i = 0; i < kPx; ++i)
+#pragma unroll
+            for (int w = 0; w < W64; ++w)
+                if (li == i && lw == w) outw = words[i][w];
+        if (lane < kPx * W64 && p0 + li < N) masks[(p0 + li) * W64 + lw] = outw;
+    }
+    red[threadIdx.x] = below;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->nparts = gridDim.x;
+}
+
+// Listed entries against the exact tau: decided by the rounded value where it
+// is clear of tau by more than the row margin, else listed again for the FP64
+// decision.
+__global__ __launch_bounds__(256) void k_median_mask_fix(const float *alpha, int k, const int64_t *didx,
+                                                         const double *margins, TauState *st, int64_t *ridx,
+                                                         uint64_t *masks) {
+    const int64_t n = (int64_t)st->n_d;
+    const double tau = st->tau;
+    const int W64 = (k + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t nr = (n + 255) / 256 * 256;  // whole waves take the ballot together
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nr; q += stride) {
+        const bool live = q < n;
+        int64_t e = 0;
+        bool near = false;
+        if (live) {
+            e = didx[q];
+            const int64_t pix = e / k;
+            const int j = (int)(e - pix * k);
+            const double a = (double)fabsf(alpha[e]);
+            const double m = margins[j];
+            if (a <= tau - m) {
+                atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * W64 + (j >> 6)), 1ull << (j & 63));
+            } else if (!(a > tau + m)) {
+                near = true;  // within the margin, or NaN
+            }
+        }
+        const unsigned long long mb = __ballot(near);
+        if (mb) {
+            const unsigned long long slot = wave_slot(mb, &st->n_r, lane);
+            if (near) ridx[slot] = e;
+        }
+    }
+}
+
+// FP64 decision of the entries listed again, one wave per entry: the exact
+// patch in LDS (element-wise steps across lanes, every sum in lane 0 in t
+// order), then the row product in lane 0.
+__global__ __launch_bounds__(64) void k_median_mask_exact(const float *rgb, int H, int W, int p,
+                                                          const double *wmask, const float *omega, int k,
+                                                          const int64_t *ridx, const TauState *st,
+                                                          uint64_t *masks) {
+    __shared__ double s[15 * 15];
+    __shared__ double sh_mu, sh_nu2;
+    const int64_t nr = (int64_t)st->n_r;
+    const double tau = st->tau;
+    const int n = p * p, h = (p - 1) / 2;
+    const int64_t N = (int64_t)H * W;
+    const int W64 = (k + 63) / 64;
+    const int lane = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < nr; c += gridDim.x) {
+        const int64_t e = ridx[c];
+        const int64_t pix = e / k;
+        const int j = (int)(e - pix * k);
+        const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
+        for (int t = lane; t < n; t += 64) {
+            const int u = t / p, vv = t - u * p;
+            const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + vv - h, W);
+            s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
+        }
+        __syncthreads();
+        if (lane == 0) {
+            double sum = 0.0;
+            for (int t = 0; t < n; ++t) sum = sum + s[t];
+            sh_mu = sum / (double)n;
+        }
+        __syncthreads();
+        const double mu = sh_mu;
+        for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
+        __syncthreads();
+        if (lane == 0) {
+            double nu2 = 0.0;
+            for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
+            sh_nu2 = nu2;
+        }
+        __syncthreads();
+        const double nu2 = sh_nu2;
+        const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
+        for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / nu;
+        __syncthreads();
+        if (lane == 0 && fabs(dot64(omega + (int64_t)j * n, s, n)) <= tau)
+            atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * W64 + (j >> 6)), 1ull << (j & 63));
+        __syncthreads();  // s is rewritten by the next entry
+    }
+}
+
+hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N, int k,
+                              const double *max_margin, const double *margins, double frac, TauState *st,
+                              int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
+                              uint64_t *masks) {
+    if (N <= 0) return hipSuccess;
+    int64_t blocks = (N + 4 * kPx - 1) / (4 * kPx);
+    int64_t bcap = (int64_t)lc.num_cu * 4;
+    if (bcap > kTauParts) bcap = kTauParts;
+    if (blocks > bcap) blocks = bcap;
+#define CS_MG_LAUNCH(WW)                                                                                    \
+    hipLaunchKernelGGL(k_median_mask_gather<WW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, N, \
+                       k, max_margin, margins, frac, st, cand, cap, parts, didx, masks)
+    switch ((k + 63) / 64) {
+        case 1: CS_MG_LAUNCH(1); break;
+        case 2: CS_MG_LAUNCH(2); break;
+        case 3: CS_MG_LAUNCH(3); break;
+        default: CS_MG_LAUNCH(4); break;
+    }
+#undef CS_MG_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t median_mask_finish(const LaunchCtx &lc, const float *alpha, const float *rgb, int H, int W, int p,
+                              const double *wmask, const float *omega, int k, const int64_t *didx,
+                              const double *margins, TauState *st, int64_t *ridx, uint64_t *masks) {
+    hipLaunchKernelGGL(k_median_mask_fix, dim3((unsigned)lc.num_cu), dim3(256), 0, lc.stream, alpha, k, didx,
+                       margins, st, ridx, masks);
+    hipLaunchKernelGGL(k_median_mask_exact, dim3((unsigned)lc.num_cu * 8), dim3(64), 0, lc.stream, rgb, H, W, p,
+                       wmask, omega, k, ridx, st, masks);
+    return hipGetLastError();
+}
+
+}  // namespace cs

@@ -28,9 +28,10 @@ constexpr int kHistBins = 2048;
 // per-row error bound (the half-width of the candidate window).
 __global__ __launch_bounds__(256) void k_tau_init(TauState *st, unsigned long long rank0,
                                                    unsigned int *hist, const float *omega, int k, int n,
-                                                   double coef, double *max_margin) {
+                                                   double coef, double *max_margin, double *margins) {
     __shared__ double red[256];
     red[threadIdx.x] = (int)threadIdx.x < k ? row_margin(omega, threadIdx.x, n, -1.0, coef) : 0.0;
+    if (margins && (int)threadIdx.x < k) margins[threadIdx.x] = red[threadIdx.x];
     __syncthreads();
     for (int s2 = 128; s2 > 0; s2 >>= 1) {
         if ((int)threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
@@ -41,8 +42,10 @@ __global__ __launch_bounds__(256) void k_tau_init(TauState *st, unsigned long lo
         st->rank0 = rank0;
         st->rank = rank0;
         st->prefix = 0;
-        st->below = 0;
+        st->nparts = 0;
         st->ncand = 0;
+        st->n_d = 0;
+        st->n_r = 0;
         st->lo = st->hi = 0.0;
         st->median = 0.0;
         st->tau = 0.0;
@@ -139,33 +142,47 @@ __global__ __launch_bounds__(256) void k_tau_pick(unsigned int *hist, int shift,
     for (int i = 0; i < per; ++i) hist[t * per + i] = 0;
 }
 
+hipError_t tau_pick(const LaunchCtx &lc, unsigned int *hist, int shift, TauState *st) {
+    hipLaunchKernelGGL(k_tau_pick, dim3(1), dim3(256), 0, lc.stream, hist, shift, st);
+    return hipGetLastError();
+}
+
+namespace {
+unsigned hist_blocks(const LaunchCtx &lc, int64_t count, int per_cu) {
+    int64_t b = (count / 4 + 255) / 256;
+    const int64_t cap = (int64_t)lc.num_cu * per_cu;
+    if (b > cap) b = cap;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+}  // namespace
+
+hipError_t tau_first_digit(const LaunchCtx &lc, const float *alpha, int64_t count, unsigned int *hist,
+                           TauState *st, const float *omega, int k, int n, double coef, double *max_margin,
+                           double *margins) {
+    hipLaunchKernelGGL(k_tau_init, dim3(1), dim3(256), 0, lc.stream, st,
+                       (unsigned long long)((count - 1) / 2), hist, omega, k, n, coef, max_margin, margins);
+    hipLaunchKernelGGL(k_tau_hist<8>, dim3(hist_blocks(lc, count, 2)), dim3(256), 0, lc.stream, alpha, count, 21,
+                       0u, st, hist);
+    return tau_pick(lc, hist, 21, st);
+}
+
 hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t count,
                             unsigned int *hist, TauState *st, const float *omega, int k, int n,
-                            double coef, double *max_margin) {
-    hipLaunchKernelGGL(k_tau_init, dim3(1), dim3(256), 0, lc.stream, st,
-                       (unsigned long long)((count - 1) / 2), hist, omega, k, n, coef, max_margin);
-    const int shifts[3] = {21, 10, 0};
-    const unsigned int pmasks[3] = {0u, 0xFFE00000u, 0xFFFFFC00u};
-    auto blocks_for = [&](int per_cu) {
-        int64_t b = (count / 4 + 255) / 256;
-        const int64_t cap = (int64_t)lc.num_cu * per_cu;
-        if (b > cap) b = cap;
-        return (unsigned)(b < 1 ? 1 : b);
-    };
-    for (int pass = 0; pass < 3; ++pass) {
-        if (pass == 0)
-            hipLaunchKernelGGL(k_tau_hist<8>, dim3(blocks_for(2)), dim3(256), 0, lc.stream, alpha, count,
-                               shifts[pass], pmasks[pass], st, hist);
-        else
-            hipLaunchKernelGGL(k_tau_hist<1>, dim3(blocks_for(4)), dim3(256), 0, lc.stream, alpha, count,
-                               shifts[pass], pmasks[pass], st, hist);
-        hipLaunchKernelGGL(k_tau_pick, dim3(1), dim3(256), 0, lc.stream, hist, shifts[pass], st);
+                            double coef, double *max_margin, double *margins) {
+    hipError_t e = tau_first_digit(lc, alpha, count, hist, st, omega, k, n, coef, max_margin, margins);
+    if (e != hipSuccess) return e;
+    const int shifts[2] = {10, 0};
+    const unsigned int pmasks[2] = {0xFFE00000u, 0xFFFFFC00u};
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_tau_hist<1>, dim3(hist_blocks(lc, count, 1)), dim3(256), 0, lc.stream, alpha, count,
+                           shifts[pass], pmasks[pass], st, hist);
+        if ((e = tau_pick(lc, hist, shifts[pass], st)) != hipSuccess) return e;
     }
     return hipGetLastError();
 }
 
 __global__ void k_tau_reset(TauState *st) {
-    st->below = 0;
+    st->nparts = 0;
     st->ncand = 0;
 }
 
@@ -176,7 +193,7 @@ hipError_t tau_reset_gather(const LaunchCtx &lc, TauState *st) {
 
 __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t count,
                                                      const double *max_margin, TauState *st,
-                                                     int64_t *cand, int64_t cap) {
+                                                     int64_t *cand, int64_t cap, unsigned long long *parts) {
     __shared__ unsigned long long red[256];
     // The three digit passes left the selected float's bit pattern in prefix.
     const double v = (double)__uint_as_float(st->prefix);
@@ -251,17 +268,20 @@ __global__ __launch_bounds__(256) void k_tau_gather(const float *alpha, int64_t 
         if (threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && red[0]) atomicAdd(&st->below, red[0]);
+    if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->nparts = gridDim.x;
 }
 
 hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
-                      const double *max_margin, TauState *st, int64_t *cand, int64_t cap) {
+                      const double *max_margin, TauState *st, int64_t *cand, int64_t cap,
+                      unsigned long long *parts) {
     int64_t blocks = (count / 4 + 256) / 256;
-    const int64_t bcap = (int64_t)lc.num_cu * 4;
+    int64_t bcap = (int64_t)lc.num_cu * 4;
+    if (bcap > kTauParts) bcap = kTauParts;
     if (blocks > bcap) blocks = bcap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_tau_gather, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, count,
-                       max_margin, st, cand, cap);
+                       max_margin, st, cand, cap, parts);
     return hipGetLastError();
 }
 
@@ -328,13 +348,21 @@ __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, i
 // differ are common to all candidates and skipped; the remaining digits are
 // selected 8 bits at a time with an LDS histogram and a one-wave scan.
 __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t cap, double frac,
-                                                      TauState *st, double *tau_out) {
+                                                      TauState *st, const unsigned long long *parts,
+                                                      double *tau_out) {
     __shared__ unsigned int hist[256];
-    __shared__ unsigned long long s_min, s_max, s_prefix, s_rank;
-    __shared__ int s_ok;
+    __shared__ unsigned long long s_min, s_max, s_prefix, s_rank, s_below;
     const int tid = threadIdx.x;
+    // entries below the candidate window: the gather's per-workgroup counts
+    if (tid == 0) s_below = 0;
+    __syncthreads();
+    unsigned long long pb = 0;
+    for (int i = tid; i < (int)st->nparts; i += 1024) pb += parts[i];
+    if (pb) atomicAdd(&s_below, pb);
+    __syncthreads();
     const unsigned long long nc = st->ncand;
-    const unsigned long long r0 = st->rank0, below = st->below;
+    const unsigned long long r0 = st->rank0, below = s_below;
+    if (tid == 0) st->below = below;
     const bool ok = nc <= (unsigned long long)cap && r0 >= below && r0 - below < nc;
     if (!ok) {
         if (tid == 0) {
@@ -425,14 +453,15 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
 
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
-                      int64_t cap, double *vals, double frac, TauState *st, double *tau_out) {
+                      int64_t cap, double *vals, double frac, TauState *st, const unsigned long long *parts,
+                      double *tau_out) {
     (void)n;
     int64_t blocks = (int64_t)lc.num_cu * 16;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_tau_recompute, dim3((unsigned)blocks), dim3(64), 0, lc.stream, rgb, H, W, p, wmask, omega,
                        k, cand, st, cap, vals);
-    hipLaunchKernelGGL(k_tau_select, dim3(1), dim3(1024), 0, lc.stream, vals, cap, frac, st, tau_out);
+    hipLaunchKernelGGL(k_tau_select, dim3(1), dim3(1024), 0, lc.stream, vals, cap, frac, st, parts, tau_out);
     return hipGetLastError();
 }
 
