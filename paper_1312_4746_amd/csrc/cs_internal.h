@@ -83,7 +83,7 @@ struct TauState {
     unsigned long long n_r;       // deferred entries for the FP64 decision
 };
 // Upper bound of the workgroups of a candidate gather (per-workgroup counts).
-constexpr int kTauParts = 4096;
+constexpr int kTauParts = 1 << 16;
 // Radix select of the float |alpha| of the target rank; the first kernel also
 // writes the largest per-row error bound (coef) of the rows of omega, and the
 // per-row bounds to margins when non-null.

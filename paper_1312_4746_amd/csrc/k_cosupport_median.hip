@@ -36,8 +36,9 @@ __device__ __forceinline__ unsigned long long wave_slot(unsigned long long m, un
 }
 }  // namespace
 
-// The gather pass.  A persistent grid; each wave takes rounds of kPx
-// consecutive pixels, lane = row within a 64-bit mask word.  Per workgroup the
+// The gather pass.  Each wave takes rounds of kPx consecutive pixels (one
+// round unless the image exceeds the grid), lane = row within a 64-bit mask
+// word.  Per workgroup the
 // count of entries below the candidate window goes to parts[blockIdx.x].
 template <int W64>
 __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, int64_t N, int k,
@@ -234,10 +235,9 @@ hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N
                               int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
                               uint64_t *masks) {
     if (N <= 0) return hipSuccess;
+    // one round per wave where the per-workgroup counts fit, else persistent
     int64_t blocks = (N + 4 * kPx - 1) / (4 * kPx);
-    int64_t bcap = (int64_t)lc.num_cu * 4;
-    if (bcap > kTauParts) bcap = kTauParts;
-    if (blocks > bcap) blocks = bcap;
+    if (blocks > kTauParts) blocks = kTauParts;
 #define CS_MG_LAUNCH(WW)                                                                                    \
     hipLaunchKernelGGL(k_median_mask_gather<WW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, N, \
                        k, max_margin, margins, frac, st, cand, cap, parts, didx, masks)
