@@ -600,6 +600,7 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_feat = fast ? cv.take((size_t)Mpad_max * KP) : 0;
     const size_t o_srec = fast ? cv.take(sizeof(float) * 12 * (size_t)Mpad_max) : 0;
     const size_t o_fix = fast ? cv.take(sizeof(int2) * (size_t)ntiles_pad * L) : 0;
+    const size_t o_pix4 = fast ? cv.take(sizeof(float4) * (size_t)ntiles_pad * kTilePix) : 0;
     const size_t o_meta = cv.take(sizeof(int32_t) * (3 * (size_t)L + 1));
     const size_t o_coef = cv.take(sizeof(float4) * (size_t)L *
                                   (size_t)(fast ? ntiles_pad * kTilePix : npix));
@@ -653,6 +654,8 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         const float cscale = (float)std::sqrt(1.4426950408889634 / (2.0 * prm->sigma_c * prm->sigma_c));
         HIP_TRY(launch_stream_build(lc, recs, k, KP, L, segs, segs.pseg[L], cscale, (uint8_t *)(ctx->ws + o_feat),
                                     (float *)(ctx->ws + o_srec)));
+        HIP_TRY(launch_pixel_tiles(lc, rgb, masks, H, W, k, tiles_x, (int)ntiles, ntiles_pad * kTilePix, cscale,
+                                   (float4 *)(ctx->ws + o_pix4)));
     }
     unsigned int *fcnt = (unsigned int *)(ctx->ws + o_fcnt);
     ParzenArgs pa{};
@@ -703,6 +706,7 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         fa.feat = (const uint8_t *)(ctx->ws + o_feat);
         fa.rec = (const float *)(ctx->ws + o_srec);
         fa.coef = coef;
+        fa.pix4 = (const float4 *)(ctx->ws + o_pix4);
         fa.loglik = loglik;
         fa.work_counter = fcnt;
         fa.fix_count = fcnt + 1;

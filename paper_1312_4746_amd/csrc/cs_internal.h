@@ -183,6 +183,7 @@ struct ParzenFastArgs {
                            // (positions below 2048: the location product is exact)
     const float *rec;      // per chunk of 64 slots: BF16 location pieces (2 x 1 KiB), colours (1 KiB)
     const float4 *coef;    // tiled: [label][group*4 + tile][kTilePix] {nA, nB, -R, K}
+    const float4 *pix4;    // tiled: [group*4 + tile][kTilePix] {scaled r, g, b, |A|}
     float *loglik;
     unsigned int *work_counter;
     unsigned int *fix_count;  // [0] queued (label, tile), [1] rescaled wave-chunks, [2] overflows
@@ -199,6 +200,9 @@ struct ParzenFastArgs {
 hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,
                                const StreamSegs &segs, int64_t Mpad, float cscale, uint8_t *feat, float *rec);
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a);
+// Pixel records of the full-image path (nslots = padded tiles x kTilePix).
+hipError_t launch_pixel_tiles(const LaunchCtx &lc, const float *rgb, const uint64_t *masks, int H, int W, int k,
+                              int tiles_x, int ntiles, int64_t nslots, float cscale, float4 *pix4);
 hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
 
 // ---- learned surrogate (k_mlp.hip) ----

@@ -35,14 +35,14 @@
 // registers), double-buffered: chunk c+1 is in flight while chunk c is
 // computed.
 //
-// Log-sum-exp: every lane keeps its own reference per pixel, starting at the
-// per-pixel value from the coefficient kernel (an achieved exponent plus a
-// margin, capped by the upper bound from the nearest sample distance).  After
-// each chunk a lane sum above 2^64 moves that reference up by a whole power of
-// two (exact rescale).  At the end of the item the 16 lanes that share a pixel
-// (one sample column each) are combined at their largest reference.  An
-// overflowed, non-finite or empty sum queues the (label, tile) for the exact
-// two-pass kernel.
+// Log-sum-exp: each pixel has one reference, shared by the 16 lanes that hold
+// its sample columns, starting at the per-pixel value from the coefficient
+// kernel (an achieved exponent plus a margin, capped by the upper bound from
+// the nearest sample distance).  After each chunk a lane sum above 2^64 moves
+// the reference of that pixel up by a whole power of two, the largest needed
+// by any of its 16 lanes (exact rescale); at the end of the item the 16 lane
+// sums are added.  An overflowed, non-finite or empty sum queues the (label,
+// tile) for the exact two-pass kernel.
 #include <type_traits>
 
 #include "cs_internal.h"
@@ -180,6 +180,40 @@ hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k
 }
 
 
+// Pixel records of the full-image path, tiled like the coefficients
+// ([tile][kTilePix], in-tile index dy * 8 + dx): colours scaled by
+// sqrt(log2(e) / (2 sigma_c^2)) (so that the colour term is minus the squared
+// difference) and the co-support size |A| as a float; zeros outside the image.
+__global__ __launch_bounds__(256) void k_pixel_tiles(const float *rgb, const uint64_t *masks, int H, int W, int k,
+                                                      int tiles_x, int ntiles, int64_t nslots, float cscale,
+                                                      float4 *pix4) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= nslots) return;
+    const int tile = (int)(s / kTilePix), i = (int)(s - (int64_t)tile * kTilePix);
+    const int ty = tile / tiles_x;
+    const int px = (tile - ty * tiles_x) * 8 + (i & 7), py = ty * 2 * kParzenRB + (i >> 3);
+    float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (tile < ntiles && px < W && py < H) {
+        const int64_t N = (int64_t)H * W, pix = (int64_t)py * W + px;
+        const int W64 = (k + 63) / 64;
+        uint32_t cnt = 0;
+        for (int w = 0; w < W64; ++w) {
+            uint64_t m = masks[pix * W64 + w];
+            if (w == W64 - 1 && (k & 63)) m &= (1ull << (k & 63)) - 1ull;
+            cnt += (uint32_t)__popcll(m);
+        }
+        out = make_float4(cscale * rgb[pix], cscale * rgb[N + pix], cscale * rgb[2 * N + pix], (float)cnt);
+    }
+    pix4[s] = out;
+}
+
+hipError_t launch_pixel_tiles(const LaunchCtx &lc, const float *rgb, const uint64_t *masks, int H, int W, int k,
+                              int tiles_x, int ntiles, int64_t nslots, float cscale, float4 *pix4) {
+    hipLaunchKernelGGL(k_pixel_tiles, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, lc.stream, rgb, masks,
+                       H, W, k, tiles_x, ntiles, nslots, cscale, pix4);
+    return hipGetLastError();
+}
+
 // Register budget: four waves per SIMD (128 VGPRs) with one 128-feature MFMA
 // step, two with the wider feature rows.
 template <int KSTEPS>
@@ -195,15 +229,14 @@ void k_parzen_mfma(ParzenFastArgs a) {
     __shared__ __align__(16) uint8_t s_feat1[FEAT_B];
     __shared__ __align__(16) float s_rec0[kRecChunkF];
     __shared__ __align__(16) float s_rec1[kRecChunkF];
+    // each wave's BF16 location operands (read at every step; kept here
+    // rather than in registers, which the kernel has none left of)
+    __shared__ __align__(16) s16x8 s_abf[4][RB][64];
     __shared__ int s_item;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, jl = lane & 15;
-    const int64_t N = (int64_t)a.H * a.W;
     const int W64 = (a.k + 63) / 64;
-    // colours are scaled by sqrt(log2(e) / (2 sigma_c^2)) (samples by the
-    // stream builder), so the colour term is minus the squared difference
-    const float cscale = (float)sqrt(kLog2eF / (2.0 * a.sigma_c * a.sigma_c));
     const uint32_t *mask32 = reinterpret_cast<const uint32_t *>(a.masks);
     const int nitems = a.ngroups * a.L;
     const int64_t coef_label_stride = (int64_t)a.ngroups * 4 * kTilePix;
@@ -254,56 +287,55 @@ void k_parzen_mfma(ParzenFastArgs a) {
         const int x0 = (tile_ok ? tile - ty_t * a.tiles_x : 0) * 8, y0 = ty_t * 2 * RB;
 
         // Async copy of chunk c into a buffer pair.
+        // (The lane's byte offset is rebuilt at every copy: held across the
+        // chunk loop, its 64-bit address would be spilled at the register limit
+        // and reloaded in front of the copies.)
         auto issue = [&](int c, uint8_t *sf, float *sr) {
-            const int64_t s0 = (int64_t)c * kChunkS;
+            int off = tid * 16;
+            __asm__ volatile("" : "+v"(off));
+            const uint8_t *fbase = a.feat + (int64_t)c * FEAT_B;
 #pragma unroll
-            for (int u = 0; u < FEAT_B / 4096; ++u) {
-                const uint8_t *src = a.feat + s0 * KP + u * 4096 + tid * 16;
-                __builtin_amdgcn_global_load_lds(src, (lds_void *)(sf + u * 4096 + wave * 1024), 16, 0, 0);
-            }
+            for (int u = 0; u < FEAT_B / 4096; ++u)
+                __builtin_amdgcn_global_load_lds(fbase + u * 4096 + off, (lds_void *)(sf + u * 4096 + wave * 1024), 16,
+                                                 0, 0);
             if (wave < 3) {
-                const float *src = a.rec + (int64_t)c * kRecChunkF + tid * 4;
-                __builtin_amdgcn_global_load_lds(src, (lds_void *)(sr + wave * 256), 16, 0, 0);
+                const uint8_t *rbase = reinterpret_cast<const uint8_t *>(a.rec) + (int64_t)c * (kRecChunkF * 4);
+                __builtin_amdgcn_global_load_lds(rbase + off, (lds_void *)(sr + wave * 256), 16, 0, 0);
             }
         };
         issue(c0, s_feat0, s_rec0);
 
-        // ---- pixel colours: lane holds pixels (rb, r) -> (x0 + 4(g&1) + r, y0 + 2rb + (g>>1)),
-        // the rows 4g + r of the MFMA result blocks
+        // ---- pixel colours (scaled) and coefficients of this label (log2
+        // units): lane holds pixels (rb, r) -> (x0 + 4(g&1) + r, y0 + 2rb + (g>>1)),
+        // the rows 4g + r of the MFMA result blocks; both arrays are tiled
+        // [tile][kTilePix] with the same in-tile order
+        const float4 *pt = a.pix4 + (int64_t)tile * kTilePix;
+        const float4 *cf = a.coef + (int64_t)lab * coef_label_stride + (int64_t)tile * kTilePix;
         float pr[RB][4], pg[RB][4], pb[RB][4];
-        bool anyvalid = false;
+        float nA[RB][4], nB[RB][4], nR[RB][4];  // location and texture factors, -reference
+        bool anyvalid = false, weak = false;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
+                const int ti = (2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r;
                 const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
                 const bool v = tile_ok && px < a.W && py < a.H;
                 anyvalid |= v;
-                const int64_t pix = v ? (int64_t)py * a.W + px : 0;
-                pr[rb][r] = cscale * a.rgb[pix];
-                pg[rb][r] = cscale * a.rgb[N + pix];
-                pb[rb][r] = cscale * a.rgb[2 * N + pix];
+                const float4 c = pt[ti];
+                pr[rb][r] = c.x;
+                pg[rb][r] = c.y;
+                pb[rb][r] = c.z;
+                const float4 q = cf[ti];
+                nA[rb][r] = q.x;
+                nB[rb][r] = q.y;
+                nR[rb][r] = q.z;
+                // padding samples sit at Q ~ 2^100; a bandwidth wide enough to
+                // reach them (or a non-finite one) goes to the exact kernel
+                weak |= v && !(q.x < -1e-18f);
             }
         bool active = __ballot(anyvalid) != 0ull;  // wave-uniform
         const bool wave_valid = active;
-
-        // ---- per-pixel coefficients of this label (log2 units)
-        const float4 *cf = a.coef + (int64_t)lab * coef_label_stride + (int64_t)tile * kTilePix;
-        float nA[RB][4], nB[RB][4], nR[RB][4];  // location and texture factors, -reference
-        bool weak = false;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float4 v = cf[(2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r];
-                nA[rb][r] = v.x;
-                nB[rb][r] = v.y;
-                nR[rb][r] = v.z;
-                const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
-                // padding samples sit at Q ~ 2^100; a bandwidth wide enough to
-                // reach them (or a non-finite one) goes to the exact kernel
-                weak |= tile_ok && px < a.W && py < a.H && !(v.x < -1e-18f);
-            }
 
         // ---- pixel rows of both MFMAs: row i = lane%16 of row block rb is
         // pixel rb*16 + jl of the tile = (x0 + (jl & 7), y0 + 2rb + (jl >> 3)).
@@ -312,16 +344,15 @@ void k_parzen_mfma(ParzenFastArgs a) {
         // pieces of |p|^2, -2 px and -2 py against the sample pieces (lane
         // groups 0 and 1 hold K 0..7 and 8..15, groups 2 and 3 zeros).
         i32x8 Aop[RB][KSTEPS];
-        s16x8 Abf[RB];
+
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const int dxi = jl & 7, dyi = 2 * rb + (jl >> 3);
             const int px = x0 + dxi, py = y0 + dyi;
             const bool v = tile_ok && px < a.W && py < a.H;
-            const int64_t pix = v ? (int64_t)py * a.W + px : 0;
+            const int pix = v ? py * a.W + px : 0;  // below 2^22 on this path
             const uint32_t *mw = mask32 + pix * 2 * W64;
-            uint32_t cnt = 0;
-            for (int w = 0; w < nw32; ++w) cnt += __popc(mw[w] & (w == nw32 - 1 ? lastmask : ~0u));
+            const uint32_t cnt = (uint32_t)pt[dyi * 8 + dxi].w;
 #pragma unroll
             for (int q = 0; q < KSTEPS; ++q) {
                 const uint32_t m = lowm[q] ? mw[4 * q + g] & lowm[q] : 0u;
@@ -346,8 +377,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
                 for (int t = 0; t < 8; ++t) e[t] = 0.0f;
             }
+            s16x8 ab;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) Abf[rb][t] = bf16_bits(e[t]);
+            for (int t = 0; t < 8; ++t) ab[t] = bf16_bits(e[t]);
+            s_abf[wave][rb][lane] = ab;
         }
         bool item_bad = __ballot(weak) != 0ull;
         if (item_bad) active = false;
@@ -370,6 +403,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
             for (int st = 0; st < kChunkS / 16; ++st) {
                 if (st >= nst) break;
+                // opaque lane index: the operand is read here at every step
+                // instead of being hoisted out of the loop into registers
+                int al = lane;
+                __asm__ volatile("" : "+v"(al));
                 const uint8_t *Fs = F + st * 16 * KP;
                 const uint8_t *Rs = reinterpret_cast<const uint8_t *>(Rr) + st * 256;
                 i32x8 Bop[KSTEPS];
@@ -390,7 +427,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
                     for (int q = 0; q < KSTEPS; ++q)
                         T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(Aop[rb][q], Bop[q], T[rb], 0, 0,
                                                                                   0, 127, 0, 127);
-                    Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Abf[rb]),
+                    Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, s_abf[wave][rb][al]),
                                                                     __builtin_bit_cast(bf16x8, Bbf),
                                                                     f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
                 }
@@ -417,6 +454,9 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) big |= !(S[rb][r] <= 0x1p64f);
             if (__ballot(big)) {
+                // the 16 lanes of a pixel (one sample column each) move
+                // together, by the largest exponent among them, so that the
+                // pixel keeps one reference
                 ++n_rescale;
                 bool over = false;
 #pragma unroll
@@ -424,14 +464,16 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float s = S[rb][r];
+                        int e = 0;
                         if (!(s <= 0x1p64f)) {
-                            if (s <= 3.0e38f) {
-                                const int e = (int)((__float_as_uint(s) >> 23) & 0xFFu) - 127;
-                                S[rb][r] = ldexpf(s, -e);
-                                nR[rb][r] -= (float)e;
-                            } else {
-                                over = true;
-                            }
+                            if (s <= 3.0e38f) e = (int)((__float_as_uint(s) >> 23) & 0xFFu) - 127;
+                            else over = true;
+                        }
+#pragma unroll
+                        for (int off = 1; off < 16; off <<= 1) e = max(e, __shfl_xor(e, off));
+                        if (e > 0) {
+                            S[rb][r] = ldexpf(s, -e);
+                            nR[rb][r] -= (float)e;
                         }
                     }
                 if (__ballot(over)) {
@@ -447,9 +489,9 @@ void k_parzen_mfma(ParzenFastArgs a) {
         }
         if (!wave_valid) continue;
 
-        // ---- end of item: combine the 16 lanes sharing each pixel (one sample
-        // column each) at their largest reference; lane jl < 8 of each 16-lane
-        // group keeps pixel (rb, r) = (jl >> 2, jl & 3) for the write
+        // ---- end of item: sum the 16 lanes sharing each pixel (one sample
+        // column each, one reference); lane jl < 8 of each 16-lane group keeps
+        // pixel (rb, r) = (jl >> 2, jl & 3) for the write
         bool bad = item_bad;
         float Rw = 0.0f, Sw = 1.0f;
         if (!bad) {
@@ -457,11 +499,8 @@ void k_parzen_mfma(ParzenFastArgs a) {
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float Rl = -nR[rb][r];
-                    float Rm = Rl;
-#pragma unroll
-                    for (int off = 1; off < 16; off <<= 1) Rm = fmaxf(Rm, __shfl_xor(Rm, off));
-                    float sp = S[rb][r] * __builtin_amdgcn_exp2f(Rl - Rm);
+                    const float Rm = -nR[rb][r];
+                    float sp = S[rb][r];
 #pragma unroll
                     for (int off = 1; off < 16; off <<= 1) sp += __shfl_xor(sp, off);
                     const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
