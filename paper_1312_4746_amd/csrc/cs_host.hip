@@ -381,7 +381,7 @@ struct TauWs {
         o_hist = cv.take(sizeof(unsigned int) * 2048);
         o_st = cv.take(sizeof(TauState));
         o_max = cv.take(sizeof(double));
-        o_parts = cv.take(sizeof(unsigned long long) * kTauParts);
+        o_parts = cv.take(sizeof(unsigned long long) * (kTauParts + kTauRank));
     }
 };
 
@@ -601,6 +601,8 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_srec = fast ? cv.take(sizeof(float) * 12 * (size_t)Mpad_max) : 0;
     const size_t o_fix = fast ? cv.take(sizeof(int2) * (size_t)ntiles_pad * L) : 0;
     const size_t o_pix4 = fast ? cv.take(sizeof(float4) * (size_t)ntiles_pad * kTilePix) : 0;
+    const size_t o_aop = fast ? cv.take((size_t)ntiles_pad * kParzenRB * (KP / 128) * 64 * 32) : 0;
+    const size_t o_abf = fast ? cv.take((size_t)ntiles_pad * kParzenRB * 64 * 16) : 0;
     const size_t o_meta = cv.take(sizeof(int32_t) * (3 * (size_t)L + 1));
     const size_t o_coef = cv.take(sizeof(float4) * (size_t)L *
                                   (size_t)(fast ? ntiles_pad * kTilePix : npix));
@@ -656,6 +658,8 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
                                     (float *)(ctx->ws + o_srec)));
         HIP_TRY(launch_pixel_tiles(lc, rgb, masks, H, W, k, tiles_x, (int)ntiles, ntiles_pad * kTilePix, cscale,
                                    (float4 *)(ctx->ws + o_pix4)));
+        HIP_TRY(launch_pixel_operands(lc, masks, H, W, k, tiles_x, (int)ntiles, ntiles_pad, KP / 128,
+                                      (uint32_t *)(ctx->ws + o_aop), (uint4 *)(ctx->ws + o_abf)));
     }
     unsigned int *fcnt = (unsigned int *)(ctx->ws + o_fcnt);
     ParzenArgs pa{};
@@ -707,6 +711,8 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         fa.rec = (const float *)(ctx->ws + o_srec);
         fa.coef = coef;
         fa.pix4 = (const float4 *)(ctx->ws + o_pix4);
+        fa.aop = (const uint32_t *)(ctx->ws + o_aop);
+        fa.abf = (const uint8_t *)(ctx->ws + o_abf);
         fa.loglik = loglik;
         fa.work_counter = fcnt;
         fa.fix_count = fcnt + 1;

@@ -82,8 +82,11 @@ struct TauState {
     unsigned long long n_d;       // deferred mask entries (fused co-support pass)
     unsigned long long n_r;       // deferred entries for the FP64 decision
 };
-// Upper bound of the workgroups of a candidate gather (per-workgroup counts).
+// Upper bound of the workgroups of a candidate gather (per-workgroup counts);
+// the counts array is followed by kTauRank words for the ranks of short
+// candidate lists.
 constexpr int kTauParts = 1 << 16;
+constexpr int kTauRank = 1 << 14;
 // Radix select of the float |alpha| of the target rank; the first kernel also
 // writes the largest per-row error bound (coef) of the rows of omega, and the
 // per-row bounds to margins when non-null.
@@ -104,10 +107,11 @@ hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
                       unsigned long long *parts);
 // FP64 recompute of the candidates and the exact selection; the candidate
 // count is read on the device (at most cap are used; more leaves NaN).  tau
-// also goes to tau_out (device) when non-null.
+// also goes to tau_out (device) when non-null.  parts holds kTauParts +
+// kTauRank words.
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
-                      int64_t cap, double *vals, double frac, TauState *st, const unsigned long long *parts,
+                      int64_t cap, double *vals, double frac, TauState *st, unsigned long long *parts,
                       double *tau_out);
 
 // ---- co-support at frac * median|a| fused with the candidate gather
@@ -184,6 +188,8 @@ struct ParzenFastArgs {
     const float *rec;      // per chunk of 64 slots: BF16 location pieces (2 x 1 KiB), colours (1 KiB)
     const float4 *coef;    // tiled: [label][group*4 + tile][kTilePix] {nA, nB, -R, K}
     const float4 *pix4;    // tiled: [group*4 + tile][kTilePix] {scaled r, g, b, |A|}
+    const uint32_t *aop;   // [tile][row block][step][lane][8]: FP8 texture operands
+    const uint8_t *abf;    // [tile][row block][lane][16 B]: BF16 location operands
     float *loglik;
     unsigned int *work_counter;
     unsigned int *fix_count;  // [0] queued (label, tile), [1] rescaled wave-chunks, [2] overflows
@@ -203,6 +209,9 @@ hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a);
 // Pixel records of the full-image path (nslots = padded tiles x kTilePix).
 hipError_t launch_pixel_tiles(const LaunchCtx &lc, const float *rgb, const uint64_t *masks, int H, int W, int k,
                               int tiles_x, int ntiles, int64_t nslots, float cscale, float4 *pix4);
+// MFMA pixel operands of the full-image path (ntiles_pad tiles).
+hipError_t launch_pixel_operands(const LaunchCtx &lc, const uint64_t *masks, int H, int W, int k, int tiles_x,
+                                 int ntiles, int64_t ntiles_pad, int ksteps, uint32_t *aop, uint4 *abf);
 hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
 
 // ---- learned surrogate (k_mlp.hip) ----

@@ -207,6 +207,79 @@ __global__ __launch_bounds__(256) void k_pixel_tiles(const float *rgb, const uin
     pix4[s] = out;
 }
 
+// Pixel operands of the full-image path, built once per call: for every
+// padded tile, row block rb and lane (g, jl) of the MFMA operands, the pixel
+// of row jl is (x0 + (jl & 7), y0 + 2 rb + (jl >> 3)).
+//  * FP8 texture operand (32 B per lane and 128-feature step q): features
+//    32 (4q + g) .. +31, i.e. mask bits j < k, 1 at k and k+1, 16 floor(|A|/16)
+//    at k+2 and |A| mod 16 at k+3 (zero for pixels outside the image);
+//  * BF16 location operand (16 B per lane): K 0..7 [|p|^2 pieces (3), -2 px
+//    pieces (2, each twice), -2 py high] for g = 0, K 8..15 [-2 py high, -2 py
+//    low (twice), 1, 1, 1, 1 (far term), 0] for g = 1, zeros for g >= 2.
+__global__ __launch_bounds__(256) void k_pixel_operands(const uint64_t *masks, int H, int W, int k, int tiles_x,
+                                                         int ntiles, int64_t nthreads, int ksteps, uint32_t *aop,
+                                                         uint4 *abf) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= nthreads) return;
+    const int lane = (int)(s & 63);
+    const int64_t tr = s >> 6;  // tile * RB + rb
+    const int rb = (int)(tr % kParzenRB);
+    const int tile = (int)(tr / kParzenRB);
+    const int g = lane >> 4, jl = lane & 15;
+    const int ty = tile / tiles_x;
+    const int x0 = (tile - ty * tiles_x) * 8, y0 = ty * 2 * kParzenRB;
+    const int px = x0 + (jl & 7), py = y0 + 2 * rb + (jl >> 3);
+    const bool v = tile < ntiles && px < W && py < H;
+    const int W64 = (k + 63) / 64;
+    const uint32_t *mw = reinterpret_cast<const uint32_t *>(masks) + (v ? ((int64_t)py * W + px) * 2 * W64 : 0);
+    const int nw32 = (k + 31) / 32;
+    const uint32_t lastmask = (k & 31) ? (1u << (k & 31)) - 1u : ~0u;
+    uint32_t cnt = 0;
+    if (v)
+        for (int w = 0; w < nw32; ++w) cnt += __popc(mw[w] & (w == nw32 - 1 ? lastmask : ~0u));
+    // features k+2 and k+3 (the pixel's |A|): which lane group, step and byte
+    const int fa = k + 2, fb = k + 3;
+    for (int q = 0; q < ksteps; ++q) {
+        const int wi = 4 * q + g;  // the lane's 32-feature slice is mask word wi
+        const int rel = k - 32 * wi;
+        const uint32_t lowm = wi < nw32 - 1 ? ~0u : wi == nw32 - 1 ? lastmask : 0u;
+        const uint32_t spec = (rel >= 0 && rel < 32 ? 1u << rel : 0u) | (rel + 1 >= 0 && rel + 1 < 32 ? 1u << (rel + 1) : 0u);
+        const uint32_t m = lowm ? mw[wi] & lowm : 0u;
+        const uint32_t ext = v ? (m | spec) : 0u;
+        uint32_t out[8];
+        for (int d = 0; d < 8; ++d) out[d] = nibble_bytes((ext >> (4 * d)) & 0xFu, 0x38u);  // 1.0 per set bit
+        if (v && ((fa >> 5) & 3) == g && (fa >> 7) == q)
+            out[(fa & 31) >> 2] |= fp8_of_int(16u * (cnt >> 4)) << (8 * (fa & 3));
+        if (v && ((fb >> 5) & 3) == g && (fb >> 7) == q)
+            out[(fb & 31) >> 2] |= fp8_of_int(cnt & 15u) << (8 * (fb & 3));
+        uint4 *dst = reinterpret_cast<uint4 *>(aop + (((int64_t)tr * ksteps + q) * 64 + lane) * 8);
+        dst[0] = make_uint4(out[0], out[1], out[2], out[3]);
+        dst[1] = make_uint4(out[4], out[5], out[6], out[7]);
+    }
+    const uint32_t p2 = (uint32_t)(px * px + py * py), X = 2u * (uint32_t)px, Y = 2u * (uint32_t)py;
+    const float xh = -(float)(X & ~0xFFu), xl = -(float)(X & 0xFFu);
+    const float yh = -(float)(Y & ~0xFFu), yl = -(float)(Y & 0xFFu);
+    float e[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (g == 0) {
+        e[0] = (float)(p2 & ~0xFFFFu); e[1] = (float)(p2 & 0xFF00u); e[2] = (float)(p2 & 0xFFu);
+        e[3] = xh; e[4] = xh; e[5] = xl; e[6] = xl; e[7] = yh;
+    } else if (g == 1) {
+        e[0] = yh; e[1] = yl; e[2] = yl; e[3] = 1.0f; e[4] = 1.0f; e[5] = 1.0f; e[6] = 1.0f;
+    }
+    uint32_t pk[4];
+    for (int t = 0; t < 4; ++t)
+        pk[t] = (uint32_t)(uint16_t)bf16_bits(e[2 * t]) | ((uint32_t)(uint16_t)bf16_bits(e[2 * t + 1]) << 16);
+    abf[s] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+}
+
+hipError_t launch_pixel_operands(const LaunchCtx &lc, const uint64_t *masks, int H, int W, int k, int tiles_x,
+                                 int ntiles, int64_t ntiles_pad, int ksteps, uint32_t *aop, uint4 *abf) {
+    const int64_t nthreads = ntiles_pad * kParzenRB * 64;
+    hipLaunchKernelGGL(k_pixel_operands, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, lc.stream, masks, H,
+                       W, k, tiles_x, ntiles, nthreads, ksteps, aop, abf);
+    return hipGetLastError();
+}
+
 hipError_t launch_pixel_tiles(const LaunchCtx &lc, const float *rgb, const uint64_t *masks, int H, int W, int k,
                               int tiles_x, int ntiles, int64_t nslots, float cscale, float4 *pix4) {
     hipLaunchKernelGGL(k_pixel_tiles, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, lc.stream, rgb, masks,
@@ -236,26 +309,8 @@ void k_parzen_mfma(ParzenFastArgs a) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, jl = lane & 15;
-    const int W64 = (a.k + 63) / 64;
-    const uint32_t *mask32 = reinterpret_cast<const uint32_t *>(a.masks);
     const int nitems = a.ngroups * a.L;
     const int64_t coef_label_stride = (int64_t)a.ngroups * 4 * kTilePix;
-    // the lane's 32-feature slice q of the pixel features covers mask word
-    // 4q + g: which of its bits are real mask bits, which are the unit features
-    const int nw32 = (a.k + 31) / 32;
-    const uint32_t lastmask = (a.k & 31) ? (1u << (a.k & 31)) - 1u : ~0u;
-    uint32_t lowm[KSTEPS], spec[KSTEPS];
-#pragma unroll
-    for (int q = 0; q < KSTEPS; ++q) {
-        const int wi = 4 * q + g, rel = a.k - 32 * wi;
-        lowm[q] = wi < nw32 - 1 ? ~0u : wi == nw32 - 1 ? lastmask : 0u;
-        spec[q] = (rel >= 0 && rel < 32 ? 1u << rel : 0u) | (rel + 1 >= 0 && rel + 1 < 32 ? 1u << (rel + 1) : 0u);
-    }
-    // where the pixel's |A| features (k + 2, k + 3) sit: lane group, step, byte
-    const int fa = a.k + 2;
-    const int fa_g = (fa >> 5) & 3, fa_q = fa >> 7, fa_b = fa & 31;
-    const int fb = a.k + 3;
-    const int fb_g = (fb >> 5) & 3, fb_q = fb >> 7, fb_b = fb & 31;
     // LDS byte offsets of the lane's operands in step 0 of a chunk buffer (step
     // st adds st * 16 rows; the swizzle depends on the row only through
     // (row / 2) mod 8, the same for rows jl and 16 st + jl)
@@ -337,50 +392,23 @@ void k_parzen_mfma(ParzenFastArgs a) {
         bool active = __ballot(anyvalid) != 0ull;  // wave-uniform
         const bool wave_valid = active;
 
-        // ---- pixel rows of both MFMAs: row i = lane%16 of row block rb is
-        // pixel rb*16 + jl of the tile = (x0 + (jl & 7), y0 + 2rb + (jl >> 3)).
-        // FP8 operand: the lane's 32-feature slice of the mask bits plus the
-        // unit features at k, k+1 and |A| at k+2, k+3.  BF16 operand: the
-        // pieces of |p|^2, -2 px and -2 py against the sample pieces (lane
-        // groups 0 and 1 hold K 0..7 and 8..15, groups 2 and 3 zeros).
+        // ---- pixel rows of both MFMAs (built once per call by
+        // k_pixel_operands): the FP8 texture operand into registers, the BF16
+        // location operand straight into LDS (read at every step)
         i32x8 Aop[RB][KSTEPS];
-
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            const int dxi = jl & 7, dyi = 2 * rb + (jl >> 3);
-            const int px = x0 + dxi, py = y0 + dyi;
-            const bool v = tile_ok && px < a.W && py < a.H;
-            const int pix = v ? py * a.W + px : 0;  // below 2^22 on this path
-            const uint32_t *mw = mask32 + pix * 2 * W64;
-            const uint32_t cnt = (uint32_t)pt[dyi * 8 + dxi].w;
 #pragma unroll
             for (int q = 0; q < KSTEPS; ++q) {
-                const uint32_t m = lowm[q] ? mw[4 * q + g] & lowm[q] : 0u;
-                const uint32_t ext = v ? (m | spec[q]) : 0u;
-#pragma unroll
-                for (int vv = 0; vv < 8; ++vv) Aop[rb][q][vv] = (int)nibble_bytes((ext >> (4 * vv)) & 0xFu, 0x38u);
-                if (v && g == fa_g && q == fa_q)
-                    Aop[rb][q][fa_b >> 2] |= (int)(fp8_of_int(16u * (cnt >> 4)) << (8 * (fa_b & 3)));
-                if (v && g == fb_g && q == fb_q)
-                    Aop[rb][q][fb_b >> 2] |= (int)(fp8_of_int(cnt & 15u) << (8 * (fb_b & 3)));
+                // 8 dwords (32 bytes) per lane
+                const uint4 *src = reinterpret_cast<const uint4 *>(
+                    a.aop + ((((int64_t)tile * RB + rb) * KSTEPS + q) * 64 + lane) * 8);
+                const uint4 lo4 = src[0], hi4 = src[1];
+                Aop[rb][q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
+                                   (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
             }
-            const uint32_t p2 = (uint32_t)(px * px + py * py), X = 2u * (uint32_t)px, Y = 2u * (uint32_t)py;
-            const float xh = -(float)(X & ~0xFFu), xl = -(float)(X & 0xFFu);
-            const float yh = -(float)(Y & ~0xFFu), yl = -(float)(Y & 0xFFu);
-            float e[8];
-            if (g == 0) {
-                e[0] = (float)(p2 & ~0xFFFFu); e[1] = (float)(p2 & 0xFF00u); e[2] = (float)(p2 & 0xFFu);
-                e[3] = xh; e[4] = xh; e[5] = xl; e[6] = xl; e[7] = yh;
-            } else if (g == 1) {
-                e[0] = yh; e[1] = yl; e[2] = yl; e[3] = 1.0f; e[4] = 1.0f; e[5] = 1.0f; e[6] = 1.0f; e[7] = 0.0f;
-            } else {
-#pragma unroll
-                for (int t = 0; t < 8; ++t) e[t] = 0.0f;
-            }
-            s16x8 ab;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) ab[t] = bf16_bits(e[t]);
-            s_abf[wave][rb][lane] = ab;
+            const uint8_t *bsrc = a.abf + (((int64_t)tile * RB + rb) * 64 + lane) * 16;
+            __builtin_amdgcn_global_load_lds(bsrc, (lds_void *)&s_abf[wave][rb][0], 16, 0, 0);
         }
         bool item_bad = __ballot(weak) != 0ull;
         if (item_bad) active = false;

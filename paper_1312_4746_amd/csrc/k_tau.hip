@@ -342,6 +342,34 @@ __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, i
     }
 }
 
+// Short candidate lists (up to kRankMax): the rank of every candidate by
+// comparison with all of them, one wave per candidate (lanes split the list),
+// stored as (less, equal) for the selection below.  Longer lists are left to
+// its radix select.
+constexpr int kRankMax = kTauRank;
+__global__ __launch_bounds__(64) void k_tau_rank(const double *vals, int64_t cap, const TauState *st,
+                                                  unsigned long long *rk) {
+    const unsigned long long nc = st->ncand;
+    if (nc > (unsigned long long)kRankMax || nc > (unsigned long long)cap) return;
+    const int64_t n = (int64_t)nc;
+    const int lane = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < n; c += gridDim.x) {
+        const unsigned long long key = (unsigned long long)__double_as_longlong(vals[c]);
+        unsigned int less = 0, equal = 0;
+        for (int64_t q = lane; q < n; q += 64) {
+            const unsigned long long o = (unsigned long long)__double_as_longlong(vals[q]);
+            less += o < key ? 1u : 0u;
+            equal += o == key ? 1u : 0u;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            less += __shfl_xor(less, off);
+            equal += __shfl_xor(equal, off);
+        }
+        if (lane == 0) rk[c] = (unsigned long long)less | ((unsigned long long)equal << 32);
+    }
+}
+
 // Single-workgroup radix select of rank (rank0 - below) among the FP64
 // candidate values (non-negative doubles order like their bit patterns).
 // The digits above the highest bit in which the smallest and largest key
@@ -349,7 +377,7 @@ __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, i
 // selected 8 bits at a time with an LDS histogram and a one-wave scan.
 __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t cap, double frac,
                                                       TauState *st, const unsigned long long *parts,
-                                                      double *tau_out) {
+                                                      const unsigned long long *rk, double *tau_out) {
     __shared__ unsigned int hist[256];
     __shared__ unsigned long long s_min, s_max, s_prefix, s_rank, s_below;
     const int tid = threadIdx.x;
@@ -373,6 +401,22 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
         return;
     }
     const int64_t ncand = (int64_t)nc;
+    if (ncand <= kRankMax) {
+        // ranked by k_tau_rank: the candidate whose rank range [less, less +
+        // equal) holds the target (equal keys give the same value)
+        const unsigned long long r = r0 - below;
+        for (int64_t c = tid; c < ncand; c += 1024) {
+            const unsigned long long v = rk[c];
+            const unsigned long long less = v & 0xFFFFFFFFull, equal = v >> 32;
+            if (r >= less && r < less + equal) {
+                const double med = vals[c];
+                st->median = med;
+                st->tau = frac * med;
+                if (tau_out) *tau_out = frac * med;
+            }
+        }
+        return;
+    }
     if (tid == 0) {
         s_min = ~0ull;
         s_max = 0ull;
@@ -453,7 +497,7 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
 
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
-                      int64_t cap, double *vals, double frac, TauState *st, const unsigned long long *parts,
+                      int64_t cap, double *vals, double frac, TauState *st, unsigned long long *parts,
                       double *tau_out) {
     (void)n;
     int64_t blocks = (int64_t)lc.num_cu * 16;
@@ -461,7 +505,9 @@ hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_tau_recompute, dim3((unsigned)blocks), dim3(64), 0, lc.stream, rgb, H, W, p, wmask, omega,
                        k, cand, st, cap, vals);
-    hipLaunchKernelGGL(k_tau_select, dim3(1), dim3(1024), 0, lc.stream, vals, cap, frac, st, parts, tau_out);
+    unsigned long long *rk = parts + kTauParts;  // kRankMax (less, equal) pairs
+    hipLaunchKernelGGL(k_tau_rank, dim3((unsigned)lc.num_cu * 4), dim3(64), 0, lc.stream, vals, cap, st, rk);
+    hipLaunchKernelGGL(k_tau_select, dim3(1), dim3(1024), 0, lc.stream, vals, cap, frac, st, parts, rk, tau_out);
     return hipGetLastError();
 }
 
