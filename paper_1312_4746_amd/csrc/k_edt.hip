@@ -97,22 +97,23 @@ __global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H,
                                                     int32_t *d2, int32_t *nearest) {
     extern __shared__ int32_t lds[];
     const int nb = (W + kRowBlk - 1) / kRowBlk;
-    int32_t *f = lds;            // squared column distance, kInf where the column has no seed
-    int32_t *rowof = lds + W;    // nearest seed row of each column
-    int32_t *fmin = lds + 2 * W; // smallest f over each block of kRowBlk columns
+    // f: squared column distance, kInf where the column has no seed, padded to
+    // whole blocks with kInf (16-byte aligned: blocks are read as int4)
+    int32_t *f = lds;
+    int32_t *rowof = lds + nb * kRowBlk;      // nearest seed row of each column
+    int32_t *fmin = lds + 2 * nb * kRowBlk;   // smallest f over each block
     const int r = blockIdx.x, l = blockIdx.y;
     const int64_t N = (int64_t)H * W;
     const int32_t *cr = colrow + (int64_t)l * N + (int64_t)r * W;
-    for (int c = threadIdx.x; c < W; c += blockDim.x) {
-        const int q = cr[c];
+    for (int c = threadIdx.x; c < nb * kRowBlk; c += blockDim.x) {
+        const int q = c < W ? cr[c] : -1;
         rowof[c] = q;
         f[c] = q < 0 ? kInf : (r - q) * (r - q);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         int m = kInf;
-        const int q1 = min(W, (b + 1) * kRowBlk);
-        for (int q = b * kRowBlk; q < q1; ++q) m = min(m, f[q]);
+        for (int q = b * kRowBlk; q < b * kRowBlk + kRowBlk; ++q) m = min(m, f[q]);
         fmin[b] = m;
     }
     __syncthreads();
@@ -120,16 +121,26 @@ __global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H,
     int32_t *nn = nearest + (int64_t)l * N + (int64_t)r * W;
     for (int c = threadIdx.x; c < W; c += blockDim.x) {
         int best = f[c], bq = c;
-        const int cb = c / kRowBlk;
-        // own block, every column
-        const int o0 = cb * kRowBlk, o1 = min(W, o0 + kRowBlk);
-        for (int q = o0; q < o1; ++q) {
-            const int v = (c - q) * (c - q) + f[q];
-            if (v < best) {
-                best = v;
-                bq = q;
+        // one block of 16 columns: four 16-byte LDS reads, then the 16
+        // candidates in ascending column order (strict improvement, so the
+        // first best column of the walk wins, as in a one-by-one scan)
+        auto scan = [&](int b) {
+            const int4 *f4 = reinterpret_cast<const int4 *>(f + b * kRowBlk);
+            const int4 v0 = f4[0], v1 = f4[1], v2 = f4[2], v3 = f4[3];
+            const int fv[16] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w,
+                                v2.x, v2.y, v2.z, v2.w, v3.x, v3.y, v3.z, v3.w};
+#pragma unroll
+            for (int i = 0; i < kRowBlk; ++i) {
+                const int q = b * kRowBlk + i;
+                const int v = (c - q) * (c - q) + fv[i];
+                if (v < best) {
+                    best = v;
+                    bq = q;
+                }
             }
-        }
+        };
+        const int cb = c / kRowBlk;
+        scan(cb);  // own block, every column
         // blocks outward on both sides; a block is scanned only if its
         // nearest column and smallest f could beat the best so far, and the
         // walk stops once the nearest column of the next blocks is too far
@@ -140,25 +151,8 @@ __global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H,
             const bool lok = bl >= 0 && gl * gl < best;
             const bool rok = br < nb && gr * gr < best;
             if (!lok && !rok) break;
-            if (lok && gl * gl + fmin[bl] < best) {
-                for (int q = bl * kRowBlk; q < bl * kRowBlk + kRowBlk; ++q) {
-                    const int v = (c - q) * (c - q) + f[q];
-                    if (v < best) {
-                        best = v;
-                        bq = q;
-                    }
-                }
-            }
-            if (rok && gr * gr + fmin[br] < best) {
-                const int q1 = min(W, br * kRowBlk + kRowBlk);
-                for (int q = br * kRowBlk; q < q1; ++q) {
-                    const int v = (c - q) * (c - q) + f[q];
-                    if (v < best) {
-                        best = v;
-                        bq = q;
-                    }
-                }
-            }
+            if (lok && gl * gl + fmin[bl] < best) scan(bl);
+            if (rok && gr * gr + fmin[br] < best) scan(br);
         }
         if (best >= kInf) {  // no seed of this label anywhere (rejected before launch)
             dd[c] = -1;
@@ -184,7 +178,8 @@ hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, i
     hipLaunchKernelGGL(k_edt_col_summary, g1, dim3(64), 0, lc.stream, seeds, H, W, nseg, first, last);
     hipLaunchKernelGGL(k_edt_col_fill, g1, dim3(64), 0, lc.stream, seeds, H, W, nseg, first, last,
                        colrow);
-    const size_t lds = sizeof(int32_t) * (2 * (size_t)W + (W + kRowBlk - 1) / kRowBlk);
+    const size_t nbk = (size_t)(W + kRowBlk - 1) / kRowBlk;
+    const size_t lds = sizeof(int32_t) * (2 * nbk * kRowBlk + nbk);
     hipError_t e = hipFuncSetAttribute((const void *)k_edt_rows,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
