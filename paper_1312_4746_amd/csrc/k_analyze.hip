@@ -39,7 +39,10 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 template <int P>
 struct AnalyzeTile {
-    static constexpr int h = (P - 1) / 2, n = P * P, np = (n + 15) / 16 * 16, ss = np + 1;
+    // ss: LDS row stride of the FP32 patches; np / 4 + 1 is odd, so lane (g, jl)
+    // of an MFMA operand read (row jl, column 4 kb + g) hits bank 4 odd jl + g,
+    // 64 distinct banks
+    static constexpr int h = (P - 1) / 2, n = P * P, np = (n + 15) / 16 * 16, ss = np + 4;
     static constexpr int np4 = (n + 3) / 4 * 4;    // K extent of the FP32 MFMA steps
     static constexpr int TP = P <= 9 ? 128 : 64;  // pixels per workgroup
     static constexpr int hw = TP + 2 * h;
