@@ -29,7 +29,8 @@
 //
 // Work decomposition.  A workgroup of 4 waves owns four 8x4 pixel tiles (one
 // per wave); a work item is such a group and one label, taken from an atomic
-// queue (labels of a group by decreasing sample count).  The samples of each
+// queue (labels by decreasing sample count, every group of a label before the
+// next label).  The samples of each
 // label are padded to whole chunks of 64 with samples that contribute exactly
 // 0.  Chunks are copied from HBM/L2 straight into LDS with global_load_lds (no
 // registers), double-buffered: chunk c+1 is in flight while chunk c is
@@ -330,10 +331,13 @@ void k_parzen_mfma(ParzenFastArgs a) {
         __syncthreads();
         const int item = s_item;
         if (item >= nitems) break;
-        // item -> (group of 4 tiles, label); labels of a group in order of
-        // decreasing sample count, so the queue ends with the short items
-        const int grp = item / a.L;
-        const int lab = a.meta[a.L + 1 + (item - grp * a.L)];
+        // item -> (label, group of 4 tiles): labels in order of decreasing
+        // sample count, all groups of a label before the next label, so the
+        // queue ends with the shortest items (and consecutive items share the
+        // label's sample stream in L2)
+        const int lrank = item / a.ngroups;
+        const int grp = item - lrank * a.ngroups;
+        const int lab = a.meta[a.L + 1 + lrank];
         const int c0 = a.meta[lab], c1 = a.meta[lab + 1];
         const int last_steps = a.meta[2 * a.L + 1 + lab];  // 16-sample steps of the last chunk
         const int tile = grp * 4 + wave;
