@@ -331,15 +331,29 @@ __global__ __launch_bounds__(256) void k_mlp_convert(MlpAdamArgs a) {
 // holds units 4g..4g+3 of each 16-unit block in lane (g, j); the K = 32 step
 // over blocks 2s and 2s+1 takes the B fragment [block 2s units 4g..4g+3,
 // block 2s+1 units 4g..4g+3] and the matching weight columns in the same
-// (permuted) order, so no data moves between lanes.  Each wave stages the
-// inputs of its 16 pixels in LDS (the analysed vectors of 16 consecutive
-// pixels are one contiguous block, read with coalesced loads).
+// (permuted) order, so no data moves between lanes.
+//
+// The first layer's B fragment of lane (g, j) is features 32 ks + 8 g .. +7 of
+// row j, read straight from global memory.  The kernel orders a surrogate
+// input [r, g, b, col, row, a_0..a_{k-1}] as [a_0..a_{k-1}, 0 ..., r, g, b,
+// col, row] (the five leading features in the last five of the 128 slots;
+// the first layer's weight columns are permuted to match when they are staged
+// in LDS), so a window below k is two 16-byte loads and the window that holds
+// k takes clamped element loads.  Explicit rows x of more than five features
+// take the same order, so both forms round alike; narrower rows keep theirs.
+// Two 12-wave workgroups per CU (76 VGPRs, six waves per SIMD) hide the
+// input loads without a prefetch; the hidden activations are evaluated as
+// twice the GELU (gelu2x), 12 VALU instructions each, which is what bounds
+// the kernel.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
-constexpr int kInfWaves = 8;
-constexpr int kInfIn = 128;             // input features padded to whole K = 32 steps
-constexpr int kInfLd = kMlpHid + 8;     // LDS row stride (elements) of weights and staged inputs
-constexpr int kInfLoads = (16 * (kInfIn - 5) + 255) / 256;  // 16-byte loads per lane for 16 rows of a
+constexpr int kInfWaves = 12;          // waves per workgroup; two workgroups per CU (weights in LDS twice)
+constexpr int kInfBlocksPerCu = 2;
+constexpr int kInfNT = 1;              // 16-pixel tiles per wave and round (each weight fragment read feeds kInfNT products)
+constexpr int kInfRows = 16 * kInfNT;  // pixels per wave and round
+constexpr int kInfIn = 128;            // input features padded to whole K = 32 steps
+constexpr int kInfKs = kInfIn / 32;
+constexpr int kInfLd = kMlpHid + 8;    // LDS row stride (elements) of the weights
 
 __device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
@@ -348,146 +362,200 @@ __device__ __forceinline__ f32x4 mfma32(s16x8 a, s16x8 b, f32x4 c) {
 __device__ __forceinline__ s16x8 cat4(s16x4 lo, s16x4 hi) {
     return s16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
+// Twice the GELU with the erf approximation above: 2 GELU(z) = z + |z| erf(|z|
+// / sqrt 2) = z + |z| (1 - P(t) e^{-z^2/2}), t = 1 / (1 + p |z| / sqrt 2) --
+// 12 instructions.  The factor 2 is exact and is undone by halving the next
+// layer's (BF16) weights, which is exact too.
+__device__ __forceinline__ float gelu2x(float z) {
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f((z * z) * (-0.5f * 1.4426950408889634f));
+    return fmaf(az, fmaf(-(q * t), e, 1.0f), z);
+}
+__device__ __forceinline__ short half_bf16(short w) {
+    return to_bf16(0.5f * __builtin_bit_cast(float, (uint32_t)(uint16_t)w << 16));
+}
 
-__global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(MlpInferArgs a) {
+__global__ __launch_bounds__(64 * kInfWaves) __attribute__((amdgpu_waves_per_eu(kInfWaves * kInfBlocksPerCu / 4))) void k_mlp_infer(MlpInferArgs a) {
     __shared__ __align__(16) short sW1[kMlpHid * kInfLd];
     __shared__ __align__(16) short sW2[kMlpHid * kInfLd];
     __shared__ __align__(16) short sW3[kMlpOutPad * kInfLd];
-    __shared__ __align__(16) short sX[kInfWaves][16 * kInfLd];
-    __shared__ float sb[2 * kMlpHid + kMlpOutPad];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ __align__(16) float sb[2 * kMlpHid + kMlpOutPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, j = lane & 15;
+    // head: the five leading features go to slots kInfIn-5 .. kInfIn-1, the
+    // w features after them to slots 0 .. w-1 (source rows of stride ld)
+    const bool rows_x = a.x != nullptr;
+    const bool head = !rows_x || a.in > 5;
+    const int w = rows_x ? (head ? a.in - 5 : a.in) : a.k;
+    const int ld = rows_x ? a.in : a.k;
+    const float *src0 = rows_x ? a.x + (head ? 5 : 0) : a.alpha;
     for (int e = tid; e < kMlpHid * kInfIn; e += 64 * kInfWaves) {
-        const int h = e / kInfIn, i = e - h * kInfIn;
-        sW1[h * kInfLd + i] = i < a.in_pad ? a.W1b[h * a.in_pad + i] : (short)0;
+        const int h = e / kInfIn, c = e - h * kInfIn;
+        // network column of kernel feature c, or -1 for a zero slot
+        const int nc = !head ? (c < a.in ? c : -1) : c < w ? 5 + c : c >= kInfIn - 5 ? c - (kInfIn - 5) : -1;
+        sW1[h * kInfLd + c] = nc >= 0 ? a.W1b[h * a.in_pad + nc] : (short)0;
     }
-    for (int e = tid; e < kMlpHid * kMlpHid; e += 64 * kInfWaves) sW2[(e / kMlpHid) * kInfLd + e % kMlpHid] = a.W2b[e];
-    for (int e = tid; e < kMlpOutPad * kMlpHid; e += 64 * kInfWaves) sW3[(e / kMlpHid) * kInfLd + e % kMlpHid] = a.W3b[e];
+    // the hidden layers hold twice their activations (gelu2x): halved weights
+    for (int e = tid; e < kMlpHid * kMlpHid; e += 64 * kInfWaves)
+        sW2[(e / kMlpHid) * kInfLd + e % kMlpHid] = half_bf16(a.W2b[e]);
+    for (int e = tid; e < kMlpOutPad * kMlpHid; e += 64 * kInfWaves)
+        sW3[(e / kMlpHid) * kInfLd + e % kMlpHid] = half_bf16(a.W3b[e]);
     for (int e = tid; e < 2 * kMlpHid + kMlpOutPad; e += 64 * kInfWaves)
         sb[e] = e < kMlpHid ? a.b1[e] : e < 2 * kMlpHid ? a.b2[e - kMlpHid] : (e - 2 * kMlpHid < a.out ? a.b3[e - 2 * kMlpHid] : 0.f);
     __syncthreads();
-    short *X = sX[wave];
-    const int ks1 = (a.in + 31) / 32;
-    const int64_t ntiles = (a.n + 15) / 16;
+    const int ks1 = head ? kInfKs : (a.in + 31) / 32;
+    const int64_t ngrp = (a.n + kInfRows - 1) / kInfRows;
     const int64_t N = (int64_t)a.H * a.W;
     const float sx = a.W > 1 ? 1.0f / (float)(a.W - 1) : 0.0f, sy = a.H > 1 ? 1.0f / (float)(a.H - 1) : 0.0f;
-    // Inputs of a tile in registers: the analysed vectors (16-byte loads) and
-    // colour / position (lane l < 80: row l / 5, feature l % 5).  The loads of
-    // the next tile are issued before the current tile is computed.
-    float4 vb[kInfLoads];
-    float vc[2];
+    // raw inputs of the round: features 32 ks + 8 g .. +7 of row 16 tt + j
+    float raw[kInfNT][kInfKs][8];
+    // Windows of the K steps below kf lie below w for every lane; the window
+    // of step kf may cross w (its elements at or past w become zero).  The
+    // source is read through a buffer resource that ends at the round's last
+    // valid element, so rows past the end read zero.
+    const int kf = w >> 5;
+    const int voff = (j * ld + 8 * g) * 4;
     auto fetch = [&](int64_t t) {
-        const int64_t p0 = t * 16;
-        const int np = t < ntiles ? (int)(a.n - p0 < 16 ? a.n - p0 : 16) : 0;
-        if (a.x) return;
-        const float *ab = a.alpha + p0 * a.k;
-        const int nval = np * a.k;
+        if (t >= ngrp) return;
+        const int64_t p0 = t * kInfRows;
+        const int rows = (int)(a.n - p0 < kInfRows ? a.n - p0 : kInfRows);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(src0 + p0 * ld), (short)0, ((rows - 1) * ld + w) * 4, 0x00020000);
 #pragma unroll
-        for (int u = 0; u < kInfLoads; ++u) {
-            const int e0 = 4 * (lane + 64 * u);
-            if (e0 + 3 < nval) {
-                vb[u] = *reinterpret_cast<const float4 *>(ab + e0);
-            } else {
-                vb[u].x = e0 < nval ? ab[e0] : 0.0f;
-                vb[u].y = e0 + 1 < nval ? ab[e0 + 1] : 0.0f;
-                vb[u].z = e0 + 2 < nval ? ab[e0 + 2] : 0.0f;
-                vb[u].w = 0.0f;
-            }
-        }
+        for (int tt = 0; tt < kInfNT; ++tt) {
+            const int vo = voff + 16 * tt * ld * 4;  // the range check covers the vector offset only
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int e = lane + 64 * u, r = e / 5, f = e - r * 5;
-            float v = 0.0f;
-            if (r < np) {
-                const int pix = (int)(p0 + r);  // images hold fewer than 2^31 pixels
-                const int prow = pix / a.W;
-                v = f < 3 ? a.rgb[f * N + pix] : f == 3 ? (float)(pix - prow * a.W) * sx : (float)prow * sy;
+            for (int ks = 0; ks < kInfKs; ++ks) {
+                if (ks < kf) {
+                    const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 128 * ks, 0, 0));
+                    const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 128 * ks + 16, 0, 0));
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        raw[tt][ks][c] = lo[c];
+                        raw[tt][ks][4 + c] = hi[c];
+                    }
+                } else if (ks == kf) {
+                    // opaque copies: keeps the compiler from hoisting 8 offsets
+                    // and 8 lane masks per K step out of the loop
+                    int o = vo + 128 * ks, nv = w - 32 * ks - 8 * g;
+                    __asm__ volatile("" : "+v"(o), "+v"(nv));
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o + 4 * c, 0, 0));
+                        raw[tt][ks][c] = c < nv ? v : 0.0f;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) raw[tt][ks][c] = 0.0f;
+                }
             }
-            vc[u] = v;
+            int64_t row = p0 + 16 * tt + j;
+            if (row > a.n - 1) row = a.n - 1;  // rows past the end repeat the last (their outputs are not written)
+            if (head) {
+                float hv[5];
+                if (rows_x) {
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) hv[c] = a.x[row * a.in + c];
+                } else {
+                    const int pix = (int)row;  // images hold fewer than 2^31 pixels
+                    const int prow = pix / a.W;
+                    hv[0] = a.rgb[pix];
+                    hv[1] = a.rgb[N + pix];
+                    hv[2] = a.rgb[2 * N + pix];
+                    hv[3] = (float)(pix - prow * a.W) * sx;
+                    hv[4] = (float)prow * sy;
+                }
+#pragma unroll
+                for (int c = 0; c < 5; ++c)
+                    if (g == 3) raw[tt][kInfKs - 1][3 + c] = hv[c];
+            }
         }
     };
     int64_t t = (int64_t)blockIdx.x * kInfWaves + wave;
-    fetch(t);
-    for (; t < ntiles; t += (int64_t)gridDim.x * kInfWaves) {
-        const int64_t p0 = t * 16;
-        const int np = (int)(a.n - p0 < 16 ? a.n - p0 : 16);
-        // stage the 16 input rows (BF16), zero beyond the real features
-        if (a.x) {
-            for (int e = lane; e < 16 * kInfIn; e += 64) {
-                const int r = e / kInfIn, f = e - r * kInfIn;
-                X[r * kInfLd + f] = to_bf16(r < np && f < a.in ? a.x[(p0 + r) * a.in + f] : 0.0f);
-            }
-        } else {
+    for (; t < ngrp; t += (int64_t)gridDim.x * kInfWaves) {
+        const int64_t p0 = t * kInfRows;
+        const int np = (int)(a.n - p0 < kInfRows ? a.n - p0 : kInfRows);
+        fetch(t);
+        s16x8 xb[kInfNT][kInfKs];
 #pragma unroll
-            for (int u = 0; u < kInfLoads; ++u) {
-                const int e0 = 4 * (lane + 64 * u);
-                if (e0 >= 16 * a.k) break;
-                int r = e0 / a.k, f = e0 - r * a.k;
-                const float vv[4] = {vb[u].x, vb[u].y, vb[u].z, vb[u].w};
+        for (int tt = 0; tt < kInfNT; ++tt)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if (r < 16) X[r * kInfLd + 5 + f] = to_bf16(vv[c]);
-                    if (++f == a.k) {
-                        f = 0;
-                        ++r;
-                    }
-                }
-            }
+            for (int ks = 0; ks < kInfKs; ++ks)
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = lane + 64 * u, r = e / 5, f = e - r * 5;
-                if (r < 16) X[r * kInfLd + f] = to_bf16(vc[u]);
-            }
-            for (int e = lane; e < 16 * (kInfIn - a.in); e += 64) {
-                const int r = e / (kInfIn - a.in), f = a.in + (e - r * (kInfIn - a.in));
-                X[r * kInfLd + f] = 0;
-            }
-            fetch(t + (int64_t)gridDim.x * kInfWaves);  // next tile's loads in flight
-        }
-        // layer 1 (natural K order: features 32 ks + 8 g .. +7)
-        s16x8 xb[kInfIn / 32];
-#pragma unroll
-        for (int ks = 0; ks < kInfIn / 32; ++ks) xb[ks] = *reinterpret_cast<const s16x8 *>(X + j * kInfLd + 32 * ks + 8 * g);
-        s16x4 h1b[8];
+                for (int c = 0; c < 8; ++c) xb[tt][ks][c] = to_bf16(raw[tt][ks][c]);
+        // layer 1 (kernel feature order, natural K: features 32 ks + 8 g .. +7)
+        s16x4 h1b[kInfNT][8];
 #pragma unroll
         for (int hb = 0; hb < 8; ++hb) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const f32x4 bias = *reinterpret_cast<const f32x4 *>(sb + 16 * hb + 4 * g);
+            f32x4 acc[kInfNT];
+#pragma unroll
+            for (int tt = 0; tt < kInfNT; ++tt) acc[tt] = bias;
             const short *wr = sW1 + (16 * hb + j) * kInfLd + 8 * g;
 #pragma unroll
-            for (int ks = 0; ks < kInfIn / 32; ++ks)
-                if (ks < ks1) acc = mfma32(*reinterpret_cast<const s16x8 *>(wr + 32 * ks), xb[ks], acc);
+            for (int ks = 0; ks < kInfKs; ++ks)
+                if (ks < ks1) {
+                    const s16x8 wf = *reinterpret_cast<const s16x8 *>(wr + 32 * ks);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) h1b[hb][r] = to_bf16(gelu(acc[r] + sb[16 * hb + 4 * g + r]));
-            // every second block: keeps the weight loads of later blocks from
-            // piling up in VGPRs while two blocks' chains still overlap
-            if (hb & 1) __builtin_amdgcn_sched_barrier(0);
+                    for (int tt = 0; tt < kInfNT; ++tt) acc[tt] = mfma32(wf, xb[tt][ks], acc[tt]);
+                }
+#pragma unroll
+            for (int tt = 0; tt < kInfNT; ++tt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h1b[tt][hb][r] = to_bf16(gelu2x(acc[tt][r]));
+            // every block: keeps the weight loads of later blocks from piling
+            // up in VGPRs
+            __builtin_amdgcn_sched_barrier(0);
         }
         // layer 2 (permuted K order over block pairs)
-        s16x4 h2b[8];
+        s16x4 h2b[kInfNT][8];
 #pragma unroll
         for (int hb = 0; hb < 8; ++hb) {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const f32x4 bias = *reinterpret_cast<const f32x4 *>(sb + kMlpHid + 16 * hb + 4 * g);
+            f32x4 acc[kInfNT];
+#pragma unroll
+            for (int tt = 0; tt < kInfNT; ++tt) acc[tt] = bias;
             const short *wr = sW2 + (16 * hb + j) * kInfLd + 4 * g;
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2)
-                acc = mfma32(cat4(ld4(wr + 32 * s2), ld4(wr + 32 * s2 + 16)), cat4(h1b[2 * s2], h1b[2 * s2 + 1]), acc);
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const s16x8 wf = cat4(ld4(wr + 32 * s2), ld4(wr + 32 * s2 + 16));
 #pragma unroll
-            for (int r = 0; r < 4; ++r) h2b[hb][r] = to_bf16(gelu(acc[r] + sb[kMlpHid + 16 * hb + 4 * g + r]));
-            if (hb & 1) __builtin_amdgcn_sched_barrier(0);
+                for (int tt = 0; tt < kInfNT; ++tt)
+                    acc[tt] = mfma32(wf, cat4(h1b[tt][2 * s2], h1b[tt][2 * s2 + 1]), acc[tt]);
+            }
+#pragma unroll
+            for (int tt = 0; tt < kInfNT; ++tt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h2b[tt][hb][r] = to_bf16(gelu2x(acc[tt][r]));
+            __builtin_amdgcn_sched_barrier(0);
         }
-        f32x4 y = {0.f, 0.f, 0.f, 0.f};
+        const f32x4 bias3 = *reinterpret_cast<const f32x4 *>(sb + 2 * kMlpHid + 4 * g);
+        f32x4 y[kInfNT];
+#pragma unroll
+        for (int tt = 0; tt < kInfNT; ++tt) y[tt] = bias3;
         {
             const short *wr = sW3 + j * kInfLd + 4 * g;
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2)
-                y = mfma32(cat4(ld4(wr + 32 * s2), ld4(wr + 32 * s2 + 16)), cat4(h2b[2 * s2], h2b[2 * s2 + 1]), y);
-        }
-        if (j < np)
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const s16x8 wf = cat4(ld4(wr + 32 * s2), ld4(wr + 32 * s2 + 16));
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int o = 4 * g + r;
-                if (o < a.out) a.y[(p0 + j) * a.out + o] = y[r] + sb[2 * kMlpHid + o];
+                for (int tt = 0; tt < kInfNT; ++tt)
+                    y[tt] = mfma32(wf, cat4(h2b[tt][2 * s2], h2b[tt][2 * s2 + 1]), y[tt]);
             }
+        }
+#pragma unroll
+        for (int tt = 0; tt < kInfNT; ++tt)
+            if (16 * tt + j < np)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int o = 4 * g + r;
+                    if (o < a.out) a.y[(p0 + 16 * tt + j) * a.out + o] = y[tt][r];
+                }
     }
 }
 
@@ -554,9 +622,9 @@ hipError_t launch_mlp_convert(const LaunchCtx &lc, const MlpAdamArgs &a) {
     return hipGetLastError();
 }
 hipError_t launch_mlp_infer(const LaunchCtx &lc, const MlpInferArgs &a) {
-    const int64_t ntiles = (a.n + 15) / 16;
-    int64_t blocks = (int64_t)lc.num_cu;
-    if (blocks > (ntiles + kInfWaves - 1) / kInfWaves) blocks = (ntiles + kInfWaves - 1) / kInfWaves;
+    const int64_t ngrp = (a.n + kInfRows - 1) / kInfRows;
+    int64_t blocks = (int64_t)lc.num_cu * kInfBlocksPerCu;
+    if (blocks > (ngrp + kInfWaves - 1) / kInfWaves) blocks = (ngrp + kInfWaves - 1) / kInfWaves;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(64 * kInfWaves), 0, lc.stream, a);
     return hipGetLastError();
