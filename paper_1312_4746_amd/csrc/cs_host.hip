@@ -583,6 +583,7 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_tf = cv.take(sizeof(int32_t) * (L + 1 + 2 + 4));
     const size_t o_cnt = o_tf + sizeof(int32_t) * (L + 1);
     const size_t o_fcnt = o_cnt + sizeof(unsigned int) * 2;
+    const size_t o_queue = cv.take(sizeof(unsigned int) * kParzenQueues * kQueueStride);  // right after o_tf
     const size_t o_rec = cv.take(sizeof(SampleRec) * (size_t)M);
     const size_t o_seed = cv.take((size_t)L * N);
     const size_t o_col = cv.take(sizeof(int32_t) * (size_t)L * N);
@@ -618,7 +619,9 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
 
     {
         Timed t(ctx, "samples");
-        HIP_TRY(launch_fill_u32(lc, (unsigned int *)tf, (size_t)L + 1 + 2 + 4, 0u));
+        // counts, counters and the fast kernel's queues: one fill
+        HIP_TRY(launch_fill_u32(lc, (unsigned int *)tf,
+                                (o_queue - o_tf) / sizeof(unsigned int) + kParzenQueues * kQueueStride, 0u));
         HIP_TRY(launch_sample_count(lc, sample_label, sample_pix, M, L, N, bc, tf, nblocks));
         if (pix_subset) HIP_TRY(launch_check_pix(lc, pix_subset, npix, N, tf + L));
     }
@@ -714,7 +717,7 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         fa.aop = (const uint32_t *)(ctx->ws + o_aop);
         fa.abf = (const uint8_t *)(ctx->ws + o_abf);
         fa.loglik = loglik;
-        fa.work_counter = fcnt;
+        fa.work_counter = (unsigned int *)(ctx->ws + o_queue);
         fa.fix_count = fcnt + 1;
         fa.fixlist = (int2 *)(ctx->ws + o_fix);
         fa.H = H;

@@ -17,6 +17,10 @@ constexpr int kRecWords = 16;
 // 16-pixel row blocks per wave in the MFMA Parzen kernel: a wave owns an
 // 8 x (2 kParzenRB) pixel tile of kTilePix pixels.
 constexpr int kParzenRB = 2;
+// Work queues of the full-image Parzen kernel: one per XCD (workgroups are
+// dispatched to the 8 XCDs round-robin), each counter on its own 128-byte line.
+constexpr int kParzenQueues = 8;
+constexpr int kQueueStride = 32;  // unsigned ints
 constexpr int kTilePix = 8 * 2 * kParzenRB;
 // Samples per chunk of the padded sample stream (label segments are rounded
 // up to whole chunks).
@@ -191,7 +195,7 @@ struct ParzenFastArgs {
     const uint32_t *aop;   // [tile][row block][step][lane][8]: FP8 texture operands
     const uint8_t *abf;    // [tile][row block][lane][16 B]: BF16 location operands
     float *loglik;
-    unsigned int *work_counter;
+    unsigned int *work_counter;  // kParzenQueues counters, kQueueStride apart, zero at launch
     unsigned int *fix_count;  // [0] queued (label, tile), [1] rescaled wave-chunks, [2] overflows
     int2 *fixlist;
     int fix_cap;

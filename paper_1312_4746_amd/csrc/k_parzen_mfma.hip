@@ -28,9 +28,16 @@
 // holds the VALU for its whole duration; the BF16 one largely overlaps it.)
 //
 // Work decomposition.  A workgroup of 4 waves owns four 8x4 pixel tiles (one
-// per wave); a work item is such a group and one label, taken from an atomic
-// queue (labels by decreasing sample count, every group of a label before the
-// next label).  The samples of each
+// per wave); a work item is such a group and one label.  Items come from one
+// atomic queue per XCD: queue x holds the groups x, x + 8, x + 16, ... with
+// the labels of a group consecutive (by decreasing sample count), and a
+// workgroup takes from the queue of its own XCD first (workgroup w runs on
+// XCD w mod 8), then from the others.  The ten items of a group thus run at
+// about the same time on one XCD: its pixel operands are fetched into that
+// XCD's L2 once, and the partial lines of its pixel-major log-likelihood rows
+// are mostly merged there before they are written back.  The last
+// kTailGroups groups of a queue go label by label instead, so that the queue
+// ends with the items of the smallest label.  The samples of each
 // label are padded to whole chunks of 64 with samples that contribute exactly
 // 0.  Chunks are copied from HBM/L2 straight into LDS with global_load_lds (no
 // registers), double-buffered: chunk c+1 is in flight while chunk c is
@@ -63,6 +70,7 @@ constexpr float kFarQ = 0x1p100f;      // location feature of padding samples: Q
 // Floats of one chunk's records: location pieces K 0..7 (64 x 16 B), K 8..15
 // (64 x 16 B), colours (64 x float4).
 constexpr int kRecChunkF = kChunkS * 12;
+constexpr int kTailGroups = 32;  // groups at the end of each work queue taken label by label
 
 // BF16 bit pattern of a float that BF16 holds exactly.
 __device__ __forceinline__ short bf16_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
@@ -306,11 +314,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
     // each wave's BF16 location operands (read at every step; kept here
     // rather than in registers, which the kernel has none left of)
     __shared__ __align__(16) s16x8 s_abf[4][RB][64];
-    __shared__ int s_item;
+    __shared__ int s_item, s_queue;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, jl = lane & 15;
-    const int nitems = a.ngroups * a.L;
     const int64_t coef_label_stride = (int64_t)a.ngroups * 4 * kTilePix;
     // LDS byte offsets of the lane's operands in step 0 of a chunk buffer (step
     // st adds st * 16 rows; the swizzle depends on the row only through
@@ -325,18 +332,46 @@ void k_parzen_mfma(ParzenFastArgs a) {
     uint32_t n_rescale = 0;  // wave-chunks whose reference moved (wave-uniform)
     uint32_t n_overflow = 0; // (label, tile) items handed to the exact kernel on overflow
 
+    // queue state (thread 0): current queue and how many have been emptied
+    int queue = blockIdx.x % kParzenQueues, emptied = 0;
     for (;;) {
         __syncthreads();  // the previous item's LDS reads are done
-        if (tid == 0) s_item = (int)atomicAdd(a.work_counter, 1u);
+        if (tid == 0) {
+            int it = -1;
+            while (emptied < kParzenQueues) {
+                // groups queue, queue + 8, ... : nq of them, L items each
+                const int nq = queue < a.ngroups ? (a.ngroups - 1 - queue) / kParzenQueues + 1 : 0;
+                const int t = (int)atomicAdd(a.work_counter + queue * kQueueStride, 1u);
+                if (t < nq * a.L) {
+                    it = t;
+                    break;
+                }
+                queue = queue + 1 == kParzenQueues ? 0 : queue + 1;
+                ++emptied;
+            }
+            s_item = it;
+            s_queue = queue;
+        }
         __syncthreads();
         const int item = s_item;
-        if (item >= nitems) break;
-        // item -> (label, group of 4 tiles): labels in order of decreasing
-        // sample count, all groups of a label before the next label, so the
-        // queue ends with the shortest items (and consecutive items share the
-        // label's sample stream in L2)
-        const int lrank = item / a.ngroups;
-        const int grp = item - lrank * a.ngroups;
+        if (item < 0) break;
+        // item -> (group, label): the labels of a group consecutive, in order
+        // of decreasing sample count, except over the queue's last
+        // kTailGroups groups, which go label by label so that the queue ends
+        // with the shortest items (their operands stay in L2 meanwhile)
+        const int qg = s_queue < a.ngroups ? (a.ngroups - 1 - s_queue) / kParzenQueues + 1 : 0;
+        const int tg = qg < kTailGroups ? qg : kTailGroups;
+        const int head_items = (qg - tg) * a.L;
+        int gi, lrank;
+        if (item < head_items) {
+            gi = item / a.L;
+            lrank = item - gi * a.L;
+        } else {
+            const int j = item - head_items;
+            lrank = j / tg;
+            gi = qg - tg + (j - lrank * tg);
+        }
+        const int grp = s_queue + kParzenQueues * gi;
         const int lab = a.meta[a.L + 1 + lrank];
         const int c0 = a.meta[lab], c1 = a.meta[lab + 1];
         const int last_steps = a.meta[2 * a.L + 1 + lab];  // 16-sample steps of the last chunk
