@@ -308,6 +308,8 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
         tout[w] = jv ? t_out[j] : 0.0f;
         vmask[w] = __ballot(jv);
     }
+    // loads issued unconditionally (clamped indices, all in flight together),
+    // padding replaced afterwards
     float v[kMaskPx][W64];
 #pragma unroll
     for (int i = 0; i < kMaskPx; ++i)
@@ -315,8 +317,12 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
         for (int w = 0; w < W64; ++w) {
             const int j = 64 * w + lane;
             const int64_t pix = p0 + i;
-            v[i][w] = (j < k && pix < N) ? fabsf(alpha[pix * k + j]) : INFINITY;
+            v[i][w] = alpha[(pix < N ? pix : N - 1) * k + (j < k ? j : k - 1)];
         }
+#pragma unroll
+    for (int i = 0; i < kMaskPx; ++i)
+#pragma unroll
+        for (int w = 0; w < W64; ++w) v[i][w] = (64 * w + lane < k && p0 + i < N) ? fabsf(v[i][w]) : INFINITY;
     uint64_t words[kMaskPx][W64], nearw[kMaskPx][W64];
     uint64_t anyn = 0;
 #pragma unroll

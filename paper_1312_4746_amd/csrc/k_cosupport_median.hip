@@ -23,6 +23,7 @@ namespace cs {
 
 namespace {
 constexpr int kPx = 8;  // pixels per wave and round in the pixel-major pass
+constexpr int kRoundsPerWave = 4;
 
 // Reserve slots for the lanes set in m (one atomic per wave), return the slot
 // of this lane (meaningful where its bit is set).
@@ -36,9 +37,9 @@ __device__ __forceinline__ unsigned long long wave_slot(unsigned long long m, un
 }
 }  // namespace
 
-// The gather pass.  Each wave takes rounds of kPx consecutive pixels (one
-// round unless the image exceeds the grid), lane = row within a 64-bit mask
-// word.  Per workgroup the
+// The gather pass.  Each wave takes rounds of kPx consecutive pixels (about
+// kRoundsPerWave of them, the loads of the next in flight while one is
+// decided), lane = row within a 64-bit mask word.  Per workgroup the
 // count of entries below the candidate window goes to parts[blockIdx.x].
 template <int W64>
 __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, int64_t N, int k,
@@ -46,6 +47,7 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
                                                             double frac, TauState *st, int64_t *cand, int64_t cap,
                                                             unsigned long long *parts, int64_t *didx,
                                                             uint64_t *masks) {
+    static_assert(kPx * W64 <= 64, "one mask word per lane");
     __shared__ unsigned long long red[256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // candidate window [v - 2m, v + 2m] as float bit patterns (non-negative
@@ -87,18 +89,35 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
     }
     unsigned long long below = 0;
     const int64_t nrounds = (N + kPx - 1) / kPx;
-    for (int64_t rd = (int64_t)blockIdx.x * 4 + wave; rd < nrounds; rd += (int64_t)gridDim.x * 4) {
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    // the keys of a round, loaded unconditionally (clamped indices: the loads
+    // are in flight together; padding is replaced when the round is used)
+    auto load = [&](int64_t rd, uint32_t (&kk)[kPx][W64]) {
         const int64_t p0 = rd * kPx;
-        uint32_t key[kPx][W64];
 #pragma unroll
         for (int i = 0; i < kPx; ++i)
 #pragma unroll
             for (int w = 0; w < W64; ++w) {
                 const int j = 64 * w + lane;
                 const int64_t pix = p0 + i;
-                key[i][w] = (j < k && pix < N) ? (__float_as_uint(alpha[pix * k + j]) & 0x7FFFFFFFu) : 0x7F800000u;
+                kk[i][w] = __float_as_uint(alpha[(pix < N ? pix : N - 1) * k + (j < k ? j : k - 1)]);
             }
-        uint64_t words[kPx][W64];
+    };
+    uint32_t key[kPx][W64], nkey[kPx][W64];
+    int64_t rd = (int64_t)blockIdx.x * 4 + wave;
+    if (rd < nrounds) load(rd, key);
+    for (; rd < nrounds; rd += stride) {
+        const int64_t p0 = rd * kPx;
+        if (rd + stride < nrounds) load(rd + stride, nkey);  // next round in flight
+#pragma unroll
+        for (int i = 0; i < kPx; ++i)
+#pragma unroll
+            for (int w = 0; w < W64; ++w)
+                key[i][w] = (64 * w + lane < k && p0 + i < N) ? (key[i][w] & 0x7FFFFFFFu) : 0x7F800000u;
+        // lane l < kPx * W64 stores word (l / W64, l % W64), picked up as the
+        // words are formed (no array of ballots held in scalar registers)
+        const int li = lane / W64, lw = lane - li * W64;
+        uint64_t outw = 0;
 #pragma unroll
         for (int i = 0; i < kPx; ++i)
 #pragma unroll
@@ -114,24 +133,22 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
                 }
                 const float f = __uint_as_float(x);
                 const uint64_t inb = __ballot(f <= tin[w]);
-                const uint64_t outb = __ballot(f > tout[w]);
-                words[i][w] = inb & vmask[w];
+                if (li == i && lw == w) outw = inb & vmask[w];
                 const bool defer = live && !(f <= tin[w]) && !(f > tout[w]);  // NaN: deferred
                 const unsigned long long dm = __ballot(defer);
                 if (dm) {
                     const unsigned long long slot = wave_slot(dm, &st->n_d, lane);
                     if (defer) didx[slot] = (p0 + i) * k + 64 * w + lane;
                 }
+                // one entry at a time: keeps the ballots from piling up in
+                // scalar registers
+                __builtin_amdgcn_sched_barrier(0);
             }
-        // lane l < kPx * W64 stores word (l / W64, l % W64)
-        const int li = lane / W64, lw = lane - li * W64;
-        uint64_t outw = 0;
+        if (lane < kPx * W64 && p0 + li < N) masks[(p0 + li) * W64 + lw] = outw;
 #pragma unroll
         for (int i = 0; i < kPx; ++i)
 #pragma unroll
-            for (int w = 0; w < W64; ++w)
-                if (li == i && lw == w) outw = words[i][w];
-        if (lane < kPx * W64 && p0 + li < N) masks[(p0 + li) * W64 + lw] = outw;
+            for (int w = 0; w < W64; ++w) key[i][w] = nkey[i][w];
     }
     red[threadIdx.x] = below;
     __syncthreads();
@@ -235,8 +252,9 @@ hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N
                               int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
                               uint64_t *masks) {
     if (N <= 0) return hipSuccess;
-    // one round per wave where the per-workgroup counts fit, else persistent
-    int64_t blocks = (N + 4 * kPx - 1) / (4 * kPx);
+    // kRoundsPerWave rounds per wave (each prefetches the next), more where
+    // the per-workgroup counts would not fit
+    int64_t blocks = (N + 4 * kPx * kRoundsPerWave - 1) / (4 * kPx * kRoundsPerWave);
     if (blocks > kTauParts) blocks = kTauParts;
 #define CS_MG_LAUNCH(WW)                                                                                    \
     hipLaunchKernelGGL(k_median_mask_gather<WW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, N, \

@@ -72,12 +72,17 @@ __global__ __launch_bounds__(64) void k_edt_col_fill(const uint8_t *seeds, int H
     const uint8_t *sd = seeds + (int64_t)l * N + c;
     int32_t *cr = colrow + (int64_t)l * N + c;
     const int r0 = seg * kSegRows, r1 = min(H, r0 + kSegRows);
+    // the segment's seed bytes, loaded unconditionally (rows clamped) so that
+    // the loads are in flight together
+    bool sv[kSegRows];
+#pragma unroll
+    for (int i = 0; i < kSegRows; ++i) sv[i] = sd[(int64_t)min(r0 + i, H - 1) * W] != 0;
     int up[kSegRows];
     int lastr = above;
 #pragma unroll
     for (int i = 0; i < kSegRows; ++i) {
         const int r = r0 + i;
-        if (r < r1 && sd[(int64_t)r * W]) lastr = r;
+        if (r < r1 && sv[i]) lastr = r;
         up[i] = lastr;
     }
     int nextr = below;
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(64) void k_edt_col_fill(const uint8_t *seeds, int H
     for (int i = kSegRows - 1; i >= 0; --i) {
         const int r = r0 + i;
         if (r >= r1) continue;
-        if (sd[(int64_t)r * W]) nextr = r;
+        if (sv[i]) nextr = r;
         const int a = up[i];
         int best = a;
         if (nextr >= 0 && (a < 0 || nextr - r < r - a)) best = nextr;

@@ -74,9 +74,13 @@ __device__ __forceinline__ void mlp_tile_forward(const s16x4 (&xb)[kMlpMaxIn / 1
     for (int hb = 0; hb < 8; ++hb) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         const short *wr = W1 + (16 * hb + j) * ld1 + 4 * g;
+        // weight fragments loaded unconditionally (clamped step), used below nks
+        s16x4 wf[kMlpMaxIn / 16];
+#pragma unroll
+        for (int ks = 0; ks < kMlpMaxIn / 16; ++ks) wf[ks] = ld4(wr + 16 * (ks < nks ? ks : nks - 1));
 #pragma unroll
         for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
-            if (ks < nks) acc = mfma(ld4(wr + 16 * ks), xb[ks], acc);
+            if (ks < nks) acc = mfma(wf[ks], xb[ks], acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float z = acc[r] + b1[16 * hb + 4 * g + r];
@@ -119,14 +123,21 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
     int64_t row = a.idx ? (int64_t)a.idx[rb] : (int64_t)rb;
     row = row < 0 ? 0 : (row >= a.n_rows ? a.n_rows - 1 : row);  // memory-safe on bad input
     const int nks = a.in_pad / 16;
-    s16x4 xb[kMlpMaxIn / 16];
+    // inputs loaded unconditionally (clamped feature index: the loads are in
+    // flight together), zero past in
+    float xv[kMlpMaxIn / 16][4];
 #pragma unroll
     for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int f = 16 * ks + 4 * g + q;
-            xb[ks][q] = to_bf16(f < a.in ? a.x[row * a.in + f] : 0.0f);
+            xv[ks][q] = a.x[row * a.in + (f < a.in ? f : a.in - 1)];
         }
+    s16x4 xb[kMlpMaxIn / 16];
+#pragma unroll
+    for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xb[ks][q] = to_bf16(16 * ks + 4 * g + q < a.in ? xv[ks][q] : 0.0f);
     float z1[8][4], z2[8][4];
     s16x4 h2b[8];
     f32x4 y;
