@@ -212,6 +212,10 @@ int cs_profile_enable(cs_ctx *ctx, int on);
 /* Record only the kernel `name` (NULL: every kernel); each recorded launch
  * adds two events to the stream. */
 int cs_profile_only(cs_ctx *ctx, const char *name);
+/* Record one launch in `period` (>= 1, default 1) of each profiled kernel,
+ * counted from the last cs_profile_enable; the others run without events.
+ * Averages over the recorded launches then cost the stream fewer bubbles. */
+int cs_profile_sample(cs_ctx *ctx, int period);
 int cs_profile_read(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 
 /* ---- Learned surrogate of the data term ----

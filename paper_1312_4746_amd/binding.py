@@ -56,6 +56,7 @@ SIGNATURES = {
     "cs_last_loglik_stats": (_I, [_P, ctypes.POINTER(_LoglikStatsC)]),
     "cs_profile_enable": (_I, [_P, _I]),
     "cs_profile_only": (_I, [_P, ctypes.c_char_p]),
+    "cs_profile_sample": (_I, [_P, ctypes.c_int]),
     "cs_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "cs_mlp_param_count": (_I64, [_I, _I, _I]),
     "cs_mlp_init": (_I, [_P, ctypes.POINTER(_P), _I, _I, _I, _P]),
@@ -294,6 +295,9 @@ class Context:
 
     def profile_only(self, name: Optional[str]):
         self._check(lib().cs_profile_only(self._h, name.encode() if name else None))
+
+    def profile_sample(self, period: int):
+        self._check(lib().cs_profile_sample(self._h, int(period)))
 
     def profile_read(self, name: str):
         ms = ctypes.c_double()

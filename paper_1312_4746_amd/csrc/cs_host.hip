@@ -2,6 +2,8 @@
 // device workspace, kernel-event timing and the order of launches behind each
 // C-ABI call declared in include/cosparse.h.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -9,6 +11,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/cosparse.h"
@@ -29,10 +32,12 @@ struct cs_ctx {
     // FP32 analysed vectors for the exact median of a BF16 analysis
     float *alpha32 = nullptr;
     size_t alpha32_bytes = 0;
-    // pinned host staging for small device-to-host results, and the event
-    // that marks the label counts of a log-likelihood call as copied
+    // pinned host staging for small device-to-host results
     char *pinned = nullptr;
-    hipEvent_t ev_counts = nullptr;
+    // coherent host memory that the sample scan writes the label counts and a
+    // tag into (a log-likelihood call waits on the tag, not on the stream)
+    int32_t *hcounts = nullptr, *hcounts_dev = nullptr;
+    int32_t tag = 0;
     // Gaussian patch mask of the last (p, sigma)
     double *wmask = nullptr;
     int wmask_p = 0;
@@ -40,6 +45,8 @@ struct cs_ctx {
     // kernel-event timing (of every span, or only of the spans named `only`)
     bool prof = false;
     std::string only;
+    int prof_period = 1;                       // record one launch in prof_period per name
+    std::map<std::string, int64_t> prof_seen;  // launches of each name seen while recording
     struct Span {
         std::string name;
         hipEvent_t a, b;
@@ -73,6 +80,29 @@ int fail(cs_ctx *c, int code, const char *fmt, ...) {
     } while (0)
 
 LaunchCtx lc_of(const cs_ctx *c) { return LaunchCtx{c->stream, c->num_cu}; }
+
+// Waits until the sample scan of this call has written `tag` into host memory
+// (the label counts before it are then visible): spins, yields after 2 ms,
+// and after 5 s waits for the stream and looks once more (a failed stream
+// reports its error there).
+int wait_host_tag(cs_ctx *ctx, int32_t tag) {
+    volatile int32_t *t = ctx->hcounts + kHostTag;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int64_t it = 0; *t != tag; ++it) {
+        if ((it & 1023) == 1023) {
+            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (sec > 5.0) {
+                HIP_TRY(hipStreamSynchronize(ctx->stream));
+                if (*t != tag) return fail(ctx, CS_ERR_HIP, "the label counts did not arrive from the device");
+                break;
+            }
+            if (sec > 2e-3) std::this_thread::yield();
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return CS_OK;
+}
 
 struct Carve {
     size_t off = 0;
@@ -119,6 +149,7 @@ struct Timed {
     hipEvent_t a = nullptr, b = nullptr;
     Timed(cs_ctx *ctx, const char *nm) : c(ctx), name(nm) {
         if (!c->prof || (!c->only.empty() && c->only != nm)) return;
+        if (c->prof_period > 1 && c->prof_seen[nm]++ % c->prof_period != 0) return;
         a = take();
         b = take();
         if (a) hipEventRecord(a, c->stream);
@@ -203,12 +234,17 @@ int cs_create(cs_ctx **out, int device, void *hip_stream) {
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e == hipSuccess) e = hipHostMalloc((void **)&ctx->pinned, kPinnedBytes, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_counts, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&ctx->hcounts, sizeof(int32_t) * (kHostTag + 1),
+                          hipHostMallocCoherent | hipHostMallocMapped);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&ctx->hcounts_dev, ctx->hcounts, 0);
     if (e != hipSuccess) {
         if (ctx->pinned) hipHostFree(ctx->pinned);
+        if (ctx->hcounts) hipHostFree(ctx->hcounts);
         delete ctx;
         return CS_ERR_HIP;
     }
+    std::memset(ctx->hcounts, 0, sizeof(int32_t) * (kHostTag + 1));
     *out = ctx;
     return CS_OK;
 }
@@ -226,7 +262,7 @@ int cs_destroy(cs_ctx *ctx) {
     if (ctx->alpha32) hipFree(ctx->alpha32);
     if (ctx->wmask) hipFree(ctx->wmask);
     if (ctx->pinned) hipHostFree(ctx->pinned);
-    if (ctx->ev_counts) hipEventDestroy(ctx->ev_counts);
+    if (ctx->hcounts) hipHostFree(ctx->hcounts);
     delete ctx;
     return CS_OK;
 }
@@ -578,6 +614,9 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const int nblocks = (int)((M + 255) / 256);
     Carve cv;
     const size_t o_bc = cv.take(sizeof(int32_t) * (size_t)L * nblocks);
+    const LaunchCtx lc0 = lc_of(ctx);
+    const int npix_blocks = pix_subset && npix > 0 ? check_pix_blocks(lc0, npix) : 0;
+    const size_t o_bflags = cv.take(sizeof(int32_t) * ((size_t)nblocks + npix_blocks));
     // label counts (L+1), the exact kernel's two counters and the fast
     // kernel's four counters share one region, cleared by one fill
     const size_t o_tf = cv.take(sizeof(int32_t) * (L + 1 + 2 + 4));
@@ -604,7 +643,6 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_pix4 = fast ? cv.take(sizeof(float4) * (size_t)ntiles_pad * kTilePix) : 0;
     const size_t o_aop = fast ? cv.take((size_t)ntiles_pad * kParzenRB * (KP / 128) * 64 * 32) : 0;
     const size_t o_abf = fast ? cv.take((size_t)ntiles_pad * kParzenRB * 64 * 16) : 0;
-    const size_t o_meta = cv.take(sizeof(int32_t) * (3 * (size_t)L + 1));
     const size_t o_coef = cv.take(sizeof(float4) * (size_t)L *
                                   (size_t)(fast ? ntiles_pad * kTilePix : npix));
     int rc = ensure_ws(ctx, cv.off);
@@ -617,16 +655,19 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
             *nearest = (int32_t *)(ctx->ws + o_nn);
     const LaunchCtx lc = lc_of(ctx);
 
+    int32_t *bflags = (int32_t *)(ctx->ws + o_bflags), *pflags = bflags + nblocks;
+    const int32_t tag = ctx->tag = ctx->tag >= 0x3FFFFFFF ? 1 : ctx->tag + 1;
     {
         Timed t(ctx, "samples");
-        // counts, counters and the fast kernel's queues: one fill
-        HIP_TRY(launch_fill_u32(lc, (unsigned int *)tf,
-                                (o_queue - o_tf) / sizeof(unsigned int) + kParzenQueues * kQueueStride, 0u));
-        HIP_TRY(launch_sample_count(lc, sample_label, sample_pix, M, L, N, bc, tf, nblocks));
-        if (pix_subset) HIP_TRY(launch_check_pix(lc, pix_subset, npix, N, tf + L));
+        HIP_TRY(launch_sample_count(lc, sample_label, sample_pix, M, L, N, bc, bflags, nblocks));
+        if (pix_subset) HIP_TRY(launch_check_pix(lc, pix_subset, npix, N, pflags));
+        // totals and flags to the host; the exact kernel's and the fast
+        // kernel's counters and queues cleared for this call
+        ctx->hcounts[kHostTag] = 0;
+        HIP_TRY(launch_sample_scan(lc, bc, L, nblocks, bflags, pflags, npix_blocks, tf, cnt,
+                                   (int)((o_queue - o_cnt) / sizeof(unsigned int)) + kParzenQueues * kQueueStride,
+                                   ctx->hcounts_dev, tag));
     }
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, tf, sizeof(int32_t) * (L + 1), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipEventRecord(ctx->ev_counts, ctx->stream));
     // The scatter and the distance transforms need no host decision (invalid
     // samples are skipped on the device): they run while the host waits for
     // the counts, which it needs for the segment layout and the constants.
@@ -640,9 +681,10 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         Timed t(ctx, "edt");
         HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest, (int32_t *)(ctx->ws + o_edt)));
     }
-    HIP_TRY(hipEventSynchronize(ctx->ev_counts));
+    int rc_wait = wait_host_tag(ctx, tag);
+    if (rc_wait) return rc_wait;
     int32_t counts[kMaxLabels + 1];
-    std::memcpy(counts, ctx->pinned, sizeof(int32_t) * (L + 1));
+    for (int l = 0; l <= L; ++l) counts[l] = ((volatile int32_t *)ctx->hcounts)[l];
     if (counts[L] & 1) return fail(ctx, CS_ERR_ARG, "a sample label or pixel index is out of range");
     if (counts[L] & 2) return fail(ctx, CS_ERR_ARG, "a pixel index of pix_subset is out of range");
     for (int l = 0; l < L; ++l)
@@ -730,20 +772,13 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         fa.ngroups = (int)ngroups;
         fa.fix_cap = (int)(ntiles_pad * L);
         fa.sigma_c = pa.sigma_c;
-        // per-label chunk ranges and the label order, staged through the upper
-        // half of the pinned buffer (the copy of the previous call, enqueued
-        // before the counts, finished before the event above)
-        int32_t *meta_h = (int32_t *)(ctx->pinned + kPinnedBytes / 2);
-        for (int l = 0; l <= L; ++l) meta_h[l] = segs.pseg[l] / kStreamChunk;
-        for (int l = 0; l < L; ++l) meta_h[L + 1 + l] = pa.label_order[l];
+        // per-label chunk ranges and the label order (kernel arguments: no copy)
+        for (int l = 0; l <= L; ++l) fa.meta[l] = segs.pseg[l] / kStreamChunk;
+        for (int l = 0; l < L; ++l) fa.meta[L + 1 + l] = pa.label_order[l];
         for (int l = 0; l < L; ++l) {
             const int in_last = counts[l] - (segs.pseg[l + 1] - segs.pseg[l] - kStreamChunk);
-            meta_h[2 * L + 1 + l] = (in_last + 15) / 16;
+            fa.meta[2 * L + 1 + l] = (in_last + 15) / 16;
         }
-        int32_t *meta_d = (int32_t *)(ctx->ws + o_meta);
-        HIP_TRY(hipMemcpyAsync(meta_d, meta_h, sizeof(int32_t) * (3 * (size_t)L + 1), hipMemcpyHostToDevice,
-                               ctx->stream));
-        fa.meta = meta_d;
         ctx->loglik_counters = fcnt;
         {
             Timed t(ctx, "parzen");
@@ -794,7 +829,16 @@ int cs_profile_enable(cs_ctx *ctx, int on) {
     }
     ctx->spans.clear();
     ctx->totals.clear();
+    ctx->prof_seen.clear();
     ctx->prof = on != 0;
+    return CS_OK;
+}
+
+int cs_profile_sample(cs_ctx *ctx, int period) {
+    if (!ctx) return CS_ERR_ARG;
+    if (period < 1) return fail(ctx, CS_ERR_ARG, "period must be >= 1");
+    ctx->prof_period = period;
+    ctx->prof_seen.clear();
     return CS_OK;
 }
 

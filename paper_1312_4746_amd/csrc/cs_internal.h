@@ -137,15 +137,22 @@ hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const 
                       int64_t nb, int k, int32_t *out);
 
 // ---- samples, distance transform, Parzen sum (k_parzen.hip, k_edt.hip) ----
+// Host-memory slot that k_sample_scan sets to its tag once totals and flags
+// are visible to the host.
+constexpr int kHostTag = 255;
 hipError_t launch_sample_count(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
                                int64_t M, int L, int64_t N, int32_t *block_counts,
-                               int32_t *totals_flags, int nblocks);
+                               int32_t *block_flags, int nblocks);
+hipError_t launch_sample_scan(const LaunchCtx &lc, int32_t *block_counts, int L, int nblocks,
+                              const int32_t *block_flags, const int32_t *pix_flags, int npix_blocks,
+                              int32_t *totals_flags, unsigned int *zero, int nzero, int32_t *host_out,
+                              int32_t tag);
+int check_pix_blocks(const LaunchCtx &lc, int64_t n);
 hipError_t launch_sample_scatter(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
                                  int64_t M, int L, int H, int W, const float *rgb,
                                  const uint64_t *masks, int k, const int32_t *block_counts,
                                  int nblocks, SampleRec *recs, uint8_t *seeds);
-hipError_t launch_check_pix(const LaunchCtx &lc, const int32_t *pix, int64_t n, int64_t N,
-                            int32_t *flags);
+hipError_t launch_check_pix(const LaunchCtx &lc, const int32_t *pix, int64_t n, int64_t N, int32_t *flags);
 size_t edt_scratch_bytes(int H, int W, int L);
 hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, int L,
                       int32_t *colrow, int32_t *d2, int32_t *nearest, int32_t *scratch);
@@ -202,10 +209,11 @@ struct ParzenFastArgs {
     int H, W, L, k, ksteps;
     int tiles_x, ntiles, ngroups;
     double sigma_c;
-    // device: [0..L] first chunk of each label's padded segment (chunk units),
-    // [L+1 .. 2L] the labels by decreasing sample count, [2L+1 .. 3L] the
-    // 16-sample steps of each label's last chunk that hold real samples
-    const int *meta;
+    // passed by value (kernel arguments): [0..L] first chunk of each label's
+    // padded segment (chunk units), [L+1 .. 2L] the labels by decreasing
+    // sample count, [2L+1 .. 3L] the 16-sample steps of each label's last
+    // chunk that hold real samples
+    int meta[3 * kMaxLabels + 1];
 };
 hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,
                                const StreamSegs &segs, int64_t Mpad, float cscale, uint8_t *feat, float *rec);
