@@ -7,6 +7,8 @@
 
 #include <cstdint>
 
+#include "cs_internal.h"
+
 namespace cs {
 
 // Symmetric border reflection that repeats the edge pixel: -1 -> 0, n -> n-1.
@@ -15,10 +17,12 @@ __device__ __forceinline__ int reflect_idx(int i, int n) {
 }
 
 // Gray value, FP64, order (0.299 R + 0.587 G) + 0.114 B.
-__device__ __forceinline__ double gray64(const float *rgb, int64_t N, int64_t idx) {
+__device__ __forceinline__ double gray64_of(float r, float g, float b) {
 #pragma clang fp contract(off)
-    double r = (double)rgb[idx], g = (double)rgb[N + idx], b = (double)rgb[2 * N + idx];
-    return (0.299 * r + 0.587 * g) + 0.114 * b;
+    return (0.299 * (double)r + 0.587 * (double)g) + 0.114 * (double)b;
+}
+__device__ __forceinline__ double gray64(const float *rgb, int64_t N, int64_t idx) {
+    return gray64_of(rgb[idx], rgb[N + idx], rgb[2 * N + idx]);
 }
 
 // sum_t O_jt s_t, sequential in t, no FMA.
@@ -71,6 +75,92 @@ __device__ __forceinline__ double row_margin(const float *omega, int j, int n, d
         ss = ss + o * o;
     }
     return coef * sqrt(ss) * (1.0 + 0x1p-20) + 0x1p-100;
+}
+
+// Radix selection helpers (256-thread workgroups).
+// The digit holding the remaining rank in a complete kHistBins-bin histogram
+// (parallel prefix over the bins): the prefix with that digit set and the
+// rank left inside it, returned to every thread.
+__device__ __forceinline__ void tau_pick_digit(const unsigned int *hist, int shift, unsigned int prefix_in,
+                                               unsigned long long rank_in, unsigned int &prefix_out,
+                                               unsigned long long &rank_out) {
+    constexpr int per = kHistBins / 256;
+    __shared__ unsigned long long scan[256];
+    __shared__ unsigned int s_pfx;
+    __shared__ unsigned long long s_rank;
+    const int t = threadIdx.x;
+    unsigned int loc[per];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        loc[i] = hist[t * per + i];
+        sum += loc[i];
+    }
+    scan[t] = sum;
+    if (t == 0) {
+        s_pfx = prefix_in;
+        s_rank = rank_in;
+    }
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const unsigned long long v = t >= off ? scan[t - off] : 0ull;
+        __syncthreads();
+        scan[t] += v;
+        __syncthreads();
+    }
+    const unsigned long long before = scan[t] - sum;
+    if (rank_in >= before && rank_in < scan[t]) {
+        unsigned long long rr = rank_in - before;
+        for (int i = 0; i < per; ++i) {
+            if (rr < loc[i]) {
+                s_pfx = prefix_in | ((unsigned int)(t * per + i) << shift);
+                s_rank = rr;
+                break;
+            }
+            rr -= loc[i];
+        }
+    }
+    __syncthreads();
+    prefix_out = s_pfx;
+    rank_out = s_rank;
+}
+
+// Set-up of a folded selection by one 256-thread workgroup: per-row margins
+// and their maximum, the state (digit 0: empty prefix, the target rank) and
+// three cleared histograms.
+__device__ __forceinline__ void tau_setup(TauState *st, unsigned int *hist3, const float *omega, int k, int n,
+                                          double coef, unsigned long long rank0, double *margins,
+                                          double *max_margin) {
+    __shared__ double red[4];
+    const int t = threadIdx.x;
+    double m = 0.0;
+    for (int j = t; j < k; j += 256) {
+        const double mj = row_margin(omega, j, n, -1.0, coef);
+        margins[j] = mj;
+        m = fmax(m, mj);
+    }
+    for (int off = 1; off < 64; off <<= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((t & 63) == 0) red[t >> 6] = m;
+    for (int i = t; i < 3 * kHistBins; i += 256) hist3[i] = 0u;
+    __syncthreads();
+    if (t == 0) {
+        *max_margin = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        st->rank0 = rank0;
+        st->rank = rank0;
+        st->prefix = 0;
+        for (int d = 0; d < 4; ++d) {
+            st->pfx[d] = 0;
+            st->rk[d] = rank0;
+        }
+        st->nparts = 0;
+        st->below = 0;
+        st->ncand = 0;
+        st->n_d = 0;
+        st->n_r = 0;
+        st->lo = st->hi = 0.0;
+        st->median = 0.0;
+        st->tau = 0.0;
+    }
 }
 
 __device__ __forceinline__ short bf16_rne(float f) {

@@ -513,16 +513,18 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
     HIP_TRY(hipSetDevice(ctx->device));
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     const int64_t count = (int64_t)H * W * k;
-    if ((rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha))) return rc;
     if (precision == CS_FP32 && margin < 0.0) {
         // the masks are decided in the candidate gather of the median: four
-        // passes over alpha instead of five
+        // passes over alpha instead of five; the analysis kernel also sets up
+        // the selection, and each digit is picked by the kernel after its
+        // histogram
         const int n = p * p;
         const LaunchCtx lc = lc_of(ctx);
         Carve cv;
         TauWs tw;
         tw.carve(cv);
         const size_t o_marg = cv.take(sizeof(double) * k);
+        const size_t o_hist3 = cv.take(sizeof(unsigned int) * 3 * kHistBins);
         if ((rc = ensure_ws(ctx, cv.off))) return rc;
         // candidates, their FP64 values, listed mask entries (room for all)
         if ((rc = ensure_cand(ctx, (size_t)count * 24))) return rc;
@@ -534,14 +536,37 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
         int64_t *cand = (int64_t *)ctx->cand;
         double *vals = (double *)(ctx->cand + (size_t)count * 8);
         int64_t *didx = (int64_t *)(ctx->cand + (size_t)count * 16);
+        unsigned int *hist3 = (unsigned int *)(ctx->ws + o_hist3);
+        (void)hist;
+        {
+            AnalyzeArgs a{};
+            a.rgb = rgb;
+            a.H = H;
+            a.W = W;
+            a.p = p;
+            a.n = n;
+            a.n_pad = n_pad_of(n);
+            a.k = k;
+            a.wmask = ctx->wmask;
+            a.omega = omega;
+            a.alpha = alpha;
+            a.tau_st = st;
+            a.tau_hist3 = hist3;
+            a.tau_margins = marg;
+            a.tau_max_margin = mmax;
+            a.tau_coef = margin_coef(CS_FP32, n);
+            a.tau_rank0 = (unsigned long long)((count - 1) / 2);
+            Timed t(ctx, "analyze");
+            HIP_TRY(launch_analyze(lc, a, precision));
+        }
         {
             Timed t(ctx, "tau_select");
-            HIP_TRY(tau_select_float(lc, alpha, count, hist, st, omega, k, n, margin_coef(CS_FP32, n), mmax, marg));
+            HIP_TRY(tau_digits_folded(lc, alpha, count, hist3, st));
         }
         {
             Timed t(ctx, "cosupport");
             HIP_TRY(median_mask_gather(lc, alpha, (int64_t)H * W, k, mmax, marg, frac, st, cand, count, parts, didx,
-                                       masks));
+                                       masks, hist3));
         }
         {
             Timed t(ctx, "tau_exact");
@@ -555,6 +580,7 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
         }
         return CS_OK;
     }
+    if ((rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha))) return rc;
     const float *a32 = nullptr;
     if ((rc = median_source(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha, &a32))) return rc;
     Carve cv;
@@ -699,12 +725,28 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     if (fast) {
         Timed t(ctx, "stream");
         const float cscale = (float)std::sqrt(1.4426950408889634 / (2.0 * prm->sigma_c * prm->sigma_c));
-        HIP_TRY(launch_stream_build(lc, recs, k, KP, L, segs, segs.pseg[L], cscale, (uint8_t *)(ctx->ws + o_feat),
-                                    (float *)(ctx->ws + o_srec)));
-        HIP_TRY(launch_pixel_tiles(lc, rgb, masks, H, W, k, tiles_x, (int)ntiles, ntiles_pad * kTilePix, cscale,
-                                   (float4 *)(ctx->ws + o_pix4)));
-        HIP_TRY(launch_pixel_operands(lc, masks, H, W, k, tiles_x, (int)ntiles, ntiles_pad, KP / 128,
-                                      (uint32_t *)(ctx->ws + o_aop), (uint4 *)(ctx->ws + o_abf)));
+        PrepArgs pr{};
+        pr.recs = recs;
+        pr.k = k;
+        pr.KP = KP;
+        pr.L = L;
+        pr.segs = segs;
+        pr.Mpad = segs.pseg[L];
+        pr.cscale = cscale;
+        pr.feat = (uint8_t *)(ctx->ws + o_feat);
+        pr.rec = (float *)(ctx->ws + o_srec);
+        pr.rgb = rgb;
+        pr.masks = masks;
+        pr.H = H;
+        pr.W = W;
+        pr.tiles_x = tiles_x;
+        pr.ntiles = (int)ntiles;
+        pr.ksteps = KP / 128;
+        pr.ntiles_pad = ntiles_pad;
+        pr.pix4 = (float4 *)(ctx->ws + o_pix4);
+        pr.aop = (uint32_t *)(ctx->ws + o_aop);
+        pr.abf = (uint4 *)(ctx->ws + o_abf);
+        HIP_TRY(launch_prep(lc, pr));
     }
     unsigned int *fcnt = (unsigned int *)(ctx->ws + o_fcnt);
     ParzenArgs pa{};

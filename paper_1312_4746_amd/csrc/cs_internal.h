@@ -53,6 +53,15 @@ struct AnalyzeArgs {
     const float *t_out;   // k thresholds (|a| > t_out: out)
     double tau;
     unsigned long long *recomputed;  // device counter or null
+    // optional: the first workgroup also sets up the median selection that
+    // follows (state, the three digit histograms, per-row margins); null st:
+    // none
+    struct TauState *tau_st;
+    unsigned int *tau_hist3;       // 3 x kHistBins, cleared
+    double *tau_margins;           // k per-row bounds
+    double *tau_max_margin;        // their maximum
+    double tau_coef;
+    unsigned long long tau_rank0;  // target rank
 };
 hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precision);
 
@@ -73,10 +82,15 @@ hipError_t launch_thresholds(const LaunchCtx &lc, const float *omega, int k, int
                              double *margins, double *max_margin, unsigned long long *zero);
 
 // ---- exact median of |alpha| (k_tau.hip) ----
+constexpr int kHistBins = 2048;  // radix digit histogram bins
 struct TauState {
     unsigned long long rank0;     // target rank floor((count-1)/2)
     unsigned long long rank;      // remaining rank inside the current prefix
     unsigned int prefix;          // float bits selected so far
+    // folded selection: prefix and remaining rank after digit d (d = 0: none
+    // yet), written by the kernel that picks digit d, read by the next
+    unsigned int pfx[4];
+    unsigned long long rk[4];
     unsigned int nparts;          // per-workgroup counts of entries below the window
     unsigned long long below;     // their sum (written by the selection)
     unsigned long long ncand;     // candidates found (may exceed capacity)
@@ -94,6 +108,12 @@ constexpr int kTauRank = 1 << 14;
 // Radix select of the float |alpha| of the target rank; the first kernel also
 // writes the largest per-row error bound (coef) of the rows of omega, and the
 // per-row bounds to margins when non-null.
+// The same selection with each digit picked at the start of the next
+// kernel (every workgroup from the complete histogram): the state, the three
+// histograms (hist3, cleared) and the margins come from the analysis kernel
+// before; the third digit is picked by the candidate gather.
+hipError_t tau_digits_folded(const LaunchCtx &lc, const float *alpha, int64_t count, unsigned int *hist3,
+                             TauState *st);
 hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t count,
                             unsigned int *hist, TauState *st, const float *omega, int k, int n,
                             double coef, double *max_margin, double *margins);
@@ -126,7 +146,7 @@ hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p
 hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N, int k,
                               const double *max_margin, const double *margins, double frac, TauState *st,
                               int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
-                              uint64_t *masks);
+                              uint64_t *masks, const unsigned int *hist3);
 // After the exact tau: the listed entries (ridx: room for N*k indices).
 hipError_t median_mask_finish(const LaunchCtx &lc, const float *alpha, const float *rgb, int H, int W, int p,
                               const double *wmask, const float *omega, int k, const int64_t *didx,
@@ -215,15 +235,32 @@ struct ParzenFastArgs {
     // chunk that hold real samples
     int meta[3 * kMaxLabels + 1];
 };
-hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,
-                               const StreamSegs &segs, int64_t Mpad, float cscale, uint8_t *feat, float *rec);
+// The full-image path's per-call preparation (one launch): the sample stream
+// (FP8 features and per-chunk records), the tiled pixel records and the pixel
+// operands of both MFMAs.
+struct PrepArgs {
+    const SampleRec *recs;
+    int k, KP, L;
+    StreamSegs segs;
+    int64_t Mpad;
+    float cscale;
+    uint8_t *feat;
+    float *rec;
+    const float *rgb;
+    const uint64_t *masks;
+    int H, W, tiles_x, ntiles, ksteps;
+    int64_t ntiles_pad;
+    float4 *pix4;
+    uint32_t *aop;
+    uint4 *abf;
+    // set by launch_prep
+    int64_t nslots, nthreads;
+    int b_stream, b_tiles;
+};
+hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a);
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a);
 // Pixel records of the full-image path (nslots = padded tiles x kTilePix).
-hipError_t launch_pixel_tiles(const LaunchCtx &lc, const float *rgb, const uint64_t *masks, int H, int W, int k,
-                              int tiles_x, int ntiles, int64_t nslots, float cscale, float4 *pix4);
 // MFMA pixel operands of the full-image path (ntiles_pad tiles).
-hipError_t launch_pixel_operands(const LaunchCtx &lc, const uint64_t *masks, int H, int W, int k, int tiles_x,
-                                 int ntiles, int64_t ntiles_pad, int ksteps, uint32_t *aop, uint4 *abf);
 hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
 
 // ---- learned surrogate (k_mlp.hip) ----

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
     double *st_mu = gh + (2 * h + 1) * hw;            // TP exact means
     double *st_nu2 = st_mu + TP;                       // TP exact squared norms
     double *st_rinv = st_nu2 + TP;                     // TP values 1/sqrt(nu2) (0 if nu2 = 0)
-    float *s = reinterpret_cast<float *>(st_rinv + TP); // TP x ss FP32 patches
+    double *wm = st_rinv + TP;                         // the n mask weights (read at every t)
+    float *s = reinterpret_cast<float *>(wm + np);     // TP x ss FP32 patches
     uint16_t *mk = reinterpret_cast<uint16_t *>(s + TP * ss);  // TP x 4*W64 pieces
     const int W64 = (a.k + 63) / 64;
 
@@ -85,17 +86,29 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
     const int64_t N = (int64_t)a.H * a.W;
     const int valid_px = min(TP, a.W - c0);
 
-    // 1. FP64 gray halo of the segment.
+    // 1. FP64 gray halo of the segment (all colour loads issued before the
+    // first is used; positions past the row end read pixel 0 and store 0).
+    constexpr int kHalo = (2 * h + 1) * hw, kHaloIt = (kHalo + 255) / 256;
     const int ncols = valid_px + 2 * h;
-    for (int idx = tid; idx < (2 * h + 1) * hw; idx += 256) {
+    float hr[kHaloIt], hg[kHaloIt], hb[kHaloIt];
+#pragma unroll
+    for (int it = 0; it < kHaloIt; ++it) {
+        const int idx = tid + 256 * it;
         const int rr = idx / hw, cc = idx - rr * hw;
-        double g = 0.0;
-        if (cc < ncols) {
-            const int gr = reflect_idx(row - h + rr, a.H), gc = reflect_idx(c0 - h + cc, a.W);
-            g = gray64(a.rgb, N, (int64_t)gr * a.W + gc);
-        }
-        gh[idx] = g;
+        int64_t src = 0;
+        if (idx < kHalo && cc < ncols)
+            src = (int64_t)reflect_idx(row - h + rr, a.H) * a.W + reflect_idx(c0 - h + cc, a.W);
+        hr[it] = a.rgb[src];
+        hg[it] = a.rgb[N + src];
+        hb[it] = a.rgb[2 * N + src];
     }
+#pragma unroll
+    for (int it = 0; it < kHaloIt; ++it) {
+        const int idx = tid + 256 * it;
+        const int cc = idx - (idx / hw) * hw;
+        if (idx < kHalo) gh[idx] = cc < ncols ? gray64_of(hr[it], hg[it], hb[it]) : 0.0;
+    }
+    for (int t = tid; t < n; t += 256) wm[t] = a.wmask[t];
     if (a.masks)
         for (int idx = tid; idx < TP * 4 * W64; idx += 256) mk[idx] = 0;
     __syncthreads();
@@ -106,13 +119,13 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
         double sum = 0.0;
         for (int t = 0; t < n; ++t) {
             const int u = t / P, v = t - u * P;
-            sum = sum + a.wmask[t] * gh[u * hw + i + v];
+            sum = sum + wm[t] * gh[u * hw + i + v];
         }
         const double mu = sum / (double)n;
         double nu2 = 0.0;
         for (int t = 0; t < n; ++t) {
             const int u = t / P, v = t - u * P;
-            const double z = a.wmask[t] * gh[u * hw + i + v] - mu;
+            const double z = wm[t] * gh[u * hw + i + v] - mu;
             nu2 = nu2 + z * z;
         }
         st_mu[i] = mu;
@@ -127,7 +140,7 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
         float sv = 0.0f;
         if (i < valid_px && t < n) {
             const int u = t / P, v = t - u * P;
-            sv = (float)((a.wmask[t] * gh[u * hw + i + v] - st_mu[i]) * st_rinv[i]);
+            sv = (float)((wm[t] * gh[u * hw + i + v] - st_mu[i]) * st_rinv[i]);
         }
         s[i * ss + t] = sv;
     }
@@ -136,16 +149,19 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
     // 4. a = O s on MFMA: wave w owns pixel blocks rb = w, w+4, ...; all j-blocks.
     const int nblk_j = (a.k + 15) / 16;
     unsigned long long nrecomp = 0;
-    // B fragments of j-block jb (FP32 path), loaded one block ahead
+    // B fragments of j-block jb (FP32 path), loaded one block ahead.  The
+    // loads are unconditional (clamped row and column, so the next block's
+    // loads stay in flight under this block's products): a clamped t >= n
+    // meets a zero patch entry, and operator rows past k give outputs that
+    // are not stored.
     float bnext[T::np4 / 4];
     auto load_b = [&](int jb, float (&dst)[T::np4 / 4]) {
         const int jj = jb * 16 + (lane & 15);
-        const bool ok = jb < nblk_j && jj < a.k;
-        const float *o = a.omega + (int64_t)(ok ? jj : 0) * n;
+        const float *o = a.omega + (int64_t)(jj < a.k ? jj : a.k - 1) * n;
 #pragma unroll
         for (int kb = 0; kb < T::np4 / 4; ++kb) {
             const int t = kb * 4 + (lane >> 4);
-            dst[kb] = (ok && t < n) ? o[t] : 0.f;
+            dst[kb] = o[t < n ? t : n - 1];
         }
     };
     if (PREC == CS_FP32) load_b(0, bnext);
@@ -215,7 +231,7 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
                         bool in = av <= tin;
                         const bool out = av > tout;
                         const bool near = !in && !out && pv && jv;
-                        if (near) in = fabs(exact_dot<P>(om, gh, a.wmask, il, st_mu[il], st_nu2[il])) <= a.tau;
+                        if (near) in = fabs(exact_dot<P>(om, gh, wm, il, st_mu[il], st_nu2[il])) <= a.tau;
                         nrecomp += (unsigned long long)__popcll(__ballot(near));
                         const unsigned long long bits = __ballot(in && pv && jv);
                         if (lane < 4)
@@ -236,13 +252,16 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
         }
         if (a.recomputed && lane == 0 && nrecomp) atomicAdd(a.recomputed, nrecomp);
     }
+    // the set-up of the median selection that follows this kernel
+    if (a.tau_st && blockIdx.x == 0 && blockIdx.y == 0)
+        tau_setup(a.tau_st, a.tau_hist3, a.omega, a.k, n, a.tau_coef, a.tau_rank0, a.tau_margins, a.tau_max_margin);
 }
 
 template <int PREC, int P>
 static hipError_t launch_analyze_p(const LaunchCtx &lc, const AnalyzeArgs &a) {
     using T = AnalyzeTile<P>;
     const int W64 = (a.k + 63) / 64;
-    const size_t lds = sizeof(double) * ((size_t)(2 * T::h + 1) * T::hw + 3 * (size_t)T::TP) +
+    const size_t lds = sizeof(double) * ((size_t)(2 * T::h + 1) * T::hw + 3 * (size_t)T::TP + T::np) +
                        sizeof(float) * (size_t)T::TP * T::ss + sizeof(uint16_t) * (size_t)T::TP * 4 * W64;
     dim3 grid((a.W + T::TP - 1) / T::TP, a.H);
     hipError_t e = hipFuncSetAttribute((const void *)k_analyze<PREC, P>,

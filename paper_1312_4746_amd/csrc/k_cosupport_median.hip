@@ -46,13 +46,22 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
                                                             const double *max_margin, const double *margins,
                                                             double frac, TauState *st, int64_t *cand, int64_t cap,
                                                             unsigned long long *parts, int64_t *didx,
-                                                            uint64_t *masks) {
+                                                            uint64_t *masks, const unsigned int *hist3) {
     static_assert(kPx * W64 <= 64, "one mask word per lane");
     __shared__ unsigned long long red[256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the third digit, from its complete histogram: the float v of the target
+    // rank among the rounded |a| (workgroup 0 records it)
+    unsigned int prefix;
+    unsigned long long rank;
+    tau_pick_digit(hist3 + 2 * kHistBins, 0, st->pfx[2], st->rk[2], prefix, rank);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pfx[3] = st->prefix = prefix;
+        st->rk[3] = st->rank = rank;
+    }
     // candidate window [v - 2m, v + 2m] as float bit patterns (non-negative
     // floats order like their bit patterns), as in the separate gather
-    const double v = (double)__uint_as_float(st->prefix);
+    const double v = (double)__uint_as_float(prefix);
     const double mm = *max_margin;
     const double wlo = v - 2.0 * mm, whi = v + 2.0 * mm;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -250,7 +259,7 @@ __global__ __launch_bounds__(64) void k_median_mask_exact(const float *rgb, int 
 hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N, int k,
                               const double *max_margin, const double *margins, double frac, TauState *st,
                               int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
-                              uint64_t *masks) {
+                              uint64_t *masks, const unsigned int *hist3) {
     if (N <= 0) return hipSuccess;
     // kRoundsPerWave rounds per wave (each prefetches the next), more where
     // the per-workgroup counts would not fit
@@ -258,7 +267,7 @@ hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N
     if (blocks > kTauParts) blocks = kTauParts;
 #define CS_MG_LAUNCH(WW)                                                                                    \
     hipLaunchKernelGGL(k_median_mask_gather<WW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, N, \
-                       k, max_margin, margins, frac, st, cand, cap, parts, didx, masks)
+                       k, max_margin, margins, frac, st, cand, cap, parts, didx, masks, hist3)
     switch ((k + 63) / 64) {
         case 1: CS_MG_LAUNCH(1); break;
         case 2: CS_MG_LAUNCH(2); break;

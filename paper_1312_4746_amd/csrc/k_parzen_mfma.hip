@@ -105,10 +105,9 @@ __device__ __forceinline__ int swz(int p, int row) { return (p & ~7) | ((p & 7) 
 // [sy_l, sy_h, sy_l, q_h, q_m, q_l, far, 0] (q = sx^2 + sy^2), then the
 // scaled colours {r, g, b, 0}.  Padding slots have zero features and pieces
 // except far = 2^100.
-__global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int k, int KP, int L,
-                                                       StreamSegs segs, int64_t Mpad, float cscale,
-                                                       uint8_t *feat, float *rec) {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void stream_build(const SampleRec *recs, int k, int KP, int L, const StreamSegs &segs,
+                                             int64_t Mpad, float cscale, uint8_t *feat, float *rec, int bid) {
+    const int64_t s = (int64_t)bid * 256 + threadIdx.x;
     if (s >= Mpad) return;
     int l = 0;
     while (l + 1 < L && s >= segs.pseg[l + 1]) ++l;
@@ -181,22 +180,14 @@ __global__ __launch_bounds__(256) void k_stream_build(const SampleRec *recs, int
     }
 }
 
-hipError_t launch_stream_build(const LaunchCtx &lc, const SampleRec *recs, int k, int KP, int L,
-                               const StreamSegs &segs, int64_t Mpad, float cscale, uint8_t *feat, float *rec) {
-    hipLaunchKernelGGL(k_stream_build, dim3((unsigned)((Mpad + 255) / 256)), dim3(256), 0, lc.stream,
-                       recs, k, KP, L, segs, Mpad, cscale, feat, rec);
-    return hipGetLastError();
-}
-
-
 // Pixel records of the full-image path, tiled like the coefficients
 // ([tile][kTilePix], in-tile index dy * 8 + dx): colours scaled by
 // sqrt(log2(e) / (2 sigma_c^2)) (so that the colour term is minus the squared
 // difference) and the co-support size |A| as a float; zeros outside the image.
-__global__ __launch_bounds__(256) void k_pixel_tiles(const float *rgb, const uint64_t *masks, int H, int W, int k,
-                                                      int tiles_x, int ntiles, int64_t nslots, float cscale,
-                                                      float4 *pix4) {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void pixel_tiles(const float *rgb, const uint64_t *masks, int H, int W, int k,
+                                            int tiles_x, int ntiles, int64_t nslots, float cscale, float4 *pix4,
+                                            int bid) {
+    const int64_t s = (int64_t)bid * 256 + threadIdx.x;
     if (s >= nslots) return;
     const int tile = (int)(s / kTilePix), i = (int)(s - (int64_t)tile * kTilePix);
     const int ty = tile / tiles_x;
@@ -225,10 +216,9 @@ __global__ __launch_bounds__(256) void k_pixel_tiles(const float *rgb, const uin
 //  * BF16 location operand (16 B per lane): K 0..7 [|p|^2 pieces (3), -2 px
 //    pieces (2, each twice), -2 py high] for g = 0, K 8..15 [-2 py high, -2 py
 //    low (twice), 1, 1, 1, 1 (far term), 0] for g = 1, zeros for g >= 2.
-__global__ __launch_bounds__(256) void k_pixel_operands(const uint64_t *masks, int H, int W, int k, int tiles_x,
-                                                         int ntiles, int64_t nthreads, int ksteps, uint32_t *aop,
-                                                         uint4 *abf) {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void pixel_operands(const uint64_t *masks, int H, int W, int k, int tiles_x, int ntiles,
+                                               int64_t nthreads, int ksteps, uint32_t *aop, uint4 *abf, int bid) {
+    const int64_t s = (int64_t)bid * 256 + threadIdx.x;
     if (s >= nthreads) return;
     const int lane = (int)(s & 63);
     const int64_t tr = s >> 6;  // tile * RB + rb
@@ -281,18 +271,31 @@ __global__ __launch_bounds__(256) void k_pixel_operands(const uint64_t *masks, i
     abf[s] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
 }
 
-hipError_t launch_pixel_operands(const LaunchCtx &lc, const uint64_t *masks, int H, int W, int k, int tiles_x,
-                                 int ntiles, int64_t ntiles_pad, int ksteps, uint32_t *aop, uint4 *abf) {
-    const int64_t nthreads = ntiles_pad * kParzenRB * 64;
-    hipLaunchKernelGGL(k_pixel_operands, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, lc.stream, masks, H,
-                       W, k, tiles_x, ntiles, nthreads, ksteps, aop, abf);
-    return hipGetLastError();
+// The per-call preparation of the full-image path in one launch: workgroups
+// [0, b_stream) build the sample stream, the next b_tiles the pixel records,
+// the rest the pixel operands (no dependence between the three).
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+    int b = blockIdx.x;
+    if (b < a.b_stream) {
+        stream_build(a.recs, a.k, a.KP, a.L, a.segs, a.Mpad, a.cscale, a.feat, a.rec, b);
+        return;
+    }
+    b -= a.b_stream;
+    if (b < a.b_tiles) {
+        pixel_tiles(a.rgb, a.masks, a.H, a.W, a.k, a.tiles_x, a.ntiles, a.nslots, a.cscale, a.pix4, b);
+        return;
+    }
+    b -= a.b_tiles;
+    pixel_operands(a.masks, a.H, a.W, a.k, a.tiles_x, a.ntiles, a.nthreads, a.ksteps, a.aop, a.abf, b);
 }
 
-hipError_t launch_pixel_tiles(const LaunchCtx &lc, const float *rgb, const uint64_t *masks, int H, int W, int k,
-                              int tiles_x, int ntiles, int64_t nslots, float cscale, float4 *pix4) {
-    hipLaunchKernelGGL(k_pixel_tiles, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, lc.stream, rgb, masks,
-                       H, W, k, tiles_x, ntiles, nslots, cscale, pix4);
+hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
+    a.nslots = a.ntiles_pad * kTilePix;
+    a.nthreads = a.ntiles_pad * kParzenRB * 64;
+    a.b_stream = (int)((a.Mpad + 255) / 256);
+    a.b_tiles = (int)((a.nslots + 255) / 256);
+    const int64_t blocks = a.b_stream + a.b_tiles + (a.nthreads + 255) / 256;
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
     return hipGetLastError();
 }
 

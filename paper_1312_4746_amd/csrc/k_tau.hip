@@ -22,8 +22,6 @@
 
 namespace cs {
 
-constexpr int kHistBins = 2048;
-
 // Clears the selection state and the histogram, and writes the largest
 // per-row error bound (the half-width of the candidate window).
 __global__ __launch_bounds__(256) void k_tau_init(TauState *st, unsigned long long rank0,
@@ -57,14 +55,27 @@ __global__ __launch_bounds__(256) void k_tau_init(TauState *st, unsigned long lo
 // prefix selected so far.  SUB sub-histograms per workgroup (by lane % SUB)
 // spread the LDS atomics of lanes that fall into the same few bins (first
 // digit); later digits see few matching entries and use one.
+// With pick_hist set the workgroup first picks digit pick_d (at pick_shift)
+// from that complete histogram, from the state after digit pick_d - 1
+// (workgroup 0 records the result for the next kernel).
 template <int SUB>
 __global__ __launch_bounds__(256) void k_tau_hist(const float *alpha, int64_t count, int shift,
-                                                   unsigned int pmask, const TauState *st,
-                                                   unsigned int *hist) {
+                                                   unsigned int pmask, TauState *st,
+                                                   unsigned int *hist, const unsigned int *pick_hist,
+                                                   int pick_shift, int pick_d) {
     __shared__ unsigned int lh[SUB * kHistBins];
+    unsigned int prefix = st->prefix;
+    if (pick_hist) {
+        unsigned long long rank;
+        tau_pick_digit(pick_hist, pick_shift, st->pfx[pick_d - 1], st->rk[pick_d - 1], prefix, rank);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pfx[pick_d] = prefix;
+            st->rk[pick_d] = rank;
+        }
+    }
     for (int i = threadIdx.x; i < SUB * kHistBins; i += 256) lh[i] = 0;
     __syncthreads();
-    const unsigned int pval = st->prefix & pmask;
+    const unsigned int pval = prefix & pmask;
     unsigned int *mine = lh + (threadIdx.x & (SUB - 1)) * kHistBins;
     auto add = [&](float x) {
         const unsigned int key = __float_as_uint(x) & 0x7FFFFFFFu;
@@ -162,7 +173,7 @@ hipError_t tau_first_digit(const LaunchCtx &lc, const float *alpha, int64_t coun
     hipLaunchKernelGGL(k_tau_init, dim3(1), dim3(256), 0, lc.stream, st,
                        (unsigned long long)((count - 1) / 2), hist, omega, k, n, coef, max_margin, margins);
     hipLaunchKernelGGL(k_tau_hist<8>, dim3(hist_blocks(lc, count, 2)), dim3(256), 0, lc.stream, alpha, count, 21,
-                       0u, st, hist);
+                       0u, st, hist, nullptr, 0, 0);
     return tau_pick(lc, hist, 21, st);
 }
 
@@ -175,9 +186,21 @@ hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t cou
     const unsigned int pmasks[2] = {0xFFE00000u, 0xFFFFFC00u};
     for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_tau_hist<1>, dim3(hist_blocks(lc, count, 1)), dim3(256), 0, lc.stream, alpha, count,
-                           shifts[pass], pmasks[pass], st, hist);
+                           shifts[pass], pmasks[pass], st, hist, nullptr, 0, 0);
         if ((e = tau_pick(lc, hist, shifts[pass], st)) != hipSuccess) return e;
     }
+    return hipGetLastError();
+}
+
+hipError_t tau_digits_folded(const LaunchCtx &lc, const float *alpha, int64_t count, unsigned int *hist3,
+                             TauState *st) {
+    unsigned int *h1 = hist3, *h2 = hist3 + kHistBins, *h3 = hist3 + 2 * kHistBins;
+    hipLaunchKernelGGL(k_tau_hist<8>, dim3(hist_blocks(lc, count, 2)), dim3(256), 0, lc.stream, alpha, count, 21,
+                       0u, st, h1, nullptr, 0, 0);
+    hipLaunchKernelGGL(k_tau_hist<1>, dim3(hist_blocks(lc, count, 1)), dim3(256), 0, lc.stream, alpha, count, 10,
+                       0xFFE00000u, st, h2, h1, 21, 1);
+    hipLaunchKernelGGL(k_tau_hist<1>, dim3(hist_blocks(lc, count, 1)), dim3(256), 0, lc.stream, alpha, count, 0,
+                       0xFFFFFC00u, st, h3, h2, 10, 2);
     return hipGetLastError();
 }
 
