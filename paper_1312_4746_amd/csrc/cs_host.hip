@@ -574,9 +574,8 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
                                tau_dev));
         }
         {
-            // the second list reuses the candidate array (the selection is done)
             Timed t(ctx, "cosupport_fix");
-            HIP_TRY(median_mask_finish(lc, alpha, rgb, H, W, p, ctx->wmask, omega, k, didx, marg, st, cand, masks));
+            HIP_TRY(median_mask_finish(lc, alpha, rgb, H, W, p, ctx->wmask, omega, k, didx, marg, st, masks));
         }
         return CS_OK;
     }
@@ -650,7 +649,8 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_fcnt = o_cnt + sizeof(unsigned int) * 2;
     const size_t o_queue = cv.take(sizeof(unsigned int) * kParzenQueues * kQueueStride);  // right after o_tf
     const size_t o_rec = cv.take(sizeof(SampleRec) * (size_t)M);
-    const size_t o_seed = cv.take((size_t)L * N);
+    const size_t seed_bytes = ((size_t)L * N + 15) / 16 * 16;  // cleared in 16-byte words
+    const size_t o_seed = cv.take(seed_bytes);
     const size_t o_col = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_d2 = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_nn = cv.take(sizeof(int32_t) * (size_t)L * N);
@@ -685,7 +685,7 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const int32_t tag = ctx->tag = ctx->tag >= 0x3FFFFFFF ? 1 : ctx->tag + 1;
     {
         Timed t(ctx, "samples");
-        HIP_TRY(launch_sample_count(lc, sample_label, sample_pix, M, L, N, bc, bflags, nblocks));
+        HIP_TRY(launch_sample_count(lc, sample_label, sample_pix, M, L, N, bc, bflags, nblocks, seeds, seed_bytes));
         if (pix_subset) HIP_TRY(launch_check_pix(lc, pix_subset, npix, N, pflags));
         // totals and flags to the host; the exact kernel's and the fast
         // kernel's counters and queues cleared for this call
@@ -699,7 +699,6 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     // the counts, which it needs for the segment layout and the constants.
     {
         Timed t(ctx, "samples");
-        HIP_TRY(launch_fill_u8(lc, seeds, (size_t)L * N, 0));
         HIP_TRY(launch_sample_scatter(lc, sample_label, sample_pix, M, L, H, W, rgb, masks, k, bc,
                                       nblocks, recs, seeds));
     }

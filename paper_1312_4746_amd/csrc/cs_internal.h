@@ -147,10 +147,11 @@ hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N
                               const double *max_margin, const double *margins, double frac, TauState *st,
                               int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
                               uint64_t *masks, const unsigned int *hist3);
-// After the exact tau: the listed entries (ridx: room for N*k indices).
+// After the exact tau: the listed entries, decided in one launch (the rounded
+// value where it is clear of tau by the row margin, else in FP64).
 hipError_t median_mask_finish(const LaunchCtx &lc, const float *alpha, const float *rgb, int H, int W, int p,
                               const double *wmask, const float *omega, int k, const int64_t *didx,
-                              const double *margins, TauState *st, int64_t *ridx, uint64_t *masks);
+                              const double *margins, const TauState *st, uint64_t *masks);
 
 // ---- texture similarity (k_tsm.hip) ----
 hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const uint64_t *B,
@@ -160,9 +161,11 @@ hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const 
 // Host-memory slot that k_sample_scan sets to its tag once totals and flags
 // are visible to the host.
 constexpr int kHostTag = 255;
+// Label counts per chunk of samples, and the per-label seed plane cleared
+// (seed_bytes, a multiple of 16) in the same launch.
 hipError_t launch_sample_count(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
                                int64_t M, int L, int64_t N, int32_t *block_counts,
-                               int32_t *block_flags, int nblocks);
+                               int32_t *block_flags, int nblocks, uint8_t *seeds, size_t seed_bytes);
 hipError_t launch_sample_scan(const LaunchCtx &lc, int32_t *block_counts, int L, int nblocks,
                               const int32_t *block_flags, const int32_t *pix_flags, int npix_blocks,
                               int32_t *totals_flags, unsigned int *zero, int nzero, int32_t *host_out,

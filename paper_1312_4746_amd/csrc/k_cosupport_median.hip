@@ -169,90 +169,78 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
     if (blockIdx.x == 0 && threadIdx.x == 0) st->nparts = gridDim.x;
 }
 
-// Listed entries against the exact tau: decided by the rounded value where it
-// is clear of tau by more than the row margin, else listed again for the FP64
-// decision.
-__global__ __launch_bounds__(256) void k_median_mask_fix(const float *alpha, int k, const int64_t *didx,
-                                                         const double *margins, TauState *st, int64_t *ridx,
-                                                         uint64_t *masks) {
-    const int64_t n = (int64_t)st->n_d;
-    const double tau = st->tau;
-    const int W64 = (k + 63) / 64;
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    const int64_t nr = (n + 255) / 256 * 256;  // whole waves take the ballot together
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nr; q += stride) {
-        const bool live = q < n;
-        int64_t e = 0;
-        bool near = false;
-        if (live) {
-            e = didx[q];
-            const int64_t pix = e / k;
-            const int j = (int)(e - pix * k);
-            const double a = (double)fabsf(alpha[e]);
-            const double m = margins[j];
-            if (a <= tau - m) {
-                atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * W64 + (j >> 6)), 1ull << (j & 63));
-            } else if (!(a > tau + m)) {
-                near = true;  // within the margin, or NaN
-            }
-        }
-        const unsigned long long mb = __ballot(near);
-        if (mb) {
-            const unsigned long long slot = wave_slot(mb, &st->n_r, lane);
-            if (near) ridx[slot] = e;
-        }
-    }
-}
-
-// FP64 decision of the entries listed again, one wave per entry: the exact
-// patch in LDS (element-wise steps across lanes, every sum in lane 0 in t
-// order), then the row product in lane 0.
-__global__ __launch_bounds__(64) void k_median_mask_exact(const float *rgb, int H, int W, int p,
-                                                          const double *wmask, const float *omega, int k,
-                                                          const int64_t *ridx, const TauState *st,
-                                                          uint64_t *masks) {
+// The listed entries against the exact tau, up to 64 per wave: an
+// entry whose rounded |a| is clear of tau by more than its row's margin is
+// decided at once; the few within the margin (or NaN) are recomputed in FP64
+// by the whole wave, one after the other, from the exact patch (Sec. 2 a = O s
+// with the Sec. 3.1 normalised, Gaussian-masked gray patch, in the oracle's
+// operation order) and decided exactly.
+__global__ __launch_bounds__(64) void k_median_mask_finish(const float *alpha, const float *rgb, int H, int W,
+                                                           int p, const double *wmask, const float *omega, int k,
+                                                           const int64_t *didx, const double *margins,
+                                                           const TauState *st, uint64_t *masks) {
     __shared__ double s[15 * 15];
     __shared__ double sh_mu, sh_nu2;
-    const int64_t nr = (int64_t)st->n_r;
+    const int64_t nd = (int64_t)st->n_d;
     const double tau = st->tau;
     const int n = p * p, h = (p - 1) / 2;
     const int64_t N = (int64_t)H * W;
     const int W64 = (k + 63) / 64;
     const int lane = threadIdx.x;
-    for (int64_t c = blockIdx.x; c < nr; c += gridDim.x) {
-        const int64_t e = ridx[c];
-        const int64_t pix = e / k;
-        const int j = (int)(e - pix * k);
-        const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
-        for (int t = lane; t < n; t += 64) {
-            const int u = t / p, vv = t - u * p;
-            const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + vv - h, W);
-            s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
+    // entry q of round q0 is lane (q - q0) / G of wave q mod G (G waves): the
+    // entries of one wave are G apart, so listed neighbours (often near
+    // entries together) fall on different waves
+    const int64_t G = gridDim.x;
+    for (int64_t q0 = 0; q0 < nd; q0 += 64 * G) {
+        const int64_t q = q0 + (int64_t)lane * G + blockIdx.x;
+        int64_t e = 0;
+        bool near = false;
+        if (q < nd) {
+            e = didx[q];
+            const int64_t pix = e / k;
+            const int j = (int)(e - pix * k);
+            const double a = (double)fabsf(alpha[e]);
+            const double m = margins[j];
+            if (a <= tau - m)
+                atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * W64 + (j >> 6)), 1ull << (j & 63));
+            else if (!(a > tau + m))
+                near = true;  // within the margin, or NaN
         }
-        __syncthreads();
-        if (lane == 0) {
-            double sum = 0.0;
-            for (int t = 0; t < n; ++t) sum = sum + s[t];
-            sh_mu = sum / (double)n;
+        for (unsigned long long mb = __ballot(near); mb; mb &= mb - 1) {
+            const int c = __ffsll((long long)mb) - 1;
+            const int64_t ec = __shfl(e, c);
+            const int64_t pix = ec / k;
+            const int j = (int)(ec - pix * k);
+            const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
+            for (int t = lane; t < n; t += 64) {
+                const int u = t / p, vv = t - u * p;
+                const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + vv - h, W);
+                s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
+            }
+            __syncthreads();
+            if (lane == 0) {
+                double sum = 0.0;
+                for (int t = 0; t < n; ++t) sum = sum + s[t];
+                sh_mu = sum / (double)n;
+            }
+            __syncthreads();
+            const double mu = sh_mu;
+            for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
+            __syncthreads();
+            if (lane == 0) {
+                double nu2 = 0.0;
+                for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
+                sh_nu2 = nu2;
+            }
+            __syncthreads();
+            const double nu2 = sh_nu2;
+            const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
+            for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / nu;
+            __syncthreads();
+            if (lane == 0 && fabs(dot64(omega + (int64_t)j * n, s, n)) <= tau)
+                atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * W64 + (j >> 6)), 1ull << (j & 63));
+            __syncthreads();  // s is rewritten by the next entry
         }
-        __syncthreads();
-        const double mu = sh_mu;
-        for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
-        __syncthreads();
-        if (lane == 0) {
-            double nu2 = 0.0;
-            for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
-            sh_nu2 = nu2;
-        }
-        __syncthreads();
-        const double nu2 = sh_nu2;
-        const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
-        for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / nu;
-        __syncthreads();
-        if (lane == 0 && fabs(dot64(omega + (int64_t)j * n, s, n)) <= tau)
-            atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * W64 + (j >> 6)), 1ull << (j & 63));
-        __syncthreads();  // s is rewritten by the next entry
     }
 }
 
@@ -280,11 +268,9 @@ hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N
 
 hipError_t median_mask_finish(const LaunchCtx &lc, const float *alpha, const float *rgb, int H, int W, int p,
                               const double *wmask, const float *omega, int k, const int64_t *didx,
-                              const double *margins, TauState *st, int64_t *ridx, uint64_t *masks) {
-    hipLaunchKernelGGL(k_median_mask_fix, dim3((unsigned)lc.num_cu), dim3(256), 0, lc.stream, alpha, k, didx,
-                       margins, st, ridx, masks);
-    hipLaunchKernelGGL(k_median_mask_exact, dim3((unsigned)lc.num_cu * 8), dim3(64), 0, lc.stream, rgb, H, W, p,
-                       wmask, omega, k, ridx, st, masks);
+                              const double *margins, const TauState *st, uint64_t *masks) {
+    hipLaunchKernelGGL(k_median_mask_finish, dim3((unsigned)lc.num_cu * 8), dim3(64), 0, lc.stream, alpha, rgb, H,
+                       W, p, wmask, omega, k, didx, margins, st, masks);
     return hipGetLastError();
 }
 

@@ -10,11 +10,19 @@ namespace cs {
 constexpr int kChunk = 256;
 
 // Per-chunk label counts (label-major: block_counts[l * nblocks + b]); a chunk
-// with a bad label or pixel sets block_flags[b] = 1 (else 0).
+// with a bad label or pixel sets block_flags[b] = 1 (else 0).  Workgroups past
+// nblocks clear the per-label seed plane (nseed16 16-byte words) instead.
 __global__ __launch_bounds__(kChunk) void k_sample_count(const int32_t *label, const int32_t *pix,
                                                           int64_t M, int L, int64_t N,
                                                           int32_t *block_counts, int32_t *block_flags,
-                                                          int nblocks) {
+                                                          int nblocks, uint4 *seeds16, int64_t nseed16,
+                                                          int nclear) {
+    if ((int)blockIdx.x >= nblocks) {
+        const int64_t stride = (int64_t)nclear * kChunk;
+        for (int64_t i = (int64_t)(blockIdx.x - nblocks) * kChunk + threadIdx.x; i < nseed16; i += stride)
+            seeds16[i] = make_uint4(0u, 0u, 0u, 0u);
+        return;
+    }
     __shared__ int cnt[kMaxLabels];
     __shared__ int bad;
     if (threadIdx.x < kMaxLabels) cnt[threadIdx.x] = 0;
@@ -88,9 +96,14 @@ __global__ __launch_bounds__(1024) void k_sample_scan(int32_t *block_counts, int
 
 hipError_t launch_sample_count(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
                                int64_t M, int L, int64_t N, int32_t *block_counts,
-                               int32_t *block_flags, int nblocks) {
-    hipLaunchKernelGGL(k_sample_count, dim3(nblocks), dim3(kChunk), 0, lc.stream, label, pix, M, L,
-                       N, block_counts, block_flags, nblocks);
+                               int32_t *block_flags, int nblocks, uint8_t *seeds, size_t seed_bytes) {
+    // the seed plane is a multiple of 16 bytes (its caller pads it)
+    const int64_t nseed16 = (int64_t)(seed_bytes / 16);
+    int64_t nclear = (nseed16 + kChunk - 1) / kChunk;
+    if (nclear > (int64_t)lc.num_cu * 4) nclear = (int64_t)lc.num_cu * 4;
+    hipLaunchKernelGGL(k_sample_count, dim3((unsigned)(nblocks + nclear)), dim3(kChunk), 0, lc.stream, label, pix,
+                       M, L, N, block_counts, block_flags, nblocks, reinterpret_cast<uint4 *>(seeds), nseed16,
+                       (int)nclear);
     return hipGetLastError();
 }
 
