@@ -125,23 +125,26 @@ __global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H,
     int32_t *dd = d2 + (int64_t)l * N + (int64_t)r * W;
     int32_t *nn = nearest + (int64_t)l * N + (int64_t)r * W;
     for (int c = threadIdx.x; c < W; c += blockDim.x) {
-        int best = f[c], bq = c;
-        // one block of 16 columns: four 16-byte LDS reads, then the 16
-        // candidates in ascending column order (strict improvement, so the
-        // first best column of the walk wins, as in a one-by-one scan)
+        // The walk keeps only the smallest value and the block that first
+        // reached it (strict improvement); the column is found afterwards in
+        // that block, the first in ascending order with the smallest value.
+        // Ties go as in a one-by-one scan: the own column first, then the
+        // blocks in walk order, then ascending columns.
+        int best = f[c], bb = -1;
         auto scan = [&](int b) {
             const int4 *f4 = reinterpret_cast<const int4 *>(f + b * kRowBlk);
             const int4 v0 = f4[0], v1 = f4[1], v2 = f4[2], v3 = f4[3];
             const int fv[16] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w,
                                 v2.x, v2.y, v2.z, v2.w, v3.x, v3.y, v3.z, v3.w};
+            int m = best;
 #pragma unroll
             for (int i = 0; i < kRowBlk; ++i) {
-                const int q = b * kRowBlk + i;
-                const int v = (c - q) * (c - q) + fv[i];
-                if (v < best) {
-                    best = v;
-                    bq = q;
-                }
+                const int d = c - (b * kRowBlk + i);
+                m = min(m, __mul24(d, d) + fv[i]);
+            }
+            if (m < best) {
+                best = m;
+                bb = b;
             }
         };
         const int cb = c / kRowBlk;
@@ -158,6 +161,13 @@ __global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H,
             if (!lok && !rok) break;
             if (lok && gl * gl + fmin[bl] < best) scan(bl);
             if (rok && gr * gr + fmin[br] < best) scan(br);
+        }
+        int bq = c;
+        if (bb >= 0) {
+            for (int i = kRowBlk - 1; i >= 0; --i) {
+                const int q = bb * kRowBlk + i, d = c - q;
+                if (__mul24(d, d) + f[q] == best) bq = q;
+            }
         }
         if (best >= kInf) {  // no seed of this label anywhere (rejected before launch)
             dd[c] = -1;
