@@ -38,6 +38,8 @@ struct cs_ctx {
     // tag into (a log-likelihood call waits on the tag, not on the stream)
     int32_t *hcounts = nullptr, *hcounts_dev = nullptr;
     int32_t tag = 0;
+    // device counters that are zero between calls (kCtr*)
+    unsigned int *dctr = nullptr;
     // Gaussian patch mask of the last (p, sigma)
     double *wmask = nullptr;
     int wmask_p = 0;
@@ -238,9 +240,13 @@ int cs_create(cs_ctx **out, int device, void *hip_stream) {
         e = hipHostMalloc((void **)&ctx->hcounts, sizeof(int32_t) * (kHostTag + 1),
                           hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&ctx->hcounts_dev, ctx->hcounts, 0);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->dctr, sizeof(unsigned int) * kCtrWords);
+    if (e == hipSuccess) e = launch_fill_u32(lc_of(ctx), ctx->dctr, kCtrWords, 0u);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         if (ctx->pinned) hipHostFree(ctx->pinned);
         if (ctx->hcounts) hipHostFree(ctx->hcounts);
+        if (ctx->dctr) hipFree(ctx->dctr);
         delete ctx;
         return CS_ERR_HIP;
     }
@@ -263,6 +269,7 @@ int cs_destroy(cs_ctx *ctx) {
     if (ctx->wmask) hipFree(ctx->wmask);
     if (ctx->pinned) hipHostFree(ctx->pinned);
     if (ctx->hcounts) hipHostFree(ctx->hcounts);
+    if (ctx->dctr) hipFree(ctx->dctr);
     delete ctx;
     return CS_OK;
 }
@@ -685,14 +692,29 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const int32_t tag = ctx->tag = ctx->tag >= 0x3FFFFFFF ? 1 : ctx->tag + 1;
     {
         Timed t(ctx, "samples");
-        HIP_TRY(launch_sample_count(lc, sample_label, sample_pix, M, L, N, bc, bflags, nblocks, seeds, seed_bytes));
         if (pix_subset) HIP_TRY(launch_check_pix(lc, pix_subset, npix, N, pflags));
-        // totals and flags to the host; the exact kernel's and the fast
-        // kernel's counters and queues cleared for this call
+        // counts, their scan and the totals and flags to the host; the exact
+        // kernel's and the fast kernel's counters and queues cleared for this
+        // call; the seed plane cleared
         ctx->hcounts[kHostTag] = 0;
-        HIP_TRY(launch_sample_scan(lc, bc, L, nblocks, bflags, pflags, npix_blocks, tf, cnt,
-                                   (int)((o_queue - o_cnt) / sizeof(unsigned int)) + kParzenQueues * kQueueStride,
-                                   ctx->hcounts_dev, tag));
+        SampleCountArgs sc{};
+        sc.label = sample_label;
+        sc.pix = sample_pix;
+        sc.M = M;
+        sc.N = N;
+        sc.L = L;
+        sc.nblocks = nblocks;
+        sc.block_counts = bc;
+        sc.block_flags = bflags;
+        sc.pix_flags = pflags;
+        sc.npix_blocks = npix_blocks;
+        sc.totals_flags = tf;
+        sc.zero = cnt;
+        sc.nzero = (int)((o_queue - o_cnt) / sizeof(unsigned int)) + kParzenQueues * kQueueStride;
+        sc.host_out = ctx->hcounts_dev;
+        sc.tag = tag;
+        sc.done = ctx->dctr + kCtrSampleCount;
+        HIP_TRY(launch_sample_count(lc, sc, seeds, seed_bytes));
     }
     // The scatter and the distance transforms need no host decision (invalid
     // samples are skipped on the device): they run while the host waits for

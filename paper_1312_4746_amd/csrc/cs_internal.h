@@ -137,6 +137,9 @@ hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p
                       const double *wmask, const float *omega, int k, const int64_t *cand,
                       int64_t cap, double *vals, double frac, TauState *st, unsigned long long *parts,
                       double *tau_out);
+// Device counters of a context that are zero between calls (each use resets
+// its own): [kCtrSampleCount] the sample-count workgroups done.
+constexpr int kCtrSampleCount = 0, kCtrWords = 64;
 
 // ---- co-support at frac * median|a| fused with the candidate gather
 // (k_cosupport_median.hip) ----
@@ -161,15 +164,28 @@ hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const 
 // Host-memory slot that k_sample_scan sets to its tag once totals and flags
 // are visible to the host.
 constexpr int kHostTag = 255;
-// Label counts per chunk of samples, and the per-label seed plane cleared
-// (seed_bytes, a multiple of 16) in the same launch.
-hipError_t launch_sample_count(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
-                               int64_t M, int L, int64_t N, int32_t *block_counts,
-                               int32_t *block_flags, int nblocks, uint8_t *seeds, size_t seed_bytes);
-hipError_t launch_sample_scan(const LaunchCtx &lc, int32_t *block_counts, int L, int nblocks,
-                              const int32_t *block_flags, const int32_t *pix_flags, int npix_blocks,
-                              int32_t *totals_flags, unsigned int *zero, int nzero, int32_t *host_out,
-                              int32_t tag);
+// Label counts per chunk of samples, their scan and the hand-over of the
+// label totals to the host (host_out, then the tag), and the per-label seed
+// plane cleared (seed_bytes, a multiple of 16), in one launch.
+struct SampleCountArgs {
+    const int32_t *label, *pix;
+    int64_t M, N;
+    int L, nblocks;
+    int32_t *block_counts, *block_flags;
+    const int32_t *pix_flags;  // workgroup flags of the pixel-list check (npix_blocks)
+    int npix_blocks;
+    int32_t *totals_flags;     // device copy of the totals and flags (L + 1)
+    unsigned int *zero;        // counters cleared for the kernels that follow
+    int nzero;
+    int32_t *host_out;         // coherent host memory (device address)
+    int32_t tag;
+    unsigned int *done;        // device counter, zero between calls
+    // set by launch_sample_count
+    uint4 *seeds16;
+    int64_t nseed16;
+    int nclear;
+};
+hipError_t launch_sample_count(const LaunchCtx &lc, SampleCountArgs a, uint8_t *seeds, size_t seed_bytes);
 int check_pix_blocks(const LaunchCtx &lc, int64_t n);
 hipError_t launch_sample_scatter(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
                                  int64_t M, int L, int H, int W, const float *rgb,
@@ -318,6 +334,5 @@ hipError_t launch_mlp_bias_mean(const LaunchCtx &lc, const float *ell, int64_t n
 hipError_t launch_mlp_features(const LaunchCtx &lc, const float *rgb, int H, int W, const float *alpha, int k,
                                const int32_t *pix, int64_t n, float *x);
 hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, unsigned int v);
-hipError_t launch_fill_u8(const LaunchCtx &lc, uint8_t *p, size_t count, uint8_t v);
 
 }  // namespace cs

@@ -9,110 +9,108 @@ namespace cs {
 
 constexpr int kChunk = 256;
 
+// Exclusive scan of block_counts in label-major order (in place), the label
+// totals and the flags (bit 0: a bad sample, bit 1: a bad pixel of the list),
+// by one workgroup (any power-of-two size up to 1024).  Also clears `nzero`
+// words of counters for the kernels that follow, and hands totals and flags
+// to the host: written to host memory (host_out[0..L]) and, after a
+// system-scope fence, host_out[kHostTag] = tag.
+__device__ void sample_scan(int32_t *block_counts, int L, int nblocks, const int32_t *block_flags,
+                            const int32_t *pix_flags, int npix_blocks, int32_t *totals_flags, unsigned int *zero,
+                            int nzero, volatile int32_t *host_out, int32_t tag) {
+    __shared__ int32_t buf[1024];
+    __shared__ int32_t carry, sflags;
+    __shared__ int32_t tot[kMaxLabels];
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int64_t total = (int64_t)L * nblocks;
+    if (tid == 0) {
+        carry = 0;
+        sflags = 0;
+    }
+    for (int i = tid; i < kMaxLabels; i += B) tot[i] = 0;
+    for (int i = tid; i < nzero; i += B) zero[i] = 0u;
+    __syncthreads();
+    int32_t f = 0;
+    for (int i = tid; i < nblocks; i += B) f |= block_flags[i] ? 1 : 0;
+    for (int i = tid; i < npix_blocks; i += B) f |= pix_flags[i] ? 2 : 0;
+    if (f) atomicOr(&sflags, f);
+    for (int64_t base = 0; base < total; base += B) {
+        const int64_t i = base + tid;
+        const int32_t v = i < total ? block_counts[i] : 0;
+        if (i < total) atomicAdd(&tot[i / nblocks], v);
+        buf[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < B; off <<= 1) {  // Hillis-Steele inclusive scan
+            int32_t t = tid >= off ? buf[tid - off] : 0;
+            __syncthreads();
+            buf[tid] += t;
+            __syncthreads();
+        }
+        if (i < total) block_counts[i] = carry + buf[tid] - v;
+        __syncthreads();
+        if (tid == B - 1) carry += buf[B - 1];
+        __syncthreads();
+    }
+    for (int l = tid; l <= L; l += B) {
+        const int32_t v = l < L ? tot[l] : sflags;
+        totals_flags[l] = v;
+        host_out[l] = v;
+    }
+    __threadfence_system();
+    __syncthreads();
+    if (tid == 0) host_out[kHostTag] = tag;
+}
+
 // Per-chunk label counts (label-major: block_counts[l * nblocks + b]); a chunk
-// with a bad label or pixel sets block_flags[b] = 1 (else 0).  Workgroups past
-// nblocks clear the per-label seed plane (nseed16 16-byte words) instead.
-__global__ __launch_bounds__(kChunk) void k_sample_count(const int32_t *label, const int32_t *pix,
-                                                          int64_t M, int L, int64_t N,
-                                                          int32_t *block_counts, int32_t *block_flags,
-                                                          int nblocks, uint4 *seeds16, int64_t nseed16,
-                                                          int nclear) {
-    if ((int)blockIdx.x >= nblocks) {
-        const int64_t stride = (int64_t)nclear * kChunk;
-        for (int64_t i = (int64_t)(blockIdx.x - nblocks) * kChunk + threadIdx.x; i < nseed16; i += stride)
-            seeds16[i] = make_uint4(0u, 0u, 0u, 0u);
+// with a bad label or pixel sets block_flags[b] = 1 (else 0).  The last
+// counting workgroup to finish (a device counter, zero between calls, reset
+// by that workgroup) runs the scan.  Workgroups past nblocks clear the
+// per-label seed plane (nseed16 16-byte words) instead.
+__global__ __launch_bounds__(kChunk) void k_sample_count(SampleCountArgs a) {
+    if ((int)blockIdx.x >= a.nblocks) {
+        const int64_t stride = (int64_t)a.nclear * kChunk;
+        for (int64_t i = (int64_t)(blockIdx.x - a.nblocks) * kChunk + threadIdx.x; i < a.nseed16; i += stride)
+            a.seeds16[i] = make_uint4(0u, 0u, 0u, 0u);
         return;
     }
     __shared__ int cnt[kMaxLabels];
-    __shared__ int bad;
+    __shared__ int bad, s_last;
     if (threadIdx.x < kMaxLabels) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     const int64_t idx = (int64_t)blockIdx.x * kChunk + threadIdx.x;
-    if (idx < M) {
-        const int l = label[idx];
-        const int32_t px = pix[idx];
-        if (l < 0 || l >= L || px < 0 || (int64_t)px >= N)
+    if (idx < a.M) {
+        const int l = a.label[idx];
+        const int32_t px = a.pix[idx];
+        if (l < 0 || l >= a.L || px < 0 || (int64_t)px >= a.N)
             bad = 1;
         else
             atomicAdd(&cnt[l], 1);
     }
     __syncthreads();
-    if (threadIdx.x < L) block_counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
-    if (threadIdx.x == 0) block_flags[blockIdx.x] = bad;
-}
-
-// Exclusive scan of block_counts in label-major order (in place), the label
-// totals and the flags (bit 0: a bad sample, bit 1: a bad pixel of the list),
-// one workgroup.  Also clears `nzero` words of counters for the kernels that
-// follow, and hands totals and flags to the host: written to host memory
-// (host_out[0..L]) and, after a system-scope fence, host_out[kHostTag] = tag.
-__global__ __launch_bounds__(1024) void k_sample_scan(int32_t *block_counts, int L, int nblocks,
-                                                       const int32_t *block_flags, const int32_t *pix_flags,
-                                                       int npix_blocks, int32_t *totals_flags,
-                                                       unsigned int *zero, int nzero,
-                                                       volatile int32_t *host_out, int32_t tag) {
-    __shared__ int32_t buf[1024];
-    __shared__ int32_t carry, sflags;
-    __shared__ int32_t tot[kMaxLabels];
-    const int64_t total = (int64_t)L * nblocks;
+    if (threadIdx.x < a.L) a.block_counts[(int64_t)threadIdx.x * a.nblocks + blockIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x == 0) a.block_flags[blockIdx.x] = bad;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        carry = 0;
-        sflags = 0;
+        __threadfence();  // this workgroup's counts before its done count
+        s_last = atomicAdd(a.done, 1u) == (unsigned int)a.nblocks - 1u;
     }
-    if (threadIdx.x < kMaxLabels) tot[threadIdx.x] = 0;
-    for (int i = threadIdx.x; i < nzero; i += 1024) zero[i] = 0u;
     __syncthreads();
-    int32_t f = 0;
-    for (int i = threadIdx.x; i < nblocks; i += 1024) f |= block_flags[i] ? 1 : 0;
-    for (int i = threadIdx.x; i < npix_blocks; i += 1024) f |= pix_flags[i] ? 2 : 0;
-    if (f) atomicOr(&sflags, f);
-    for (int64_t base = 0; base < total; base += 1024) {
-        const int64_t i = base + threadIdx.x;
-        const int32_t v = i < total ? block_counts[i] : 0;
-        if (i < total) atomicAdd(&tot[i / nblocks], v);
-        buf[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
-            int32_t t = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
-            __syncthreads();
-            buf[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < total) block_counts[i] = carry + buf[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry += buf[1023];
-        __syncthreads();
-    }
-    if ((int)threadIdx.x <= L) {
-        const int32_t v = (int)threadIdx.x < L ? tot[threadIdx.x] : sflags;
-        totals_flags[threadIdx.x] = v;
-        host_out[threadIdx.x] = v;
-    }
-    __threadfence_system();
-    __syncthreads();
-    if (threadIdx.x == 0) host_out[kHostTag] = tag;
+    if (!s_last) return;
+    __threadfence();  // every workgroup's counts
+    if (threadIdx.x == 0) *a.done = 0u;
+    sample_scan(a.block_counts, a.L, a.nblocks, a.block_flags, a.pix_flags, a.npix_blocks, a.totals_flags, a.zero,
+                a.nzero, a.host_out, a.tag);
 }
 
-hipError_t launch_sample_count(const LaunchCtx &lc, const int32_t *label, const int32_t *pix,
-                               int64_t M, int L, int64_t N, int32_t *block_counts,
-                               int32_t *block_flags, int nblocks, uint8_t *seeds, size_t seed_bytes) {
+hipError_t launch_sample_count(const LaunchCtx &lc, SampleCountArgs a, uint8_t *seeds, size_t seed_bytes) {
     // the seed plane is a multiple of 16 bytes (its caller pads it)
-    const int64_t nseed16 = (int64_t)(seed_bytes / 16);
-    int64_t nclear = (nseed16 + kChunk - 1) / kChunk;
+    a.seeds16 = reinterpret_cast<uint4 *>(seeds);
+    a.nseed16 = (int64_t)(seed_bytes / 16);
+    int64_t nclear = (a.nseed16 + kChunk - 1) / kChunk;
     if (nclear > (int64_t)lc.num_cu * 4) nclear = (int64_t)lc.num_cu * 4;
-    hipLaunchKernelGGL(k_sample_count, dim3((unsigned)(nblocks + nclear)), dim3(kChunk), 0, lc.stream, label, pix,
-                       M, L, N, block_counts, block_flags, nblocks, reinterpret_cast<uint4 *>(seeds), nseed16,
-                       (int)nclear);
-    return hipGetLastError();
-}
-
-hipError_t launch_sample_scan(const LaunchCtx &lc, int32_t *block_counts, int L, int nblocks,
-                              const int32_t *block_flags, const int32_t *pix_flags, int npix_blocks,
-                              int32_t *totals_flags, unsigned int *zero, int nzero, int32_t *host_out,
-                              int32_t tag) {
-    hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(1024), 0, lc.stream, block_counts, L, nblocks, block_flags,
-                       pix_flags, npix_blocks, totals_flags, zero, nzero, host_out, tag);
+    a.nclear = (int)nclear;
+    hipLaunchKernelGGL(k_sample_count, dim3((unsigned)(a.nblocks + nclear)), dim3(kChunk), 0, lc.stream, a);
     return hipGetLastError();
 }
 
@@ -171,13 +169,6 @@ __global__ void k_fill_u32(unsigned int *p, size_t count, unsigned int v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }
 
-// 16 bytes per thread and step; the last count % 16 bytes by the first threads
-__global__ void k_fill_u8x16(uint4 *p, size_t count16, unsigned int v4, int rem) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (size_t i = t; i < count16; i += stride) p[i] = make_uint4(v4, v4, v4, v4);
-    if (t < (size_t)rem) reinterpret_cast<uint8_t *>(p + count16)[t] = (uint8_t)v4;
-}
 
 hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, unsigned int v) {
     if (!count) return hipSuccess;
@@ -187,18 +178,6 @@ hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, u
     return hipGetLastError();
 }
 
-// p must be 16-byte aligned (workspace allocations are).
-hipError_t launch_fill_u8(const LaunchCtx &lc, uint8_t *p, size_t count, uint8_t v) {
-    if (!count) return hipSuccess;
-    const unsigned int v4 = 0x01010101u * v;
-    const size_t c16 = count / 16;
-    size_t blocks = (c16 + 255) / 256;
-    if (blocks > (size_t)lc.num_cu * 8) blocks = (size_t)lc.num_cu * 8;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_fill_u8x16, dim3((unsigned)blocks), dim3(256), 0, lc.stream, reinterpret_cast<uint4 *>(p),
-                       c16, v4, (int)(count - c16 * 16));
-    return hipGetLastError();
-}
 
 }  // namespace cs
 
