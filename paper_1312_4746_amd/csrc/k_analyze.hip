@@ -146,90 +146,89 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
     }
     __syncthreads();
 
-    // 4. a = O s on MFMA: wave w owns pixel blocks rb = w, w+4, ...; all j-blocks.
+    // 4. a = O s on MFMA.  Wave w owns the operator row blocks (j-blocks)
+    // w, w + 4, w + 8, ..., taken in pairs (jb, jb + 4); the B fragments of a
+    // pair are loaded once (unconditional loads with clamped row and column: a
+    // clamped t >= n meets a zero patch entry, rows past k give outputs that
+    // are not stored), then every 16-pixel block of the tile streams its A
+    // fragments from LDS past both.
     const int nblk_j = (a.k + 15) / 16;
     unsigned long long nrecomp = 0;
-    // B fragments of j-block jb (FP32 path), loaded one block ahead.  The
-    // loads are unconditional (clamped row and column, so the next block's
-    // loads stay in flight under this block's products): a clamped t >= n
-    // meets a zero patch entry, and operator rows past k give outputs that
-    // are not stored.
-    float bnext[T::np4 / 4];
-    auto load_b = [&](int jb, float (&dst)[T::np4 / 4]) {
-        const int jj = jb * 16 + (lane & 15);
-        const float *o = a.omega + (int64_t)(jj < a.k ? jj : a.k - 1) * n;
+    constexpr int KF = T::np4 / 4, KH = np / 16;  // FP32 and BF16 K steps
+    for (int jp = wave; jp < nblk_j; jp += 8) {
+        const int jbs[2] = {jp, jp + 4};
+        const bool pair = jp + 4 < nblk_j;
+        float bf[2][KF];
+        s16x4 bb[2][KH];
 #pragma unroll
-        for (int kb = 0; kb < T::np4 / 4; ++kb) {
-            const int t = kb * 4 + (lane >> 4);
-            dst[kb] = o[t < n ? t : n - 1];
-        }
-    };
-    if (PREC == CS_FP32) load_b(0, bnext);
-    for (int jb = 0; jb < nblk_j; ++jb) {
-        const int j = jb * 16 + (lane & 15);
-        const bool jv = j < a.k;
-        const float *om = a.omega + (int64_t)(jv ? j : 0) * n;
-        float bf[T::np4 / 4];
-        s16x4 bb[np / 16];
-        if (PREC == CS_FP32) {
-#pragma unroll
-            for (int kb = 0; kb < T::np4 / 4; ++kb) bf[kb] = bnext[kb];
-            load_b(jb + 1, bnext);
-        } else {
-#pragma unroll
-            for (int kb = 0; kb < np / 16; ++kb) {
-                const int t0 = kb * 16 + 4 * (lane >> 4);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) bb[kb][q] = bf16_rne((jv && t0 + q < n) ? om[t0 + q] : 0.f);
-            }
-        }
-        const float tin = (a.masks && jv) ? a.t_in[j] : 0.f;
-        const float tout = (a.masks && jv) ? a.t_out[j] : 0.f;
-        // two 16-pixel blocks per pass (rb and rb + 4): independent MFMA chains
-        for (int rb0 = wave; rb0 < TP / 16; rb0 += 8) {
-            if (rb0 * 16 >= valid_px) break;
-            const int rb1 = rb0 + 4;
-            const bool two = rb1 < TP / 16 && rb1 * 16 < valid_px;
-            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-            const float *srow0 = s + (rb0 * 16 + (lane & 15)) * ss;
-            const float *srow1 = s + ((two ? rb1 : rb0) * 16 + (lane & 15)) * ss;
+        for (int u = 0; u < 2; ++u) {
+            const int jj = jbs[u] * 16 + (lane & 15);
+            const float *o = a.omega + (int64_t)(jj < a.k ? jj : a.k - 1) * n;
             if (PREC == CS_FP32) {
 #pragma unroll
-                for (int kb = 0; kb < T::np4 / 4; ++kb) {
+                for (int kb = 0; kb < KF; ++kb) {
                     const int t = kb * 4 + (lane >> 4);
-                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(srow0[t], bf[kb], acc[0], 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(srow1[t], bf[kb], acc[1], 0, 0, 0);
+                    bf[u][kb] = o[t < n ? t : n - 1];
                 }
             } else {
 #pragma unroll
-                for (int kb = 0; kb < np / 16; ++kb) {
-                    const int t0 = kb * 16 + 4 * (lane >> 4);
-                    s16x4 av0, av1;
+                for (int kb = 0; kb < KH; ++kb)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        av0[q] = bf16_rne(srow0[t0 + q]);
-                        av1[q] = bf16_rne(srow1[t0 + q]);
+                        const int t = kb * 16 + 4 * (lane >> 4) + q;
+                        bb[u][kb][q] = bf16_rne(o[t < n ? t : n - 1]);
                     }
-                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av0, bb[kb], acc[0], 0, 0, 0);
-                    acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av1, bb[kb], acc[1], 0, 0, 0);
+            }
+        }
+        float tin[2], tout[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int j = jbs[u] * 16 + (lane & 15);
+            const bool jv = j < a.k;
+            tin[u] = (a.masks && jv) ? a.t_in[j] : 0.f;
+            tout[u] = (a.masks && jv) ? a.t_out[j] : 0.f;
+        }
+        for (int rb = 0; rb < TP / 16; ++rb) {
+            if (rb * 16 >= valid_px) break;
+            const float *srow = s + (rb * 16 + (lane & 15)) * ss;
+            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            if (PREC == CS_FP32) {
+#pragma unroll
+                for (int kb = 0; kb < KF; ++kb) {
+                    const float av = srow[kb * 4 + (lane >> 4)];
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[0][kb], acc[0], 0, 0, 0);
+                    if (pair) acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[1][kb], acc[1], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int kb = 0; kb < KH; ++kb) {
+                    const int t0 = kb * 16 + 4 * (lane >> 4);
+                    s16x4 av;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) av[q] = bf16_rne(srow[t0 + q]);
+                    acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bb[0][kb], acc[0], 0, 0, 0);
+                    if (pair) acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bb[1][kb], acc[1], 0, 0, 0);
                 }
             }
             // Epilogue: store a and/or decide the co-support bits.
 #pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                if (tt == 1 && !two) break;
-                const int rb = tt == 0 ? rb0 : rb1;
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !pair) break;
+                const int jb = jbs[u];
+                const int j = jb * 16 + (lane & 15);
+                const bool jv = j < a.k;
+                const float *om = a.omega + (int64_t)(jv ? j : 0) * n;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int il = rb * 16 + 4 * (lane >> 4) + r;
                     const bool pv = il < valid_px;
-                    const float v = acc[tt][r];
+                    const float v = acc[u][r];
                     const int64_t pix = (int64_t)row * a.W + c0 + il;
                     if (a.alpha && pv && jv) a.alpha[pix * a.k + j] = v;
                     if (a.masks) {
                         const float av = fabsf(v);
-                        bool in = av <= tin;
-                        const bool out = av > tout;
+                        bool in = av <= tin[u];
+                        const bool out = av > tout[u];
                         const bool near = !in && !out && pv && jv;
                         if (near) in = fabs(exact_dot<P>(om, gh, wm, il, st_mu[il], st_nu2[il])) <= a.tau;
                         nrecomp += (unsigned long long)__popcll(__ballot(near));
