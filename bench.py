@@ -336,7 +336,8 @@ def main():
     achieved = ops / avg_parzen_s
     traffic = None
     tr = load_traffic("parzen_bsds_traffic.json")
-    if tr and tr.get("source_digest") == kernel_source_digest():
+    # counters taken on this kernel source and this workload only
+    if tr and tr.get("source_digest") == kernel_source_digest() and tr.get("workload") == w.name:
         traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
