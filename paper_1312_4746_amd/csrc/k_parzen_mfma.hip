@@ -70,7 +70,7 @@ constexpr float kFarQ = 0x1p100f;      // location feature of padding samples: Q
 // Floats of one chunk's records: location pieces K 0..7 (64 x 16 B), K 8..15
 // (64 x 16 B), colours (64 x float4).
 constexpr int kRecChunkF = kChunkS * 12;
-constexpr int kTailGroups = 32;  // groups at the end of each work queue taken label by label
+constexpr int kTailGroups = 64;  // groups at the end of each work queue taken label by label
 
 // BF16 bit pattern of a float that BF16 holds exactly.
 __device__ __forceinline__ short bf16_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }

@@ -411,3 +411,31 @@ def test_loglik_feature_width_boundary(ctx, k):
     masks, _, _ = oracle.full_masks(w)
     got, ref = _loglik_both(ctx, w, masks)
     _ll_check(got, ref)
+
+
+def test_two_contexts_interleaved(ctx):
+    """Two contexts on one device, their calls interleaved: each context keeps
+    its own device counters, label-count hand-over and work queues, so the
+    results equal those of one context alone (bit for bit)."""
+    from paper_1312_4746_amd import Context, LoglikParams
+    ws = [make_workload("ctx_a", H=40, W=56, R=3, p=5, k=40, seed=21, per_region=20),
+          make_workload("ctx_b", H=33, W=47, R=4, p=7, k=98, seed=22, per_region=15)]
+
+    def run(c, w):
+        rgb = dev(w.rgb)
+        _, m, tau = c.cosupport_median(rgb, w.p, w.mask_sigma, dev(w.omega), 0.1)
+        prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
+                           rho_floor_px=w.rho_floor_px)
+        ll = c.label_loglik(rgb, m, w.k, dev(w.sample_pix), dev(w.sample_label), w.L, prm)
+        return float(tau.item()), m.cpu(), ll.cpu()
+
+    ref = [run(ctx, w) for w in ws]
+    other = Context(0)
+    try:
+        got = [run(other, ws[0]), run(ctx, ws[1]), run(other, ws[1]), run(ctx, ws[0]), run(other, ws[0])]
+    finally:
+        other.close()
+    for (tau, m, ll), i in zip(got, (0, 1, 1, 0, 0)):
+        assert tau == ref[i][0]
+        assert torch.equal(m, ref[i][1])
+        assert torch.equal(ll, ref[i][2])
