@@ -536,7 +536,6 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
         // candidates, their FP64 values, listed mask entries (room for all)
         if ((rc = ensure_cand(ctx, (size_t)count * 24))) return rc;
         TauState *st = (TauState *)(ctx->ws + tw.o_st);
-        unsigned int *hist = (unsigned int *)(ctx->ws + tw.o_hist);
         double *mmax = (double *)(ctx->ws + tw.o_max);
         unsigned long long *parts = (unsigned long long *)(ctx->ws + tw.o_parts);
         double *marg = (double *)(ctx->ws + o_marg);
@@ -544,7 +543,6 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
         double *vals = (double *)(ctx->cand + (size_t)count * 8);
         int64_t *didx = (int64_t *)(ctx->cand + (size_t)count * 16);
         unsigned int *hist3 = (unsigned int *)(ctx->ws + o_hist3);
-        (void)hist;
         {
             AnalyzeArgs a{};
             a.rgb = rgb;
