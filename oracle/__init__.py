@@ -68,6 +68,9 @@ def lib():
         "cso_nearest_d2": (i32, [i32, i32, P, P, i64, i32, P, i64, P]),
         "cso_label_loglik": (i32, [P, i32, i32, P, i32, P, P, i64, i32, dbl, dbl, dbl, dbl, i32,
                                    P, i64, P]),
+        "cso_label_rep": (i32, [P, i64, i32, P, P, i64, i32, P]),
+        "cso_label_loglik_joint": (i32, [P, i32, i32, P, i32, P, P, i64, i32, dbl, dbl, dbl, dbl,
+                                         i32, P, i64, P]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -174,9 +177,24 @@ def nearest_d2(H: int, W: int, sample_pix, sample_label, L: int, pix=None) -> np
     return out
 
 
+def label_rep(masks, k: int, sample_pix, sample_label, L: int) -> np.ndarray:
+    """Textural representative c_i of every label (majority of its samples'
+    co-supports): L x ceil(k/64) uint64."""
+    masks = _c(masks, np.uint64)
+    sp = _c(sample_pix, np.int32)
+    sl = _c(sample_label, np.int32)
+    out = np.empty((L, (k + 63) // 64), dtype=np.uint64)
+    _check(lib().cso_label_rep(_p(masks), masks.shape[0], k, _p(sp), _p(sl), sp.size, L, _p(out)),
+           "cso_label_rep")
+    return out
+
+
 def label_loglik(rgb, masks, k: int, sample_pix, sample_label, L: int, alpha_rho: float = 1.3,
                  sigma_c: float = 0.05, beta_scale: float = 1.0, rho_floor: float = 1.0,
-                 normalise: bool = False, pix=None) -> np.ndarray:
+                 normalise: bool = False, pix=None, joint: bool = False) -> np.ndarray:
+    """joint=False: texture factor per sample inside the Parzen sum;
+    joint=True: colour/location Parzen density times the texture posterior
+    against the label representatives (eq:joined)."""
     rgb = _c(rgb, np.float32)
     _, H, W = rgb.shape
     masks = _c(masks, np.uint64)
@@ -185,9 +203,10 @@ def label_loglik(rgb, masks, k: int, sample_pix, sample_label, L: int, alpha_rho
     pix_a = None if pix is None else _c(pix, np.int32)
     cnt = H * W if pix_a is None else pix_a.size
     out = np.empty((cnt, L), dtype=np.float64)
-    _check(lib().cso_label_loglik(_p(rgb), H, W, _p(masks), k, _p(sp), _p(sl), sp.size, L,
-                                  float(alpha_rho), float(sigma_c), float(beta_scale),
-                                  float(rho_floor), int(bool(normalise)), _p(pix_a), cnt, _p(out)),
+    fn = lib().cso_label_loglik_joint if joint else lib().cso_label_loglik
+    _check(fn(_p(rgb), H, W, _p(masks), k, _p(sp), _p(sl), sp.size, L,
+              float(alpha_rho), float(sigma_c), float(beta_scale),
+              float(rho_floor), int(bool(normalise)), _p(pix_a), cnt, _p(out)),
            "cso_label_loglik")
     return out
 

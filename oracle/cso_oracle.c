@@ -248,6 +248,41 @@ int cso_nearest_d2(int H, int W, const int32_t *sample_pix, const int32_t *sampl
 }
 
 /*
+ * Textural representative of each label (Sec. 2, the majority definition of a
+ * representative's co-support; Sec. 3.1, c_i of the label's samples): bit j
+ * of c_l is set iff at least half of the label's m_l samples have j in their
+ * co-support, 2 * count_j >= m_l.  For binary vectors this is the
+ * component-wise median of eq:approx_cosupp with a tie (even m_l, half the
+ * votes) counted in.  rep: L x ceil(k/64) words, bits k.. zero.
+ */
+int cso_label_rep(const uint64_t *masks, int64_t N, int k, const int32_t *sample_pix,
+                  const int32_t *sample_label, int64_t M, int L, uint64_t *rep) {
+    if (!masks || N < 1 || k < 1 || !sample_pix || !sample_label || M < 1 || L < 1 || !rep)
+        return CSO_ERR_ARG;
+    int words = (k + 63) / 64;
+    int64_t *votes = (int64_t *)calloc((size_t)L * k, sizeof(int64_t));
+    int64_t *m = (int64_t *)calloc((size_t)L, sizeof(int64_t));
+    if (!votes || !m) { free(votes); free(m); return CSO_ERR_NOMEM; }
+    for (int64_t s = 0; s < M; ++s) {
+        int l = sample_label[s];
+        if (l < 0 || l >= L || sample_pix[s] < 0 || sample_pix[s] >= N) {
+            free(votes); free(m); return CSO_ERR_ARG;
+        }
+        m[l]++;
+        for (int j = 0; j < k; ++j) votes[(int64_t)l * k + j] += bit_of(masks + sample_pix[s] * words, j);
+    }
+    for (int l = 0; l < L; ++l) {
+        if (m[l] == 0) { free(votes); free(m); return CSO_ERR_EMPTY_LABEL; }
+        for (int w = 0; w < words; ++w) rep[(int64_t)l * words + w] = 0;
+        for (int j = 0; j < k; ++j)
+            if (2 * votes[(int64_t)l * k + j] >= m[l]) rep[(int64_t)l * words + j / 64] |= (uint64_t)1 << (j % 64);
+    }
+    free(votes);
+    free(m);
+    return CSO_OK;
+}
+
+/*
  * Per-pixel, per-label log-likelihood l_i(x) = -f_i(x) (Sec. 3.1, Sec. 3.2).
  *
  * For label i with samples S_i (m_i = |S_i| >= 1):
@@ -263,10 +298,10 @@ int cso_nearest_d2(int H, int W, const int32_t *sample_pix, const int32_t *sampl
  * masks: co-support masks of every image pixel (N x ceil(k/64) words); each
  * sample's colour, position and mask are those of its pixel.
  */
-int cso_label_loglik(const float *rgb, int H, int W, const uint64_t *masks, int k,
-                     const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
-                     double alpha_rho, double sigma_c, double beta_scale, double rho_floor,
-                     int normalise, const int32_t *pix, int64_t npix, double *out) {
+static int loglik(const float *rgb, int H, int W, const uint64_t *masks, int k,
+                  const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
+                  double alpha_rho, double sigma_c, double beta_scale, double rho_floor,
+                  int normalise, const int32_t *pix, int64_t npix, double *out, int joint) {
     if (!rgb || H <= 0 || W <= 0 || !masks || k < 1 || !sample_pix || !sample_label || M < 1 ||
         L < 1 || !out || !(alpha_rho > 0.0) || !(sigma_c > 0.0) || !(beta_scale > 0.0) ||
         !(rho_floor > 0.0))
@@ -299,6 +334,12 @@ int cso_label_loglik(const float *rgb, int H, int W, const uint64_t *masks, int 
         }
         free(fill);
     }
+    uint64_t *rep = NULL;
+    if (joint) {
+        rep = (uint64_t *)malloc((size_t)L * words * sizeof(uint64_t));
+        if (!rep) { free(count); free(start); free(order); return CSO_ERR_NOMEM; }
+        cso_label_rep(masks, N, k, sample_pix, sample_label, M, L, rep);
+    }
     const double pi = 3.14159265358979323846;
     double col_norm = 1.5 * log(2.0 * pi * sigma_c * sigma_c);
     int bad = 0;
@@ -306,13 +347,14 @@ int cso_label_loglik(const float *rgb, int H, int W, const uint64_t *masks, int 
     {
         double *e = (double *)malloc((size_t)maxm * sizeof(double));
         double *lab = (double *)malloc((size_t)L * sizeof(double));
-        if (!e || !lab) {
+        double *u = (double *)malloc((size_t)L * sizeof(double));
+        if (!e || !lab || !u) {
 #pragma omp atomic write
             bad = 1;
         }
 #pragma omp for schedule(static)
         for (int64_t i = 0; i < cnt; ++i) {
-            if (!e || !lab) continue;
+            if (!e || !lab || !u) continue;
             int64_t px = pix ? pix[i] : i;
             int64_t xr = px / W, xc = px % W;
             double Ir = rgb[px], Ig = rgb[N + px], Ib = rgb[2 * N + px];
@@ -338,14 +380,26 @@ int cso_label_loglik(const float *rgb, int H, int W, const uint64_t *masks, int 
                     double dr = Ir - (double)rgb[y], dg = Ig - (double)rgb[N + y],
                            db = Ib - (double)rgb[2 * N + y];
                     double col2 = dr * dr + dg * dg + db * db;
-                    int t = tsm_pair(mx, masks + y * words, k);
-                    double ev = -loc2 / (2.0 * rho2) - col2 / (2.0 * sigma_c * sigma_c) - (double)t / beta;
+                    double ev = -loc2 / (2.0 * rho2) - col2 / (2.0 * sigma_c * sigma_c);
+                    if (!joint) ev = ev - (double)tsm_pair(mx, masks + y * words, k) / beta;
                     e[q] = ev;
                     if (ev > E) E = ev;
                 }
                 double sum = 0.0;
                 for (int64_t q = 0; q < m; ++q) sum = sum + exp(e[q] - E);
                 lab[l] = E + log(sum) - log((double)m) - log(2.0 * pi * rho2) - col_norm;
+                /* texture exponent of eq:post_text against the label's representative */
+                if (joint) u[l] = -(double)tsm_pair(mx, rep + (int64_t)l * words, k) / beta;
+            }
+            if (joint) {
+                /* log of the texture posterior: u_l - log sum_l' exp(u_l') */
+                double U = -INFINITY;
+                for (int l = 0; l < L; ++l)
+                    if (u[l] > U) U = u[l];
+                double usum = 0.0;
+                for (int l = 0; l < L; ++l) usum = usum + exp(u[l] - U);
+                double lz = U + log(usum);
+                for (int l = 0; l < L; ++l) lab[l] = lab[l] + (u[l] - lz);
             }
             if (normalise) {
                 double Lm = -INFINITY;
@@ -361,9 +415,40 @@ int cso_label_loglik(const float *rgb, int H, int W, const uint64_t *masks, int 
         }
         free(e);
         free(lab);
+        free(u);
     }
+    free(rep);
     free(count);
     free(start);
     free(order);
     return bad ? CSO_ERR_NOMEM : CSO_OK;
+}
+
+int cso_label_loglik(const float *rgb, int H, int W, const uint64_t *masks, int k,
+                     const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
+                     double alpha_rho, double sigma_c, double beta_scale, double rho_floor,
+                     int normalise, const int32_t *pix, int64_t npix, double *out) {
+    return loglik(rgb, H, W, masks, k, sample_pix, sample_label, M, L, alpha_rho, sigma_c,
+                  beta_scale, rho_floor, normalise, pix, npix, out, 0);
+}
+
+/*
+ * The paper's own combination (eq:joined): the colour/location Parzen density
+ * (eq:color) times the texture posterior (eq:post_text),
+ *   l_i(x) = P_i(x) + u_i(x) - log sum_i' exp u_i'(x),
+ *   P_i(x) = log( (1/m_i) sum_{y in S_i} (2 pi rho^2)^-1 (2 pi sigma_c^2)^-3/2
+ *                 exp(-|x-y|^2 / (2 rho^2) - |I(x)-I(y)|^2 / (2 sigma_c^2)) ),
+ *   u_i(x) = -TSM(m_x, c_i) / beta_i(x),
+ * with c_i the label's textural representative (cso_label_rep) and rho, beta
+ * as in cso_label_loglik.  Hard co-supports stand in for the smooth map of
+ * Sec. 2 (its sigma -> 0 limit), so the median of eq:approx_cosupp is the
+ * majority vote.  normalise as in cso_label_loglik, applied last.
+ */
+int cso_label_loglik_joint(const float *rgb, int H, int W, const uint64_t *masks, int k,
+                           const int32_t *sample_pix, const int32_t *sample_label, int64_t M,
+                           int L, double alpha_rho, double sigma_c, double beta_scale,
+                           double rho_floor, int normalise, const int32_t *pix, int64_t npix,
+                           double *out) {
+    return loglik(rgb, H, W, masks, k, sample_pix, sample_label, M, L, alpha_rho, sigma_c,
+                  beta_scale, rho_floor, normalise, pix, npix, out, 1);
 }
