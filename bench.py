@@ -94,7 +94,7 @@ def precision_sweep(ctx, w, rgb, om, alpha, spix, slab, prm):
     return {"tau": tau, "proven_margin_max": st["max_margin"], "rows": rows}
 
 
-def cpu_baseline(w, n_sample: int):
+def cpu_baseline(w, n_sample: int, joint: bool = False):
     """The FP64 oracle on the host: full-image analysis, tau and masks (needed
     for any pixel), then the Parzen log-likelihood on a strided subset of
     pixels; the per-pixel front-end time is scaled to the subset."""
@@ -109,7 +109,7 @@ def cpu_baseline(w, n_sample: int):
     t_front = time.perf_counter() - t0
     pix = np.linspace(0, w.N - 1, n_sample).astype(np.int32)
     t1 = time.perf_counter()
-    oracle.label_loglik(w.rgb, masks, w.k, w.sample_pix, w.sample_label, w.L, pix=pix)
+    oracle.label_loglik(w.rgb, masks, w.k, w.sample_pix, w.sample_label, w.L, pix=pix, joint=joint)
     t_ll = time.perf_counter() - t1
     t_equiv = t_ll + t_front * n_sample / w.N
     pairs = n_sample * w.M
@@ -235,6 +235,9 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--joint", action="store_true",
+                    help="the paper's combination: colour/location Parzen density times the "
+                         "texture posterior against label representatives")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale the HBM "
                          "byte counters of a profiler run")
@@ -286,7 +289,7 @@ def main():
         # trip), then the per-label log-likelihoods of every pixel
         ctx.cosupport_median(rgb, w.p, w.mask_sigma, om, w.tau_frac, precision=w.precision, alpha=alpha,
                              out=masks, tau=tau)
-        ctx.label_loglik(rgb, masks, w.k, spix, slab, w.L, prm, out=ll)
+        ctx.label_loglik(rgb, masks, w.k, spix, slab, w.L, prm, out=ll, joint=args.joint)
 
     for _ in range(args.warmup):
         step()
@@ -337,7 +340,8 @@ def main():
     traffic = None
     tr = load_traffic("parzen_bsds_traffic.json")
     # counters taken on this kernel source and this workload only
-    if tr and tr.get("source_digest") == kernel_source_digest() and tr.get("workload") == w.name:
+    if (tr and not args.joint and tr.get("source_digest") == kernel_source_digest()
+            and tr.get("workload") == w.name):
         traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
@@ -361,7 +365,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, min(args.cpu_sample, w.N))
+        cpu = cpu_baseline(w, min(args.cpu_sample, w.N), joint=args.joint)
 
     out = {
         "metric": "data-term pixel x sample pairs/s",
@@ -376,7 +380,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if w.precision == "fp32" else "bf16+f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "H": w.H, "W": w.W, "p": w.p, "k": w.k, "labels": w.L,
+        "config": {"workload": w.name + ("+joint" if args.joint else ""), "H": w.H, "W": w.W, "p": w.p,
+                   "k": w.k, "labels": w.L,
+                   "texture": "label representatives (eq:joined)" if args.joint else "per sample in the sum",
                    "samples": w.M, "pixels": w.N, "pairs": pairs, "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -193,6 +193,24 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
                     const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
                     float *loglik);
 
+/*
+ * The paper's own combination of the two factors (eq:joined): the colour and
+ * location Parzen density of eq:color times the texture posterior of
+ * eq:post_text,
+ *   l_i(x) = log( 1/m_i * sum_{y in S_i} N2(x; y, rho_i(x)^2) * N3(I(x); I(y), sigma_c^2) )
+ *            + u_i(x) - log sum_i' exp u_i'(x),   u_i(x) = -TSM(x, c_i) / beta_i(x),
+ * where c_i is the textural representative of label i (Sec. 2, majority
+ * definition; Sec. 3.1): bit j of c_i is set iff at least half of the
+ * label's samples have j in their co-support (2 count_j >= m_i, the
+ * component-wise median of eq:approx_cosupp for hard co-supports).  rho_i,
+ * beta_i, the arguments, layouts, ownership, synchronisation and errors are
+ * those of cs_label_loglik; prm->normalise is applied last.
+ */
+int cs_label_loglik_joint(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks,
+                          int k, const int32_t *sample_pix, const int32_t *sample_label, int64_t M,
+                          int L, const cs_loglik_params *prm, const int32_t *pix_subset,
+                          int64_t n_subset, float *loglik);
+
 typedef struct {
     int64_t rescaled_chunks;  /* wave-chunks whose log-sum-exp reference moved up   */
     int64_t overflow_tiles;   /* (label, tile) pairs whose fast sum overflowed       */

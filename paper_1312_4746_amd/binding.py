@@ -53,6 +53,8 @@ SIGNATURES = {
     "cs_texture_similarity": (_I, [_P, _P, _I64, _P, _I64, _I, _P]),
     "cs_label_loglik": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, _I64, _I,
                              ctypes.POINTER(_LoglikParamsC), _P, _I64, _P]),
+    "cs_label_loglik_joint": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, _I64, _I,
+                                   ctypes.POINTER(_LoglikParamsC), _P, _I64, _P]),
     "cs_last_loglik_stats": (_I, [_P, ctypes.POINTER(_LoglikStatsC)]),
     "cs_profile_enable": (_I, [_P, _I]),
     "cs_profile_only": (_I, [_P, ctypes.c_char_p]),
@@ -258,7 +260,9 @@ class Context:
 
     def label_loglik(self, rgb, masks, k: int, sample_pix, sample_label, L: int,
                      params: Optional[LoglikParams] = None, pix_subset=None,
-                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                     out: Optional[torch.Tensor] = None, joint: bool = False) -> torch.Tensor:
+        """joint=False: cs_label_loglik (texture factor per sample inside the
+        Parzen sum); joint=True: cs_label_loglik_joint (eq:joined)."""
         self._dev(rgb, torch.float32, "rgb")
         self._dev(masks, torch.int64, "masks")
         self._dev(sample_pix, torch.int32, "sample_pix")
@@ -277,11 +281,12 @@ class Context:
             # an empty subset is (non-null pointer, count 0); NULL means every pixel
             subset_ptr = ctypes.c_void_p(sample_pix.data_ptr())
         self._sync_stream()
-        self._check(lib().cs_label_loglik(self._h, _ptr(rgb), H, W, _ptr(masks), k,
-                                          _ptr(sample_pix), _ptr(sample_label), sample_pix.numel(),
-                                          L, ctypes.byref(prm), subset_ptr,
-                                          0 if pix_subset is None else pix_subset.numel(),
-                                          _ptr(out) if out.numel() else None))
+        fn = lib().cs_label_loglik_joint if joint else lib().cs_label_loglik
+        self._check(fn(self._h, _ptr(rgb), H, W, _ptr(masks), k,
+                       _ptr(sample_pix), _ptr(sample_label), sample_pix.numel(),
+                       L, ctypes.byref(prm), subset_ptr,
+                       0 if pix_subset is None else pix_subset.numel(),
+                       _ptr(out) if out.numel() else None))
         return out
 
     def last_loglik_stats(self) -> dict:

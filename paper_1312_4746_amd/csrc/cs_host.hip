@@ -618,10 +618,13 @@ int cs_texture_similarity(cs_ctx *ctx, const uint64_t *A, int64_t na, const uint
     return CS_OK;
 }
 
-int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
-                    const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
-                    const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
-                    float *loglik) {
+// joint = false: the texture factor exp(-TSM/beta) inside the Parzen sum,
+// one per sample; joint = true: eq:joined, the Parzen sum without it times
+// the texture posterior against the label representatives.
+static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
+                        const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
+                        const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
+                        float *loglik, bool joint) {
     if (!ctx) return CS_ERR_ARG;
     if (!rgb || !masks || !sample_pix || !sample_label || !prm)
         return fail(ctx, CS_ERR_ARG, "null pointer argument");
@@ -676,6 +679,7 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     const size_t o_abf = fast ? cv.take((size_t)ntiles_pad * kParzenRB * 64 * 16) : 0;
     const size_t o_coef = cv.take(sizeof(float4) * (size_t)L *
                                   (size_t)(fast ? ntiles_pad * kTilePix : npix));
+    const size_t o_rep = joint ? cv.take(sizeof(uint64_t) * 4 * (size_t)L) : 0;
     int rc = ensure_ws(ctx, cv.off);
     if (rc) return rc;
     int32_t *bc = (int32_t *)(ctx->ws + o_bc), *tf = (int32_t *)(ctx->ws + o_tf);
@@ -799,6 +803,26 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
     }
     std::stable_sort(pa.label_order, pa.label_order + L,
                      [&](int x, int y) { return counts[x] > counts[y]; });
+    pa.texture_in_sum = joint ? 0 : 1;
+    TextureArgs tx{};
+    if (joint) {
+        tx.recs = recs;
+        tx.masks = masks;
+        tx.d2 = d2;
+        tx.subset = pix_subset;
+        tx.rep = (uint64_t *)(ctx->ws + o_rep);
+        tx.loglik = loglik;
+        tx.N = N;
+        tx.npix = npix;
+        tx.k = k;
+        tx.L = L;
+        tx.alpha_rho = prm->alpha_rho;
+        tx.beta_scale = prm->beta_scale;
+        tx.rho_floor = prm->rho_floor_px;
+        for (int l = 0; l <= L; ++l) tx.seg[l] = pa.seg_off[l];
+        Timed t(ctx, "texture_rep");
+        HIP_TRY(launch_label_rep(lc, tx));
+    }
     float4 *coef = (float4 *)(ctx->ws + o_coef);
     pa.coef = coef;
     pa.coef_tiled = fast ? 1 : 0;
@@ -859,11 +883,31 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
         Timed t(ctx, "parzen");
         HIP_TRY(launch_parzen(lc, pa));
     }
+    if (joint) {
+        Timed t(ctx, "texture");
+        HIP_TRY(launch_texture_post(lc, tx));
+    }
     if (prm->normalise) {
         Timed t(ctx, "normalise");
         HIP_TRY(launch_normalise(lc, loglik, npix, L));
     }
     return CS_OK;
+}
+
+int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
+                    const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
+                    const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
+                    float *loglik) {
+    return label_loglik(ctx, rgb, H, W, masks, k, sample_pix, sample_label, M, L, prm, pix_subset,
+                        n_subset, loglik, false);
+}
+
+int cs_label_loglik_joint(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks,
+                          int k, const int32_t *sample_pix, const int32_t *sample_label, int64_t M,
+                          int L, const cs_loglik_params *prm, const int32_t *pix_subset,
+                          int64_t n_subset, float *loglik) {
+    return label_loglik(ctx, rgb, H, W, masks, k, sample_pix, sample_label, M, L, prm, pix_subset,
+                        n_subset, loglik, true);
 }
 
 int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats) {

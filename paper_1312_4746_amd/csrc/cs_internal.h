@@ -219,11 +219,28 @@ struct ParzenArgs {
     int64_t npix;
     int tiles;               // ceil(npix / 64)
     double alpha_rho, sigma_c, beta_scale, rho_floor;
+    int texture_in_sum;      // 0: the texture factor leaves the Parzen sum
     int seg_off[kMaxLabels + 1];
     int label_order[kMaxLabels];
     double kconst[kMaxLabels];  // -log m_i - log(2 pi) - 1.5 log(2 pi sigma_c^2)
 };
 hipError_t launch_parzen(const LaunchCtx &lc, const ParzenArgs &a);
+
+// ---- joint texture factor (k_texture.hip) ----
+struct TextureArgs {
+    const SampleRec *recs;   // samples sorted by label
+    const uint64_t *masks;   // N x ceil(k/64)
+    const int32_t *d2;       // L x N squared distances to the nearest sample
+    const int32_t *subset;   // or null
+    uint64_t *rep;           // L x 4 words, the label representatives
+    float *loglik;           // npix x L, updated in place
+    int64_t N, npix;
+    int k, L;
+    double alpha_rho, beta_scale, rho_floor;
+    int seg[kMaxLabels + 1];
+};
+hipError_t launch_label_rep(const LaunchCtx &lc, const TextureArgs &a);
+hipError_t launch_texture_post(const LaunchCtx &lc, const TextureArgs &a);
 hipError_t launch_coef(const LaunchCtx &lc, const ParzenArgs &a, float4 *coef);
 
 struct StreamSegs {

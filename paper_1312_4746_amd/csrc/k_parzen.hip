@@ -54,6 +54,7 @@ __device__ __forceinline__ float pair_e(float px, float py, float pr, float pg, 
 // Per (label, pixel) coefficients of the pair exponent in log2 units, from
 // the exact nearest-sample distance d (FP64, rounded once):
 //   nA = -log2(e) / (2 rho^2), nB = -log2(e) / beta, rho = alpha_rho max(d, r_f),
+//   (nB = 0 when the texture factor is applied outside the sum, eq:joined),
 //   K  = -log m_i - log(2 pi) - 1.5 log(2 pi sigma_c^2) - log(rho^2),
 //   nR = -R with the log-sum-exp reference R = min(U, e^ + kRefMargin):
 //   U = nA d^2 bounds every exponent from above, e^ is the largest exponent
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(256) void k_coef(ParzenArgs a, float4 *__restrict__
     const double rho2 = a.alpha_rho * a.alpha_rho * dm;
     const double rho = sqrt(rho2);
     const float nA = (float)(-kLog2e / (2.0 * rho2));
-    const float nB = (float)(-kLog2e / (a.beta_scale * rho));
+    const float nB = a.texture_in_sum ? (float)(-kLog2e / (a.beta_scale * rho)) : 0.0f;
     const float K = (float)(a.kconst[l] - log(rho2));
     uint32_t mx[NW], nrec[kRecWords];
 #pragma unroll
