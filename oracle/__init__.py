@@ -69,6 +69,9 @@ def lib():
         "cso_label_loglik": (i32, [P, i32, i32, P, i32, P, P, i64, i32, dbl, dbl, dbl, dbl, i32,
                                    P, i64, P]),
         "cso_label_rep": (i32, [P, i64, i32, P, P, i64, i32, P]),
+        "cso_label_rep_soft": (i32, [P, i64, i32, dbl, P, P, i64, i32, P]),
+        "cso_label_loglik_soft": (i32, [P, i32, i32, P, i32, dbl, P, P, i64, i32, dbl, dbl, dbl,
+                                        dbl, i32, P, i64, P]),
         "cso_label_loglik_joint": (i32, [P, i32, i32, P, i32, P, P, i64, i32, dbl, dbl, dbl, dbl,
                                          i32, P, i64, P]),
     }
@@ -186,6 +189,36 @@ def label_rep(masks, k: int, sample_pix, sample_label, L: int) -> np.ndarray:
     out = np.empty((L, (k + 63) // 64), dtype=np.uint64)
     _check(lib().cso_label_rep(_p(masks), masks.shape[0], k, _p(sp), _p(sl), sp.size, L, _p(out)),
            "cso_label_rep")
+    return out
+
+
+def label_rep_soft(alpha, sigma_iota: float, sample_pix, sample_label, L: int) -> np.ndarray:
+    """Median representative of the smooth co-supports of every label: L x k."""
+    a = _c(alpha, np.float64)
+    sp = _c(sample_pix, np.int32)
+    sl = _c(sample_label, np.int32)
+    out = np.empty((L, a.shape[1]), dtype=np.float64)
+    _check(lib().cso_label_rep_soft(_p(a), a.shape[0], a.shape[1], float(sigma_iota), _p(sp), _p(sl),
+                                    sp.size, L, _p(out)), "cso_label_rep_soft")
+    return out
+
+
+def label_loglik_soft(rgb, alpha, sigma_iota: float, sample_pix, sample_label, L: int,
+                      alpha_rho: float = 1.3, sigma_c: float = 0.05, beta_scale: float = 1.0,
+                      rho_floor: float = 1.0, normalise: bool = False, pix=None) -> np.ndarray:
+    """Joint form with smooth co-supports (eq:map_tsm, eq:tsm, eq:approx_cosupp)."""
+    rgb = _c(rgb, np.float32)
+    _, H, W = rgb.shape
+    a = _c(alpha, np.float64)
+    sp = _c(sample_pix, np.int32)
+    sl = _c(sample_label, np.int32)
+    pix_a = None if pix is None else _c(pix, np.int32)
+    cnt = H * W if pix_a is None else pix_a.size
+    out = np.empty((cnt, L), dtype=np.float64)
+    _check(lib().cso_label_loglik_soft(_p(rgb), H, W, _p(a), a.shape[1], float(sigma_iota), _p(sp),
+                                       _p(sl), sp.size, L, float(alpha_rho), float(sigma_c),
+                                       float(beta_scale), float(rho_floor), int(bool(normalise)),
+                                       _p(pix_a), cnt, _p(out)), "cso_label_loglik_soft")
     return out
 
 

@@ -283,6 +283,43 @@ int cso_label_rep(const uint64_t *masks, int64_t N, int k, const int32_t *sample
 }
 
 /*
+ * Smooth-co-support representative of each label (eq:approx_cosupp; c_i of
+ * Sec. 3.1): c_lj = the median over the label's samples of
+ * iota(a)_j = exp(-a_j^2 / sigma_iota) (eq:map_tsm), taken as the element of
+ * 0-based rank floor(m_l/2) of the ascending values (the upper median: for
+ * 0/1 values it is the majority with a tie counted in, as in cso_label_rep).
+ * alpha: N x k, FP64.  rep: L x k.
+ */
+int cso_label_rep_soft(const double *alpha, int64_t N, int k, double sigma_iota,
+                       const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
+                       double *rep) {
+    if (!alpha || N < 1 || k < 1 || !(sigma_iota > 0.0) || !sample_pix || !sample_label || M < 1 ||
+        L < 1 || !rep)
+        return CSO_ERR_ARG;
+    double *v = (double *)malloc((size_t)M * sizeof(double));
+    if (!v) return CSO_ERR_NOMEM;
+    for (int64_t s = 0; s < M; ++s)
+        if (sample_label[s] < 0 || sample_label[s] >= L || sample_pix[s] < 0 || sample_pix[s] >= N) {
+            free(v); return CSO_ERR_ARG;
+        }
+    for (int l = 0; l < L; ++l) {
+        for (int j = 0; j < k; ++j) {
+            int64_t m = 0;
+            for (int64_t s = 0; s < M; ++s) {
+                if (sample_label[s] != l) continue;
+                double a = alpha[(int64_t)sample_pix[s] * k + j];
+                v[m++] = exp(-(a * a) / sigma_iota);
+            }
+            if (m == 0) { free(v); return CSO_ERR_EMPTY_LABEL; }
+            qsort(v, (size_t)m, sizeof(double), cmp_double);
+            rep[(int64_t)l * k + j] = v[m / 2];
+        }
+    }
+    free(v);
+    return CSO_OK;
+}
+
+/*
  * Per-pixel, per-label log-likelihood l_i(x) = -f_i(x) (Sec. 3.1, Sec. 3.2).
  *
  * For label i with samples S_i (m_i = |S_i| >= 1):
@@ -298,14 +335,19 @@ int cso_label_rep(const uint64_t *masks, int64_t N, int k, const int32_t *sample
  * masks: co-support masks of every image pixel (N x ceil(k/64) words); each
  * sample's colour, position and mask are those of its pixel.
  */
-static int loglik(const float *rgb, int H, int W, const uint64_t *masks, int k,
-                  const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
-                  double alpha_rho, double sigma_c, double beta_scale, double rho_floor,
-                  int normalise, const int32_t *pix, int64_t npix, double *out, int joint) {
-    if (!rgb || H <= 0 || W <= 0 || !masks || k < 1 || !sample_pix || !sample_label || M < 1 ||
+/* joint: 0 texture factor per sample inside the sum (masks), 1 hard label
+ * representatives (masks), 2 smooth co-supports and their median
+ * representatives (alpha, sigma_iota). */
+static int loglik(const float *rgb, int H, int W, const uint64_t *masks, const double *alpha,
+                  double sigma_iota, int k, const int32_t *sample_pix, const int32_t *sample_label,
+                  int64_t M, int L, double alpha_rho, double sigma_c, double beta_scale,
+                  double rho_floor, int normalise, const int32_t *pix, int64_t npix, double *out,
+                  int joint) {
+    if (!rgb || H <= 0 || W <= 0 || k < 1 || !sample_pix || !sample_label || M < 1 ||
         L < 1 || !out || !(alpha_rho > 0.0) || !(sigma_c > 0.0) || !(beta_scale > 0.0) ||
         !(rho_floor > 0.0))
         return CSO_ERR_ARG;
+    if (joint == 2 ? (!alpha || !(sigma_iota > 0.0)) : !masks) return CSO_ERR_ARG;
     int64_t N = (int64_t)H * W;
     int64_t cnt = pix ? npix : N;
     int words = (k + 63) / 64;
@@ -335,10 +377,16 @@ static int loglik(const float *rgb, int H, int W, const uint64_t *masks, int k,
         free(fill);
     }
     uint64_t *rep = NULL;
-    if (joint) {
+    double *crep = NULL;
+    if (joint == 1) {
         rep = (uint64_t *)malloc((size_t)L * words * sizeof(uint64_t));
         if (!rep) { free(count); free(start); free(order); return CSO_ERR_NOMEM; }
         cso_label_rep(masks, N, k, sample_pix, sample_label, M, L, rep);
+    } else if (joint == 2) {
+        crep = (double *)malloc((size_t)L * k * sizeof(double));
+        if (!crep || cso_label_rep_soft(alpha, N, k, sigma_iota, sample_pix, sample_label, M, L, crep)) {
+            free(crep); free(count); free(start); free(order); return CSO_ERR_NOMEM;
+        }
     }
     const double pi = 3.14159265358979323846;
     double col_norm = 1.5 * log(2.0 * pi * sigma_c * sigma_c);
@@ -358,7 +406,7 @@ static int loglik(const float *rgb, int H, int W, const uint64_t *masks, int k,
             int64_t px = pix ? pix[i] : i;
             int64_t xr = px / W, xc = px % W;
             double Ir = rgb[px], Ig = rgb[N + px], Ib = rgb[2 * N + px];
-            const uint64_t *mx = masks + px * words;
+            const uint64_t *mx = masks ? masks + px * words : NULL;
             for (int l = 0; l < L; ++l) {
                 int64_t m = count[l];
                 int64_t d2 = -1;
@@ -389,7 +437,16 @@ static int loglik(const float *rgb, int H, int W, const uint64_t *masks, int k,
                 for (int64_t q = 0; q < m; ++q) sum = sum + exp(e[q] - E);
                 lab[l] = E + log(sum) - log((double)m) - log(2.0 * pi * rho2) - col_norm;
                 /* texture exponent of eq:post_text against the label's representative */
-                if (joint) u[l] = -(double)tsm_pair(mx, rep + (int64_t)l * words, k) / beta;
+                if (joint == 1) u[l] = -(double)tsm_pair(mx, rep + (int64_t)l * words, k) / beta;
+                if (joint == 2) {
+                    /* eq:tsm: l1 distance between the smooth co-supports */
+                    double d = 0.0;
+                    for (int j = 0; j < k; ++j) {
+                        double a = alpha[px * k + j];
+                        d = d + fabs(crep[(int64_t)l * k + j] - exp(-(a * a) / sigma_iota));
+                    }
+                    u[l] = -d / beta;
+                }
             }
             if (joint) {
                 /* log of the texture posterior: u_l - log sum_l' exp(u_l') */
@@ -418,6 +475,7 @@ static int loglik(const float *rgb, int H, int W, const uint64_t *masks, int k,
         free(u);
     }
     free(rep);
+    free(crep);
     free(count);
     free(start);
     free(order);
@@ -428,8 +486,8 @@ int cso_label_loglik(const float *rgb, int H, int W, const uint64_t *masks, int 
                      const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
                      double alpha_rho, double sigma_c, double beta_scale, double rho_floor,
                      int normalise, const int32_t *pix, int64_t npix, double *out) {
-    return loglik(rgb, H, W, masks, k, sample_pix, sample_label, M, L, alpha_rho, sigma_c,
-                  beta_scale, rho_floor, normalise, pix, npix, out, 0);
+    return loglik(rgb, H, W, masks, NULL, 0.0, k, sample_pix, sample_label, M, L, alpha_rho,
+                  sigma_c, beta_scale, rho_floor, normalise, pix, npix, out, 0);
 }
 
 /*
@@ -449,6 +507,25 @@ int cso_label_loglik_joint(const float *rgb, int H, int W, const uint64_t *masks
                            int L, double alpha_rho, double sigma_c, double beta_scale,
                            double rho_floor, int normalise, const int32_t *pix, int64_t npix,
                            double *out) {
-    return loglik(rgb, H, W, masks, k, sample_pix, sample_label, M, L, alpha_rho, sigma_c,
-                  beta_scale, rho_floor, normalise, pix, npix, out, 1);
+    return loglik(rgb, H, W, masks, NULL, 0.0, k, sample_pix, sample_label, M, L, alpha_rho,
+                  sigma_c, beta_scale, rho_floor, normalise, pix, npix, out, 1);
+}
+
+/*
+ * The joint form with the smooth co-support of Sec. 2 (eq:map_tsm), as in
+ * the paper's experiments: iota(a)_j = exp(-a_j^2 / sigma_iota), the texture
+ * distance of eq:tsm (l1 norm of the difference of the smooth co-supports),
+ * the representative c_i of eq:approx_cosupp (cso_label_rep_soft), and
+ *   l_i(x) = P_i(x) + u_i(x) - log sum_i' exp u_i'(x),
+ *   u_i(x) = -|| c_i - iota(a_x) ||_1 / beta_i(x),
+ * with P_i the colour/location density of cso_label_loglik_joint.
+ * alpha: N x k analysed vectors of every pixel (row-major, FP64).
+ */
+int cso_label_loglik_soft(const float *rgb, int H, int W, const double *alpha, int k,
+                          double sigma_iota, const int32_t *sample_pix, const int32_t *sample_label,
+                          int64_t M, int L, double alpha_rho, double sigma_c, double beta_scale,
+                          double rho_floor, int normalise, const int32_t *pix, int64_t npix,
+                          double *out) {
+    return loglik(rgb, H, W, NULL, alpha, sigma_iota, k, sample_pix, sample_label, M, L, alpha_rho,
+                  sigma_c, beta_scale, rho_floor, normalise, pix, npix, out, 2);
 }

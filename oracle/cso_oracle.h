@@ -43,6 +43,14 @@ int cso_label_loglik(const float *rgb, int H, int W, const uint64_t *masks, int 
                      int normalise, const int32_t *pix, int64_t npix, double *out);
 int cso_label_rep(const uint64_t *masks, int64_t N, int k, const int32_t *sample_pix,
                   const int32_t *sample_label, int64_t M, int L, uint64_t *rep);
+int cso_label_rep_soft(const double *alpha, int64_t N, int k, double sigma_iota,
+                       const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
+                       double *rep);
+int cso_label_loglik_soft(const float *rgb, int H, int W, const double *alpha, int k,
+                          double sigma_iota, const int32_t *sample_pix, const int32_t *sample_label,
+                          int64_t M, int L, double alpha_rho, double sigma_c, double beta_scale,
+                          double rho_floor, int normalise, const int32_t *pix, int64_t npix,
+                          double *out);
 int cso_label_loglik_joint(const float *rgb, int H, int W, const uint64_t *masks, int k,
                            const int32_t *sample_pix, const int32_t *sample_label, int64_t M,
                            int L, double alpha_rho, double sigma_c, double beta_scale,
