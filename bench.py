@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 PEAK_LANE_OPS = 157.3e12 / 2
 PEAK_HBM = 8.0e12
 # the Parzen kernel carries timing events on one launch in this many inside the timed region
+# smooth co-support map exp(-a^2 / sigma) of the paper's experiments
+SIGMA_IOTA = 0.01
 PARZEN_EVENT_PERIOD = 8
 PEAK_MFMA = {"fp32": 157.3e12, "bf16": 2.5e15}
 
@@ -94,7 +96,7 @@ def precision_sweep(ctx, w, rgb, om, alpha, spix, slab, prm):
     return {"tau": tau, "proven_margin_max": st["max_margin"], "rows": rows}
 
 
-def cpu_baseline(w, n_sample: int, joint: bool = False):
+def cpu_baseline(w, n_sample: int, joint: bool = False, soft: bool = False):
     """The FP64 oracle on the host: full-image analysis, tau and masks (needed
     for any pixel), then the Parzen log-likelihood on a strided subset of
     pixels; the per-pixel front-end time is scaled to the subset."""
@@ -109,7 +111,10 @@ def cpu_baseline(w, n_sample: int, joint: bool = False):
     t_front = time.perf_counter() - t0
     pix = np.linspace(0, w.N - 1, n_sample).astype(np.int32)
     t1 = time.perf_counter()
-    oracle.label_loglik(w.rgb, masks, w.k, w.sample_pix, w.sample_label, w.L, pix=pix, joint=joint)
+    if soft:
+        oracle.label_loglik_soft(w.rgb, alpha, SIGMA_IOTA, w.sample_pix, w.sample_label, w.L, pix=pix)
+    else:
+        oracle.label_loglik(w.rgb, masks, w.k, w.sample_pix, w.sample_label, w.L, pix=pix, joint=joint)
     t_ll = time.perf_counter() - t1
     t_equiv = t_ll + t_front * n_sample / w.N
     pairs = n_sample * w.M
@@ -235,6 +240,9 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=32768)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--soft", action="store_true",
+                    help="the joint form with smooth co-supports (sigma 0.01) of the stored "
+                         "analysed vectors")
     ap.add_argument("--joint", action="store_true",
                     help="the paper's combination: colour/location Parzen density times the "
                          "texture posterior against label representatives")
@@ -291,6 +299,15 @@ def main():
                              out=masks, tau=tau)
         ctx.label_loglik(rgb, masks, w.k, spix, slab, w.L, prm, out=ll, joint=args.joint)
 
+    def step_soft():
+        # analysis with the analysed vectors stored, then the joint form on
+        # their smooth co-supports (no threshold, no masks)
+        ctx.analyze_patches(rgb, w.p, w.mask_sigma, om, precision=w.precision, out=alpha)
+        ctx.label_loglik_soft(rgb, alpha, SIGMA_IOTA, spix, slab, w.L, prm, out=ll)
+
+    if args.soft:
+        step = step_soft  # noqa: F811
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -340,7 +357,7 @@ def main():
     traffic = None
     tr = load_traffic("parzen_bsds_traffic.json")
     # counters taken on this kernel source and this workload only
-    if (tr and not args.joint and tr.get("source_digest") == kernel_source_digest()
+    if (tr and not (args.joint or args.soft) and tr.get("source_digest") == kernel_source_digest()
             and tr.get("workload") == w.name):
         traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
@@ -365,7 +382,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, min(args.cpu_sample, w.N), joint=args.joint)
+        cpu = cpu_baseline(w, min(args.cpu_sample, w.N), joint=args.joint, soft=args.soft)
 
     out = {
         "metric": "data-term pixel x sample pairs/s",
@@ -380,9 +397,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if w.precision == "fp32" else "bf16+f32",
         "data": "synthetic",
-        "config": {"workload": w.name + ("+joint" if args.joint else ""), "H": w.H, "W": w.W, "p": w.p,
-                   "k": w.k, "labels": w.L,
-                   "texture": "label representatives (eq:joined)" if args.joint else "per sample in the sum",
+        "config": {"workload": w.name + ("+soft" if args.soft else "+joint" if args.joint else ""),
+                   "H": w.H, "W": w.W, "p": w.p, "k": w.k, "labels": w.L,
+                   "texture": ("smooth co-supports, median representatives (eq:map_tsm, eq:joined)"
+                               if args.soft else "label representatives (eq:joined)" if args.joint
+                               else "per sample in the sum"),
                    "samples": w.M, "pixels": w.N, "pairs": pairs, "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -211,6 +211,28 @@ int cs_label_loglik_joint(cs_ctx *ctx, const float *rgb, int H, int W, const uin
                           int L, const cs_loglik_params *prm, const int32_t *pix_subset,
                           int64_t n_subset, float *loglik);
 
+/*
+ * The joint form with the smooth co-support of Sec. 2 (eq:map_tsm), the
+ * setting of the paper's experiments: iota(a)_j = exp(-a_j^2 / sigma_iota)
+ * (the paper uses sigma_iota = 0.01), the texture distance of eq:tsm and the
+ * median representative of eq:approx_cosupp:
+ *   l_i(x) = log( 1/m_i * sum_{y in S_i} N2(x; y, rho_i(x)^2) * N3(I(x); I(y), sigma_c^2) )
+ *            + u_i(x) - log sum_i' exp u_i'(x),   u_i(x) = -||c_i - iota(a_x)||_1 / beta_i(x),
+ * c_ij = the element of rank floor(m_i/2) of the ascending iota(a_y)_j over
+ * the label's samples y (the upper median; for 0/1 values the majority of
+ * cs_label_loglik_joint).
+ *   alpha       device, N*k float32 analysed vectors of every pixel, row-major
+ *               (as written by cs_analyze_patches)
+ *   sigma_iota  > 0 and finite
+ * The other arguments, layouts, ownership, synchronisation and errors are
+ * those of cs_label_loglik (no masks are read); CS_ERR_ARG also for
+ * sigma_iota.
+ */
+int cs_label_loglik_soft(cs_ctx *ctx, const float *rgb, int H, int W, const float *alpha, int k,
+                         double sigma_iota, const int32_t *sample_pix, const int32_t *sample_label,
+                         int64_t M, int L, const cs_loglik_params *prm, const int32_t *pix_subset,
+                         int64_t n_subset, float *loglik);
+
 typedef struct {
     int64_t rescaled_chunks;  /* wave-chunks whose log-sum-exp reference moved up   */
     int64_t overflow_tiles;   /* (label, tile) pairs whose fast sum overflowed       */

@@ -55,6 +55,8 @@ SIGNATURES = {
                              ctypes.POINTER(_LoglikParamsC), _P, _I64, _P]),
     "cs_label_loglik_joint": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, _I64, _I,
                                    ctypes.POINTER(_LoglikParamsC), _P, _I64, _P]),
+    "cs_label_loglik_soft": (_I, [_P, _P, _I, _I, _P, _I, _D, _P, _P, _I64, _I,
+                                  ctypes.POINTER(_LoglikParamsC), _P, _I64, _P]),
     "cs_last_loglik_stats": (_I, [_P, ctypes.POINTER(_LoglikStatsC)]),
     "cs_profile_enable": (_I, [_P, _I]),
     "cs_profile_only": (_I, [_P, ctypes.c_char_p]),
@@ -287,6 +289,39 @@ class Context:
                        L, ctypes.byref(prm), subset_ptr,
                        0 if pix_subset is None else pix_subset.numel(),
                        _ptr(out) if out.numel() else None))
+        return out
+
+    def label_loglik_soft(self, rgb, alpha, sigma_iota: float, sample_pix, sample_label, L: int,
+                          params: Optional[LoglikParams] = None, pix_subset=None,
+                          out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """cs_label_loglik_soft: the joint form with smooth co-supports of the
+        analysed vectors alpha (N x k float32)."""
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(alpha, torch.float32, "alpha")
+        self._dev(sample_pix, torch.int32, "sample_pix")
+        self._dev(sample_label, torch.int32, "sample_label")
+        _, H, W = rgb.shape
+        if alpha.dim() != 2 or alpha.shape[0] != H * W:
+            raise ValueError("alpha must be (H*W, k)")
+        k = alpha.shape[1]
+        params = params or LoglikParams()
+        if pix_subset is not None:
+            self._dev(pix_subset, torch.int32, "pix_subset")
+        npix = H * W if pix_subset is None else pix_subset.numel()
+        if out is None:
+            out = torch.empty((npix, L), dtype=torch.float32, device=rgb.device)
+        self._dev(out, torch.float32, "loglik")
+        prm = params.c()
+        subset_ptr = _ptr(pix_subset)
+        if pix_subset is not None and pix_subset.numel() == 0:
+            subset_ptr = ctypes.c_void_p(sample_pix.data_ptr())
+        self._sync_stream()
+        self._check(lib().cs_label_loglik_soft(self._h, _ptr(rgb), H, W, _ptr(alpha), k,
+                                               float(sigma_iota), _ptr(sample_pix),
+                                               _ptr(sample_label), sample_pix.numel(), L,
+                                               ctypes.byref(prm), subset_ptr,
+                                               0 if pix_subset is None else pix_subset.numel(),
+                                               _ptr(out) if out.numel() else None))
         return out
 
     def last_loglik_stats(self) -> dict:

@@ -618,16 +618,20 @@ int cs_texture_similarity(cs_ctx *ctx, const uint64_t *A, int64_t na, const uint
     return CS_OK;
 }
 
-// joint = false: the texture factor exp(-TSM/beta) inside the Parzen sum,
-// one per sample; joint = true: eq:joined, the Parzen sum without it times
-// the texture posterior against the label representatives.
+// mode 0: the texture factor exp(-TSM/beta) inside the Parzen sum, one per
+// sample; mode 1: eq:joined, the Parzen sum without it times the texture
+// posterior against the hard label representatives; mode 2: the same with
+// smooth co-supports (alpha, sigma_iota) and median representatives.
 static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
                         const int32_t *sample_pix, const int32_t *sample_label, int64_t M, int L,
                         const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
-                        float *loglik, bool joint) {
+                        float *loglik, int mode, const float *alpha = nullptr,
+                        double sigma_iota = 0.0) {
     if (!ctx) return CS_ERR_ARG;
-    if (!rgb || !masks || !sample_pix || !sample_label || !prm)
+    if (!rgb || (mode == 2 ? !alpha : !masks) || !sample_pix || !sample_label || !prm)
         return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    if (mode == 2 && !(sigma_iota > 0.0 && std::isfinite(sigma_iota) && std::isfinite(1.0 / sigma_iota)))
+        return fail(ctx, CS_ERR_ARG, "sigma_iota must be positive and finite");
     if (!loglik && !(pix_subset && n_subset == 0))
         return fail(ctx, CS_ERR_ARG, "loglik must be non-null unless the pixel subset is empty");
     if (H < 1 || W < 1 || H > 32767 || W > 16384)
@@ -679,9 +683,18 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
     const size_t o_abf = fast ? cv.take((size_t)ntiles_pad * kParzenRB * 64 * 16) : 0;
     const size_t o_coef = cv.take(sizeof(float4) * (size_t)L *
                                   (size_t)(fast ? ntiles_pad * kTilePix : npix));
-    const size_t o_rep = joint ? cv.take(sizeof(uint64_t) * 4 * (size_t)L) : 0;
+    const size_t o_rep = mode == 1 ? cv.take(sizeof(uint64_t) * 4 * (size_t)L) : 0;
+    const size_t o_crep = mode == 2 ? cv.take(sizeof(float) * (size_t)L * k) : 0;
+    // smooth mode: the Parzen stages run on all-zero masks (their texture
+    // coefficient is 0, so the masks' values never reach a result)
+    const size_t zwords = (size_t)N * ((k + 63) / 64) * 2;
+    const size_t o_zmask = mode == 2 ? cv.take(sizeof(uint32_t) * zwords) : 0;
     int rc = ensure_ws(ctx, cv.off);
     if (rc) return rc;
+    if (mode == 2) {
+        masks = (const uint64_t *)(ctx->ws + o_zmask);
+        HIP_TRY(launch_fill_u32(lc_of(ctx), (unsigned int *)(ctx->ws + o_zmask), zwords, 0u));
+    }
     int32_t *bc = (int32_t *)(ctx->ws + o_bc), *tf = (int32_t *)(ctx->ws + o_tf);
     unsigned int *cnt = (unsigned int *)(ctx->ws + o_cnt);
     SampleRec *recs = (SampleRec *)(ctx->ws + o_rec);
@@ -803,9 +816,9 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
     }
     std::stable_sort(pa.label_order, pa.label_order + L,
                      [&](int x, int y) { return counts[x] > counts[y]; });
-    pa.texture_in_sum = joint ? 0 : 1;
+    pa.texture_in_sum = mode == 0 ? 1 : 0;
     TextureArgs tx{};
-    if (joint) {
+    if (mode != 0) {
         tx.recs = recs;
         tx.masks = masks;
         tx.d2 = d2;
@@ -819,9 +832,13 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         tx.alpha_rho = prm->alpha_rho;
         tx.beta_scale = prm->beta_scale;
         tx.rho_floor = prm->rho_floor_px;
+        tx.W = W;
+        tx.alpha = alpha;
+        tx.crep = mode == 2 ? (float *)(ctx->ws + o_crep) : nullptr;
+        tx.inv_sigma = (float)(1.0 / sigma_iota);
         for (int l = 0; l <= L; ++l) tx.seg[l] = pa.seg_off[l];
         Timed t(ctx, "texture_rep");
-        HIP_TRY(launch_label_rep(lc, tx));
+        HIP_TRY(mode == 2 ? launch_label_rep_soft(lc, tx) : launch_label_rep(lc, tx));
     }
     float4 *coef = (float4 *)(ctx->ws + o_coef);
     pa.coef = coef;
@@ -883,9 +900,9 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         Timed t(ctx, "parzen");
         HIP_TRY(launch_parzen(lc, pa));
     }
-    if (joint) {
+    if (mode != 0) {
         Timed t(ctx, "texture");
-        HIP_TRY(launch_texture_post(lc, tx));
+        HIP_TRY(mode == 2 ? launch_texture_post_soft(lc, tx) : launch_texture_post(lc, tx));
     }
     if (prm->normalise) {
         Timed t(ctx, "normalise");
@@ -899,7 +916,7 @@ int cs_label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t 
                     const cs_loglik_params *prm, const int32_t *pix_subset, int64_t n_subset,
                     float *loglik) {
     return label_loglik(ctx, rgb, H, W, masks, k, sample_pix, sample_label, M, L, prm, pix_subset,
-                        n_subset, loglik, false);
+                        n_subset, loglik, 0);
 }
 
 int cs_label_loglik_joint(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks,
@@ -907,7 +924,15 @@ int cs_label_loglik_joint(cs_ctx *ctx, const float *rgb, int H, int W, const uin
                           int L, const cs_loglik_params *prm, const int32_t *pix_subset,
                           int64_t n_subset, float *loglik) {
     return label_loglik(ctx, rgb, H, W, masks, k, sample_pix, sample_label, M, L, prm, pix_subset,
-                        n_subset, loglik, true);
+                        n_subset, loglik, 1);
+}
+
+int cs_label_loglik_soft(cs_ctx *ctx, const float *rgb, int H, int W, const float *alpha, int k,
+                         double sigma_iota, const int32_t *sample_pix, const int32_t *sample_label,
+                         int64_t M, int L, const cs_loglik_params *prm, const int32_t *pix_subset,
+                         int64_t n_subset, float *loglik) {
+    return label_loglik(ctx, rgb, H, W, nullptr, k, sample_pix, sample_label, M, L, prm, pix_subset,
+                        n_subset, loglik, 2, alpha, sigma_iota);
 }
 
 int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats) {

@@ -235,12 +235,18 @@ struct TextureArgs {
     uint64_t *rep;           // L x 4 words, the label representatives
     float *loglik;           // npix x L, updated in place
     int64_t N, npix;
-    int k, L;
+    int k, L, W;
     double alpha_rho, beta_scale, rho_floor;
+    // smooth co-supports: analysed vectors N x k, representatives L x k
+    const float *alpha;
+    float *crep;
+    float inv_sigma;         // 1 / sigma of the smooth map
     int seg[kMaxLabels + 1];
 };
 hipError_t launch_label_rep(const LaunchCtx &lc, const TextureArgs &a);
 hipError_t launch_texture_post(const LaunchCtx &lc, const TextureArgs &a);
+hipError_t launch_label_rep_soft(const LaunchCtx &lc, const TextureArgs &a);
+hipError_t launch_texture_post_soft(const LaunchCtx &lc, const TextureArgs &a);
 hipError_t launch_coef(const LaunchCtx &lc, const ParzenArgs &a, float4 *coef);
 
 struct StreamSegs {

@@ -21,6 +21,17 @@
 // kernel moves 12 L + 8 ceil(k/64) bytes (the row of L log-likelihoods read
 // and written once, L distances, the mask): HBM-bound.
 
+//
+// Smooth co-supports (eq:map_tsm, the setting of the paper's experiments).
+// iota(a)_j = exp(-a_j^2 / sigma); c_lj = the median of iota_j over the
+// label's samples (eq:approx_cosupp), the element of rank floor(m/2) of the
+// ascending values; u_i = -||c_i - iota(a_x)||_1 / beta_i(x) (eq:tsm).  The
+// median is an exact radix selection on the FP32 bit patterns (non-negative
+// values order as unsigned integers): one workgroup per (component, label),
+// four 8-bit digit passes with an LDS histogram, the digit found by one
+// wave's prefix scan.  The posterior kernel keeps the L distances of a pixel
+// in registers while it streams the pixel's k analysed values once.
+
 #include "cs_internal.h"
 
 namespace cs {
@@ -111,6 +122,173 @@ __global__ __launch_bounds__(256) void k_texture_post(TextureArgs a) {
     const float lz = um + logf(s);
     float *row = a.loglik + i * a.L;
     for (int l = 0; l < a.L; ++l) row[l] += u_of(l) - lz;
+}
+
+__device__ __forceinline__ uint32_t soft_bits(const TextureArgs &a, int s, int j) {
+    const uint32_t *rw = a.recs[s].w;
+    const int64_t pix = (int64_t)__uint_as_float(rw[1]) * a.W + (int64_t)__uint_as_float(rw[0]);
+    const float v = a.alpha[pix * a.k + j];
+    return __float_as_uint(expf(-(v * v) * a.inv_sigma));
+}
+
+// Values a thread keeps in registers across the four digit passes (labels of
+// up to 256 kRepCache samples; larger ones recompute them each pass).
+constexpr int kRepCache = 8;
+
+__global__ __launch_bounds__(256) void k_label_rep_soft(TextureArgs a) {
+    const int j = blockIdx.x, l = blockIdx.y;
+    const int s0 = a.seg[l], m = a.seg[l + 1] - s0;
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_prefix, s_rank;
+    const bool cached = m <= 256 * kRepCache;
+    uint32_t cache[kRepCache];
+    if (cached) {
+        // clamped indices (m >= 1): every load is in bounds and independent
+#pragma unroll
+        for (int q = 0; q < kRepCache; ++q) {
+            const int s = (int)threadIdx.x + 256 * q;
+            cache[q] = soft_bits(a, s0 + (s < m ? s : m - 1), j);
+        }
+    }
+    uint32_t prefix = 0u, mask = 0u, rank = (uint32_t)(m / 2);
+#pragma unroll 1
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        hist[threadIdx.x] = 0u;
+        __syncthreads();
+        if (cached) {
+#pragma unroll
+            for (int q = 0; q < kRepCache; ++q) {
+                const int s = (int)threadIdx.x + 256 * q;
+                const uint32_t v = cache[q];
+                if (s < m && (v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+            }
+        } else {
+            for (int s = threadIdx.x; s < m; s += 256) {
+                const uint32_t v = soft_bits(a, s0 + s, j);
+                if ((v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int t = threadIdx.x;
+            const uint32_t h0 = hist[4 * t], h1 = hist[4 * t + 1], h2 = hist[4 * t + 2], h3 = hist[4 * t + 3];
+            const uint32_t c = h0 + h1 + h2 + h3;
+            uint32_t incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o);
+                if (t >= o) incl += y;
+            }
+            const uint32_t excl = incl - c;
+            // the values matching the prefix number at least rank + 1, so
+            // exactly one lane holds the rank
+            if (rank >= excl && rank < incl) {
+                uint32_t rr = rank - excl;
+                int d = 0;
+                if (rr >= h0) { rr -= h0; d = 1;
+                    if (rr >= h1) { rr -= h1; d = 2;
+                        if (rr >= h2) { rr -= h2; d = 3; } } }
+                s_prefix = prefix | ((uint32_t)(4 * t + d) << shift);
+                s_rank = rr;
+            }
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        rank = s_rank;
+        mask |= 255u << shift;
+    }
+    if (threadIdx.x == 0) a.crep[l * a.k + j] = __uint_as_float(prefix);
+}
+
+// LM: compile-time bound on the label count (registers for the distances).
+template <int LM>
+__global__ __launch_bounds__(256) void k_texture_post_soft(TextureArgs a) {
+    extern __shared__ float screp[];  // L x k
+    for (int t = threadIdx.x; t < a.L * a.k; t += 256) screp[t] = a.crep[t];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.npix) return;
+    const int64_t pix = a.subset ? (int64_t)a.subset[i] : i;
+    const float *ax = a.alpha + pix * a.k;
+    float d[LM];
+#pragma unroll
+    for (int l = 0; l < LM; ++l) d[l] = 0.0f;
+    // the row streams in chunks of 8 values, the next chunk's loads in
+    // flight while the current one is consumed
+    auto add = [&](const float (&v)[8], int j0, int nv) {
+        float io[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) io[c] = expf(-(v[c] * v[c]) * a.inv_sigma);
+#pragma unroll
+        for (int l = 0; l < LM; ++l) {
+            if (l < a.L) {
+                const float *cr = screp + l * a.k + j0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (c < nv) d[l] += fabsf(cr[c] - io[c]);
+            }
+        }
+    };
+    const int k8 = a.k & ~7;
+    float nxt[8];
+    if (k8 > 0) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) nxt[c] = ax[c];
+    }
+    for (int j0 = 0; j0 < k8; j0 += 8) {
+        float cur[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cur[c] = nxt[c];
+        if (j0 + 8 < k8) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) nxt[c] = ax[j0 + 8 + c];
+        }
+        add(cur, j0, 8);
+    }
+    if (k8 < a.k) {
+        const int nv = a.k - k8;
+        float tl[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) tl[c] = ax[k8 + (c < nv ? c : 0)];
+        add(tl, k8, nv);
+    }
+    const double fl2 = a.rho_floor * a.rho_floor;
+    float um = -INFINITY;
+#pragma unroll
+    for (int l = 0; l < LM; ++l) {
+        if (l < a.L) {
+            const double d2 = (double)a.d2[(int64_t)l * a.N + pix];
+            const double rho = a.alpha_rho * sqrt(d2 > fl2 ? d2 : fl2);
+            d[l] = (float)(-(double)d[l] / (a.beta_scale * rho));
+            um = fmaxf(um, d[l]);
+        }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int l = 0; l < LM; ++l)
+        if (l < a.L) s += expf(d[l] - um);
+    const float lz = um + logf(s);
+    float *row = a.loglik + i * a.L;
+#pragma unroll
+    for (int l = 0; l < LM; ++l)
+        if (l < a.L) row[l] += d[l] - lz;
+}
+
+hipError_t launch_label_rep_soft(const LaunchCtx &lc, const TextureArgs &a) {
+    hipLaunchKernelGGL(k_label_rep_soft, dim3((unsigned)a.k, (unsigned)a.L), dim3(256), 0, lc.stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_texture_post_soft(const LaunchCtx &lc, const TextureArgs &a) {
+    if (!a.npix) return hipSuccess;
+    const dim3 grid((unsigned)((a.npix + 255) / 256));
+    const size_t lds = sizeof(float) * (size_t)a.L * a.k;
+    if (a.L <= 16)
+        hipLaunchKernelGGL(k_texture_post_soft<16>, grid, dim3(256), lds, lc.stream, a);
+    else
+        hipLaunchKernelGGL(k_texture_post_soft<kMaxLabels>, grid, dim3(256), lds, lc.stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_label_rep(const LaunchCtx &lc, const TextureArgs &a) {
