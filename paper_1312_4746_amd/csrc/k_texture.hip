@@ -36,8 +36,12 @@
 
 namespace cs {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kRepThreads = 1024;
 constexpr int kRepWaves = kRepThreads / 64;
+// Threads per workgroup of the posterior kernels (one thread per pixel).
+constexpr int kPostThreads = 256;
 
 __global__ __launch_bounds__(kRepThreads) void k_label_rep(TextureArgs a) {
     const int l = blockIdx.x;
@@ -83,11 +87,11 @@ __global__ __launch_bounds__(kRepThreads) void k_label_rep(TextureArgs a) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_texture_post(TextureArgs a) {
+__global__ __launch_bounds__(kPostThreads) void k_texture_post(TextureArgs a) {
     __shared__ uint64_t srep[kMaxLabels * 4];
-    for (int t = threadIdx.x; t < a.L * 4; t += 256) srep[t] = a.rep[t];
+    for (int t = threadIdx.x; t < a.L * 4; t += kPostThreads) srep[t] = a.rep[t];
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kPostThreads + threadIdx.x;
     if (i >= a.npix) return;
     const int64_t pix = a.subset ? (int64_t)a.subset[i] : i;
     const int W64 = (a.k + 63) / 64;
@@ -202,20 +206,28 @@ __global__ __launch_bounds__(256) void k_label_rep_soft(TextureArgs a) {
 }
 
 // LM: compile-time bound on the label count (registers for the distances).
-template <int LM>
-__global__ __launch_bounds__(256) void k_texture_post_soft(TextureArgs a) {
-    extern __shared__ float screp[];  // L x k
-    for (int t = threadIdx.x; t < a.L * a.k; t += 256) screp[t] = a.crep[t];
+// BUF: the analysed vectors are read with 16-byte buffer loads through one
+// resource over the whole array (its size below 2^32 bytes), else with
+// 4-byte global loads.
+// The representatives sit in LDS with rows padded to a multiple of 8 values,
+// so a chunk of 8 arrives with two 16-byte broadcast reads.
+template <int LM, bool BUF>
+__global__ __launch_bounds__(kPostThreads) void k_texture_post_soft(TextureArgs a) {
+    extern __shared__ f32x4 screp4[];  // L x kp/4
+    const int kp = (a.k + 7) & ~7;
+    float *screp = reinterpret_cast<float *>(screp4);
+    for (int t = threadIdx.x; t < a.L * kp; t += kPostThreads) {
+        const int l = t / kp, j = t - l * kp;
+        screp[t] = j < a.k ? a.crep[l * a.k + j] : 0.0f;
+    }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kPostThreads + threadIdx.x;
     if (i >= a.npix) return;
     const int64_t pix = a.subset ? (int64_t)a.subset[i] : i;
     const float *ax = a.alpha + pix * a.k;
     float d[LM];
 #pragma unroll
     for (int l = 0; l < LM; ++l) d[l] = 0.0f;
-    // the row streams in chunks of 8 values, the next chunk's loads in
-    // flight while the current one is consumed
     auto add = [&](const float (&v)[8], int j0, int nv) {
         float io[8];
 #pragma unroll
@@ -223,35 +235,74 @@ __global__ __launch_bounds__(256) void k_texture_post_soft(TextureArgs a) {
 #pragma unroll
         for (int l = 0; l < LM; ++l) {
             if (l < a.L) {
-                const float *cr = screp + l * a.k + j0;
+                const f32x4 c0 = screp4[(l * kp + j0) / 4], c1 = screp4[(l * kp + j0) / 4 + 1];
+                const float cr[8] = {c0[0], c0[1], c0[2], c0[3], c1[0], c1[1], c1[2], c1[3]};
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
                     if (c < nv) d[l] += fabsf(cr[c] - io[c]);
             }
         }
     };
-    const int k8 = a.k & ~7;
-    float nxt[8];
-    if (k8 > 0) {
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)a.alpha, (short)0, (int)((uint32_t)(a.N * a.k * 4)), 0x00020000);
+        const int vo = (int)((uint32_t)(pix * a.k * 4));
+        auto ld8 = [&](int j0, float (&v)[8]) {
+            const f32x4 lo = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 4 * j0, 0, 0));
+            const f32x4 hi = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 4 * j0 + 16, 0, 0));
 #pragma unroll
-        for (int c = 0; c < 8; ++c) nxt[c] = ax[c];
-    }
-    for (int j0 = 0; j0 < k8; j0 += 8) {
-        float cur[8];
+            for (int c = 0; c < 4; ++c) {
+                v[c] = lo[c];
+                v[4 + c] = hi[c];
+            }
+        };
+        // whole chunks with 16-byte loads (inside the row, so inside the
+        // resource), the tail with 4-byte loads clamped to the row
+        const int k8 = a.k & ~7;
+        float nxt[8];
+        if (k8 > 0) ld8(0, nxt);
+        for (int j0 = 0; j0 < k8; j0 += 8) {
+            float cur[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) cur[c] = nxt[c];
-        if (j0 + 8 < k8) {
-#pragma unroll
-            for (int c = 0; c < 8; ++c) nxt[c] = ax[j0 + 8 + c];
+            for (int c = 0; c < 8; ++c) cur[c] = nxt[c];
+            if (j0 + 8 < k8) ld8(j0 + 8, nxt);
+            add(cur, j0, 8);
         }
-        add(cur, j0, 8);
-    }
-    if (k8 < a.k) {
-        const int nv = a.k - k8;
-        float tl[8];
+        if (k8 < a.k) {
+            const int nv = a.k - k8;
+            float tl[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) tl[c] = ax[k8 + (c < nv ? c : 0)];
-        add(tl, k8, nv);
+            for (int c = 0; c < 8; ++c)
+                tl[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                      rs, vo + 4 * (k8 + (c < nv ? c : 0)), 0, 0));
+            add(tl, k8, nv);
+        }
+    } else {
+        // the row streams in chunks of 8 values, the next chunk's loads in
+        // flight while the current one is consumed
+        const int k8 = a.k & ~7;
+        float nxt[8];
+        if (k8 > 0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) nxt[c] = ax[c];
+        }
+        for (int j0 = 0; j0 < k8; j0 += 8) {
+            float cur[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) cur[c] = nxt[c];
+            if (j0 + 8 < k8) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) nxt[c] = ax[j0 + 8 + c];
+            }
+            add(cur, j0, 8);
+        }
+        if (k8 < a.k) {
+            const int nv = a.k - k8;
+            float tl[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) tl[c] = ax[k8 + (c < nv ? c : 0)];
+            add(tl, k8, nv);
+        }
     }
     const double fl2 = a.rho_floor * a.rho_floor;
     float um = -INFINITY;
@@ -282,12 +333,16 @@ hipError_t launch_label_rep_soft(const LaunchCtx &lc, const TextureArgs &a) {
 
 hipError_t launch_texture_post_soft(const LaunchCtx &lc, const TextureArgs &a) {
     if (!a.npix) return hipSuccess;
-    const dim3 grid((unsigned)((a.npix + 255) / 256));
-    const size_t lds = sizeof(float) * (size_t)a.L * a.k;
-    if (a.L <= 16)
-        hipLaunchKernelGGL(k_texture_post_soft<16>, grid, dim3(256), lds, lc.stream, a);
-    else
-        hipLaunchKernelGGL(k_texture_post_soft<kMaxLabels>, grid, dim3(256), lds, lc.stream, a);
+    const dim3 grid((unsigned)((a.npix + kPostThreads - 1) / kPostThreads));
+    const size_t lds = sizeof(float) * (size_t)a.L * ((a.k + 7) & ~7);
+    const bool buf = (uint64_t)a.N * (uint64_t)a.k * 4u < 0xFFFFFFF0ull;
+    if (a.L <= 16) {
+        if (buf) hipLaunchKernelGGL((k_texture_post_soft<16, true>), grid, dim3(kPostThreads), lds, lc.stream, a);
+        else hipLaunchKernelGGL((k_texture_post_soft<16, false>), grid, dim3(kPostThreads), lds, lc.stream, a);
+    } else {
+        if (buf) hipLaunchKernelGGL((k_texture_post_soft<kMaxLabels, true>), grid, dim3(kPostThreads), lds, lc.stream, a);
+        else hipLaunchKernelGGL((k_texture_post_soft<kMaxLabels, false>), grid, dim3(kPostThreads), lds, lc.stream, a);
+    }
     return hipGetLastError();
 }
 
@@ -298,8 +353,8 @@ hipError_t launch_label_rep(const LaunchCtx &lc, const TextureArgs &a) {
 
 hipError_t launch_texture_post(const LaunchCtx &lc, const TextureArgs &a) {
     if (!a.npix) return hipSuccess;
-    hipLaunchKernelGGL(k_texture_post, dim3((unsigned)((a.npix + 255) / 256)), dim3(256), 0,
-                       lc.stream, a);
+    hipLaunchKernelGGL(k_texture_post, dim3((unsigned)((a.npix + kPostThreads - 1) / kPostThreads)),
+                       dim3(kPostThreads), 0, lc.stream, a);
     return hipGetLastError();
 }
 
