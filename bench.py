@@ -34,13 +34,16 @@ PARZEN_EVENT_PERIOD = 8
 PEAK_MFMA = {"fp32": 157.3e12, "bf16": 2.5e15}
 
 
-def parzen_ops_per_pair(k: int) -> int:
+def parzen_ops_per_pair(k: int, texture: bool = True) -> int:
     """Algorithmic VALU issue slots per pixel x sample pair of the direct
     evaluation: location difference and square (4), colour differences and
     squares (6), XOR and popcount per 32-bit co-support word (2 ceil(k/32)),
     conversion of the count and the three-term exponent (4), log-sum-exp
     max, shift and accumulate (3), and one v_exp_f32 at a quarter of the
-    FP32 issue rate (4 slots)."""
+    FP32 issue rate (4 slots).  Without the texture factor in the sum (the
+    joint forms): no popcounts, no conversion, a two-term exponent (2)."""
+    if not texture:
+        return 4 + 6 + 2 + 3 + 4
     return 17 + 2 * ((k + 31) // 32) + 4
 
 
@@ -352,7 +355,8 @@ def main():
     value = pairs / (ms_per_step / 1e3)
 
     avg_parzen_s = parzen_ms / 1e3 / max(parzen_n, 1)
-    ops = pairs * parzen_ops_per_pair(w.k)
+    tex_in_sum = not (args.joint or args.soft)
+    ops = pairs * parzen_ops_per_pair(w.k, tex_in_sum)
     achieved = ops / avg_parzen_s
     traffic = None
     tr = load_traffic("parzen_bsds_traffic.json")
@@ -363,7 +367,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
                 "kernel": "k_parzen_mfma", "avg_launch_ms": avg_parzen_s * 1e3,
-                "ops_per_pair": parzen_ops_per_pair(w.k)}
+                "ops_per_pair": parzen_ops_per_pair(w.k, tex_in_sum)}
     avg_an = analyze_ms / 1e3 / max(analyze_n, 1)
     gemm_flops = 2.0 * w.k * w.n * w.N
     extra = {

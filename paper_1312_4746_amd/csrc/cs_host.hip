@@ -874,6 +874,7 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         fa.ngroups = (int)ngroups;
         fa.fix_cap = (int)(ntiles_pad * L);
         fa.sigma_c = pa.sigma_c;
+        fa.texture = pa.texture_in_sum;
         // per-label chunk ranges and the label order (kernel arguments: no copy)
         for (int l = 0; l <= L; ++l) fa.meta[l] = segs.pseg[l] / kStreamChunk;
         for (int l = 0; l < L; ++l) fa.meta[L + 1 + l] = pa.label_order[l];

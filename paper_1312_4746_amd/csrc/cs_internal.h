@@ -270,6 +270,7 @@ struct ParzenFastArgs {
     int fix_cap;
     int H, W, L, k, ksteps;
     int tiles_x, ntiles, ngroups;
+    int texture;           // 0: texture factor out of the sum (no FP8 products)
     double sigma_c;
     // passed by value (kernel arguments): [0..L] first chunk of each label's
     // padded segment (chunk units), [L+1 .. 2L] the labels by decreasing

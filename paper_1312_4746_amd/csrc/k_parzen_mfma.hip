@@ -301,12 +301,14 @@ hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
 
 // Register budget: four waves per SIMD (128 VGPRs) with one 128-feature MFMA
 // step, two with the wider feature rows.
-template <int KSTEPS>
+// TEX = false: the texture factor stays out of the sum (eq:joined forms):
+// no feature stream, no FP8 products, only the location and colour terms.
+template <int KSTEPS, bool TEX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 ? 4 : 2)))
 void k_parzen_mfma(ParzenFastArgs a) {
     constexpr int RB = kParzenRB;
     constexpr int KP = 128 * KSTEPS;
-    constexpr int FEAT_B = kChunkS * KP;  // feature bytes per chunk
+    constexpr int FEAT_B = TEX ? kChunkS * KP : 16;  // feature bytes per chunk
     // Separate LDS objects per buffer: with the buffer known at compile time the
     // compiler can tell that reads of one buffer do not depend on the copy in
     // flight into the other, and does not wait for it.
@@ -390,11 +392,13 @@ void k_parzen_mfma(ParzenFastArgs a) {
         auto issue = [&](int c, uint8_t *sf, float *sr) {
             int off = tid * 16;
             __asm__ volatile("" : "+v"(off));
-            const uint8_t *fbase = a.feat + (int64_t)c * FEAT_B;
+            if constexpr (TEX) {
+                const uint8_t *fbase = a.feat + (int64_t)c * FEAT_B;
 #pragma unroll
-            for (int u = 0; u < FEAT_B / 4096; ++u)
-                __builtin_amdgcn_global_load_lds(fbase + u * 4096 + off, (lds_void *)(sf + u * 4096 + wave * 1024), 16,
-                                                 0, 0);
+                for (int u = 0; u < FEAT_B / 4096; ++u)
+                    __builtin_amdgcn_global_load_lds(fbase + u * 4096 + off,
+                                                     (lds_void *)(sf + u * 4096 + wave * 1024), 16, 0, 0);
+            }
             if (wave < 3) {
                 const uint8_t *rbase = reinterpret_cast<const uint8_t *>(a.rec) + (int64_t)c * (kRecChunkF * 4);
                 __builtin_amdgcn_global_load_lds(rbase + off, (lds_void *)(sr + wave * 256), 16, 0, 0);
@@ -440,14 +444,16 @@ void k_parzen_mfma(ParzenFastArgs a) {
         i32x8 Aop[RB][KSTEPS];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
+            if constexpr (TEX) {
 #pragma unroll
-            for (int q = 0; q < KSTEPS; ++q) {
-                // 8 dwords (32 bytes) per lane
-                const uint4 *src = reinterpret_cast<const uint4 *>(
-                    a.aop + ((((int64_t)tile * RB + rb) * KSTEPS + q) * 64 + lane) * 8);
-                const uint4 lo4 = src[0], hi4 = src[1];
-                Aop[rb][q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
-                                   (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
+                for (int q = 0; q < KSTEPS; ++q) {
+                    // 8 dwords (32 bytes) per lane
+                    const uint4 *src = reinterpret_cast<const uint4 *>(
+                        a.aop + ((((int64_t)tile * RB + rb) * KSTEPS + q) * 64 + lane) * 8);
+                    const uint4 lo4 = src[0], hi4 = src[1];
+                    Aop[rb][q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
+                                       (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
+                }
             }
             const uint8_t *bsrc = a.abf + (((int64_t)tile * RB + rb) * 64 + lane) * 16;
             __builtin_amdgcn_global_load_lds(bsrc, (lds_void *)&s_abf[wave][rb][0], 16, 0, 0);
@@ -480,12 +486,14 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 const uint8_t *Fs = F + st * 16 * KP;
                 const uint8_t *Rs = reinterpret_cast<const uint8_t *>(Rr) + st * 256;
                 i32x8 Bop[KSTEPS];
+                if constexpr (TEX) {
 #pragma unroll
-                for (int q = 0; q < KSTEPS; ++q) {
-                    const uint4 lo4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][0]);
-                    const uint4 hi4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][1]);
-                    Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
-                                   (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
+                    for (int q = 0; q < KSTEPS; ++q) {
+                        const uint4 lo4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][0]);
+                        const uint4 hi4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][1]);
+                        Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
+                                       (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
+                    }
                 }
                 const s16x8 Bbf = *reinterpret_cast<const s16x8 *>(Rs + loff);
                 const float4 col = *reinterpret_cast<const float4 *>(Rs + coff);
@@ -493,10 +501,12 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
                     T[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    if constexpr (TEX) {
 #pragma unroll
-                    for (int q = 0; q < KSTEPS; ++q)
-                        T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(Aop[rb][q], Bop[q], T[rb], 0, 0,
-                                                                                  0, 127, 0, 127);
+                        for (int q = 0; q < KSTEPS; ++q)
+                            T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(Aop[rb][q], Bop[q], T[rb],
+                                                                                      0, 0, 0, 127, 0, 127);
+                    }
                     Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, s_abf[wave][rb][al]),
                                                                     __builtin_bit_cast(bf16x8, Bbf),
                                                                     f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
@@ -506,7 +516,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const float dr = pr[rb][r] - col.x, dg = pg[rb][r] - col.y, db = pb[rb][r] - col.z;
-                        float u = fmaf(T[rb][r], nB[rb][r], nR[rb][r]);
+                        float u = TEX ? fmaf(T[rb][r], nB[rb][r], nR[rb][r]) : nR[rb][r];
                         u = fmaf(Q[rb][r], nA[rb][r], u);
                         u = fmaf(-dr, dr, u);
                         u = fmaf(-dg, dg, u);
@@ -605,25 +615,26 @@ void k_parzen_mfma(ParzenFastArgs a) {
     }
 }
 
-template <int KSTEPS>
+template <int KSTEPS, bool TEX>
 static hipError_t launch_mfma_k(const LaunchCtx &lc, const ParzenFastArgs &a) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS>, 256, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS, TEX>, 256, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     int64_t blocks = (int64_t)lc.num_cu * per_cu;
     const int64_t items = (int64_t)a.ngroups * a.L;
     if (blocks > items) blocks = items;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_parzen_mfma<KSTEPS>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
+    hipLaunchKernelGGL((k_parzen_mfma<KSTEPS, TEX>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a) {
+    if (!a.texture) return launch_mfma_k<1, false>(lc, a);
     switch (a.ksteps) {
-        case 1: return launch_mfma_k<1>(lc, a);
-        case 2: return launch_mfma_k<2>(lc, a);
-        default: return launch_mfma_k<3>(lc, a);
+        case 1: return launch_mfma_k<1, true>(lc, a);
+        case 2: return launch_mfma_k<2, true>(lc, a);
+        default: return launch_mfma_k<3, true>(lc, a);
     }
 }
 
