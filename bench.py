@@ -109,8 +109,9 @@ def cpu_baseline(w, n_sample: int, joint: bool = False, soft: bool = False):
     oracle.lib()
     t0 = time.perf_counter()
     alpha = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega)
-    tau, _ = oracle.tau_median(alpha, w.tau_frac)
-    masks = oracle.cosupport(alpha, tau)
+    if not soft:  # the smooth form needs no threshold and no masks
+        tau, _ = oracle.tau_median(alpha, w.tau_frac)
+        masks = oracle.cosupport(alpha, tau)
     t_front = time.perf_counter() - t0
     pix = np.linspace(0, w.N - 1, n_sample).astype(np.int32)
     t1 = time.perf_counter()
@@ -126,7 +127,7 @@ def cpu_baseline(w, n_sample: int, joint: bool = False, soft: bool = False):
         "unit": "pairs/s",
         "cores": oracle.get_threads(),
         "kind": "oracle",
-        "sample": (f"FP64 oracle: analysis, tau and masks of all {w.N} pixels ({t_front:.2f} s, "
+        "sample": (f"FP64 oracle: analysis{'' if soft else ', tau and masks'} of all {w.N} pixels ({t_front:.2f} s, "
                    f"scaled to the subset) + Parzen log-likelihood of {n_sample} evenly strided "
                    f"pixels x {w.M} samples ({t_ll:.2f} s)"),
     }
