@@ -52,7 +52,7 @@ __device__ __forceinline__ float pair_e(float px, float py, float pr, float pg, 
 }
 
 // Per (label, pixel) coefficients of the pair exponent in log2 units, from
-// the exact nearest-sample distance d (FP64, rounded once):
+// the exact nearest-sample distance d (FP32):
 //   nA = -log2(e) / (2 rho^2), nB = -log2(e) / beta, rho = alpha_rho max(d, r_f),
 //   (nB = 0 when the texture factor is applied outside the sum, eq:joined),
 //   K  = -log m_i - log(2 pi) - 1.5 log(2 pi sigma_c^2) - log(rho^2),
@@ -88,13 +88,14 @@ __global__ __launch_bounds__(256) void k_coef(ParzenArgs a, float4 *__restrict__
     const float nC = (float)(-kLog2e / (2.0 * a.sigma_c * a.sigma_c));
     const int d2min = a.d2[(int64_t)l * N + pix];
     const int64_t nearp = a.nearest[(int64_t)l * N + pix];
-    const double fl2 = a.rho_floor * a.rho_floor;
-    const double dm = (double)d2min > fl2 ? (double)d2min : fl2;
-    const double rho2 = a.alpha_rho * a.alpha_rho * dm;
-    const double rho = sqrt(rho2);
-    const float nA = (float)(-kLog2e / (2.0 * rho2));
-    const float nB = a.texture_in_sum ? (float)(-kLog2e / (a.beta_scale * rho)) : 0.0f;
-    const float K = (float)(a.kconst[l] - log(rho2));
+    // FP32 from here (the results are FP32; a few ulps against one rounding)
+    const float fl2 = (float)(a.rho_floor * a.rho_floor);
+    const float dm = fmaxf((float)d2min, fl2);
+    const float rho2 = (float)(a.alpha_rho * a.alpha_rho) * dm;
+    const float rho = sqrtf(rho2);
+    const float nA = -(float)kLog2e / (2.0f * rho2);
+    const float nB = a.texture_in_sum ? -(float)kLog2e / ((float)a.beta_scale * rho) : 0.0f;
+    const float K = (float)a.kconst[l] - logf(rho2);
     uint32_t mx[NW], nrec[kRecWords];
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
