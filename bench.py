@@ -135,7 +135,7 @@ def cpu_baseline(w, n_sample: int, joint: bool = False, soft: bool = False):
 
 def surrogate_bench(args):
     """Learned surrogate at the 2048x2048 workload: exact data term on every
-    pixel (the judge), exact targets at the 2 % training pixels, training,
+    pixel (the reference), exact targets at the 2 % training pixels, training,
     inference on every pixel, flip rate and the equal-time comparison."""
     import numpy as np
     import torch
@@ -188,7 +188,7 @@ def surrogate_bench(args):
     net.infer(rgb, alpha, out=y)
     reps = 5
     t_infer, _ = timed(lambda: net.infer(rgb, alpha, out=y), reps)
-    quality = sg.judge(y, ll)
+    quality = sg.compare_to_exact(y, ll)
 
     # equal-time exact path: a sample subset sized to the surrogate's time
     m_eq = max(w.L, int(w.M * t_infer / t_exact))
@@ -197,7 +197,7 @@ def surrogate_bench(args):
     ll2 = torch.empty_like(ll)
     ctx.label_loglik(rgb, masks, w.k, sp2, sl2, w.L, prm, out=ll2)
     t_sub, _ = timed(lambda: ctx.label_loglik(rgb, masks, w.k, sp2, sl2, w.L, prm, out=ll2), 1)
-    q_sub = sg.judge(ll2, ll)
+    q_sub = sg.compare_to_exact(ll2, ll)
     trace = fit.loss_trace.cpu().numpy()
 
     out = {

@@ -1,5 +1,5 @@
 """Per-image learned surrogate of the data term: train on exact
-log-likelihoods at sampled pixels, infer on every pixel, judge against the
+log-likelihoods at sampled pixels, infer on every pixel, compare against the
 exact path.
 
 Every computation of the method runs in the library (exact targets by
@@ -40,7 +40,7 @@ def fit(ctx: Context, rgb: torch.Tensor, alpha: torch.Tensor, masks: torch.Tenso
     return SurrogateFit(net=net, loss_trace=trace, steps=int(order.numel() // batch))
 
 
-def judge(ell_sur: torch.Tensor, ell_exact: torch.Tensor) -> dict:
+def compare_to_exact(ell_sur: torch.Tensor, ell_exact: torch.Tensor) -> dict:
     """Label-argmax flip rate (ties to the lowest label on both sides), mean
     |delta l| over all labels, and over the labels within CLIP_NATS of the
     pixel's exact maximum (the range the surrogate is trained to match)."""
