@@ -44,6 +44,8 @@ extern "C" {
 #define CS_ERR_EMPTY_LABEL 2  /* some label has no scribble sample (m_i = 0)     */
 #define CS_ERR_HIP 3          /* a HIP runtime call failed                        */
 #define CS_ERR_NOMEM 4        /* device workspace allocation failed               */
+#define CS_ERR_NONFINITE 5    /* an input holds a NaN or an infinity (optional    */
+                              /* check, see cs_set_check_finite)                  */
 
 #define CS_FP32 0 /* O s on FP32 MFMA, FP32 accumulation                        */
 #define CS_BF16 1 /* O s on BF16 MFMA (both operands rounded), FP32 accumulation */
@@ -59,6 +61,15 @@ int cs_destroy(cs_ctx *ctx);
 int cs_set_stream(cs_ctx *ctx, void *hip_stream);
 /* Message of the last failed call on this context ("" if none). */
 const char *cs_last_error(const cs_ctx *ctx);
+/* Optional finite check of the inputs (default off).  When on, every call
+ * that reads an image or an operator (cs_analyze_patches, cs_tau_median,
+ * cs_cosupport, cs_cosupport_median: rgb and omega; the cs_label_loglik
+ * forms: rgb) first scans them on the device, synchronises the stream and
+ * returns CS_ERR_NONFINITE, launching nothing else, if any value is a NaN
+ * or an infinity.  The method's arithmetic is only defined on finite
+ * colours and operator entries (Sec. 2, Sec. 3.1).  Off, no call
+ * synchronises for it and non-finite inputs give unspecified outputs. */
+int cs_set_check_finite(cs_ctx *ctx, int on);
 
 /*
  * Analysed vectors a = O s_x of every pixel (Sec. 2; the patch s_x of Sec. 3.1
@@ -240,8 +251,10 @@ typedef struct {
                               /* kernel (overflow, non-finite or empty sums)         */
 } cs_loglik_stats;
 
-/* Counters of the last cs_label_loglik call on this context (full-image path;
- * zeros for a pixel subset).  Synchronises the stream. */
+/* Counters of the last log-likelihood call (any of the three forms) on this
+ * context that got past its argument checks: full-image path only, zeros for
+ * a pixel subset.  They live in context-owned device memory that no other
+ * call touches.  Synchronises the stream. */
 int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats);
 
 /* Kernel timing on the context stream (HIP events around each launch of the

@@ -23,6 +23,7 @@ CSO_OK = 0
 CSO_ERR_ARG = 1
 CSO_ERR_EMPTY_LABEL = 2
 CSO_ERR_NOMEM = 4
+CSO_ERR_NONFINITE = 5
 
 _lib = None
 

@@ -117,6 +117,14 @@ static void patch_s(const float *rgb, int H, int W, int p, const double *w, int6
     for (int t = 0; t < n; ++t) s[t] = s[t] / nu;
 }
 
+/* 1 when every one of the n floats is finite (no NaN, no infinity): the
+ * method is defined on finite colours and operator entries only. */
+static int all_finite(const float *v, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
 static int check_image(const float *rgb, int H, int W, int p) {
     if (!rgb || p < 1 || p > 15 || (p % 2) == 0) return 0;
     int h = (p - 1) / 2;
@@ -148,6 +156,7 @@ int cso_analyze(const float *rgb, int H, int W, int p, double mask_sigma,
     int64_t N = (int64_t)H * W;
     int64_t cnt = pix ? npix : N;
     int n = p * p;
+    if (!all_finite(rgb, 3 * N) || !all_finite(omega, (int64_t)k * n)) return CSO_ERR_NONFINITE;
     if (pix)
         for (int64_t i = 0; i < cnt; ++i)
             if (pix[i] < 0 || pix[i] >= N) return CSO_ERR_ARG;
@@ -351,6 +360,7 @@ static int loglik(const float *rgb, int H, int W, const uint64_t *masks, const d
     int64_t N = (int64_t)H * W;
     int64_t cnt = pix ? npix : N;
     int words = (k + 63) / 64;
+    if (!all_finite(rgb, 3 * N)) return CSO_ERR_NONFINITE;
     /* label segments in sample-index order */
     int64_t *count = (int64_t *)calloc((size_t)L, sizeof(int64_t));
     int64_t *start = (int64_t *)calloc((size_t)L + 1, sizeof(int64_t));
@@ -370,6 +380,7 @@ static int loglik(const float *rgb, int H, int W, const uint64_t *masks, const d
     }
     {
         int64_t *fill = (int64_t *)calloc((size_t)L, sizeof(int64_t));
+        if (!fill) { free(count); free(start); free(order); return CSO_ERR_NOMEM; }
         for (int64_t s = 0; s < M; ++s) {
             int l = sample_label[s];
             order[start[l] + fill[l]++] = s;
@@ -381,12 +392,13 @@ static int loglik(const float *rgb, int H, int W, const uint64_t *masks, const d
     if (joint == 1) {
         rep = (uint64_t *)malloc((size_t)L * words * sizeof(uint64_t));
         if (!rep) { free(count); free(start); free(order); return CSO_ERR_NOMEM; }
-        cso_label_rep(masks, N, k, sample_pix, sample_label, M, L, rep);
+        int rc = cso_label_rep(masks, N, k, sample_pix, sample_label, M, L, rep);
+        if (rc) { free(rep); free(count); free(start); free(order); return rc; }
     } else if (joint == 2) {
         crep = (double *)malloc((size_t)L * k * sizeof(double));
-        if (!crep || cso_label_rep_soft(alpha, N, k, sigma_iota, sample_pix, sample_label, M, L, crep)) {
-            free(crep); free(count); free(start); free(order); return CSO_ERR_NOMEM;
-        }
+        if (!crep) { free(count); free(start); free(order); return CSO_ERR_NOMEM; }
+        int rc = cso_label_rep_soft(alpha, N, k, sigma_iota, sample_pix, sample_label, M, L, crep);
+        if (rc) { free(crep); free(count); free(start); free(order); return rc; }
     }
     const double pi = 3.14159265358979323846;
     double col_norm = 1.5 * log(2.0 * pi * sigma_c * sigma_c);

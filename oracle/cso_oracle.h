@@ -20,6 +20,7 @@ extern "C" {
 #define CSO_ERR_ARG 1
 #define CSO_ERR_EMPTY_LABEL 2
 #define CSO_ERR_NOMEM 4
+#define CSO_ERR_NONFINITE 5 /* an input colour or operator entry is a NaN or an infinity */
 
 void cso_set_threads(int n);
 int cso_get_threads(void);

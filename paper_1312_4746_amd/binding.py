@@ -16,6 +16,7 @@ CS_ERR_ARG = 1
 CS_ERR_EMPTY_LABEL = 2
 CS_ERR_HIP = 3
 CS_ERR_NOMEM = 4
+CS_ERR_NONFINITE = 5
 CS_FP32 = 0
 CS_BF16 = 1
 
@@ -45,6 +46,7 @@ SIGNATURES = {
     "cs_destroy": (_I, [_P]),
     "cs_set_stream": (_I, [_P, _P]),
     "cs_last_error": (ctypes.c_char_p, [_P]),
+    "cs_set_check_finite": (_I, [_P, _I]),
     "cs_analyze_patches": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P]),
     "cs_tau_median": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, ctypes.POINTER(_D)]),
     "cs_cosupport": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, _D, _P,
@@ -108,6 +110,40 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _nw(k: int) -> int:
+    return (int(k) + 63) // 64
+
+
+def _image_hw(rgb) -> tuple:
+    """(H, W) of a (3, H, W) colour tensor."""
+    if rgb.dim() != 3 or rgb.shape[0] != 3:
+        raise ValueError(f"rgb must be (3, H, W), got {tuple(rgb.shape)}")
+    return int(rgb.shape[1]), int(rgb.shape[2])
+
+
+def _omega_k(omega, p: int) -> int:
+    if omega.dim() != 2 or omega.shape[1] != p * p:
+        raise ValueError(f"omega must be (k, p*p) = (k, {p * p}), got {tuple(omega.shape)}")
+    return int(omega.shape[0])
+
+
+def _numel(t, n: int, name: str, what: str):
+    """The device kernels see only pointers: a buffer of the wrong size would be
+    read or written out of bounds, so sizes are checked before any launch."""
+    if t is not None and t.numel() != n:
+        raise ValueError(f"{name} must hold {what} = {n} elements, got {t.numel()}")
+
+
+def _masks_shape(masks, npix: int, k: int, name: str = "masks"):
+    if masks.dim() != 2 or masks.shape[0] != npix or masks.shape[1] != _nw(k):
+        raise ValueError(f"{name} must be (N, ceil(k/64)) = ({npix}, {_nw(k)}), got {tuple(masks.shape)}")
+
+
+def _samples(sample_pix, sample_label):
+    if sample_label.numel() != sample_pix.numel():
+        raise ValueError(f"sample_label holds {sample_label.numel()} labels for {sample_pix.numel()} samples")
+
+
 @dataclasses.dataclass
 class LoglikParams:
     alpha_rho: float = 1.3
@@ -164,12 +200,11 @@ class Context:
     # -- C-ABI calls ----------------------------------------------------
     def analyze_patches(self, rgb: torch.Tensor, p: int, mask_sigma: float, omega: torch.Tensor,
                         precision="fp32", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        H, W = _image_hw(rgb)
+        k = _omega_k(omega, p)
+        _numel(out, H * W * k, "alpha", "H*W*k")
         self._dev(rgb, torch.float32, "rgb")
         self._dev(omega, torch.float32, "omega")
-        _, H, W = rgb.shape
-        k = omega.shape[0]
-        if omega.shape[1] != p * p:
-            raise ValueError("omega must be k x p*p")
         if out is None:
             out = torch.empty((H * W, k), dtype=torch.float32, device=rgb.device)
         self._dev(out, torch.float32, "alpha")
@@ -179,13 +214,12 @@ class Context:
         return out
 
     def tau_median(self, rgb, p, mask_sigma, omega, alpha, frac=0.1, precision="fp32") -> float:
+        H, W = _image_hw(rgb)
+        k = _omega_k(omega, p)
+        _numel(alpha, H * W * k, "alpha", "H*W*k")
         self._dev(rgb, torch.float32, "rgb")
         self._dev(omega, torch.float32, "omega")
         self._dev(alpha, torch.float32, "alpha")
-        _, H, W = rgb.shape
-        k = omega.shape[0]
-        if alpha.numel() != H * W * k:
-            raise ValueError("alpha must hold H*W*k entries")
         tau = ctypes.c_double()
         self._sync_stream()
         self._check(lib().cs_tau_median(self._h, _ptr(rgb), H, W, p, float(mask_sigma), _ptr(omega),
@@ -200,14 +234,15 @@ class Context:
         patterns; with stats=True returns (masks, {recomputed, max_margin}).
         With alpha (the analysed vectors of the same inputs and precision) the
         masks are decided from it instead of a fresh analysis."""
+        H, W = _image_hw(rgb)
+        k = _omega_k(omega, p)
+        _numel(alpha, H * W * k, "alpha", "H*W*k")
+        if out is not None:
+            _masks_shape(out, H * W, k)
         self._dev(rgb, torch.float32, "rgb")
         self._dev(omega, torch.float32, "omega")
-        _, H, W = rgb.shape
-        k = omega.shape[0]
         if alpha is not None:
             self._dev(alpha, torch.float32, "alpha")
-            if alpha.numel() != H * W * k:
-                raise ValueError("alpha must hold H*W*k entries")
         if out is None:
             out = torch.empty((H * W, (k + 63) // 64), dtype=torch.int64, device=rgb.device)
         self._dev(out, torch.int64, "masks")
@@ -227,15 +262,17 @@ class Context:
         """Analysed vectors, tau = frac * median|a| and the masks at that tau
         in one enqueue-only call.  Returns (alpha (N, k) float32, masks (N,
         ceil(k/64)) int64, tau (1,) float64 on the device)."""
+        H, W = _image_hw(rgb)
+        k = _omega_k(omega, p)
+        _numel(alpha, H * W * k, "alpha", "H*W*k")
+        if out is not None:
+            _masks_shape(out, H * W, k)
+        _numel(tau, 1, "tau", "one value")
         self._dev(rgb, torch.float32, "rgb")
         self._dev(omega, torch.float32, "omega")
-        _, H, W = rgb.shape
-        k = omega.shape[0]
         if alpha is None:
             alpha = torch.empty((H * W, k), dtype=torch.float32, device=rgb.device)
         self._dev(alpha, torch.float32, "alpha")
-        if alpha.numel() != H * W * k:
-            raise ValueError("alpha must hold H*W*k entries")
         if out is None:
             out = torch.empty((H * W, (k + 63) // 64), dtype=torch.int64, device=rgb.device)
         self._dev(out, torch.int64, "masks")
@@ -250,9 +287,12 @@ class Context:
 
     def texture_similarity(self, A: torch.Tensor, B: torch.Tensor, k: int,
                            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        _masks_shape(A, A.shape[0] if A.dim() == 2 else -1, k, "A")
+        _masks_shape(B, B.shape[0] if B.dim() == 2 else -1, k, "B")
+        na, nb = A.shape[0], B.shape[0]
+        _numel(out, na * nb, "out", "na*nb")
         self._dev(A, torch.int64, "A")
         self._dev(B, torch.int64, "B")
-        na, nb = A.shape[0], B.shape[0]
         if out is None:
             out = torch.empty((na, nb), dtype=torch.int32, device=A.device)
         self._dev(out, torch.int32, "out")
@@ -265,15 +305,18 @@ class Context:
                      out: Optional[torch.Tensor] = None, joint: bool = False) -> torch.Tensor:
         """joint=False: cs_label_loglik (texture factor per sample inside the
         Parzen sum); joint=True: cs_label_loglik_joint (eq:joined)."""
+        H, W = _image_hw(rgb)
+        _masks_shape(masks, H * W, k)
+        _samples(sample_pix, sample_label)
+        npix = H * W if pix_subset is None else pix_subset.numel()
+        _numel(out, npix * L, "loglik", "npix*L")
         self._dev(rgb, torch.float32, "rgb")
         self._dev(masks, torch.int64, "masks")
         self._dev(sample_pix, torch.int32, "sample_pix")
         self._dev(sample_label, torch.int32, "sample_label")
-        _, H, W = rgb.shape
         params = params or LoglikParams()
         if pix_subset is not None:
             self._dev(pix_subset, torch.int32, "pix_subset")
-        npix = H * W if pix_subset is None else pix_subset.numel()
         if out is None:
             out = torch.empty((npix, L), dtype=torch.float32, device=rgb.device)
         self._dev(out, torch.float32, "loglik")
@@ -296,18 +339,20 @@ class Context:
                           out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """cs_label_loglik_soft: the joint form with smooth co-supports of the
         analysed vectors alpha (N x k float32)."""
+        H, W = _image_hw(rgb)
+        if alpha.dim() != 2 or alpha.shape[0] != H * W:
+            raise ValueError("alpha must be (H*W, k)")
+        k = alpha.shape[1]
+        _samples(sample_pix, sample_label)
+        npix = H * W if pix_subset is None else pix_subset.numel()
+        _numel(out, npix * L, "loglik", "npix*L")
         self._dev(rgb, torch.float32, "rgb")
         self._dev(alpha, torch.float32, "alpha")
         self._dev(sample_pix, torch.int32, "sample_pix")
         self._dev(sample_label, torch.int32, "sample_label")
-        _, H, W = rgb.shape
-        if alpha.dim() != 2 or alpha.shape[0] != H * W:
-            raise ValueError("alpha must be (H*W, k)")
-        k = alpha.shape[1]
         params = params or LoglikParams()
         if pix_subset is not None:
             self._dev(pix_subset, torch.int32, "pix_subset")
-        npix = H * W if pix_subset is None else pix_subset.numel()
         if out is None:
             out = torch.empty((npix, L), dtype=torch.float32, device=rgb.device)
         self._dev(out, torch.float32, "loglik")
@@ -323,6 +368,10 @@ class Context:
                                                0 if pix_subset is None else pix_subset.numel(),
                                                _ptr(out) if out.numel() else None))
         return out
+
+    def set_check_finite(self, on: bool = True):
+        """Optional finite check of rgb and omega before each call (synchronises)."""
+        self._check(lib().cs_set_check_finite(self._h, int(bool(on))))
 
     def last_loglik_stats(self) -> dict:
         st = _LoglikStatsC()
@@ -375,6 +424,12 @@ class Mlp:
         except Exception:
             pass
 
+    def _rows(self, x, ell):
+        if x.dim() != 2 or x.shape[1] != self.in_dim:
+            raise ValueError(f"x must be (n, {self.in_dim}), got {tuple(x.shape)}")
+        if ell.dim() != 2 or ell.shape[0] != x.shape[0] or ell.shape[1] != self.out_dim:
+            raise ValueError(f"ell must be ({x.shape[0]}, {self.out_dim}), got {tuple(ell.shape)}")
+
     def params(self) -> torch.Tensor:
         out = torch.empty(self.P, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
         self.ctx._sync_stream()
@@ -383,6 +438,7 @@ class Mlp:
 
     def grad(self, x: torch.Tensor, ell: torch.Tensor):
         """(gradient of the mean loss over all rows, loss) without an update."""
+        self._rows(x, ell)
         self.ctx._dev(x, torch.float32, "x")
         self.ctx._dev(ell, torch.float32, "ell")
         g = torch.empty(self.P, dtype=torch.float32, device=x.device)
@@ -394,6 +450,8 @@ class Mlp:
 
     def fit_output_bias(self, ell: torch.Tensor):
         """b3 = mean clipped target of each label over the rows of ell."""
+        if ell.dim() != 2 or ell.shape[1] != self.out_dim:
+            raise ValueError(f"ell must be (n, {self.out_dim})")
         self.ctx._dev(ell, torch.float32, "ell")
         self.ctx._sync_stream()
         self.ctx._check(lib().cs_mlp_fit_output_bias(self.ctx._h, self._h, _ptr(ell), ell.shape[0]))
@@ -401,6 +459,9 @@ class Mlp:
     def train(self, x: torch.Tensor, ell: torch.Tensor, order: torch.Tensor, batch: int,
               lr: float = 1e-3) -> torch.Tensor:
         """Adam steps over the batches order.view(-1, batch); returns the loss trace."""
+        self._rows(x, ell)
+        if order.numel() % batch:
+            raise ValueError(f"order holds {order.numel()} indices, not a multiple of batch {batch}")
         self.ctx._dev(x, torch.float32, "x")
         self.ctx._dev(ell, torch.float32, "ell")
         self.ctx._dev(order, torch.int32, "order")
@@ -412,8 +473,11 @@ class Mlp:
         return trace[:steps]
 
     def forward(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        self.ctx._dev(x, torch.float32, "x")
+        if x.dim() != 2 or x.shape[1] != self.in_dim:
+            raise ValueError(f"x must be (n, {self.in_dim}), got {tuple(x.shape)}")
         n = x.shape[0]
+        _numel(out, n * self.out_dim, "out", "n*out_dim")
+        self.ctx._dev(x, torch.float32, "x")
         if out is None:
             out = torch.empty((n, self.out_dim), dtype=torch.float32, device=x.device)
         self.ctx._sync_stream()
@@ -421,10 +485,12 @@ class Mlp:
         return out
 
     def infer(self, rgb: torch.Tensor, alpha: torch.Tensor, out: Optional[torch.Tensor] = None):
+        H, W = _image_hw(rgb)
+        k = self.in_dim - 5
+        _numel(alpha, H * W * k, "alpha", "H*W*(in_dim-5)")
+        _numel(out, H * W * self.out_dim, "out", "H*W*out_dim")
         self.ctx._dev(rgb, torch.float32, "rgb")
         self.ctx._dev(alpha, torch.float32, "alpha")
-        _, H, W = rgb.shape
-        k = alpha.numel() // (H * W)
         if out is None:
             out = torch.empty((H * W, self.out_dim), dtype=torch.float32, device=rgb.device)
         self.ctx._sync_stream()
@@ -440,11 +506,14 @@ def param_count(in_dim: int, hidden: int, out_dim: int) -> int:
 def mlp_features(ctx: Context, rgb: torch.Tensor, alpha: torch.Tensor, pix: torch.Tensor,
                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Surrogate input rows of the pixels `pix` (int32, cuda)."""
+    H, W = _image_hw(rgb)
+    if alpha.dim() != 2 or alpha.shape[0] != H * W:
+        raise ValueError("alpha must be (H*W, k)")
+    k = alpha.shape[1]
+    _numel(out, pix.numel() * (5 + k), "out", "n*(5+k)")
     ctx._dev(rgb, torch.float32, "rgb")
     ctx._dev(alpha, torch.float32, "alpha")
     ctx._dev(pix, torch.int32, "pix")
-    _, H, W = rgb.shape
-    k = alpha.numel() // (H * W)
     if out is None:
         out = torch.empty((pix.numel(), 5 + k), dtype=torch.float32, device=rgb.device)
     ctx._sync_stream()

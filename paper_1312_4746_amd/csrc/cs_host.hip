@@ -56,8 +56,13 @@ struct cs_ctx {
     std::vector<Span> spans;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<double, int64_t>> totals;
-    // device counters of the last full-image log-likelihood call (4 x u32) or null
-    const unsigned int *loglik_counters = nullptr;
+    // counters of the last full-image log-likelihood call (4 x u32, context-owned
+    // device memory, cleared by that call's sample scan); valid when the last
+    // log-likelihood call took the full-image path
+    unsigned int *lstats = nullptr;
+    bool lstats_valid = false;
+    // optional finite check of rgb and omega before any launch
+    bool check_finite = false;
 };
 
 namespace {
@@ -115,10 +120,13 @@ struct Carve {
     }
 };
 
+// Work enqueued earlier may still read a buffer that is about to be freed, on
+// this stream or on a stream used before cs_set_stream switched it: wait for
+// the whole device before a workspace buffer is replaced.
 int ensure_ws(cs_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->ws_bytes) return CS_OK;
     const size_t want = std::max(bytes, ctx->ws_bytes + ctx->ws_bytes / 4);
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipDeviceSynchronize());
     if (ctx->ws) HIP_TRY(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
@@ -132,7 +140,7 @@ int ensure_ws(cs_ctx *ctx, size_t bytes) {
 
 int ensure_cand(cs_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->cand_bytes) return CS_OK;
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipDeviceSynchronize());
     if (ctx->cand) HIP_TRY(hipFree(ctx->cand));
     ctx->cand = nullptr;
     ctx->cand_bytes = 0;
@@ -210,6 +218,29 @@ int check_patch_args(cs_ctx *ctx, const float *rgb, int H, int W, int p, double 
     return CS_OK;
 }
 
+// Optional finite check (cs_set_check_finite): the n0 floats at a and the n1
+// floats at b (either may be null) are scanned on the device; the host reads
+// the flag (this synchronises the stream) and fails with CS_ERR_NONFINITE
+// before anything else is launched.
+int check_inputs_finite(cs_ctx *ctx, const float *a, int64_t n0, const float *b, int64_t n1) {
+    if (!ctx->check_finite) return CS_OK;
+    unsigned int *flag = ctx->dctr + kCtrNonFinite;
+    const LaunchCtx lc = lc_of(ctx);
+    if (a) HIP_TRY(launch_check_finite(lc, a, n0, flag));
+    if (b) HIP_TRY(launch_check_finite(lc, b, n1, flag));
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, flag, sizeof(unsigned int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    unsigned int f;
+    std::memcpy(&f, ctx->pinned, sizeof f);
+    if (!f) return CS_OK;
+    HIP_TRY(launch_fill_u32(lc, flag, 1, 0u));  // the counter is zero between calls
+    return fail(ctx, CS_ERR_NONFINITE, "an input (rgb or omega) holds a NaN or an infinity");
+}
+
+int check_patch_inputs_finite(cs_ctx *ctx, const float *rgb, int H, int W, const float *omega, int k, int p) {
+    return check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, omega, (int64_t)k * p * p);
+}
+
 // Coefficient of the proven bound |a_rounded - a| <= coef * ||O_j||_2 (unit-norm patch):
 // FP32: s and the accumulation each contribute at most (n + 2) unit roundoffs, doubled
 // to allow round-toward-zero accumulation; BF16: both operands rounded to 8-bit
@@ -241,12 +272,15 @@ int cs_create(cs_ctx **out, int device, void *hip_stream) {
                           hipHostMallocCoherent | hipHostMallocMapped);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&ctx->hcounts_dev, ctx->hcounts, 0);
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->dctr, sizeof(unsigned int) * kCtrWords);
+    if (e == hipSuccess) e = hipMalloc((void **)&ctx->lstats, sizeof(unsigned int) * 4);
     if (e == hipSuccess) e = launch_fill_u32(lc_of(ctx), ctx->dctr, kCtrWords, 0u);
+    if (e == hipSuccess) e = launch_fill_u32(lc_of(ctx), ctx->lstats, 4, 0u);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         if (ctx->pinned) hipHostFree(ctx->pinned);
         if (ctx->hcounts) hipHostFree(ctx->hcounts);
         if (ctx->dctr) hipFree(ctx->dctr);
+        if (ctx->lstats) hipFree(ctx->lstats);
         delete ctx;
         return CS_ERR_HIP;
     }
@@ -270,6 +304,7 @@ int cs_destroy(cs_ctx *ctx) {
     if (ctx->pinned) hipHostFree(ctx->pinned);
     if (ctx->hcounts) hipHostFree(ctx->hcounts);
     if (ctx->dctr) hipFree(ctx->dctr);
+    if (ctx->lstats) hipFree(ctx->lstats);
     delete ctx;
     return CS_OK;
 }
@@ -282,6 +317,12 @@ int cs_set_stream(cs_ctx *ctx, void *hip_stream) {
 
 const char *cs_last_error(const cs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+int cs_set_check_finite(cs_ctx *ctx, int on) {
+    if (!ctx) return CS_ERR_ARG;
+    ctx->check_finite = on != 0;
+    return CS_OK;
+}
+
 int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
                        const float *omega, int k, int precision, float *alpha) {
     if (!ctx) return CS_ERR_ARG;
@@ -289,6 +330,7 @@ int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, doubl
     if (rc) return rc;
     if (!alpha) return fail(ctx, CS_ERR_ARG, "alpha must be non-null");
     HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = check_patch_inputs_finite(ctx, rgb, H, W, omega, k, p))) return rc;
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     AnalyzeArgs a{};
     a.rgb = rgb;
@@ -373,7 +415,7 @@ int median_source(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
     if (precision != CS_BF16) return CS_OK;
     const size_t bytes = sizeof(float) * (size_t)H * W * k;
     if (bytes > ctx->alpha32_bytes) {
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        HIP_TRY(hipDeviceSynchronize());
         if (ctx->alpha32) HIP_TRY(hipFree(ctx->alpha32));
         ctx->alpha32 = nullptr;
         ctx->alpha32_bytes = 0;
@@ -442,6 +484,7 @@ int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask
     if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ctx, CS_ERR_ARG, "tau must be finite and >= 0");
     if (std::isnan(margin) || std::isinf(margin)) return fail(ctx, CS_ERR_ARG, "margin must be finite");
     HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = check_patch_inputs_finite(ctx, rgb, H, W, omega, k, p))) return rc;
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     Carve cv;
     CosupportWs cw;
@@ -477,6 +520,7 @@ int cs_tau_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
     if (reinterpret_cast<uintptr_t>(alpha) % 16) return fail(ctx, CS_ERR_ARG, "alpha must be 16-byte aligned");
     if (!(frac >= 0.0) || !std::isfinite(frac)) return fail(ctx, CS_ERR_ARG, "frac must be finite and >= 0");
     HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = check_patch_inputs_finite(ctx, rgb, H, W, omega, k, p))) return rc;
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     const int64_t count = (int64_t)H * W * k;
     const float *a32 = nullptr;
@@ -518,6 +562,7 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
     if (!(frac >= 0.0) || !std::isfinite(frac)) return fail(ctx, CS_ERR_ARG, "frac must be finite and >= 0");
     if (std::isnan(margin) || std::isinf(margin)) return fail(ctx, CS_ERR_ARG, "margin must be finite");
     HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = check_patch_inputs_finite(ctx, rgb, H, W, omega, k, p))) return rc;
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     const int64_t count = (int64_t)H * W * k;
     if (precision == CS_FP32 && margin < 0.0) {
@@ -648,17 +693,21 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
     const int64_t tiles = (npix + 63) / 64;
     if (tiles * L > (((int64_t)1 << 31) - 1)) return fail(ctx, CS_ERR_ARG, "too many pixels x labels");
     HIP_TRY(hipSetDevice(ctx->device));
+    {
+        int rcf = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, nullptr, 0);
+        if (rcf) return rcf;
+    }
     const int nblocks = (int)((M + 255) / 256);
     Carve cv;
     const size_t o_bc = cv.take(sizeof(int32_t) * (size_t)L * nblocks);
     const LaunchCtx lc0 = lc_of(ctx);
     const int npix_blocks = pix_subset && npix > 0 ? check_pix_blocks(lc0, npix) : 0;
     const size_t o_bflags = cv.take(sizeof(int32_t) * ((size_t)nblocks + npix_blocks));
-    // label counts (L+1), the exact kernel's two counters and the fast
-    // kernel's four counters share one region, cleared by one fill
-    const size_t o_tf = cv.take(sizeof(int32_t) * (L + 1 + 2 + 4));
+    // label counts (L+1) and the exact kernel's two counters share one
+    // region, cleared by the sample scan (the fast kernel's counters are the
+    // context's own, cleared by the same scan, and outlive the call)
+    const size_t o_tf = cv.take(sizeof(int32_t) * (L + 1 + 2));
     const size_t o_cnt = o_tf + sizeof(int32_t) * (L + 1);
-    const size_t o_fcnt = o_cnt + sizeof(unsigned int) * 2;
     const size_t o_queue = cv.take(sizeof(unsigned int) * kParzenQueues * kQueueStride);  // right after o_tf
     const size_t o_rec = cv.take(sizeof(SampleRec) * (size_t)M);
     const size_t seed_bytes = ((size_t)L * N + 15) / 16 * 16;  // cleared in 16-byte words
@@ -726,6 +775,8 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         sc.totals_flags = tf;
         sc.zero = cnt;
         sc.nzero = (int)((o_queue - o_cnt) / sizeof(unsigned int)) + kParzenQueues * kQueueStride;
+        sc.zero2 = ctx->lstats;
+        sc.nzero2 = 4;
         sc.host_out = ctx->hcounts_dev;
         sc.tag = tag;
         sc.done = ctx->dctr + kCtrSampleCount;
@@ -784,7 +835,7 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         pr.abf = (uint4 *)(ctx->ws + o_abf);
         HIP_TRY(launch_prep(lc, pr));
     }
-    unsigned int *fcnt = (unsigned int *)(ctx->ws + o_fcnt);
+    unsigned int *fcnt = ctx->lstats;
     ParzenArgs pa{};
     pa.rgb = rgb;
     pa.masks = masks;
@@ -882,7 +933,7 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
             const int in_last = counts[l] - (segs.pseg[l + 1] - segs.pseg[l] - kStreamChunk);
             fa.meta[2 * L + 1 + l] = (in_last + 15) / 16;
         }
-        ctx->loglik_counters = fcnt;
+        ctx->lstats_valid = true;
         {
             Timed t(ctx, "parzen");
             HIP_TRY(launch_parzen_mfma(lc, fa));
@@ -897,7 +948,7 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
             HIP_TRY(launch_parzen(lc, pa));
         }
     } else {
-        ctx->loglik_counters = nullptr;
+        ctx->lstats_valid = false;
         Timed t(ctx, "parzen");
         HIP_TRY(launch_parzen(lc, pa));
     }
@@ -939,8 +990,8 @@ int cs_label_loglik_soft(cs_ctx *ctx, const float *rgb, int H, int W, const floa
 int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats) {
     if (!ctx || !stats) return CS_ERR_ARG;
     stats->rescaled_chunks = stats->overflow_tiles = stats->exact_tiles = 0;
-    if (!ctx->loglik_counters) return CS_OK;
-    HIP_TRY(hipMemcpyAsync(ctx->pinned, ctx->loglik_counters, 4 * sizeof(unsigned int),
+    if (!ctx->lstats_valid) return CS_OK;
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, ctx->lstats, 4 * sizeof(unsigned int),
                            hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     unsigned int c[4];

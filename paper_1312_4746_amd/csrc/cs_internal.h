@@ -138,8 +138,12 @@ hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p
                       int64_t cap, double *vals, double frac, TauState *st, unsigned long long *parts,
                       double *tau_out);
 // Device counters of a context that are zero between calls (each use resets
-// its own): [kCtrSampleCount] the sample-count workgroups done.
-constexpr int kCtrSampleCount = 0, kCtrWords = 64;
+// its own): [kCtrSampleCount] the sample-count workgroups done,
+// [kCtrNonFinite] the flag of the optional finite check of the inputs.
+constexpr int kCtrSampleCount = 0, kCtrNonFinite = 1, kCtrWords = 64;
+// Sets *flag (device, zero before) to 1 when any of the n floats at p is a NaN
+// or an infinity.
+hipError_t launch_check_finite(const LaunchCtx &lc, const float *p, int64_t n, unsigned int *flag);
 
 // ---- co-support at frac * median|a| fused with the candidate gather
 // (k_cosupport_median.hip) ----
@@ -177,6 +181,8 @@ struct SampleCountArgs {
     int32_t *totals_flags;     // device copy of the totals and flags (L + 1)
     unsigned int *zero;        // counters cleared for the kernels that follow
     int nzero;
+    unsigned int *zero2;       // a second such region (context-owned counters) or null
+    int nzero2;
     int32_t *host_out;         // coherent host memory (device address)
     int32_t tag;
     unsigned int *done;        // device counter, zero between calls

@@ -17,7 +17,8 @@ constexpr int kChunk = 256;
 // system-scope fence, host_out[kHostTag] = tag.
 __device__ void sample_scan(int32_t *block_counts, int L, int nblocks, const int32_t *block_flags,
                             const int32_t *pix_flags, int npix_blocks, int32_t *totals_flags, unsigned int *zero,
-                            int nzero, volatile int32_t *host_out, int32_t tag) {
+                            int nzero, unsigned int *zero2, int nzero2, volatile int32_t *host_out,
+                            int32_t tag) {
     __shared__ int32_t buf[1024];
     __shared__ int32_t carry, sflags;
     __shared__ int32_t tot[kMaxLabels];
@@ -29,6 +30,7 @@ __device__ void sample_scan(int32_t *block_counts, int L, int nblocks, const int
     }
     for (int i = tid; i < kMaxLabels; i += B) tot[i] = 0;
     for (int i = tid; i < nzero; i += B) zero[i] = 0u;
+    for (int i = tid; i < nzero2; i += B) zero2[i] = 0u;
     __syncthreads();
     int32_t f = 0;
     for (int i = tid; i < nblocks; i += B) f |= block_flags[i] ? 1 : 0;
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(kChunk) void k_sample_count(SampleCountArgs a) {
     __threadfence();  // every workgroup's counts
     if (threadIdx.x == 0) *a.done = 0u;
     sample_scan(a.block_counts, a.L, a.nblocks, a.block_flags, a.pix_flags, a.npix_blocks, a.totals_flags, a.zero,
-                a.nzero, a.host_out, a.tag);
+                a.nzero, a.zero2, a.nzero2, a.host_out, a.tag);
 }
 
 hipError_t launch_sample_count(const LaunchCtx &lc, SampleCountArgs a, uint8_t *seeds, size_t seed_bytes) {
@@ -178,6 +180,26 @@ hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, u
     return hipGetLastError();
 }
 
+
+// Finite check of an input array: any NaN or infinity sets *flag.  Grid-stride
+// loop, one float per thread and step.
+__global__ __launch_bounds__(256) void k_check_finite(const float *p, int64_t n, unsigned int *flag) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t b = __float_as_uint(p[i]);
+        bad |= (b & 0x7f800000u) == 0x7f800000u;  // exponent all ones: NaN or infinity
+    }
+    if (bad) atomicOr(flag, 1u);
+}
+
+hipError_t launch_check_finite(const LaunchCtx &lc, const float *p, int64_t n, unsigned int *flag) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > (int64_t)lc.num_cu * 8) blocks = (int64_t)lc.num_cu * 8;
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, lc.stream, p, n, flag);
+    return hipGetLastError();
+}
 
 }  // namespace cs
 

@@ -157,3 +157,23 @@ def test_nullspace_patch_lies_in_cosupport():
     m = oracle.cosupport(a[None, :], 1e-5)[0]
     got = [j for j in range(k) if (int(m[j // 64]) >> (j % 64)) & 1]
     assert got == sorted(J)
+
+
+def test_nonfinite_inputs_are_rejected(cfg0):
+    """A NaN or an infinity in the colours or the operator has no meaning in the
+    method (Sec. 2, Sec. 3.1): the oracle reports it instead of computing."""
+    import numpy as np
+    import oracle
+    w = cfg0
+    for which, val in (("rgb", np.nan), ("rgb", np.inf), ("omega", -np.inf)):
+        rgb, om = w.rgb.copy(), w.omega.copy()
+        (rgb if which == "rgb" else om).flat[17] = val
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.analyze(rgb, w.p, w.mask_sigma, om)
+        assert e.value.code == oracle.CSO_ERR_NONFINITE
+    rgb = w.rgb.copy()
+    rgb[1, 3, 4] = np.nan
+    masks = np.zeros((w.N, 1), np.uint64)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.label_loglik(rgb, masks, w.k, w.sample_pix, w.sample_label, w.L)
+    assert e.value.code == oracle.CSO_ERR_NONFINITE

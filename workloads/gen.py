@@ -73,7 +73,8 @@ class Workload:
         return int(self.sample_pix.shape[0])
 
 
-# Shapes of the five workloads (the metric is quoted on "bsds_fp32").
+# Shapes of the workloads: the tiny case, the BSDS-sized case and its BF16
+# form, the large case and its BF16 form, and the surrogate case.
 CONFIGS: Dict[int, dict] = {
     0: dict(name="tiny_64x64_p5_k50_L3", H=64, W=64, R=3, p=5, k=50,
             scribble="uniform", per_region=200, bandnoise=False, train_frac=0.0),
@@ -86,7 +87,12 @@ CONFIGS: Dict[int, dict] = {
             scribble="strokes", total=50000, bandnoise=True, train_frac=0.0),
     4: dict(name="surrogate_2048x2048_p7_k98_L10", H=2048, W=2048, R=10, p=7, k=98,
             scribble="strokes", total_frac=0.05, bandnoise=False, train_frac=0.02),
+    5: dict(name="large_1024x1024_p11_k242_L16_bf16", H=1024, W=1024, R=16, p=11, k=242,
+            scribble="strokes", total=50000, bandnoise=True, train_frac=0.0, precision="bf16"),
 }
+
+# Precision forms run on exactly the inputs of their FP32 case.
+_SAME_INPUTS = {2: 1, 5: 3}
 
 
 def make_omega(k: int, n: int, rng: np.random.Generator) -> np.ndarray:
@@ -251,10 +257,11 @@ def make_workload(name: str, H: int, W: int, R: int, p: int, k: int, seed: int,
 
 def make_config(c: int) -> Workload:
     """Workload c of CONFIGS with its fixed seed BASE_SEED + c.  The BF16
-    precision form (2) runs on exactly the inputs of the FP32 case (1)."""
+    precision forms (2 and 5) run on exactly the inputs of their FP32 cases
+    (1 and 3)."""
     cfg = dict(CONFIGS[c])
     name = cfg.pop("name")
-    seed = BASE_SEED + (1 if c == 2 else c)
+    seed = BASE_SEED + _SAME_INPUTS.get(c, c)
     return make_workload(name=name, seed=seed, **cfg)
 
 
