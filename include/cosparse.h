@@ -132,6 +132,26 @@ int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask
                  double margin, uint64_t *masks, cs_cosupport_stats *stats);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the masks of
+ * cs_cosupport, bit for bit, from a call that allocates nothing.  Its scratch
+ * (per-row thresholds and margins, a counter and the patch mask table, at
+ * most 8 KiB: k <= 256, p <= 15 always fit) lives in a static device array of
+ * the library, one per device, set up by cs_create and held until the process
+ * ends; the call only launches kernels on the context's stream (no copy, no
+ * synchronisation, no allocation, no event).  Every call on one device shares
+ * that array: calls that overlap on one device (other streams, other contexts,
+ * other host threads) race and must be ordered by the caller.  No statistics
+ * are returned and the optional finite check is not applied (both would
+ * synchronise).
+ * Arguments, layouts, ownership and errors: as cs_cosupport (without stats);
+ * CS_ERR_ARG also when the scratch would exceed its maximum.
+ */
+int cs_cosupport_noalloc(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                         const float *omega, int k, int precision, const float *alpha, double tau,
+                         double margin, uint64_t *masks);
+
+/*
  * The whole co-support step of Sec. 2 from pixels, with no host round trip:
  * analysed vectors (as cs_analyze_patches), tau = frac * median{|a|} selected
  * exactly on the device (as cs_tau_median), and the masks at that tau (as

@@ -51,6 +51,7 @@ SIGNATURES = {
     "cs_tau_median": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, ctypes.POINTER(_D)]),
     "cs_cosupport": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, _D, _P,
                           ctypes.POINTER(_CosupportStatsC)]),
+    "cs_cosupport_noalloc": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _P, _D, _D, _P]),
     "cs_cosupport_median": (_I, [_P, _P, _I, _I, _I, _D, _P, _I, _I, _D, _D, _P, _P, _P]),
     "cs_texture_similarity": (_I, [_P, _P, _I64, _P, _I64, _I, _P]),
     "cs_label_loglik": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, _I64, _I,
@@ -254,6 +255,25 @@ class Context:
                                        ctypes.byref(st) if stats else None))
         if stats:
             return out, {"recomputed": int(st.recomputed), "max_margin": float(st.max_margin)}
+        return out
+
+    def cosupport_noalloc(self, rgb, p, mask_sigma, omega, tau, out: torch.Tensor, margin=-1.0,
+                          precision="fp32", alpha: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """cs_cosupport_noalloc: the masks of cosupport() from a call that
+        allocates nothing (the caller passes the output buffer)."""
+        H, W = _image_hw(rgb)
+        k = _omega_k(omega, p)
+        _numel(alpha, H * W * k, "alpha", "H*W*k")
+        _masks_shape(out, H * W, k)
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(omega, torch.float32, "omega")
+        if alpha is not None:
+            self._dev(alpha, torch.float32, "alpha")
+        self._dev(out, torch.int64, "masks")
+        self._sync_stream()
+        self._check(lib().cs_cosupport_noalloc(self._h, _ptr(rgb), H, W, p, float(mask_sigma), _ptr(omega), k,
+                                               _PREC[precision], _ptr(alpha), float(tau), float(margin),
+                                               _ptr(out)))
         return out
 
     def cosupport_median(self, rgb, p, mask_sigma, omega, frac=0.1, margin=-1.0, precision="fp32",

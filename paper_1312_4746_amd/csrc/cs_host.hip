@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -18,6 +19,14 @@
 #include "cs_internal.h"
 
 using namespace cs;
+
+// Scratch memory of the allocation-free entry point (cs_cosupport_noalloc):
+// one array per device, part of the library's code object, held until the
+// process ends.  Host code must never use the array's name as an address:
+// its device address on each device comes from hipGetSymbolAddress (see
+// scratch_address), and every call on one device shares it.
+constexpr size_t kScratchBytes = 8192;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 struct cs_ctx {
     int device = 0;
@@ -63,6 +72,8 @@ struct cs_ctx {
     bool lstats_valid = false;
     // optional finite check of rgb and omega before any launch
     bool check_finite = false;
+    // the device's allocation-free scratch array (address on this device)
+    char *scratch = nullptr;
 };
 
 namespace {
@@ -87,6 +98,27 @@ int fail(cs_ctx *c, int code, const char *fmt, ...) {
     } while (0)
 
 LaunchCtx lc_of(const cs_ctx *c) { return LaunchCtx{c->stream, c->num_cu}; }
+
+// Device address of the scratch array on `device` (current), looked up once
+// per device and kept for the life of the process.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, char **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = (char *)ptr;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
 
 // Waits until the sample scan of this call has written `tag` into host memory
 // (the label counts before it are then visible): spins, yields after 2 ms,
@@ -183,15 +215,19 @@ struct Timed {
 
 // Gaussian mask w_t = exp(-(u^2+v^2) / (2 sigma^2)) of Sec. 3.1, host FP64,
 // uploaded once per (p, sigma).
-int ensure_mask(cs_ctx *ctx, int p, double sigma) {
-    if (ctx->wmask && ctx->wmask_p == p && ctx->wmask_sigma == sigma) return CS_OK;
-    double w[15 * 15];
+void mask_table(int p, double sigma, double *w) {
     const int h = (p - 1) / 2;
     for (int u = -h; u <= h; ++u)
         for (int v = -h; v <= h; ++v) {
             const double r2 = (double)(u * u + v * v);
             w[(u + h) * p + (v + h)] = std::exp(-r2 / (2.0 * sigma * sigma));
         }
+}
+
+int ensure_mask(cs_ctx *ctx, int p, double sigma) {
+    if (ctx->wmask && ctx->wmask_p == p && ctx->wmask_sigma == sigma) return CS_OK;
+    double w[15 * 15];
+    mask_table(p, sigma, w);
     if (!ctx->wmask) HIP_TRY(hipMalloc((void **)&ctx->wmask, sizeof(double) * 15 * 15));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     HIP_TRY(hipMemcpy(ctx->wmask, w, sizeof(double) * p * p, hipMemcpyHostToDevice));
@@ -275,6 +311,7 @@ int cs_create(cs_ctx **out, int device, void *hip_stream) {
     if (e == hipSuccess) e = hipMalloc((void **)&ctx->lstats, sizeof(unsigned int) * 4);
     if (e == hipSuccess) e = launch_fill_u32(lc_of(ctx), ctx->dctr, kCtrWords, 0u);
     if (e == hipSuccess) e = launch_fill_u32(lc_of(ctx), ctx->lstats, 4, 0u);
+    if (e == hipSuccess) e = scratch_address(device, &ctx->scratch);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         if (ctx->pinned) hipHostFree(ctx->pinned);
@@ -506,6 +543,63 @@ int cs_cosupport(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask
         std::memcpy(&m, ctx->pinned + 8, 8);
         stats->recomputed = (int64_t)c;
         stats->max_margin = m;
+    }
+    return CS_OK;
+}
+
+int cs_cosupport_noalloc(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                         const float *omega, int k, int precision, const float *alpha, double tau,
+                         double margin, uint64_t *masks) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
+    if (rc) return rc;
+    if (!masks) return fail(ctx, CS_ERR_ARG, "masks must be non-null");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(ctx, CS_ERR_ARG, "tau must be finite and >= 0");
+    if (std::isnan(margin) || std::isinf(margin)) return fail(ctx, CS_ERR_ARG, "margin must be finite");
+    // scratch layout: thresholds t_in, t_out (k floats each), per-row margins
+    // (k doubles), the largest margin, the recompute counter, the mask table
+    Carve cv;
+    CosupportWs cw;
+    cw.carve(cv, k);
+    const size_t o_w = cv.take(sizeof(double) * p * p);
+    if (cv.off > kScratchBytes)
+        return fail(ctx, CS_ERR_ARG, "k = %d, p = %d need %zu bytes of scratch; the maximum is %zu", k, p, cv.off,
+                    kScratchBytes);
+    if (!ctx->scratch) return fail(ctx, CS_ERR_HIP, "the scratch array of device %d was not set up", ctx->device);
+    HIP_TRY(hipSetDevice(ctx->device));
+    const LaunchCtx lc = lc_of(ctx);
+    char *sp = ctx->scratch;
+    MaskTable tbl;
+    mask_table(p, mask_sigma, tbl.w);
+    double *wmask = (double *)(sp + o_w);
+    HIP_TRY(launch_put_table(lc, wmask, tbl, p * p));
+    float *t_in = (float *)(sp + cw.o_tin), *t_out = (float *)(sp + cw.o_tout);
+    double *marg = (double *)(sp + cw.o_marg), *mmax = (double *)(sp + cw.o_max);
+    unsigned long long *cnt = (unsigned long long *)(sp + cw.o_cnt);
+    const int n = p * p;
+    // the thresholds kernel also clears the recompute counter
+    HIP_TRY(launch_thresholds(lc, omega, k, n, tau, nullptr, margin, margin_coef(precision, n), t_in, t_out, marg,
+                              mmax, cnt));
+    if (alpha) {
+        HIP_TRY(launch_mask_alpha(lc, alpha, (int64_t)H * W, k, t_in, t_out, tau, nullptr, rgb, H, W, p, wmask,
+                                  omega, masks, cnt));
+    } else {
+        AnalyzeArgs a{};
+        a.rgb = rgb;
+        a.H = H;
+        a.W = W;
+        a.p = p;
+        a.n = n;
+        a.n_pad = n_pad_of(n);
+        a.k = k;
+        a.wmask = wmask;
+        a.omega = omega;
+        a.masks = masks;
+        a.t_in = t_in;
+        a.t_out = t_out;
+        a.tau = tau;
+        a.recomputed = cnt;
+        HIP_TRY(launch_analyze(lc, a, precision));
     }
     return CS_OK;
 }

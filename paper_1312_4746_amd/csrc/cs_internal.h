@@ -65,6 +65,14 @@ struct AnalyzeArgs {
 };
 hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precision);
 
+// The Gaussian patch mask table written to device memory by a one-workgroup
+// kernel that receives it by value as a kernel argument (no copy from host
+// memory, no allocation).
+struct MaskTable {
+    double w[15 * 15];
+};
+hipError_t launch_put_table(const LaunchCtx &lc, double *dst, const MaskTable &t, int n);
+
 // Masks from stored analysed vectors, same decisions as the analysis epilogue.
 // A non-null tau_dev (device) replaces tau, read by the kernel.
 hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N, int k, const float *t_in,

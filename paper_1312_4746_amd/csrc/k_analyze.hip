@@ -425,6 +425,15 @@ hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N,
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_put_table(double *dst, MaskTable t, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = t.w[i];
+}
+
+hipError_t launch_put_table(const LaunchCtx &lc, double *dst, const MaskTable &t, int n) {
+    hipLaunchKernelGGL(k_put_table, dim3(1), dim3(256), 0, lc.stream, dst, t, n);
+    return hipGetLastError();
+}
+
 // Per-row decision thresholds.  One workgroup of 256 threads (k <= 256).
 __global__ __launch_bounds__(256) void k_thresholds(const float *omega, int k, int n, double tau,
                                                      const double *tau_dev, double margin, double coef,
