@@ -2,14 +2,16 @@
 
 One step = the whole data-term path over one synthetic image: analysed
 vectors (MFMA), exact threshold tau, co-support masks, and the per-pixel,
-per-label log-likelihood (distance transform + Parzen sum).  The workload is
-the BSDS-sized case: 481x321 RGB, 7x7 patches, k = 98, 10 labels, 7,720
-scribble samples, FP32.  Inputs are resident in HBM before timing starts.
+per-label log-likelihood (distance transform + Parzen sum).  The default
+workload is the large case: 1024x1024 RGB, 11x11 patches, k = 242, 16 labels,
+50,000 scribble samples, FP32 (5.24e10 pixel x sample pairs per step).
+Inputs are resident in HBM before timing starts.
 
 Prints one JSON line with the whole-job throughput (pixel x sample pairs/s),
 the roofline of the dominant kernel (the Parzen sum, measured with HIP events
-on the stream it runs on) and the FP64 oracle timed on the host on a bounded
-sample of the same workload.
+on the stream it runs on), the FP64 oracle timed on the host on a bounded
+sample of the same workload, and the learned surrogate's pixel rate on its
+own workload (2048x2048) with its flip rate against the exact path.
 """
 from __future__ import annotations
 
@@ -22,16 +24,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs at 2.4 GHz; the published FP32 vector rate 157.3 TFLOP/s is
-# 128 FMA lanes per clock per CU, i.e. 7.86e13 single-rate VALU lane-operations
-# per second; HBM3E 8 TB/s; FP32 matrix 157.3 TFLOP/s; BF16 dense 2.5 PFLOP/s.
-PEAK_LANE_OPS = 157.3e12 / 2
+# MI355X published peaks: FP32 vector 157.3 TFLOP/s (256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz x 2 flops per FMA x 2 for packed FP32), FP32 matrix 157.3
+# TFLOP/s, BF16 dense matrix 2.5 PFLOP/s, HBM3E 8 TB/s.
+PEAK_FP32_VECTOR = 157.3e12
 PEAK_HBM = 8.0e12
+PEAK_MFMA = {"fp32": 157.3e12, "bf16": 2.5e15}
+# issue model of the VALU (measured on gfx950 with a probe kernel): a wave64
+# VALU instruction occupies its SIMD for 4 cycles, a transcendental for 8
+SIMDS, CLOCK_HZ, VALU_CYCLES, TRANS_CYCLES = 1024, 2.4e9, 4, 8
 # the Parzen kernel carries timing events on one launch in this many inside the timed region
+PARZEN_EVENT_PERIOD = 8
 # smooth co-support map exp(-a^2 / sigma) of the paper's experiments
 SIGMA_IOTA = 0.01
-PARZEN_EVENT_PERIOD = 8
-PEAK_MFMA = {"fp32": 157.3e12, "bf16": 2.5e15}
 
 
 def parzen_ops_per_pair(k: int, texture: bool = True) -> int:
@@ -47,7 +52,8 @@ def parzen_ops_per_pair(k: int, texture: bool = True) -> int:
     return 17 + 2 * ((k + 31) // 32) + 4
 
 
-def load_traffic(name: str):
+def load_profile(name: str):
+    """A committed counter summary (profiles/<name>) or None."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -99,52 +105,113 @@ def precision_sweep(ctx, w, rgb, om, alpha, spix, slab, prm):
     return {"tau": tau, "proven_margin_max": st["max_margin"], "rows": rows}
 
 
-def cpu_baseline(w, n_sample: int, joint: bool = False, soft: bool = False):
-    """The FP64 oracle on the host: full-image analysis, tau and masks (needed
-    for any pixel), then the Parzen log-likelihood on a strided subset of
-    pixels; the per-pixel front-end time is scaled to the subset."""
+def cpu_baseline(w, n_sample: int, joint: bool = False, soft: bool = False, n_front: int = 65536):
+    """The FP64 oracle on the host, on a bounded sample of the workload: the
+    Parzen log-likelihood of n_sample evenly strided pixels, plus their share
+    of the front end (analysis, tau and masks of every pixel, needed for any
+    pixel).  Up to 2 n_front pixels the front end runs on the whole image;
+    above, it runs on n_front strided pixels and is scaled to the image:
+    analysis and masks by the pixel count, the sort of the median by
+    n log n of the entry count (an extrapolation, stated in the sample)."""
+    import math
+
     import numpy as np
 
     import oracle
     oracle.lib()
-    t0 = time.perf_counter()
-    alpha = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega)
-    if not soft:  # the smooth form needs no threshold and no masks
-        tau, _ = oracle.tau_median(alpha, w.tau_frac)
-        masks = oracle.cosupport(alpha, tau)
-    t_front = time.perf_counter() - t0
-    pix = np.linspace(0, w.N - 1, n_sample).astype(np.int32)
+    N, k = w.N, w.k
+    nw = (k + 63) // 64
+    pix = np.linspace(0, N - 1, n_sample).astype(np.int32)
+    if N <= 2 * n_front:
+        t0 = time.perf_counter()
+        alpha = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega)
+        if not soft:  # the smooth form needs no threshold and no masks
+            tau, _ = oracle.tau_median(alpha, w.tau_frac)
+            masks = oracle.cosupport(alpha, tau)
+        t_front = time.perf_counter() - t0
+        how = f"analysis{'' if soft else ', tau and masks'} of all {N} pixels ({t_front:.2f} s)"
+    else:
+        fpix = np.linspace(0, N - 1, n_front).astype(np.int32)
+        t0 = time.perf_counter()
+        a_f = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega, pix=fpix)
+        t_an = time.perf_counter() - t0
+        tau = None
+        t_sort = t_cos = 0.0
+        if not soft:
+            t0 = time.perf_counter()
+            tau, _ = oracle.tau_median(a_f, w.tau_frac)
+            t_sort = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            oracle.cosupport(a_f, tau)
+            t_cos = time.perf_counter() - t0
+        # the log-likelihood needs the co-supports (or analysed vectors) of the
+        # listed pixels and of every sample's pixel (work of the front end above)
+        need = np.unique(np.concatenate([pix, w.sample_pix])).astype(np.int32)
+        a_n = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega, pix=need)
+        if soft:
+            alpha = np.zeros((N, k))
+            alpha[need] = a_n
+        else:
+            masks = np.zeros((N, nw), np.uint64)
+            masks[need] = oracle.cosupport(a_n, tau)
+        e_f, e_full = n_front * k, N * k
+        t_front = (t_an + t_cos) * N / n_front + t_sort * (e_full * math.log2(e_full)) / (e_f * math.log2(e_f))
+        how = (f"analysis{'' if soft else ', tau (sort) and masks'} of {n_front} strided pixels "
+               f"({t_an + t_sort + t_cos:.2f} s), extrapolated to all {N} pixels ({t_front:.1f} s: analysis and "
+               f"masks by pixel count, the sort by n log n)")
     t1 = time.perf_counter()
     if soft:
         oracle.label_loglik_soft(w.rgb, alpha, SIGMA_IOTA, w.sample_pix, w.sample_label, w.L, pix=pix)
     else:
-        oracle.label_loglik(w.rgb, masks, w.k, w.sample_pix, w.sample_label, w.L, pix=pix, joint=joint)
+        oracle.label_loglik(w.rgb, masks, k, w.sample_pix, w.sample_label, w.L, pix=pix, joint=joint)
     t_ll = time.perf_counter() - t1
-    t_equiv = t_ll + t_front * n_sample / w.N
+    t_equiv = t_ll + t_front * n_sample / N
     pairs = n_sample * w.M
     return {
         "value": pairs / t_equiv,
         "unit": "pairs/s",
         "cores": oracle.get_threads(),
         "kind": "oracle",
-        "sample": (f"FP64 oracle: analysis{'' if soft else ', tau and masks'} of all {w.N} pixels ({t_front:.2f} s, "
-                   f"scaled to the subset) + Parzen log-likelihood of {n_sample} evenly strided "
-                   f"pixels x {w.M} samples ({t_ll:.2f} s)"),
+        "sample": (f"FP64 oracle: {how}, scaled to the subset, + Parzen log-likelihood of {n_sample} evenly "
+                   f"strided pixels x {w.M} samples ({t_ll:.2f} s)"),
     }
 
 
-def surrogate_bench(args):
-    """Learned surrogate at the 2048x2048 workload: exact data term on every
-    pixel (the reference), exact targets at the 2 % training pixels, training,
-    inference on every pixel, flip rate and the equal-time comparison."""
+def add_surrogate_args(ap):
+    ap.add_argument("--mlp-steps", type=int, default=3000)
+    ap.add_argument("--mlp-batch", type=int, default=4096)
+    ap.add_argument("--mlp-lr", type=float, default=3e-3)
+    ap.add_argument("--fallback-margin", type=float, default=1.0,
+                    help="pixels whose two largest surrogate outputs differ by less than this (nats) "
+                         "take the exact data term")
+    ap.add_argument("--sur-precision", default="bf16", choices=["bf16", "fp32"],
+                    help="analysis precision of the surrogate path (its features; the masks of its "
+                         "exact targets and fallback are exact either way)")
+
+
+def surrogate_line(args) -> dict:
+    """The learned surrogate at the 2048x2048 workload, per image and measured
+    against the plain FP32 exact data term on the same GPU.
+
+    Exact path: co-support step (FP32) and the Parzen log-likelihood of every
+    pixel.  Surrogate path: co-support step with the BF16 analysis (the
+    analysed vectors are the network's features; the masks are the exact
+    ones), exact targets at the 2 % training pixels, training, then inference
+    on every pixel with the exact data term for the pixels whose two largest
+    outputs differ by less than the fallback margin.  Reported: the pixel
+    rate once trained (analysis + inference + fallback), the rate per image
+    with targets and training included, the flip rate and |dl| against the
+    exact path, and the exact path on a random sample subset sized to the
+    surrogate path's whole per-image time (the method without the network at
+    equal time)."""
     import numpy as np
     import torch
 
-    from paper_1312_4746_amd import Context, LoglikParams
+    from paper_1312_4746_amd import Context, LoglikParams, Mlp, mlp_features
     from paper_1312_4746_amd import surrogate as sg
     from workloads import make_config, mlp_init, mlp_order
 
-    w = make_config(args.config)
+    w = make_config(4)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     rgb, om = dev(w.rgb), dev(w.omega)
     spix, slab = dev(w.sample_pix), dev(w.sample_label)
@@ -152,9 +219,13 @@ def surrogate_bench(args):
     prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
                        rho_floor_px=w.rho_floor_px)
     ctx = Context(0)
-    alpha = torch.empty((w.N, w.k), dtype=torch.float32, device="cuda")
-    masks = torch.empty((w.N, (w.k + 63) // 64), dtype=torch.int64, device="cuda")
+    nw = (w.k + 63) // 64
+    a32 = torch.empty((w.N, w.k), dtype=torch.float32, device="cuda")
+    m32 = torch.empty((w.N, nw), dtype=torch.int64, device="cuda")
+    asur = torch.empty_like(a32)
+    msur = torch.empty_like(m32)
     ll = torch.empty((w.N, w.L), dtype=torch.float32, device="cuda")
+    y = torch.empty_like(ll)
 
     def timed(fn, reps=1):
         torch.cuda.synchronize()
@@ -164,86 +235,125 @@ def surrogate_bench(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps, r
 
-    def front():
-        ctx.analyze_patches(rgb, w.p, w.mask_sigma, om, precision=w.precision, out=alpha)
-        tau = ctx.tau_median(rgb, w.p, w.mask_sigma, om, alpha, w.tau_frac, precision=w.precision)
-        ctx.cosupport(rgb, w.p, w.mask_sigma, om, tau, precision=w.precision, out=masks, alpha=alpha)
-
-    front()  # warm-up
-    t_front, _ = timed(front, 2)
-    t_analyze, _ = timed(lambda: ctx.analyze_patches(rgb, w.p, w.mask_sigma, om, precision=w.precision,
-                                                     out=alpha), 2)
-    front()
-    exact = lambda: ctx.label_loglik(rgb, masks, w.k, spix, slab, w.L, prm, out=ll)  # noqa: E731
+    # exact path (the reference)
+    front32 = lambda: ctx.cosupport_median(rgb, w.p, w.mask_sigma, om, w.tau_frac, alpha=a32, out=m32)  # noqa: E731
+    exact = lambda: ctx.label_loglik(rgb, m32, w.k, spix, slab, w.L, prm, out=ll)  # noqa: E731
+    front32()
     exact()
+    t_front32, _ = timed(front32, 3)
     t_exact, _ = timed(exact, 1)
 
-    batch, steps = args.mlp_batch, args.mlp_steps
+    # surrogate path
+    steps, batch = args.mlp_steps, args.mlp_batch
     order = dev(mlp_order(len(w.train_pix), steps, batch, seed=w.seed + 101).ravel())
     init = dev(mlp_init(5 + w.k, 128, w.L, seed=w.seed + 100))
-    t_fit, fit = timed(lambda: sg.fit(ctx, rgb, alpha, masks, w.k, spix, slab, w.L, prm, tpix, init, order,
-                                      batch, args.mlp_lr))
-    net = fit.net
-    y = torch.empty((w.N, w.L), dtype=torch.float32, device="cuda")
-    net.infer(rgb, alpha, out=y)
-    reps = 5
-    t_infer, _ = timed(lambda: net.infer(rgb, alpha, out=y), reps)
-    quality = sg.compare_to_exact(y, ll)
+    front_s = lambda: ctx.cosupport_median(rgb, w.p, w.mask_sigma, om, w.tau_frac,  # noqa: E731
+                                           precision=args.sur_precision, alpha=asur, out=msur)
+    front_s()
+    t_front_s, _ = timed(front_s, 3)
+    ctx.label_loglik(rgb, msur, w.k, spix, slab, w.L, prm, pix_subset=tpix)  # warm-up of the list path
+    t_targets, ell = timed(lambda: ctx.label_loglik(rgb, msur, w.k, spix, slab, w.L, prm, pix_subset=tpix))
+    t_feat, x = timed(lambda: mlp_features(ctx, rgb, asur, tpix))
+    net = Mlp(ctx, 5 + w.k, w.L, init)
 
-    # equal-time exact path: a sample subset sized to the surrogate's time
-    m_eq = max(w.L, int(w.M * t_infer / t_exact))
+    def fit():
+        net.fit_output_bias(ell)
+        return net.train(x, ell, order, batch, args.mlp_lr)
+
+    t_fit, trace = timed(fit)
+    net.infer(rgb, asur, out=y)
+    t_infer, _ = timed(lambda: net.infer(rgb, asur, out=y), 5)
+    q_plain = sg.compare_to_exact(y, ll)
+    net.infer_fallback(rgb, asur, msur, w.k, spix, slab, prm, margin=args.fallback_margin, out=y)
+    t_infer_fb, (_, n_exact) = timed(lambda: net.infer_fallback(rgb, asur, msur, w.k, spix, slab, prm,
+                                                                margin=args.fallback_margin, out=y), 3)
+    q = sg.compare_to_exact(y, ll)
+    t_image = t_front_s + t_targets + t_feat + t_fit + t_infer_fb
+
+    # the method without the network at equal time: the exact path on a random
+    # sample subset sized so that front + Parzen take the surrogate path's time
+    frac_eq = max(0.0, min(1.0, (t_image - t_front32) / t_exact))
+    m_eq = max(w.L, int(w.M * frac_eq))
     gen = torch.Generator().manual_seed(w.seed + 102)
     sp2, sl2 = sg.equal_time_subset(spix, slab, w.L, m_eq, gen)
     ll2 = torch.empty_like(ll)
-    ctx.label_loglik(rgb, masks, w.k, sp2, sl2, w.L, prm, out=ll2)
-    t_sub, _ = timed(lambda: ctx.label_loglik(rgb, masks, w.k, sp2, sl2, w.L, prm, out=ll2), 1)
+    ctx.label_loglik(rgb, m32, w.k, sp2, sl2, w.L, prm, out=ll2)
+    t_sub, _ = timed(lambda: ctx.label_loglik(rgb, m32, w.k, sp2, sl2, w.L, prm, out=ll2), 1)
     q_sub = sg.compare_to_exact(ll2, ll)
-    trace = fit.loss_trace.cpu().numpy()
-
+    tr = trace.cpu().numpy()
+    t_exact_total = t_front32 + t_exact
     out = {
         "metric": "surrogate px/s at <=0.5% label-argmax flips",
-        "value": w.N / t_infer,
+        "value": w.N / (t_front_s + t_infer_fb),
         "unit": "px/s",
         "n_gpus": 1,
-        "steps": reps,
+        "steps": 3,
         "warmup": 1,
-        "ms_per_step": t_infer * 1e3,
+        "ms_per_step": (t_front_s + t_infer_fb) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f32",
+        "dtype": f"{args.sur_precision}+f32",
         "data": "synthetic",
         "config": {"workload": w.name, "H": w.H, "W": w.W, "k": w.k, "labels": w.L, "samples": w.M,
                    "pixels": w.N, "train_pixels": int(len(w.train_pix)), "parallelism": "1 GPU"},
         "surrogate": {
-            "flip_rate": quality["flip_rate"],
-            "meets_0p5pct": quality["flip_rate"] <= 0.005,
-            "mean_abs_dl": quality["mean_abs_dl"],
-            "mean_abs_dl_within_20_nats": quality["mean_abs_dl_within_20_nats"],
-            "infer_ms": t_infer * 1e3,
+            "flip_rate": q["flip_rate"],
+            "meets_0p5pct": q["flip_rate"] <= 0.005,
+            "mean_abs_dl": q["mean_abs_dl"],
+            "mean_abs_dl_within_20_nats": q["mean_abs_dl_within_20_nats"],
+            "fallback": {"margin_nats": args.fallback_margin, "pixels": n_exact,
+                         "fraction": n_exact / w.N},
+            "without_fallback": {"flip_rate": q_plain["flip_rate"],
+                                 "mean_abs_dl_within_20_nats": q_plain["mean_abs_dl_within_20_nats"]},
+            "analysis_precision": args.sur_precision,
+            "ms": {"front": t_front_s * 1e3, "targets": t_targets * 1e3, "features": t_feat * 1e3,
+                   "fit": t_fit * 1e3, "infer": t_infer * 1e3, "infer_with_fallback": t_infer_fb * 1e3,
+                   "per_image": t_image * 1e3},
+            "px_per_s_trained": w.N / (t_front_s + t_infer_fb),
+            "px_per_s_per_image_incl_fit": w.N / t_image,
             "train": {"steps": steps, "batch": batch, "lr": args.mlp_lr,
-                      "fit_ms_incl_targets": t_fit * 1e3,
-                      "loss_first": float(trace[:20].mean()), "loss_last": float(trace[-20:].mean())},
+                      "loss_first": float(tr[:20].mean()), "loss_last": float(tr[-20:].mean())},
         },
-        "exact": {"px_per_s": w.N / (t_front + t_exact), "front_ms": t_front * 1e3,
-                  "loglik_ms": t_exact * 1e3, "pairs_per_s": w.N * w.M / t_exact},
-        "speedup_vs_exact_data_term": (t_front + t_exact) / (t_analyze + t_infer),
-        "equal_time_exact": {"samples": int(sp2.numel()), "ms": t_sub * 1e3, "flip_rate": q_sub["flip_rate"],
+        "exact": {"px_per_s": w.N / t_exact_total, "front_ms": t_front32 * 1e3, "loglik_ms": t_exact * 1e3,
+                  "pairs_per_s": w.N * w.M / t_exact},
+        "speedup_per_image_incl_fit": t_exact_total / t_image,
+        "speedup_trained": t_exact_total / (t_front_s + t_infer_fb),
+        "equal_time_exact": {"samples": int(sp2.numel()), "sample_fraction": sp2.numel() / w.M,
+                             "ms": (t_front32 + t_sub) * 1e3, "flip_rate": q_sub["flip_rate"],
                              "mean_abs_dl_within_20_nats": q_sub["mean_abs_dl_within_20_nats"]},
     }
-    print(json.dumps(out))
     net.close()
     ctx.close()
+    return out
+
+
+def counter_profile(kernel: str, workload: str, digest_of=None):
+    """The committed counter summary of `kernel` at `workload`
+    (profiles/<kernel>_<workload>_counters.json), or None when it is absent or
+    was taken on another source of the kernel."""
+    prof = load_profile(f"{kernel}_{workload}_counters.json")
+    if not prof or prof.get("workload") != workload:
+        return None
+    if digest_of is not None and prof.get("source_digest") != digest_of():
+        return None
+    return prof
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--config", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=32768)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=3,
+                    help="workload: 3 large (default), 5 large with BF16 analysis, 1 BSDS-sized, "
+                         "2 BSDS-sized with BF16 analysis, 0 tiny, 4 the surrogate case alone")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="pixels of the oracle's log-likelihood sample (0: 2048 for images above "
+                         "131072 pixels, else 32768)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="leave out the surrogate leg (2048x2048) of the headline line")
     ap.add_argument("--soft", action="store_true",
                     help="the joint form with smooth co-supports (sigma 0.01) of the stored "
                          "analysed vectors")
@@ -253,9 +363,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times), to scale the HBM "
                          "byte counters of a profiler run")
-    ap.add_argument("--mlp-steps", type=int, default=3000)
-    ap.add_argument("--mlp-batch", type=int, default=4096)
-    ap.add_argument("--mlp-lr", type=float, default=1e-3)
+    add_surrogate_args(ap)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the data term runs on a single MI355X "
@@ -274,7 +382,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes_per_launch_read": n * 4, "written": n * 4, "launches": 5}))
         return
     if args.config == 4:
-        surrogate_bench(args)
+        print(json.dumps(surrogate_line(args)))
         return
 
     import numpy as np
@@ -312,6 +420,7 @@ def main():
     if args.soft:
         step = step_soft  # noqa: F811
 
+    print(f"[bench] {w.name}: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -332,7 +441,7 @@ def main():
     parzen_ms, parzen_n = ctx.profile_read("parzen")
     ctx.profile_sample(1)
     # the per-step spread, from events between steps outside the timed region
-    spread_steps = min(args.steps, 50)
+    spread_steps = min(args.steps, 20)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(spread_steps + 1)]
     ev[0].record()
     for i in range(spread_steps):
@@ -340,15 +449,20 @@ def main():
         ev[i + 1].record()
     torch.cuda.synchronize()
     per_step = [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(spread_steps)]
-    # the other stages' kernel times, from a few more steps outside the timed region
+    # every stage's kernel time, from a few more steps outside the timed region
     stage_steps = 3
     ctx.profile_only(None)
     ctx.profile_enable(True)
     for _ in range(stage_steps):
         step()
+    stage_names = ["analyze", "tau_select", "cosupport", "tau_exact", "cosupport_fix", "thresholds", "samples",
+                   "edt", "stream", "texture_rep", "coef", "parzen", "parzen_fixup", "texture", "normalise"]
+    stages = {}
+    for nm in stage_names:
+        ms_, n_ = ctx.profile_read(nm)
+        if n_:
+            stages[nm] = ms_ / stage_steps
     analyze_ms, analyze_n = ctx.profile_read("analyze")
-    cos_ms, cos_n = ctx.profile_read("cosupport")
-    edt_ms, _ = ctx.profile_read("edt")
     ctx.profile_enable(False)
 
     ms_per_step = dt * 1e3 / args.steps
@@ -357,26 +471,32 @@ def main():
 
     avg_parzen_s = parzen_ms / 1e3 / max(parzen_n, 1)
     tex_in_sum = not (args.joint or args.soft)
-    ops = pairs * parzen_ops_per_pair(w.k, tex_in_sum)
-    achieved = ops / avg_parzen_s
-    traffic = None
-    tr = load_traffic("parzen_bsds_traffic.json")
-    # counters taken on this kernel source and this workload only
-    if (tr and not (args.joint or args.soft) and tr.get("source_digest") == kernel_source_digest()
-            and tr.get("workload") == w.name):
-        traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                "kernel": "k_parzen_mfma", "avg_launch_ms": avg_parzen_s * 1e3,
-                "ops_per_pair": parzen_ops_per_pair(w.k, tex_in_sum)}
+    ops_pp = parzen_ops_per_pair(w.k, tex_in_sum)
+    achieved = pairs * ops_pp / avg_parzen_s
+    prof = counter_profile("k_parzen_mfma", w.name, kernel_source_digest) if tex_in_sum else None
+    traffic = prof.get("bytes_per_launch") if prof else None
+    counters = None
+    if prof:
+        counters = {k_: prof.get(k_) for k_ in ("valu_issue_frac", "valu_busy_frac", "mfma_busy_frac",
+                                                "valu_insts_per_pair", "avg_duration_us")}
+        if traffic:
+            counters["hbm_gbs_live"] = traffic / avg_parzen_s / 1e9
+            counters["hbm_frac"] = traffic / avg_parzen_s / PEAK_HBM
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
+                "kernel": "k_parzen_mfma", "avg_launch_ms": avg_parzen_s * 1e3, "ops_per_pair": ops_pp,
+                "ops_model": "direct evaluation per pair: location 4, colour 6, XOR+popcount 2 ceil(k/32), "
+                             "convert+exponent 4, log-sum-exp 3, v_exp_f32 as 4 slots",
+                "counters": counters}
     avg_an = analyze_ms / 1e3 / max(analyze_n, 1)
     gemm_flops = 2.0 * w.k * w.n * w.N
+    an_prof = counter_profile("k_analyze", w.name)
     extra = {
         "analyze_mfma": {"avg_launch_ms": avg_an * 1e3, "achieved_tflops": gemm_flops / avg_an / 1e12,
                          "peak_tflops": PEAK_MFMA[w.precision] / 1e12,
-                         "frac": gemm_flops / avg_an / PEAK_MFMA[w.precision]},
-        "cosupport_avg_launch_ms": cos_ms / max(cos_n, 1),
-        "edt_ms_per_step": edt_ms / stage_steps,
+                         "frac": gemm_flops / avg_an / PEAK_MFMA[w.precision],
+                         "mfma_busy_frac": an_prof.get("mfma_busy_frac") if an_prof else None},
+        "stage_ms_per_step": stages,
         "px_per_s": w.N / (ms_per_step / 1e3),
         "step_ms_min_median_max": [min(per_step) * 1e3, float(np.median(per_step)) * 1e3,
                                    max(per_step) * 1e3],
@@ -384,10 +504,21 @@ def main():
     }
     if w.precision == "bf16":
         extra["precision_sweep"] = precision_sweep(ctx, w, rgb, om, alpha, spix, slab, prm)
+    ctx.close()
+    del alpha, masks, ll
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, min(args.cpu_sample, w.N), joint=args.joint, soft=args.soft)
+        print("[bench] oracle baseline on the host", file=sys.stderr, flush=True)
+        n_cpu = args.cpu_sample or (2048 if w.N > 131072 else 32768)
+        cpu = cpu_baseline(w, min(n_cpu, w.N), joint=args.joint, soft=args.soft)
+
+    sur = None
+    if not args.no_surrogate and not (args.joint or args.soft):
+        print("[bench] surrogate leg (2048x2048)", file=sys.stderr, flush=True)
+        full = surrogate_line(args)
+        sur = {k_: full[k_] for k_ in ("value", "unit", "ms_per_step")}
+        sur.update({"workload": full["config"]["workload"], **full["surrogate"]})
 
     out = {
         "metric": "data-term pixel x sample pairs/s",
@@ -410,10 +541,10 @@ def main():
                    "samples": w.M, "pixels": w.N, "pairs": pairs, "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "surrogate": sur,
         "extra": extra,
     }
     print(json.dumps(out))
-    ctx.close()
 
 
 if __name__ == "__main__":

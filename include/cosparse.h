@@ -362,6 +362,27 @@ int cs_mlp_train(cs_ctx *ctx, cs_mlp *net, const float *x, const float *ell, int
 int cs_mlp_infer(cs_ctx *ctx, const cs_mlp *net, const float *rgb, int H, int W, const float *alpha, int k,
                  float *out);
 
+/* Surrogate log-likelihoods of every pixel with the exact data term as the
+ * fallback: after cs_mlp_infer, every pixel whose two largest outputs differ
+ * by less than `margin` nats (the surrogate is unsure of the label argmax) is
+ * recomputed exactly, as cs_label_loglik computes it for a pixel list, and
+ * its row of `out` replaced.
+ *   net, rgb, H, W, alpha, k, out   as cs_mlp_infer (out_dim must equal L)
+ *   masks, kmask, sample_pix, sample_label, M, L, prm   as cs_label_loglik
+ *               (masks of k_mask entries; kmask may differ from the
+ *               surrogate's k, e.g. a BF16 analysis feeding the network and
+ *               exact FP64-decided masks feeding the fallback)
+ *   margin      >= 0 and finite (0: no pixel is recomputed unless its two
+ *               outputs tie or are not numbers)
+ *   n_exact     host out or NULL: the number of pixels recomputed
+ * Synchronises once (to read the count).  The context keeps a device buffer
+ * of 4 N (L + 1) bytes for the list and the exact rows.
+ * Errors: those of cs_mlp_infer and cs_label_loglik, CS_ERR_ARG for margin. */
+int cs_mlp_infer_fallback(cs_ctx *ctx, const cs_mlp *net, const float *rgb, int H, int W, const float *alpha, int k,
+                          const uint64_t *masks, int kmask, const int32_t *sample_pix, const int32_t *sample_label,
+                          int64_t M, int L, const cs_loglik_params *prm, double margin, float *out,
+                          int64_t *n_exact);
+
 /* Surrogate outputs of explicit input rows x (device n*in_dim) into out
  * (device n*out_dim).  Errors: CS_ERR_ARG. */
 int cs_mlp_forward(cs_ctx *ctx, const cs_mlp *net, const float *x, int64_t n, float *out);

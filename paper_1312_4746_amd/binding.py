@@ -75,6 +75,8 @@ SIGNATURES = {
     "cs_mlp_fit_output_bias": (_I, [_P, _P, _P, _I64]),
     "cs_mlp_infer": (_I, [_P, _P, _P, _I, _I, _P, _I, _P]),
     "cs_mlp_forward": (_I, [_P, _P, _P, _I64, _P]),
+    "cs_mlp_infer_fallback": (_I, [_P, _P, _P, _I, _I, _P, _I, _P, _I, _P, _P, _I64, _I,
+                                   ctypes.POINTER(_LoglikParamsC), _D, _P, ctypes.POINTER(_I64)]),
 }
 
 _lib = None
@@ -517,6 +519,33 @@ class Mlp:
         self.ctx._check(lib().cs_mlp_infer(self.ctx._h, self._h, _ptr(rgb), H, W, _ptr(alpha), k,
                                            _ptr(out)))
         return out
+
+
+    def infer_fallback(self, rgb: torch.Tensor, alpha: torch.Tensor, masks: torch.Tensor, kmask: int,
+                       sample_pix: torch.Tensor, sample_label: torch.Tensor, params: Optional[LoglikParams] = None,
+                       margin: float = 2.0, out: Optional[torch.Tensor] = None):
+        """Inference with the exact data term for the pixels whose two largest
+        outputs differ by less than `margin` nats; returns (out, pixels
+        recomputed exactly)."""
+        H, W = _image_hw(rgb)
+        k = self.in_dim - 5
+        _numel(alpha, H * W * k, "alpha", "H*W*(in_dim-5)")
+        _numel(out, H * W * self.out_dim, "out", "H*W*out_dim")
+        _masks_shape(masks, H * W, kmask)
+        _samples(sample_pix, sample_label)
+        for t, dt, nm in ((rgb, torch.float32, "rgb"), (alpha, torch.float32, "alpha"), (masks, torch.int64, "masks"),
+                          (sample_pix, torch.int32, "sample_pix"), (sample_label, torch.int32, "sample_label")):
+            self.ctx._dev(t, dt, nm)
+        if out is None:
+            out = torch.empty((H * W, self.out_dim), dtype=torch.float32, device=rgb.device)
+        prm = (params or LoglikParams()).c()
+        n = ctypes.c_int64()
+        self.ctx._sync_stream()
+        self.ctx._check(lib().cs_mlp_infer_fallback(self.ctx._h, self._h, _ptr(rgb), H, W, _ptr(alpha), k, _ptr(masks),
+                                                    kmask, _ptr(sample_pix), _ptr(sample_label), sample_pix.numel(),
+                                                    self.out_dim, ctypes.byref(prm), float(margin), _ptr(out),
+                                                    ctypes.byref(n)))
+        return out, int(n.value)
 
 
 def param_count(in_dim: int, hidden: int, out_dim: int) -> int:

@@ -74,6 +74,9 @@ struct cs_ctx {
     bool check_finite = false;
     // the device's allocation-free scratch array (address on this device)
     char *scratch = nullptr;
+    // the surrogate's exact fallback: pixel list, count and exact rows
+    char *fb = nullptr;
+    size_t fb_bytes = 0;
 };
 
 namespace {
@@ -167,6 +170,20 @@ int ensure_ws(cs_ctx *ctx, size_t bytes) {
         return fail(ctx, CS_ERR_NOMEM, "device workspace of %zu bytes could not be allocated", want);
     }
     ctx->ws_bytes = want;
+    return CS_OK;
+}
+
+int ensure_fb(cs_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->fb_bytes) return CS_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    if (ctx->fb) HIP_TRY(hipFree(ctx->fb));
+    ctx->fb = nullptr;
+    ctx->fb_bytes = 0;
+    if (hipMalloc((void **)&ctx->fb, bytes) != hipSuccess) {
+        ctx->fb = nullptr;
+        return fail(ctx, CS_ERR_NOMEM, "fallback buffer of %zu bytes could not be allocated", bytes);
+    }
+    ctx->fb_bytes = bytes;
     return CS_OK;
 }
 
@@ -336,6 +353,7 @@ int cs_destroy(cs_ctx *ctx) {
     for (auto e : ctx->pool) hipEventDestroy(e);
     if (ctx->ws) hipFree(ctx->ws);
     if (ctx->cand) hipFree(ctx->cand);
+    if (ctx->fb) hipFree(ctx->fb);
     if (ctx->alpha32) hipFree(ctx->alpha32);
     if (ctx->wmask) hipFree(ctx->wmask);
     if (ctx->pinned) hipHostFree(ctx->pinned);
@@ -1020,6 +1038,24 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         fa.fix_cap = (int)(ntiles_pad * L);
         fa.sigma_c = pa.sigma_c;
         fa.texture = pa.texture_in_sum;
+        // labels per block of the work order: as many as keep their sample
+        // streams (features and records of every chunk) within about half of
+        // an XCD's 4 MiB L2 together, counted from the largest labels (at
+        // least one)
+        {
+            const size_t chunk_bytes = (size_t)(fa.texture ? kStreamChunk * KP : 0) + 12 * sizeof(float) * kStreamChunk;
+            const size_t budget = (size_t)2 << 20;
+            size_t used = 0;
+            int lb = 0;
+            while (lb < L) {
+                const int l = pa.label_order[lb];  // decreasing sample count
+                const size_t bytes = (size_t)((segs.pseg[l + 1] - segs.pseg[l]) / kStreamChunk) * chunk_bytes;
+                if (lb > 0 && used + bytes > budget) break;
+                used += bytes;
+                ++lb;
+            }
+            fa.lblock = lb;
+        }
         // per-label chunk ranges and the label order (kernel arguments: no copy)
         for (int l = 0; l <= L; ++l) fa.meta[l] = segs.pseg[l] / kStreamChunk;
         for (int l = 0; l < L; ++l) fa.meta[L + 1 + l] = pa.label_order[l];
@@ -1454,6 +1490,44 @@ int cs_mlp_forward(cs_ctx *ctx, const cs_mlp *net, const float *x, int64_t n, fl
     if (n == 0) return CS_OK;
     if (!x || !out) return fail(ctx, CS_ERR_ARG, "null pointer argument");
     return mlp_forward_impl(ctx, net, x, nullptr, 1, 1, nullptr, 0, n, out);
+}
+
+int cs_mlp_infer_fallback(cs_ctx *ctx, const cs_mlp *net, const float *rgb, int H, int W, const float *alpha, int k,
+                          const uint64_t *masks, int kmask, const int32_t *sample_pix, const int32_t *sample_label,
+                          int64_t M, int L, const cs_loglik_params *prm, double margin, float *out,
+                          int64_t *n_exact) {
+    if (!ctx) return CS_ERR_ARG;
+    if (!net || !rgb || !alpha || !out || !masks) return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    if (net->out != L) return fail(ctx, CS_ERR_ARG, "out_dim %d does not match L = %d", net->out, L);
+    if (!(margin >= 0.0) || !std::isfinite(margin)) return fail(ctx, CS_ERR_ARG, "margin must be finite and >= 0");
+    int rc = cs_mlp_infer(ctx, net, rgb, H, W, alpha, k, out);
+    if (rc) return rc;
+    const int64_t N = (int64_t)H * W;
+    // list (N int32) then the count, then room for the exact rows of every
+    // pixel (the count is known only after the list is made)
+    const size_t o_cnt = ((size_t)N * 4 + 255) / 256 * 256;
+    const size_t o_ex = o_cnt + 256;
+    if ((rc = ensure_fb(ctx, o_ex + sizeof(float) * (size_t)N * L))) return rc;
+    const LaunchCtx lc = lc_of(ctx);
+    int32_t *list = (int32_t *)ctx->fb;
+    unsigned int *cnt = (unsigned int *)(ctx->fb + o_cnt);
+    HIP_TRY(launch_fill_u32(lc, cnt, 1, 0u));
+    {
+        Timed t(ctx, "mlp_uncertain");
+        HIP_TRY(launch_mlp_uncertain(lc, out, N, L, (float)margin, list, cnt));
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, cnt, sizeof(unsigned int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    unsigned int m = 0;
+    std::memcpy(&m, ctx->pinned, sizeof m);
+    if (n_exact) *n_exact = (int64_t)m;
+    if (m == 0) return CS_OK;
+    float *ex = (float *)(ctx->fb + o_ex);
+    rc = label_loglik(ctx, rgb, H, W, masks, kmask, sample_pix, sample_label, M, L, prm, list, (int64_t)m, ex, 0);
+    if (rc) return rc;
+    Timed t(ctx, "mlp_scatter");
+    HIP_TRY(launch_mlp_scatter_rows(lc, ex, list, (int64_t)m, L, out));
+    return CS_OK;
 }
 
 }  // extern "C"

@@ -279,12 +279,13 @@ struct ParzenFastArgs {
     const uint8_t *abf;    // [tile][row block][lane][16 B]: BF16 location operands
     float *loglik;
     unsigned int *work_counter;  // kParzenQueues counters, kQueueStride apart, zero at launch
-    unsigned int *fix_count;  // [0] queued (label, tile), [1] rescaled wave-chunks, [2] overflows
+    unsigned int *fix_count;  // [0] queued (label, tile), [1] rescaled wave-chunks, [2] overflowed passes
     int2 *fixlist;
     int fix_cap;
     int H, W, L, k, ksteps;
     int tiles_x, ntiles, ngroups;
     int texture;           // 0: texture factor out of the sum (no FP8 products)
+    int lblock;            // labels per block of the work order (1..L)
     double sigma_c;
     // passed by value (kernel arguments): [0..L] first chunk of each label's
     // padded segment (chunk units), [L+1 .. 2L] the labels by decreasing
@@ -369,6 +370,12 @@ hipError_t launch_mlp_adam(const LaunchCtx &lc, const MlpAdamArgs &a);
 hipError_t launch_mlp_convert(const LaunchCtx &lc, const MlpAdamArgs &a);
 hipError_t launch_mlp_infer(const LaunchCtx &lc, const MlpInferArgs &a);
 hipError_t launch_mlp_bias_mean(const LaunchCtx &lc, const float *ell, int64_t n, int out, float *b3);
+// Exact fallback of the surrogate: pixels whose top-two outputs differ by less
+// than margin are listed (count zero before), and exact rows are put back.
+hipError_t launch_mlp_uncertain(const LaunchCtx &lc, const float *y, int64_t n, int L, float margin, int32_t *list,
+                                unsigned int *count);
+hipError_t launch_mlp_scatter_rows(const LaunchCtx &lc, const float *ex, const int32_t *list, int64_t m, int L,
+                                   float *out);
 hipError_t launch_mlp_features(const LaunchCtx &lc, const float *rgb, int H, int W, const float *alpha, int k,
                                const int32_t *pix, int64_t n, float *x);
 hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, unsigned int v);

@@ -272,25 +272,8 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(MlpWgradArgs a) {
 }
 
 // ---- Adam (or gradient output) over the flat parameter vector ----
-__global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p == 0 && (a.loss_out)) {
-        double s = 0.0;
-        for (int t = 0; t < a.ntiles; ++t) s += (double)a.lossp[t];
-        *a.loss_out = (float)(s / ((double)a.B * (double)a.out));
-    }
-    if (p >= a.P) return;
-    // which tensor p belongs to
-    float gsum = 0.0f;
-    int bias_unit = -1;
-    if (p >= a.off_b1 && p < a.off_W2) bias_unit = (int)(p - a.off_b1);
-    else if (p >= a.off_b2 && p < a.off_W3) bias_unit = kMlpHid + (int)(p - a.off_b2);
-    else if (p >= a.off_b3) bias_unit = 2 * kMlpHid + (int)(p - a.off_b3);
-    if (bias_unit >= 0) {
-        for (int t = 0; t < a.ntiles; ++t) gsum += a.bgrad[(int64_t)t * kMlpBiasStride + bias_unit];
-    } else {
-        for (int c = 0; c < a.kc; ++c) gsum += a.gpart[(int64_t)c * a.P + p];
-    }
+// Adam update of parameter p with gradient g, and its BF16 working copies.
+__device__ void adam_update(const MlpAdamArgs &a, int64_t p, float gsum) {
     if (a.grad_out) {
         a.grad_out[p] = gsum;
         return;
@@ -302,7 +285,6 @@ __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a) {
     const float mhat = m / a.bc1, vhat = v / a.bc2;
     const float w = a.params[p] - a.lr * mhat / (sqrtf(vhat) + kAdamEps);
     a.params[p] = w;
-    // BF16 working copies
     const short wb = to_bf16(w);
     if (p < a.off_b1) {
         const int h = (int)(p / a.in), i = (int)(p % a.in);
@@ -316,6 +298,107 @@ __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a) {
         a.W3b[o * kMlpHid + h] = wb;
         a.W3Tb[h * kMlpOutPad + o] = wb;
     }
+}
+
+// Sum over the lanes of a wave in a fixed order (butterfly), every lane gets it.
+__device__ float wave_sum_f32(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// The first `wblocks` workgroups update the weights: thread p adds the kc
+// row-chunk partials of its gradient (coalesced over p).  The others take one
+// wave per bias unit (and one for the loss): each lane adds every 64th
+// per-tile partial, in a fixed order, then the wave adds its lanes.
+__global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a, int wblocks) {
+    if ((int)blockIdx.x < wblocks) {
+        const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+        if (p >= a.P) return;
+        const bool bias = (p >= a.off_b1 && p < a.off_W2) || (p >= a.off_b2 && p < a.off_W3) || p >= a.off_b3;
+        if (bias) return;
+        float gsum = 0.0f;
+        for (int c = 0; c < a.kc; ++c) gsum += a.gpart[(int64_t)c * a.P + p];
+        adam_update(a, p, gsum);
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int u = ((int)blockIdx.x - wblocks) * 4 + (threadIdx.x >> 6);  // bias unit, or the loss
+    const int nbias = 2 * kMlpHid + a.out;
+    if (u > nbias) return;
+    if (u == nbias) {
+        if (!a.loss_out) return;
+        float s = 0.0f;
+        for (int t = lane; t < a.ntiles; t += 64) s += a.lossp[t];
+        s = wave_sum_f32(s);
+        if (lane == 0) *a.loss_out = s / ((float)a.B * (float)a.out);
+        return;
+    }
+    float s = 0.0f;
+    for (int t = lane; t < a.ntiles; t += 64) s += a.bgrad[(int64_t)t * kMlpBiasStride + u];
+    s = wave_sum_f32(s);
+    if (lane != 0) return;
+    const int64_t p = u < kMlpHid ? a.off_b1 + u : u < 2 * kMlpHid ? a.off_b2 + (u - kMlpHid) : a.off_b3 + (u - 2 * kMlpHid);
+    adam_update(a, p, s);
+}
+
+// ---- exact fallback of the surrogate ----
+// Pixels whose two largest surrogate outputs differ by less than `margin`
+// nats are listed (list[*count ...]; *count is zero before): one thread per
+// pixel, a wave's flags compacted by ballot and one atomic per wave.  The
+// order of the list depends on the wave schedule; each listed pixel is
+// recomputed on its own, so the results do not.
+__global__ __launch_bounds__(256) void k_mlp_uncertain(const float *y, int64_t n, int L, float margin,
+                                                       int32_t *list, unsigned int *count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool flag = false;
+    if (i < n) {
+        const float *r = y + i * L;
+        float t1 = r[0], t2 = -INFINITY;
+        for (int l = 1; l < L; ++l) {
+            const float v = r[l];
+            if (v > t1) {
+                t2 = t1;
+                t1 = v;
+            } else if (v > t2) {
+                t2 = v;
+            }
+        }
+        flag = L > 1 && !(t1 - t2 >= margin);  // NaN outputs are listed too
+    }
+    const uint64_t b = __ballot(flag);
+    if (!b) return;
+    const int lane = threadIdx.x & 63;
+    unsigned int base = 0;
+    if (lane == __ffsll((unsigned long long)b) - 1) base = atomicAdd(count, (unsigned int)__popcll(b));
+    base = __shfl(base, __ffsll((unsigned long long)b) - 1);
+    if (flag) list[base + __popcll(b & ((1ull << lane) - 1ull))] = (int32_t)i;
+}
+
+// out[list[i]][l] = ex[i][l] for the m listed rows of L values.
+__global__ __launch_bounds__(256) void k_mlp_scatter_rows(const float *ex, const int32_t *list, int64_t m, int L,
+                                                          float *out) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= m * L) return;
+    const int64_t i = t / L;
+    const int l = (int)(t - i * L);
+    out[(int64_t)list[i] * L + l] = ex[t];
+}
+
+hipError_t launch_mlp_uncertain(const LaunchCtx &lc, const float *y, int64_t n, int L, float margin, int32_t *list,
+                                unsigned int *count) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_uncertain, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, lc.stream, y, n, L, margin,
+                       list, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_scatter_rows(const LaunchCtx &lc, const float *ex, const int32_t *list, int64_t m, int L,
+                                   float *out) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_scatter_rows, dim3((unsigned)((m * L + 255) / 256)), dim3(256), 0, lc.stream, ex, list,
+                       m, L, out);
+    return hipGetLastError();
 }
 
 // BF16 working copies of the master FP32 parameters (padding stays zero).
@@ -625,7 +708,9 @@ hipError_t launch_mlp_wgrad(const LaunchCtx &lc, const MlpWgradArgs &a) {
     return hipGetLastError();
 }
 hipError_t launch_mlp_adam(const LaunchCtx &lc, const MlpAdamArgs &a) {
-    hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, lc.stream, a);
+    const int wblocks = (int)((a.P + 255) / 256);
+    const int bblocks = (2 * kMlpHid + a.out + 1 + 3) / 4;  // one wave per bias unit and one for the loss
+    hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)(wblocks + bblocks)), dim3(256), 0, lc.stream, a, wblocks);
     return hipGetLastError();
 }
 hipError_t launch_mlp_convert(const LaunchCtx &lc, const MlpAdamArgs &a) {

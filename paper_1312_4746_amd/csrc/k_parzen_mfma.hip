@@ -49,8 +49,10 @@
 // the nearest sample distance).  After each chunk a lane sum above 2^64 moves
 // the reference of that pixel up by a whole power of two, the largest needed
 // by any of its 16 lanes (exact rescale); at the end of the item the 16 lane
-// sums are added.  An overflowed, non-finite or empty sum queues the (label,
-// tile) for the exact two-pass kernel.
+// sums are added.  A sum that overflows within a chunk stops the pass; the
+// item is computed again with the overflowed pixels' references raised (up to
+// kRetries times).  A sum that still overflows, or is non-finite or empty,
+// queues the (label, tile) for the exact two-pass kernel.
 #include <type_traits>
 
 #include "cs_internal.h"
@@ -71,6 +73,8 @@ constexpr float kFarQ = 0x1p100f;      // location feature of padding samples: Q
 // (64 x 16 B), colours (64 x float4).
 constexpr int kRecChunkF = kChunkS * 12;
 constexpr int kTailGroups = 64;  // groups at the end of each work queue taken label by label
+constexpr int kRetries = 8;      // passes again over an item whose sums overflowed
+constexpr float kRaise = 170.0f; // reference raise per retry (log2 units)
 
 // BF16 bit pattern of a float that BF16 holds exactly.
 __device__ __forceinline__ short bf16_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
@@ -320,6 +324,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
     // rather than in registers, which the kernel has none left of)
     __shared__ __align__(16) s16x8 s_abf[4][RB][64];
     __shared__ int s_item, s_queue;
+    // overflow retry: any wave of the workgroup overflowed in the last pass,
+    // and per lane the pixels (bit 4 rb + r) whose sums overflowed
+    __shared__ int s_ovf;
+    __shared__ uint8_t s_ovp[4][64];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, jl = lane & 15;
@@ -339,6 +347,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
 
     // queue state (thread 0): current queue and how many have been emptied
     int queue = blockIdx.x % kParzenQueues, emptied = 0;
+    if (tid == 0) s_ovf = 0;
     for (;;) {
         __syncthreads();  // the previous item's LDS reads are done
         if (tid == 0) {
@@ -360,17 +369,28 @@ void k_parzen_mfma(ParzenFastArgs a) {
         __syncthreads();
         const int item = s_item;
         if (item < 0) break;
-        // item -> (group, label): the labels of a group consecutive, in order
-        // of decreasing sample count, except over the queue's last
-        // kTailGroups groups, which go label by label so that the queue ends
-        // with the shortest items (their operands stay in L2 meanwhile)
+        // item -> (group, label).  The labels (in order of decreasing sample
+        // count) are cut into blocks of a.lblock; block by block, the groups
+        // of the queue go in order with the labels of the block consecutive.
+        // With one block (the label streams fit the L2 together) a group's
+        // items run at about the same time, its pixel operands fetched once;
+        // with several, the workgroups of an XCD share the streams of a few
+        // labels at a time, which then stay in its L2.  The queue's last
+        // kTailGroups groups go label by label so that the queue ends with the
+        // shortest items (their operands stay in L2 meanwhile).
         const int qg = s_queue < a.ngroups ? (a.ngroups - 1 - s_queue) / kParzenQueues + 1 : 0;
         const int tg = qg < kTailGroups ? qg : kTailGroups;
-        const int head_items = (qg - tg) * a.L;
+        const int hg = qg - tg;
+        const int head_items = hg * a.L;
         int gi, lrank;
         if (item < head_items) {
-            gi = item / a.L;
-            lrank = item - gi * a.L;
+            const int nblk = (a.L + a.lblock - 1) / a.lblock;
+            int b = item / (hg * a.lblock);
+            if (b > nblk - 1) b = nblk - 1;
+            const int bsz = b < nblk - 1 ? a.lblock : a.L - a.lblock * (nblk - 1);
+            const int rr = item - hg * a.lblock * b;
+            gi = rr / bsz;
+            lrank = a.lblock * b + (rr - gi * bsz);
         } else {
             const int j = item - head_items;
             lrank = j / tg;
@@ -460,6 +480,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
         }
         bool item_bad = __ballot(weak) != 0ull;
         if (item_bad) active = false;
+        bool ovf_wave = false;  // this wave's sums overflowed in the last pass
 
         float S[RB][4];
 #pragma unroll
@@ -526,8 +547,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
             }
             // A lane sum above 2^64 moves that pixel's reference up by a whole
             // power of two (exact rescale).  Entering a chunk the sums are at
-            // most 2^64, so an overflowed sum means terms beyond 2^128 that make
-            // the earlier part negligible; such a tile goes to the exact kernel.
+            // most 2^64, so an overflowed sum means a term beyond 2^122 (64
+            // terms per lane and chunk): the pass stops, and the item is
+            // computed again with the reference of each such pixel raised (see
+            // the retry below).
             bool big = false;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -539,6 +562,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 // pixel keeps one reference
                 ++n_rescale;
                 bool over = false;
+                uint32_t ob = 0;  // pixels (bit 4 rb + r) of this lane group that overflowed
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -547,25 +571,61 @@ void k_parzen_mfma(ParzenFastArgs a) {
                         int e = 0;
                         if (!(s <= 0x1p64f)) {
                             if (s <= 3.0e38f) e = (int)((__float_as_uint(s) >> 23) & 0xFFu) - 127;
-                            else over = true;
+                            else e = 255;  // overflowed (or not a number)
                         }
 #pragma unroll
                         for (int off = 1; off < 16; off <<= 1) e = max(e, __shfl_xor(e, off));
-                        if (e > 0) {
+                        if (e == 255) {
+                            over = true;
+                            ob |= 1u << (4 * rb + r);
+                        } else if (e > 0) {
                             S[rb][r] = ldexpf(s, -e);
                             nR[rb][r] -= (float)e;
                         }
                     }
                 if (__ballot(over)) {
-                    item_bad = true;
+                    s_ovp[wave][lane] = (uint8_t)ob;
+                    if (lane == 0) s_ovf = 1;
+                    ovf_wave = true;
                     active = false;
                     ++n_overflow;
                 }
             }
         };
-        for (int c = c0; c < c1; c += 2) {
-            process(c, s_feat0, s_rec0, s_feat1, s_rec1);
-            if (c + 1 < c1) process(c + 1, s_feat1, s_rec1, s_feat0, s_rec0);
+        // Overflow retry.  A pixel whose sum overflowed has a term at least
+        // 2^122 times its reference, so raising the reference by kRaise = 170
+        // (log2 units) keeps every term of that size below 2^48 and loses only
+        // terms below 2^-122 of it; the waves that overflowed compute the item
+        // again (the others keep their sums and only help stream the chunks),
+        // up to kRetries times before the item goes to the exact kernel.
+        for (int attempt = 0;; ++attempt) {
+            for (int c = c0; c < c1; c += 2) {
+                process(c, s_feat0, s_rec0, s_feat1, s_rec1);
+                if (c + 1 < c1) process(c + 1, s_feat1, s_rec1, s_feat0, s_rec0);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();  // every wave is past the pass; both buffer pairs are free
+            const int again = s_ovf;
+            __syncthreads();  // every wave has read the flag
+            if (!again) break;
+            if (tid == 0) s_ovf = 0;
+            if (attempt == kRetries) {
+                if (ovf_wave) item_bad = true;
+                break;
+            }
+            active = ovf_wave;
+            if (ovf_wave) {
+                const uint32_t ob = s_ovp[wave][lane];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        S[rb][r] = 0.0f;
+                        if (ob & (1u << (4 * rb + r))) nR[rb][r] -= kRaise;
+                    }
+            }
+            ovf_wave = false;
+            issue(c0, s_feat0, s_rec0);
         }
         if (!wave_valid) continue;
 
