@@ -328,6 +328,88 @@ def surrogate_line(args) -> dict:
     return out
 
 
+def mean_dice(labels, truth, L: int) -> float:
+    """Mean over the labels of the Dice score 2 |A n B| / (|A| + |B|) (evaluation)."""
+    import numpy as np
+    d = []
+    for i in range(L):
+        a, b = labels == i, truth == i
+        den = int(a.sum() + b.sum())
+        d.append(2.0 * int((a & b).sum()) / den if den else 1.0)
+    return float(np.mean(d))
+
+
+def segment_line(args, config: int = 1) -> dict:
+    """Segmentation by convex relaxation (Sec. 4) on the exact data term of
+    workload `config`: the primal-dual iteration's time per iteration against
+    the HBM roofline (algorithmic bytes per pixel and label: read u_bar, xi_x,
+    xi_y, u, f; write xi_x, xi_y, u, u_bar: 36 B in FP32), the energies and the
+    relaxation gap, Dice against the synthetic regions, and the FP64 oracle's
+    iteration on the host."""
+    import numpy as np
+    import torch
+
+    from paper_1312_4746_amd import Context, LoglikParams, SegmentParams
+    from workloads import make_config
+
+    w = make_config(config)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rgb = dev(w.rgb)
+    prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
+                       rho_floor_px=w.rho_floor_px)
+    ctx = Context(0)
+    _, masks, _ = ctx.cosupport_median(rgb, w.p, w.mask_sigma, dev(w.omega), w.tau_frac)
+    ll = ctx.label_loglik(rgb, masks, w.k, dev(w.sample_pix), dev(w.sample_label), w.L, prm)
+    sp = SegmentParams(lam=args.seg_lambda, nu=0.0, iterations=args.seg_iters, precision="fp32")
+    ctx.segment(rgb, ll, sp)  # warm-up
+    torch.cuda.synchronize()
+    ctx.profile_only("pd_iter")
+    ctx.profile_sample(4)
+    ctx.profile_enable(True)
+    t0 = time.perf_counter()
+    lab, _, st = ctx.segment(rgb, ll, sp)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    it_ms, it_n = ctx.profile_read("pd_iter")
+    ctx.profile_enable(False)
+    ctx.profile_sample(1)
+    ctx.profile_only(None)
+    avg_it = it_ms / 1e3 / max(it_n, 1)
+    bytes_it = w.N * w.L * 36 + w.N * 4
+    lab_np = lab.cpu().numpy().reshape(w.H, w.W)
+    ll_np = ll.cpu().numpy()
+    dice0 = mean_dice(np.argmax(ll_np, 1).reshape(w.H, w.W), w.region, w.L)
+    dice1 = mean_dice(lab_np, w.region, w.L)
+    ctx.close()
+    cpu = None
+    if not args.no_cpu:
+        # the oracle's iteration (numpy FP64) on the same data term, a few iterations timed
+        from oracle import segment as osg
+        f = osg.data_term(ll_np.astype(np.float64), w.H, w.W)
+        g, _ = osg.edge_weight(w.rgb)
+        n_cpu = 10
+        t0 = time.perf_counter()
+        osg.solve(f, g, lam=args.seg_lambda, iterations=n_cpu)
+        t_cpu = (time.perf_counter() - t0) / n_cpu
+        cpu = {"value": 1.0 / t_cpu, "unit": "iterations/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 numpy oracle, {n_cpu} iterations on {w.H}x{w.W}x{w.L} ({t_cpu * 1e3:.1f} ms each)"}
+    return {
+        "metric": "primal-dual iterations/s",
+        "value": 1.0 / avg_it,
+        "unit": "iterations/s",
+        "workload": w.name, "H": w.H, "W": w.W, "labels": w.L,
+        "iterations": args.seg_iters, "lambda": args.seg_lambda, "dtype": "f32",
+        "ms_per_iteration": avg_it * 1e3, "solve_ms": t_solve * 1e3,
+        "roofline": {"bound": "hbm", "achieved": bytes_it / avg_it / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": bytes_it / avg_it / PEAK_HBM, "traffic": None, "kernel": "k_pd_iter",
+                     "bytes_per_iteration": bytes_it},
+        "energies": st,
+        "relaxation_gap": (st["binary"] - st["dual"]) / abs(st["dual"]),
+        "dice_vs_regions": {"pointwise_argmax": dice0, "segmentation": dice1},
+        "cpu_baseline": cpu,
+    }
+
+
 def counter_profile(kernel: str, workload: str, digest_of=None):
     """The committed counter summary of `kernel` at `workload`
     (profiles/<kernel>_<workload>_counters.json), or None when it is absent or
@@ -354,6 +436,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true",
                     help="leave out the surrogate leg (2048x2048) of the headline line")
+    ap.add_argument("--no-segment", action="store_true",
+                    help="leave out the segmentation leg (primal-dual iteration) of the headline line")
+    ap.add_argument("--segment", action="store_true",
+                    help="only the segmentation leg (primal-dual iteration) on --config's data term")
+    ap.add_argument("--seg-iters", type=int, default=300)
+    ap.add_argument("--seg-lambda", type=float, default=1.0)
     ap.add_argument("--soft", action="store_true",
                     help="the joint form with smooth co-supports (sigma 0.01) of the stored "
                          "analysed vectors")
@@ -383,6 +471,9 @@ def main():
         return
     if args.config == 4:
         print(json.dumps(surrogate_line(args)))
+        return
+    if args.segment:
+        print(json.dumps(segment_line(args, args.config)))
         return
 
     import numpy as np
@@ -520,6 +611,11 @@ def main():
         sur = {k_: full[k_] for k_ in ("value", "unit", "ms_per_step")}
         sur.update({"workload": full["config"]["workload"], **full["surrogate"]})
 
+    seg = None
+    if not args.no_segment and not (args.joint or args.soft):
+        print("[bench] segmentation leg (BSDS-sized data term)", file=sys.stderr, flush=True)
+        seg = segment_line(args, 1)
+
     out = {
         "metric": "data-term pixel x sample pairs/s",
         "value": value,
@@ -542,6 +638,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "surrogate": sur,
+        "segmentation": seg,
         "extra": extra,
     }
     print(json.dumps(out))

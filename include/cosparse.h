@@ -49,6 +49,7 @@ extern "C" {
 
 #define CS_FP32 0 /* O s on FP32 MFMA, FP32 accumulation                        */
 #define CS_BF16 1 /* O s on BF16 MFMA (both operands rounded), FP32 accumulation */
+#define CS_FP64 2 /* (segmentation only) the primal-dual iteration in FP64        */
 
 typedef struct cs_ctx cs_ctx;
 
@@ -290,6 +291,67 @@ int cs_profile_only(cs_ctx *ctx, const char *name);
  * Averages over the recorded launches then cost the stream fewer bubbles. */
 int cs_profile_sample(cs_ctx *ctx, int period);
 int cs_profile_read(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
+
+/* ---- Segmentation by convex relaxation (Sec. 3.2 energy, Sec. 4) ----
+ * The data term f_i = -l_i of every pixel and label, the boundary length of
+ * each region weighted by the edge metric g (Sec. 3.2 prior) and, for
+ * unsupervised use, a cost nu per label present (eq:mdl) make the energy of
+ * eq:energy1.  Its convex relaxation (Sec. 4.1: indicator functions u_i
+ * relaxed to [0, 1] with sum_i u_i = 1, the boundary length as the weighted
+ * total variation sup over |xi_i(x)| <= lambda g(x) / 2 of -sum u_i div xi_i,
+ * label variables m_i >= u_i(x) with multipliers mu <= 0) is solved by the
+ * primal-dual iteration of Sec. 4.2, and the segmentation is
+ * l(x) = argmax_i u_i(x) (ties to the lowest label).
+ * Readings: forward differences with zero gradient across the last column
+ * and row, the divergence as minus their adjoint, isotropic norms; |grad I|
+ * the Euclidean norm over the three colour channels; steps by diagonal
+ * preconditioning with the interior column sums (sigma_xi = sigma_mu = 1/2,
+ * tau_u = 1/4, or 1/5 with label variables, tau_m = 1/N); start u = 1/L,
+ * xi = 0, mu = 0, m = 1; nu = 0 leaves the label variables out. */
+
+/* Edge metric of Sec. 3.2: g(x) = exp(-|grad I(x)| / gamma) / (2 gamma), with
+ * gamma <= 0 selecting the mean of |grad I| over the image.
+ *   rgb        device, 3*H*W float32
+ *   g          device out, H*W float32
+ *   gamma_out  host out or NULL: the gamma used
+ * Synchronises (reads gamma back to validate it).
+ * Errors: CS_ERR_ARG for null pointers, a non-finite gamma, or gamma <= 0 on
+ * an image without gradient. */
+int cs_edge_weight(cs_ctx *ctx, const float *rgb, int H, int W, double gamma, float *g, double *gamma_out);
+
+typedef struct {
+    double lambda;   /* weight of the boundary length, >= 0                        */
+    double gamma;    /* edge metric scale; <= 0: the mean |grad I| of the image    */
+    double nu;       /* cost per label present (eq:mdl), >= 0; 0 = supervised     */
+    int iterations;  /* primal-dual iterations, 0..1000000                        */
+    int precision;   /* CS_FP32 or CS_FP64: arithmetic of the iteration          */
+} cs_segment_params;
+
+typedef struct {
+    double primal;   /* relaxed energy of u (the label cost as nu max_x u_i)       */
+    double binary;   /* energy (eq:energy1) of the segmentation l = argmax u       */
+    double dual;     /* dual energy at (xi, mu): a lower bound of the relaxed      */
+                     /* optimum, so binary - dual bounds l's distance from it      */
+    double gamma;    /* gamma used by the edge metric                              */
+    int labels_used; /* labels present in l                                        */
+} cs_segment_stats;
+
+/* Segmentation of the image from its per-pixel, per-label log-likelihoods.
+ *   rgb        device, 3*H*W float32 (for the edge metric)
+ *   loglik     device, H*W*L float32, pixel-major (as cs_label_loglik writes
+ *              it); the data term is f_i = -loglik_i
+ *   labels     device out, H*W int32
+ *   u          device out, H*W*L float32 pixel-major (the relaxed solution),
+ *              or NULL
+ *   stats      host out or NULL (energies; non-NULL adds a synchronisation)
+ * The context's workspace holds the iteration's planes (about 9 L N values
+ * of the working precision, 11 L N with a label cost).  Synchronises once to
+ * read gamma back.
+ * Errors: CS_ERR_ARG for null pointers, sizes, L outside 1..64, lambda or nu
+ * negative or not finite, iterations outside 0..1000000, an unknown
+ * precision, or an undefined edge metric (see cs_edge_weight). */
+int cs_segment(cs_ctx *ctx, const float *rgb, int H, int W, const float *loglik, int L,
+               const cs_segment_params *prm, int32_t *labels, float *u, cs_segment_stats *stats);
 
 /* ---- Learned surrogate of the data term ----
  * A two-hidden-layer perceptron maps a pixel's colour, normalised position

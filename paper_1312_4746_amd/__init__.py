@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     CosparseError,
     LoglikParams,
     Mlp,
+    SegmentParams,
     lib,
     library_path,
     mlp_features,

@@ -19,8 +19,9 @@ CS_ERR_NOMEM = 4
 CS_ERR_NONFINITE = 5
 CS_FP32 = 0
 CS_BF16 = 1
+CS_FP64 = 2
 
-_PREC = {"fp32": CS_FP32, "bf16": CS_BF16, CS_FP32: CS_FP32, CS_BF16: CS_BF16}
+_PREC = {"fp32": CS_FP32, "bf16": CS_BF16, "fp64": CS_FP64, CS_FP32: CS_FP32, CS_BF16: CS_BF16, CS_FP64: CS_FP64}
 
 # Every entry point the header declares, with (restype, argtypes).
 _P, _I, _I64, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
@@ -35,6 +36,16 @@ class _LoglikParamsC(ctypes.Structure):
 class _LoglikStatsC(ctypes.Structure):
     _fields_ = [("rescaled_chunks", ctypes.c_int64), ("overflow_tiles", ctypes.c_int64),
                 ("exact_tiles", ctypes.c_int64)]
+
+
+class _SegmentParamsC(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
+                ("iterations", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class _SegmentStatsC(ctypes.Structure):
+    _fields_ = [("primal", ctypes.c_double), ("binary", ctypes.c_double), ("dual", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("labels_used", ctypes.c_int)]
 
 
 class _CosupportStatsC(ctypes.Structure):
@@ -65,6 +76,9 @@ SIGNATURES = {
     "cs_profile_only": (_I, [_P, ctypes.c_char_p]),
     "cs_profile_sample": (_I, [_P, ctypes.c_int]),
     "cs_profile_read": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    "cs_edge_weight": (_I, [_P, _P, _I, _I, _D, _P, ctypes.POINTER(_D)]),
+    "cs_segment": (_I, [_P, _P, _I, _I, _P, _I, ctypes.POINTER(_SegmentParamsC), _P, _P,
+                        ctypes.POINTER(_SegmentStatsC)]),
     "cs_mlp_param_count": (_I64, [_I, _I, _I]),
     "cs_mlp_init": (_I, [_P, ctypes.POINTER(_P), _I, _I, _I, _P]),
     "cs_mlp_free": (_I, [_P]),
@@ -158,6 +172,19 @@ class LoglikParams:
     def c(self) -> _LoglikParamsC:
         return _LoglikParamsC(self.alpha_rho, self.sigma_c, self.beta_scale, self.rho_floor_px,
                               int(bool(self.normalise)))
+
+
+@dataclasses.dataclass
+class SegmentParams:
+    lam: float = 1.0
+    gamma: float = 0.0
+    nu: float = 0.0
+    iterations: int = 300
+    precision: str = "fp32"
+
+    def c(self) -> _SegmentParamsC:
+        return _SegmentParamsC(float(self.lam), float(self.gamma), float(self.nu), int(self.iterations),
+                               _PREC[self.precision])
 
 
 class Context:
@@ -390,6 +417,50 @@ class Context:
                                                0 if pix_subset is None else pix_subset.numel(),
                                                _ptr(out) if out.numel() else None))
         return out
+
+    def edge_weight(self, rgb: torch.Tensor, gamma: float = 0.0, out: Optional[torch.Tensor] = None):
+        """cs_edge_weight: g (H, W) float32 on the device and the gamma used."""
+        H, W = _image_hw(rgb)
+        _numel(out, H * W, "g", "H*W")
+        self._dev(rgb, torch.float32, "rgb")
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=rgb.device)
+        self._dev(out, torch.float32, "g")
+        gam = ctypes.c_double()
+        self._sync_stream()
+        self._check(lib().cs_edge_weight(self._h, _ptr(rgb), H, W, float(gamma), _ptr(out), ctypes.byref(gam)))
+        return out, gam.value
+
+    def segment(self, rgb: torch.Tensor, loglik: torch.Tensor, params: "SegmentParams",
+                labels: Optional[torch.Tensor] = None, u: Optional[torch.Tensor] = None, want_u: bool = False,
+                stats: bool = True):
+        """cs_segment: labels (H*W int32), u (H*W, L) float32 or None, and the
+        energies (dict, or None without stats)."""
+        H, W = _image_hw(rgb)
+        if loglik.dim() != 2 or loglik.shape[0] != H * W:
+            raise ValueError(f"loglik must be (H*W, L), got {tuple(loglik.shape)}")
+        L = int(loglik.shape[1])
+        _numel(labels, H * W, "labels", "H*W")
+        _numel(u, H * W * L, "u", "H*W*L")
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(loglik, torch.float32, "loglik")
+        if labels is None:
+            labels = torch.empty(H * W, dtype=torch.int32, device=rgb.device)
+        self._dev(labels, torch.int32, "labels")
+        if u is None and want_u:
+            u = torch.empty((H * W, L), dtype=torch.float32, device=rgb.device)
+        if u is not None:
+            self._dev(u, torch.float32, "u")
+        prm = params.c()
+        st = _SegmentStatsC()
+        self._sync_stream()
+        self._check(lib().cs_segment(self._h, _ptr(rgb), H, W, _ptr(loglik), L, ctypes.byref(prm), _ptr(labels),
+                                     _ptr(u), ctypes.byref(st) if stats else None))
+        info = None
+        if stats:
+            info = {"primal": st.primal, "binary": st.binary, "dual": st.dual, "gamma": st.gamma,
+                    "labels_used": int(st.labels_used)}
+        return labels, u, info
 
     def set_check_finite(self, on: bool = True):
         """Optional finite check of rgb and omega before each call (synchronises)."""

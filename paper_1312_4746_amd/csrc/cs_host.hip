@@ -1530,4 +1530,156 @@ int cs_mlp_infer_fallback(cs_ctx *ctx, const cs_mlp *net, const float *rgb, int 
     return CS_OK;
 }
 
+// ---- segmentation by convex relaxation ----
+}  // extern "C"
+
+namespace {
+
+int check_segment_image(cs_ctx *ctx, const float *rgb, int H, int W) {
+    if (!rgb) return fail(ctx, CS_ERR_ARG, "rgb must be non-null");
+    if (H < 1 || W < 1 || (int64_t)H * W > ((int64_t)1 << 31) - 1)
+        return fail(ctx, CS_ERR_ARG, "bad image size %dx%d", W, H);
+    return CS_OK;
+}
+
+// Edge metric into g (working precision) and/or g32; returns the gamma used
+// (read back on the host: a mean of zero, an image without gradient, leaves
+// the metric undefined and is an argument error).
+int edge_weight_stage(cs_ctx *ctx, const float *rgb, int H, int W, double gamma, int precision, void *g,
+                      float *g32, double *mag, double *part, double *gamma_dev, double *gamma_used) {
+    const LaunchCtx lc = lc_of(ctx);
+    {
+        Timed t(ctx, "edge_weight");
+        HIP_TRY(launch_edge_weight(lc, rgb, H, W, gamma, mag, part, precision, g, g32, gamma_dev));
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->pinned, gamma_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    std::memcpy(gamma_used, ctx->pinned, sizeof(double));
+    if (!(*gamma_used > 0.0) || !std::isfinite(*gamma_used))
+        return fail(ctx, CS_ERR_ARG, "the edge metric needs gamma > 0 (the image has no gradient; pass gamma)");
+    return CS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cs_edge_weight(cs_ctx *ctx, const float *rgb, int H, int W, double gamma, float *g, double *gamma_out) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_segment_image(ctx, rgb, H, W);
+    if (rc) return rc;
+    if (!g) return fail(ctx, CS_ERR_ARG, "g must be non-null");
+    if (std::isnan(gamma) || std::isinf(gamma)) return fail(ctx, CS_ERR_ARG, "gamma must be finite");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, nullptr, 0))) return rc;
+    const int64_t N = (int64_t)H * W;
+    Carve cv;
+    const size_t o_mag = cv.take(sizeof(double) * (size_t)N);
+    const size_t o_part = cv.take(sizeof(double) * (size_t)((N + 255) / 256));
+    const size_t o_gam = cv.take(sizeof(double));
+    if ((rc = ensure_ws(ctx, cv.off))) return rc;
+    double used = 0.0;
+    rc = edge_weight_stage(ctx, rgb, H, W, gamma, CS_FP32, nullptr, g, (double *)(ctx->ws + o_mag),
+                           (double *)(ctx->ws + o_part), (double *)(ctx->ws + o_gam), &used);
+    if (rc) return rc;
+    if (gamma_out) *gamma_out = used;
+    return CS_OK;
+}
+
+int cs_segment(cs_ctx *ctx, const float *rgb, int H, int W, const float *loglik, int L,
+               const cs_segment_params *prm, int32_t *labels, float *u, cs_segment_stats *stats) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_segment_image(ctx, rgb, H, W);
+    if (rc) return rc;
+    if (!loglik || !prm || !labels) return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    if (L < 1 || L > kMaxLabels) return fail(ctx, CS_ERR_ARG, "L must be in 1..%d (got %d)", kMaxLabels, L);
+    if (!(prm->lambda >= 0.0) || !std::isfinite(prm->lambda)) return fail(ctx, CS_ERR_ARG, "lambda must be finite and >= 0");
+    if (!(prm->nu >= 0.0) || !std::isfinite(prm->nu)) return fail(ctx, CS_ERR_ARG, "nu must be finite and >= 0");
+    if (std::isnan(prm->gamma) || std::isinf(prm->gamma)) return fail(ctx, CS_ERR_ARG, "gamma must be finite");
+    if (prm->iterations < 0 || prm->iterations > 1000000)
+        return fail(ctx, CS_ERR_ARG, "iterations must be in 0..1000000");
+    if (prm->precision != CS_FP32 && prm->precision != CS_FP64)
+        return fail(ctx, CS_ERR_ARG, "precision must be CS_FP32 or CS_FP64");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, loglik, (int64_t)H * W * L))) return rc;
+    const int64_t N = (int64_t)H * W;
+    const int64_t nb = (N + 255) / 256;
+    const bool mdl = prm->nu > 0.0;
+    const size_t es = prm->precision == CS_FP64 ? sizeof(double) : sizeof(float);
+    const size_t plane = es * (size_t)N * L;
+    Carve cv;
+    const size_t o_mag = cv.take(sizeof(double) * (size_t)N);
+    const size_t o_part = cv.take(sizeof(double) * (size_t)nb * (3 + L));
+    const size_t o_small = cv.take(sizeof(double) * 8);  // gamma, energies, labels present
+    const size_t o_g = cv.take(es * (size_t)N);
+    const size_t o_f = cv.take(plane);
+    size_t o_state[2][5];
+    for (int b = 0; b < 2; ++b)
+        for (int v = 0; v < 5; ++v) o_state[b][v] = (v < 4 || mdl) ? cv.take(plane) : 0;
+    const size_t o_m = cv.take(sizeof(double) * (size_t)(prm->iterations + 1) * L);
+    const size_t o_ms = cv.take(sizeof(double) * (size_t)(prm->iterations + 1) * L);
+    if ((rc = ensure_ws(ctx, cv.off))) return rc;
+    char *ws = ctx->ws;
+    double *small = (double *)(ws + o_small);
+    unsigned long long *used = (unsigned long long *)(small + 4);
+    const LaunchCtx lc = lc_of(ctx);
+    HIP_TRY(launch_fill_u32(lc, (unsigned int *)used, 2, 0u));
+    double gamma = 0.0;
+    rc = edge_weight_stage(ctx, rgb, H, W, prm->gamma, prm->precision, ws + o_g, nullptr, (double *)(ws + o_mag),
+                           (double *)(ws + o_part), small, &gamma);
+    if (rc) return rc;
+    PdArgs a{};
+    a.H = H;
+    a.W = W;
+    a.L = L;
+    a.iters = prm->iterations;
+    a.mdl = mdl ? 1 : 0;
+    a.N = N;
+    a.lambda = prm->lambda;
+    a.nu = prm->nu;
+    // diagonal preconditioning (alpha = 1) with the interior column sums
+    a.sigma_xi = 0.5;
+    a.sigma_mu = 0.5;
+    a.tau_u = mdl ? 0.2 : 0.25;
+    a.tau_m = 1.0 / (double)N;
+    a.g = ws + o_g;
+    a.f = ws + o_f;
+    for (int b = 0; b < 2; ++b) {
+        a.u[b] = ws + o_state[b][0];
+        a.ub[b] = ws + o_state[b][1];
+        a.px[b] = ws + o_state[b][2];
+        a.py[b] = ws + o_state[b][3];
+        a.mu[b] = mdl ? ws + o_state[b][4] : nullptr;
+    }
+    a.mval = (double *)(ws + o_m);
+    a.msum = (double *)(ws + o_ms);
+    {
+        Timed t(ctx, "pd_init");
+        HIP_TRY(launch_pd_init(lc, a, prm->precision, loglik));
+    }
+    for (int it = 0; it < prm->iterations; ++it) {
+        Timed t(ctx, "pd_iter");
+        HIP_TRY(launch_pd_iter(lc, a, prm->precision, it));
+    }
+    {
+        Timed t(ctx, "pd_finish");
+        HIP_TRY(launch_pd_finish(lc, a, prm->precision, labels, u, used, (double *)(ws + o_part),
+                                 stats ? small + 1 : nullptr));
+    }
+    if (stats) {
+        HIP_TRY(hipMemcpyAsync(ctx->pinned, small, sizeof(double) * 5, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        double e[4];
+        unsigned long long bits;
+        std::memcpy(e, ctx->pinned, sizeof(double) * 4);
+        std::memcpy(&bits, ctx->pinned + 4 * sizeof(double), sizeof bits);
+        stats->gamma = gamma;
+        stats->labels_used = __builtin_popcountll(bits);
+        stats->primal = e[1];
+        stats->binary = e[2] + prm->nu * (double)stats->labels_used;
+        stats->dual = e[3];
+    }
+    return CS_OK;
+}
+
 }  // extern "C"

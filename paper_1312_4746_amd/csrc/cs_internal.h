@@ -321,6 +321,34 @@ hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a);
 // MFMA pixel operands of the full-image path (ntiles_pad tiles).
 hipError_t launch_normalise(const LaunchCtx &lc, float *loglik, int64_t npix, int L);
 
+// ---- segmentation by convex relaxation (k_segment.hip) ----
+// State of the primal-dual iteration: label-major planes of N values in the
+// working precision (float or double), ping-pong pairs for the iterated fields.
+struct PdArgs {
+    int H, W, L, iters, mdl;
+    int64_t N;
+    double lambda, nu, sigma_xi, sigma_mu, tau_u, tau_m;
+    const void *g;           // edge metric, N values
+    void *f;                 // data term f_i = -l_i, L planes
+    void *u[2], *ub[2], *px[2], *py[2], *mu[2];
+    double *mval;            // (iters + 1) x L: m^t
+    double *msum;            // (iters + 1) x L: sum_x mu^t (zero before)
+};
+// |grad I| into mag (N doubles), per-workgroup partial sums into part
+// (ceil(N / 256) doubles), then g in the working precision (g, N values) and/or
+// FP32 (g32), and the gamma used (gamma_out, device, nullable).
+hipError_t launch_edge_weight(const LaunchCtx &lc, const float *rgb, int H, int W, double gamma, double *mag,
+                              double *part, int precision, void *g, float *g32, double *gamma_out);
+// Start state (and f = -loglik as planes), iteration t (reads buffer t & 1,
+// writes the other), then the labels (and u pixel-major into u_out when
+// non-null), the labels present (used, zero before) and, with energies
+// non-null, {primal, binary without label cost, dual} (part: ceil(N / 256) x
+// (3 + L) doubles of scratch).
+hipError_t launch_pd_init(const LaunchCtx &lc, const PdArgs &a, int precision, const float *loglik);
+hipError_t launch_pd_iter(const LaunchCtx &lc, const PdArgs &a, int precision, int t);
+hipError_t launch_pd_finish(const LaunchCtx &lc, const PdArgs &a, int precision, int32_t *labels, float *u_out,
+                            unsigned long long *used, double *part, double *energies);
+
 // ---- learned surrogate (k_mlp.hip) ----
 constexpr int kMlpHid = 128;                          // hidden units per layer
 constexpr int kMlpMaxIn = 128;                        // input features (padded to 16)
