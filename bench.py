@@ -410,6 +410,69 @@ def segment_line(args, config: int = 1) -> dict:
     }
 
 
+def partition_scores(labels, truth) -> dict:
+    """Rand index and variation of information (bits) between two labellings
+    (evaluation of a segmentation against the synthetic regions)."""
+    import numpy as np
+    a = np.asarray(labels).ravel().astype(np.int64)
+    b = np.asarray(truth).ravel().astype(np.int64)
+    n = a.size
+    ka, kb = int(a.max()) + 1, int(b.max()) + 1
+    cont = np.bincount(a * kb + b, minlength=ka * kb).reshape(ka, kb).astype(np.float64)
+    ra, rb = cont.sum(1), cont.sum(0)
+    c2 = lambda v: (v * (v - 1) / 2.0).sum()  # noqa: E731
+    disagree = c2(ra) + c2(rb) - 2.0 * c2(cont)
+    ri = 1.0 - disagree / (n * (n - 1) / 2.0)
+    p = cont / n
+    nz = p > 0
+    h = lambda q: -(q[q > 0] * np.log2(q[q > 0])).sum()  # noqa: E731
+    voi = 2.0 * (-(p[nz] * np.log2(p[nz])).sum()) - h(ra / n) - h(rb / n)
+    return {"rand_index": float(ri), "voi_bits": float(voi), "segments": int((ra > 0).sum())}
+
+
+def unsup_line(args, config: int = 1) -> dict:
+    """Unsupervised segmentation (Sec. 3.1, Sec. 3.2 eq:mdl, Sec. 4) on
+    workload `config`: co-supports, k-means on colours and k-medians on
+    co-supports into 4 x 4 product classes (the paper's 16 initial regions),
+    their likelihoods, then the convex relaxation with the label cost
+    (lambda = 6, nu = 1100 as in the paper's BSDS runs); time per image, the
+    labels kept, and the Rand index / variation of information against the
+    synthetic regions."""
+    import numpy as np
+    import torch
+
+    from paper_1312_4746_amd import Context, SegmentParams, UnsupParams
+    from workloads import make_config, unsup_init
+
+    w = make_config(config)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rgb, om = dev(w.rgb), dev(w.omega)
+    ctx = Context(0)
+    ic, it = unsup_init(w.N, 4, 4, w.seed + 200)
+    up = UnsupParams(colour_classes=4, texture_classes=4, iterations=10, sigma_c=w.sigma_c, beta=2.0)
+    sp = SegmentParams(lam=6.0, nu=1100.0, iterations=args.seg_iters, precision="fp32")
+
+    def run():
+        _, m, _ = ctx.cosupport_median(rgb, w.p, w.mask_sigma, om, w.tau_frac)
+        ll, _ = ctx.unsupervised_loglik(rgb, m, w.k, ic, it, up)
+        return ctx.segment(rgb, ll, sp)
+
+    run()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lab, _, st = run()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    sc = partition_scores(lab.cpu().numpy(), w.region)
+    ctx.close()
+    return {"metric": "unsupervised segmentations/s", "value": 1.0 / t, "unit": "images/s", "workload": w.name,
+            "ms_per_image": t * 1e3, "classes": 16, "lambda": 6.0, "nu": 1100.0, "iterations": args.seg_iters,
+            "labels_used": st["labels_used"], "relaxation_gap": (st["binary"] - st["dual"]) / abs(st["dual"]),
+            "vs_regions": sc}
+
+
 def counter_profile(kernel: str, workload: str, digest_of=None):
     """The committed counter summary of `kernel` at `workload`
     (profiles/<kernel>_<workload>_counters.json), or None when it is absent or
@@ -441,6 +504,8 @@ def main():
     ap.add_argument("--segment", action="store_true",
                     help="only the segmentation leg (primal-dual iteration) on --config's data term")
     ap.add_argument("--seg-iters", type=int, default=300)
+    ap.add_argument("--unsup", action="store_true",
+                    help="only the unsupervised segmentation leg on --config's image")
     ap.add_argument("--seg-lambda", type=float, default=1.0)
     ap.add_argument("--soft", action="store_true",
                     help="the joint form with smooth co-supports (sigma 0.01) of the stored "
@@ -474,6 +539,9 @@ def main():
         return
     if args.segment:
         print(json.dumps(segment_line(args, args.config)))
+        return
+    if args.unsup:
+        print(json.dumps(unsup_line(args, args.config)))
         return
 
     import numpy as np
@@ -615,6 +683,8 @@ def main():
     if not args.no_segment and not (args.joint or args.soft):
         print("[bench] segmentation leg (BSDS-sized data term)", file=sys.stderr, flush=True)
         seg = segment_line(args, 1)
+        print("[bench] unsupervised leg (BSDS-sized image)", file=sys.stderr, flush=True)
+        seg["unsupervised"] = unsup_line(args, 1)
 
     out = {
         "metric": "data-term pixel x sample pairs/s",

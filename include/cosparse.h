@@ -353,6 +353,48 @@ typedef struct {
 int cs_segment(cs_ctx *ctx, const float *rgb, int H, int W, const float *loglik, int L,
                const cs_segment_params *prm, int32_t *labels, float *u, cs_segment_stats *stats);
 
+/* ---- Unsupervised data term (Sec. 3.1, unsupervised segmentation) ----
+ * Without scribbles the segment classes come from clustering: k-means on the
+ * pixels' colours (Lloyd: assign to the nearest centroid in squared Euclidean
+ * distance, move each centroid to its pixels' mean) gives Kc colour classes,
+ * k-medians on the co-support masks (assign by TSM, the Hamming distance;
+ * move each centroid to the component-wise median, i.e. the majority of its
+ * masks, a tie in) gives Kt texture classes, and every pair (a, b) is a
+ * segment class i = a Kt + b represented by the two centroids.  Each pixel
+ * gets a colour and a texture likelihood in the form of eq:post_text:
+ *   loglik_i(x) = -d_c(x, a) - log sum_j exp(-d_c(x, a_j))
+ *                 - d_t(x, b) - log sum_j exp(-d_t(x, b_j))   (sums over all Kc Kt classes)
+ * with d_c = ||I(x) - mu_a||^2 / (2 sigma_c^2) and d_t = TSM(x, c_b) / beta
+ * (no scribbles, so no location term and a constant beta).  cs_segment with a
+ * label cost nu > 0 (eq:mdl) then removes unneeded classes.
+ * Readings: the first centroids are the colours and masks of caller-given
+ * pixels (random numbers of the method are inputs); a fixed iteration count;
+ * distance ties to the lowest class; a class without pixels keeps its
+ * centroid. */
+typedef struct {
+    int colour_classes;   /* Kc, 1..16                                           */
+    int texture_classes;  /* Kt, 1..16, Kc * Kt <= 64                            */
+    int iterations;       /* Lloyd iterations of each clustering, 0..100000     */
+    double sigma_c;       /* colour kernel standard deviation, > 0              */
+    double beta;          /* texture temperature, > 0                           */
+} cs_unsup_params;
+
+/* Clustering and class likelihoods of every pixel.
+ *   rgb              device, 3*H*W float32
+ *   masks, k         device, H*W*ceil(k/64) uint64 co-supports (as cs_cosupport)
+ *   init_colour      host, Kc pixel indices (the first colour centroids)
+ *   init_texture     host, Kt pixel indices (the first texture centroids)
+ *   loglik           device out, H*W*(Kc*Kt) float32, pixel-major
+ *   colour_centroids device out, Kc*3 float64, or NULL
+ *   texture_centroids device out, Kt*ceil(k/64) uint64, or NULL
+ *   colour_labels, texture_labels  device out, H*W int32 each, or NULL
+ * Errors: CS_ERR_ARG for null pointers, sizes, class counts, iterations,
+ * sigma_c or beta not positive, initial pixels out of range. */
+int cs_unsupervised_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
+                           const int32_t *init_colour, const int32_t *init_texture, const cs_unsup_params *prm,
+                           float *loglik, double *colour_centroids, uint64_t *texture_centroids,
+                           int32_t *colour_labels, int32_t *texture_labels);
+
 /* ---- Learned surrogate of the data term ----
  * A two-hidden-layer perceptron maps a pixel's colour, normalised position
  * and analysed vector (Sec. 2 a = O s of the Sec. 3.1 patch) to its per-label

@@ -16,6 +16,7 @@ from .binding import (  # noqa: F401
     LoglikParams,
     Mlp,
     SegmentParams,
+    UnsupParams,
     lib,
     library_path,
     mlp_features,

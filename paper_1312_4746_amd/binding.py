@@ -48,6 +48,11 @@ class _SegmentStatsC(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("labels_used", ctypes.c_int)]
 
 
+class _UnsupParamsC(ctypes.Structure):
+    _fields_ = [("colour_classes", ctypes.c_int), ("texture_classes", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("sigma_c", ctypes.c_double), ("beta", ctypes.c_double)]
+
+
 class _CosupportStatsC(ctypes.Structure):
     _fields_ = [("recomputed", ctypes.c_int64), ("max_margin", ctypes.c_double)]
 
@@ -79,6 +84,8 @@ SIGNATURES = {
     "cs_edge_weight": (_I, [_P, _P, _I, _I, _D, _P, ctypes.POINTER(_D)]),
     "cs_segment": (_I, [_P, _P, _I, _I, _P, _I, ctypes.POINTER(_SegmentParamsC), _P, _P,
                         ctypes.POINTER(_SegmentStatsC)]),
+    "cs_unsupervised_loglik": (_I, [_P, _P, _I, _I, _P, _I, _P, _P, ctypes.POINTER(_UnsupParamsC), _P, _P, _P,
+                                    _P, _P]),
     "cs_mlp_param_count": (_I64, [_I, _I, _I]),
     "cs_mlp_init": (_I, [_P, ctypes.POINTER(_P), _I, _I, _I, _P]),
     "cs_mlp_free": (_I, [_P]),
@@ -172,6 +179,19 @@ class LoglikParams:
     def c(self) -> _LoglikParamsC:
         return _LoglikParamsC(self.alpha_rho, self.sigma_c, self.beta_scale, self.rho_floor_px,
                               int(bool(self.normalise)))
+
+
+@dataclasses.dataclass
+class UnsupParams:
+    colour_classes: int = 4
+    texture_classes: int = 4
+    iterations: int = 10
+    sigma_c: float = 0.05
+    beta: float = 2.0
+
+    def c(self) -> _UnsupParamsC:
+        return _UnsupParamsC(int(self.colour_classes), int(self.texture_classes), int(self.iterations),
+                             float(self.sigma_c), float(self.beta))
 
 
 @dataclasses.dataclass
@@ -461,6 +481,34 @@ class Context:
             info = {"primal": st.primal, "binary": st.binary, "dual": st.dual, "gamma": st.gamma,
                     "labels_used": int(st.labels_used)}
         return labels, u, info
+
+    def unsupervised_loglik(self, rgb: torch.Tensor, masks: torch.Tensor, k: int, init_colour, init_texture,
+                            params: "UnsupParams", out: Optional[torch.Tensor] = None):
+        """cs_unsupervised_loglik: class log-likelihoods (H*W, Kc*Kt) and a dict
+        with the colour and texture centroids and classes of every pixel."""
+        H, W = _image_hw(rgb)
+        _masks_shape(masks, H * W, k)
+        Kc, Kt = int(params.colour_classes), int(params.texture_classes)
+        ic = (ctypes.c_int32 * max(Kc, 1))(*[int(v) for v in init_colour])
+        it = (ctypes.c_int32 * max(Kt, 1))(*[int(v) for v in init_texture])
+        if len(init_colour) != Kc or len(init_texture) != Kt:
+            raise ValueError("one initial pixel per colour and per texture class")
+        _numel(out, H * W * Kc * Kt, "loglik", "H*W*Kc*Kt")
+        self._dev(rgb, torch.float32, "rgb")
+        self._dev(masks, torch.int64, "masks")
+        dev = rgb.device
+        if out is None:
+            out = torch.empty((H * W, Kc * Kt), dtype=torch.float32, device=dev)
+        self._dev(out, torch.float32, "loglik")
+        cc = torch.empty((max(Kc, 1), 3), dtype=torch.float64, device=dev)
+        tc = torch.empty((max(Kt, 1), _nw(k)), dtype=torch.int64, device=dev)
+        cl = torch.empty(H * W, dtype=torch.int32, device=dev)
+        tl = torch.empty(H * W, dtype=torch.int32, device=dev)
+        prm = params.c()
+        self._sync_stream()
+        self._check(lib().cs_unsupervised_loglik(self._h, _ptr(rgb), H, W, _ptr(masks), k, ic, it, ctypes.byref(prm),
+                                                 _ptr(out), _ptr(cc), _ptr(tc), _ptr(cl), _ptr(tl)))
+        return out, {"colour_centroids": cc, "texture_centroids": tc, "colour_labels": cl, "texture_labels": tl}
 
     def set_check_finite(self, on: bool = True):
         """Optional finite check of rgb and omega before each call (synchronises)."""

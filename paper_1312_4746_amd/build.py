@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["cs_host.hip", "k_analyze.hip", "k_tau.hip", "k_tsm.hip", "k_samples.hip",
            "k_edt.hip", "k_parzen.hip", "k_parzen_mfma.hip", "k_mlp.hip",
-           "k_cosupport_median.hip", "k_texture.hip", "k_segment.hip"]
+           "k_cosupport_median.hip", "k_texture.hip", "k_segment.hip", "k_unsup.hip"]
 
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

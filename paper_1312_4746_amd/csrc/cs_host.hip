@@ -1682,4 +1682,75 @@ int cs_segment(cs_ctx *ctx, const float *rgb, int H, int W, const float *loglik,
     return CS_OK;
 }
 
+int cs_unsupervised_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint64_t *masks, int k,
+                           const int32_t *init_colour, const int32_t *init_texture, const cs_unsup_params *prm,
+                           float *loglik, double *colour_centroids, uint64_t *texture_centroids,
+                           int32_t *colour_labels, int32_t *texture_labels) {
+    if (!ctx) return CS_ERR_ARG;
+    int rc = check_segment_image(ctx, rgb, H, W);
+    if (rc) return rc;
+    if (!masks || !init_colour || !init_texture || !prm || !loglik) return fail(ctx, CS_ERR_ARG, "null pointer argument");
+    if (k < 1 || k > kMaxK) return fail(ctx, CS_ERR_ARG, "k must be in 1..%d (got %d)", kMaxK, k);
+    const int Kc = prm->colour_classes, Kt = prm->texture_classes;
+    if (Kc < 1 || Kc > kUnsupMaxClasses || Kt < 1 || Kt > kUnsupMaxClasses || Kc * Kt > kMaxLabels)
+        return fail(ctx, CS_ERR_ARG, "colour and texture classes must be in 1..%d with a product of at most %d",
+                    kUnsupMaxClasses, kMaxLabels);
+    if (prm->iterations < 0 || prm->iterations > 100000) return fail(ctx, CS_ERR_ARG, "iterations must be in 0..100000");
+    auto pos = [](double v) { return v > 0.0 && std::isfinite(v); };
+    if (!pos(prm->sigma_c) || !pos(prm->beta)) return fail(ctx, CS_ERR_ARG, "sigma_c and beta must be positive and finite");
+    const int64_t N = (int64_t)H * W;
+    UnsupInit init{};
+    for (int i = 0; i < Kc; ++i) init.pix[i] = init_colour[i];
+    for (int i = 0; i < Kt; ++i) init.pix[Kc + i] = init_texture[i];
+    for (int i = 0; i < Kc + Kt; ++i)
+        if (init.pix[i] < 0 || init.pix[i] >= N) return fail(ctx, CS_ERR_ARG, "an initial pixel is out of range");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((rc = check_inputs_finite(ctx, rgb, 3 * N, nullptr, 0))) return rc;
+    const int nw = (k + 63) / 64;
+    const int64_t nb = (N + 255) / 256;
+    Carve cv;
+    const size_t o_cc = cv.take(sizeof(double) * Kc * 3);
+    const size_t o_tc = cv.take(sizeof(uint64_t) * Kt * nw);
+    const size_t o_cl = cv.take(sizeof(int32_t) * (size_t)N);
+    const size_t o_tl = cv.take(sizeof(int32_t) * (size_t)N);
+    const size_t o_cp = cv.take(sizeof(double) * (size_t)nb * Kc * 4);
+    const size_t o_tn = cv.take(sizeof(unsigned int) * ((size_t)Kt * k + Kt));
+    if ((rc = ensure_ws(ctx, cv.off))) return rc;
+    UnsupArgs a{};
+    a.rgb = rgb;
+    a.masks = masks;
+    a.N = N;
+    a.H = H;
+    a.W = W;
+    a.k = k;
+    a.nw = nw;
+    a.Kc = Kc;
+    a.Kt = Kt;
+    a.sigma_c = prm->sigma_c;
+    a.beta = prm->beta;
+    a.ccent = colour_centroids ? colour_centroids : (double *)(ctx->ws + o_cc);
+    a.tcent = texture_centroids ? texture_centroids : (uint64_t *)(ctx->ws + o_tc);
+    a.clab = colour_labels ? colour_labels : (int32_t *)(ctx->ws + o_cl);
+    a.tlab = texture_labels ? texture_labels : (int32_t *)(ctx->ws + o_tl);
+    a.cpart = (double *)(ctx->ws + o_cp);
+    a.tcount = (unsigned int *)(ctx->ws + o_tn);
+    a.tsize = a.tcount + (size_t)Kt * k;
+    const LaunchCtx lc = lc_of(ctx);
+    HIP_TRY(launch_fill_u32(lc, a.tcount, (size_t)Kt * k + Kt, 0u));
+    HIP_TRY(launch_unsup_init(lc, a, init));
+    {
+        Timed t(ctx, "kmeans");
+        for (int it = 0; it < prm->iterations; ++it) HIP_TRY(launch_kmeans_step(lc, a, true));
+        HIP_TRY(launch_kmeans_step(lc, a, false));
+    }
+    {
+        Timed t(ctx, "kmedians");
+        for (int it = 0; it < prm->iterations; ++it) HIP_TRY(launch_kmedians_step(lc, a, true));
+        HIP_TRY(launch_kmedians_step(lc, a, false));
+    }
+    Timed t(ctx, "unsup_loglik");
+    HIP_TRY(launch_unsup_loglik(lc, a, loglik));
+    return CS_OK;
+}
+
 }  // extern "C"

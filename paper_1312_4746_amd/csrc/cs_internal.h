@@ -349,6 +349,30 @@ hipError_t launch_pd_iter(const LaunchCtx &lc, const PdArgs &a, int precision, i
 hipError_t launch_pd_finish(const LaunchCtx &lc, const PdArgs &a, int precision, int32_t *labels, float *u_out,
                             unsigned long long *used, double *part, double *energies);
 
+// ---- unsupervised data term (k_unsup.hip) ----
+constexpr int kUnsupMaxClasses = 16;  // colour or texture classes
+struct UnsupArgs {
+    const float *rgb;
+    const uint64_t *masks;
+    int64_t N;
+    int H, W, k, nw, Kc, Kt;
+    double sigma_c, beta;
+    double *ccent;          // Kc x 3 colour centroids
+    uint64_t *tcent;        // Kt x nw texture centroids
+    int32_t *clab, *tlab;   // N colour and texture classes
+    double *cpart;          // ceil(N / 256) x Kc x 4 partial sums
+    unsigned int *tcount;   // Kt x k bit counts (zero before an assignment with counts)
+    unsigned int *tsize;    // Kt class sizes (idem)
+};
+struct UnsupInit {
+    int32_t pix[2 * kUnsupMaxClasses];  // pixels of the first centroids: Kc colour, then Kt texture
+};
+hipError_t launch_unsup_init(const LaunchCtx &lc, const UnsupArgs &a, const UnsupInit &init);
+// One assignment (and, with update, the centroids moved to their classes).
+hipError_t launch_kmeans_step(const LaunchCtx &lc, const UnsupArgs &a, bool update);
+hipError_t launch_kmedians_step(const LaunchCtx &lc, const UnsupArgs &a, bool update);
+hipError_t launch_unsup_loglik(const LaunchCtx &lc, const UnsupArgs &a, float *loglik);
+
 // ---- learned surrogate (k_mlp.hip) ----
 constexpr int kMlpHid = 128;                          // hidden units per layer
 constexpr int kMlpMaxIn = 128;                        // input features (padded to 16)

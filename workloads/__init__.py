@@ -1,7 +1,8 @@
 """Seeded synthetic workloads for the co-sparse data term.
 
 This package only draws inputs (images, analysis operators, scribble
-samples, training-pixel subsets, initial surrogate weights and data order).  It contains none of the method's
+samples, training-pixel subsets, initial surrogate weights and data order,
+the pixels that start the unsupervised clustering).  It contains none of the method's
 arithmetic, so both the FP64 oracle and the HIP library can be fed from
 it without sharing any computation.
 """
@@ -13,4 +14,5 @@ from .gen import (  # noqa: F401
     make_omega,
     mlp_init,
     mlp_order,
+    unsup_init,
 )

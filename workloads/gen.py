@@ -288,3 +288,11 @@ def mlp_order(n_rows: int, steps: int, batch: int, seed: int) -> np.ndarray:
         chunks.append(rng.permutation(n_rows))
         have += n_rows
     return np.concatenate(chunks)[:need].astype(np.int32).reshape(steps, batch)
+
+
+def unsup_init(N: int, colour_classes: int, texture_classes: int, seed: int):
+    """Pixels whose colours and co-supports start the unsupervised clustering
+    (random numbers only): distinct pixels drawn uniformly."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    pix = rng.choice(N, size=colour_classes + texture_classes, replace=False).astype(np.int32)
+    return pix[:colour_classes], pix[colour_classes:]
