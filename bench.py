@@ -178,10 +178,10 @@ def cpu_baseline(w, n_sample: int, joint: bool = False, soft: bool = False, n_fr
 
 
 def add_surrogate_args(ap):
-    ap.add_argument("--mlp-steps", type=int, default=3000)
+    ap.add_argument("--mlp-steps", type=int, default=1000)
     ap.add_argument("--mlp-batch", type=int, default=4096)
     ap.add_argument("--mlp-lr", type=float, default=3e-3)
-    ap.add_argument("--fallback-margin", type=float, default=1.0,
+    ap.add_argument("--fallback-margin", type=float, default=2.0,
                     help="pixels whose two largest surrogate outputs differ by less than this (nats) "
                          "take the exact data term")
     ap.add_argument("--sur-precision", default="bf16", choices=["bf16", "fp32"],
@@ -678,6 +678,8 @@ def main():
         full = surrogate_line(args)
         sur = {k_: full[k_] for k_ in ("value", "unit", "ms_per_step")}
         sur.update({"workload": full["config"]["workload"], **full["surrogate"]})
+        for k_ in ("exact", "speedup_per_image_incl_fit", "speedup_trained", "equal_time_exact"):
+            sur[k_] = full[k_]
 
     seg = None
     if not args.no_segment and not (args.joint or args.soft):

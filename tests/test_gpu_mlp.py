@@ -229,3 +229,67 @@ def test_output_bias_is_mean_clipped_target(ctx):
     # the other parameters are untouched
     assert np.array_equal(om.unpack(p, sh)["W3"], om.unpack(p0, sh)["W3"].astype(np.float32))
     net.close()
+
+
+def test_surrogate_gain_on_the_2048_workload(ctx):
+    """What the trained network gains over the method without it, per image
+    and fit included: the surrogate path (BF16 analysis as features, exact
+    targets at 2 % of the pixels, 1000 Adam steps, inference with the exact
+    data term for pixels whose two best labels are within 2 nats) flips at most
+    0.5 % of the label decisions of the exact FP32 data term, takes less time
+    than it, and flips fewer labels than the exact data term restricted to a
+    random sample subset sized to the surrogate path's whole time."""
+    import time
+
+    from paper_1312_4746_amd import LoglikParams, Mlp, mlp_features
+    from paper_1312_4746_amd import surrogate as sg
+    from workloads import make_config
+    w = make_config(4)
+    rgb, om = dev(w.rgb), dev(w.omega)
+    spix, slab, tpix = dev(w.sample_pix), dev(w.sample_label), dev(w.train_pix)
+    prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
+                       rho_floor_px=w.rho_floor_px)
+    steps, batch = 1000, 4096
+    order = dev(mlp_order(len(w.train_pix), steps, batch, seed=w.seed + 101).ravel())
+    init = dev(mlp_init(5 + w.k, 128, w.L, seed=w.seed + 100))
+
+    def exact_path():
+        _, m, _ = ctx.cosupport_median(rgb, w.p, w.mask_sigma, om, 0.1)
+        return m, ctx.label_loglik(rgb, m, w.k, spix, slab, w.L, prm)
+
+    def surrogate_path():
+        a, m, _ = ctx.cosupport_median(rgb, w.p, w.mask_sigma, om, 0.1, precision="bf16")
+        ell = ctx.label_loglik(rgb, m, w.k, spix, slab, w.L, prm, pix_subset=tpix)
+        x = mlp_features(ctx, rgb, a, tpix)
+        net = Mlp(ctx, 5 + w.k, w.L, init)
+        net.fit_output_bias(ell)
+        net.train(x, ell, order, batch, 3e-3)
+        y, n = net.infer_fallback(rgb, a, m, w.k, spix, slab, prm, margin=2.0)
+        net.close()
+        return y, n
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    exact_path()
+    surrogate_path()  # warm-ups (workspace, code objects)
+    t_exact, (m32, ll) = timed(exact_path)
+    t_sur, (y, n_exact) = timed(surrogate_path)
+    q = sg.compare_to_exact(y, ll)
+    print(f"surrogate: {q['flip_rate']:.5f} flips, {n_exact} pixels exact, {t_sur * 1e3:.1f} ms per image "
+          f"against {t_exact * 1e3:.1f} ms exact", flush=True)
+    assert q["flip_rate"] <= 0.005
+    assert t_sur < t_exact
+    # the method without the network at the surrogate path's time
+    t_front, _ = timed(lambda: ctx.cosupport_median(rgb, w.p, w.mask_sigma, om, 0.1))
+    frac = max(0.0, (t_sur - t_front) / (t_exact - t_front))
+    gen = torch.Generator().manual_seed(w.seed + 102)
+    sp2, sl2 = sg.equal_time_subset(spix, slab, w.L, max(w.L, int(w.M * frac)), gen)
+    ll2 = ctx.label_loglik(rgb, m32, w.k, sp2, sl2, w.L, prm)
+    q2 = sg.compare_to_exact(ll2, ll)
+    print(f"equal time: {sp2.numel()} samples ({frac:.2f} of them), {q2['flip_rate']:.5f} flips", flush=True)
+    assert q["flip_rate"] < q2["flip_rate"]
