@@ -214,6 +214,12 @@ typedef struct {
  *   pix_subset    device, n_subset int32 pixel indices, or NULL for all N pixels
  *   loglik        device out, (n_subset or N) * L float32, loglik[r*L + i]
  *                 (may be NULL when pix_subset is non-NULL and n_subset is 0)
+ * Route: images up to 2048 x 2048 go to the matrix-core kernel, the full
+ * image in 8 x 4 pixel tiles, a subset of 1024 or more entries in tiles of 32
+ * consecutive entries (duplicates allowed); smaller subsets and larger images
+ * to the exact per-pixel kernel.  Both give the same sums within FP32
+ * rounding; on the matrix-core path a pixel's row does not depend on which
+ * other pixels are computed with it.
  * Synchronises once after sorting the samples by label (to check labels).
  * Errors: CS_ERR_ARG (null pointers, H outside 1..32767, W outside 1..16384,
  * k outside 1..256, L outside 1..64, prm values <= 0 or not finite, sample
@@ -273,9 +279,10 @@ typedef struct {
 } cs_loglik_stats;
 
 /* Counters of the last log-likelihood call (any of the three forms) on this
- * context that got past its argument checks: full-image path only, zeros for
- * a pixel subset.  They live in context-owned device memory that no other
- * call touches.  Synchronises the stream. */
+ * context that got past its argument checks: matrix-core path only (full
+ * image, or a subset of 1024 or more pixels), zeros for a call that took the
+ * exact kernel.  They live in context-owned device memory that no other call
+ * touches.  Synchronises the stream. */
 int cs_last_loglik_stats(cs_ctx *ctx, cs_loglik_stats *stats);
 
 /* Kernel timing on the context stream (HIP events around each launch of the

@@ -828,12 +828,17 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
     const size_t o_d2 = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_nn = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_edt = cv.take(edt_scratch_bytes(H, W, L));
-    // full-image path (matrix-core kernel; its exact integer location product
-    // needs positions below 2048): FP8 sample features, records, fix-up queue
-    const bool fast = pix_subset == nullptr && W <= 2048 && H <= 2048;
+    // matrix-core path (its exact integer location product needs positions
+    // below 2048): FP8 sample features, records, fix-up queue.  The full image
+    // goes in 8 x 4 pixel tiles; a pixel subset of at least kListFastMin
+    // entries in tiles of kTilePix consecutive entries (below that the exact
+    // kernel, whose set-up is lighter, takes it).
+    const bool fast = W <= 2048 && H <= 2048 && (pix_subset == nullptr || npix >= kListFastMin);
+    const bool listed = fast && pix_subset != nullptr;
     const int KP = (k + 4 + 127) / 128 * 128;
-    const int tiles_x = (W + 7) / 8, tiles_y = (H + 2 * kParzenRB - 1) / (2 * kParzenRB);
-    const int64_t ntiles = (int64_t)tiles_x * tiles_y;
+    const int tiles_x = listed ? 1 : (W + 7) / 8;
+    const int64_t ntiles = listed ? (npix + kTilePix - 1) / kTilePix
+                                  : (int64_t)tiles_x * ((H + 2 * kParzenRB - 1) / (2 * kParzenRB));
     const int64_t ngroups = (ntiles + 3) / 4, ntiles_pad = ngroups * 4;
     const int64_t Mpad_max = M + (int64_t)(kStreamChunk - 1) * L;
     const size_t o_feat = fast ? cv.take((size_t)Mpad_max * KP) : 0;
@@ -942,6 +947,8 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         pr.ntiles = (int)ntiles;
         pr.ksteps = KP / 128;
         pr.ntiles_pad = ntiles_pad;
+        pr.list = listed ? pix_subset : nullptr;
+        pr.nlist = listed ? npix : 0;
         pr.pix4 = (float4 *)(ctx->ws + o_pix4);
         pr.aop = (uint32_t *)(ctx->ws + o_aop);
         pr.abf = (uint4 *)(ctx->ws + o_abf);
@@ -1038,6 +1045,8 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         fa.fix_cap = (int)(ntiles_pad * L);
         fa.sigma_c = pa.sigma_c;
         fa.texture = pa.texture_in_sum;
+        fa.list = listed ? pix_subset : nullptr;
+        fa.nlist = listed ? npix : 0;
         // labels per block of the work order: as many as keep their sample
         // streams (features and records of every chunk) within about half of
         // an XCD's 4 MiB L2 together, counted from the largest labels (at

@@ -22,6 +22,28 @@ constexpr int kParzenRB = 2;
 constexpr int kParzenQueues = 8;
 constexpr int kQueueStride = 32;  // unsigned ints
 constexpr int kTilePix = 8 * 2 * kParzenRB;
+// Smallest pixel subset that the matrix-core Parzen path takes.
+constexpr int64_t kListFastMin = 1024;
+
+// Slot q (0 .. kTilePix-1) of tile t on the matrix-core Parzen path.  On the
+// tile grid (list == nullptr) it is pixel (x0 + q % 8, y0 + q / 8) of the
+// image, tiles_x tiles per band of 2 kParzenRB rows, and the output row is
+// that pixel; with a pixel list the slot is list entry t kTilePix + q and the
+// output row is that entry's index.  -1: outside the image or past the list.
+__device__ __forceinline__ int64_t fast_slot_row(const int32_t *list, int64_t nlist, int H, int W, int tiles_x,
+                                                 int ntiles, int t, int q) {
+    if (list) {
+        const int64_t s = (int64_t)t * kTilePix + q;
+        return s < nlist ? s : -1;
+    }
+    const int ty = t / tiles_x;
+    const int px = (t - ty * tiles_x) * 8 + (q & 7), py = ty * 2 * kParzenRB + (q >> 3);
+    return t < ntiles && px < W && py < H ? (int64_t)py * W + px : -1;
+}
+// The pixel behind an output row of fast_slot_row (row >= 0).
+__device__ __forceinline__ int64_t fast_row_pixel(const int32_t *list, int64_t row) {
+    return list ? (int64_t)list[row] : row;
+}
 // Samples per chunk of the padded sample stream (label segments are rounded
 // up to whole chunks).
 constexpr int kStreamChunk = 64;
@@ -227,6 +249,8 @@ struct ParzenArgs {
     int tiles_x;
     // coefficients {nA, nB, -R, K} (k_coef): [label][npix] for a pixel list, or
     // tiled [label][ntiles_pad][kTilePix] for the full image
+    // (with coef_tiled and a subset, the slots of the tiles are the subset's
+    // entries in order: see fast_slot_row)
     const float4 *coef;
     int coef_tiled, ntiles_real, ntiles_pad;
     int H, W, L, k, nw32;
@@ -286,6 +310,8 @@ struct ParzenFastArgs {
     int tiles_x, ntiles, ngroups;
     int texture;           // 0: texture factor out of the sum (no FP8 products)
     int lblock;            // labels per block of the work order (1..L)
+    const int32_t *list;   // pixel list (tile slots are its entries) or null (tile grid)
+    int64_t nlist;
     double sigma_c;
     // passed by value (kernel arguments): [0..L] first chunk of each label's
     // padded segment (chunk units), [L+1 .. 2L] the labels by decreasing
@@ -308,6 +334,8 @@ struct PrepArgs {
     const uint64_t *masks;
     int H, W, tiles_x, ntiles, ksteps;
     int64_t ntiles_pad;
+    const int32_t *list;   // pixel list (tile slots are its entries) or null (tile grid)
+    int64_t nlist;
     float4 *pix4;
     uint32_t *aop;
     uint4 *abf;

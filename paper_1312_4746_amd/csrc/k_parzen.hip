@@ -61,8 +61,9 @@ __device__ __forceinline__ float pair_e(float px, float py, float pr, float pg, 
 //   over the nearest sample and kRefSubset strided samples of the label (an
 //   achieved value, so the sum is at least 2^-kRefMargin).
 // coef[l * npix + i] = {nA, nB, nR, K}; pixel i is subset[i] or i.
-// Tiled layout: slot i = tile * kTilePix + q, q -> (x0 + q % 8, y0 + q / 8);
-// slots outside the image get {0, 0, -200, 0} (their terms vanish).
+// Tiled layout (matrix-core path): slot i = tile * kTilePix + q, the pixel of
+// fast_slot_row (the tile grid, or entry i of the subset); empty slots get
+// {0, 0, -200, 0} (their terms vanish).
 template <int NW>
 __global__ __launch_bounds__(256) void k_coef(ParzenArgs a, float4 *__restrict__ coef) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -74,13 +75,12 @@ __global__ __launch_bounds__(256) void k_coef(ParzenArgs a, float4 *__restrict__
     int64_t pix;
     if (a.coef_tiled) {
         const int t = (int)(i / kTilePix), q = (int)(i - (int64_t)t * kTilePix);
-        const int ty = t / a.tiles_x;
-        const int px = (t - ty * a.tiles_x) * 8 + (q & 7), py = ty * 2 * kParzenRB + (q >> 3);
-        if (t >= a.ntiles_real || px >= a.W || py >= a.H) {
+        const int64_t row = fast_slot_row(a.subset, a.npix, a.H, a.W, a.tiles_x, a.ntiles_real, t, q);
+        if (row < 0) {
             coef[(int64_t)l * nslots + i] = make_float4(0.0f, 0.0f, -200.0f, 0.0f);
             return;
         }
-        pix = (int64_t)py * a.W + px;
+        pix = fast_row_pixel(a.subset, row);
     } else {
         pix = a.subset ? (int64_t)a.subset[i] : i;
     }
@@ -158,12 +158,13 @@ __global__ __launch_bounds__(256) void k_parzen(ParzenArgs a, const uint32_t *__
             const int2 fx = a.fixlist[item];
             l = __builtin_amdgcn_readfirstlane(fx.x);
             tile = __builtin_amdgcn_readfirstlane(fx.y);
-            const int tyy = tile / a.tiles_x;
-            const int px = (tile - tyy * a.tiles_x) * 8 + (lane & 7);
-            const int py = tyy * 2 * kParzenRB + (lane >> 3);
-            valid = (lane >> 3) < 2 * kParzenRB && px < a.W && py < a.H;
-            pix = valid ? (int64_t)py * a.W + px : 0;
-            i = pix;
+            // lanes 0 .. kTilePix-1 take the tile's slots (fast_slot_row)
+            const int64_t row = lane < kTilePix
+                                    ? fast_slot_row(a.subset, a.npix, a.H, a.W, a.tiles_x, a.ntiles_real, tile, lane)
+                                    : -1;
+            valid = row >= 0;
+            i = valid ? row : 0;
+            pix = valid ? fast_row_pixel(a.subset, row) : 0;
         } else {
             l = a.label_order[item / a.tiles];
             tile = item - (item / a.tiles) * a.tiles;

@@ -184,21 +184,20 @@ __device__ __forceinline__ void stream_build(const SampleRec *recs, int k, int K
     }
 }
 
-// Pixel records of the full-image path, tiled like the coefficients
-// ([tile][kTilePix], in-tile index dy * 8 + dx): colours scaled by
+// Pixel records of the matrix-core path, tiled like the coefficients
+// ([tile][kTilePix], slot q of a tile as in fast_slot_row): colours scaled by
 // sqrt(log2(e) / (2 sigma_c^2)) (so that the colour term is minus the squared
-// difference) and the co-support size |A| as a float; zeros outside the image.
+// difference) and the co-support size |A| as a float; zeros for empty slots.
 __device__ __forceinline__ void pixel_tiles(const float *rgb, const uint64_t *masks, int H, int W, int k,
-                                            int tiles_x, int ntiles, int64_t nslots, float cscale, float4 *pix4,
-                                            int bid) {
+                                            int tiles_x, int ntiles, const int32_t *list, int64_t nlist,
+                                            int64_t nslots, float cscale, float4 *pix4, int bid) {
     const int64_t s = (int64_t)bid * 256 + threadIdx.x;
     if (s >= nslots) return;
     const int tile = (int)(s / kTilePix), i = (int)(s - (int64_t)tile * kTilePix);
-    const int ty = tile / tiles_x;
-    const int px = (tile - ty * tiles_x) * 8 + (i & 7), py = ty * 2 * kParzenRB + (i >> 3);
+    const int64_t row = fast_slot_row(list, nlist, H, W, tiles_x, ntiles, tile, i);
     float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (tile < ntiles && px < W && py < H) {
-        const int64_t N = (int64_t)H * W, pix = (int64_t)py * W + px;
+    if (row >= 0) {
+        const int64_t N = (int64_t)H * W, pix = fast_row_pixel(list, row);
         const int W64 = (k + 63) / 64;
         uint32_t cnt = 0;
         for (int w = 0; w < W64; ++w) {
@@ -211,9 +210,9 @@ __device__ __forceinline__ void pixel_tiles(const float *rgb, const uint64_t *ma
     pix4[s] = out;
 }
 
-// Pixel operands of the full-image path, built once per call: for every
-// padded tile, row block rb and lane (g, jl) of the MFMA operands, the pixel
-// of row jl is (x0 + (jl & 7), y0 + 2 rb + (jl >> 3)).
+// Pixel operands of the matrix-core path, built once per call: for every
+// padded tile, row block rb and lane (g, jl) of the MFMA operands, row jl is
+// the tile's slot (2 rb + (jl >> 3)) * 8 + (jl & 7) (fast_slot_row).
 //  * FP8 texture operand (32 B per lane and 128-feature step q): features
 //    32 (4q + g) .. +31, i.e. mask bits j < k, 1 at k and k+1, 16 floor(|A|/16)
 //    at k+2 and |A| mod 16 at k+3 (zero for pixels outside the image);
@@ -221,7 +220,8 @@ __device__ __forceinline__ void pixel_tiles(const float *rgb, const uint64_t *ma
 //    pieces (2, each twice), -2 py high] for g = 0, K 8..15 [-2 py high, -2 py
 //    low (twice), 1, 1, 1, 1 (far term), 0] for g = 1, zeros for g >= 2.
 __device__ __forceinline__ void pixel_operands(const uint64_t *masks, int H, int W, int k, int tiles_x, int ntiles,
-                                               int64_t nthreads, int ksteps, uint32_t *aop, uint4 *abf, int bid) {
+                                               const int32_t *list, int64_t nlist, int64_t nthreads, int ksteps,
+                                               uint32_t *aop, uint4 *abf, int bid) {
     const int64_t s = (int64_t)bid * 256 + threadIdx.x;
     if (s >= nthreads) return;
     const int lane = (int)(s & 63);
@@ -229,12 +229,12 @@ __device__ __forceinline__ void pixel_operands(const uint64_t *masks, int H, int
     const int rb = (int)(tr % kParzenRB);
     const int tile = (int)(tr / kParzenRB);
     const int g = lane >> 4, jl = lane & 15;
-    const int ty = tile / tiles_x;
-    const int x0 = (tile - ty * tiles_x) * 8, y0 = ty * 2 * kParzenRB;
-    const int px = x0 + (jl & 7), py = y0 + 2 * rb + (jl >> 3);
-    const bool v = tile < ntiles && px < W && py < H;
+    const int64_t row = fast_slot_row(list, nlist, H, W, tiles_x, ntiles, tile, (2 * rb + (jl >> 3)) * 8 + (jl & 7));
+    const bool v = row >= 0;
+    const int64_t pix = v ? fast_row_pixel(list, row) : 0;
+    const int px = (int)(pix % W), py = (int)(pix / W);
     const int W64 = (k + 63) / 64;
-    const uint32_t *mw = reinterpret_cast<const uint32_t *>(masks) + (v ? ((int64_t)py * W + px) * 2 * W64 : 0);
+    const uint32_t *mw = reinterpret_cast<const uint32_t *>(masks) + pix * 2 * W64;
     const int nw32 = (k + 31) / 32;
     const uint32_t lastmask = (k & 31) ? (1u << (k & 31)) - 1u : ~0u;
     uint32_t cnt = 0;
@@ -286,11 +286,13 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     }
     b -= a.b_stream;
     if (b < a.b_tiles) {
-        pixel_tiles(a.rgb, a.masks, a.H, a.W, a.k, a.tiles_x, a.ntiles, a.nslots, a.cscale, a.pix4, b);
+        pixel_tiles(a.rgb, a.masks, a.H, a.W, a.k, a.tiles_x, a.ntiles, a.list, a.nlist, a.nslots, a.cscale,
+                    a.pix4, b);
         return;
     }
     b -= a.b_tiles;
-    pixel_operands(a.masks, a.H, a.W, a.k, a.tiles_x, a.ntiles, a.nthreads, a.ksteps, a.aop, a.abf, b);
+    pixel_operands(a.masks, a.H, a.W, a.k, a.tiles_x, a.ntiles, a.list, a.nlist, a.nthreads, a.ksteps, a.aop,
+                   a.abf, b);
 }
 
 hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
@@ -307,7 +309,7 @@ hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
 // step, two with the wider feature rows.
 // TEX = false: the texture factor stays out of the sum (eq:joined forms):
 // no feature stream, no FP8 products, only the location and colour terms.
-template <int KSTEPS, bool TEX>
+template <int KSTEPS, bool TEX, bool LIST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 ? 4 : 2)))
 void k_parzen_mfma(ParzenFastArgs a) {
     constexpr int RB = kParzenRB;
@@ -328,6 +330,8 @@ void k_parzen_mfma(ParzenFastArgs a) {
     // and per lane the pixels (bit 4 rb + r) whose sums overflowed
     __shared__ int s_ovf;
     __shared__ uint8_t s_ovp[4][64];
+    // per wave, lane and pixel (4 rb + r): how often the reference was raised
+    __shared__ uint32_t s_nraise[4][64];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, jl = lane & 15;
@@ -401,9 +405,21 @@ void k_parzen_mfma(ParzenFastArgs a) {
         const int c0 = a.meta[lab], c1 = a.meta[lab + 1];
         const int last_steps = a.meta[2 * a.L + 1 + lab];  // 16-sample steps of the last chunk
         const int tile = grp * 4 + wave;
+        // slots of the tile that hold a pixel (fast_slot_row): on the tile
+        // grid those inside the image, on a list the first qlim
         const bool tile_ok = tile < a.ntiles;
         const int ty_t = tile_ok ? tile / a.tiles_x : 0;
         const int x0 = (tile_ok ? tile - ty_t * a.tiles_x : 0) * 8, y0 = ty_t * 2 * RB;
+        int qlim = 0;
+        if constexpr (LIST) {
+            const int64_t rem = a.nlist - (int64_t)tile * kTilePix;
+            qlim = rem < 0 ? 0 : rem > kTilePix ? kTilePix : (int)rem;
+        }
+        auto slot_ok = [&](int rb, int r) {
+            if constexpr (LIST) return (2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r < qlim;
+            const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
+            return tile_ok && px < a.W && py < a.H;
+        };
 
         // Async copy of chunk c into a buffer pair.
         // (The lane's byte offset is rebuilt at every copy: held across the
@@ -427,9 +443,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
         issue(c0, s_feat0, s_rec0);
 
         // ---- pixel colours (scaled) and coefficients of this label (log2
-        // units): lane holds pixels (rb, r) -> (x0 + 4(g&1) + r, y0 + 2rb + (g>>1)),
-        // the rows 4g + r of the MFMA result blocks; both arrays are tiled
-        // [tile][kTilePix] with the same in-tile order
+        // units): lane holds the tile's slots (rb, r) -> (2rb + (g>>1)) * 8 +
+        // 4(g&1) + r, the rows 4g + r of the MFMA result blocks (on the tile
+        // grid the pixel (x0 + 4(g&1) + r, y0 + 2rb + (g>>1))); both arrays
+        // are tiled [tile][kTilePix] with the same slot order
         const float4 *pt = a.pix4 + (int64_t)tile * kTilePix;
         const float4 *cf = a.coef + (int64_t)lab * coef_label_stride + (int64_t)tile * kTilePix;
         float pr[RB][4], pg[RB][4], pb[RB][4];
@@ -440,8 +457,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ti = (2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r;
-                const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
-                const bool v = tile_ok && px < a.W && py < a.H;
+                const bool v = slot_ok(rb, r);
                 anyvalid |= v;
                 const float4 c = pt[ti];
                 pr[rb][r] = c.x;
@@ -481,6 +497,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
         bool item_bad = __ballot(weak) != 0ull;
         if (item_bad) active = false;
         bool ovf_wave = false;  // this wave's sums overflowed in the last pass
+        s_nraise[wave][lane] = 0u;
 
         float S[RB][4];
 #pragma unroll
@@ -597,7 +614,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
         // (log2 units) keeps every term of that size below 2^48 and loses only
         // terms below 2^-122 of it; the waves that overflowed compute the item
         // again (the others keep their sums and only help stream the chunks),
-        // up to kRetries times before the item goes to the exact kernel.
+        // up to kRetries times before the item goes to the exact kernel.  Every
+        // pixel of such a wave starts again from its own first reference less
+        // kRaise per overflow of its own, so its result does not depend on the
+        // pixels it shares the wave with.
         for (int attempt = 0;; ++attempt) {
             for (int c = c0; c < c1; c += 2) {
                 process(c, s_feat0, s_rec0, s_feat1, s_rec1);
@@ -616,13 +636,22 @@ void k_parzen_mfma(ParzenFastArgs a) {
             active = ovf_wave;
             if (ovf_wave) {
                 const uint32_t ob = s_ovp[wave][lane];
+                // raise counts, four bits per pixel (at most kRetries)
+                uint32_t nr = s_nraise[wave][lane];
+                int al = lane;
+                __asm__ volatile("" : "+v"(al));
+                const float4 *cr = a.coef + (int64_t)lab * coef_label_stride + (int64_t)tile * kTilePix +
+                                   (((al >> 5) * 8 + ((al >> 4) & 1) * 4));
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
+                        const int j = 4 * rb + r;
+                        nr += ((ob >> j) & 1u) << (4 * j);
                         S[rb][r] = 0.0f;
-                        if (ob & (1u << (4 * rb + r))) nR[rb][r] -= kRaise;
+                        nR[rb][r] = cr[16 * rb + r].z - kRaise * (float)((nr >> (4 * j)) & 15u);
                     }
+                s_nraise[wave][lane] = nr;
             }
             ovf_wave = false;
             issue(c0, s_feat0, s_rec0);
@@ -643,9 +672,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
                     float sp = S[rb][r];
 #pragma unroll
                     for (int off = 1; off < 16; off <<= 1) sp += __shfl_xor(sp, off);
-                    const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
-                    const bool v = tile_ok && px < a.W && py < a.H;
-                    if (v && !(sp <= 0x1p126f && sp > 0.0f)) bad = true;
+                    if (slot_ok(rb, r) && !(sp <= 0x1p126f && sp > 0.0f)) bad = true;
                     if (jl == 4 * rb + r) {
                         Rw = Rm;
                         Sw = sp;
@@ -661,11 +688,13 @@ void k_parzen_mfma(ParzenFastArgs a) {
         }
         if (jl < 4 * RB) {
             const int rb = jl >> 2, r = jl & 3;
-            const int px = x0 + 4 * (g & 1) + r, py = y0 + 2 * rb + (g >> 1);
-            if (tile_ok && px < a.W && py < a.H) {
-                const double K = (double)cf[(2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r].w;
+            const int ti = (2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r;
+            if (slot_ok(rb, r)) {
+                const int64_t row = LIST ? (int64_t)tile * kTilePix + ti
+                                         : (int64_t)(y0 + 2 * rb + (g >> 1)) * a.W + x0 + 4 * (g & 1) + r;
+                const double K = (double)cf[ti].w;
                 const double lg = kLn2F * ((double)Rw + (double)__builtin_amdgcn_logf(Sw)) + K;
-                a.loglik[((int64_t)py * a.W + px) * a.L + lab] = (float)lg;
+                a.loglik[row * a.L + lab] = (float)lg;
             }
         }
     }
@@ -675,27 +704,32 @@ void k_parzen_mfma(ParzenFastArgs a) {
     }
 }
 
-template <int KSTEPS, bool TEX>
+template <int KSTEPS, bool TEX, bool LIST>
 static hipError_t launch_mfma_k(const LaunchCtx &lc, const ParzenFastArgs &a) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS, TEX>, 256, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS, TEX, LIST>, 256, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     int64_t blocks = (int64_t)lc.num_cu * per_cu;
     const int64_t items = (int64_t)a.ngroups * a.L;
     if (blocks > items) blocks = items;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_parzen_mfma<KSTEPS, TEX>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
+    hipLaunchKernelGGL((k_parzen_mfma<KSTEPS, TEX, LIST>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a) {
-    if (!a.texture) return launch_mfma_k<1, false>(lc, a);
+template <bool LIST>
+static hipError_t launch_mfma_list(const LaunchCtx &lc, const ParzenFastArgs &a) {
+    if (!a.texture) return launch_mfma_k<1, false, LIST>(lc, a);
     switch (a.ksteps) {
-        case 1: return launch_mfma_k<1, true>(lc, a);
-        case 2: return launch_mfma_k<2, true>(lc, a);
-        default: return launch_mfma_k<3, true>(lc, a);
+        case 1: return launch_mfma_k<1, true, LIST>(lc, a);
+        case 2: return launch_mfma_k<2, true, LIST>(lc, a);
+        default: return launch_mfma_k<3, true, LIST>(lc, a);
     }
+}
+
+hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a) {
+    return a.list ? launch_mfma_list<true>(lc, a) : launch_mfma_list<false>(lc, a);
 }
 
 }  // namespace cs

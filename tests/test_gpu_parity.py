@@ -481,3 +481,75 @@ def test_loglik_overflow_retry_on_matrix_core_path(ctx):
     st = ctx.last_loglik_stats()
     assert st["overflow_tiles"] > 0, st
     assert st["exact_tiles"] == 0, st
+
+
+def _list_case():
+    return make_workload("list", H=40, W=56, R=4, p=5, k=40, seed=31, per_region=20)
+
+
+@pytest.mark.parametrize("n", [1023, 1024, 1061])
+def test_loglik_pixel_list_routes(ctx, n):
+    """Pixel subsets below 1024 entries take the exact kernel, from 1024 on the
+    matrix-core kernel in tiles of 32 consecutive entries (1024: 32 whole
+    tiles; 1061: a ragged last tile); duplicates and the corner pixels
+    included.  On the matrix-core path every row equals the full-image
+    result of its pixel bit for bit."""
+    w = _list_case()
+    masks, _, _ = oracle.full_masks(w)
+    rng = np.random.default_rng(n)
+    pix = rng.integers(0, w.N, n).astype(np.int32)
+    pix[:4] = [0, w.N - 1, 7, 7]
+    got, ref = _loglik_both(ctx, w, masks, pix=pix)
+    _ll_check(got, ref)
+    st = ctx.last_loglik_stats()
+    if n < 1024:
+        assert st == {"rescaled_chunks": 0, "overflow_tiles": 0, "exact_tiles": 0}
+        return
+    assert st["exact_tiles"] == 0, st
+    full, _ = _loglik_both(ctx, w, masks)
+    assert np.array_equal(got, full[pix])
+
+
+def test_loglik_pixel_list_overflow_retry(ctx):
+    """The overflow-retry construction as a pixel list (every pixel three times
+    in shuffled order): the overflowing sums are computed again on the
+    matrix-core path, and each row equals the full-image row of its pixel bit
+    for bit although its wave companions differ."""
+    H, W = 16, 24
+    rgb = np.full((3, H, W), 0.5, np.float32)
+    bad = [(r, c) for r in range(6, 10) for c in range(7, 17)]
+    for r, c in bad:
+        rgb[:, r, c] = 1.3
+    pixs = [r * W + c for r, c in bad]
+    pixs[5] = 0
+    pixs[15] = H * W - 1
+    w = make_workload("retry_list", H=H, W=W, R=1, p=3, k=8, seed=1, per_region=2)
+    w.rgb = rgb
+    w.sample_pix = np.array(pixs, np.int32)
+    w.sample_label = np.zeros(len(pixs), np.int32)
+    w.L = 1
+    w.k = 8
+    masks = np.zeros((H * W, 1), np.uint64)
+    pix = np.random.default_rng(4).permutation(np.tile(np.arange(H * W, dtype=np.int32), 3))
+    got, ref = _loglik_both(ctx, w, masks, pix=pix)
+    _ll_check(got, ref)
+    st = ctx.last_loglik_stats()
+    assert st["overflow_tiles"] > 0 and st["exact_tiles"] == 0, st
+    full, _ = _loglik_both(ctx, w, masks)
+    assert np.array_equal(got, full[pix])
+
+
+@pytest.mark.parametrize("listed", [False, True], ids=["grid", "list"])
+def test_loglik_exact_fixup_on_matrix_core_path(ctx, listed):
+    """A spatial bandwidth so wide that the padding samples of the stream
+    (parked 2^100 away) could reach the sum: every item is handed to the exact
+    two-pass kernel, on the tile grid and on a pixel list."""
+    w = _list_case()
+    masks, _, _ = oracle.full_masks(w)
+    pix = None
+    if listed:
+        pix = np.random.default_rng(8).integers(0, w.N, 1100).astype(np.int32)
+    got, ref = _loglik_both(ctx, w, masks, pix=pix, rho_floor=1e10)
+    _ll_check(got, ref)
+    st = ctx.last_loglik_stats()
+    assert st["exact_tiles"] > 0, st
