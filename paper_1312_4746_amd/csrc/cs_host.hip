@@ -829,13 +829,13 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
     const size_t o_nn = cv.take(sizeof(int32_t) * (size_t)L * N);
     const size_t o_edt = cv.take(edt_scratch_bytes(H, W, L));
     // matrix-core path (its exact integer location product needs positions
-    // below 2048): FP8 sample features, records, fix-up queue.  The full image
+    // below 2048): FP6 sample features, records, fix-up queue.  The full image
     // goes in 8 x 4 pixel tiles; a pixel subset of at least kListFastMin
     // entries in tiles of kTilePix consecutive entries (below that the exact
     // kernel, whose set-up is lighter, takes it).
     const bool fast = W <= 2048 && H <= 2048 && (pix_subset == nullptr || npix >= kListFastMin);
     const bool listed = fast && pix_subset != nullptr;
-    const int KP = (k + 4 + 127) / 128 * 128;
+    const int KP = 128 * tex_steps(k);  // bytes of a sample's feature row (32 per lane group and step)
     const int tiles_x = listed ? 1 : (W + 7) / 8;
     const int64_t ntiles = listed ? (npix + kTilePix - 1) / kTilePix
                                   : (int64_t)tiles_x * ((H + 2 * kParzenRB - 1) / (2 * kParzenRB));

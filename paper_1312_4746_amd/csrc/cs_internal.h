@@ -22,6 +22,12 @@ constexpr int kParzenRB = 2;
 constexpr int kParzenQueues = 8;
 constexpr int kQueueStride = 32;  // unsigned ints
 constexpr int kTilePix = 8 * 2 * kParzenRB;
+// Texture features of the matrix-core Parzen path (FP6 dot product of the
+// TSM, see k_parzen_mfma.hip): the k mask bits, then tex_digits(k) + 1 slots
+// for |A| and as many for |B|; 128 features per MFMA step.
+__host__ __device__ constexpr int tex_digits(int k) { return (k / 7 + 6) / 7; }
+__host__ __device__ constexpr int tex_features(int k) { return k + 2 * tex_digits(k) + 2; }
+__host__ __device__ constexpr int tex_steps(int k) { return (tex_features(k) + 127) / 128; }
 // Smallest pixel subset that the matrix-core Parzen path takes.
 constexpr int64_t kListFastMin = 1024;
 
@@ -294,12 +300,12 @@ struct StreamSegs {
 struct ParzenFastArgs {
     const float *rgb;
     const uint64_t *masks;
-    const uint8_t *feat;   // Mpad x 128*ksteps FP8 sample features (swizzled rows)
+    const uint8_t *feat;   // Mpad x 128*ksteps FP6 sample features (swizzled rows, 32 B per 32 features)
                            // (positions below 2048: the location product is exact)
     const float *rec;      // per chunk of 64 slots: BF16 location pieces (2 x 1 KiB), colours (1 KiB)
     const float4 *coef;    // tiled: [label][group*4 + tile][kTilePix] {nA, nB, -R, K}
     const float4 *pix4;    // tiled: [group*4 + tile][kTilePix] {scaled r, g, b, |A|}
-    const uint32_t *aop;   // [tile][row block][step][lane][8]: FP8 texture operands
+    const uint32_t *aop;   // [tile][row block][step][lane][8]: FP6 texture operands (6 of 8 dwords)
     const uint8_t *abf;    // [tile][row block][lane][16 B]: BF16 location operands
     float *loglik;
     unsigned int *work_counter;  // kParzenQueues counters, kQueueStride apart, zero at launch
@@ -308,7 +314,7 @@ struct ParzenFastArgs {
     int fix_cap;
     int H, W, L, k, ksteps;
     int tiles_x, ntiles, ngroups;
-    int texture;           // 0: texture factor out of the sum (no FP8 products)
+    int texture;           // 0: texture factor out of the sum (no FP6 products)
     int lblock;            // labels per block of the work order (1..L)
     const int32_t *list;   // pixel list (tile slots are its entries) or null (tile grid)
     int64_t nlist;
@@ -320,7 +326,7 @@ struct ParzenFastArgs {
     int meta[3 * kMaxLabels + 1];
 };
 // The full-image path's per-call preparation (one launch): the sample stream
-// (FP8 features and per-chunk records), the tiled pixel records and the pixel
+// (FP6 features and per-chunk records), the tiled pixel records and the pixel
 // operands of both MFMAs.
 struct PrepArgs {
     const SampleRec *recs;

@@ -3,15 +3,16 @@
 // bandwidth; Sec. 2 texture similarity inside the sum; Sec. 3.2 data term).
 //
 // The texture similarity of a pixel x and a sample y is the Hamming distance
-// of their co-support masks, TSM = |A| + |B| - 2 |A n B|.  Its sample-dependent
-// part |B| - 2 |A n B| is a dot product of two short feature vectors, so a
-// whole 16-pixel x 16-sample block of it is one MFMA:
-// v_mfma_scale_f32_16x16x128_f8f6f4 with FP8 (E4M3) operands and unit scales.
-// Pixel features: mask bit j in {0, 1} for j < k, then [1, 1, 16 floor(|A|/16),
-// |A| mod 16]; sample features: -2 x bit j, then [16 floor(|B|/16), |B| mod 16,
-// 1, 1].  The product is the whole TSM.  Every operand is an exactly
-// representable FP8 value and every partial sum an integer below 2^10, so the
-// FP32 accumulator holds it exactly.
+// of their co-support masks, TSM = |A| + |B| - 2 |A n B|: a dot product of two
+// short integer feature vectors, so a whole 16-pixel x 16-sample block of it
+// is one matrix-core product, v_mfma_scale_f32_16x16x128_f8f6f4 with FP6
+// (E2M3) operands and unit scales.  Pixel features: mask bit j in {0, 1} for
+// j < k, then the base-7 digits of |A| (D slots of values 0..7 whose sum
+// times 7 is 7 floor(|A|/7)), |A| mod 7, D sevens and a one; sample features:
+// -2 x bit j, then D sevens, a one, the digits of |B| and |B| mod 7.  The
+// product is the whole TSM.  Every operand is an integer in -7..7, exactly
+// representable in E2M3, and every partial sum an integer below 2^10, so the
+// FP32 accumulator holds it exactly; FP6 operands run at twice the FP8 rate.
 //
 // The location term nA |p - s|^2 needs the integer Q = |p - s|^2 = |p|^2 -
 // 2 p.s + |s|^2 of two pixel positions.  With every coordinate below 2048 each
@@ -79,19 +80,45 @@ constexpr float kRaise = 170.0f; // reference raise per retry (log2 units)
 // BF16 bit pattern of a float that BF16 holds exactly.
 __device__ __forceinline__ short bf16_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
 
-// E4M3 (bias 7) bit pattern of an integer 0..256 that is exactly representable
-// (0..16 and multiples of 16 up to 256).
-__device__ __forceinline__ uint32_t fp8_of_int(uint32_t v) {
-    if (v == 0) return 0u;
-    const int e = 31 - __clz(v);
-    const uint32_t m = ((v << 3) >> e) & 7u;
-    return ((uint32_t)(e + 7) << 3) | m;
+// E2M3 (bias 1) bit pattern of an integer -7..7 (all exactly representable).
+__device__ __forceinline__ uint32_t fp6_of_int(int v) {
+    const uint32_t a = (uint32_t)(v < 0 ? -v : v);
+    // 0, 1, 2, 3 = 1.5 x 2, 4, 5 = 1.25 x 4, 6 = 1.5 x 4, 7 = 1.75 x 4
+    const uint32_t code = (0x1E1C1A1814100800ull >> (8 * a)) & 0x3Fu;
+    return code | (v < 0 ? 0x20u : 0u);
 }
 
-// Spread the 4 bits of a nibble into the 4 bytes of a word, each byte 0 or b:
-// the copies nib << 7i do not overlap, so bit i lands alone at bit 8i.
-__device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib, uint32_t b) {
-    return ((nib * 0x00204081u) & 0x01010101u) * b;
+// Texture feature f of a pixel (PIX) or a sample with co-support bits `bits`
+// (bit j of word j / 32) and |co-support| c: see the header.
+template <bool PIX>
+__device__ __forceinline__ int tex_feature(int f, int k, const uint32_t *bits, uint32_t c) {
+    const int D = tex_digits(k);
+    if (f < k) {
+        const int b = (int)((bits[f >> 5] >> (f & 31)) & 1u);
+        return PIX ? b : -2 * b;
+    }
+    f -= k;
+    const int q = (int)(c / 7u), r = (int)(c % 7u);
+    auto digit = [&](int s) { const int d = q - 7 * s; return d < 0 ? 0 : d > 7 ? 7 : d; };
+    if (f < D) return PIX ? digit(f) : 7;
+    if (f == D) return PIX ? r : 1;
+    f -= D + 1;
+    if (f < D) return PIX ? 7 : digit(f);
+    if (f == D) return PIX ? 1 : r;
+    return 0;
+}
+
+// The 32 FP6 codes of features f0 .. f0 + 31 packed as the lane operand of one
+// 16x16x128 step: feature f0 + v at bits 6v .. 6v + 5 of six dwords.
+template <bool PIX>
+__device__ __forceinline__ void tex_pack(int f0, int k, const uint32_t *bits, uint32_t c, uint32_t (&o)[6]) {
+    for (int d = 0; d < 6; ++d) o[d] = 0u;
+    for (int v = 0; v < 32; ++v) {
+        const uint32_t code = fp6_of_int(tex_feature<PIX>(f0 + v, k, bits, c));
+        const int b = 6 * v, d = b >> 5, sh = b & 31;
+        o[d] |= code << sh;
+        if (sh > 26) o[d + 1] |= code >> (32 - sh);
+    }
 }
 
 // Physical 16-byte slot of logical slot p in a sample row.  Rows are 128 B
@@ -102,7 +129,8 @@ __device__ __forceinline__ uint32_t nibble_bytes(uint32_t nib, uint32_t b) {
 __device__ __forceinline__ int swz(int p, int row) { return (p & ~7) | ((p & 7) ^ ((row >> 1) & 7)); }
 
 // Padded sample stream: for every padded slot s (label segments rounded up to
-// whole chunks), the FP8 feature row (swizzled) and its record.  The records
+// whole chunks), the FP6 feature row (swizzled; 32 bytes per 32-feature group,
+// six dwords used) and its record.  The records
 // of a chunk of 64 slots take 3 KiB, three planes of 64 x 16 B so that 16 lanes
 // reading 16 consecutive slots touch distinct LDS banks: the BF16 location
 // pieces for K 0..7 [1, 1, 1, sx_h, sx_l, sx_h, sx_l, sy_h] and K 8..15
@@ -161,26 +189,18 @@ __device__ __forceinline__ void stream_build(const SampleRec *recs, int k, int K
     rcol[2] = col[2];
     rcol[3] = 0.0f;
     uint32_t *fo = reinterpret_cast<uint32_t *>(feat + s * KP);
-    for (int p = 0; p < KP / 16; ++p) {  // logical 16-byte slot p holds features 16p..16p+15
-        uint32_t out4[4];
-        for (int q = 0; q < 4; ++q) {
-            const int f0 = 16 * p + 4 * q;
-            uint32_t val = 0;
-            if (real) {
-                if (f0 < 256) val = nibble_bytes((words[f0 >> 5] >> (f0 & 31)) & 0xFu, 0xC0u);  // -2.0
-                for (int b = 0; b < 4; ++b) {
-                    const int f = f0 + b;
-                    uint32_t byte = 0xFFFFFFFFu;
-                    if (f == k) byte = fp8_of_int(16u * (cnt >> 4));
-                    else if (f == k + 1) byte = fp8_of_int(cnt & 15u);
-                    else if (f == k + 2 || f == k + 3) byte = 0x38u;  // 1.0
-                    if (byte != 0xFFFFFFFFu) val = (val & ~(0xFFu << (8 * b))) | (byte << (8 * b));
-                }
-            }
-            out4[q] = val;
-        }
-        uint32_t *dst = fo + 4 * swz(p, row);
-        for (int q = 0; q < 4; ++q) dst[q] = out4[q];
+    for (int grp = 0; grp < KP / 32; ++grp) {  // features 32 grp .. 32 grp + 31: logical slots 2 grp, 2 grp + 1
+        uint32_t o[6] = {0, 0, 0, 0, 0, 0};
+        if (real) tex_pack<false>(32 * grp, k, words, cnt, o);
+        uint32_t *d0 = fo + 4 * swz(2 * grp, row), *d1 = fo + 4 * swz(2 * grp + 1, row);
+        d0[0] = o[0];
+        d0[1] = o[1];
+        d0[2] = o[2];
+        d0[3] = o[3];
+        d1[0] = o[4];
+        d1[1] = o[5];
+        d1[2] = 0u;
+        d1[3] = 0u;
     }
 }
 
@@ -213,9 +233,9 @@ __device__ __forceinline__ void pixel_tiles(const float *rgb, const uint64_t *ma
 // Pixel operands of the matrix-core path, built once per call: for every
 // padded tile, row block rb and lane (g, jl) of the MFMA operands, row jl is
 // the tile's slot (2 rb + (jl >> 3)) * 8 + (jl & 7) (fast_slot_row).
-//  * FP8 texture operand (32 B per lane and 128-feature step q): features
-//    32 (4q + g) .. +31, i.e. mask bits j < k, 1 at k and k+1, 16 floor(|A|/16)
-//    at k+2 and |A| mod 16 at k+3 (zero for pixels outside the image);
+//  * FP6 texture operand (32 B per lane and 128-feature step q, six dwords
+//    used): pixel features 128 q + 32 g .. + 31 (tex_feature; zero for empty
+//    slots);
 //  * BF16 location operand (16 B per lane): K 0..7 [|p|^2 pieces (3), -2 px
 //    pieces (2, each twice), -2 py high] for g = 0, K 8..15 [-2 py high, -2 py
 //    low (twice), 1, 1, 1, 1 (far term), 0] for g = 1, zeros for g >= 2.
@@ -236,28 +256,20 @@ __device__ __forceinline__ void pixel_operands(const uint64_t *masks, int H, int
     const int W64 = (k + 63) / 64;
     const uint32_t *mw = reinterpret_cast<const uint32_t *>(masks) + pix * 2 * W64;
     const int nw32 = (k + 31) / 32;
-    const uint32_t lastmask = (k & 31) ? (1u << (k & 31)) - 1u : ~0u;
+    uint32_t bits[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t cnt = 0;
     if (v)
-        for (int w = 0; w < nw32; ++w) cnt += __popc(mw[w] & (w == nw32 - 1 ? lastmask : ~0u));
-    // features k+2 and k+3 (the pixel's |A|): which lane group, step and byte
-    const int fa = k + 2, fb = k + 3;
+        for (int w = 0; w < nw32; ++w) {
+            const uint32_t m = mw[w] & (w == nw32 - 1 && (k & 31) ? (1u << (k & 31)) - 1u : ~0u);
+            bits[w] = m;
+            cnt += __popc(m);
+        }
     for (int q = 0; q < ksteps; ++q) {
-        const int wi = 4 * q + g;  // the lane's 32-feature slice is mask word wi
-        const int rel = k - 32 * wi;
-        const uint32_t lowm = wi < nw32 - 1 ? ~0u : wi == nw32 - 1 ? lastmask : 0u;
-        const uint32_t spec = (rel >= 0 && rel < 32 ? 1u << rel : 0u) | (rel + 1 >= 0 && rel + 1 < 32 ? 1u << (rel + 1) : 0u);
-        const uint32_t m = lowm ? mw[wi] & lowm : 0u;
-        const uint32_t ext = v ? (m | spec) : 0u;
-        uint32_t out[8];
-        for (int d = 0; d < 8; ++d) out[d] = nibble_bytes((ext >> (4 * d)) & 0xFu, 0x38u);  // 1.0 per set bit
-        if (v && ((fa >> 5) & 3) == g && (fa >> 7) == q)
-            out[(fa & 31) >> 2] |= fp8_of_int(16u * (cnt >> 4)) << (8 * (fa & 3));
-        if (v && ((fb >> 5) & 3) == g && (fb >> 7) == q)
-            out[(fb & 31) >> 2] |= fp8_of_int(cnt & 15u) << (8 * (fb & 3));
+        uint32_t o[6] = {0, 0, 0, 0, 0, 0};
+        if (v) tex_pack<true>(128 * q + 32 * g, k, bits, cnt, o);
         uint4 *dst = reinterpret_cast<uint4 *>(aop + (((int64_t)tr * ksteps + q) * 64 + lane) * 8);
-        dst[0] = make_uint4(out[0], out[1], out[2], out[3]);
-        dst[1] = make_uint4(out[4], out[5], out[6], out[7]);
+        dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
+        dst[1] = make_uint4(o[4], o[5], 0u, 0u);
     }
     const uint32_t p2 = (uint32_t)(px * px + py * py), X = 2u * (uint32_t)px, Y = 2u * (uint32_t)py;
     const float xh = -(float)(X & ~0xFFu), xl = -(float)(X & 0xFFu);
@@ -308,7 +320,7 @@ hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
 // Register budget: four waves per SIMD (128 VGPRs) with one 128-feature MFMA
 // step, two with the wider feature rows.
 // TEX = false: the texture factor stays out of the sum (eq:joined forms):
-// no feature stream, no FP8 products, only the location and colour terms.
+// no feature stream, no FP6 products, only the location and colour terms.
 template <int KSTEPS, bool TEX, bool LIST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 ? 4 : 2)))
 void k_parzen_mfma(ParzenFastArgs a) {
@@ -475,7 +487,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
         const bool wave_valid = active;
 
         // ---- pixel rows of both MFMAs (built once per call by
-        // k_pixel_operands): the FP8 texture operand into registers, the BF16
+        // k_pixel_operands): the FP6 texture operand into registers, the BF16
         // location operand straight into LDS (read at every step)
         i32x8 Aop[RB][KSTEPS];
 #pragma unroll
@@ -483,12 +495,12 @@ void k_parzen_mfma(ParzenFastArgs a) {
             if constexpr (TEX) {
 #pragma unroll
                 for (int q = 0; q < KSTEPS; ++q) {
-                    // 8 dwords (32 bytes) per lane
+                    // six dwords (FP6) of the lane's 32-byte slot
                     const uint4 *src = reinterpret_cast<const uint4 *>(
                         a.aop + ((((int64_t)tile * RB + rb) * KSTEPS + q) * 64 + lane) * 8);
-                    const uint4 lo4 = src[0], hi4 = src[1];
-                    Aop[rb][q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
-                                       (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
+                    const uint4 lo4 = src[0];
+                    const uint2 hi2 = *reinterpret_cast<const uint2 *>(src + 1);
+                    Aop[rb][q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w, (int)hi2.x, (int)hi2.y, 0, 0};
                 }
             }
             const uint8_t *bsrc = a.abf + (((int64_t)tile * RB + rb) * 64 + lane) * 16;
@@ -528,9 +540,8 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
                     for (int q = 0; q < KSTEPS; ++q) {
                         const uint4 lo4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][0]);
-                        const uint4 hi4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][1]);
-                        Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w,
-                                       (int)hi4.x, (int)hi4.y, (int)hi4.z, (int)hi4.w};
+                        const uint2 hi2 = *reinterpret_cast<const uint2 *>(Fs + foff[q][1]);
+                        Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w, (int)hi2.x, (int)hi2.y, 0, 0};
                     }
                 }
                 const s16x8 Bbf = *reinterpret_cast<const s16x8 *>(Rs + loff);
@@ -542,8 +553,9 @@ void k_parzen_mfma(ParzenFastArgs a) {
                     if constexpr (TEX) {
 #pragma unroll
                         for (int q = 0; q < KSTEPS; ++q)
+                            // formats 2, 2: both operands FP6 E2M3; unit scales
                             T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(Aop[rb][q], Bop[q], T[rb],
-                                                                                      0, 0, 0, 127, 0, 127);
+                                                                                      2, 2, 0, 127, 0, 127);
                     }
                     Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, s_abf[wave][rb][al]),
                                                                     __builtin_bit_cast(bf16x8, Bbf),

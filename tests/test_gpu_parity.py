@@ -417,10 +417,11 @@ def test_loglik_wide_image_exact_route(ctx):
     assert st == {"rescaled_chunks": 0, "overflow_tiles": 0, "exact_tiles": 0}
 
 
-@pytest.mark.parametrize("k", [123, 124, 125, 126])
+@pytest.mark.parametrize("k", [6, 7, 119, 120, 121, 124, 125, 244, 245])
 def test_loglik_feature_width_boundary(ctx, k):
-    """k + 4 features (the mask bits, two |B| and two |A| features) fill one
-    128-wide FP8 step up to k = 124 and take two from k = 125."""
+    """The texture features (k mask bits, then D + 1 slots each for |A| and |B|,
+    D = ceil(floor(k/7) / 7) base-7 digits) fill one 128-wide FP6 step up to
+    k = 120, two up to k = 244 and three above; k < 7 needs no digit."""
     w = make_workload(f"kb{k}", H=18, W=27, R=3, p=5, k=k, seed=k, per_region=8)
     masks, _, _ = oracle.full_masks(w)
     got, ref = _loglik_both(ctx, w, masks)
