@@ -62,6 +62,72 @@ __device__ __noinline__ inline void patch_s64(const float *rgb, int H, int W, in
     for (int t = 0; t < n; ++t) s[t] = s[t] / nu;
 }
 
+// Exact FP64 a_j = sum_t O_jt s_t of pixel pix (om = row j of O): the
+// normalised Gaussian-masked gray patch rebuilt from the image in the
+// oracle's operation order, q_t = w_t g_t, s_t = (q_t - mu) / sqrt(nu2) (0 when
+// nu2 = 0), every sum sequential in t and no contraction.  mu = sum_t q_t / n
+// and nu2 = sum_t (q_t - mu)^2 come from stats[2 pix], stats[2 pix + 1] (the
+// analysis kernel's exact values, the same operations) when stats is
+// non-null, else they are computed here.  One lane per entry: loads are
+// issued eight elements at a time.
+__device__ __noinline__ inline double exact_entry(const float *rgb, int H, int W, int p, const double *wmask,
+                                                  const float *om, int64_t pix, const double *stats) {
+#pragma clang fp contract(off)
+    const int64_t N = (int64_t)H * W;
+    const int h = (p - 1) / 2, n = p * p;
+    const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
+    auto q_at = [&](int t) {
+        const int u = t / p, v = t - u * p;
+        const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + v - h, W);
+        return wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
+    };
+    double mu, nu2;
+    if (stats) {
+        mu = stats[2 * pix];
+        nu2 = stats[2 * pix + 1];
+    } else {
+        double sum = 0.0;
+        for (int t0 = 0; t0 < n; t0 += 8) {
+            double qv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) qv[u] = q_at(t0 + u < n ? t0 + u : n - 1);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (t0 + u < n) sum = sum + qv[u];
+        }
+        mu = sum / (double)n;
+        nu2 = 0.0;
+        for (int t0 = 0; t0 < n; t0 += 8) {
+            double qv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) qv[u] = q_at(t0 + u < n ? t0 + u : n - 1);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (t0 + u < n) {
+                    const double z = qv[u] - mu;
+                    nu2 = nu2 + z * z;
+                }
+        }
+    }
+    if (nu2 == 0.0) return 0.0;
+    const double nu = sqrt(nu2);
+    double acc = 0.0;
+    for (int t0 = 0; t0 < n; t0 += 8) {
+        double qv[8];
+        float ov[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + u < n ? t0 + u : n - 1;
+            qv[u] = q_at(t);
+            ov[u] = om[t];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t0 + u < n) acc = acc + (double)ov[u] * ((qv[u] - mu) / nu);
+    }
+    return acc;
+}
+
 // Per-row decision margin: the given absolute margin when >= 0, else the
 // proven bound coef * ||O_j||_2 of the rounded analysed vector (unit-norm
 // patch) with a relative safety factor for the FP64 evaluation of the bound

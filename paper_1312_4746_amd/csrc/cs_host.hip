@@ -378,8 +378,14 @@ int cs_set_check_finite(cs_ctx *ctx, int on) {
     return CS_OK;
 }
 
-int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
-                       const float *omega, int k, int precision, float *alpha) {
+}  // extern "C"
+
+namespace {
+
+// The analysis of cs_analyze_patches; pstats (N x 2, device) receives the
+// exact patch statistics when non-null.
+int analyze_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma, const float *omega, int k,
+                  int precision, float *alpha, double *pstats) {
     if (!ctx) return CS_ERR_ARG;
     int rc = check_patch_args(ctx, rgb, H, W, p, mask_sigma, omega, k, precision);
     if (rc) return rc;
@@ -398,9 +404,19 @@ int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, doubl
     a.wmask = ctx->wmask;
     a.omega = omega;
     a.alpha = alpha;
+    a.pstats = pstats;
     Timed t(ctx, "analyze");
     HIP_TRY(launch_analyze(lc_of(ctx), a, precision));
     return CS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cs_analyze_patches(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma,
+                       const float *omega, int k, int precision, float *alpha) {
+    return analyze_stage(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha, nullptr);
 }
 
 }  // extern "C"
@@ -414,7 +430,7 @@ namespace {
 int cosupport_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, const float *omega, int k,
                     int precision, const float *alpha, double tau, const double *tau_dev, double margin,
                     uint64_t *masks, unsigned long long *cnt, double *mmax, float *t_in, float *t_out,
-                    double *marg) {
+                    double *marg, const double *pstats = nullptr) {
     const LaunchCtx lc = lc_of(ctx);
     const int n = p * p;
     {
@@ -425,7 +441,7 @@ int cosupport_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, const fl
     if (alpha) {
         Timed t(ctx, "cosupport");
         HIP_TRY(launch_mask_alpha(lc, alpha, (int64_t)H * W, k, t_in, t_out, tau, tau_dev, rgb, H, W, p,
-                                  ctx->wmask, omega, masks, cnt));
+                                  ctx->wmask, omega, masks, cnt, pstats));
     } else {
         AnalyzeArgs a{};
         a.rgb = rgb;
@@ -491,7 +507,7 @@ int median_source(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mas
 // gather and the exact stage run again (a retry with a larger cap).
 int tau_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, const float *omega, int k, const float *a32,
               double frac, int64_t cap, bool first, unsigned int *hist, TauState *st, double *mmax,
-              unsigned long long *parts, double *tau_out) {
+              unsigned long long *parts, double *tau_out, const double *pstats = nullptr) {
     const LaunchCtx lc = lc_of(ctx);
     const int64_t count = (int64_t)H * W * k;
     const int n = p * p;
@@ -510,7 +526,8 @@ int tau_stage(cs_ctx *ctx, const float *rgb, int H, int W, int p, const float *o
     }
     {
         Timed t(ctx, "tau_exact");
-        HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, cap, vals, frac, st, parts, tau_out));
+        HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, cap, vals, frac, st, parts, tau_out,
+                           pstats));
     }
     return CS_OK;
 }
@@ -600,7 +617,7 @@ int cs_cosupport_noalloc(cs_ctx *ctx, const float *rgb, int H, int W, int p, dou
                               mmax, cnt));
     if (alpha) {
         HIP_TRY(launch_mask_alpha(lc, alpha, (int64_t)H * W, k, t_in, t_out, tau, nullptr, rgb, H, W, p, wmask,
-                                  omega, masks, cnt));
+                                  omega, masks, cnt, nullptr));
     } else {
         AnalyzeArgs a{};
         a.rgb = rgb;
@@ -689,7 +706,24 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
         tw.carve(cv);
         const size_t o_marg = cv.take(sizeof(double) * k);
         const size_t o_hist3 = cv.take(sizeof(unsigned int) * 3 * kHistBins);
+        const size_t o_pst = cv.take(sizeof(double) * 2 * (size_t)H * W);
+        // per-wave list counts of the gather and the candidate regions' offsets
+        const size_t o_ccnt = cv.take(sizeof(unsigned int) * kMedianWavesMax);
+        const size_t o_dcnt = cv.take(sizeof(unsigned int) * kMedianWavesMax);
+        const size_t o_coff = cv.take(sizeof(unsigned long long) * kMedianWavesMax);
+        const size_t o_doff = cv.take(sizeof(unsigned long long) * kMedianWavesMax);
+        // compact lists (each up to kListCap entries, or count when smaller)
+        const int64_t lcap = count < kListCap ? count : kListCap;
+        const size_t o_ccomp = cv.take(sizeof(int64_t) * (size_t)lcap);
+        const size_t o_dcomp = cv.take(sizeof(int64_t) * (size_t)lcap);
         if ((rc = ensure_ws(ctx, cv.off))) return rc;
+        double *pst = (double *)(ctx->ws + o_pst);
+        unsigned int *ccnt = (unsigned int *)(ctx->ws + o_ccnt), *dcnt = (unsigned int *)(ctx->ws + o_dcnt);
+        FusedLists fl;
+        fl.coff = (unsigned long long *)(ctx->ws + o_coff);
+        fl.doff = (unsigned long long *)(ctx->ws + o_doff);
+        fl.ccomp = (int64_t *)(ctx->ws + o_ccomp);
+        fl.dcomp = (int64_t *)(ctx->ws + o_dcomp);
         // candidates, their FP64 values, listed mask entries (room for all)
         if ((rc = ensure_cand(ctx, (size_t)count * 24))) return rc;
         TauState *st = (TauState *)(ctx->ws + tw.o_st);
@@ -712,6 +746,7 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
             a.wmask = ctx->wmask;
             a.omega = omega;
             a.alpha = alpha;
+            a.pstats = pst;
             a.tau_st = st;
             a.tau_hist3 = hist3;
             a.tau_margins = marg;
@@ -727,38 +762,42 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
         }
         {
             Timed t(ctx, "cosupport");
-            HIP_TRY(median_mask_gather(lc, alpha, (int64_t)H * W, k, mmax, marg, frac, st, cand, count, parts, didx,
-                                       masks, hist3));
+            HIP_TRY(median_mask_gather(lc, alpha, (int64_t)H * W, k, mmax, marg, frac, st, cand, ccnt, parts, didx,
+                                       dcnt, masks, hist3));
+            HIP_TRY(list_compact(lc, median_gather_waves((int64_t)H * W), cand, ccnt, didx, dcnt, st, fl));
         }
         {
             Timed t(ctx, "tau_exact");
             HIP_TRY(tau_finish(lc, rgb, H, W, p, n, ctx->wmask, omega, k, cand, count, vals, frac, st, parts,
-                               tau_dev));
+                               tau_dev, pst, ccnt, &fl));
         }
         {
             Timed t(ctx, "cosupport_fix");
-            HIP_TRY(median_mask_finish(lc, alpha, rgb, H, W, p, ctx->wmask, omega, k, didx, marg, st, masks));
+            HIP_TRY(median_mask_finish(lc, alpha, rgb, H, W, p, ctx->wmask, omega, k, didx, dcnt, fl.dcomp, marg, st,
+                                       masks, pst));
         }
         return CS_OK;
     }
-    if ((rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha))) return rc;
-    const float *a32 = nullptr;
-    if ((rc = median_source(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha, &a32))) return rc;
     Carve cv;
     TauWs tw;
     tw.carve(cv);
     CosupportWs cw;
     cw.carve(cv, k);
+    const size_t o_pst = cv.take(sizeof(double) * 2 * (size_t)H * W);
     if ((rc = ensure_ws(ctx, cv.off))) return rc;
+    double *pst = (double *)(ctx->ws + o_pst);
+    if ((rc = analyze_stage(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha, pst))) return rc;
+    const float *a32 = nullptr;
+    if ((rc = median_source(ctx, rgb, H, W, p, mask_sigma, omega, k, precision, alpha, &a32))) return rc;
     TauState *st = (TauState *)(ctx->ws + tw.o_st);
     // room for every entry: the selection never needs the host
     rc = tau_stage(ctx, rgb, H, W, p, omega, k, a32, frac, count, true, (unsigned int *)(ctx->ws + tw.o_hist), st,
-                   (double *)(ctx->ws + tw.o_max), (unsigned long long *)(ctx->ws + tw.o_parts), tau_dev);
+                   (double *)(ctx->ws + tw.o_max), (unsigned long long *)(ctx->ws + tw.o_parts), tau_dev, pst);
     if (rc) return rc;
     rc = cosupport_stage(ctx, rgb, H, W, p, omega, k, precision, alpha, 0.0, &st->tau, margin, masks,
                          (unsigned long long *)(ctx->ws + cw.o_cnt), (double *)(ctx->ws + cw.o_max),
                          (float *)(ctx->ws + cw.o_tin), (float *)(ctx->ws + cw.o_tout),
-                         (double *)(ctx->ws + cw.o_marg));
+                         (double *)(ctx->ws + cw.o_marg), pst);
     return rc;
 }
 

@@ -81,6 +81,7 @@ struct AnalyzeArgs {
     const float *t_out;   // k thresholds (|a| > t_out: out)
     double tau;
     unsigned long long *recomputed;  // device counter or null
+    double *pstats;       // N x 2 exact patch statistics (mean, squared norm) out, or null
     // optional: the first workgroup also sets up the median selection that
     // follows (state, the three digit histograms, per-row margins); null st:
     // none
@@ -107,7 +108,7 @@ hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N,
                              const float *t_out, double tau, const double *tau_dev, const float *rgb, int H,
                              int W, int p,
                              const double *wmask, const float *omega, uint64_t *masks,
-                             unsigned long long *recomputed);
+                             unsigned long long *recomputed, const double *pstats);
 
 // Per-row thresholds t_in/t_out = tau -/+ margin_j, rounded outward to float.
 // margin < 0 selects the proven bound coef * ||O_j||_2 + tiny; writes the
@@ -135,6 +136,10 @@ struct TauState {
     double tau;                   // frac * median
     unsigned long long n_d;       // deferred mask entries (fused co-support pass)
     unsigned long long n_r;       // deferred entries for the FP64 decision
+    // fused co-support pass: its waves and the entries of each wave's region
+    // of the candidate and deferred lists (wave w writes from w * rg_size on)
+    unsigned int rg_waves;
+    long long rg_size;
 };
 // Upper bound of the workgroups of a candidate gather (per-workgroup counts);
 // the counts array is followed by kTauRank words for the ranks of short
@@ -169,10 +174,25 @@ hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
 // count is read on the device (at most cap are used; more leaves NaN).  tau
 // also goes to tau_out (device) when non-null.  parts holds kTauParts +
 // kTauRank words.
+// Compact forms of the fused co-support pass's per-wave lists: region
+// offsets (kMedianWavesMax words each) and lists of up to kListCap entries.
+constexpr int64_t kListCap = (int64_t)1 << 22;
+struct FusedLists {
+    unsigned long long *coff, *doff;
+    int64_t *ccomp, *dcomp;
+};
+// Scan of the region counts (totals into st->ncand, st->n_d) and the copy of
+// each list that fits kListCap into its compact array.
+hipError_t list_compact(const LaunchCtx &lc, int64_t nw, const int64_t *cand, const unsigned int *ccnt,
+                        const int64_t *didx, const unsigned int *dcnt, TauState *st, FusedLists fl);
+// pstats: the exact patch statistics of every pixel (N x 2) or null.  With
+// ccnt non-null the candidates come from the fused co-support pass (fl: its
+// compact list, or its per-wave regions of cand when it did not fit).
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
                       int64_t cap, double *vals, double frac, TauState *st, unsigned long long *parts,
-                      double *tau_out);
+                      double *tau_out, const double *pstats, const unsigned int *ccnt = nullptr,
+                      const FusedLists *fl = nullptr);
 // Device counters of a context that are zero between calls (each use resets
 // its own): [kCtrSampleCount] the sample-count workgroups done,
 // [kCtrNonFinite] the flag of the optional finite check of the inputs.
@@ -184,17 +204,23 @@ hipError_t launch_check_finite(const LaunchCtx &lc, const float *p, int64_t n, u
 // ---- co-support at frac * median|a| fused with the candidate gather
 // (k_cosupport_median.hip) ----
 // After the three digits: the candidate window and the masks of every entry
-// whose rounded |a| is clear of the tau interval by more than its row margin;
-// the others are listed in didx (room for N*k).
+// whose rounded |a| is clear of the tau interval by more than its row margin.
+// Each wave lists its candidates and the other undecided entries in its own
+// region of cand and didx (both with room for N*k entries; counts in ccnt and
+// dcnt, kMedianWavesMax words each), so the pass takes no global atomics.
+constexpr int kMedianWavesMax = 4 * kTauParts;
 hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N, int k,
                               const double *max_margin, const double *margins, double frac, TauState *st,
-                              int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
-                              uint64_t *masks, const unsigned int *hist3);
+                              int64_t *cand, unsigned int *ccnt, unsigned long long *parts, int64_t *didx,
+                              unsigned int *dcnt, uint64_t *masks, const unsigned int *hist3);
 // After the exact tau: the listed entries, decided in one launch (the rounded
 // value where it is clear of tau by the row margin, else in FP64).
 hipError_t median_mask_finish(const LaunchCtx &lc, const float *alpha, const float *rgb, int H, int W, int p,
                               const double *wmask, const float *omega, int k, const int64_t *didx,
-                              const double *margins, const TauState *st, uint64_t *masks);
+                              const unsigned int *dcnt, const int64_t *dcomp, const double *margins,
+                              const TauState *st, uint64_t *masks, const double *pstats);
+// The number of waves of median_mask_gather for N pixels.
+int64_t median_gather_waves(int64_t N);
 
 // ---- texture similarity (k_tsm.hip) ----
 hipError_t launch_tsm(const LaunchCtx &lc, const uint64_t *A, int64_t na, const uint64_t *B,

@@ -131,6 +131,11 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
         st_mu[i] = mu;
         st_nu2[i] = nu2;
         st_rinv[i] = nu2 == 0.0 ? 0.0 : 1.0 / sqrt(nu2);
+        if (a.pstats && i < valid_px) {
+            double *ps = a.pstats + 2 * ((int64_t)row * a.W + c0 + i);
+            ps[0] = mu;
+            ps[1] = nu2;
+        }
     }
     __syncthreads();
 
@@ -292,30 +297,41 @@ hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precisi
 // Co-support masks from stored analysed vectors (the same decision as the
 // analysis epilogue): bit j of pixel x is set when the rounded |a_j| is at most
 // t_in[j] and clear above t_out[j]; in between the entry is recomputed in FP64
-// from the exact patch (Sec. 2 co-support, Sec. 3.1 patch).  A wave owns
-// kMaskPx consecutive pixels, lane = row j within a 64-bit mask word, so the
-// loads are coalesced and each mask word is the ballot of one comparison.
-// The rare entries in between are resolved per pixel by the whole wave: the
-// pixel's exact patch is built in the wave's LDS slice (LDS accesses of one
-// wave complete in issue order, so the hand-offs between the lanes and lane
-// 0, which runs every sum in t order, need no barrier), then lane j
-// recomputes row j.
+// from the exact patch (Sec. 2 co-support, Sec. 3.1 patch).  A wave takes
+// blocks of kMaskPx consecutive pixels, lane = row j within a 64-bit mask
+// word, so the loads are coalesced and each mask word is the ballot of one
+// comparison.  The entries in between are resolved per pixel by the whole
+// wave: the pixel's exact normalised patch is built in the wave's LDS slice
+// (its mean and squared norm from the analysis when pstats is given, else
+// summed by lane 0 in t order; LDS accesses of one wave complete in issue
+// order, so the hand-offs need no barrier), then every lane recomputes all of
+// its rows j = 64 w + lane that are in between in one pass over the patch.
+// Persistent workgroups of kMaskWaves waves; with OML the FP32 operator is
+// staged in LDS once per workgroup, so the recompute reads it there.
 constexpr int kMaskPx = 8;
-template <int W64>
-__global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t N, int k,
-                                                     const float *t_in, const float *t_out, double tau,
-                                                     const double *tau_dev, const float *rgb, int H, int W,
-                                                     int p, const double *wmask, const float *omega,
-                                                     uint64_t *masks, unsigned long long *recomputed) {
+constexpr int kMaskWaves = 16;
+template <int W64, bool OML>
+__global__ __launch_bounds__(64 * kMaskWaves) void k_mask_alpha(const float *alpha, int64_t N, int k,
+                                                                 const float *t_in, const float *t_out, double tau,
+                                                                 const double *tau_dev, const float *rgb, int H,
+                                                                 int W, int p, const double *wmask,
+                                                                 const float *omega, uint64_t *masks,
+                                                                 unsigned long long *recomputed,
+                                                                 const double *pstats) {
 #pragma clang fp contract(off)
-    __shared__ double s_all[4][15 * 15];
+    extern __shared__ __align__(16) unsigned char smem[];
     if (tau_dev) tau = *tau_dev;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *s = s_all[wave];
     const int n = p * p, h = (p - 1) / 2;
+    double *s = reinterpret_cast<double *>(smem) + wave * n;  // this wave's patch
+    float *s_om = reinterpret_cast<float *>(smem + sizeof(double) * kMaskWaves * n);
+    if constexpr (OML) {
+        for (int idx = threadIdx.x; idx < k * n; idx += 64 * kMaskWaves) s_om[idx] = omega[idx];
+        __syncthreads();
+    }
     const int64_t NN = (int64_t)H * W;
-    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * kMaskPx;
-    if (p0 >= N) return;
+    // pixels per block: fewer for long masks (their ballots are held in SGPRs)
+    constexpr int PX = W64 >= 3 ? kMaskPx / 2 : kMaskPx;
     float tin[W64], tout[W64];
     uint64_t vmask[W64];
 #pragma unroll
@@ -326,11 +342,16 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
         tout[w] = jv ? t_out[j] : 0.0f;
         vmask[w] = __ballot(jv);
     }
+    unsigned long long nrec = 0;
+    const int64_t nblk = (N + PX - 1) / PX;
+    for (int64_t blk = (int64_t)blockIdx.x * kMaskWaves + wave; blk < nblk;
+         blk += (int64_t)gridDim.x * kMaskWaves) {
+    const int64_t p0 = blk * PX;
     // loads issued unconditionally (clamped indices, all in flight together),
     // padding replaced afterwards
-    float v[kMaskPx][W64];
+    float v[PX][W64];
 #pragma unroll
-    for (int i = 0; i < kMaskPx; ++i)
+    for (int i = 0; i < PX; ++i)
 #pragma unroll
         for (int w = 0; w < W64; ++w) {
             const int j = 64 * w + lane;
@@ -338,13 +359,13 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
             v[i][w] = alpha[(pix < N ? pix : N - 1) * k + (j < k ? j : k - 1)];
         }
 #pragma unroll
-    for (int i = 0; i < kMaskPx; ++i)
+    for (int i = 0; i < PX; ++i)
 #pragma unroll
         for (int w = 0; w < W64; ++w) v[i][w] = (64 * w + lane < k && p0 + i < N) ? fabsf(v[i][w]) : INFINITY;
-    uint64_t words[kMaskPx][W64], nearw[kMaskPx][W64];
+    uint64_t words[PX][W64], nearw[PX][W64];
     uint64_t anyn = 0;
 #pragma unroll
-    for (int i = 0; i < kMaskPx; ++i)
+    for (int i = 0; i < PX; ++i)
 #pragma unroll
         for (int w = 0; w < W64; ++w) {
             const uint64_t inb = __ballot(v[i][w] <= tin[w]);
@@ -353,10 +374,9 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
             nearw[i][w] = ~(inb | outb) & vmask[w];  // NaN: neither, so recomputed
             anyn |= nearw[i][w];
         }
-    unsigned long long nrec = 0;
     if (anyn) {
 #pragma unroll
-        for (int i = 0; i < kMaskPx; ++i) {
+        for (int i = 0; i < PX; ++i) {
             const int64_t pix = p0 + i;
             if (pix >= N) break;
             uint64_t any_i = 0;
@@ -369,60 +389,124 @@ __global__ __launch_bounds__(256) void k_mask_alpha(const float *alpha, int64_t 
                 const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + vv - h, W);
                 s[t] = wmask[t] * gray64(rgb, NN, (int64_t)rr * W + cc);
             }
-            double mu = 0.0;
-            if (lane == 0) {
-                double sum = 0.0;
-                for (int t = 0; t < n; ++t) sum = sum + s[t];
-                mu = sum / (double)n;
+            double mu = 0.0, nu2 = 0.0;
+            if (pstats) {
+                mu = pstats[2 * pix];
+                nu2 = pstats[2 * pix + 1];
+            } else {
+                if (lane == 0) {
+                    double sum = 0.0;
+                    for (int t = 0; t < n; ++t) sum = sum + s[t];
+                    mu = sum / (double)n;
+                    for (int t = 0; t < n; ++t) {
+                        const double z = s[t] - mu;
+                        nu2 = nu2 + z * z;
+                    }
+                }
+                mu = __shfl(mu, 0);
+                nu2 = __shfl(nu2, 0);
             }
-            mu = __shfl(mu, 0);
-            for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
-            double nu2 = 0.0;
-            if (lane == 0)
-                for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
-            nu2 = __shfl(nu2, 0);
-            for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / sqrt(nu2);
+            const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
+            for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : (s[t] - mu) / nu;
+            __builtin_amdgcn_wave_barrier();
+            // every row of this lane in between, one pass over the patch
+            bool fl[W64];
+            bool anyl = false;
+#pragma unroll
+            for (int w = 0; w < W64; ++w) {
+                fl[w] = (nearw[i][w] >> lane) & 1ull;
+                anyl |= fl[w];
+            }
+            double acc[W64];
+#pragma unroll
+            for (int w = 0; w < W64; ++w) acc[w] = 0.0;
+            if (anyl) {
+                for (int t0 = 0; t0 < n; t0 += 8) {
+                    double sv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) sv[u] = s[t0 + u < n ? t0 + u : n - 1];
+#pragma unroll
+                    for (int w = 0; w < W64; ++w) {
+                        if (!fl[w]) continue;
+                        const float *om = (OML ? s_om : omega) + (int64_t)(64 * w + lane) * n;
+                        float ov[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) ov[u] = om[t0 + u < n ? t0 + u : n - 1];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (t0 + u < n) acc[w] = acc[w] + (double)ov[u] * sv[u];
+                    }
+                }
+            }
 #pragma unroll
             for (int w = 0; w < W64; ++w) {
                 const uint64_t nm = nearw[i][w];
                 if (!nm) continue;
-                bool in = false;
-                if ((nm >> lane) & 1ull) in = fabs(dot64(omega + (int64_t)(64 * w + lane) * n, s, n)) <= tau;
+                const bool in = fl[w] && fabs(acc[w]) <= tau;
                 words[i][w] = (words[i][w] & ~nm) | (__ballot(in) & nm);
                 nrec += (unsigned long long)__popcll(nm);
             }
+            __builtin_amdgcn_wave_barrier();  // s is rewritten for the next pixel
         }
     }
-    // lane l < kMaskPx * W64 stores word (l / W64, l % W64)
+// lane l < PX * W64 stores word (l / W64, l % W64)
     const int li = lane / W64, lw = lane - li * W64;
     uint64_t outw = 0;
 #pragma unroll
-    for (int i = 0; i < kMaskPx; ++i)
+    for (int i = 0; i < PX; ++i)
 #pragma unroll
         for (int w = 0; w < W64; ++w)
             if (li == i && lw == w) outw = words[i][w];
-    if (lane < kMaskPx * W64 && p0 + li < N) masks[(p0 + li) * W64 + lw] = outw;
+    if (lane < PX * W64 && p0 + li < N) masks[(p0 + li) * W64 + lw] = outw;
+    }
     if (recomputed && lane == 0 && nrec) atomicAdd(recomputed, nrec);
+}
+
+template <int W64, bool OML>
+static hipError_t launch_mask_k(const LaunchCtx &lc, size_t lds, const float *alpha, int64_t N, int k,
+                                const float *t_in, const float *t_out, double tau, const double *tau_dev,
+                                const float *rgb, int H, int W, int p, const double *wmask, const float *omega,
+                                uint64_t *masks, unsigned long long *recomputed, const double *pstats) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_mask_alpha<W64, OML>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mask_alpha<W64, OML>, 64 * kMaskWaves, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t blocks = (int64_t)lc.num_cu * per_cu;
+    const int64_t px = W64 >= 3 ? kMaskPx / 2 : kMaskPx;
+    const int64_t need = (N + px * kMaskWaves - 1) / (px * kMaskWaves);
+    if (blocks > need) blocks = need;
+    hipLaunchKernelGGL((k_mask_alpha<W64, OML>), dim3((unsigned)blocks), dim3(64 * kMaskWaves), lds, lc.stream,
+                       alpha, N, k, t_in, t_out, tau, tau_dev, rgb, H, W, p, wmask, omega, masks, recomputed,
+                       pstats);
+    return hipGetLastError();
 }
 
 hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N, int k, const float *t_in,
                              const float *t_out, double tau, const double *tau_dev, const float *rgb, int H,
                              int W, int p,
                              const double *wmask, const float *omega, uint64_t *masks,
-                             unsigned long long *recomputed) {
+                             unsigned long long *recomputed, const double *pstats) {
     if (N <= 0) return hipSuccess;
-    const int64_t blocks = (N + 4 * kMaskPx - 1) / (4 * kMaskPx);
-#define CS_MASK_LAUNCH(WW)                                                                              \
-    hipLaunchKernelGGL(k_mask_alpha<WW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, N, k, t_in, \
-                       t_out, tau, tau_dev, rgb, H, W, p, wmask, omega, masks, recomputed)
+    const int n = p * p;
+    const size_t patches = sizeof(double) * kMaskWaves * (size_t)n;
+    const size_t om = sizeof(float) * (size_t)k * n;
+    const bool oml = patches + om <= (size_t)150 * 1024;  // operator in LDS when it fits beside the patches
+    const size_t lds = patches + (oml ? om : 0);
+#define CS_MASK_LAUNCH(WW)                                                                                       \
+    return oml ? launch_mask_k<WW, true>(lc, lds, alpha, N, k, t_in, t_out, tau, tau_dev, rgb, H, W, p, wmask,  \
+                                         omega, masks, recomputed, pstats)                                      \
+               : launch_mask_k<WW, false>(lc, lds, alpha, N, k, t_in, t_out, tau, tau_dev, rgb, H, W, p, wmask, \
+                                          omega, masks, recomputed, pstats)
     switch ((k + 63) / 64) {
-        case 1: CS_MASK_LAUNCH(1); break;
-        case 2: CS_MASK_LAUNCH(2); break;
-        case 3: CS_MASK_LAUNCH(3); break;
-        default: CS_MASK_LAUNCH(4); break;
+        case 1: CS_MASK_LAUNCH(1);
+        case 2: CS_MASK_LAUNCH(2);
+        case 3: CS_MASK_LAUNCH(3);
+        default: CS_MASK_LAUNCH(4);
     }
 #undef CS_MASK_LAUNCH
-    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_put_table(double *dst, MaskTable t, int n) {

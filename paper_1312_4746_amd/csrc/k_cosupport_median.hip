@@ -25,28 +25,22 @@ namespace {
 constexpr int kPx = 8;  // pixels per wave and round in the pixel-major pass
 constexpr int kRoundsPerWave = 4;
 
-// Reserve slots for the lanes set in m (one atomic per wave), return the slot
-// of this lane (meaningful where its bit is set).
-__device__ __forceinline__ unsigned long long wave_slot(unsigned long long m, unsigned long long *counter,
-                                                        int lane) {
-    const int first = __ffsll((long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane == first) base = atomicAdd(counter, (unsigned long long)__popcll(m));
-    base = __shfl(base, first);
-    return base + __popcll(m & ((1ull << lane) - 1ull));
-}
 }  // namespace
 
-// The gather pass.  Each wave takes rounds of kPx consecutive pixels (about
-// kRoundsPerWave of them, the loads of the next in flight while one is
-// decided), lane = row within a 64-bit mask word.  Per workgroup the
-// count of entries below the candidate window goes to parts[blockIdx.x].
+// The gather pass.  Each wave takes a contiguous run of rounds of kPx
+// consecutive pixels (about kRoundsPerWave of them, the loads of the next in
+// flight while one is decided), lane = row within a 64-bit mask word.  Its
+// candidates and undecided entries go to its own region of cand and didx,
+// which starts at its first entry (so it can never overflow), counted in
+// ccnt and dcnt: no global atomics.  Per workgroup the count of entries below
+// the candidate window goes to parts[blockIdx.x].
 template <int W64>
 __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, int64_t N, int k,
                                                             const double *max_margin, const double *margins,
-                                                            double frac, TauState *st, int64_t *cand, int64_t cap,
-                                                            unsigned long long *parts, int64_t *didx,
-                                                            uint64_t *masks, const unsigned int *hist3) {
+                                                            double frac, TauState *st, int64_t *cand,
+                                                            unsigned int *ccnt, unsigned long long *parts,
+                                                            int64_t *didx, unsigned int *dcnt, uint64_t *masks,
+                                                            const unsigned int *hist3) {
     static_assert(kPx * W64 <= 64, "one mask word per lane");
     __shared__ unsigned long long red[256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -98,7 +92,18 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
     }
     unsigned long long below = 0;
     const int64_t nrounds = (N + kPx - 1) / kPx;
-    const int64_t stride = (int64_t)gridDim.x * 4;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t R = (nrounds + nw - 1) / nw;  // rounds per wave
+    const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t r_end = (gw + 1) * R < nrounds ? (gw + 1) * R : nrounds;
+    const int64_t region = R * kPx * k;  // entries of a wave's run of rounds
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rg_waves = (unsigned int)nw;
+        st->rg_size = (long long)region;
+    }
+    int64_t *creg = cand + gw * region, *dreg = didx + gw * region;
+    unsigned int nc_w = 0, nd_w = 0;  // wave-uniform counts
+    const unsigned long long lt = (1ull << lane) - 1ull;
     // the keys of a round, loaded unconditionally (clamped indices: the loads
     // are in flight together; padding is replaced when the round is used)
     auto load = [&](int64_t rd, uint32_t (&kk)[kPx][W64]) {
@@ -113,11 +118,11 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
             }
     };
     uint32_t key[kPx][W64], nkey[kPx][W64];
-    int64_t rd = (int64_t)blockIdx.x * 4 + wave;
-    if (rd < nrounds) load(rd, key);
-    for (; rd < nrounds; rd += stride) {
+    int64_t rd = gw * R;
+    if (rd < r_end) load(rd, key);
+    for (; rd < r_end; ++rd) {
         const int64_t p0 = rd * kPx;
-        if (rd + stride < nrounds) load(rd + stride, nkey);  // next round in flight
+        if (rd + 1 < r_end) load(rd + 1, nkey);  // next round in flight
 #pragma unroll
         for (int i = 0; i < kPx; ++i)
 #pragma unroll
@@ -137,8 +142,8 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
                 const bool is_cand = live && x >= blo && x <= bhi;
                 const unsigned long long cm = __ballot(is_cand);
                 if (cm) {
-                    const unsigned long long slot = wave_slot(cm, &st->ncand, lane);
-                    if (is_cand && (int64_t)slot < cap) cand[slot] = (p0 + i) * k + 64 * w + lane;
+                    if (is_cand) creg[nc_w + __popcll(cm & lt)] = (p0 + i) * k + 64 * w + lane;
+                    nc_w += (unsigned int)__popcll(cm);
                 }
                 const float f = __uint_as_float(x);
                 const uint64_t inb = __ballot(f <= tin[w]);
@@ -146,8 +151,8 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
                 const bool defer = live && !(f <= tin[w]) && !(f > tout[w]);  // NaN: deferred
                 const unsigned long long dm = __ballot(defer);
                 if (dm) {
-                    const unsigned long long slot = wave_slot(dm, &st->n_d, lane);
-                    if (defer) didx[slot] = (p0 + i) * k + 64 * w + lane;
+                    if (defer) dreg[nd_w + __popcll(dm & lt)] = (p0 + i) * k + 64 * w + lane;
+                    nd_w += (unsigned int)__popcll(dm);
                 }
                 // one entry at a time: keeps the ballots from piling up in
                 // scalar registers
@@ -159,6 +164,10 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
 #pragma unroll
             for (int w = 0; w < W64; ++w) key[i][w] = nkey[i][w];
     }
+    if (lane == 0 && gw < nw) {
+        ccnt[gw] = nc_w;
+        dcnt[gw] = nd_w;
+    }
     red[threadIdx.x] = below;
     __syncthreads();
     for (int s2 = 128; s2 > 0; s2 >>= 1) {
@@ -169,93 +178,60 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
     if (blockIdx.x == 0 && threadIdx.x == 0) st->nparts = gridDim.x;
 }
 
-// The listed entries against the exact tau, up to 64 per wave: an
-// entry whose rounded |a| is clear of tau by more than its row's margin is
-// decided at once; the few within the margin (or NaN) are recomputed in FP64
-// by the whole wave, one after the other, from the exact patch (Sec. 2 a = O s
-// with the Sec. 3.1 normalised, Gaussian-masked gray patch, in the oracle's
-// operation order) and decided exactly.
+// The listed entries against the exact tau: lane = one wave region of the
+// gather, its entries in order.  An entry whose rounded |a| is clear of tau
+// by more than its row margin is decided at once; the few within the margin
+// (or NaN) are recomputed in FP64 by their lane from the exact patch (Sec. 2
+// a = O s with the Sec. 3.1 normalised, Gaussian-masked gray patch, in the
+// oracle's operation order, the patch statistics from the analysis when
+// given) and decided exactly.
+__device__ __forceinline__ void finish_entry(int64_t e, const float *alpha, const float *rgb, int H, int W, int p,
+                                             const double *wmask, const float *omega, int k, const double *margins,
+                                             double tau, uint64_t *masks, const double *pstats) {
+    const int64_t pix = e / k;
+    const int j = (int)(e - pix * k);
+    const double a = (double)fabsf(alpha[e]);
+    const double m = margins[j];
+    bool in = a <= tau - m;
+    if (!in && !(a > tau + m))  // within the margin, or NaN
+        in = fabs(exact_entry(rgb, H, W, p, wmask, omega + (int64_t)j * p * p, pix, pstats)) <= tau;
+    if (in) atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * ((k + 63) / 64) + (j >> 6)), 1ull << (j & 63));
+}
+
 __global__ __launch_bounds__(64) void k_median_mask_finish(const float *alpha, const float *rgb, int H, int W,
                                                            int p, const double *wmask, const float *omega, int k,
-                                                           const int64_t *didx, const double *margins,
-                                                           const TauState *st, uint64_t *masks) {
-    __shared__ double s[15 * 15];
-    __shared__ double sh_mu, sh_nu2;
-    const int64_t nd = (int64_t)st->n_d;
+                                                           const int64_t *didx, const unsigned int *dcnt,
+                                                           const int64_t *dcomp, const double *margins,
+                                                           const TauState *st, uint64_t *masks,
+                                                           const double *pstats) {
     const double tau = st->tau;
-    const int n = p * p, h = (p - 1) / 2;
-    const int64_t N = (int64_t)H * W;
-    const int W64 = (k + 63) / 64;
-    const int lane = threadIdx.x;
-    // entry q of round q0 is lane (q - q0) / G of wave q mod G (G waves): the
-    // entries of one wave are G apart, so listed neighbours (often near
-    // entries together) fall on different waves
-    const int64_t G = gridDim.x;
-    for (int64_t q0 = 0; q0 < nd; q0 += 64 * G) {
-        const int64_t q = q0 + (int64_t)lane * G + blockIdx.x;
-        int64_t e = 0;
-        bool near = false;
-        if (q < nd) {
-            e = didx[q];
-            const int64_t pix = e / k;
-            const int j = (int)(e - pix * k);
-            const double a = (double)fabsf(alpha[e]);
-            const double m = margins[j];
-            if (a <= tau - m)
-                atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * W64 + (j >> 6)), 1ull << (j & 63));
-            else if (!(a > tau + m))
-                near = true;  // within the margin, or NaN
-        }
-        for (unsigned long long mb = __ballot(near); mb; mb &= mb - 1) {
-            const int c = __ffsll((long long)mb) - 1;
-            const int64_t ec = __shfl(e, c);
-            const int64_t pix = ec / k;
-            const int j = (int)(ec - pix * k);
-            const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
-            for (int t = lane; t < n; t += 64) {
-                const int u = t / p, vv = t - u * p;
-                const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + vv - h, W);
-                s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
-            }
-            __syncthreads();
-            if (lane == 0) {
-                double sum = 0.0;
-                for (int t = 0; t < n; ++t) sum = sum + s[t];
-                sh_mu = sum / (double)n;
-            }
-            __syncthreads();
-            const double mu = sh_mu;
-            for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
-            __syncthreads();
-            if (lane == 0) {
-                double nu2 = 0.0;
-                for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
-                sh_nu2 = nu2;
-            }
-            __syncthreads();
-            const double nu2 = sh_nu2;
-            const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
-            for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / nu;
-            __syncthreads();
-            if (lane == 0 && fabs(dot64(omega + (int64_t)j * n, s, n)) <= tau)
-                atomicOr(reinterpret_cast<unsigned long long *>(masks + pix * W64 + (j >> 6)), 1ull << (j & 63));
-            __syncthreads();  // s is rewritten by the next entry
-        }
+    const int64_t stride = (int64_t)gridDim.x * 64;
+    const int64_t nd = (int64_t)st->n_d;
+    if (nd <= kListCap) {  // the compact list: one lane per entry
+        for (int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x; q < nd; q += stride)
+            finish_entry(dcomp[q], alpha, rgb, H, W, p, wmask, omega, k, margins, tau, masks, pstats);
+        return;
+    }
+    const int64_t nw = (int64_t)st->rg_waves, region = (int64_t)st->rg_size;
+    for (int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x; r < nw; r += stride) {
+        const unsigned int cnt = dcnt[r];
+        const int64_t *lst = didx + r * region;
+        for (unsigned int q = 0; q < cnt; ++q)
+            finish_entry(lst[q], alpha, rgb, H, W, p, wmask, omega, k, margins, tau, masks, pstats);
     }
 }
 
 hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N, int k,
                               const double *max_margin, const double *margins, double frac, TauState *st,
-                              int64_t *cand, int64_t cap, unsigned long long *parts, int64_t *didx,
-                              uint64_t *masks, const unsigned int *hist3) {
+                              int64_t *cand, unsigned int *ccnt, unsigned long long *parts, int64_t *didx,
+                              unsigned int *dcnt, uint64_t *masks, const unsigned int *hist3) {
     if (N <= 0) return hipSuccess;
     // kRoundsPerWave rounds per wave (each prefetches the next), more where
     // the per-workgroup counts would not fit
-    int64_t blocks = (N + 4 * kPx * kRoundsPerWave - 1) / (4 * kPx * kRoundsPerWave);
-    if (blocks > kTauParts) blocks = kTauParts;
+    const int64_t blocks = median_gather_waves(N) / 4;
 #define CS_MG_LAUNCH(WW)                                                                                    \
     hipLaunchKernelGGL(k_median_mask_gather<WW>, dim3((unsigned)blocks), dim3(256), 0, lc.stream, alpha, N, \
-                       k, max_margin, margins, frac, st, cand, cap, parts, didx, masks, hist3)
+                       k, max_margin, margins, frac, st, cand, ccnt, parts, didx, dcnt, masks, hist3)
     switch ((k + 63) / 64) {
         case 1: CS_MG_LAUNCH(1); break;
         case 2: CS_MG_LAUNCH(2); break;
@@ -266,11 +242,22 @@ hipError_t median_mask_gather(const LaunchCtx &lc, const float *alpha, int64_t N
     return hipGetLastError();
 }
 
+int64_t median_gather_waves(int64_t N) {
+    int64_t blocks = (N + 4 * kPx * kRoundsPerWave - 1) / (4 * kPx * kRoundsPerWave);
+    if (blocks > kTauParts) blocks = kTauParts;
+    return 4 * blocks;
+}
+
 hipError_t median_mask_finish(const LaunchCtx &lc, const float *alpha, const float *rgb, int H, int W, int p,
                               const double *wmask, const float *omega, int k, const int64_t *didx,
-                              const double *margins, const TauState *st, uint64_t *masks) {
-    hipLaunchKernelGGL(k_median_mask_finish, dim3((unsigned)lc.num_cu * 8), dim3(64), 0, lc.stream, alpha, rgb, H,
-                       W, p, wmask, omega, k, didx, margins, st, masks);
+                              const unsigned int *dcnt, const int64_t *dcomp, const double *margins,
+                              const TauState *st, uint64_t *masks, const double *pstats) {
+    // one lane per listed entry, or per gather wave when the list did not fit
+    int64_t blocks = (int64_t)lc.num_cu * 8;
+    const int64_t nw = median_gather_waves((int64_t)H * W);
+    if (blocks < (nw + 63) / 64) blocks = (nw + 63) / 64;
+    hipLaunchKernelGGL(k_median_mask_finish, dim3((unsigned)blocks), dim3(64), 0, lc.stream, alpha, rgb, H, W, p,
+                       wmask, omega, k, didx, dcnt, dcomp, margins, st, masks, pstats);
     return hipGetLastError();
 }
 

@@ -308,60 +308,113 @@ hipError_t tau_gather(const LaunchCtx &lc, const float *alpha, int64_t count,
     return hipGetLastError();
 }
 
-// FP64 recompute of each candidate entry e = pixel * k + j, one wave per
-// candidate: element-wise steps run across lanes, every sum runs in lane 0 in
-// t order, so the result is the same bit pattern as a sequential evaluation.
-// Persistent waves read the candidate count from the device state (no host
-// round trip); counts beyond the capacity are left to the host's retry.
+// FP64 recompute of each candidate entry e = pixel * k + j, one lane per
+// candidate (exact_entry: every sum sequential in t, so the result is the
+// bit pattern of the oracle's evaluation).  Persistent waves read the
+// candidate count from the device state (no host round trip); counts beyond
+// the capacity are left to the host's retry.
 __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, int W, int p,
                                                        const double *wmask, const float *omega,
                                                        int k, const int64_t *cand, const TauState *st,
-                                                       int64_t cap, double *vals) {
-#pragma clang fp contract(off)
-    __shared__ double s[15 * 15];
-    __shared__ double sh_mu, sh_nu2;
+                                                       int64_t cap, double *vals, const double *pstats,
+                                                       const unsigned int *ccnt, const unsigned long long *coff,
+                                                       const int64_t *ccomp) {
+    const int n = p * p;
+    const int64_t stride = (int64_t)gridDim.x * 64;
+    if (ccnt && (int64_t)st->ncand > kListCap) {
+        // per-wave regions of the fused gather (a list too long to compact):
+        // lane = region, its values written at the region's offset
+        const int64_t nw = (int64_t)st->rg_waves, region = (int64_t)st->rg_size;
+        for (int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x; r < nw; r += stride) {
+            const unsigned int cnt = ccnt[r];
+            const int64_t *src = cand + r * region;
+            double *dst = vals + coff[r];
+            for (unsigned int q = 0; q < cnt; ++q) {
+                const int64_t e = src[q];
+                const int64_t pix = e / k;
+                const int j = (int)(e - pix * k);
+                dst[q] = fabs(exact_entry(rgb, H, W, p, wmask, omega + (int64_t)j * n, pix, pstats));
+            }
+        }
+        return;
+    }
+    // compact list: the fused gather's in ccomp (see k_list_compact), else cand
+    const int64_t *lst = ccnt ? ccomp : cand;
     const unsigned long long nc = st->ncand;
     const int64_t ncand = (int64_t)nc < cap ? (int64_t)nc : cap;
-    const int n = p * p, h = (p - 1) / 2;
-    const int64_t N = (int64_t)H * W;
-    const int lane = threadIdx.x;
-    for (int64_t c = blockIdx.x; c < ncand; c += gridDim.x) {
-        const int64_t e = cand[c];
+    for (int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x; c < ncand; c += stride) {
+        const int64_t e = lst[c];
         const int64_t pix = e / k;
         const int j = (int)(e - pix * k);
-        const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
-        for (int t = lane; t < n; t += 64) {
-            const int u = t / p, v = t - u * p;
-            const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + v - h, W);
-            s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
+        vals[c] = fabs(exact_entry(rgb, H, W, p, wmask, omega + (int64_t)j * n, pix, pstats));
+    }
+}
+
+// Offsets of the fused gather's per-wave regions in the compact lists
+// (exclusive scans of their candidate and undecided-entry counts) and the two
+// totals; one workgroup.
+__global__ __launch_bounds__(1024) void k_list_scan(const unsigned int *ccnt, const unsigned int *dcnt,
+                                                    TauState *st, unsigned long long *coff,
+                                                    unsigned long long *doff) {
+    __shared__ unsigned long long s[2][1024];
+    const int nw = (int)st->rg_waves;
+    const int per = (nw + 1023) / 1024;
+    const int t = threadIdx.x;
+    unsigned long long sc = 0, sd = 0;
+    for (int i = 0; i < per; ++i) {
+        const int r = t * per + i;
+        if (r < nw) {
+            sc += ccnt[r];
+            sd += dcnt[r];
         }
+    }
+    s[0][t] = sc;
+    s[1][t] = sd;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long vc = t >= off ? s[0][t - off] : 0ull, vd = t >= off ? s[1][t - off] : 0ull;
         __syncthreads();
-        if (lane == 0) {
-            double sum = 0.0;
-            for (int t = 0; t < n; ++t) sum = sum + s[t];
-            sh_mu = sum / (double)n;
+        s[0][t] += vc;
+        s[1][t] += vd;
+        __syncthreads();
+    }
+    unsigned long long bc = s[0][t] - sc, bd = s[1][t] - sd;
+    for (int i = 0; i < per; ++i) {
+        const int r = t * per + i;
+        if (r < nw) {
+            coff[r] = bc;
+            doff[r] = bd;
+            bc += ccnt[r];
+            bd += dcnt[r];
         }
-        __syncthreads();
-        const double mu = sh_mu;
-        for (int t = lane; t < n; t += 64) s[t] = s[t] - mu;
-        __syncthreads();
-        if (lane == 0) {
-            double nu2 = 0.0;
-            for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
-            sh_nu2 = nu2;
+    }
+    if (t == 1023) {
+        st->ncand = s[0][1023];
+        st->n_d = s[1][1023];
+    }
+}
+
+// Both lists of the fused gather into compact form (lane = region), each only
+// when its total fits kListCap; otherwise its consumer walks the regions.
+__global__ __launch_bounds__(64) void k_list_compact(const int64_t *cand, const unsigned int *ccnt,
+                                                     const unsigned long long *coff, const int64_t *didx,
+                                                     const unsigned int *dcnt, const unsigned long long *doff,
+                                                     const TauState *st, int64_t *ccomp, int64_t *dcomp) {
+    const int64_t nw = (int64_t)st->rg_waves, region = (int64_t)st->rg_size;
+    const bool cfit = (int64_t)st->ncand <= kListCap, dfit = (int64_t)st->n_d <= kListCap;
+    for (int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x; r < nw; r += (int64_t)gridDim.x * 64) {
+        if (cfit) {
+            const unsigned int n = ccnt[r];
+            const int64_t *src = cand + r * region;
+            int64_t *dst = ccomp + coff[r];
+            for (unsigned int q = 0; q < n; ++q) dst[q] = src[q];
         }
-        __syncthreads();
-        const double nu2 = sh_nu2;
-        const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
-        for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : s[t] / nu;
-        __syncthreads();
-        if (lane == 0) {
-            const float *om = omega + (int64_t)j * n;
-            double acc = 0.0;
-            for (int t = 0; t < n; ++t) acc = acc + (double)om[t] * s[t];
-            vals[c] = fabs(acc);
+        if (dfit) {
+            const unsigned int n = dcnt[r];
+            const int64_t *src = didx + r * region;
+            int64_t *dst = dcomp + doff[r];
+            for (unsigned int q = 0; q < n; ++q) dst[q] = src[q];
         }
-        __syncthreads();  // s is rewritten by the next candidate
     }
 }
 
@@ -518,16 +571,27 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
     }
 }
 
+hipError_t list_compact(const LaunchCtx &lc, int64_t nw, const int64_t *cand, const unsigned int *ccnt,
+                        const int64_t *didx, const unsigned int *dcnt, TauState *st, FusedLists fl) {
+    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, lc.stream, ccnt, dcnt, st, fl.coff, fl.doff);
+    hipLaunchKernelGGL(k_list_compact, dim3((unsigned)((nw + 63) / 64)), dim3(64), 0, lc.stream, cand, ccnt, fl.coff,
+                       didx, dcnt, fl.doff, st, fl.ccomp, fl.dcomp);
+    return hipGetLastError();
+}
+
 hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p, int n,
                       const double *wmask, const float *omega, int k, const int64_t *cand,
                       int64_t cap, double *vals, double frac, TauState *st, unsigned long long *parts,
-                      double *tau_out) {
+                      double *tau_out, const double *pstats, const unsigned int *ccnt, const FusedLists *fl) {
     (void)n;
-    int64_t blocks = (int64_t)lc.num_cu * 16;
-    if (blocks > cap) blocks = cap;
+    // one lane per entry of a compact list (or per region when the fused
+    // gather's list was too long to compact: at most kMedianWavesMax of them)
+    int64_t blocks = (int64_t)lc.num_cu * 8;
+    if (!ccnt && blocks > (cap + 63) / 64) blocks = (cap + 63) / 64;
+    if (ccnt && blocks < kMedianWavesMax / 64) blocks = kMedianWavesMax / 64;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_tau_recompute, dim3((unsigned)blocks), dim3(64), 0, lc.stream, rgb, H, W, p, wmask, omega,
-                       k, cand, st, cap, vals);
+                       k, cand, st, cap, vals, pstats, ccnt, fl ? fl->coff : nullptr, fl ? fl->ccomp : nullptr);
     unsigned long long *rk = parts + kTauParts;  // kRankMax (less, equal) pairs
     hipLaunchKernelGGL(k_tau_rank, dim3((unsigned)lc.num_cu * 4), dim3(64), 0, lc.stream, vals, cap, st, rk);
     hipLaunchKernelGGL(k_tau_select, dim3(1), dim3(1024), 0, lc.stream, vals, cap, frac, st, parts, rk, tau_out);
