@@ -113,12 +113,20 @@ __device__ __forceinline__ int tex_feature(int f, int k, const uint32_t *bits, u
 template <bool PIX>
 __device__ __forceinline__ void tex_pack(int f0, int k, const uint32_t *bits, uint32_t c, uint32_t (&o)[6]) {
     for (int d = 0; d < 6; ++d) o[d] = 0u;
-    for (int v = 0; v < 32; ++v) {
-        const uint32_t code = fp6_of_int(tex_feature<PIX>(f0 + v, k, bits, c));
+    auto put = [&](int v, uint32_t code) {
         const int b = 6 * v, d = b >> 5, sh = b & 31;
         o[d] |= code << sh;
         if (sh > 26) o[d + 1] |= code >> (32 - sh);
+    };
+    if (f0 + 32 <= k && (f0 & 31) == 0) {
+        // a whole mask word: 1 (pixel) or -2 (sample) per set bit
+        const uint32_t w = bits[f0 >> 5], code = PIX ? fp6_of_int(1) : fp6_of_int(-2);
+#pragma unroll
+        for (int v = 0; v < 32; ++v)
+            if ((w >> v) & 1u) put(v, code);
+        return;
     }
+    for (int v = 0; v < 32; ++v) put(v, fp6_of_int(tex_feature<PIX>(f0 + v, k, bits, c)));
 }
 
 // Physical 16-byte slot of logical slot p in a sample row.  Rows are 128 B

@@ -360,12 +360,24 @@ __global__ __launch_bounds__(1024) void k_list_scan(const unsigned int *ccnt, co
     const int nw = (int)st->rg_waves;
     const int per = (nw + 1023) / 1024;
     const int t = threadIdx.x;
+    // counts read eight at a time (loads in flight together)
+    auto batch = [&](int i0, unsigned int (&cv)[8], unsigned int (&dv)[8]) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int r = t * per + i0 + u;
+            const bool ok = i0 + u < per && r < nw;
+            cv[u] = ok ? ccnt[r] : 0u;
+            dv[u] = ok ? dcnt[r] : 0u;
+        }
+    };
     unsigned long long sc = 0, sd = 0;
-    for (int i = 0; i < per; ++i) {
-        const int r = t * per + i;
-        if (r < nw) {
-            sc += ccnt[r];
-            sd += dcnt[r];
+    for (int i0 = 0; i0 < per; i0 += 8) {
+        unsigned int cv[8], dv[8];
+        batch(i0, cv, dv);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sc += cv[u];
+            sd += dv[u];
         }
     }
     s[0][t] = sc;
@@ -379,13 +391,18 @@ __global__ __launch_bounds__(1024) void k_list_scan(const unsigned int *ccnt, co
         __syncthreads();
     }
     unsigned long long bc = s[0][t] - sc, bd = s[1][t] - sd;
-    for (int i = 0; i < per; ++i) {
-        const int r = t * per + i;
-        if (r < nw) {
-            coff[r] = bc;
-            doff[r] = bd;
-            bc += ccnt[r];
-            bd += dcnt[r];
+    for (int i0 = 0; i0 < per; i0 += 8) {
+        unsigned int cv[8], dv[8];
+        batch(i0, cv, dv);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int r = t * per + i0 + u;
+            if (i0 + u < per && r < nw) {
+                coff[r] = bc;
+                doff[r] = bd;
+            }
+            bc += cv[u];
+            bd += dv[u];
         }
     }
     if (t == 1023) {
@@ -461,7 +478,17 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
     if (tid == 0) s_below = 0;
     __syncthreads();
     unsigned long long pb = 0;
-    for (int i = tid; i < (int)st->nparts; i += 1024) pb += parts[i];
+    const int np = (int)st->nparts;
+    for (int i0 = 0; i0 < np; i0 += 8 * 1024) {
+        unsigned long long pv8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024 + tid;
+            pv8[u] = i < np ? parts[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) pb += pv8[u];
+    }
     if (pb) atomicAdd(&s_below, pb);
     __syncthreads();
     const unsigned long long nc = st->ncand;
@@ -499,11 +526,27 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
         s_rank = r0 - below;
     }
     __syncthreads();
+    // the candidate values are read eight per thread at a time (loads in flight
+    // together): 8 x 1024 consecutive values per block of the loops below
+    auto keys8 = [&](int64_t c0, unsigned long long (&kv)[8], bool (&ok)[8]) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t c = c0 + (int64_t)u * 1024 + tid;
+            ok[u] = c < ncand;
+            kv[u] = (unsigned long long)__double_as_longlong(vals[ok[u] ? c : 0]);
+        }
+    };
     unsigned long long mn = ~0ull, mx = 0ull;
-    for (int64_t c = tid; c < ncand; c += 1024) {
-        const unsigned long long key = (unsigned long long)__double_as_longlong(vals[c]);
-        mn = key < mn ? key : mn;
-        mx = key > mx ? key : mx;
+    for (int64_t c0 = 0; c0 < ncand; c0 += 8 * 1024) {
+        unsigned long long kv[8];
+        bool ok[8];
+        keys8(c0, kv, ok);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (ok[u]) {
+                mn = kv[u] < mn ? kv[u] : mn;
+                mx = kv[u] > mx ? kv[u] : mx;
+            }
     }
     atomicMin(&s_min, mn);
     atomicMax(&s_max, mx);
@@ -527,9 +570,13 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
         __syncthreads();
         const unsigned long long hmask = shift + 8 >= 64 ? 0ull : (~0ull << (shift + 8));
         const unsigned long long pv = s_prefix;
-        for (int64_t c = tid; c < ncand; c += 1024) {
-            const unsigned long long key = (unsigned long long)__double_as_longlong(vals[c]);
-            if ((key & hmask) == pv) atomicAdd(&hist[(key >> shift) & 255ull], 1u);
+        for (int64_t c0 = 0; c0 < ncand; c0 += 8 * 1024) {
+            unsigned long long kv[8];
+            bool ok[8];
+            keys8(c0, kv, ok);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (ok[u] && (kv[u] & hmask) == pv) atomicAdd(&hist[(kv[u] >> shift) & 255ull], 1u);
         }
         __syncthreads();
         if (tid < 64) {
