@@ -310,6 +310,12 @@ hipError_t launch_analyze(const LaunchCtx &lc, const AnalyzeArgs &a, int precisi
 // staged in LDS once per workgroup, so the recompute reads it there.
 constexpr int kMaskPx = 8;
 constexpr int kMaskWaves = 16;
+// LDS bytes of the per-wave patch pairs and entry lists (the operator follows,
+// 16-byte aligned).
+__host__ __device__ inline size_t mask_lds_head(int n, int k) {
+    const size_t b = sizeof(double) * kMaskWaves * 2 * (size_t)n + sizeof(uint16_t) * kMaskWaves * 2 * (size_t)k;
+    return (b + 15) / 16 * 16;
+}
 template <int W64, bool OML>
 __global__ __launch_bounds__(64 * kMaskWaves) void k_mask_alpha(const float *alpha, int64_t N, int k,
                                                                  const float *t_in, const float *t_out, double tau,
@@ -323,15 +329,17 @@ __global__ __launch_bounds__(64 * kMaskWaves) void k_mask_alpha(const float *alp
     if (tau_dev) tau = *tau_dev;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = p * p, h = (p - 1) / 2;
-    double *s = reinterpret_cast<double *>(smem) + wave * n;  // this wave's patch
-    float *s_om = reinterpret_cast<float *>(smem + sizeof(double) * kMaskWaves * n);
+    double *s = reinterpret_cast<double *>(smem) + wave * 2 * n;  // this wave's two patches
+    uint16_t *lst = reinterpret_cast<uint16_t *>(smem + sizeof(double) * kMaskWaves * 2 * n) + wave * 2 * k;
+    float *s_om = reinterpret_cast<float *>(smem + mask_lds_head(n, k));
     if constexpr (OML) {
         for (int idx = threadIdx.x; idx < k * n; idx += 64 * kMaskWaves) s_om[idx] = omega[idx];
         __syncthreads();
     }
     const int64_t NN = (int64_t)H * W;
-    // pixels per block: fewer for long masks (their ballots are held in SGPRs)
-    constexpr int PX = W64 >= 3 ? kMaskPx / 2 : kMaskPx;
+    // pixels per block (even): fewer for long masks (their ballots are held in SGPRs)
+    constexpr int PX = W64 >= 2 ? kMaskPx / 2 : kMaskPx;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     float tin[W64], tout[W64];
     uint64_t vmask[W64];
 #pragma unroll
@@ -375,78 +383,105 @@ __global__ __launch_bounds__(64 * kMaskWaves) void k_mask_alpha(const float *alp
             anyn |= nearw[i][w];
         }
     if (anyn) {
+        // pixels in pairs: both exact patches in the wave's LDS slice, then
+        // the pair's entries in between listed (pixel, word, lane order) and
+        // recomputed one per lane, the decision returned in the entry's bit 15
 #pragma unroll
-        for (int i = 0; i < PX; ++i) {
-            const int64_t pix = p0 + i;
-            if (pix >= N) break;
-            uint64_t any_i = 0;
+        for (int i0 = 0; i0 < PX; i0 += 2) {
+            uint64_t any2 = 0;
 #pragma unroll
-            for (int w = 0; w < W64; ++w) any_i |= nearw[i][w];
-            if (!any_i) continue;
-            const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
-            for (int t = lane; t < n; t += 64) {
-                const int u = t / p, vv = t - u * p;
-                const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + vv - h, W);
-                s[t] = wmask[t] * gray64(rgb, NN, (int64_t)rr * W + cc);
-            }
-            double mu = 0.0, nu2 = 0.0;
-            if (pstats) {
-                mu = pstats[2 * pix];
-                nu2 = pstats[2 * pix + 1];
-            } else {
-                if (lane == 0) {
-                    double sum = 0.0;
-                    for (int t = 0; t < n; ++t) sum = sum + s[t];
-                    mu = sum / (double)n;
-                    for (int t = 0; t < n; ++t) {
-                        const double z = s[t] - mu;
-                        nu2 = nu2 + z * z;
-                    }
+            for (int w = 0; w < W64; ++w) any2 |= nearw[i0][w] | nearw[i0 + 1][w];
+            if (!any2) continue;
+            for (int idx = lane; idx < 2 * n; idx += 64) {
+                const int ii = idx >= n ? 1 : 0, t = idx - ii * n;
+                const int64_t pix = p0 + i0 + ii;
+                double q = 0.0;
+                if (pix < N) {
+                    const int row = (int)(pix / W), col = (int)(pix - (int64_t)row * W);
+                    const int u = t / p, vv = t - u * p;
+                    const int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + vv - h, W);
+                    q = wmask[t] * gray64(rgb, NN, (int64_t)rr * W + cc);
                 }
-                mu = __shfl(mu, 0);
-                nu2 = __shfl(nu2, 0);
+                s[idx] = q;
             }
-            const double nu = nu2 == 0.0 ? 0.0 : sqrt(nu2);
-            for (int t = lane; t < n; t += 64) s[t] = nu2 == 0.0 ? 0.0 : (s[t] - mu) / nu;
+            double mu[2] = {0.0, 0.0}, nu2[2] = {0.0, 0.0};
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii) {
+                const int64_t pix = p0 + i0 + ii;
+                if (pix >= N) continue;
+                if (pstats) {
+                    mu[ii] = pstats[2 * pix];
+                    nu2[ii] = pstats[2 * pix + 1];
+                } else {
+                    double m = 0.0, v2 = 0.0;
+                    if (lane == 0) {
+                        const double *sp = s + ii * n;
+                        double sum = 0.0;
+                        for (int t = 0; t < n; ++t) sum = sum + sp[t];
+                        m = sum / (double)n;
+                        for (int t = 0; t < n; ++t) {
+                            const double z = sp[t] - m;
+                            v2 = v2 + z * z;
+                        }
+                    }
+                    mu[ii] = __shfl(m, 0);
+                    nu2[ii] = __shfl(v2, 0);
+                }
+            }
+            const double nu[2] = {nu2[0] == 0.0 ? 0.0 : sqrt(nu2[0]), nu2[1] == 0.0 ? 0.0 : sqrt(nu2[1])};
+            for (int idx = lane; idx < 2 * n; idx += 64) {
+                const int ii = idx >= n ? 1 : 0;
+                s[idx] = nu2[ii] == 0.0 ? 0.0 : (s[idx] - mu[ii]) / nu[ii];
+            }
+            // the list: entry (ii << 8) | j
+            unsigned int C = 0;
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+                for (int w = 0; w < W64; ++w) {
+                    const uint64_t nm = nearw[i0 + ii][w];
+                    if (!nm) continue;
+                    if ((nm >> lane) & 1ull) lst[C + __popcll(nm & lt)] = (uint16_t)((ii << 8) | (64 * w + lane));
+                    C += (unsigned int)__popcll(nm);
+                }
             __builtin_amdgcn_wave_barrier();
-            // every row of this lane in between, one pass over the patch
-            bool fl[W64];
-            bool anyl = false;
-#pragma unroll
-            for (int w = 0; w < W64; ++w) {
-                fl[w] = (nearw[i][w] >> lane) & 1ull;
-                anyl |= fl[w];
-            }
-            double acc[W64];
-#pragma unroll
-            for (int w = 0; w < W64; ++w) acc[w] = 0.0;
-            if (anyl) {
-                for (int t0 = 0; t0 < n; t0 += 8) {
-                    double sv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) sv[u] = s[t0 + u < n ? t0 + u : n - 1];
-#pragma unroll
-                    for (int w = 0; w < W64; ++w) {
-                        if (!fl[w]) continue;
-                        const float *om = (OML ? s_om : omega) + (int64_t)(64 * w + lane) * n;
+            for (unsigned int r0 = 0; r0 < C; r0 += 64) {
+                const unsigned int q = r0 + lane;
+                if (q < C) {
+                    const unsigned int e = lst[q];
+                    const double *sp = s + (e >> 8) * n;
+                    const float *om = (OML ? s_om : omega) + (int64_t)(e & 255u) * n;
+                    double acc = 0.0;
+                    for (int t0 = 0; t0 < n; t0 += 8) {
+                        double sv[8];
                         float ov[8];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) ov[u] = om[t0 + u < n ? t0 + u : n - 1];
+                        for (int u = 0; u < 8; ++u) {
+                            const int t = t0 + u < n ? t0 + u : n - 1;
+                            sv[u] = sp[t];
+                            ov[u] = om[t];
+                        }
 #pragma unroll
                         for (int u = 0; u < 8; ++u)
-                            if (t0 + u < n) acc[w] = acc[w] + (double)ov[u] * sv[u];
+                            if (t0 + u < n) acc = acc + (double)ov[u] * sv[u];
                     }
+                    if (fabs(acc) <= tau) lst[q] = (uint16_t)(e | 0x8000u);
                 }
             }
+            __builtin_amdgcn_wave_barrier();
+            unsigned int C2 = 0;
 #pragma unroll
-            for (int w = 0; w < W64; ++w) {
-                const uint64_t nm = nearw[i][w];
-                if (!nm) continue;
-                const bool in = fl[w] && fabs(acc[w]) <= tau;
-                words[i][w] = (words[i][w] & ~nm) | (__ballot(in) & nm);
-                nrec += (unsigned long long)__popcll(nm);
-            }
-            __builtin_amdgcn_wave_barrier();  // s is rewritten for the next pixel
+            for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+                for (int w = 0; w < W64; ++w) {
+                    const uint64_t nm = nearw[i0 + ii][w];
+                    if (!nm) continue;
+                    const bool in = ((nm >> lane) & 1ull) && (lst[C2 + __popcll(nm & lt)] & 0x8000u);
+                    words[i0 + ii][w] = (words[i0 + ii][w] & ~nm) | (__ballot(in) & nm);
+                    nrec += (unsigned long long)__popcll(nm);
+                    C2 += (unsigned int)__popcll(nm);
+                }
+            __builtin_amdgcn_wave_barrier();  // s and the list are rewritten for the next pair
         }
     }
 // lane l < PX * W64 stores word (l / W64, l % W64)
@@ -475,7 +510,7 @@ static hipError_t launch_mask_k(const LaunchCtx &lc, size_t lds, const float *al
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     int64_t blocks = (int64_t)lc.num_cu * per_cu;
-    const int64_t px = W64 >= 3 ? kMaskPx / 2 : kMaskPx;
+    const int64_t px = W64 >= 2 ? kMaskPx / 2 : kMaskPx;
     const int64_t need = (N + px * kMaskWaves - 1) / (px * kMaskWaves);
     if (blocks > need) blocks = need;
     hipLaunchKernelGGL((k_mask_alpha<W64, OML>), dim3((unsigned)blocks), dim3(64 * kMaskWaves), lds, lc.stream,
@@ -491,10 +526,10 @@ hipError_t launch_mask_alpha(const LaunchCtx &lc, const float *alpha, int64_t N,
                              unsigned long long *recomputed, const double *pstats) {
     if (N <= 0) return hipSuccess;
     const int n = p * p;
-    const size_t patches = sizeof(double) * kMaskWaves * (size_t)n;
+    const size_t head = mask_lds_head(n, k);
     const size_t om = sizeof(float) * (size_t)k * n;
-    const bool oml = patches + om <= (size_t)150 * 1024;  // operator in LDS when it fits beside the patches
-    const size_t lds = patches + (oml ? om : 0);
+    const bool oml = head + om <= (size_t)160 * 1024;  // operator in LDS when it fits beside the patches
+    const size_t lds = head + (oml ? om : 0);
 #define CS_MASK_LAUNCH(WW)                                                                                       \
     return oml ? launch_mask_k<WW, true>(lc, lds, alpha, N, k, t_in, t_out, tau, tau_dev, rgb, H, W, p, wmask,  \
                                          omega, masks, recomputed, pstats)                                      \
