@@ -352,62 +352,58 @@ __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, i
 
 // Offsets of the fused gather's per-wave regions in the compact lists
 // (exclusive scans of their candidate and undecided-entry counts) and the two
-// totals; one workgroup.
+// totals; one workgroup.  The counts go through LDS in chunks of kScanChunk
+// (coalesced loads), each thread scanning 8 consecutive ones.
+constexpr int kScanChunk = 8192;
 __global__ __launch_bounds__(1024) void k_list_scan(const unsigned int *ccnt, const unsigned int *dcnt,
                                                     TauState *st, unsigned long long *coff,
                                                     unsigned long long *doff) {
+    __shared__ unsigned int lc[kScanChunk], ld[kScanChunk];
     __shared__ unsigned long long s[2][1024];
     const int nw = (int)st->rg_waves;
-    const int per = (nw + 1023) / 1024;
     const int t = threadIdx.x;
-    // counts read eight at a time (loads in flight together)
-    auto batch = [&](int i0, unsigned int (&cv)[8], unsigned int (&dv)[8]) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int r = t * per + i0 + u;
-            const bool ok = i0 + u < per && r < nw;
-            cv[u] = ok ? ccnt[r] : 0u;
-            dv[u] = ok ? dcnt[r] : 0u;
+    unsigned long long carry_c = 0, carry_d = 0;
+    for (int base = 0; base < nw; base += kScanChunk) {
+        for (int i = t; i < kScanChunk; i += 1024) {
+            const int r = base + i;
+            lc[i] = r < nw ? ccnt[r] : 0u;
+            ld[i] = r < nw ? dcnt[r] : 0u;
         }
-    };
-    unsigned long long sc = 0, sd = 0;
-    for (int i0 = 0; i0 < per; i0 += 8) {
-        unsigned int cv[8], dv[8];
-        batch(i0, cv, dv);
+        __syncthreads();
+        unsigned long long sc = 0, sd = 0;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            sc += cv[u];
-            sd += dv[u];
+            sc += lc[8 * t + u];
+            sd += ld[8 * t + u];
         }
-    }
-    s[0][t] = sc;
-    s[1][t] = sd;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const unsigned long long vc = t >= off ? s[0][t - off] : 0ull, vd = t >= off ? s[1][t - off] : 0ull;
+        s[0][t] = sc;
+        s[1][t] = sd;
         __syncthreads();
-        s[0][t] += vc;
-        s[1][t] += vd;
-        __syncthreads();
-    }
-    unsigned long long bc = s[0][t] - sc, bd = s[1][t] - sd;
-    for (int i0 = 0; i0 < per; i0 += 8) {
-        unsigned int cv[8], dv[8];
-        batch(i0, cv, dv);
+        for (int off = 1; off < 1024; off <<= 1) {
+            const unsigned long long vc = t >= off ? s[0][t - off] : 0ull, vd = t >= off ? s[1][t - off] : 0ull;
+            __syncthreads();
+            s[0][t] += vc;
+            s[1][t] += vd;
+            __syncthreads();
+        }
+        unsigned long long bc = carry_c + s[0][t] - sc, bd = carry_d + s[1][t] - sd;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int r = t * per + i0 + u;
-            if (i0 + u < per && r < nw) {
+            const int r = base + 8 * t + u;
+            if (r < nw) {
                 coff[r] = bc;
                 doff[r] = bd;
             }
-            bc += cv[u];
-            bd += dv[u];
+            bc += lc[8 * t + u];
+            bd += ld[8 * t + u];
         }
+        carry_c += s[0][1023];
+        carry_d += s[1][1023];
+        __syncthreads();  // lc, ld and s are rewritten by the next chunk
     }
-    if (t == 1023) {
-        st->ncand = s[0][1023];
-        st->n_d = s[1][1023];
+    if (t == 0) {
+        st->ncand = carry_c;
+        st->n_d = carry_d;
     }
 }
 
