@@ -113,12 +113,19 @@ __device__ __forceinline__ void mlp_tile_forward(const s16x4 (&xb)[kMlpMaxIn / 1
 }
 
 // ---- forward + backward of one batch (training and the gradient call) ----
+// One workgroup per 16-row tile; wave w owns the hidden blocks 2w and 2w + 1
+// (units 32w .. 32w + 31) of both hidden layers.  A layer's MFMA result
+// fragments are the next layer's B operand for the same lane, so they pass
+// between the waves through LDS as they are (lane l's fragment of block b at
+// [b][l]).  The output layer and dY (16 outputs, one block) are computed by
+// every wave alike; wave 0 writes them.
 __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
+    __shared__ s16x4 sh_h1[8][64], sh_h2[8][64], sh_dz2[8][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, j = lane & 15;
-    const int wt = blockIdx.x * 4 + wave;
+    const int wt = blockIdx.x;  // tile
     const int b0 = wt * 16;
-    if (b0 >= a.B) return;
+    if (b0 >= a.B) return;  // uniform over the workgroup
     const int rb = b0 + j;
     int64_t row = a.idx ? (int64_t)a.idx[rb] : (int64_t)rb;
     row = row < 0 ? 0 : (row >= a.n_rows ? a.n_rows - 1 : row);  // memory-safe on bad input
@@ -138,11 +145,62 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
     for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
 #pragma unroll
         for (int q = 0; q < 4; ++q) xb[ks][q] = to_bf16(16 * ks + 4 * g + q < a.in ? xv[ks][q] : 0.0f);
-    float z1[8][4], z2[8][4];
-    s16x4 h2b[8];
-    f32x4 y;
-    mlp_tile_forward<true>(xb, nks, a.W1b, a.in_pad, a.W2b, a.W3b, kMlpHid, a.b1, a.b2, a.b3, a.out, g, j, z1,
-                           z2, h2b, y);
+    // layer 1, own blocks
+    float z1[2][4], z2[2][4];
+    s16x4 h1b[2], h2b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int hb = 2 * wave + h;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const short *wr = a.W1b + (16 * hb + j) * a.in_pad + 4 * g;
+        s16x4 wf[kMlpMaxIn / 16];
+#pragma unroll
+        for (int ks = 0; ks < kMlpMaxIn / 16; ++ks) wf[ks] = ld4(wr + 16 * (ks < nks ? ks : nks - 1));
+#pragma unroll
+        for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
+            if (ks < nks) acc = mfma(wf[ks], xb[ks], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            z1[h][r] = acc[r] + a.b1[16 * hb + 4 * g + r];
+            h1b[h][r] = to_bf16(gelu(z1[h][r]));
+        }
+        sh_h1[hb][lane] = h1b[h];
+    }
+    __syncthreads();
+    // layer 2, own blocks, from every block of layer 1
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int hb = 2 * wave + h;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const short *wr = a.W2b + (16 * hb + j) * kMlpHid + 4 * g;
+        s16x4 wf[8];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) wf[kb] = ld4(wr + 16 * kb);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) acc = mfma(wf[kb], sh_h1[kb][lane], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            z2[h][r] = acc[r] + a.b2[16 * hb + 4 * g + r];
+            h2b[h][r] = to_bf16(gelu(z2[h][r]));
+        }
+        sh_h2[hb][lane] = h2b[h];
+    }
+    __syncthreads();
+    // output layer (every wave): y^T = W3 h2^T
+    f32x4 y = {0.f, 0.f, 0.f, 0.f};
+    {
+        const short *wr = a.W3b + j * kMlpHid + 4 * g;
+        s16x4 wf[8];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) wf[kb] = ld4(wr + 16 * kb);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) y = mfma(wf[kb], sh_h2[kb][lane], y);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = 4 * g + r;
+            y[r] += o < a.out ? a.b3[o] : 0.0f;
+        }
+    }
     // clipped targets t = max(l, max_i l_i - 20); the row max over the four
     // lanes that share row j (lanes j, j+16, j+32, j+48)
     float ell[4], mx = -INFINITY;
@@ -167,75 +225,86 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(MlpTrainArgs a) {
         dy[r] = scale * d;
         dyb[r] = to_bf16(dy[r]);
     }
-    // dH2^T = W3^T dY^T (K = 16 outputs), dZ2 = dH2 * GELU'(z2)
-    s16x4 dz2b[8];
-    float dz2[8][4];
+    // dH2^T = W3^T dY^T (K = 16 outputs), dZ2 = dH2 * GELU'(z2), own blocks
+    float dz2[2][4];
+    s16x4 dz2b[2];
 #pragma unroll
-    for (int hb = 0; hb < 8; ++hb) {
+    for (int h = 0; h < 2; ++h) {
+        const int hb = 2 * wave + h;
         const f32x4 acc = mfma(ld4(a.W3Tb + (16 * hb + j) * kMlpOutPad + 4 * g), dyb, f32x4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            dz2[hb][r] = acc[r] * gelu_grad(z2[hb][r]);
-            dz2b[hb][r] = to_bf16(dz2[hb][r]);
+            dz2[h][r] = acc[r] * gelu_grad(z2[h][r]);
+            dz2b[h][r] = to_bf16(dz2[h][r]);
         }
+        sh_dz2[hb][lane] = dz2b[h];
     }
-    // dH1^T = W2^T dZ2^T, dZ1 = dH1 * GELU'(z1)
-    float dz1[8][4];
+    __syncthreads();
+    // dH1^T = W2^T dZ2^T, dZ1 = dH1 * GELU'(z1), own blocks
+    float dz1[2][4];
 #pragma unroll
-    for (int hb = 0; hb < 8; ++hb) {
+    for (int h = 0; h < 2; ++h) {
+        const int hb = 2 * wave + h;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         const short *wr = a.W2Tb + (16 * hb + j) * kMlpHid + 4 * g;
+        s16x4 wf[8];
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb) acc = mfma(ld4(wr + 16 * kb), dz2b[kb], acc);
+        for (int kb = 0; kb < 8; ++kb) wf[kb] = ld4(wr + 16 * kb);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dz1[hb][r] = acc[r] * gelu_grad(z1[hb][r]);
+        for (int kb = 0; kb < 8; ++kb) acc = mfma(wf[kb], sh_dz2[kb][lane], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dz1[h][r] = acc[r] * gelu_grad(z1[h][r]);
     }
-    // feature-major BF16 stores for the weight-gradient products
+    // feature-major BF16 stores for the weight-gradient products (the input
+    // blocks split over the waves)
     const int B = a.B;
 #pragma unroll
     for (int ks = 0; ks < kMlpMaxIn / 16; ++ks)
-        if (ks < nks)
+        if (ks < nks && (ks & 3) == wave)
 #pragma unroll
             for (int q = 0; q < 4; ++q) a.Xt[(int64_t)(16 * ks + 4 * g + q) * B + rb] = xb[ks][q];
 #pragma unroll
-    for (int hb = 0; hb < 8; ++hb)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t u = (int64_t)(16 * hb + 4 * g + r) * B + rb;
-            a.H1t[u] = to_bf16(gelu(z1[hb][r]));
-            a.H2t[u] = h2b[hb][r];
-            a.DZ2t[u] = dz2b[hb][r];
-            a.DZ1t[u] = to_bf16(dz1[hb][r]);
+            const int64_t u = (int64_t)(16 * (2 * wave + h) + 4 * g + r) * B + rb;
+            a.H1t[u] = h1b[h][r];
+            a.H2t[u] = h2b[h][r];
+            a.DZ2t[u] = dz2b[h][r];
+            a.DZ1t[u] = to_bf16(dz1[h][r]);
         }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) a.DYt[(int64_t)(4 * g + r) * B + rb] = dyb[r];
     // bias gradients and squared error of the tile: sums over its 16 rows (FP32)
     float *bg = a.bgrad + (int64_t)wt * kMlpBiasStride;
 #pragma unroll
-    for (int hb = 0; hb < 8; ++hb)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            float s1 = dz1[hb][r], s2 = dz2[hb][r];
+            float s1 = dz1[h][r], s2 = dz2[h][r];
 #pragma unroll
             for (int off = 1; off < 16; off <<= 1) {
                 s1 += __shfl_xor(s1, off);
                 s2 += __shfl_xor(s2, off);
             }
+            const int u = 16 * (2 * wave + h) + 4 * g + r;
             if (j == 0) {
-                bg[16 * hb + 4 * g + r] = s1;
-                bg[kMlpHid + 16 * hb + 4 * g + r] = s2;
+                bg[u] = s1;
+                bg[kMlpHid + u] = s2;
             }
         }
+    if (wave == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        float s3 = dy[r];
+        for (int r = 0; r < 4; ++r) a.DYt[(int64_t)(4 * g + r) * B + rb] = dyb[r];
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) s3 += __shfl_xor(s3, off);
-        if (j == 0) bg[2 * kMlpHid + 4 * g + r] = s3;
+        for (int r = 0; r < 4; ++r) {
+            float s3 = dy[r];
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) s3 += __shfl_xor(s3, off);
+            if (j == 0) bg[2 * kMlpHid + 4 * g + r] = s3;
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) sq += __shfl_xor(sq, off);
+        if (lane == 0) a.lossp[wt] = sq;
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) sq += __shfl_xor(sq, off);
-    if (lane == 0) a.lossp[wt] = sq;
 }
 
 // ---- weight gradients: one wave per (16x16 output tile, row chunk) ----
@@ -697,8 +766,8 @@ hipError_t launch_mlp_bias_mean(const LaunchCtx &lc, const float *ell, int64_t n
 }
 
 hipError_t launch_mlp_fwdbwd(const LaunchCtx &lc, const MlpTrainArgs &a) {
-    const int waves = a.B / 16;
-    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, lc.stream, a);
+    const int tiles = a.B / 16;  // one workgroup per 16-row tile
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)tiles), dim3(256), 0, lc.stream, a);
     return hipGetLastError();
 }
 hipError_t launch_mlp_wgrad(const LaunchCtx &lc, const MlpWgradArgs &a) {
