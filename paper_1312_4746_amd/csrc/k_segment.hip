@@ -364,6 +364,103 @@ void k_pd_iter(PdArgs a, int t) {
     }
 }
 
+// The same iteration in two launches, for images too small to fill the chip
+// with one thread per pixel: one thread per (pixel, label) forms the new dual
+// vector (and multiplier) and the candidate, parked in the next u plane; then
+// one thread per pixel projects its candidates onto the simplex.  The
+// arithmetic is that of k_pd_iter element for element.
+template <typename T, bool MDL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 4)))
+void k_pd_dual(PdArgs a, int t, int nb) {
+#pragma clang fp contract(off)
+    __shared__ T red[4];
+    __shared__ double s_mb;
+    const int cur = t & 1, nxt = cur ^ 1;
+    const int L = a.L, H = a.H, W = a.W;
+    const int64_t N = a.N;
+    // workgroup -> (label, pixel block): an XCD takes consecutive pixel blocks
+    // of one label
+    const int64_t lin = xcd_block(blockIdx.x, gridDim.x);
+    const int l = (int)(lin / nb);
+    const int64_t pb = lin - (int64_t)l * nb;
+    const int64_t x = pb * 256 + threadIdx.x;
+    const bool in = x < N;
+    const int c = in ? (int)(x % W) : 0, r = in ? (int)(x / W) : 0;
+    const T s_xi = (T)a.sigma_xi, s_mu = (T)a.sigma_mu, t_u = (T)a.tau_u;
+    const T half_lam = (T)(0.5 * a.lambda);
+    if (MDL) {
+        if (threadIdx.x == 0) {
+            double m, mprev;
+            if (t == 0) {
+                m = mprev = a.mval[l];
+            } else {
+                mprev = a.mval[(int64_t)(t - 1) * L + l];
+                m = mprev - a.tau_m * (a.nu + a.msum[(int64_t)t * L + l]);
+                m = m < 0.0 ? 0.0 : (m > 1.0 ? 1.0 : m);
+                if (pb == 0) a.mval[(int64_t)t * L + l] = m;
+            }
+            s_mb = t == 0 ? m : 2.0 * m - mprev;
+        }
+        __syncthreads();
+    }
+    const int64_t o = (int64_t)l * N;
+    const T *G = (const T *)a.g;
+    T qx = 0, qy = 0, mu_n = 0;
+    if (in) {
+        const T rad = half_lam * G[x];
+        const T rad_l = c > 0 ? half_lam * G[x - 1] : (T)0;
+        const T rad_u = r > 0 ? half_lam * G[x - W] : (T)0;
+        const T v = pd_label((const T *)a.ub[cur] + o, (const T *)a.px[cur] + o, (const T *)a.py[cur] + o,
+                             (const T *)a.u[cur] + o, (const T *)a.f + o, MDL ? (const T *)a.mu[cur] + o : nullptr,
+                             x, c, r, H, W, s_xi, s_mu, t_u, MDL ? (T)s_mb : (T)0, rad, rad_l, rad_u, MDL, qx, qy,
+                             mu_n);
+        ((T *)a.px[nxt])[o + x] = qx;
+        ((T *)a.py[nxt])[o + x] = qy;
+        if constexpr (MDL) ((T *)a.mu[nxt])[o + x] = mu_n;
+        ((T *)a.u[nxt])[o + x] = v;  // the candidate, projected by k_pd_primal
+    }
+    if constexpr (MDL) {
+        const T sm = block_sum(mu_n, red);
+        if (threadIdx.x == 0) atomicAdd(a.msum + (int64_t)(t + 1) * L + l, (double)sm);
+    }
+}
+
+template <typename T, int LMAX>
+__global__ __launch_bounds__(256) void k_pd_primal(PdArgs a, int t) {
+#pragma clang fp contract(off)
+    const int cur = t & 1, nxt = cur ^ 1;
+    const int L = a.L;
+    const int64_t N = a.N;
+    const int64_t x = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (x >= N) return;
+    const T *U = (const T *)a.u[cur];
+    T *Un = (T *)a.u[nxt];
+    T *UBn = (T *)a.ub[nxt];
+    uint64_t act;
+    if constexpr (LMAX <= 16) {
+        T v[LMAX];
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) v[l] = l < L ? Un[(int64_t)l * N + x] : (T)0;
+        const T theta = simplex_theta<T, LMAX>(v, L, &act);
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+            if (l >= L) continue;
+            const int64_t o = (int64_t)l * N + x;
+            const T un = ((act >> l) & 1ull) ? v[l] - theta : (T)0;
+            UBn[o] = (T)2 * un - U[o];
+            Un[o] = un;
+        }
+    } else {
+        const T theta = simplex_theta_mem<T>(Un + x, N, L, &act);
+        for (int l = 0; l < L; ++l) {
+            const int64_t o = (int64_t)l * N + x;
+            const T un = ((act >> l) & 1ull) ? Un[o] - theta : (T)0;
+            UBn[o] = (T)2 * un - U[o];
+            Un[o] = un;
+        }
+    }
+}
+
 // Labels l(x) = argmax_i u_i(x) (ties to the lowest label) and u pixel-major.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pd_labels(PdArgs a, int buf, int32_t *labels, float *u_out,
@@ -460,30 +557,68 @@ __global__ __launch_bounds__(256) void k_pd_energy(PdArgs a, int buf, const int3
 // out: {primal, binary (without the label cost), dual}
 __global__ __launch_bounds__(64) void k_pd_energy_final(PdArgs a, const double *part, int nparts, double *out) {
 #pragma clang fp contract(off)
-    if (threadIdx.x != 0) return;
+    // lane i sums the parts of its contiguous chunk in order (loads eight at a
+    // time), then lane 0 adds the 64 lane sums in order: a fixed order
+    __shared__ double s3[3][64];
+    __shared__ double smx[64];
+    const int lane = threadIdx.x;
     const int L = a.L;
     const int64_t stride = 3 + L;
+    const int per = (nparts + 63) / 64, i0 = lane * per, i1 = i0 + per < nparts ? i0 + per : nparts;
     double p = 0.0, b = 0.0, d = 0.0;
-    for (int i = 0; i < nparts; ++i) {
-        p = p + part[(int64_t)i * stride + 0];
-        b = b + part[(int64_t)i * stride + 1];
-        d = d + part[(int64_t)i * stride + 2];
+    for (int i = i0; i < i1; i += 8) {
+        double v[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v[u][q] = i + u < i1 ? part[(int64_t)(i + u) * stride + q] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i + u < i1) {
+                p = p + v[u][0];
+                b = b + v[u][1];
+                d = d + v[u][2];
+            }
     }
+    s3[0][lane] = p;
+    s3[1][lane] = b;
+    s3[2][lane] = d;
+    __syncthreads();
+    double mdl_p = 0.0, mdl_d = 0.0;
     if (a.mdl) {
         for (int l = 0; l < L; ++l) {
-            double mx = part[3 + l];
-            for (int i = 1; i < nparts; ++i) mx = fmax(mx, part[(int64_t)i * stride + 3 + l]);
-            p = p + a.nu * mx;
-            const double s = a.nu + a.msum[(int64_t)a.iters * L + l];
-            d = d + (s < 0.0 ? s : 0.0);
+            double mx = -INFINITY;
+            for (int i = i0; i < i1; ++i) mx = fmax(mx, part[(int64_t)i * stride + 3 + l]);
+            smx[lane] = mx;
+            __syncthreads();
+            if (lane == 0) {
+                double m2 = smx[0];
+                for (int q = 1; q < 64; ++q) m2 = fmax(m2, smx[q]);
+                mdl_p = mdl_p + a.nu * m2;
+                const double sl = a.nu + a.msum[(int64_t)a.iters * L + l];
+                mdl_d = mdl_d + (sl < 0.0 ? sl : 0.0);
+            }
+            __syncthreads();
         }
     }
-    out[0] = p;
-    out[1] = b;
-    out[2] = d;
+    if (lane == 0) {
+        double pp = 0.0, bb = 0.0, dd = 0.0;
+        for (int q = 0; q < 64; ++q) {
+            pp = pp + s3[0][q];
+            bb = bb + s3[1][q];
+            dd = dd + s3[2][q];
+        }
+        out[0] = pp + mdl_p;
+        out[1] = bb;
+        out[2] = dd + mdl_d;
+    }
 }
 
 // ---- launchers ----
+// Two launches per iteration when one thread per pixel gives fewer waves than
+// eight per SIMD of the chip.
+bool pd_split(const LaunchCtx &lc, int64_t N) { return (N + 63) / 64 < (int64_t)lc.num_cu * 4 * 8; }
+
 hipError_t launch_edge_weight(const LaunchCtx &lc, const float *rgb, int H, int W, double gamma, double *mag,
                               double *part, int precision, void *g, float *g32, double *gamma_out) {
     const int64_t N = (int64_t)H * W;
@@ -512,6 +647,19 @@ hipError_t launch_pd_init(const LaunchCtx &lc, const PdArgs &a, int precision, c
 template <typename T>
 static void pd_iter_launch(const LaunchCtx &lc, const PdArgs &a, int t) {
     const dim3 grid((unsigned)((a.N + 255) / 256));
+    if (pd_split(lc, a.N)) {
+        const int nb = (int)((a.N + 255) / 256);
+        const dim3 g2((unsigned)((int64_t)nb * a.L));
+        if (a.mdl)
+            hipLaunchKernelGGL((k_pd_dual<T, true>), g2, dim3(256), 0, lc.stream, a, t, nb);
+        else
+            hipLaunchKernelGGL((k_pd_dual<T, false>), g2, dim3(256), 0, lc.stream, a, t, nb);
+        if (a.L <= 16)
+            hipLaunchKernelGGL((k_pd_primal<T, 16>), grid, dim3(256), 0, lc.stream, a, t);
+        else
+            hipLaunchKernelGGL((k_pd_primal<T, 64>), grid, dim3(256), 0, lc.stream, a, t);
+        return;
+    }
     if (a.L <= 16) {
         if (a.mdl)
             hipLaunchKernelGGL((k_pd_iter<T, 16, true>), grid, dim3(256), 0, lc.stream, a, t);

@@ -141,6 +141,20 @@ def test_bsds_shape(ctx, prec):
     _check(ctx, w.rgb, ll, 1.0, 0.0, 100, prec)
 
 
+@pytest.mark.parametrize("prec,nu,L", [("fp64", 0.0, 4), ("fp32", 0.0, 4), ("fp32", 40.0, 3), ("fp32", 0.0, 20)],
+                         ids=["fp64", "fp32", "fp32_mdl", "fp32_L20"])
+def test_one_launch_form_on_a_large_image(ctx, prec, nu, L):
+    """Images of at least 524 288 pixels (eight waves per SIMD with one thread
+    per pixel) take the one-launch iteration; smaller ones the two-launch form
+    (every other case here).  768 x 704 pixels, 12 iterations (5 with 20
+    labels, the kernel that parks its candidates in memory)."""
+    w = make_workload("seg_large", H=704, W=768, R=6, p=3, k=8, seed=13, per_region=1)
+    w.L = L
+    w.region = w.region % L
+    ll = _synthetic_term(w, seed=4)
+    _check(ctx, w.rgb, ll, 1.5, nu, 12 if L <= 16 else 5, prec)
+
+
 def test_relaxation_gap_and_dice_on_the_tiny_workload(ctx):
     """The rounded solution within 1 % of the dual bound (the paper's
     typical figure), and the boundary term raises the agreement with the
