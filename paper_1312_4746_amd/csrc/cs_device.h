@@ -25,43 +25,6 @@ __device__ __forceinline__ double gray64(const float *rgb, int64_t N, int64_t id
     return gray64_of(rgb[idx], rgb[N + idx], rgb[2 * N + idx]);
 }
 
-// sum_t O_jt s_t, sequential in t, no FMA.
-__device__ __noinline__ inline double dot64(const float *om, const double *s, int n) {
-#pragma clang fp contract(off)
-    double acc = 0.0;
-    for (int t = 0; t < n; ++t) acc = acc + (double)om[t] * s[t];
-    return acc;
-}
-
-// Exact normalised patch of one pixel from global memory: q_t = w_t g_t,
-// mu = sum_t q_t / n, z = q - mu, nu2 = sum_t z_t^2, s = z / sqrt(nu2) (or 0),
-// every sum sequential in t.  Same operations as the LDS path of the
-// analysis kernel.
-__device__ __noinline__ inline void patch_s64(const float *rgb, int H, int W, int p,
-                                              const double *wmask, int64_t pix, double *s) {
-#pragma clang fp contract(off)
-    const int64_t N = (int64_t)H * W;
-    const int h = (p - 1) / 2, n = p * p;
-    const int row = (int)(pix / W), col = (int)(pix - (int64_t)(pix / W) * W);
-    for (int t = 0; t < n; ++t) {
-        int u = t / p, v = t - u * p;
-        int rr = reflect_idx(row + u - h, H), cc = reflect_idx(col + v - h, W);
-        s[t] = wmask[t] * gray64(rgb, N, (int64_t)rr * W + cc);
-    }
-    double sum = 0.0;
-    for (int t = 0; t < n; ++t) sum = sum + s[t];
-    double mu = sum / (double)n;
-    for (int t = 0; t < n; ++t) s[t] = s[t] - mu;
-    double nu2 = 0.0;
-    for (int t = 0; t < n; ++t) nu2 = nu2 + s[t] * s[t];
-    if (nu2 == 0.0) {
-        for (int t = 0; t < n; ++t) s[t] = 0.0;
-        return;
-    }
-    double nu = sqrt(nu2);
-    for (int t = 0; t < n; ++t) s[t] = s[t] / nu;
-}
-
 // Exact FP64 a_j = sum_t O_jt s_t of pixel pix (om = row j of O): the
 // normalised Gaussian-masked gray patch rebuilt from the image in the
 // oracle's operation order, q_t = w_t g_t, s_t = (q_t - mu) / sqrt(nu2) (0 when
