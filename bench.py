@@ -217,7 +217,7 @@ def surrogate_line(args) -> dict:
     spix, slab = dev(w.sample_pix), dev(w.sample_label)
     tpix = dev(w.train_pix)
     prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
-                       rho_floor_px=w.rho_floor_px)
+                       rho_floor_px=w.rho_floor_px, colour_levels=w.colour_levels)
     ctx = Context(0)
     nw = (w.k + 63) // 64
     a32 = torch.empty((w.N, w.k), dtype=torch.float32, device="cuda")
@@ -356,7 +356,7 @@ def segment_line(args, config: int = 1) -> dict:
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     rgb = dev(w.rgb)
     prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
-                       rho_floor_px=w.rho_floor_px)
+                       rho_floor_px=w.rho_floor_px, colour_levels=w.colour_levels)
     ctx = Context(0)
     _, masks, _ = ctx.cosupport_median(rgb, w.p, w.mask_sigma, dev(w.omega), w.tau_frac)
     ll = ctx.label_loglik(rgb, masks, w.k, dev(w.sample_pix), dev(w.sample_label), w.L, prm)
@@ -555,7 +555,7 @@ def main():
     rgb, om = dev(w.rgb), dev(w.omega)
     spix, slab = dev(w.sample_pix), dev(w.sample_label)
     prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
-                       rho_floor_px=w.rho_floor_px)
+                       rho_floor_px=w.rho_floor_px, colour_levels=w.colour_levels)
     ctx = Context(0)
     alpha = torch.empty((w.N, w.k), dtype=torch.float32, device="cuda")
     masks = torch.empty((w.N, (w.k + 63) // 64), dtype=torch.int64, device="cuda")

@@ -194,6 +194,9 @@ typedef struct {
     double beta_scale;   /* b in beta_i(x) = b * rho_i(x) (beta proportional to rho)  */
     double rho_floor_px; /* rho_i(x) = alpha_rho * max(d_i(x), rho_floor_px)          */
     int normalise;       /* 1: subtract log sum_i exp l_i(x) (labels normalise)       */
+    int colour_levels;   /* 0: colours are any floats; n in 1..255: every colour      */
+                         /* value is a multiple of 1/n in [0, 255/n] (n = 255 for     */
+                         /* 8-bit images), see below                                  */
 } cs_loglik_params;
 
 /*
@@ -214,6 +217,16 @@ typedef struct {
  *   pix_subset    device, n_subset int32 pixel indices, or NULL for all N pixels
  *   loglik        device out, (n_subset or N) * L float32, loglik[r*L + i]
  *                 (may be NULL when pix_subset is non-NULL and n_subset is 0)
+ * Colour levels: with colour_levels = n > 0 the matrix-core kernel takes each
+ * colour value c as the integer q = rint(c n) (clamped to 0..255), so that the
+ * squared colour distance of two pixels is the integer sum over channels of
+ * (q_x - q_y)^2, formed exactly on the matrix cores and scaled by 1/n^2; for a
+ * value that is the FP32 rounding of a multiple of 1/n this differs from the
+ * FP32 input by less than 2^-24 relative.  Values that are not such multiples
+ * are rounded to the nearest one (the data term of the rounded image); with
+ * the finite check on (cs_set_check_finite), such a value, or one outside
+ * [0, 255/n], returns CS_ERR_ARG.  The exact per-pixel kernel and the
+ * coefficients use the FP32 values either way.
  * Route: images up to 2048 x 2048 go to the matrix-core kernel, the full
  * image in 8 x 4 pixel tiles, a subset of 1024 or more entries in tiles of 32
  * consecutive entries (duplicates allowed); smaller subsets and larger images

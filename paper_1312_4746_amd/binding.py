@@ -30,7 +30,7 @@ _P, _I, _I64, _D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_doubl
 class _LoglikParamsC(ctypes.Structure):
     _fields_ = [("alpha_rho", ctypes.c_double), ("sigma_c", ctypes.c_double),
                 ("beta_scale", ctypes.c_double), ("rho_floor_px", ctypes.c_double),
-                ("normalise", ctypes.c_int)]
+                ("normalise", ctypes.c_int), ("colour_levels", ctypes.c_int)]
 
 
 class _LoglikStatsC(ctypes.Structure):
@@ -175,10 +175,13 @@ class LoglikParams:
     beta_scale: float = 1.0
     rho_floor_px: float = 1.0
     normalise: bool = False
+    # 0: colours are any floats; n in 1..255: every colour value is a multiple
+    # of 1/n (255 for 8-bit images)
+    colour_levels: int = 0
 
     def c(self) -> _LoglikParamsC:
         return _LoglikParamsC(self.alpha_rho, self.sigma_c, self.beta_scale, self.rho_floor_px,
-                              int(bool(self.normalise)))
+                              int(bool(self.normalise)), int(self.colour_levels))
 
 
 @dataclasses.dataclass

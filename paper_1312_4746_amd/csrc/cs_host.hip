@@ -274,24 +274,26 @@ int check_patch_args(cs_ctx *ctx, const float *rgb, int H, int W, int p, double 
 // Optional finite check (cs_set_check_finite): the n0 floats at a and the n1
 // floats at b (either may be null) are scanned on the device; the host reads
 // the flag (this synchronises the stream) and fails with CS_ERR_NONFINITE
-// before anything else is launched.
-int check_inputs_finite(cs_ctx *ctx, const float *a, int64_t n0, const float *b, int64_t n1) {
+// before anything else is launched.  With colour levels n > 0 the values at a
+// (colours) must also be multiples of 1/n in [0, 255/n] (else CS_ERR_ARG).
+int check_inputs_finite(cs_ctx *ctx, const float *a, int64_t n0, const float *b, int64_t n1, int levels) {
     if (!ctx->check_finite) return CS_OK;
     unsigned int *flag = ctx->dctr + kCtrNonFinite;
     const LaunchCtx lc = lc_of(ctx);
-    if (a) HIP_TRY(launch_check_finite(lc, a, n0, flag));
-    if (b) HIP_TRY(launch_check_finite(lc, b, n1, flag));
+    if (a) HIP_TRY(launch_check_finite(lc, a, n0, levels, flag));
+    if (b) HIP_TRY(launch_check_finite(lc, b, n1, 0, flag));
     HIP_TRY(hipMemcpyAsync(ctx->pinned, flag, sizeof(unsigned int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     unsigned int f;
     std::memcpy(&f, ctx->pinned, sizeof f);
     if (!f) return CS_OK;
     HIP_TRY(launch_fill_u32(lc, flag, 1, 0u));  // the counter is zero between calls
-    return fail(ctx, CS_ERR_NONFINITE, "an input (rgb or omega) holds a NaN or an infinity");
+    if (f & 1u) return fail(ctx, CS_ERR_NONFINITE, "an input (rgb or omega) holds a NaN or an infinity");
+    return fail(ctx, CS_ERR_ARG, "a colour is not a multiple of 1/%d in [0, 255/%d]", levels, levels);
 }
 
 int check_patch_inputs_finite(cs_ctx *ctx, const float *rgb, int H, int W, const float *omega, int k, int p) {
-    return check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, omega, (int64_t)k * p * p);
+    return check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, omega, (int64_t)k * p * p, 0);
 }
 
 // Coefficient of the proven bound |a_rounded - a| <= coef * ||O_j||_2 (unit-norm patch):
@@ -838,6 +840,8 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
     auto pos = [](double v) { return v > 0.0 && std::isfinite(v); };
     if (!pos(prm->alpha_rho) || !pos(prm->sigma_c) || !pos(prm->beta_scale) || !pos(prm->rho_floor_px))
         return fail(ctx, CS_ERR_ARG, "alpha_rho, sigma_c, beta_scale and rho_floor_px must be positive and finite");
+    if (prm->colour_levels < 0 || prm->colour_levels > 255)
+        return fail(ctx, CS_ERR_ARG, "colour_levels must be in 0..255 (got %d)", prm->colour_levels);
     const int64_t N = (int64_t)H * W;
     const int64_t npix = pix_subset ? n_subset : N;
     if (npix < 0) return fail(ctx, CS_ERR_ARG, "n_subset must be >= 0");
@@ -845,7 +849,7 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
     if (tiles * L > (((int64_t)1 << 31) - 1)) return fail(ctx, CS_ERR_ARG, "too many pixels x labels");
     HIP_TRY(hipSetDevice(ctx->device));
     {
-        int rcf = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, nullptr, 0);
+        int rcf = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, nullptr, 0, prm->colour_levels);
         if (rcf) return rcf;
     }
     const int nblocks = (int)((M + 255) / 256);
@@ -976,6 +980,7 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         pr.segs = segs;
         pr.Mpad = segs.pseg[L];
         pr.cscale = cscale;
+        pr.levels = prm->colour_levels;
         pr.feat = (uint8_t *)(ctx->ws + o_feat);
         pr.rec = (float *)(ctx->ws + o_srec);
         pr.rgb = rgb;
@@ -1083,6 +1088,11 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         fa.ngroups = (int)ngroups;
         fa.fix_cap = (int)(ntiles_pad * L);
         fa.sigma_c = pa.sigma_c;
+        fa.levels = prm->colour_levels;
+        fa.kcol = prm->colour_levels > 0
+                      ? (float)(-1.4426950408889634 / (2.0 * prm->sigma_c * prm->sigma_c *
+                                                       (double)prm->colour_levels * prm->colour_levels))
+                      : 0.0f;
         fa.texture = pa.texture_in_sum;
         fa.list = listed ? pix_subset : nullptr;
         fa.nlist = listed ? npix : 0;
@@ -1619,7 +1629,7 @@ int cs_edge_weight(cs_ctx *ctx, const float *rgb, int H, int W, double gamma, fl
     if (!g) return fail(ctx, CS_ERR_ARG, "g must be non-null");
     if (std::isnan(gamma) || std::isinf(gamma)) return fail(ctx, CS_ERR_ARG, "gamma must be finite");
     HIP_TRY(hipSetDevice(ctx->device));
-    if ((rc = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, nullptr, 0))) return rc;
+    if ((rc = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, nullptr, 0, 0))) return rc;
     const int64_t N = (int64_t)H * W;
     Carve cv;
     const size_t o_mag = cv.take(sizeof(double) * (size_t)N);
@@ -1649,7 +1659,7 @@ int cs_segment(cs_ctx *ctx, const float *rgb, int H, int W, const float *loglik,
     if (prm->precision != CS_FP32 && prm->precision != CS_FP64)
         return fail(ctx, CS_ERR_ARG, "precision must be CS_FP32 or CS_FP64");
     HIP_TRY(hipSetDevice(ctx->device));
-    if ((rc = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, loglik, (int64_t)H * W * L))) return rc;
+    if ((rc = check_inputs_finite(ctx, rgb, 3 * (int64_t)H * W, loglik, (int64_t)H * W * L, 0))) return rc;
     const int64_t N = (int64_t)H * W;
     const int64_t nb = (N + 255) / 256;
     const bool mdl = prm->nu > 0.0;
@@ -1753,7 +1763,7 @@ int cs_unsupervised_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const ui
     for (int i = 0; i < Kc + Kt; ++i)
         if (init.pix[i] < 0 || init.pix[i] >= N) return fail(ctx, CS_ERR_ARG, "an initial pixel is out of range");
     HIP_TRY(hipSetDevice(ctx->device));
-    if ((rc = check_inputs_finite(ctx, rgb, 3 * N, nullptr, 0))) return rc;
+    if ((rc = check_inputs_finite(ctx, rgb, 3 * N, nullptr, 0, 0))) return rc;
     const int nw = (k + 63) / 64;
     const int64_t nb = (N + 255) / 256;
     Carve cv;

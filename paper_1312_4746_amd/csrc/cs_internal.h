@@ -199,7 +199,7 @@ hipError_t tau_finish(const LaunchCtx &lc, const float *rgb, int H, int W, int p
 constexpr int kCtrSampleCount = 0, kCtrNonFinite = 1, kCtrWords = 64;
 // Sets *flag (device, zero before) to 1 when any of the n floats at p is a NaN
 // or an infinity.
-hipError_t launch_check_finite(const LaunchCtx &lc, const float *p, int64_t n, unsigned int *flag);
+hipError_t launch_check_finite(const LaunchCtx &lc, const float *p, int64_t n, int levels, unsigned int *flag);
 
 // ---- co-support at frac * median|a| fused with the candidate gather
 // (k_cosupport_median.hip) ----
@@ -328,11 +328,12 @@ struct ParzenFastArgs {
     const uint64_t *masks;
     const uint8_t *feat;   // Mpad x 128*ksteps FP6 sample features (swizzled rows, 32 B per 32 features)
                            // (positions below 2048: the location product is exact)
-    const float *rec;      // per chunk of 64 slots: BF16 location pieces (2 x 1 KiB), colours (1 KiB)
+    const float *rec;      // per chunk of 64 slots: BF16 location pieces (2 x 1 KiB), colours (1 KiB:
+                           // scaled floats, or BF16 colour pieces with levels > 0)
     const float4 *coef;    // tiled: [label][group*4 + tile][kTilePix] {nA, nB, -R, K}
     const float4 *pix4;    // tiled: [group*4 + tile][kTilePix] {scaled r, g, b, |A|}
     const uint32_t *aop;   // [tile][row block][step][lane][8]: FP6 texture operands (6 of 8 dwords)
-    const uint8_t *abf;    // [tile][row block][lane][16 B]: BF16 location operands
+    const uint8_t *abf;    // [tile][row block][lane][16 B]: BF16 location (and colour) operands
     float *loglik;
     unsigned int *work_counter;  // kParzenQueues counters, kQueueStride apart, zero at launch
     unsigned int *fix_count;  // [0] queued (label, tile), [1] rescaled wave-chunks, [2] overflowed passes
@@ -345,6 +346,11 @@ struct ParzenFastArgs {
     const int32_t *list;   // pixel list (tile slots are its entries) or null (tile grid)
     int64_t nlist;
     double sigma_c;
+    // colour levels n > 0: colours are the integers rint(c n) and the colour
+    // term is kcol times their squared distance (kcol = -log2(e) / (2 sigma_c^2
+    // n^2)), formed on the matrix cores; 0: scaled float colours on the VALU
+    int levels;
+    float kcol;
     // passed by value (kernel arguments): [0..L] first chunk of each label's
     // padded segment (chunk units), [L+1 .. 2L] the labels by decreasing
     // sample count, [2L+1 .. 3L] the 16-sample steps of each label's last
@@ -360,6 +366,7 @@ struct PrepArgs {
     StreamSegs segs;
     int64_t Mpad;
     float cscale;
+    int levels;            // colour levels n (0: float colours; see ParzenFastArgs::levels)
     uint8_t *feat;
     float *rec;
     const float *rgb;

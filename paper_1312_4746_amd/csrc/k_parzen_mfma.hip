@@ -88,6 +88,15 @@ __device__ __forceinline__ uint32_t fp6_of_int(int v) {
     return code | (v < 0 ? 0x20u : 0u);
 }
 
+// Colour value c at n levels as a centred integer: rint(c n) clamped to
+// 0..255, minus 128 (so -128..127; for c the FP32 value of a multiple of 1/n,
+// c n is within two ulps of that integer and rounds to it).
+__device__ __forceinline__ int colour_level(float c, int n) {
+    float q = rintf(c * (float)n);
+    q = fminf(fmaxf(q, 0.0f), 255.0f);  // a NaN becomes 0
+    return (int)q - 128;
+}
+
 // Texture feature f of a pixel (PIX) or a sample with co-support bits `bits`
 // (bit j of word j / 32) and |co-support| c: see the header.
 template <bool PIX>
@@ -143,10 +152,13 @@ __device__ __forceinline__ int swz(int p, int row) { return (p & ~7) | ((p & 7) 
 // reading 16 consecutive slots touch distinct LDS banks: the BF16 location
 // pieces for K 0..7 [1, 1, 1, sx_h, sx_l, sx_h, sx_l, sy_h] and K 8..15
 // [sy_l, sy_h, sy_l, q_h, q_m, q_l, far, 0] (q = sx^2 + sy^2), then the
-// scaled colours {r, g, b, 0}.  Padding slots have zero features and pieces
-// except far = 2^100.
+// scaled colours {r, g, b, 0}, or with colour levels the BF16 colour pieces
+// for K 16..23 [-2 r, -2 g, -2 b, 1, 1, s_h, s_l, 0] of the centred integer
+// colours (s = r^2 + g^2 + b^2 < 2^16, split at bit 8).  Padding slots have
+// zero features and pieces except far = 2^100.
 __device__ __forceinline__ void stream_build(const SampleRec *recs, int k, int KP, int L, const StreamSegs &segs,
-                                             int64_t Mpad, float cscale, uint8_t *feat, float *rec, int bid) {
+                                             int64_t Mpad, float cscale, int levels, uint8_t *feat, float *rec,
+                                             int bid) {
     const int64_t s = (int64_t)bid * 256 + threadIdx.x;
     if (s >= Mpad) return;
     int l = 0;
@@ -192,10 +204,30 @@ __device__ __forceinline__ void stream_build(const SampleRec *recs, int k, int K
         r1[t] = pk[4 + t];
     }
     float *rcol = rc + 8 * kChunkS + 4 * row;
-    rcol[0] = col[0];
-    rcol[1] = col[1];
-    rcol[2] = col[2];
-    rcol[3] = 0.0f;
+    if (levels > 0) {
+        float cp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (real) {
+            const uint32_t *rw = recs[segs.seg[l] + j].w;
+            int cq[3], ss = 0;
+            for (int c = 0; c < 3; ++c) {
+                cq[c] = colour_level(__uint_as_float(rw[2 + c]), levels);
+                ss += cq[c] * cq[c];
+                cp[c] = (float)(-2 * cq[c]);
+            }
+            cp[3] = 1.0f;
+            cp[4] = 1.0f;
+            cp[5] = (float)(ss & ~0xFF);
+            cp[6] = (float)(ss & 0xFF);
+        }
+        uint32_t *rq = reinterpret_cast<uint32_t *>(rcol);
+        for (int t = 0; t < 4; ++t)
+            rq[t] = (uint32_t)(uint16_t)bf16_bits(cp[2 * t]) | ((uint32_t)(uint16_t)bf16_bits(cp[2 * t + 1]) << 16);
+    } else {
+        rcol[0] = col[0];
+        rcol[1] = col[1];
+        rcol[2] = col[2];
+        rcol[3] = 0.0f;
+    }
     uint32_t *fo = reinterpret_cast<uint32_t *>(feat + s * KP);
     for (int grp = 0; grp < KP / 32; ++grp) {  // features 32 grp .. 32 grp + 31: logical slots 2 grp, 2 grp + 1
         uint32_t o[6] = {0, 0, 0, 0, 0, 0};
@@ -246,10 +278,15 @@ __device__ __forceinline__ void pixel_tiles(const float *rgb, const uint64_t *ma
 //    slots);
 //  * BF16 location operand (16 B per lane): K 0..7 [|p|^2 pieces (3), -2 px
 //    pieces (2, each twice), -2 py high] for g = 0, K 8..15 [-2 py high, -2 py
-//    low (twice), 1, 1, 1, 1 (far term), 0] for g = 1, zeros for g >= 2.
-__device__ __forceinline__ void pixel_operands(const uint64_t *masks, int H, int W, int k, int tiles_x, int ntiles,
-                                               const int32_t *list, int64_t nlist, int64_t nthreads, int ksteps,
-                                               uint32_t *aop, uint4 *abf, int bid) {
+//    low (twice), 1, 1, 1, 1 (far term), 0] for g = 1, zeros for g = 3 and,
+//    without colour levels, for g = 2; with colour levels g = 2 holds the
+//    colour pieces K 16..23 [r, g, b, s_h, s_l, 1, 1, 0] of the centred integer
+//    colours (s = r^2 + g^2 + b^2 split at bit 8), so that against the sample
+//    pieces the product is the squared colour distance.
+__device__ __forceinline__ void pixel_operands(const float *rgb, const uint64_t *masks, int H, int W, int k,
+                                               int tiles_x, int ntiles, const int32_t *list, int64_t nlist,
+                                               int64_t nthreads, int ksteps, int levels, uint32_t *aop, uint4 *abf,
+                                               int bid) {
     const int64_t s = (int64_t)bid * 256 + threadIdx.x;
     if (s >= nthreads) return;
     const int lane = (int)(s & 63);
@@ -288,6 +325,15 @@ __device__ __forceinline__ void pixel_operands(const uint64_t *masks, int H, int
         e[3] = xh; e[4] = xh; e[5] = xl; e[6] = xl; e[7] = yh;
     } else if (g == 1) {
         e[0] = yh; e[1] = yl; e[2] = yl; e[3] = 1.0f; e[4] = 1.0f; e[5] = 1.0f; e[6] = 1.0f;
+    } else if (g == 2 && levels > 0 && v) {
+        const int64_t N = (int64_t)H * W;
+        int ss = 0;
+        for (int c = 0; c < 3; ++c) {
+            const int cq = colour_level(rgb[c * N + pix], levels);
+            ss += cq * cq;
+            e[c] = (float)cq;
+        }
+        e[3] = (float)(ss & ~0xFF); e[4] = (float)(ss & 0xFF); e[5] = 1.0f; e[6] = 1.0f;
     }
     uint32_t pk[4];
     for (int t = 0; t < 4; ++t)
@@ -301,7 +347,7 @@ __device__ __forceinline__ void pixel_operands(const uint64_t *masks, int H, int
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     int b = blockIdx.x;
     if (b < a.b_stream) {
-        stream_build(a.recs, a.k, a.KP, a.L, a.segs, a.Mpad, a.cscale, a.feat, a.rec, b);
+        stream_build(a.recs, a.k, a.KP, a.L, a.segs, a.Mpad, a.cscale, a.levels, a.feat, a.rec, b);
         return;
     }
     b -= a.b_stream;
@@ -311,8 +357,8 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
         return;
     }
     b -= a.b_tiles;
-    pixel_operands(a.masks, a.H, a.W, a.k, a.tiles_x, a.ntiles, a.list, a.nlist, a.nthreads, a.ksteps, a.aop,
-                   a.abf, b);
+    pixel_operands(a.rgb, a.masks, a.H, a.W, a.k, a.tiles_x, a.ntiles, a.list, a.nlist, a.nthreads, a.ksteps,
+                   a.levels, a.aop, a.abf, b);
 }
 
 hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
@@ -329,7 +375,10 @@ hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
 // step, two with the wider feature rows.
 // TEX = false: the texture factor stays out of the sum (eq:joined forms):
 // no feature stream, no FP6 products, only the location and colour terms.
-template <int KSTEPS, bool TEX, bool LIST>
+// COLQ: colour levels (ParzenFastArgs::levels > 0): the squared colour
+// distance is a third matrix-core product (BF16, K 16..23 of the location
+// operands, exact integers) and the pixel operands stay in registers.
+template <int KSTEPS, bool TEX, bool LIST, bool COLQ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 ? 4 : 2)))
 void k_parzen_mfma(ParzenFastArgs a) {
     constexpr int RB = kParzenRB;
@@ -344,7 +393,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
     __shared__ __align__(16) float s_rec1[kRecChunkF];
     // each wave's BF16 location operands (read at every step; kept here
     // rather than in registers, which the kernel has none left of)
-    __shared__ __align__(16) s16x8 s_abf[4][RB][64];
+    __shared__ __align__(16) s16x8 s_abf[4][COLQ ? 1 : RB][64];
     __shared__ int s_item, s_queue;
     // overflow retry: any wave of the workgroup overflowed in the last pass,
     // and per lane the pixels (bit 4 rb + r) whose sums overflowed
@@ -366,6 +415,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
         for (int h = 0; h < 2; ++h) foff[q][h] = jl * KP + 16 * swz(8 * q + 2 * g + h, jl);
     const int loff = (g & 1) * (16 * kChunkS) + 16 * jl;  // location pieces, K 0..7 or 8..15
     const int coff = 32 * kChunkS + 16 * jl;              // colours
+    // B operand of the location (and colour) products: with colour levels the
+    // lanes g = 2 take the colour pieces K 16..23 (the other lanes' K 16..31
+    // meet zero pixel pieces in one product or the other)
+    const int boff = COLQ && g == 2 ? coff : loff;
     uint32_t n_rescale = 0;  // wave-chunks whose reference moved (wave-uniform)
     uint32_t n_overflow = 0; // (label, tile) items handed to the exact kernel on overflow
 
@@ -479,10 +532,12 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 const int ti = (2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r;
                 const bool v = slot_ok(rb, r);
                 anyvalid |= v;
-                const float4 c = pt[ti];
-                pr[rb][r] = c.x;
-                pg[rb][r] = c.y;
-                pb[rb][r] = c.z;
+                if constexpr (!COLQ) {
+                    const float4 c = pt[ti];
+                    pr[rb][r] = c.x;
+                    pg[rb][r] = c.y;
+                    pb[rb][r] = c.z;
+                }
                 const float4 q = cf[ti];
                 nA[rb][r] = q.x;
                 nB[rb][r] = q.y;
@@ -498,6 +553,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
         // k_pixel_operands): the FP6 texture operand into registers, the BF16
         // location operand straight into LDS (read at every step)
         i32x8 Aop[RB][KSTEPS];
+        // with colour levels: the location and colour operands of the lane, in
+        // registers (the lane's 16-byte slot holds the location pieces for g <
+        // 2, the colour pieces for g = 2, zeros for g = 3)
+        s16x8 Aloc[RB], Acol[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             if constexpr (TEX) {
@@ -512,7 +571,14 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 }
             }
             const uint8_t *bsrc = a.abf + (((int64_t)tile * RB + rb) * 64 + lane) * 16;
-            __builtin_amdgcn_global_load_lds(bsrc, (lds_void *)&s_abf[wave][rb][0], 16, 0, 0);
+            if constexpr (COLQ) {
+                const s16x8 x = *reinterpret_cast<const s16x8 *>(bsrc);
+                const s16x8 z = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                Aloc[rb] = g < 2 ? x : z;
+                Acol[rb] = g == 2 ? x : z;
+            } else {
+                __builtin_amdgcn_global_load_lds(bsrc, (lds_void *)&s_abf[wave][rb][0], 16, 0, 0);
+            }
         }
         bool item_bad = __ballot(weak) != 0ull;
         if (item_bad) active = false;
@@ -552,9 +618,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
                         Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w, (int)hi2.x, (int)hi2.y, 0, 0};
                     }
                 }
-                const s16x8 Bbf = *reinterpret_cast<const s16x8 *>(Rs + loff);
-                const float4 col = *reinterpret_cast<const float4 *>(Rs + coff);
-                f32x4 T[RB], Q[RB];
+                const s16x8 Bbf = *reinterpret_cast<const s16x8 *>(Rs + boff);
+                float4 col = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if constexpr (!COLQ) col = *reinterpret_cast<const float4 *>(Rs + coff);
+                f32x4 T[RB], Q[RB], C[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
                     T[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -565,20 +632,33 @@ void k_parzen_mfma(ParzenFastArgs a) {
                             T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(Aop[rb][q], Bop[q], T[rb],
                                                                                       2, 2, 0, 127, 0, 127);
                     }
-                    Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, s_abf[wave][rb][al]),
-                                                                    __builtin_bit_cast(bf16x8, Bbf),
-                                                                    f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    if constexpr (COLQ) {
+                        Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Aloc[rb]),
+                                                                        __builtin_bit_cast(bf16x8, Bbf),
+                                                                        f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                        C[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Acol[rb]),
+                                                                        __builtin_bit_cast(bf16x8, Bbf),
+                                                                        f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    } else {
+                        Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, s_abf[wave][rb][al]), __builtin_bit_cast(bf16x8, Bbf),
+                            f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    }
                 }
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float dr = pr[rb][r] - col.x, dg = pg[rb][r] - col.y, db = pb[rb][r] - col.z;
                         float u = TEX ? fmaf(T[rb][r], nB[rb][r], nR[rb][r]) : nR[rb][r];
                         u = fmaf(Q[rb][r], nA[rb][r], u);
-                        u = fmaf(-dr, dr, u);
-                        u = fmaf(-dg, dg, u);
-                        u = fmaf(-db, db, u);
+                        if constexpr (COLQ) {
+                            u = fmaf(C[rb][r], a.kcol, u);
+                        } else {
+                            const float dr = pr[rb][r] - col.x, dg = pg[rb][r] - col.y, db = pb[rb][r] - col.z;
+                            u = fmaf(-dr, dr, u);
+                            u = fmaf(-dg, dg, u);
+                            u = fmaf(-db, db, u);
+                        }
                         S[rb][r] += __builtin_amdgcn_exp2f(u);
                     }
             }
@@ -724,32 +804,34 @@ void k_parzen_mfma(ParzenFastArgs a) {
     }
 }
 
-template <int KSTEPS, bool TEX, bool LIST>
+template <int KSTEPS, bool TEX, bool LIST, bool COLQ>
 static hipError_t launch_mfma_k(const LaunchCtx &lc, const ParzenFastArgs &a) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS, TEX, LIST>, 256, 0);
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS, TEX, LIST, COLQ>, 256, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     int64_t blocks = (int64_t)lc.num_cu * per_cu;
     const int64_t items = (int64_t)a.ngroups * a.L;
     if (blocks > items) blocks = items;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_parzen_mfma<KSTEPS, TEX, LIST>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
+    hipLaunchKernelGGL((k_parzen_mfma<KSTEPS, TEX, LIST, COLQ>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
     return hipGetLastError();
 }
 
-template <bool LIST>
+template <bool LIST, bool COLQ>
 static hipError_t launch_mfma_list(const LaunchCtx &lc, const ParzenFastArgs &a) {
-    if (!a.texture) return launch_mfma_k<1, false, LIST>(lc, a);
+    if (!a.texture) return launch_mfma_k<1, false, LIST, COLQ>(lc, a);
     switch (a.ksteps) {
-        case 1: return launch_mfma_k<1, true, LIST>(lc, a);
-        case 2: return launch_mfma_k<2, true, LIST>(lc, a);
-        default: return launch_mfma_k<3, true, LIST>(lc, a);
+        case 1: return launch_mfma_k<1, true, LIST, COLQ>(lc, a);
+        case 2: return launch_mfma_k<2, true, LIST, COLQ>(lc, a);
+        default: return launch_mfma_k<3, true, LIST, COLQ>(lc, a);
     }
 }
 
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a) {
-    return a.list ? launch_mfma_list<true>(lc, a) : launch_mfma_list<false>(lc, a);
+    if (a.levels > 0) return a.list ? launch_mfma_list<true, true>(lc, a) : launch_mfma_list<false, true>(lc, a);
+    return a.list ? launch_mfma_list<true, false>(lc, a) : launch_mfma_list<false, false>(lc, a);
 }
 
 }  // namespace cs

@@ -181,23 +181,31 @@ hipError_t launch_fill_u32(const LaunchCtx &lc, unsigned int *p, size_t count, u
 }
 
 
-// Finite check of an input array: any NaN or infinity sets *flag.  Grid-stride
-// loop, one float per thread and step.
-__global__ __launch_bounds__(256) void k_check_finite(const float *p, int64_t n, unsigned int *flag) {
+// Finite check of an input array: any NaN or infinity sets bit 0 of *flag;
+// with levels n > 0 a finite value farther than 1e-4 / n from a multiple q / n
+// with q in 0..255 sets bit 1.  Grid-stride loop, one float per thread and step.
+__global__ __launch_bounds__(256) void k_check_finite(const float *p, int64_t n, int levels, unsigned int *flag) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    bool bad = false;
+    bool bad = false, off = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t b = __float_as_uint(p[i]);
-        bad |= (b & 0x7f800000u) == 0x7f800000u;  // exponent all ones: NaN or infinity
+        const float v = p[i];
+        const uint32_t b = __float_as_uint(v);
+        const bool nf = (b & 0x7f800000u) == 0x7f800000u;  // exponent all ones: NaN or infinity
+        bad |= nf;
+        if (levels > 0 && !nf) {
+            const float x = v * (float)levels, q = rintf(x);
+            off |= !(q >= 0.0f && q <= 255.0f && fabsf(x - q) <= 1e-4f);
+        }
     }
-    if (bad) atomicOr(flag, 1u);
+    const unsigned int f = (bad ? 1u : 0u) | (off ? 2u : 0u);
+    if (f) atomicOr(flag, f);
 }
 
-hipError_t launch_check_finite(const LaunchCtx &lc, const float *p, int64_t n, unsigned int *flag) {
+hipError_t launch_check_finite(const LaunchCtx &lc, const float *p, int64_t n, int levels, unsigned int *flag) {
     if (n <= 0) return hipSuccess;
     int64_t blocks = (n + 255) / 256;
     if (blocks > (int64_t)lc.num_cu * 8) blocks = (int64_t)lc.num_cu * 8;
-    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, lc.stream, p, n, flag);
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)blocks), dim3(256), 0, lc.stream, p, n, levels, flag);
     return hipGetLastError();
 }
 

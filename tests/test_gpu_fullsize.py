@@ -125,7 +125,7 @@ def test_large_bf16_tau_and_masks_full_size(ctx, large):
 def _sampled_loglik(ctx, w, masks, n_sample, seed):
     from paper_1312_4746_amd import LoglikParams
     prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
-                       rho_floor_px=w.rho_floor_px)
+                       rho_floor_px=w.rho_floor_px, colour_levels=w.colour_levels)
     got = ctx.label_loglik(dev(w.rgb), dev(masks.view(np.int64)), w.k, dev(w.sample_pix), dev(w.sample_label),
                            w.L, prm).cpu().numpy()
     st = ctx.last_loglik_stats()

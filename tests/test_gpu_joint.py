@@ -43,7 +43,8 @@ def _both(ctx, w, masks, pix=None, ref_pix=None, **kw):
     prm = LoglikParams(alpha_rho=kw.get("alpha_rho", w.alpha_rho), sigma_c=kw.get("sigma_c", w.sigma_c),
                        beta_scale=kw.get("beta_scale", w.beta_scale),
                        rho_floor_px=kw.get("rho_floor", w.rho_floor_px),
-                       normalise=kw.get("normalise", False))
+                       normalise=kw.get("normalise", False),
+                       colour_levels=kw.get("colour_levels", w.colour_levels))
     got = ctx.label_loglik(dev(w.rgb), dev(masks.view(np.int64)), w.k, dev(w.sample_pix),
                            dev(w.sample_label), w.L, prm,
                            pix_subset=None if pix is None else dev(np.asarray(pix, np.int32)),

@@ -248,7 +248,7 @@ def test_surrogate_gain_on_the_2048_workload(ctx):
     rgb, om = dev(w.rgb), dev(w.omega)
     spix, slab, tpix = dev(w.sample_pix), dev(w.sample_label), dev(w.train_pix)
     prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
-                       rho_floor_px=w.rho_floor_px)
+                       rho_floor_px=w.rho_floor_px, colour_levels=w.colour_levels)
     steps, batch = 1000, 4096
     order = dev(mlp_order(len(w.train_pix), steps, batch, seed=w.seed + 101).ravel())
     init = dev(mlp_init(5 + w.k, 128, w.L, seed=w.seed + 100))

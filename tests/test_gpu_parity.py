@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import oracle
-from workloads import make_config, make_workload
+from workloads import make_config, make_workload, quantise_colours
 
 pytestmark = pytest.mark.gpu
 
@@ -227,7 +227,8 @@ def _loglik_both(ctx, w, masks, pix=None, **kw):
     prm = LoglikParams(alpha_rho=kw.get("alpha_rho", w.alpha_rho), sigma_c=kw.get("sigma_c", w.sigma_c),
                        beta_scale=kw.get("beta_scale", w.beta_scale),
                        rho_floor_px=kw.get("rho_floor", w.rho_floor_px),
-                       normalise=kw.get("normalise", False))
+                       normalise=kw.get("normalise", False),
+                       colour_levels=kw.get("colour_levels", w.colour_levels))
     got = ctx.label_loglik(dev(w.rgb), dev(masks.view(np.int64)), w.k, dev(w.sample_pix),
                            dev(w.sample_label), w.L, prm,
                            pix_subset=None if pix is None else dev(np.asarray(pix, np.int32)))
@@ -245,11 +246,62 @@ def test_loglik_tiny_config_full(ctx):
 
 
 @pytest.mark.parametrize("case", SMALL_CASES, ids=lambda c: c["name"])
-def test_loglik_small_cases_full(ctx, case):
+@pytest.mark.parametrize("levels", [0, 255, 17])
+def test_loglik_small_cases_full(ctx, case, levels):
+    """Float colours (levels 0) and colours at 255 or 17 levels per channel,
+    whose squared distances the matrix-core kernel forms as exact integers."""
     w = _small(case)
+    if levels:
+        w.rgb = quantise_colours(w.rgb, levels)
     masks, _, _ = oracle.full_masks(w)
-    got, ref = _loglik_both(ctx, w, masks)
+    got, ref = _loglik_both(ctx, w, masks, colour_levels=levels)
     _ll_check(got, ref)
+
+
+def test_loglik_colour_levels_match_float_colours(ctx):
+    """On an 8-bit image the colour-level route and the float-colour route
+    give the same rows within FP32 rounding of the exponents (both inside the
+    oracle bound), on the tile grid and on a pixel list."""
+    w = make_config(1)
+    masks, _, _ = oracle.full_masks(w)
+    rng = np.random.default_rng(5)
+    pix = rng.choice(w.N, 2048, replace=False).astype(np.int32)
+    for sub in (None, pix):
+        a, ref = _loglik_both(ctx, w, masks, pix=sub, colour_levels=255)
+        b, _ = _loglik_both(ctx, w, masks, pix=sub, colour_levels=0)
+        if sub is not None:
+            _ll_check(a, ref)
+            _ll_check(b, ref)
+        np.testing.assert_allclose(a, b, rtol=2e-5, atol=2e-5)
+
+
+def test_loglik_colour_levels_errors(ctx):
+    """colour_levels outside 0..255 is an argument error; with the input check
+    on, a colour that is no multiple of 1/n, or lies above 255/n, is too."""
+    from paper_1312_4746_amd import CosparseError, LoglikParams
+    w = make_config(0)
+    masks, _, _ = oracle.full_masks(w)
+    args = (dev(masks.view(np.int64)), w.k, dev(w.sample_pix), dev(w.sample_label), w.L)
+    for n in (-1, 256):
+        with pytest.raises(CosparseError) as e:
+            ctx.label_loglik(dev(w.rgb), *args, LoglikParams(colour_levels=n))
+        assert e.value.code == 1
+    ctx.set_check_finite(True)
+    try:
+        ctx.label_loglik(dev(w.rgb), *args, LoglikParams(colour_levels=255))  # 8-bit image: accepted
+        for bad in (0.5 / 255, 1.0 + 1.0 / 255):
+            rgb = w.rgb.copy()
+            rgb[1, 3, 4] = bad
+            with pytest.raises(CosparseError) as e:
+                ctx.label_loglik(dev(rgb), *args, LoglikParams(colour_levels=255))
+            assert e.value.code == 1
+        rgb = w.rgb.copy()
+        rgb[0, 0, 0] = np.nan
+        with pytest.raises(CosparseError) as e:
+            ctx.label_loglik(dev(rgb), *args, LoglikParams(colour_levels=255))
+        assert e.value.code == 5
+    finally:
+        ctx.set_check_finite(False)
 
 
 def test_loglik_bsds_shape_subset(ctx):
@@ -292,13 +344,15 @@ def test_loglik_overflow_fixup_case(ctx):
     _ll_check(got, ref)
 
 
-def test_loglik_overflow_case_full_image(ctx):
+@pytest.mark.parametrize("levels", [0, 255])
+def test_loglik_overflow_case_full_image(ctx, levels):
     """Same construction on the full-image path (texture term on the matrix
-    cores): the reference must move up by the dynamic rescale."""
+    cores): the reference must move up by the dynamic rescale.  With colour
+    levels the colours are 0 and 1 (the same distance 1 per channel)."""
     H, W = 16, 24
-    rgb = np.full((3, H, W), 0.5, np.float32)
-    rgb[:, 8, 9] = 1.5
-    rgb[:, 3, 20] = -0.7
+    rgb = np.full((3, H, W), 0.5 if levels == 0 else 0.0, np.float32)
+    rgb[:, 8, 9] = 1.5 if levels == 0 else 1.0
+    rgb[:, 3, 20] = -0.7 if levels == 0 else 1.0
     w = make_workload("fix2", H=H, W=W, R=1, p=3, k=8, seed=1, per_region=2)
     w.rgb = rgb
     w.sample_pix = np.array([8 * W + 9, 8 * W + 11, 0, 3 * W + 20, 3 * W + 23], np.int32)
@@ -307,7 +361,7 @@ def test_loglik_overflow_case_full_image(ctx):
     w.k = 8
     masks = np.zeros((H * W, 1), np.uint64)
     masks[::3, 0] = np.uint64(0b10110)
-    got, ref = _loglik_both(ctx, w, masks)
+    got, ref = _loglik_both(ctx, w, masks, colour_levels=levels)
     _ll_check(got, ref)
 
 
@@ -361,7 +415,7 @@ def _full_image_sampled(ctx, w, masks, n_sample, seed):
     pixels included)."""
     from paper_1312_4746_amd import LoglikParams
     prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
-                       rho_floor_px=w.rho_floor_px)
+                       rho_floor_px=w.rho_floor_px, colour_levels=w.colour_levels)
     got = ctx.label_loglik(dev(w.rgb), dev(masks.view(np.int64)), w.k, dev(w.sample_pix),
                            dev(w.sample_label), w.L, prm).cpu().numpy()
     rng = np.random.default_rng(seed)
@@ -418,11 +472,13 @@ def test_loglik_wide_image_exact_route(ctx):
 
 
 @pytest.mark.parametrize("k", [6, 7, 119, 120, 121, 124, 125, 244, 245])
-def test_loglik_feature_width_boundary(ctx, k):
+@pytest.mark.parametrize("levels", [0, 255])
+def test_loglik_feature_width_boundary(ctx, k, levels):
     """The texture features (k mask bits, then D + 1 slots each for |A| and |B|,
     D = ceil(floor(k/7) / 7) base-7 digits) fill one 128-wide FP6 step up to
-    k = 120, two up to k = 244 and three above; k < 7 needs no digit."""
-    w = make_workload(f"kb{k}", H=18, W=27, R=3, p=5, k=k, seed=k, per_region=8)
+    k = 120, two up to k = 244 and three above; k < 7 needs no digit.  Both
+    colour routes."""
+    w = make_workload(f"kb{k}", H=18, W=27, R=3, p=5, k=k, seed=k, per_region=8, colour_levels=levels)
     masks, _, _ = oracle.full_masks(w)
     got, ref = _loglik_both(ctx, w, masks)
     _ll_check(got, ref)
@@ -440,7 +496,7 @@ def test_two_contexts_interleaved(ctx):
         rgb = dev(w.rgb)
         _, m, tau = c.cosupport_median(rgb, w.p, w.mask_sigma, dev(w.omega), 0.1)
         prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
-                           rho_floor_px=w.rho_floor_px)
+                           rho_floor_px=w.rho_floor_px, colour_levels=w.colour_levels)
         ll = c.label_loglik(rgb, m, w.k, dev(w.sample_pix), dev(w.sample_label), w.L, prm)
         return float(tau.item()), m.cpu(), ll.cpu()
 

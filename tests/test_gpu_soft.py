@@ -42,7 +42,8 @@ def _both(ctx, w, a32, pix=None, ref_pix=None, sigma=SIGMA, **kw):
     prm = LoglikParams(alpha_rho=kw.get("alpha_rho", w.alpha_rho), sigma_c=kw.get("sigma_c", w.sigma_c),
                        beta_scale=kw.get("beta_scale", w.beta_scale),
                        rho_floor_px=kw.get("rho_floor", w.rho_floor_px),
-                       normalise=kw.get("normalise", False))
+                       normalise=kw.get("normalise", False),
+                       colour_levels=kw.get("colour_levels", w.colour_levels))
     got = ctx.label_loglik_soft(dev(w.rgb), dev(a32), sigma, dev(w.sample_pix), dev(w.sample_label), w.L,
                                 prm, pix_subset=None if pix is None else dev(np.asarray(pix, np.int32)))
     rp = pix if ref_pix is None else ref_pix

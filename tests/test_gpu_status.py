@@ -68,7 +68,7 @@ def test_loglik_counters_survive_other_calls(ctx):
     brgb = dev(b.rgb)
     _, bm, _ = ctx.cosupport_median(brgb, b.p, b.mask_sigma, dev(b.omega), 0.1)
     prm = LoglikParams(alpha_rho=b.alpha_rho, sigma_c=b.sigma_c, beta_scale=b.beta_scale,
-                       rho_floor_px=b.rho_floor_px)
+                       rho_floor_px=b.rho_floor_px, colour_levels=b.colour_levels)
     ctx.label_loglik(brgb, bm, b.k, dev(b.sample_pix), dev(b.sample_label), b.L, prm)
     first = ctx.last_loglik_stats()
     assert first["rescaled_chunks"] > 0

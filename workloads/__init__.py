@@ -14,5 +14,6 @@ from .gen import (  # noqa: F401
     make_omega,
     mlp_init,
     mlp_order,
+    quantise_colours,
     unsup_init,
 )

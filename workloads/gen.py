@@ -5,7 +5,8 @@ The paper evaluates on the Graz interactive benchmark and on BSDS300
 (Sec. 5); neither is available here, so these images stand in for them:
 Voronoi regions, each with its own mean colour and an oriented sinusoid
 texture (plus band-limited noise for the large case), plus i.i.d. Gaussian
-noise.  Shapes follow the paper's workloads: 481x321 is the BSDS image
+noise; the configured workloads are stored at 8 bits per channel like the
+benchmark images (each value a multiple of 1/255 in [0, 1]).  Shapes follow the paper's workloads: 481x321 is the BSDS image
 size (Sec. 5), the label counts lie in the Graz range of 2-13 labels and
 the scribbles are painted with the Graz 13-pixel brush (Sec. 5.1).
 
@@ -33,6 +34,7 @@ class Workload:
     """One synthetic problem instance.
 
     rgb:          float32 (3, H, W) colour planes (SoA), values roughly in [0, 1]
+                  (with colour_levels n > 0: multiples of 1/n in [0, 1])
     omega:        float32 (k, n) analysis operator, n = p*p, row-major
     sample_pix:   int32 (M,) linear pixel index row*W + col of each scribble sample
     sample_label: int32 (M,) label of each sample, 0..L-1
@@ -59,6 +61,7 @@ class Workload:
     tau_frac: float = 0.1
     precision: str = "fp32"
     seed: int = 0
+    colour_levels: int = 0
 
     @property
     def N(self) -> int:
@@ -77,18 +80,19 @@ class Workload:
 # form, the large case and its BF16 form, and the surrogate case.
 CONFIGS: Dict[int, dict] = {
     0: dict(name="tiny_64x64_p5_k50_L3", H=64, W=64, R=3, p=5, k=50,
-            scribble="uniform", per_region=200, bandnoise=False, train_frac=0.0),
+            scribble="uniform", per_region=200, bandnoise=False, train_frac=0.0, colour_levels=255),
     1: dict(name="bsds_481x321_p7_k98_L10_fp32", H=321, W=481, R=10, p=7, k=98,
-            scribble="strokes", total_frac=0.05, bandnoise=False, train_frac=0.0),
+            scribble="strokes", total_frac=0.05, bandnoise=False, train_frac=0.0, colour_levels=255),
     2: dict(name="bsds_481x321_p7_k98_L10_bf16", H=321, W=481, R=10, p=7, k=98,
             scribble="strokes", total_frac=0.05, bandnoise=False, train_frac=0.0,
-            precision="bf16"),
+            precision="bf16", colour_levels=255),
     3: dict(name="large_1024x1024_p11_k242_L16", H=1024, W=1024, R=16, p=11, k=242,
-            scribble="strokes", total=50000, bandnoise=True, train_frac=0.0),
+            scribble="strokes", total=50000, bandnoise=True, train_frac=0.0, colour_levels=255),
     4: dict(name="surrogate_2048x2048_p7_k98_L10", H=2048, W=2048, R=10, p=7, k=98,
-            scribble="strokes", total_frac=0.05, bandnoise=False, train_frac=0.02),
+            scribble="strokes", total_frac=0.05, bandnoise=False, train_frac=0.02, colour_levels=255),
     5: dict(name="large_1024x1024_p11_k242_L16_bf16", H=1024, W=1024, R=16, p=11, k=242,
-            scribble="strokes", total=50000, bandnoise=True, train_frac=0.0, precision="bf16"),
+            scribble="strokes", total=50000, bandnoise=True, train_frac=0.0, precision="bf16",
+            colour_levels=255),
 }
 
 # Precision forms run on exactly the inputs of their FP32 case.
@@ -142,6 +146,13 @@ def _image(region: np.ndarray, R: int, rng: np.random.Generator, bandnoise: bool
             img[c][sel] = means[r, c] + tex
     img += rng.normal(0.0, noise_sd, size=img.shape)
     return img.astype(np.float32)
+
+
+def quantise_colours(rgb: np.ndarray, n: int) -> np.ndarray:
+    """Colours at n levels per channel: clipped to [0, 1], rounded to the
+    nearest multiple of 1/n (float32 of q / n)."""
+    q = np.rint(np.clip(rgb.astype(np.float64), 0.0, 1.0) * n)
+    return (q / n).astype(np.float32)
 
 
 def _split_targets(total: int, areas: np.ndarray) -> np.ndarray:
@@ -206,15 +217,18 @@ def make_workload(name: str, H: int, W: int, R: int, p: int, k: int, seed: int,
                   scribble: str = "uniform", per_region: int = 0, total: Optional[int] = None,
                   total_frac: Optional[float] = None, bandnoise: bool = False,
                   train_frac: float = 0.0, precision: str = "fp32",
-                  mask_sigma: Optional[float] = None) -> Workload:
+                  mask_sigma: Optional[float] = None, colour_levels: int = 0) -> Workload:
     """Draw one workload.  Sub-streams (image, operator, scribbles, training
     pixels) are spawned from SeedSequence(seed) so each part is reproducible
-    on its own."""
+    on its own.  colour_levels n > 0 stores the image at n levels per channel
+    (clipped to [0, 1], rounded to the nearest multiple of 1/n)."""
     ss = np.random.SeedSequence(seed)
     s_img, s_om, s_scr, s_train, _s_mlp = ss.spawn(5)
     rng_img = np.random.default_rng(s_img)
     region = _voronoi(H, W, R, rng_img)
     rgb = _image(region, R, rng_img, bandnoise)
+    if colour_levels > 0:
+        rgb = quantise_colours(rgb, colour_levels)
     omega = make_omega(k, p * p, np.random.default_rng(s_om))
 
     rng_s = np.random.default_rng(s_scr)
@@ -252,7 +266,7 @@ def make_workload(name: str, H: int, W: int, R: int, p: int, k: int, seed: int,
                     sample_pix=sample_pix, sample_label=sample_label, region=region,
                     train_pix=train_pix,
                     mask_sigma=(p / 4.0 if mask_sigma is None else mask_sigma),
-                    precision=precision, seed=seed)
+                    precision=precision, seed=seed, colour_levels=colour_levels)
 
 
 def make_config(c: int) -> Workload:
