@@ -28,6 +28,15 @@
 // add.  (An FP32 MFMA, K = 4, also fits the location term, but on gfx950 it
 // holds the VALU for its whole duration; the BF16 one largely overlaps it.)
 //
+// Colours at n <= 255 levels per channel (8-bit images): with q = rint(c n)
+// - 128 in -128..127 per channel, the squared colour distance
+// |q_x|^2 - 2 q_x.q_y + |q_y|^2 is an integer below 2^18 whose every factor
+// is exact in BF16 (|q|^2 < 2^16 split at bit 8), so it is a third BF16
+// product, on K 16..23 of the same location operands (the lanes g = 2), exact
+// in FP32.  One FMA with kcol = -log2(e) / (2 sigma_c^2 n^2) replaces the six
+// colour instructions: five VALU instructions per pair, one of them the
+// v_exp_f32.
+//
 // Work decomposition.  A workgroup of 4 waves owns four 8x4 pixel tiles (one
 // per wave); a work item is such a group and one label.  Items come from one
 // atomic queue per XCD: queue x holds the groups x, x + 8, x + 16, ... with
@@ -379,7 +388,7 @@ hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
 // distance is a third matrix-core product (BF16, K 16..23 of the location
 // operands, exact integers) and the pixel operands stay in registers.
 template <int KSTEPS, bool TEX, bool LIST, bool COLQ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 ? 4 : 2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 || (KSTEPS == 2 && COLQ) ? 4 : 2)))
 void k_parzen_mfma(ParzenFastArgs a) {
     constexpr int RB = kParzenRB;
     constexpr int KP = 128 * KSTEPS;
@@ -404,6 +413,9 @@ void k_parzen_mfma(ParzenFastArgs a) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, jl = lane & 15;
+    // the wave index as a wave-uniform (scalar) value: the LDS destinations of
+    // the chunk copies and the copy branch need no per-lane arithmetic
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
     const int64_t coef_label_stride = (int64_t)a.ngroups * 4 * kTilePix;
     // LDS byte offsets of the lane's operands in step 0 of a chunk buffer (step
     // st adds st * 16 rows; the swizzle depends on the row only through
@@ -499,18 +511,18 @@ void k_parzen_mfma(ParzenFastArgs a) {
         // chunk loop, its 64-bit address would be spilled at the register limit
         // and reloaded in front of the copies.)
         auto issue = [&](int c, uint8_t *sf, float *sr) {
-            int off = tid * 16;
+            uint32_t off = (uint32_t)tid * 16u;
             __asm__ volatile("" : "+v"(off));
             if constexpr (TEX) {
                 const uint8_t *fbase = a.feat + (int64_t)c * FEAT_B;
 #pragma unroll
                 for (int u = 0; u < FEAT_B / 4096; ++u)
                     __builtin_amdgcn_global_load_lds(fbase + u * 4096 + off,
-                                                     (lds_void *)(sf + u * 4096 + wave * 1024), 16, 0, 0);
+                                                     (lds_void *)(sf + u * 4096 + wave_u * 1024), 16, 0, 0);
             }
-            if (wave < 3) {
+            if (wave_u < 3) {
                 const uint8_t *rbase = reinterpret_cast<const uint8_t *>(a.rec) + (int64_t)c * (kRecChunkF * 4);
-                __builtin_amdgcn_global_load_lds(rbase + off, (lds_void *)(sr + wave * 256), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(rbase + off, (lds_void *)(sr + wave_u * 256), 16, 0, 0);
             }
         };
         issue(c0, s_feat0, s_rec0);
@@ -603,10 +615,11 @@ void k_parzen_mfma(ParzenFastArgs a) {
 #pragma unroll
             for (int st = 0; st < kChunkS / 16; ++st) {
                 if (st >= nst) break;
-                // opaque lane index: the operand is read here at every step
-                // instead of being hoisted out of the loop into registers
+                // opaque lane index: the location operand is read from LDS here
+                // at every step instead of being hoisted out of the loop into
+                // registers (with colour levels it lives in registers)
                 int al = lane;
-                __asm__ volatile("" : "+v"(al));
+                if constexpr (!COLQ) __asm__ volatile("" : "+v"(al));
                 const uint8_t *Fs = F + st * 16 * KP;
                 const uint8_t *Rs = reinterpret_cast<const uint8_t *>(Rr) + st * 256;
                 i32x8 Bop[KSTEPS];
@@ -668,12 +681,14 @@ void k_parzen_mfma(ParzenFastArgs a) {
             // terms per lane and chunk): the pass stops, and the item is
             // computed again with the reference of each such pixel raised (see
             // the retry below).
-            bool big = false;
+            // (the largest of the lane's sums: a NaN is passed over here and
+            // marks the item bad at its end)
+            float smax = S[0][0];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) big |= !(S[rb][r] <= 0x1p64f);
-            if (__ballot(big)) {
+                for (int r = 0; r < 4; ++r) smax = fmaxf(smax, S[rb][r]);
+            if (__ballot(!(smax <= 0x1p64f))) {
                 // the 16 lanes of a pixel (one sample column each) move
                 // together, by the largest exponent among them, so that the
                 // pixel keeps one reference
