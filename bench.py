@@ -507,6 +507,9 @@ def main():
     ap.add_argument("--unsup", action="store_true",
                     help="only the unsupervised segmentation leg on --config's image")
     ap.add_argument("--seg-lambda", type=float, default=1.0)
+    ap.add_argument("--float-colours", action="store_true",
+                    help="pass the colours as plain floats (colour_levels 0: the colour term on the VALU) "
+                         "instead of the workload's 8-bit levels")
     ap.add_argument("--soft", action="store_true",
                     help="the joint form with smooth co-supports (sigma 0.01) of the stored "
                          "analysed vectors")
@@ -554,8 +557,9 @@ def main():
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
     rgb, om = dev(w.rgb), dev(w.omega)
     spix, slab = dev(w.sample_pix), dev(w.sample_label)
+    levels = 0 if args.float_colours else w.colour_levels
     prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
-                       rho_floor_px=w.rho_floor_px, colour_levels=w.colour_levels)
+                       rho_floor_px=w.rho_floor_px, colour_levels=levels)
     ctx = Context(0)
     alpha = torch.empty((w.N, w.k), dtype=torch.float32, device="cuda")
     masks = torch.empty((w.N, (w.k + 63) // 64), dtype=torch.int64, device="cuda")
@@ -706,6 +710,8 @@ def main():
                    "texture": ("smooth co-supports, median representatives (eq:map_tsm, eq:joined)"
                                if args.soft else "label representatives (eq:joined)" if args.joint
                                else "per sample in the sum"),
+                   "colours": (f"{levels + 1} levels per channel (colour term on the matrix cores)" if levels
+                               else "floats (colour term on the VALU)"),
                    "samples": w.M, "pixels": w.N, "pairs": pairs, "parallelism": "1 GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
