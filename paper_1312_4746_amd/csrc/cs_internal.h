@@ -149,10 +149,11 @@ constexpr int kTauRank = 1 << 14;
 // Radix select of the float |alpha| of the target rank; the first kernel also
 // writes the largest per-row error bound (coef) of the rows of omega, and the
 // per-row bounds to margins when non-null.
-// The same selection with each digit picked at the start of the next
-// kernel (every workgroup from the complete histogram): the state, the three
-// histograms (hist3, cleared) and the margins come from the analysis kernel
-// before; the third digit is picked by the candidate gather.
+// The first two digits of the same selection, each picked at the start of
+// the next kernel (every workgroup from the complete histogram): the state,
+// the histograms (hist3, cleared) and the margins come from the analysis
+// kernel before; the second digit is picked by the candidate gather, which
+// gathers over the whole bin of the top 22 bits (no third digit pass).
 hipError_t tau_digits_folded(const LaunchCtx &lc, const float *alpha, int64_t count, unsigned int *hist3,
                              TauState *st);
 hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t count,

@@ -5,10 +5,12 @@
 //
 // The separate path reads the N*k analysed vectors five times: three radix
 // digits, the candidate gather and then the masks at the exact tau.  Here the
-// gather pass decides the masks as well.  After the three digits the float
-// median v of the rounded |a| is known, and the exact median lies in
-// [v - m, v + m] (m the largest proven rounding bound), so tau lies in a short
-// interval.  Every entry whose rounded |a| is clear of that interval by more
+// gather pass decides the masks as well, and takes the place of the third
+// digit: after two digits (the top 22 bits) the float median of the rounded
+// |a| is known to lie in a bin [v_lo, v_hi] of 2^10 floats, narrower than the
+// candidate window's half-width at every workload measured, and the exact
+// median lies in [v_lo - m, v_hi + m] (m the largest proven rounding bound),
+// so tau lies in a short interval.  Every entry whose rounded |a| is clear of that interval by more
 // than its row's margin is decided in the gather pass; the few others are
 // listed and decided against the exact tau once it is selected, in FP64 where
 // the rounded value is within the margin.  Masks and tau equal those of the
@@ -44,20 +46,22 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
     static_assert(kPx * W64 <= 64, "one mask word per lane");
     __shared__ unsigned long long red[256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // the third digit, from its complete histogram: the float v of the target
-    // rank among the rounded |a| (workgroup 0 records it)
+    // the second digit, from its complete histogram: the target rank's rounded
+    // |a| has the top 22 bits prefix, so it lies in [v_lo, v_hi] (workgroup 0
+    // records the digit)
     unsigned int prefix;
     unsigned long long rank;
-    tau_pick_digit(hist3 + 2 * kHistBins, 0, st->pfx[2], st->rk[2], prefix, rank);
+    tau_pick_digit(hist3 + kHistBins, 10, st->pfx[1], st->rk[1], prefix, rank);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->pfx[3] = st->prefix = prefix;
-        st->rk[3] = st->rank = rank;
+        st->pfx[2] = st->prefix = prefix;
+        st->rk[2] = st->rank = rank;
     }
-    // candidate window [v - 2m, v + 2m] as float bit patterns (non-negative
-    // floats order like their bit patterns), as in the separate gather
-    const double v = (double)__uint_as_float(prefix);
+    // candidate window [v_lo - 2m, v_hi + 2m] as float bit patterns
+    // (non-negative floats order like their bit patterns): an entry below it
+    // is exactly below the exact median, one above it exactly above
+    const double vlo = (double)__uint_as_float(prefix), vhi = (double)__uint_as_float(prefix | 0x3FFu);
     const double mm = *max_margin;
-    const double wlo = v - 2.0 * mm, whi = v + 2.0 * mm;
+    const double wlo = vlo - 2.0 * mm, whi = vhi + 2.0 * mm;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->lo = wlo;
         st->hi = whi;
@@ -68,10 +72,10 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
     const uint32_t blo = wlo <= 0.0 ? 0u : __float_as_uint(flo);
     const uint32_t bhi = __float_as_uint(fhi);
     // tau = fl(frac * median) is monotone in the median, which lies in
-    // [v - m, v + m]; both ends are widened by the rounding of the bounds
-    double mlo = v - mm;
+    // [v_lo - m, v_hi + m]; both ends are widened by the rounding of the bounds
+    double mlo = vlo - mm;
     mlo = mlo > 0.0 ? nextafter(mlo, 0.0) : 0.0;
-    const double mhi = nextafter(v + mm, INFINITY);
+    const double mhi = nextafter(vhi + mm, INFINITY);
     const double tlo = mlo > 0.0 ? nextafter(frac * mlo, 0.0) : 0.0;
     const double thi = nextafter(frac * mhi, INFINITY);
     float tin[W64], tout[W64];

@@ -192,15 +192,16 @@ hipError_t tau_select_float(const LaunchCtx &lc, const float *alpha, int64_t cou
     return hipGetLastError();
 }
 
+// The two digit passes of the fused co-support call (the gather that follows
+// picks the second digit and gathers over its whole bin instead of a third
+// digit pass).
 hipError_t tau_digits_folded(const LaunchCtx &lc, const float *alpha, int64_t count, unsigned int *hist3,
                              TauState *st) {
-    unsigned int *h1 = hist3, *h2 = hist3 + kHistBins, *h3 = hist3 + 2 * kHistBins;
+    unsigned int *h1 = hist3, *h2 = hist3 + kHistBins;
     hipLaunchKernelGGL(k_tau_hist<8>, dim3(hist_blocks(lc, count, 2)), dim3(256), 0, lc.stream, alpha, count, 21,
                        0u, st, h1, nullptr, 0, 0);
     hipLaunchKernelGGL(k_tau_hist<1>, dim3(hist_blocks(lc, count, 1)), dim3(256), 0, lc.stream, alpha, count, 10,
                        0xFFE00000u, st, h2, h1, 21, 1);
-    hipLaunchKernelGGL(k_tau_hist<1>, dim3(hist_blocks(lc, count, 1)), dim3(256), 0, lc.stream, alpha, count, 0,
-                       0xFFFFFC00u, st, h3, h2, 10, 2);
     return hipGetLastError();
 }
 
