@@ -7,8 +7,9 @@
 // digits, the candidate gather and then the masks at the exact tau.  Here the
 // gather pass decides the masks as well, and takes the place of the third
 // digit: after two digits (the top 22 bits) the float median of the rounded
-// |a| is known to lie in a bin [v_lo, v_hi] of 2^10 floats, narrower than the
-// candidate window's half-width at every workload measured, and the exact
+// |a| is known to lie in a bin [v_lo, v_hi] of 2^10 floats (at the medians
+// and FP32 bounds of the 7 x 7 and 11 x 11 workloads, 0.6 and 0.25 of the
+// candidate window's half-width 2m, so the window grows little), and the exact
 // median lies in [v_lo - m, v_hi + m] (m the largest proven rounding bound),
 // so tau lies in a short interval.  Every entry whose rounded |a| is clear of that interval by more
 // than its row's margin is decided in the gather pass; the few others are
