@@ -159,7 +159,14 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
     // fragments from LDS past both.
     const int nblk_j = (a.k + 15) / 16;
     unsigned long long nrecomp = 0;
-    constexpr int KF = T::np4 / 4, KH = np / 16;  // FP32 and BF16 K steps
+    // FP32 K steps.  Where padding K to np costs at most one step (11 x 11
+    // and 13 x 13 patches), the K order is cut into four runs of np / 4, lane
+    // group g = lane / 16 taking patch entries (np / 4) g + kb, so the lane's A
+    // values are 16-byte aligned runs of its patch row: one ds_read_b128 per
+    // four steps, the next one in flight while four steps are multiplied
+    // (the row stride keeps a 16-lane group's reads on distinct banks).
+    constexpr bool RUNS = np / 4 - T::np4 / 4 <= 1;
+    constexpr int KF = RUNS ? np / 4 : T::np4 / 4, KH = np / 16;  // FP32 and BF16 K steps
     for (int jp = wave; jp < nblk_j; jp += 8) {
         const int jbs[2] = {jp, jp + 4};
         const bool pair = jp + 4 < nblk_j;
@@ -172,7 +179,7 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
             if (PREC == CS_FP32) {
 #pragma unroll
                 for (int kb = 0; kb < KF; ++kb) {
-                    const int t = kb * 4 + (lane >> 4);
+                    const int t = RUNS ? KF * (lane >> 4) + kb : kb * 4 + (lane >> 4);
                     bf[u][kb] = o[t < n ? t : n - 1];
                 }
             } else {
@@ -197,7 +204,24 @@ __global__ __launch_bounds__(256) void k_analyze(AnalyzeArgs a) {
             if (rb * 16 >= valid_px) break;
             const float *srow = s + (rb * 16 + (lane & 15)) * ss;
             f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-            if (PREC == CS_FP32) {
+            if (PREC == CS_FP32 && RUNS) {
+                const float4 *arun = reinterpret_cast<const float4 *>(srow + KF * (lane >> 4));
+                float4 cur = arun[0];
+#pragma unroll
+                for (int q = 0; q < KF / 4; ++q) {
+                    const float4 nxt = arun[q + 1 < KF / 4 ? q + 1 : q];
+                    const float av[4] = {cur.x, cur.y, cur.z, cur.w};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bf[0][4 * q + i], acc[0], 0, 0, 0);
+                        if (pair)
+                            acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bf[1][4 * q + i], acc[1], 0, 0, 0);
+                    }
+                    cur = nxt;
+                    // keep the next run's read one step ahead, not hoisted
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else if (PREC == CS_FP32) {
 #pragma unroll
                 for (int kb = 0; kb < KF; ++kb) {
                     const float av = srow[kb * 4 + (lane >> 4)];
