@@ -106,28 +106,12 @@ __device__ __forceinline__ int colour_level(float c, int n) {
     return (int)q - 128;
 }
 
-// Texture feature f of a pixel (PIX) or a sample with co-support bits `bits`
-// (bit j of word j / 32) and |co-support| c: see the header.
-template <bool PIX>
-__device__ __forceinline__ int tex_feature(int f, int k, const uint32_t *bits, uint32_t c) {
-    const int D = tex_digits(k);
-    if (f < k) {
-        const int b = (int)((bits[f >> 5] >> (f & 31)) & 1u);
-        return PIX ? b : -2 * b;
-    }
-    f -= k;
-    const int q = (int)(c / 7u), r = (int)(c % 7u);
-    auto digit = [&](int s) { const int d = q - 7 * s; return d < 0 ? 0 : d > 7 ? 7 : d; };
-    if (f < D) return PIX ? digit(f) : 7;
-    if (f == D) return PIX ? r : 1;
-    f -= D + 1;
-    if (f < D) return PIX ? 7 : digit(f);
-    if (f == D) return PIX ? 1 : r;
-    return 0;
-}
-
-// The 32 FP6 codes of features f0 .. f0 + 31 packed as the lane operand of one
-// 16x16x128 step: feature f0 + v at bits 6v .. 6v + 5 of six dwords.
+// The 32 FP6 codes of features f0 .. f0 + 31 (f0 a multiple of 32) packed as
+// the lane operand of one 16x16x128 step: feature f0 + v at bits 6v .. 6v + 5
+// of six dwords.  The mask-bit features of the group take one code per set
+// bit (1 for a pixel, -2 for a sample); the count features k .. k + 2D + 1
+// that fall in the group are formed directly (the digits and the remainder
+// of the count computed once); every other feature is zero.
 template <bool PIX>
 __device__ __forceinline__ void tex_pack(int f0, int k, const uint32_t *bits, uint32_t c, uint32_t (&o)[6]) {
     for (int d = 0; d < 6; ++d) o[d] = 0u;
@@ -136,15 +120,32 @@ __device__ __forceinline__ void tex_pack(int f0, int k, const uint32_t *bits, ui
         o[d] |= code << sh;
         if (sh > 26) o[d + 1] |= code >> (32 - sh);
     };
-    if (f0 + 32 <= k && (f0 & 31) == 0) {
-        // a whole mask word: 1 (pixel) or -2 (sample) per set bit
-        const uint32_t w = bits[f0 >> 5], code = PIX ? fp6_of_int(1) : fp6_of_int(-2);
-#pragma unroll
-        for (int v = 0; v < 32; ++v)
-            if ((w >> v) & 1u) put(v, code);
-        return;
+    if (f0 < k) {
+        uint32_t w = bits[f0 >> 5];
+        if (k - f0 < 32) w &= (1u << (k - f0)) - 1u;
+        const uint32_t code = PIX ? fp6_of_int(1) : fp6_of_int(-2);
+        while (w) {
+            put(__builtin_ctz(w), code);
+            w &= w - 1u;
+        }
     }
-    for (int v = 0; v < 32; ++v) put(v, fp6_of_int(tex_feature<PIX>(f0 + v, k, bits, c)));
+    const int D = tex_digits(k);
+    const int e0 = f0 > k ? f0 : k, e1 = f0 + 32 < k + 2 * D + 2 ? f0 + 32 : k + 2 * D + 2;
+    if (e0 < e1) {
+        const int q = (int)(c / 7u), r = (int)(c % 7u);
+        for (int e = e0; e < e1; ++e) {
+            const int x = e - k;
+            const int s = x < D ? x : x - D - 1;  // digit index within its run
+            int dg = q - 7 * s;
+            dg = dg < 0 ? 0 : dg > 7 ? 7 : dg;
+            int val;
+            if (x < D) val = PIX ? dg : 7;
+            else if (x == D) val = PIX ? r : 1;
+            else if (x < 2 * D + 1) val = PIX ? 7 : dg;
+            else val = PIX ? 1 : r;
+            put(e - f0, fp6_of_int(val));
+        }
+    }
 }
 
 // Physical 16-byte slot of logical slot p in a sample row.  Rows are 128 B
