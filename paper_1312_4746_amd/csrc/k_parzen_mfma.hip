@@ -108,7 +108,7 @@ __device__ __forceinline__ int colour_level(float c, int n) {
 
 // The 32 FP6 codes of features f0 .. f0 + 31 (f0 a multiple of 32) packed as
 // the lane operand of one 16x16x128 step: feature f0 + v at bits 6v .. 6v + 5
-// of six dwords.  The mask-bit features of the group take one code per set
+// of six dwords.  The mask-bit features of the group take a code for each set
 // bit (1 for a pixel, -2 for a sample); the count features k .. k + 2D + 1
 // that fall in the group are formed directly (the digits and the remainder
 // of the count computed once); every other feature is zero.
@@ -124,10 +124,10 @@ __device__ __forceinline__ void tex_pack(int f0, int k, const uint32_t *bits, ui
         uint32_t w = bits[f0 >> 5];
         if (k - f0 < 32) w &= (1u << (k - f0)) - 1u;
         const uint32_t code = PIX ? fp6_of_int(1) : fp6_of_int(-2);
-        while (w) {
-            put(__builtin_ctz(w), code);
-            w &= w - 1u;
-        }
+        // unrolled: every position a constant, so each bit is a masked OR
+#pragma unroll
+        for (int v = 0; v < 32; ++v)
+            if ((w >> v) & 1u) put(v, code);
     }
     const int D = tex_digits(k);
     const int e0 = f0 > k ? f0 : k, e1 = f0 + 32 < k + 2 * D + 2 ? f0 + 32 : k + 2 * D + 2;
