@@ -157,11 +157,13 @@ int cs_cosupport_noalloc(cs_ctx *ctx, const float *rgb, int H, int W, int p, dou
  * analysed vectors (as cs_analyze_patches), tau = frac * median{|a|} selected
  * exactly on the device (as cs_tau_median), and the masks at that tau (as
  * cs_cosupport with alpha).  Results equal those of the three calls bit for
- * bit.  The call only enqueues work; tau stays on the device.  With FP32 and
- * the proven margin (margin < 0) the masks are decided in the pass that
- * gathers the candidates of the exact median: an entry clear of the interval
- * that tau is known to lie in by then is decided at once, the few others once
- * tau is selected.  The context reserves device memory for lists that could
+ * bit.  The call only enqueues work; tau stays on the device.  With the
+ * proven margin (margin < 0) the masks are decided in the pass that gathers
+ * the candidates of the exact median: an entry clear of the interval that
+ * tau is known to lie in by then is decided at once, the few others once tau
+ * is selected.  In BF16 that pass runs on the FP32 analysis that tau is
+ * selected on (at the proven margin the masks are the exact masks either
+ * way), and the BF16 analysis then writes alpha.  The context reserves device memory for lists that could
  * hold every entry (24 bytes per entry of N*k; 16 bytes in the other forms),
  * so that their lengths never need the host.
  *   alpha    device out, N*k float32, 16-byte aligned

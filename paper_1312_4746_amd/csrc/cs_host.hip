@@ -482,23 +482,29 @@ struct CosupportWs {
 // `precision`: alpha itself for FP32; for BF16 an internal FP32 analysis (the
 // BF16 error bound would put a large share of all entries in the candidate
 // window, the FP32 one a tiny share; the selected value is the same).
+// The context's FP32 analysis buffer (the BF16 forms select tau on an FP32
+// analysis), grown to `bytes` when needed.
+int ensure_alpha32(cs_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->alpha32_bytes) return CS_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    if (ctx->alpha32) HIP_TRY(hipFree(ctx->alpha32));
+    ctx->alpha32 = nullptr;
+    ctx->alpha32_bytes = 0;
+    if (hipMalloc((void **)&ctx->alpha32, bytes) != hipSuccess) {
+        ctx->alpha32 = nullptr;
+        return fail(ctx, CS_ERR_NOMEM, "FP32 analysis buffer of %zu bytes could not be allocated", bytes);
+    }
+    ctx->alpha32_bytes = bytes;
+    return CS_OK;
+}
+
 int median_source(cs_ctx *ctx, const float *rgb, int H, int W, int p, double mask_sigma, const float *omega,
                   int k, int precision, const float *alpha, const float **src) {
     *src = alpha;
     if (precision != CS_BF16) return CS_OK;
-    const size_t bytes = sizeof(float) * (size_t)H * W * k;
-    if (bytes > ctx->alpha32_bytes) {
-        HIP_TRY(hipDeviceSynchronize());
-        if (ctx->alpha32) HIP_TRY(hipFree(ctx->alpha32));
-        ctx->alpha32 = nullptr;
-        ctx->alpha32_bytes = 0;
-        if (hipMalloc((void **)&ctx->alpha32, bytes) != hipSuccess) {
-            ctx->alpha32 = nullptr;
-            return fail(ctx, CS_ERR_NOMEM, "FP32 analysis buffer of %zu bytes could not be allocated", bytes);
-        }
-        ctx->alpha32_bytes = bytes;
-    }
-    int rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, CS_FP32, ctx->alpha32);
+    int rc = ensure_alpha32(ctx, sizeof(float) * (size_t)H * W * k);
+    if (rc) return rc;
+    rc = cs_analyze_patches(ctx, rgb, H, W, p, mask_sigma, omega, k, CS_FP32, ctx->alpha32);
     if (rc) return rc;
     *src = ctx->alpha32;
     return CS_OK;
@@ -696,11 +702,19 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
     if ((rc = check_patch_inputs_finite(ctx, rgb, H, W, omega, k, p))) return rc;
     if ((rc = ensure_mask(ctx, p, mask_sigma))) return rc;
     const int64_t count = (int64_t)H * W * k;
-    if (precision == CS_FP32 && margin < 0.0) {
+    if (margin < 0.0) {
         // the masks are decided in the candidate gather of the median: four
         // passes over alpha instead of five; the analysis kernel also sets up
         // the selection, and each digit is picked by the kernel after its
-        // histogram
+        // histogram.  For BF16 this runs on the FP32 analysis that the call
+        // selects tau on anyway (its masks at the proven margin are the exact
+        // masks, which the BF16 vectors at their proven margin give as well),
+        // and the BF16 analysis then writes alpha.
+        float *a32 = alpha;
+        if (precision == CS_BF16) {
+            if ((rc = ensure_alpha32(ctx, sizeof(float) * (size_t)count))) return rc;
+            a32 = ctx->alpha32;
+        }
         const int n = p * p;
         const LaunchCtx lc = lc_of(ctx);
         Carve cv;
@@ -747,7 +761,7 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
             a.k = k;
             a.wmask = ctx->wmask;
             a.omega = omega;
-            a.alpha = alpha;
+            a.alpha = a32;
             a.pstats = pst;
             a.tau_st = st;
             a.tau_hist3 = hist3;
@@ -756,15 +770,15 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
             a.tau_coef = margin_coef(CS_FP32, n);
             a.tau_rank0 = (unsigned long long)((count - 1) / 2);
             Timed t(ctx, "analyze");
-            HIP_TRY(launch_analyze(lc, a, precision));
+            HIP_TRY(launch_analyze(lc, a, CS_FP32));
         }
         {
             Timed t(ctx, "tau_select");
-            HIP_TRY(tau_digits_folded(lc, alpha, count, hist3, st));
+            HIP_TRY(tau_digits_folded(lc, a32, count, hist3, st));
         }
         {
             Timed t(ctx, "cosupport");
-            HIP_TRY(median_mask_gather(lc, alpha, (int64_t)H * W, k, mmax, marg, frac, st, cand, ccnt, parts, didx,
+            HIP_TRY(median_mask_gather(lc, a32, (int64_t)H * W, k, mmax, marg, frac, st, cand, ccnt, parts, didx,
                                        dcnt, masks, hist3));
             HIP_TRY(list_compact(lc, median_gather_waves((int64_t)H * W), cand, ccnt, didx, dcnt, st, fl));
         }
@@ -775,8 +789,23 @@ int cs_cosupport_median(cs_ctx *ctx, const float *rgb, int H, int W, int p, doub
         }
         {
             Timed t(ctx, "cosupport_fix");
-            HIP_TRY(median_mask_finish(lc, alpha, rgb, H, W, p, ctx->wmask, omega, k, didx, dcnt, fl.dcomp, marg, st,
+            HIP_TRY(median_mask_finish(lc, a32, rgb, H, W, p, ctx->wmask, omega, k, didx, dcnt, fl.dcomp, marg, st,
                                        masks, pst));
+        }
+        if (precision == CS_BF16) {
+            AnalyzeArgs a{};
+            a.rgb = rgb;
+            a.H = H;
+            a.W = W;
+            a.p = p;
+            a.n = n;
+            a.n_pad = n_pad_of(n);
+            a.k = k;
+            a.wmask = ctx->wmask;
+            a.omega = omega;
+            a.alpha = alpha;
+            Timed t(ctx, "analyze_bf16");
+            HIP_TRY(launch_analyze(lc, a, CS_BF16));
         }
         return CS_OK;
     }
