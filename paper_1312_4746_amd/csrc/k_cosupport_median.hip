@@ -80,7 +80,6 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
     const double tlo = mlo > 0.0 ? nextafter(frac * mlo, 0.0) : 0.0;
     const double thi = nextafter(frac * mhi, INFINITY);
     float tin[W64], tout[W64];
-    uint64_t vmask[W64];
 #pragma unroll
     for (int w = 0; w < W64; ++w) {
         const int j = 64 * w + lane;
@@ -93,7 +92,6 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
         if ((double)fb < b) fb = nextafterf(fb, INFINITY);
         tin[w] = fa;
         tout[w] = fb;
-        vmask[w] = __ballot(jv);
     }
     unsigned long long below = 0;
     const int64_t nrounds = (N + kPx - 1) / kPx;
@@ -141,10 +139,12 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
         for (int i = 0; i < kPx; ++i)
 #pragma unroll
             for (int w = 0; w < W64; ++w) {
-                const bool live = ((vmask[w] >> lane) & 1ull) && p0 + i < N;
+                // rows past k and pixels past N hold the key of +inf, which
+                // every test below rejects (not below, no candidate, not in,
+                // not deferred), so no separate liveness mask is needed
                 const uint32_t x = key[i][w];
-                below += (live && x < blo) ? 1ull : 0ull;
-                const bool is_cand = live && x >= blo && x <= bhi;
+                below += x < blo ? 1ull : 0ull;
+                const bool is_cand = x >= blo && x <= bhi;
                 const unsigned long long cm = __ballot(is_cand);
                 if (cm) {
                     if (is_cand) creg[nc_w + __popcll(cm & lt)] = (p0 + i) * k + 64 * w + lane;
@@ -152,8 +152,8 @@ __global__ __launch_bounds__(256) void k_median_mask_gather(const float *alpha, 
                 }
                 const float f = __uint_as_float(x);
                 const uint64_t inb = __ballot(f <= tin[w]);
-                if (li == i && lw == w) outw = inb & vmask[w];
-                const bool defer = live && !(f <= tin[w]) && !(f > tout[w]);  // NaN: deferred
+                if (li == i && lw == w) outw = inb;
+                const bool defer = !(f <= tin[w]) && !(f > tout[w]);  // NaN: deferred
                 const unsigned long long dm = __ballot(defer);
                 if (dm) {
                     if (defer) dreg[nd_w + __popcll(dm & lt)] = (p0 + i) * k + 64 * w + lane;
