@@ -70,6 +70,7 @@
 namespace cs {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -820,6 +821,311 @@ void k_parzen_mfma(ParzenFastArgs a) {
     }
 }
 
+// Colour levels, transposed 32 x 32 form.  The products run as
+// v_mfma_scale_f32_32x32x64_f8f6f4 (texture, FP6) and
+// v_mfma_f32_32x32x16_bf16 (location on K 0..15, colour on K 0..7) with the
+// samples as rows (A) and the pixels as columns (B): lane l owns the tile
+// slot l mod 32 (one pixel, its coefficients and its sum) and accumulates 16
+// of every 32 samples, the lane l xor 32 the other 16.  Against the 16 x 16
+// form the location and colour products use the whole K (14 and 8 of 16
+// slots instead of 14 and 8 of 32), a quarter fewer matrix-core cycles per
+// pair, and the per-pixel state is one register each.  The pair arithmetic
+// is the same; the per-pixel reference, rescale and overflow retry work as
+// in the 16 x 16 form (the two lanes of a pixel move together).  The pixel
+// operands come from the arrays k_prep builds for the 16 x 16 form.
+template <int KSTEPS, bool TEX, bool LIST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_parzen_mfma32(ParzenFastArgs a) {
+    constexpr int RB = kParzenRB;
+    constexpr int KP = 128 * KSTEPS;
+    constexpr int NQ = 2 * KSTEPS;                   // 64-feature K steps
+    constexpr int FEAT_B = TEX ? kChunkS * KP : 16;  // feature bytes per chunk
+    __shared__ __align__(16) uint8_t s_feat0[FEAT_B];
+    __shared__ __align__(16) uint8_t s_feat1[FEAT_B];
+    __shared__ __align__(16) float s_rec0[kRecChunkF];
+    __shared__ __align__(16) float s_rec1[kRecChunkF];
+    __shared__ int s_item, s_queue;
+    __shared__ int s_ovf;  // any wave of the workgroup overflowed in the last pass
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    // h: K half of the lane's operands; j: its sample row (A) and its pixel,
+    // tile slot j (B and the result column)
+    const int h = lane >> 5, j = lane & 31;
+    const int64_t coef_label_stride = (int64_t)a.ngroups * 4 * kTilePix;
+    // LDS byte offsets of the lane's sample operands in step 0 of a chunk
+    // buffer (step st adds 32 rows; the swizzle of rows j and 32 st + j is the
+    // same): FP6 group 2 q + h of row j, location plane h, the colour plane
+    int foff[NQ][2];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) foff[q][hh] = j * KP + 16 * swz(2 * (2 * q + h) + hh, j);
+    const int loff = h * (16 * kChunkS) + 16 * j;
+    const int coff = 32 * kChunkS + 16 * j;
+    uint32_t n_rescale = 0;   // wave-chunks whose reference moved (wave-uniform)
+    uint32_t n_overflow = 0;  // passes stopped by an overflow
+
+    int queue = blockIdx.x % kParzenQueues, emptied = 0;
+    if (tid == 0) s_ovf = 0;
+    for (;;) {
+        __syncthreads();  // the previous item's LDS reads are done
+        if (tid == 0) {
+            int it = -1;
+            while (emptied < kParzenQueues) {
+                const int nq = queue < a.ngroups ? (a.ngroups - 1 - queue) / kParzenQueues + 1 : 0;
+                const int t = (int)atomicAdd(a.work_counter + queue * kQueueStride, 1u);
+                if (t < nq * a.L) {
+                    it = t;
+                    break;
+                }
+                queue = queue + 1 == kParzenQueues ? 0 : queue + 1;
+                ++emptied;
+            }
+            s_item = it;
+            s_queue = queue;
+        }
+        __syncthreads();
+        const int item = s_item;
+        if (item < 0) break;
+        // item -> (group, label): as in the 16 x 16 form
+        const int qg = s_queue < a.ngroups ? (a.ngroups - 1 - s_queue) / kParzenQueues + 1 : 0;
+        const int tg = qg < kTailGroups ? qg : kTailGroups;
+        const int hg = qg - tg;
+        const int head_items = hg * a.L;
+        int gi, lrank;
+        if (item < head_items) {
+            const int nblk = (a.L + a.lblock - 1) / a.lblock;
+            int b = item / (hg * a.lblock);
+            if (b > nblk - 1) b = nblk - 1;
+            const int bsz = b < nblk - 1 ? a.lblock : a.L - a.lblock * (nblk - 1);
+            const int rr = item - hg * a.lblock * b;
+            gi = rr / bsz;
+            lrank = a.lblock * b + (rr - gi * bsz);
+        } else {
+            const int jj = item - head_items;
+            lrank = jj / tg;
+            gi = qg - tg + (jj - lrank * tg);
+        }
+        const int grp = s_queue + kParzenQueues * gi;
+        const int lab = a.meta[a.L + 1 + lrank];
+        const int c0 = a.meta[lab], c1 = a.meta[lab + 1];
+        const int last_steps = a.meta[2 * a.L + 1 + lab];  // 16-sample steps of the last chunk
+        const int tile = grp * 4 + wave;
+        const bool tile_ok = tile < a.ntiles;
+        const int ty_t = tile_ok ? tile / a.tiles_x : 0;
+        const int x0 = (tile_ok ? tile - ty_t * a.tiles_x : 0) * 8, y0 = ty_t * 2 * RB;
+        // this lane's pixel, slot j (fast_slot_row): on the grid (x0 + j mod 8,
+        // y0 + j / 8), on a list entry 32 tile + j
+        bool pv;
+        if constexpr (LIST) {
+            pv = (int64_t)tile * kTilePix + j < a.nlist;
+        } else {
+            pv = tile_ok && x0 + (j & 7) < a.W && y0 + (j >> 3) < a.H;
+        }
+
+        auto issue = [&](int c, uint8_t *sf, float *sr) {
+            uint32_t off = (uint32_t)tid * 16u;
+            __asm__ volatile("" : "+v"(off));
+            if constexpr (TEX) {
+                const uint8_t *fbase = a.feat + (int64_t)c * FEAT_B;
+#pragma unroll
+                for (int u = 0; u < FEAT_B / 4096; ++u)
+                    __builtin_amdgcn_global_load_lds(fbase + u * 4096 + off,
+                                                     (lds_void *)(sf + u * 4096 + wave_u * 1024), 16, 0, 0);
+            }
+            if (wave_u < 3) {
+                const uint8_t *rbase = reinterpret_cast<const uint8_t *>(a.rec) + (int64_t)c * (kRecChunkF * 4);
+                __builtin_amdgcn_global_load_lds(rbase + off, (lds_void *)(sr + wave_u * 256), 16, 0, 0);
+            }
+        };
+        issue(c0, s_feat0, s_rec0);
+
+        // coefficients of this label (log2 units): nA, nB, -reference, K
+        const float4 *cf = a.coef + (int64_t)lab * coef_label_stride + (int64_t)tile * kTilePix;
+        const float4 q4 = cf[j];
+        const float nA = q4.x, nB = q4.y;
+        float nR = q4.z;
+        bool active = __ballot(pv) != 0ull;  // wave-uniform
+        const bool wave_valid = active;
+        // padding samples sit at Q ~ 2^100; a bandwidth wide enough to reach
+        // them (or a non-finite one) goes to the exact kernel
+        bool item_bad = __ballot(pv && !(q4.x < -1e-18f)) != 0ull;
+        if (item_bad) active = false;
+
+        // pixel operands (B): FP6 group 2 q + h of slot j, the BF16 location
+        // pieces of K 8h .. 8h + 7 and (h = 0) the colour pieces, from the
+        // arrays k_prep lays out for the 16 x 16 form (slot 16 rb + jl is row
+        // jl of block rb there; group 4 qo + g is step qo, lane group g)
+        const int rb = j >> 4, jl = j & 15;
+        i32x8 Bop[NQ];
+        if constexpr (TEX) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int g2 = 2 * q + h, qo = g2 >> 2, g = g2 & 3;
+                const uint4 *src = reinterpret_cast<const uint4 *>(
+                    a.aop + ((((int64_t)tile * RB + rb) * KSTEPS + qo) * 64 + g * 16 + jl) * 8);
+                const uint4 lo4 = src[0];
+                const uint2 hi2 = *reinterpret_cast<const uint2 *>(src + 1);
+                Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w, (int)hi2.x, (int)hi2.y, 0, 0};
+            }
+        }
+        const uint8_t *bb = a.abf + (((int64_t)tile * RB + rb) * 64 + jl) * 16;
+        const s16x8 Bloc = *reinterpret_cast<const s16x8 *>(bb + h * 16 * 16);
+        s16x8 Bcol = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (h == 0) Bcol = *reinterpret_cast<const s16x8 *>(bb + 2 * 16 * 16);
+
+        float S = 0.0f;
+        uint32_t nraise = 0;  // overflows of this pixel so far (reference raised by kRaise each)
+        bool ovf_wave = false, ovf_pix = false;
+
+        auto process = [&](int c, const uint8_t *F, const float *Rr, uint8_t *Fn, float *Rn) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();  // chunk c resident in (F, Rr); the other pair is free
+            if (c + 1 < c1) issue(c + 1, Fn, Rn);
+            if (!active) return;
+            const int nst = c + 1 == c1 ? (last_steps + 1) / 2 : kChunkS / 32;
+#pragma unroll
+            for (int st = 0; st < kChunkS / 32; ++st) {
+                if (st >= nst) break;
+                const uint8_t *Fs = F + st * 32 * KP;
+                const uint8_t *Rs = reinterpret_cast<const uint8_t *>(Rr) + st * 32 * 16;
+                f32x16 T;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) T[v] = 0.0f;
+                if constexpr (TEX) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        const uint4 lo4 = *reinterpret_cast<const uint4 *>(Fs + foff[q][0]);
+                        const uint2 hi2 = *reinterpret_cast<const uint2 *>(Fs + foff[q][1]);
+                        const i32x8 Aop =
+                            i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w, (int)hi2.x, (int)hi2.y, 0, 0};
+                        // formats 2, 2: both operands FP6 E2M3; unit scales
+                        T = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(Aop, Bop[q], T, 2, 2, 0, 127, 0, 127);
+                    }
+                }
+                const s16x8 Aloc = *reinterpret_cast<const s16x8 *>(Rs + loff);
+                const s16x8 Acol = *reinterpret_cast<const s16x8 *>(Rs + coff);
+                f32x16 Z;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) Z[v] = 0.0f;
+                const f32x16 Q = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Aloc),
+                                                                         __builtin_bit_cast(bf16x8, Bloc), Z, 0, 0, 0);
+                const f32x16 C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Acol),
+                                                                         __builtin_bit_cast(bf16x8, Bcol), Z, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    float u = TEX ? fmaf(T[v], nB, nR) : nR;
+                    u = fmaf(Q[v], nA, u);
+                    u = fmaf(C[v], a.kcol, u);
+                    S += __builtin_amdgcn_exp2f(u);
+                }
+            }
+            // A lane sum above 2^64 moves the pixel's reference up by a whole
+            // power of two (the larger need of its two lanes; exact rescale).
+            // An overflowed sum stops the wave's pass (retry below).
+            if (__ballot(!(S <= 0x1p64f))) {
+                ++n_rescale;
+                int e = 0;
+                if (!(S <= 0x1p64f)) {
+                    if (S <= 3.0e38f) e = (int)((__float_as_uint(S) >> 23) & 0xFFu) - 127;
+                    else e = 255;  // overflowed (or not a number)
+                }
+                e = max(e, __shfl_xor(e, 32));
+                if (e == 255) {
+                    ovf_pix = true;
+                } else if (e > 0) {
+                    S = ldexpf(S, -e);
+                    nR -= (float)e;
+                }
+                if (__ballot(e == 255)) {
+                    if (lane == 0) s_ovf = 1;
+                    ovf_wave = true;
+                    active = false;
+                    ++n_overflow;
+                }
+            }
+        };
+        // Overflow retry, as in the 16 x 16 form: the waves that overflowed
+        // compute the item again, each pixel from its own first reference less
+        // kRaise per overflow of its own, up to kRetries times.
+        for (int attempt = 0;; ++attempt) {
+            for (int c = c0; c < c1; c += 2) {
+                process(c, s_feat0, s_rec0, s_feat1, s_rec1);
+                if (c + 1 < c1) process(c + 1, s_feat1, s_rec1, s_feat0, s_rec0);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();  // every wave is past the pass; both buffer pairs are free
+            const int again = s_ovf;
+            __syncthreads();  // every wave has read the flag
+            if (!again) break;
+            if (tid == 0) s_ovf = 0;
+            if (attempt == kRetries) {
+                if (ovf_wave) item_bad = true;
+                break;
+            }
+            active = ovf_wave;
+            if (ovf_wave) {
+                nraise += ovf_pix ? 1u : 0u;
+                S = 0.0f;
+                int jo = j;
+                __asm__ volatile("" : "+v"(jo));
+                nR = cf[jo].z - kRaise * (float)nraise;
+            }
+            ovf_wave = false;
+            ovf_pix = false;
+            issue(c0, s_feat0, s_rec0);
+        }
+        if (!wave_valid) continue;
+
+        // end of item: the two lanes of a pixel add their sums
+        const float sp = S + __shfl_xor(S, 32);
+        bool bad = item_bad || (pv && !(sp <= 0x1p126f && sp > 0.0f));
+        if (__ballot(bad)) {
+            if (lane == 0) {
+                const unsigned int slot = atomicAdd(a.fix_count, 1u);
+                if (slot < (unsigned int)a.fix_cap) a.fixlist[slot] = make_int2(lab, tile);
+            }
+            continue;
+        }
+        if (h == 0 && pv) {
+            const int64_t row = LIST ? (int64_t)tile * kTilePix + j
+                                     : (int64_t)(y0 + (j >> 3)) * a.W + x0 + (j & 7);
+            const double K = (double)q4.w;
+            const double lg = kLn2F * ((double)(-nR) + (double)__builtin_amdgcn_logf(sp)) + K;
+            a.loglik[row * a.L + lab] = (float)lg;
+        }
+    }
+    if (lane == 0 && (n_rescale | n_overflow)) {
+        if (n_rescale) atomicAdd(a.fix_count + 1, n_rescale);
+        if (n_overflow) atomicAdd(a.fix_count + 2, n_overflow);
+    }
+}
+
+template <int KSTEPS, bool TEX, bool LIST>
+static hipError_t launch_mfma32_k(const LaunchCtx &lc, const ParzenFastArgs &a) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma32<KSTEPS, TEX, LIST>, 256, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    int64_t blocks = (int64_t)lc.num_cu * per_cu;
+    const int64_t items = (int64_t)a.ngroups * a.L;
+    if (blocks > items) blocks = items;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_parzen_mfma32<KSTEPS, TEX, LIST>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
+    return hipGetLastError();
+}
+
+template <bool LIST>
+static hipError_t launch_mfma32_list(const LaunchCtx &lc, const ParzenFastArgs &a) {
+    if (!a.texture) return launch_mfma32_k<1, false, LIST>(lc, a);
+    switch (a.ksteps) {
+        case 1: return launch_mfma32_k<1, true, LIST>(lc, a);
+        case 2: return launch_mfma32_k<2, true, LIST>(lc, a);
+        default: return launch_mfma32_k<3, true, LIST>(lc, a);
+    }
+}
+
 template <int KSTEPS, bool TEX, bool LIST, bool COLQ>
 static hipError_t launch_mfma_k(const LaunchCtx &lc, const ParzenFastArgs &a) {
     int per_cu = 0;
@@ -846,7 +1152,7 @@ static hipError_t launch_mfma_list(const LaunchCtx &lc, const ParzenFastArgs &a)
 }
 
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a) {
-    if (a.levels > 0) return a.list ? launch_mfma_list<true, true>(lc, a) : launch_mfma_list<false, true>(lc, a);
+    if (a.levels > 0) return a.list ? launch_mfma32_list<true>(lc, a) : launch_mfma32_list<false>(lc, a);
     return a.list ? launch_mfma_list<true, false>(lc, a) : launch_mfma_list<false, false>(lc, a);
 }
 

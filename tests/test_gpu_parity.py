@@ -512,17 +512,18 @@ def test_two_contexts_interleaved(ctx):
         assert torch.equal(ll, ref[i][2])
 
 
-def test_loglik_overflow_retry_on_matrix_core_path(ctx):
+@pytest.mark.parametrize("levels", [0, 255])
+def test_loglik_overflow_retry_on_matrix_core_path(ctx, levels):
     """Sums that overflow inside a chunk are computed again on the matrix-core
     path with raised references (no hand-off to the exact kernel): every
     sample the reference is estimated from (the nearest one and four strided
     ones) is 0.8 off in every colour channel, about 550 log2 units below the
-    two good samples at the corners."""
+    two good samples at the corners (with colour levels: colours 0 and 0.8)."""
     H, W = 16, 24
-    rgb = np.full((3, H, W), 0.5, np.float32)
+    rgb = np.full((3, H, W), 0.5 if levels == 0 else 0.0, np.float32)
     bad = [(r, c) for r in range(6, 10) for c in range(7, 17)]  # 40 samples
     for r, c in bad:
-        rgb[:, r, c] = 1.3
+        rgb[:, r, c] = 1.3 if levels == 0 else 204.0 / 255.0
     pix = [r * W + c for r, c in bad]
     pix[5] = 0              # good samples (colour 0.5) at indices 5 and 15 of the label,
     pix[15] = H * W - 1     # away from the strided probes 0, 10, 20, 30
@@ -532,6 +533,7 @@ def test_loglik_overflow_retry_on_matrix_core_path(ctx):
     w.sample_label = np.zeros(len(pix), np.int32)
     w.L = 1
     w.k = 8
+    w.colour_levels = levels
     masks = np.zeros((H * W, 1), np.uint64)
     got, ref = _loglik_both(ctx, w, masks)
     _ll_check(got, ref)
@@ -545,13 +547,18 @@ def _list_case():
 
 
 @pytest.mark.parametrize("n", [1023, 1024, 1061])
-def test_loglik_pixel_list_routes(ctx, n):
+@pytest.mark.parametrize("levels", [0, 255])
+def test_loglik_pixel_list_routes(ctx, n, levels):
     """Pixel subsets below 1024 entries take the exact kernel, from 1024 on the
     matrix-core kernel in tiles of 32 consecutive entries (1024: 32 whole
     tiles; 1061: a ragged last tile); duplicates and the corner pixels
     included.  On the matrix-core path every row equals the full-image
-    result of its pixel bit for bit."""
+    result of its pixel bit for bit (float colours: the 16 x 16 kernel; 8-bit
+    colours: the 32 x 32 one)."""
     w = _list_case()
+    if levels:
+        w.rgb = quantise_colours(w.rgb, levels)
+        w.colour_levels = levels
     masks, _, _ = oracle.full_masks(w)
     rng = np.random.default_rng(n)
     pix = rng.integers(0, w.N, n).astype(np.int32)
@@ -567,16 +574,18 @@ def test_loglik_pixel_list_routes(ctx, n):
     assert np.array_equal(got, full[pix])
 
 
-def test_loglik_pixel_list_overflow_retry(ctx):
+@pytest.mark.parametrize("levels", [0, 255])
+def test_loglik_pixel_list_overflow_retry(ctx, levels):
     """The overflow-retry construction as a pixel list (every pixel three times
     in shuffled order): the overflowing sums are computed again on the
     matrix-core path, and each row equals the full-image row of its pixel bit
-    for bit although its wave companions differ."""
+    for bit although its wave companions differ.  With colour levels the
+    colours are 0 and 0.8 (distance 0.8 per channel)."""
     H, W = 16, 24
-    rgb = np.full((3, H, W), 0.5, np.float32)
+    rgb = np.full((3, H, W), 0.5 if levels == 0 else 0.0, np.float32)
     bad = [(r, c) for r in range(6, 10) for c in range(7, 17)]
     for r, c in bad:
-        rgb[:, r, c] = 1.3
+        rgb[:, r, c] = 1.3 if levels == 0 else 204.0 / 255.0
     pixs = [r * W + c for r, c in bad]
     pixs[5] = 0
     pixs[15] = H * W - 1
@@ -586,6 +595,7 @@ def test_loglik_pixel_list_overflow_retry(ctx):
     w.sample_label = np.zeros(len(pixs), np.int32)
     w.L = 1
     w.k = 8
+    w.colour_levels = levels
     masks = np.zeros((H * W, 1), np.uint64)
     pix = np.random.default_rng(4).permutation(np.tile(np.arange(H * W, dtype=np.int32), 3))
     got, ref = _loglik_both(ctx, w, masks, pix=pix)
