@@ -32,10 +32,11 @@
 // - 128 in -128..127 per channel, the squared colour distance
 // |q_x|^2 - 2 q_x.q_y + |q_y|^2 is an integer below 2^18 whose every factor
 // is exact in BF16 (|q|^2 < 2^16 split at bit 8), so it is a third BF16
-// product, on K 16..23 of the same location operands (the lanes g = 2), exact
-// in FP32.  One FMA with kcol = -log2(e) / (2 sigma_c^2 n^2) replaces the six
-// colour instructions: five VALU instructions per pair, one of them the
-// v_exp_f32.
+// product, exact in FP32.  One FMA with kcol = -log2(e) / (2 sigma_c^2 n^2)
+// replaces the six colour instructions: five VALU instructions per pair, one
+// of them the v_exp_f32.  That form (k_parzen_mfma32, below the 16 x 16 one)
+// runs the products as 32 x 32 blocks with the samples as rows and one pixel
+// per lane; the 16 x 16 form (k_parzen_mfma) takes float colours.
 //
 // Work decomposition.  A workgroup of 4 waves owns four 8x4 pixel tiles (one
 // per wave); a work item is such a group and one label.  Items come from one
@@ -386,11 +387,9 @@ hipError_t launch_prep(const LaunchCtx &lc, PrepArgs a) {
 // step, two with the wider feature rows.
 // TEX = false: the texture factor stays out of the sum (eq:joined forms):
 // no feature stream, no FP6 products, only the location and colour terms.
-// COLQ: colour levels (ParzenFastArgs::levels > 0): the squared colour
-// distance is a third matrix-core product (BF16, K 16..23 of the location
-// operands, exact integers) and the pixel operands stay in registers.
-template <int KSTEPS, bool TEX, bool LIST, bool COLQ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 || (KSTEPS == 2 && COLQ) ? 4 : 2)))
+// This form takes float colours (colour levels go to k_parzen_mfma32).
+template <int KSTEPS, bool TEX, bool LIST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KSTEPS == 1 ? 4 : 2)))
 void k_parzen_mfma(ParzenFastArgs a) {
     constexpr int RB = kParzenRB;
     constexpr int KP = 128 * KSTEPS;
@@ -404,7 +403,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
     __shared__ __align__(16) float s_rec1[kRecChunkF];
     // each wave's BF16 location operands (read at every step; kept here
     // rather than in registers, which the kernel has none left of)
-    __shared__ __align__(16) s16x8 s_abf[4][COLQ ? 1 : RB][64];
+    __shared__ __align__(16) s16x8 s_abf[4][RB][64];
     __shared__ int s_item, s_queue;
     // overflow retry: any wave of the workgroup overflowed in the last pass,
     // and per lane the pixels (bit 4 rb + r) whose sums overflowed
@@ -429,10 +428,6 @@ void k_parzen_mfma(ParzenFastArgs a) {
         for (int h = 0; h < 2; ++h) foff[q][h] = jl * KP + 16 * swz(8 * q + 2 * g + h, jl);
     const int loff = (g & 1) * (16 * kChunkS) + 16 * jl;  // location pieces, K 0..7 or 8..15
     const int coff = 32 * kChunkS + 16 * jl;              // colours
-    // B operand of the location (and colour) products: with colour levels the
-    // lanes g = 2 take the colour pieces K 16..23 (the other lanes' K 16..31
-    // meet zero pixel pieces in one product or the other)
-    const int boff = COLQ && g == 2 ? coff : loff;
     uint32_t n_rescale = 0;  // wave-chunks whose reference moved (wave-uniform)
     uint32_t n_overflow = 0; // (label, tile) items handed to the exact kernel on overflow
 
@@ -546,12 +541,10 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 const int ti = (2 * rb + (g >> 1)) * 8 + 4 * (g & 1) + r;
                 const bool v = slot_ok(rb, r);
                 anyvalid |= v;
-                if constexpr (!COLQ) {
-                    const float4 c = pt[ti];
-                    pr[rb][r] = c.x;
-                    pg[rb][r] = c.y;
-                    pb[rb][r] = c.z;
-                }
+                const float4 c = pt[ti];
+                pr[rb][r] = c.x;
+                pg[rb][r] = c.y;
+                pb[rb][r] = c.z;
                 const float4 q = cf[ti];
                 nA[rb][r] = q.x;
                 nB[rb][r] = q.y;
@@ -567,10 +560,6 @@ void k_parzen_mfma(ParzenFastArgs a) {
         // k_pixel_operands): the FP6 texture operand into registers, the BF16
         // location operand straight into LDS (read at every step)
         i32x8 Aop[RB][KSTEPS];
-        // with colour levels: the location and colour operands of the lane, in
-        // registers (the lane's 16-byte slot holds the location pieces for g <
-        // 2, the colour pieces for g = 2, zeros for g = 3)
-        s16x8 Aloc[RB], Acol[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             if constexpr (TEX) {
@@ -585,14 +574,7 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 }
             }
             const uint8_t *bsrc = a.abf + (((int64_t)tile * RB + rb) * 64 + lane) * 16;
-            if constexpr (COLQ) {
-                const s16x8 x = *reinterpret_cast<const s16x8 *>(bsrc);
-                const s16x8 z = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                Aloc[rb] = g < 2 ? x : z;
-                Acol[rb] = g == 2 ? x : z;
-            } else {
-                __builtin_amdgcn_global_load_lds(bsrc, (lds_void *)&s_abf[wave][rb][0], 16, 0, 0);
-            }
+            __builtin_amdgcn_global_load_lds(bsrc, (lds_void *)&s_abf[wave][rb][0], 16, 0, 0);
         }
         bool item_bad = __ballot(weak) != 0ull;
         if (item_bad) active = false;
@@ -619,9 +601,9 @@ void k_parzen_mfma(ParzenFastArgs a) {
                 if (st >= nst) break;
                 // opaque lane index: the location operand is read from LDS here
                 // at every step instead of being hoisted out of the loop into
-                // registers (with colour levels it lives in registers)
+                // registers
                 int al = lane;
-                if constexpr (!COLQ) __asm__ volatile("" : "+v"(al));
+                __asm__ volatile("" : "+v"(al));
                 const uint8_t *Fs = F + st * 16 * KP;
                 const uint8_t *Rs = reinterpret_cast<const uint8_t *>(Rr) + st * 256;
                 i32x8 Bop[KSTEPS];
@@ -633,10 +615,9 @@ void k_parzen_mfma(ParzenFastArgs a) {
                         Bop[q] = i32x8{(int)lo4.x, (int)lo4.y, (int)lo4.z, (int)lo4.w, (int)hi2.x, (int)hi2.y, 0, 0};
                     }
                 }
-                const s16x8 Bbf = *reinterpret_cast<const s16x8 *>(Rs + boff);
-                float4 col = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if constexpr (!COLQ) col = *reinterpret_cast<const float4 *>(Rs + coff);
-                f32x4 T[RB], Q[RB], C[RB];
+                const s16x8 Bbf = *reinterpret_cast<const s16x8 *>(Rs + loff);
+                const float4 col = *reinterpret_cast<const float4 *>(Rs + coff);
+                f32x4 T[RB], Q[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) {
                     T[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -647,33 +628,20 @@ void k_parzen_mfma(ParzenFastArgs a) {
                             T[rb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(Aop[rb][q], Bop[q], T[rb],
                                                                                       2, 2, 0, 127, 0, 127);
                     }
-                    if constexpr (COLQ) {
-                        Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Aloc[rb]),
-                                                                        __builtin_bit_cast(bf16x8, Bbf),
-                                                                        f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-                        C[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Acol[rb]),
-                                                                        __builtin_bit_cast(bf16x8, Bbf),
-                                                                        f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-                    } else {
-                        Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            __builtin_bit_cast(bf16x8, s_abf[wave][rb][al]), __builtin_bit_cast(bf16x8, Bbf),
-                            f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-                    }
+                    Q[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, s_abf[wave][rb][al]),
+                                                                    __builtin_bit_cast(bf16x8, Bbf),
+                                                                    f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
                 }
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
+                        const float dr = pr[rb][r] - col.x, dg = pg[rb][r] - col.y, db = pb[rb][r] - col.z;
                         float u = TEX ? fmaf(T[rb][r], nB[rb][r], nR[rb][r]) : nR[rb][r];
                         u = fmaf(Q[rb][r], nA[rb][r], u);
-                        if constexpr (COLQ) {
-                            u = fmaf(C[rb][r], a.kcol, u);
-                        } else {
-                            const float dr = pr[rb][r] - col.x, dg = pg[rb][r] - col.y, db = pb[rb][r] - col.z;
-                            u = fmaf(-dr, dr, u);
-                            u = fmaf(-dg, dg, u);
-                            u = fmaf(-db, db, u);
-                        }
+                        u = fmaf(-dr, dr, u);
+                        u = fmaf(-dg, dg, u);
+                        u = fmaf(-db, db, u);
                         S[rb][r] += __builtin_amdgcn_exp2f(u);
                     }
             }
@@ -1126,34 +1094,33 @@ static hipError_t launch_mfma32_list(const LaunchCtx &lc, const ParzenFastArgs &
     }
 }
 
-template <int KSTEPS, bool TEX, bool LIST, bool COLQ>
+template <int KSTEPS, bool TEX, bool LIST>
 static hipError_t launch_mfma_k(const LaunchCtx &lc, const ParzenFastArgs &a) {
     int per_cu = 0;
-    hipError_t e =
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS, TEX, LIST, COLQ>, 256, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_parzen_mfma<KSTEPS, TEX, LIST>, 256, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
     int64_t blocks = (int64_t)lc.num_cu * per_cu;
     const int64_t items = (int64_t)a.ngroups * a.L;
     if (blocks > items) blocks = items;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_parzen_mfma<KSTEPS, TEX, LIST, COLQ>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
+    hipLaunchKernelGGL((k_parzen_mfma<KSTEPS, TEX, LIST>), dim3((unsigned)blocks), dim3(256), 0, lc.stream, a);
     return hipGetLastError();
 }
 
-template <bool LIST, bool COLQ>
+template <bool LIST>
 static hipError_t launch_mfma_list(const LaunchCtx &lc, const ParzenFastArgs &a) {
-    if (!a.texture) return launch_mfma_k<1, false, LIST, COLQ>(lc, a);
+    if (!a.texture) return launch_mfma_k<1, false, LIST>(lc, a);
     switch (a.ksteps) {
-        case 1: return launch_mfma_k<1, true, LIST, COLQ>(lc, a);
-        case 2: return launch_mfma_k<2, true, LIST, COLQ>(lc, a);
-        default: return launch_mfma_k<3, true, LIST, COLQ>(lc, a);
+        case 1: return launch_mfma_k<1, true, LIST>(lc, a);
+        case 2: return launch_mfma_k<2, true, LIST>(lc, a);
+        default: return launch_mfma_k<3, true, LIST>(lc, a);
     }
 }
 
 hipError_t launch_parzen_mfma(const LaunchCtx &lc, const ParzenFastArgs &a) {
     if (a.levels > 0) return a.list ? launch_mfma32_list<true>(lc, a) : launch_mfma32_list<false>(lc, a);
-    return a.list ? launch_mfma_list<true, false>(lc, a) : launch_mfma_list<false, false>(lc, a);
+    return a.list ? launch_mfma_list<true>(lc, a) : launch_mfma_list<false>(lc, a);
 }
 
 }  // namespace cs
