@@ -636,7 +636,9 @@ def main():
     tex_in_sum = not (args.joint or args.soft)
     ops_pp = parzen_ops_per_pair(w.k, tex_in_sum)
     achieved = pairs * ops_pp / avg_parzen_s
-    prof = counter_profile("k_parzen_mfma", w.name, kernel_source_digest) if tex_in_sum else None
+    # the kernel that ran: the 32 x 32 form with colour levels, the 16 x 16 one with float colours
+    parzen_kernel = "k_parzen_mfma32" if levels else "k_parzen_mfma"
+    prof = counter_profile(parzen_kernel, w.name, kernel_source_digest) if tex_in_sum else None
     traffic = prof.get("bytes_per_launch") if prof else None
     counters = None
     if prof:
@@ -647,9 +649,12 @@ def main():
             counters["hbm_frac"] = traffic / avg_parzen_s / PEAK_HBM
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": traffic,
-                "kernel": "k_parzen_mfma", "avg_launch_ms": avg_parzen_s * 1e3, "ops_per_pair": ops_pp,
+                "kernel": parzen_kernel, "avg_launch_ms": avg_parzen_s * 1e3, "ops_per_pair": ops_pp,
                 "ops_model": "direct evaluation per pair: location 4, colour 6, XOR+popcount 2 ceil(k/32), "
                              "convert+exponent 4, log-sum-exp 3, v_exp_f32 as 4 slots",
+                "note": "algorithmic rate against the FP32 vector peak; the kernel forms the texture, location "
+                        "(and with colour levels the colour) terms as exact products on the matrix cores, so "
+                        "the rate can pass the vector peak: unit utilisations are under counters",
                 "counters": counters}
     avg_an = analyze_ms / 1e3 / max(analyze_n, 1)
     gemm_flops = 2.0 * w.k * w.n * w.N
