@@ -958,6 +958,20 @@ void k_parzen_mfma32(ParzenFastArgs a) {
                 if (st >= nst) break;
                 const uint8_t *Fs = F + st * 32 * KP;
                 const uint8_t *Rs = reinterpret_cast<const uint8_t *>(Rr) + st * 32 * 16;
+                const s16x8 Aloc = *reinterpret_cast<const s16x8 *>(Rs + loff);
+                const s16x8 Acol = *reinterpret_cast<const s16x8 *>(Rs + coff);
+                f32x16 Z;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) Z[v] = 0.0f;
+                const f32x16 Q = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Aloc),
+                                                                         __builtin_bit_cast(bf16x8, Bloc), Z, 0, 0, 0);
+                const f32x16 C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Acol),
+                                                                         __builtin_bit_cast(bf16x8, Bcol), Z, 0, 0, 0);
+                // location and colour first: their share of the exponent
+                // overlaps this wave's chain of texture products
+                f32x16 U;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) U[v] = fmaf(C[v], a.kcol, fmaf(Q[v], nA, nR));
                 f32x16 T;
 #pragma unroll
                 for (int v = 0; v < 16; ++v) T[v] = 0.0f;
@@ -972,20 +986,9 @@ void k_parzen_mfma32(ParzenFastArgs a) {
                         T = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(Aop, Bop[q], T, 2, 2, 0, 127, 0, 127);
                     }
                 }
-                const s16x8 Aloc = *reinterpret_cast<const s16x8 *>(Rs + loff);
-                const s16x8 Acol = *reinterpret_cast<const s16x8 *>(Rs + coff);
-                f32x16 Z;
-#pragma unroll
-                for (int v = 0; v < 16; ++v) Z[v] = 0.0f;
-                const f32x16 Q = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Aloc),
-                                                                         __builtin_bit_cast(bf16x8, Bloc), Z, 0, 0, 0);
-                const f32x16 C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, Acol),
-                                                                         __builtin_bit_cast(bf16x8, Bcol), Z, 0, 0, 0);
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    float u = TEX ? fmaf(T[v], nB, nR) : nR;
-                    u = fmaf(Q[v], nA, u);
-                    u = fmaf(C[v], a.kcol, u);
+                    const float u = TEX ? fmaf(T[v], nB, U[v]) : U[v];
                     S += __builtin_amdgcn_exp2f(u);
                 }
             }
