@@ -65,8 +65,9 @@ def load_profile(name: str):
 
 
 def kernel_source_digest() -> str:
-    """Digest of the Parzen kernel's source and of its argument struct (the
-    traffic counters stay valid while neither changes)."""
+    """Digest of the Parzen kernel's source, of its argument struct and of the
+    host code that cuts its work order into label blocks (the counters stay
+    valid while none of them changes)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1312_4746_amd", "csrc")
     h = hashlib.sha256()
@@ -76,6 +77,10 @@ def kernel_source_digest() -> str:
         hdr = fh.read()
     a = hdr.index("struct ParzenFastArgs")
     h.update(hdr[a:hdr.index("};", a)].encode())
+    with open(os.path.join(csrc, "cs_host.hip")) as fh:
+        host = fh.read()
+    a = host.index("// labels per block of the work order")
+    h.update(host[a:host.index("fa.lblock = lb;", a)].encode())
     return h.hexdigest()[:16]
 
 

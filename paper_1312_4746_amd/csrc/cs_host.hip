@@ -1126,12 +1126,17 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
         fa.list = listed ? pix_subset : nullptr;
         fa.nlist = listed ? npix : 0;
         // labels per block of the work order: as many as keep their sample
-        // streams (features and records of every chunk) within about half of
-        // an XCD's 4 MiB L2 together, counted from the largest labels (at
-        // least one)
+        // streams (features and records of every chunk) within an XCD's 4 MiB
+        // L2 together, counted from the largest labels (at least one).  Each
+        // pixel group's operands are fetched once per block, and a block's
+        // streams stay in L2 while the groups of a queue pass them.  At
+        // 1024 x 1024, k = 242, 16 labels (blocks of two) the kernel fetches
+        // 3.8 GB per launch; blocks of one label fetched 5.9 GB, of four 41 GB
+        // (the streams no longer fit), and blocks cut to the budget one by
+        // one (two to five labels) 5.1 GB
         {
             const size_t chunk_bytes = (size_t)(fa.texture ? kStreamChunk * KP : 0) + 12 * sizeof(float) * kStreamChunk;
-            const size_t budget = (size_t)2 << 20;
+            const size_t budget = (size_t)4 << 20;
             size_t used = 0;
             int lb = 0;
             while (lb < L) {
