@@ -449,6 +449,24 @@ def test_loglik_large_full_image_fast_path(ctx):
     _full_image_sampled(ctx, w, masks, 400, 12)
 
 
+@pytest.mark.parametrize("levels", [0, 255])
+def test_loglik_label_blocks_with_partial_last_block(ctx, levels):
+    """The work order's label blocks when they do not divide the labels: five
+    labels of 6 400 samples at k = 242 (100 stream chunks of 64 samples, 19 456
+    B each, per label) give blocks of two labels within the 4 MiB budget, so
+    the blocks are 2, 2 and 1 labels; 384 x 384 pixels make 1 152 pixel groups,
+    144 per queue, of which 80 go block by block before the 64 taken label by
+    label."""
+    w = make_workload("blocks", H=384, W=384, R=5, p=11, k=242, seed=31, per_region=6400,
+                      colour_levels=levels)
+    counts = np.bincount(w.sample_label, minlength=w.L)
+    chunk = 64 * 256 + 12 * 4 * 64
+    assert np.all(counts == 6400) and 2 * 100 * chunk <= 4 << 20 < 3 * 100 * chunk
+    masks, _, _ = oracle.full_masks(w)
+    st = _full_image_sampled(ctx, w, masks, 500, 31)
+    assert st["exact_tiles"] == 0
+
+
 @pytest.mark.parametrize("shape", [(16, 2048), (2048, 12)], ids=["W2048", "H2048"])
 def test_loglik_largest_coordinates_fast_path(ctx, shape):
     """Positions up to 2047 on the matrix-core path, whose location product is
