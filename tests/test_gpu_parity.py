@@ -437,7 +437,7 @@ def test_loglik_bsds_full_image_fast_path(ctx):
 
 
 def test_loglik_large_full_image_fast_path(ctx):
-    """1024x1024, k = 242 (two FP8 feature steps), 16 labels, 50,000 samples;
+    """1024x1024, k = 242 (two 128-feature FP6 steps), 16 labels, 50,000 samples;
     the masks come from the library (bit-exact with the oracle at every
     smaller case above, p = 11 and k = 242 included)."""
     w = make_config(3)
