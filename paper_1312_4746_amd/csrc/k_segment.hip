@@ -158,23 +158,32 @@ __device__ __forceinline__ T pd_label(const T *ub, const T *px, const T *py, con
                                       int64_t x, int c, int r, int H, int W, T s_xi, T s_mu, T t_u, T mb, T rad,
                                       T rad_l, T rad_u, bool mdl, T &qx, T &qy, T &mu_n) {
 #pragma clang fp contract(off)
-    const T ubc = ub[x];
-    qx = px[x] + s_xi * (c < W - 1 ? ub[x + 1] - ubc : (T)0);
-    qy = py[x] + s_xi * (r < H - 1 ? ub[x + W] - ubc : (T)0);
+    // every operand of the label loaded up front, the indices clamped into the
+    // plane, so that the loads are in flight together (one memory round trip
+    // per label); values of neighbours outside the image are not used
+    const int64_t last = (int64_t)H * W - 1;
+    auto at = [&](int64_t i) { return i < 0 ? (int64_t)0 : (i > last ? last : i); };
+    const T ubc = ub[x], ubr = ub[at(x + 1)], ubd = ub[at(x + W)];
+    const T ubl = ub[at(x - 1)], ubld = ub[at(x - 1 + W)];
+    const T ubu = ub[at(x - W)], ubur = ub[at(x - W + 1)];
+    const T pxc = px[x], pxl = px[at(x - 1)], pxu = px[at(x - W)];
+    const T pyc = py[x], pyl = py[at(x - 1)], pyu = py[at(x - W)];
+    const T uc = U[x], fc = F[x];
+    const T muc = mdl ? MU[x] : (T)0;
+    qx = pxc + s_xi * (c < W - 1 ? ubr - ubc : (T)0);
+    qy = pyc + s_xi * (r < H - 1 ? ubd - ubc : (T)0);
     project_disc(qx, qy, rad);
     // xi^{t+1}_x(x - 1) and xi^{t+1}_y(x - W), as their own threads compute them
     T lx = 0, uy = 0;
     if (c > 0) {
-        const T ubl = ub[x - 1];
-        T ax = px[x - 1] + s_xi * (ubc - ubl);
-        T ay = py[x - 1] + s_xi * (r < H - 1 ? ub[x - 1 + W] - ubl : (T)0);
+        T ax = pxl + s_xi * (ubc - ubl);
+        T ay = pyl + s_xi * (r < H - 1 ? ubld - ubl : (T)0);
         project_disc(ax, ay, rad_l);
         lx = ax;
     }
     if (r > 0) {
-        const T ubu = ub[x - W];
-        T bx = px[x - W] + s_xi * (c < W - 1 ? ub[x - W + 1] - ubu : (T)0);
-        T by = py[x - W] + s_xi * (ubc - ubu);
+        T bx = pxu + s_xi * (c < W - 1 ? ubur - ubu : (T)0);
+        T by = pyu + s_xi * (ubc - ubu);
         project_disc(bx, by, rad_u);
         uy = by;
     }
@@ -183,13 +192,13 @@ __device__ __forceinline__ T pd_label(const T *ub, const T *px, const T *py, con
     d = d - lx;
     if (r < H - 1) d = d + qy;
     d = d - uy;
-    T step = -d + F[x];
+    T step = -d + fc;
     if (mdl) {
-        mu_n = MU[x] + s_mu * (mb - ubc);
+        mu_n = muc + s_mu * (mb - ubc);
         mu_n = mu_n < (T)0 ? mu_n : (T)0;
         step = step - mu_n;
     }
-    return U[x] - t_u * step;
+    return uc - t_u * step;
 }
 
 // Michelot's projection of v[0..L) onto the simplex: project onto the
