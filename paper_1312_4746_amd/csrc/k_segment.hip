@@ -337,13 +337,27 @@ void k_pd_iter(PdArgs a, int t) {
         if (!in) return;
         uint64_t act;
         const T theta = simplex_theta<T, LMAX>(v, L, &act);
+        // u^t of every label loaded before any store (the loads in flight
+        // together)
+        T uo[LMAX];
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) uo[l] = l < L ? U[(int64_t)l * N + x] : (T)0;
+        // the new values first, then every store (no wait between stores)
+        T ubn[LMAX];
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+            v[l] = ((act >> l) & 1ull) ? v[l] - theta : (T)0;
+            ubn[l] = (T)2 * v[l] - uo[l];
+            // formed here, ahead of the stores (not sunk into the stores'
+            // per-label branches, where each would wait for earlier stores)
+            __asm__ volatile("" : "+v"(v[l]), "+v"(ubn[l]));
+        }
 #pragma unroll
         for (int l = 0; l < LMAX; ++l) {
             if (l >= L) continue;
             const int64_t o = (int64_t)l * N + x;
-            const T un = ((act >> l) & 1ull) ? v[l] - theta : (T)0;
-            UBn[o] = (T)2 * un - U[o];
-            Un[o] = un;
+            UBn[o] = ubn[l];
+            Un[o] = v[l];
         }
     } else {
         for (int l = 0; l < L; ++l) {
