@@ -461,17 +461,28 @@ __global__ __launch_bounds__(256) void k_pd_primal(PdArgs a, int t) {
     T *UBn = (T *)a.ub[nxt];
     uint64_t act;
     if constexpr (LMAX <= 16) {
-        T v[LMAX];
+        // the candidates and u^t loaded together, the new values formed
+        // before any store (as in k_pd_iter)
+        T v[LMAX], uo[LMAX];
 #pragma unroll
-        for (int l = 0; l < LMAX; ++l) v[l] = l < L ? Un[(int64_t)l * N + x] : (T)0;
+        for (int l = 0; l < LMAX; ++l) {
+            v[l] = l < L ? Un[(int64_t)l * N + x] : (T)0;
+            uo[l] = l < L ? U[(int64_t)l * N + x] : (T)0;
+        }
         const T theta = simplex_theta<T, LMAX>(v, L, &act);
+        T ubn[LMAX];
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+            v[l] = ((act >> l) & 1ull) ? v[l] - theta : (T)0;
+            ubn[l] = (T)2 * v[l] - uo[l];
+            __asm__ volatile("" : "+v"(v[l]), "+v"(ubn[l]));
+        }
 #pragma unroll
         for (int l = 0; l < LMAX; ++l) {
             if (l >= L) continue;
             const int64_t o = (int64_t)l * N + x;
-            const T un = ((act >> l) & 1ull) ? v[l] - theta : (T)0;
-            UBn[o] = (T)2 * un - U[o];
-            Un[o] = un;
+            UBn[o] = ubn[l];
+            Un[o] = v[l];
         }
     } else {
         const T theta = simplex_theta_mem<T>(Un + x, N, L, &act);
