@@ -558,14 +558,21 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
         }
         return;
     }
+    // digits of 8 bits from the highest bit in which the keys differ down
+    // (the last one narrower), so that the first pass spreads the keys over
+    // all 256 bins (a first digit of a few live bits would put every key into
+    // a few bins, whose LDS atomics then serialise)
     const int top = 63 - __clzll((long long)diff);
-    const int start = (top / 8) * 8;
-    if (tid == 0) s_prefix = start + 8 >= 64 ? 0ull : (s_min & (~0ull << (start + 8)));
+    if (tid == 0) s_prefix = top + 1 >= 64 ? 0ull : (s_min & (~0ull << (top + 1)));
     __syncthreads();
-    for (int shift = start; shift >= 0; shift -= 8) {
+    for (int hi = top; hi >= 0;) {
+        const int width = hi + 1 >= 8 ? 8 : hi + 1;
+        const int shift = hi + 1 - width;
+        hi = shift - 1;
         if (tid < 256) hist[tid] = 0;
         __syncthreads();
-        const unsigned long long hmask = shift + 8 >= 64 ? 0ull : (~0ull << (shift + 8));
+        const unsigned long long hmask = shift + width >= 64 ? 0ull : (~0ull << (shift + width));
+        const unsigned long long dmask = (1ull << width) - 1ull;
         const unsigned long long pv = s_prefix;
         for (int64_t c0 = 0; c0 < ncand; c0 += 8 * 1024) {
             unsigned long long kv[8];
@@ -573,7 +580,7 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
             keys8(c0, kv, ok);
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (ok[u] && (kv[u] & hmask) == pv) atomicAdd(&hist[(kv[u] >> shift) & 255ull], 1u);
+                if (ok[u] && (kv[u] & hmask) == pv) atomicAdd(&hist[(kv[u] >> shift) & dmask], 1u);
         }
         __syncthreads();
         if (tid < 64) {
