@@ -465,11 +465,16 @@ __global__ __launch_bounds__(64) void k_tau_rank(const double *vals, int64_t cap
 // The digits above the highest bit in which the smallest and largest key
 // differ are common to all candidates and skipped; the remaining digits are
 // selected 8 bits at a time with an LDS histogram and a one-wave scan.
+constexpr int kSelLds = 4096;  // candidates kept in LDS for the last digits
 __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t cap, double frac,
                                                       TauState *st, const unsigned long long *parts,
                                                       const unsigned long long *rk, double *tau_out) {
     __shared__ unsigned int hist[256];
     __shared__ unsigned long long s_min, s_max, s_prefix, s_rank, s_below;
+    // the candidates left after a digit, once few enough: the later digits
+    // read them here instead of passing over all candidates again
+    __shared__ unsigned long long s_keys[kSelLds];
+    __shared__ unsigned int s_left, s_nkeys;
     const int tid = threadIdx.x;
     // entries below the candidate window: the gather's per-workgroup counts
     if (tid == 0) s_below = 0;
@@ -565,22 +570,30 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
     const int top = 63 - __clzll((long long)diff);
     if (tid == 0) s_prefix = top + 1 >= 64 ? 0ull : (s_min & (~0ull << (top + 1)));
     __syncthreads();
+    bool in_lds = false;  // the keys left are in s_keys (workgroup-uniform)
     for (int hi = top; hi >= 0;) {
         const int width = hi + 1 >= 8 ? 8 : hi + 1;
         const int shift = hi + 1 - width;
-        hi = shift - 1;
         if (tid < 256) hist[tid] = 0;
         __syncthreads();
         const unsigned long long hmask = shift + width >= 64 ? 0ull : (~0ull << (shift + width));
         const unsigned long long dmask = (1ull << width) - 1ull;
         const unsigned long long pv = s_prefix;
-        for (int64_t c0 = 0; c0 < ncand; c0 += 8 * 1024) {
-            unsigned long long kv[8];
-            bool ok[8];
-            keys8(c0, kv, ok);
+        if (in_lds) {
+            const int nk = (int)s_nkeys;
+            for (int i = tid; i < nk; i += 1024) {
+                const unsigned long long kv = s_keys[i];
+                if ((kv & hmask) == pv) atomicAdd(&hist[(kv >> shift) & dmask], 1u);
+            }
+        } else {
+            for (int64_t c0 = 0; c0 < ncand; c0 += 8 * 1024) {
+                unsigned long long kv[8];
+                bool ok[8];
+                keys8(c0, kv, ok);
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (ok[u] && (kv[u] & hmask) == pv) atomicAdd(&hist[(kv[u] >> shift) & dmask], 1u);
+                for (int u = 0; u < 8; ++u)
+                    if (ok[u] && (kv[u] & hmask) == pv) atomicAdd(&hist[(kv[u] >> shift) & dmask], 1u);
+            }
         }
         __syncthreads();
         if (tid < 64) {
@@ -606,6 +619,7 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
                     if (rr < b[q]) {
                         s_prefix = pv | ((unsigned long long)(4 * tid + q) << shift);
                         s_rank = rr;
+                        s_left = b[q];
                         break;
                     }
                     rr -= b[q];
@@ -613,6 +627,25 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
             }
         }
         __syncthreads();
+        hi = shift - 1;
+        if (!in_lds && hi >= 0 && s_left <= (unsigned int)kSelLds) {
+            // one more pass over all candidates copies the keys that share the
+            // prefix chosen so far (exactly s_left of them) into LDS
+            if (tid == 0) s_nkeys = 0;
+            __syncthreads();
+            const unsigned long long nmask = ~0ull << shift;
+            const unsigned long long np2 = s_prefix;
+            for (int64_t c0 = 0; c0 < ncand; c0 += 8 * 1024) {
+                unsigned long long kv[8];
+                bool ok[8];
+                keys8(c0, kv, ok);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (ok[u] && (kv[u] & nmask) == np2) s_keys[atomicAdd(&s_nkeys, 1u)] = kv[u];
+            }
+            __syncthreads();
+            in_lds = true;
+        }
     }
     if (tid == 0) {
         const double med = __longlong_as_double((long long)s_prefix);
