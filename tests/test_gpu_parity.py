@@ -148,6 +148,34 @@ def test_cosupport_median_bsds_shape_and_zero_image(ctx):
     assert np.all(mm[:, 1] == np.uint64(63))
 
 
+@pytest.mark.parametrize("period", [2, 3])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_tau_and_masks_with_heavy_ties(ctx, period, prec):
+    """A degenerate image for the exact selection: vertical stripes of period
+    2 or 3 on 256 x 256 pixels, k = 242, so that the patches repeat and the
+    few analysed values near the median each occur tens of thousands of times
+    (about 63 000 candidates in three values, or 21 000 in two).  The list
+    exceeds the ranked selection's limit, and the radix passes meet more keys
+    sharing a digit than the selection keeps in LDS; tau and the masks of the
+    separate and the fused calls against the oracle, bit for bit."""
+    import dataclasses
+    w = make_workload("ties", H=256, W=256, R=2, p=11, k=242, seed=41, per_region=10)
+    x = np.arange(w.W)
+    pat = (x % period == 0).astype(np.float32)
+    rgb = pat[None, None, :] * np.array([0.8, 0.5, 0.2], np.float32)[:, None, None] + np.float32(0.1)
+    w = dataclasses.replace(w, rgb=np.ascontiguousarray(np.broadcast_to(rgb, (3, w.H, w.W))))
+    a_ref = oracle.analyze(w.rgb, w.p, w.mask_sigma, w.omega)
+    tau_ref, _ = oracle.tau_median(a_ref, 0.1)
+    m_ref = oracle.cosupport(a_ref, tau_ref)
+    a_gpu = ctx.analyze_patches(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), precision=prec)
+    tau = ctx.tau_median(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), a_gpu, 0.1, precision=prec)
+    assert tau == tau_ref
+    assert np.array_equal(masks_u64(gpu_masks(ctx, w, tau, prec)), m_ref)
+    _, m, tau_d = ctx.cosupport_median(dev(w.rgb), w.p, w.mask_sigma, dev(w.omega), 0.1, precision=prec)
+    assert float(tau_d.item()) == tau_ref
+    assert np.array_equal(masks_u64(m), m_ref)
+
+
 def test_bf16_stated_margin_reports_mismatches(ctx):
     """Precision form at the stated margin 2^-8 tau: entries outside it are
     decided by the BF16 value; the mismatch count is reported, and the proven
