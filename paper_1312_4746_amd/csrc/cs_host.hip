@@ -981,7 +981,8 @@ static int label_loglik(cs_ctx *ctx, const float *rgb, int H, int W, const uint6
     }
     if (npix > 0) {
         Timed t(ctx, "edt");
-        HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest, (int32_t *)(ctx->ws + o_edt)));
+        HIP_TRY(launch_edt(lc, seeds, H, W, L, colrow, d2, nearest, (int32_t *)(ctx->ws + o_edt), pix_subset,
+                           pix_subset ? npix : 0));
     }
     int rc_wait = wait_host_tag(ctx, tag);
     if (rc_wait) return rc_wait;

@@ -262,8 +262,12 @@ hipError_t launch_sample_scatter(const LaunchCtx &lc, const int32_t *label, cons
                                  int nblocks, SampleRec *recs, uint8_t *seeds);
 hipError_t launch_check_pix(const LaunchCtx &lc, const int32_t *pix, int64_t n, int64_t N, int32_t *flags);
 size_t edt_scratch_bytes(int H, int W, int L);
+// list (or null: every pixel): with a list of npix entries the row pass runs
+// for the listed pixels only (d2 and nearest of other pixels are left as they
+// were); the listed entries equal those of the full pass bit for bit
 hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, int L,
-                      int32_t *colrow, int32_t *d2, int32_t *nearest, int32_t *scratch);
+                      int32_t *colrow, int32_t *d2, int32_t *nearest, int32_t *scratch,
+                      const int32_t *list = nullptr, int64_t npix = 0);
 
 struct ParzenArgs {
     const float *rgb;

@@ -179,20 +179,130 @@ __global__ __launch_bounds__(1024) void k_edt_rows(const int32_t *colrow, int H,
     }
 }
 
-// Scratch: first/last summaries, 2 * L * ceil(H/16) * W int32.
+// Smallest f over each block of kRowBlk columns of every row and label (the
+// block minima of k_edt_rows, for the listed form below): one thread per
+// (row, block, label).
+__global__ __launch_bounds__(256) void k_edt_block_min(const int32_t *colrow, int H, int W, int32_t *bmin) {
+    const int nb = (W + kRowBlk - 1) / kRowBlk;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int l = blockIdx.y;
+    if (i >= (int64_t)H * nb) return;
+    const int r = (int)(i / nb), b = (int)(i - (int64_t)r * nb);
+    const int32_t *cr = colrow + (int64_t)l * H * W + (int64_t)r * W;
+    int fv[kRowBlk];
+#pragma unroll
+    for (int u = 0; u < kRowBlk; ++u) {
+        const int q = b * kRowBlk + u;
+        const int s = q < W ? cr[q] : -1;
+        fv[u] = s < 0 ? kInf : (r - s) * (r - s);
+    }
+    int m = kInf;
+#pragma unroll
+    for (int u = 0; u < kRowBlk; ++u) m = min(m, fv[u]);
+    bmin[(int64_t)l * H * nb + i] = m;
+}
+
+// The row pass for listed pixels only, one thread per (entry, label): the
+// walk of k_edt_rows for the entry's column, reading f and the block minima
+// from global memory instead of LDS (the same blocks are scanned in the same
+// order, so the result and its ties are those of k_edt_rows).  Entries
+// outside the image are skipped (the host rejects them after the launch).
+__global__ __launch_bounds__(256) void k_edt_rows_list(const int32_t *colrow, const int32_t *bmin, int H,
+                                                       int W, const int32_t *list, int64_t npix, int32_t *d2,
+                                                       int32_t *nearest) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int l = blockIdx.y;
+    if (e >= npix) return;
+    const int64_t N = (int64_t)H * W;
+    const int64_t pix = list[e];
+    if (pix < 0 || pix >= N) return;
+    const int r = (int)(pix / W), c = (int)(pix - (int64_t)r * W);
+    const int nb = (W + kRowBlk - 1) / kRowBlk;
+    const int32_t *cr = colrow + (int64_t)l * N + (int64_t)r * W;
+    const int32_t *fm = bmin + ((int64_t)l * H + r) * nb;
+    auto fval = [&](int q) {
+        const int s = cr[q];
+        return s < 0 ? kInf : (r - s) * (r - s);
+    };
+    int best = fval(c), bb = -1;
+    auto scan = [&](int b) {
+        int fv[kRowBlk];
+#pragma unroll
+        for (int i = 0; i < kRowBlk; ++i) {
+            const int q = b * kRowBlk + i;
+            fv[i] = q < W ? fval(q) : kInf;  // the full pass pads with kInf
+        }
+        int m = best;
+#pragma unroll
+        for (int i = 0; i < kRowBlk; ++i) {
+            const int d = c - (b * kRowBlk + i);
+            m = min(m, __mul24(d, d) + fv[i]);
+        }
+        if (m < best) {
+            best = m;
+            bb = b;
+        }
+    };
+    const int cb = c / kRowBlk;
+    scan(cb);
+    for (int db = 1;; ++db) {
+        const int bl = cb - db, br = cb + db;
+        const int gl = c - (bl * kRowBlk + kRowBlk - 1);
+        const int gr = br * kRowBlk - c;
+        const bool lok = bl >= 0 && gl * gl < best;
+        const bool rok = br < nb && gr * gr < best;
+        if (!lok && !rok) break;
+        const int ml = lok ? fm[bl] : kInf, mr = rok ? fm[br] : kInf;
+        if (lok && gl * gl + ml < best) scan(bl);
+        if (rok && gr * gr + mr < best) scan(br);
+    }
+    int bq = c;
+    if (bb >= 0) {
+        for (int i = kRowBlk - 1; i >= 0; --i) {
+            const int q = bb * kRowBlk + i, d = c - q;
+            if (q < W && __mul24(d, d) + fval(q) == best) bq = q;
+        }
+    }
+    const int64_t o = (int64_t)l * N + pix;
+    if (best >= kInf) {
+        d2[o] = -1;
+        nearest[o] = -1;
+    } else {
+        d2[o] = best;
+        nearest[o] = cr[bq] * W + bq;
+    }
+}
+
+// Scratch: first/last summaries, 2 * L * ceil(H/16) * W int32, then (listed
+// form) the block minima, L * H * ceil(W/16) int32.
 size_t edt_scratch_bytes(int H, int W, int L) {
     const int nseg = (H + kSegRows - 1) / kSegRows;
-    return sizeof(int32_t) * 2 * (size_t)L * nseg * W;
+    const size_t nb = (size_t)(W + kRowBlk - 1) / kRowBlk;
+    const size_t summaries = 2 * (size_t)L * nseg * W, minima = (size_t)L * H * nb;
+    return sizeof(int32_t) * (summaries > minima ? summaries : minima);
 }
 
 hipError_t launch_edt(const LaunchCtx &lc, const uint8_t *seeds, int H, int W, int L,
-                      int32_t *colrow, int32_t *d2, int32_t *nearest, int32_t *scratch) {
+                      int32_t *colrow, int32_t *d2, int32_t *nearest, int32_t *scratch,
+                      const int32_t *list, int64_t npix) {
     const int nseg = (H + kSegRows - 1) / kSegRows;
     int32_t *first = scratch, *last = scratch + (size_t)L * nseg * W;
     dim3 g1((W + 63) / 64, nseg, L);
     hipLaunchKernelGGL(k_edt_col_summary, g1, dim3(64), 0, lc.stream, seeds, H, W, nseg, first, last);
     hipLaunchKernelGGL(k_edt_col_fill, g1, dim3(64), 0, lc.stream, seeds, H, W, nseg, first, last,
                        colrow);
+    // a short list (at most an eighth of the pixels) takes the per-entry row
+    // pass; longer ones the full pass, whose rows share their staging
+    if (list && npix * 8 <= (int64_t)H * W) {
+        if (npix == 0) return hipGetLastError();
+        // block minima into the scratch (the column summaries are dead by now)
+        const int64_t nbr = (int64_t)H * ((W + kRowBlk - 1) / kRowBlk);
+        hipLaunchKernelGGL(k_edt_block_min, dim3((unsigned)((nbr + 255) / 256), L), dim3(256), 0, lc.stream,
+                           colrow, H, W, scratch);
+        hipLaunchKernelGGL(k_edt_rows_list, dim3((unsigned)((npix + 255) / 256), L), dim3(256), 0, lc.stream,
+                           colrow, scratch, H, W, list, npix, d2, nearest);
+        return hipGetLastError();
+    }
     const size_t nbk = (size_t)(W + kRowBlk - 1) / kRowBlk;
     const size_t lds = sizeof(int32_t) * (2 * nbk * kRowBlk + nbk);
     hipError_t e = hipFuncSetAttribute((const void *)k_edt_rows,

@@ -621,6 +621,35 @@ def test_loglik_pixel_list_routes(ctx, n, levels):
 
 
 @pytest.mark.parametrize("levels", [0, 255])
+def test_loglik_pixel_list_distance_rows(ctx, levels):
+    """A list of at most an eighth of the pixels takes the distance
+    transform's row pass per listed entry: its rows equal the full image's bit
+    for bit (the distances, and the nearest samples that set each pixel's
+    log-sum-exp reference, are those of the full pass, ties included), on the
+    matrix-core path (3 000 entries with duplicates and the corners) and on
+    the exact kernel (600 entries) against the oracle."""
+    from paper_1312_4746_amd import LoglikParams
+    w = make_workload("lrows", H=192, W=160, R=5, p=5, k=40, seed=33, per_region=25, colour_levels=levels)
+    masks, _, _ = oracle.full_masks(w)
+    prm = LoglikParams(alpha_rho=w.alpha_rho, sigma_c=w.sigma_c, beta_scale=w.beta_scale,
+                       rho_floor_px=w.rho_floor_px, colour_levels=levels)
+    args = (dev(w.rgb), dev(masks.view(np.int64)), w.k, dev(w.sample_pix), dev(w.sample_label), w.L, prm)
+    full = ctx.label_loglik(*args).cpu().numpy()
+    rng = np.random.default_rng(34)
+    pix = rng.choice(w.N, 2990, replace=False).astype(np.int32)
+    pix = np.concatenate([pix, [0, w.W - 1, w.N - w.W, w.N - 1], pix[:6]]).astype(np.int32)
+    assert pix.size * 8 <= w.N
+    got = ctx.label_loglik(*args, pix_subset=dev(pix)).cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), full[pix].view(np.uint32))
+    small = pix[:600]
+    got_s = ctx.label_loglik(*args, pix_subset=dev(small)).cpu().numpy()
+    ref = oracle.label_loglik(w.rgb, masks, w.k, w.sample_pix, w.sample_label, w.L, alpha_rho=prm.alpha_rho,
+                              sigma_c=prm.sigma_c, beta_scale=prm.beta_scale, rho_floor=prm.rho_floor_px,
+                              pix=small)
+    _ll_check(got_s, ref)
+
+
+@pytest.mark.parametrize("levels", [0, 255])
 def test_loglik_pixel_list_overflow_retry(ctx, levels):
     """The overflow-retry construction as a pixel list (every pixel three times
     in shuffled order): the overflowing sums are computed again on the
