@@ -413,35 +413,56 @@ __global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a, int wblocks) {
 
 // ---- exact fallback of the surrogate ----
 // Pixels whose two largest surrogate outputs differ by less than `margin`
-// nats are listed (list[*count ...]; *count is zero before): one thread per
-// pixel, a wave's flags compacted by ballot and one atomic per wave.  The
-// order of the list depends on the wave schedule; each listed pixel is
-// recomputed on its own, so the results do not.
+// nats are listed (list[*count ...]; *count is zero before): each thread
+// tests kUncPer pixels, each wave compacts its flags by ballot, and one atomic
+// per workgroup (not per wave: returning atomics on one address serialise
+// across the chip) reserves the workgroup's slots.  The order of the list
+// depends on the schedule; each listed pixel is recomputed on its own, so the
+// results do not.
+constexpr int kUncPer = 16;
 __global__ __launch_bounds__(256) void k_mlp_uncertain(const float *y, int64_t n, int L, float margin,
                                                        int32_t *list, unsigned int *count) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool flag = false;
-    if (i < n) {
-        const float *r = y + i * L;
-        float t1 = r[0], t2 = -INFINITY;
-        for (int l = 1; l < L; ++l) {
-            const float v = r[l];
-            if (v > t1) {
-                t2 = t1;
-                t1 = v;
-            } else if (v > t2) {
-                t2 = v;
+    __shared__ unsigned int s_wcnt[4], s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t p0 = (int64_t)blockIdx.x * 256 * kUncPer + threadIdx.x;
+    uint64_t ball[kUncPer];
+    unsigned int wc = 0;
+#pragma unroll
+    for (int u = 0; u < kUncPer; ++u) {
+        const int64_t i = p0 + (int64_t)u * 256;
+        bool flag = false;
+        if (i < n) {
+            const float *r = y + i * L;
+            float t1 = r[0], t2 = -INFINITY;
+            for (int l = 1; l < L; ++l) {
+                const float v = r[l];
+                if (v > t1) {
+                    t2 = t1;
+                    t1 = v;
+                } else if (v > t2) {
+                    t2 = v;
+                }
             }
+            flag = L > 1 && !(t1 - t2 >= margin);  // NaN outputs are listed too
         }
-        flag = L > 1 && !(t1 - t2 >= margin);  // NaN outputs are listed too
+        ball[u] = __ballot(flag);
+        wc += (unsigned int)__popcll(ball[u]);
     }
-    const uint64_t b = __ballot(flag);
-    if (!b) return;
-    const int lane = threadIdx.x & 63;
-    unsigned int base = 0;
-    if (lane == __ffsll((unsigned long long)b) - 1) base = atomicAdd(count, (unsigned int)__popcll(b));
-    base = __shfl(base, __ffsll((unsigned long long)b) - 1);
-    if (flag) list[base + __popcll(b & ((1ull << lane) - 1ull))] = (int32_t)i;
+    if (lane == 0) s_wcnt[wave] = wc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int tot = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+        s_base = tot ? atomicAdd(count, tot) : 0u;
+    }
+    __syncthreads();
+    unsigned int off = s_base;
+    for (int w = 0; w < wave; ++w) off += s_wcnt[w];
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int u = 0; u < kUncPer; ++u) {
+        if ((ball[u] >> lane) & 1ull) list[off + __popcll(ball[u] & lt)] = (int32_t)(p0 + (int64_t)u * 256);
+        off += (unsigned int)__popcll(ball[u]);
+    }
 }
 
 // out[list[i]][l] = ex[i][l] for the m listed rows of L values.
@@ -457,8 +478,8 @@ __global__ __launch_bounds__(256) void k_mlp_scatter_rows(const float *ex, const
 hipError_t launch_mlp_uncertain(const LaunchCtx &lc, const float *y, int64_t n, int L, float margin, int32_t *list,
                                 unsigned int *count) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_uncertain, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, lc.stream, y, n, L, margin,
-                       list, count);
+    hipLaunchKernelGGL(k_mlp_uncertain, dim3((unsigned)((n + 256 * kUncPer - 1) / (256 * kUncPer))), dim3(256), 0,
+                       lc.stream, y, n, L, margin, list, count);
     return hipGetLastError();
 }
 
