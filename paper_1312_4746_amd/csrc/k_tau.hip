@@ -353,58 +353,78 @@ __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, i
 
 // Offsets of the fused gather's per-wave regions in the compact lists
 // (exclusive scans of their candidate and undecided-entry counts) and the two
-// totals; one workgroup.  The counts go through LDS in chunks of kScanChunk
-// (coalesced loads), each thread scanning 8 consecutive ones.
+// totals.  One workgroup per chunk of kScanChunk counts: it first adds up the
+// counts of the chunks before its own (eight loads per thread in flight),
+// then scans its chunk through LDS (coalesced loads, each thread scanning 8
+// consecutive counts); the last workgroup writes the totals.  (One workgroup
+// walking every chunk in turn took 0.22 ms at 2048 x 2048.)
 constexpr int kScanChunk = 8192;
 __global__ __launch_bounds__(1024) void k_list_scan(const unsigned int *ccnt, const unsigned int *dcnt,
                                                     TauState *st, unsigned long long *coff,
                                                     unsigned long long *doff) {
     __shared__ unsigned int lc[kScanChunk], ld[kScanChunk];
     __shared__ unsigned long long s[2][1024];
+    __shared__ unsigned long long s_carry[2];
     const int nw = (int)st->rg_waves;
     const int t = threadIdx.x;
-    unsigned long long carry_c = 0, carry_d = 0;
-    for (int base = 0; base < nw; base += kScanChunk) {
-        for (int i = t; i < kScanChunk; i += 1024) {
-            const int r = base + i;
-            lc[i] = r < nw ? ccnt[r] : 0u;
-            ld[i] = r < nw ? dcnt[r] : 0u;
-        }
-        __syncthreads();
-        unsigned long long sc = 0, sd = 0;
+    const int base = blockIdx.x * kScanChunk;
+    if (base >= nw) return;  // workgroup-uniform
+    // counts of the chunks before this one
+    unsigned long long pc = 0, pd = 0;
+    for (int i0 = 0; i0 < base; i0 += 8 * 1024) {
+        unsigned int vc[8], vd[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            sc += lc[8 * t + u];
-            sd += ld[8 * t + u];
+            const int r = i0 + u * 1024 + t;
+            vc[u] = r < base ? ccnt[r] : 0u;
+            vd[u] = r < base ? dcnt[r] : 0u;
         }
-        s[0][t] = sc;
-        s[1][t] = sd;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const unsigned long long vc = t >= off ? s[0][t - off] : 0ull, vd = t >= off ? s[1][t - off] : 0ull;
-            __syncthreads();
-            s[0][t] += vc;
-            s[1][t] += vd;
-            __syncthreads();
-        }
-        unsigned long long bc = carry_c + s[0][t] - sc, bd = carry_d + s[1][t] - sd;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int r = base + 8 * t + u;
-            if (r < nw) {
-                coff[r] = bc;
-                doff[r] = bd;
-            }
-            bc += lc[8 * t + u];
-            bd += ld[8 * t + u];
+            pc += vc[u];
+            pd += vd[u];
         }
-        carry_c += s[0][1023];
-        carry_d += s[1][1023];
-        __syncthreads();  // lc, ld and s are rewritten by the next chunk
     }
-    if (t == 0) {
-        st->ncand = carry_c;
-        st->n_d = carry_d;
+    if (t == 0) s_carry[0] = s_carry[1] = 0ull;
+    for (int i = t; i < kScanChunk; i += 1024) {
+        const int r = base + i;
+        lc[i] = r < nw ? ccnt[r] : 0u;
+        ld[i] = r < nw ? dcnt[r] : 0u;
+    }
+    __syncthreads();
+    if (pc) atomicAdd(&s_carry[0], pc);
+    if (pd) atomicAdd(&s_carry[1], pd);
+    unsigned long long sc = 0, sd = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        sc += lc[8 * t + u];
+        sd += ld[8 * t + u];
+    }
+    s[0][t] = sc;
+    s[1][t] = sd;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long vc = t >= off ? s[0][t - off] : 0ull, vd = t >= off ? s[1][t - off] : 0ull;
+        __syncthreads();
+        s[0][t] += vc;
+        s[1][t] += vd;
+        __syncthreads();
+    }
+    const unsigned long long carry_c = s_carry[0], carry_d = s_carry[1];
+    unsigned long long bc = carry_c + s[0][t] - sc, bd = carry_d + s[1][t] - sd;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int r = base + 8 * t + u;
+        if (r < nw) {
+            coff[r] = bc;
+            doff[r] = bd;
+        }
+        bc += lc[8 * t + u];
+        bd += ld[8 * t + u];
+    }
+    if (t == 0 && base + kScanChunk >= nw) {
+        st->ncand = carry_c + s[0][1023];
+        st->n_d = carry_d + s[1][1023];
     }
 }
 
@@ -657,7 +677,8 @@ __global__ __launch_bounds__(1024) void k_tau_select(const double *vals, int64_t
 
 hipError_t list_compact(const LaunchCtx &lc, int64_t nw, const int64_t *cand, const unsigned int *ccnt,
                         const int64_t *didx, const unsigned int *dcnt, TauState *st, FusedLists fl) {
-    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, lc.stream, ccnt, dcnt, st, fl.coff, fl.doff);
+    hipLaunchKernelGGL(k_list_scan, dim3((unsigned)((nw + kScanChunk - 1) / kScanChunk)), dim3(1024), 0, lc.stream,
+                       ccnt, dcnt, st, fl.coff, fl.doff);
     hipLaunchKernelGGL(k_list_compact, dim3((unsigned)((nw + 63) / 64)), dim3(64), 0, lc.stream, cand, ccnt, fl.coff,
                        didx, dcnt, fl.doff, st, fl.ccomp, fl.dcomp);
     return hipGetLastError();
