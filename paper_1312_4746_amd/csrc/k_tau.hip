@@ -354,7 +354,8 @@ __global__ __launch_bounds__(64) void k_tau_recompute(const float *rgb, int H, i
 // Offsets of the fused gather's per-wave regions in the compact lists
 // (exclusive scans of their candidate and undecided-entry counts) and the two
 // totals.  One workgroup per chunk of kScanChunk counts: it first adds up the
-// counts of the chunks before its own (eight loads per thread in flight),
+// counts of the chunks before its own (eight 16-byte loads per thread in
+// flight, four of each count array),
 // then scans its chunk through LDS (coalesced loads, each thread scanning 8
 // consecutive counts); the last workgroup writes the totals.  (One workgroup
 // walking every chunk in turn took 0.22 ms at 2048 x 2048.)
@@ -369,20 +370,22 @@ __global__ __launch_bounds__(1024) void k_list_scan(const unsigned int *ccnt, co
     const int t = threadIdx.x;
     const int base = blockIdx.x * kScanChunk;
     if (base >= nw) return;  // workgroup-uniform
-    // counts of the chunks before this one
+    // counts of the chunks before this one, four per 16-byte load (base is a
+    // multiple of kScanChunk, the arrays 256-byte aligned)
     unsigned long long pc = 0, pd = 0;
-    for (int i0 = 0; i0 < base; i0 += 8 * 1024) {
-        unsigned int vc[8], vd[8];
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(ccnt), *d4 = reinterpret_cast<const uint4 *>(dcnt);
+    for (int i0 = 0; i0 < base / 4; i0 += 4 * 1024) {
+        uint4 vc[4], vd[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int r = i0 + u * 1024 + t;
-            vc[u] = r < base ? ccnt[r] : 0u;
-            vd[u] = r < base ? dcnt[r] : 0u;
+            vc[u] = r < base / 4 ? c4[r] : make_uint4(0u, 0u, 0u, 0u);
+            vd[u] = r < base / 4 ? d4[r] : make_uint4(0u, 0u, 0u, 0u);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            pc += vc[u];
-            pd += vd[u];
+        for (int u = 0; u < 4; ++u) {
+            pc += (unsigned long long)vc[u].x + vc[u].y + vc[u].z + vc[u].w;
+            pd += (unsigned long long)vd[u].x + vd[u].y + vd[u].z + vd[u].w;
         }
     }
     if (t == 0) s_carry[0] = s_carry[1] = 0ull;
